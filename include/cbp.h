@@ -1,0 +1,181 @@
+/*
+ * cbp.h -- C ABI of the MI355X (gfx950) coprime-blurred-pair deblurring library.
+ *
+ * Problem (Sec. 4, eq. 1 and eq. 4 of Thorpe et al., "A Co-Prime Blur Scheme
+ * for Data Security in Video Surveillance"): two frames B1 = L (x) K1 + N1 and
+ * B2 = L (x) K2 + N2 of one latent frame L, blurred by two unknown kernels that
+ * are coprime as bivariate polynomials (Sec. 3).  Given B1, B2 and the latent
+ * size (Sec. 6: all frames have a known resolution), the library recovers K1,
+ * K2 (the cofactors of the GCD) and L.
+ *
+ * Method (Sec. 4 and Sec. 5), every step on the GPU inside one call:
+ *   1. evaluate both frames as polynomials at S roots of unity along one axis
+ *      at a time (eq. 3; Sec. 5: "exactly a DFT"), for both axis orders;
+ *   2. at every sample, the 1-D cofactors are the null vector of the stacked
+ *      convolution matrix [C(b1) | -C(b2)], taken as the smallest eigenvector
+ *      of its Hermitian Gram matrix (Sec. 5: one small factorisation per
+ *      sample and direction);
+ *   3. the per-sample scales of the two evaluation orders are fixed by one
+ *      least-squares problem with 2S unknowns (Sec. 4 last paragraph, Sec. 5);
+ *   4. the two scaled kernel spectra are averaged, inverse-DFT'd and
+ *      normalised (Sec. 5; abstract);
+ *   5. the latent is recovered by Fourier division (Sec. 4; Sec. 5), here over
+ *      both channels with a Tikhonov term lambda.
+ *
+ * Conventions shared by every entry point
+ *   - Images are row-major [c][y][x] in DEVICE memory: element (c, y, x) is at
+ *     data[c*channel_stride + y*pitch + x] (pitch and channel_stride in
+ *     elements).  B_c is H_c x W_c; the latent is m x n; a full convolution
+ *     gives H_c = m + k_c - 1 and W_c = n + k_c - 1, so k_c = H_c - m + 1.
+ *   - Kernels are FP64, row-major k_c x k_c, in DEVICE memory.
+ *   - The caller owns every buffer, including the workspace, whose size comes
+ *     from cbp_workspace_size().  The library allocates no device memory.
+ *   - Calls are asynchronous on options->stream (a hipStream_t; NULL = the
+ *     default stream).  The returned status covers HOST-side validation only;
+ *     numerical outcomes are written to options->diag (device, nullable) and
+ *     are valid after the stream is synchronised.
+ *   - Nothing here is thread-safe for calls that share a workspace.
+ *   - No exception crosses this ABI.
+ */
+#ifndef CBP_H_
+#define CBP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CBP_MAX_K 32   /* largest kernel size */
+#define CBP_MAX_S 32   /* largest number of samples per axis */
+#define CBP_MAX_N 64   /* largest per-sample unknown count k1 + k2 */
+#define CBP_MAX_FFT_F32 2048  /* largest FFT grid side, FP32 division */
+#define CBP_MAX_FFT_F64 1792  /* largest FFT grid side, FP64 division */
+
+typedef enum {
+  CBP_OK = 0,
+  CBP_E_INVALID = 1,      /* null pointer, bad option value, S < max k */
+  CBP_E_SHAPE = 2,        /* frames not full convolutions of one m x n latent, k outside 1..32, grid too large */
+  CBP_E_DEGENERATE = 3,   /* reserved for callers that check diag flags */
+  CBP_E_DEVICE = 4,       /* a HIP launch or query failed */
+  CBP_E_NOMEM = 5,        /* workspace smaller than cbp_workspace_size() */
+  CBP_E_UNSUPPORTED = 6   /* option combination not built */
+} cbp_status;
+
+typedef enum { CBP_F32 = 0, CBP_F64 = 1 } cbp_dtype;
+
+/* Precision form.
+ *   FP64  : FP64 frames; evaluation, Gram (double-double accumulated), the
+ *           eigen-solves, scale fix and Fourier division all in FP64.
+ *   MIXED : FP32 frames; evaluation accumulated in FP64, Gram double-double,
+ *           eigen-solves and scale fix FP64, FFT and division in FP32. */
+typedef enum { CBP_PREC_FP64 = 0, CBP_PREC_MIXED = 1, CBP_PREC_MFMA32 = 2, CBP_PREC_BF16 = 3 } cbp_precision;
+
+typedef struct cbp_image {
+  void*     data;            /* device pointer */
+  int32_t   dtype;           /* cbp_dtype */
+  int32_t   height, width;   /* H x W */
+  int32_t   channels;        /* 1 (grayscale) or more; all channels share one kernel pair */
+  int64_t   pitch;           /* elements between rows, >= width */
+  int64_t   channel_stride;  /* elements between channels, >= height*pitch */
+} cbp_image;
+
+typedef struct cbp_options {
+  int32_t     precision;        /* cbp_precision */
+  int32_t     samples;          /* S per axis; 0 = max(k1, k2); must be >= max(k1, k2) and <= CBP_MAX_S */
+  double      lambda;           /* Tikhonov term of the Fourier division, >= 0 */
+  double      tau;              /* reserved (learned form), must be 0 */
+  int32_t     learned;          /* reserved (learned form), must be 0 */
+  int32_t     flags;            /* reserved, must be 0 */
+  const void* mlp_blob;         /* reserved, must be NULL */
+  void*       stream;           /* hipStream_t */
+  void*       workspace;        /* device scratch owned by the caller */
+  size_t      workspace_bytes;  /* its size in bytes */
+  void*       diag;             /* device cbp_diag (one per frame for the batch call), or NULL */
+} cbp_options;
+
+/* Diagnostic flags (cbp_diag.flags). */
+#define CBP_DIAG_NONFINITE      1  /* a non-finite value reached the kernels */
+#define CBP_DIAG_SAMPLE_WEAK    2  /* some per-sample Gram had no clear null direction */
+#define CBP_DIAG_SCALE_WEAK     4  /* the scale system had no clear null direction */
+#define CBP_DIAG_KERNEL_ZERO    8  /* a kernel estimate summed to ~0 before normalisation */
+
+/* Per-frame numerical diagnostics, written in device memory when
+ * options->diag is not NULL.  Complex values are (re, im) pairs. */
+typedef struct cbp_diag {
+  int32_t k1, k2, S, n;                      /* sizes used: n = k1 + k2 */
+  int32_t flags;                             /* CBP_DIAG_* */
+  int32_t reserved;
+  double  sample_lambda0[2][CBP_MAX_S];      /* Rayleigh quotient of each null vector (pass X, pass Y) */
+  double  sample_scale[2][CBP_MAX_S];        /* largest Gram diagonal entry of each sample */
+  double  scale_lambda0, scale_scale;        /* same two figures for the scale system */
+  double  kernel_imag[2];                    /* ||Im K|| / ||Re K|| after normalisation */
+  double  kernel_outside[2];                 /* energy fraction of the S x S inverse DFT outside the k x k support */
+  double  sample_vec[2][CBP_MAX_S][CBP_MAX_N][2];  /* unit null vectors x = (u: k2 entries, v: k1 entries) */
+  double  scale_vec[2 * CBP_MAX_S][2];             /* unit (a_0..a_{S-1}, b_0..b_{S-1}) */
+  double  khat[2][CBP_MAX_S][CBP_MAX_S][2];        /* averaged kernel spectra [kernel][i (x freq)][j (y freq)] */
+} cbp_diag;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* cbp_status_string(cbp_status s);
+
+/* Library version, "major.minor.patch" (static string). */
+const char* cbp_version(void);
+
+/* Bytes of workspace needed by one call on frames of at most maxH x maxW
+ * pixels with kernels of at most maxk, for `channels` channels and `batch`
+ * frames in flight (the batch call).  Returns 0 for invalid sizes.
+ * `opts` may be NULL (then precision FP64 and S = maxk are assumed). */
+size_t cbp_workspace_size(int32_t maxH, int32_t maxW, int32_t maxk,
+                          int32_t channels, int32_t batch, const cbp_options* opts);
+
+/* Unit-circle evaluation of one frame (Sec. 4 eq. 3; Sec. 5): writes
+ *   ex[j*W + x] = sum_y B[y][x] w_j^y   (S x W complex, interleaved FP64)
+ *   ey[i*H + y] = sum_x B[y][x] w_i^x   (S x H complex, interleaved FP64)
+ * with w_j = exp(-2 pi i j / S), accumulated in FP64.  ex, ey are device
+ * buffers of 2*S*W and 2*S*H doubles.  Channel 0 only.  Uses the workspace
+ * (>= cbp_workspace_size(H, W, S, 1, 1, opts)). */
+cbp_status cbp_eval_unit_circle(const cbp_image* b, int32_t S, double* ex, double* ey,
+                                const cbp_options* opts);
+
+/* Kernel recovery (steps 1-4).  b1, b2: the blurred pair (same dtype and
+ * channel count); m, n: latent size.  K1 (k1*k1 doubles) and K2 (k2*k2)
+ * receive the kernels normalised to sum 1.  Multi-channel frames: the
+ * per-sample Gram matrices are summed over channels. */
+cbp_status cbp_recover_kernels(const cbp_image* b1, const cbp_image* b2, int32_t m, int32_t n,
+                               double* K1, double* K2, const cbp_options* opts);
+
+/* Kernel recovery followed by two-channel regularised Fourier division
+ * (steps 1-5).  The latent size m x n and channel count are read from
+ * `latent`, whose dtype must equal the inputs'.  K1, K2 may be NULL (then
+ * the kernels stay in the workspace). */
+cbp_status cbp_deblur(const cbp_image* b1, const cbp_image* b2, cbp_image* latent,
+                      double* K1, double* K2, const cbp_options* opts);
+
+/* cbp_deblur over `nframes` independent frames (each with its own kernel
+ * pair and sizes).  b1s, b2s, latents, K1s, K2s are HOST arrays of nframes
+ * entries (K1s / K2s entries may be NULL).  per_frame (host, nullable)
+ * receives each frame's validation status; the call returns the first
+ * failure or CBP_OK.  The workspace must hold `nframes` frames of the
+ * largest size (cbp_workspace_size(..., batch = nframes, ...)).
+ * opts->diag, when set, points to nframes cbp_diag records. */
+cbp_status cbp_deblur_batch(int32_t nframes, const cbp_image* b1s, const cbp_image* b2s,
+                            cbp_image* latents, double* const* K1s, double* const* K2s,
+                            cbp_status* per_frame, const cbp_options* opts);
+
+/* Phase timing.  While enabled, every call records a HIP event pair around
+ * each phase on its stream; cbp_profile_read() waits for the recorded events,
+ * adds their elapsed times to per-phase totals and returns the number of
+ * phases (at most max_phases are written to ms_total / counts).  Names come
+ * from cbp_profile_phase_name().  cbp_profile_reset() clears the totals. */
+void        cbp_profile_enable(int32_t on);
+void        cbp_profile_reset(void);
+int32_t     cbp_profile_read(double* ms_total, int64_t* counts, int32_t max_phases);
+const char* cbp_profile_phase_name(int32_t phase);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CBP_H_ */

@@ -1,0 +1,18 @@
+"""Slow, plain FP64 CPU oracle for coprime-blurred-pair (CBP) deblurring.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg may import anything from this package; the
+product path (the HIP library and its Python binding) never does, and this
+package imports nothing from it.
+
+Modules
+  cbp    -- the method, step by step, in the paper's order (Sec. 4 and 5):
+            unit-circle evaluation, per-sample cofactor null vectors, the
+            two-order scale fix, assembly + inverse DFT, Fourier division.
+  tls2d  -- an independent route: the 2-D null space of the full system
+            B1 (x) U = B2 (x) V by brute force.
+  exact  -- exact rational / Gaussian-rational arithmetic (SymPy) on tiny
+            integer inputs: GCD, resultants, exact null spaces.
+"""
+
+from . import cbp, tls2d, exact  # noqa: F401
