@@ -1,0 +1,241 @@
+"""Benchmark: deblurred Mpixel/s of the CBP hot path (kernel recovery + two-channel
+Fourier division) on one MI355X.
+
+Workload: one 480x640 grayscale frame per step (smooth scene of 40 anisotropic
+Gaussians + 0.1 texture), coprime 9x9 / 11x11 kernels (Gaussian sigma 2 + 0.2
+uniform, sum 1), additive noise sigma 1e-3, lambda 1e-4, S = 11.  Inputs are
+generated on the host, copied to the device once and resident in HBM before
+the timed region.  The headline `value` is the mixed form (FP32 frames and FFT,
+FP64 kernel recovery); the plain FP64 form is timed the same way and reported
+beside it, each with its PSNR against the FP64 oracle's latent.
+
+A step is one cbp_deblur call (every kernel of the path).  W untimed warm-up
+steps, then exactly K timed steps between two device synchronisations.  A
+second pass of K steps records HIP events around every kernel (on the stream
+the kernels run on) for the per-kernel averages and the roofline line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 256 MiB (counter calibration runs)")
+    return ap.parse_args()
+
+
+def psnr(a, b, peak=1.0):
+    mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
+    return float("inf") if mse == 0 else 10.0 * np.log10(peak * peak / mse)
+
+
+def source_hash(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1203_4874_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+# Algorithmic cost of each kernel for one frame of this workload.  Bytes: the
+# minimum HBM traffic of the kernel's own inputs and outputs.  FLOPs: the
+# arithmetic of the kernel's algorithm (stated in the design notes).
+def kernel_models(H1, W1, H2, W2, m, n, k1, k2, S, Py, Px, esize, sweeps_hint):
+    hx = Px // 2 + 1
+    N = k1 + k2
+    cplx = 2 * esize
+    pix_in = (H1 * W1 + H2 * W2)
+    models = {
+        "fold_cols": dict(bound="hbm", bytes=pix_in * esize + 8 * S * (W1 + W2)),
+        "eval_rows": dict(bound="hbm", bytes=pix_in * esize + 16 * S * (H1 + H2)),
+        "row_fft_fwd": dict(bound="hbm", bytes=pix_in * esize + cplx * hx * (H1 + H2)),
+        "col_fft_filter": dict(bound="hbm", bytes=cplx * hx * (H1 + H2) + cplx * hx * m),
+        "row_fft_inv": dict(bound="hbm", bytes=cplx * hx * m + esize * m * n),
+        # Jacobi: per sweep n(n-1)/2 rotations, each rewriting 2 rows and 2
+        # columns of A and 2 columns of V (6n complex outputs, 14 flops each)
+        "sample_eig": dict(bound="alu", flops=2 * S * sweeps_hint * (N * (N - 1) // 2) * 6 * N * 14,
+                           peak=FP64_PEAK_TFLOPS),
+    }
+    return models
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1203_4874_amd as P
+
+    dev = torch.device("cuda:0")
+    P.lib()
+    c = synth.config2()
+    m, n, lam = c["m"], c["n"], c["lam"]
+    H1, W1 = c["B1"].shape
+    H2, W2 = c["B2"].shape
+    k1, k2, S = c["K1"].shape[0], c["K2"].shape[0], c["S"]
+
+    forms = {}
+    for name, npd, tdt, prec in (("mixed", np.float32, torch.float32, P.Precision.MIXED),
+                                 ("fp64", np.float64, torch.float64, P.Precision.FP64)):
+        B1 = c["B1"].astype(npd)
+        B2 = c["B2"].astype(npd)
+        b1 = torch.as_tensor(B1, device=dev)
+        b2 = torch.as_tensor(B2, device=dev)
+        d = P.Deblurrer(max(H1, H2), max(W1, W2), max(k1, k2), precision=prec, device=dev)
+        out = torch.empty((m, n), dtype=tdt, device=dev)
+        K1 = torch.empty((k1, k1), dtype=torch.float64, device=dev)
+        K2 = torch.empty((k2, k2), dtype=torch.float64, device=dev)
+        forms[name] = dict(B1=B1, B2=B2, b1=b1, b2=b2, d=d, out=out, K1=K1, K2=K2)
+
+    def step(f):
+        f["d"].deblur(f["b1"], f["b2"], m, n, lam=lam, out=f["out"], K1=f["K1"], K2=f["K2"])
+
+    results = {}
+    for name, f in forms.items():
+        for _ in range(args.warmup):
+            step(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(f)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms = 1e3 * dt / args.steps
+        print(f"[bench] {name}: {args.steps} steps in {dt:.3f} s ({ms:.4f} ms/step)", file=sys.stderr, flush=True)
+        # per-kernel timing pass (HIP events on the call's stream)
+        with P.profile() as prof:
+            for _ in range(args.steps):
+                step(f)
+            torch.cuda.synchronize()
+        phases = {k: (v[0] / v[1] * 1e3 if v[1] else None) for k, v in prof.result.items()}
+        results[name] = dict(ms=ms, phases_us=phases)
+
+    # accuracy of each form against the FP64 oracle (outside the timed regions)
+    from oracle import cbp as orc
+    Lo, R1, R2 = orc.deblur(c["B1"], c["B2"], m, n, S, lam)
+    for name, f in forms.items():
+        step(f)
+        torch.cuda.synchronize()
+        L = f["out"].double().cpu().numpy()
+        kr = float(np.linalg.norm(f["K1"].cpu().numpy() - R1) / np.linalg.norm(R1))
+        kr2 = float(np.linalg.norm(f["K2"].cpu().numpy() - R2) / np.linalg.norm(R2))
+        results[name].update(psnr_vs_oracle=psnr(L, Lo), psnr_vs_truth=psnr(L, c["L"]),
+                             kernel_rel_l2_vs_oracle=max(kr, kr2))
+
+    mpix = m * n / 1e6
+    main_form = results["mixed"]
+    value = mpix / (main_form["ms"] / 1e3)
+
+    # roofline of the dominant kernel of the headline form
+    ph = {k: v for k, v in main_form["phases_us"].items() if v}
+    dom = max(ph, key=ph.get)
+    Py, Px = orc.smooth7(max(H1, H2)), orc.smooth7(max(W1, W2))
+    models = kernel_models(H1, W1, H2, W2, m, n, k1, k2, S, Py, Px, 4, sweeps_hint=8)
+    roof = None
+    if dom in models:
+        mdl = models[dom]
+        t = ph[dom] * 1e-6
+        if mdl["bound"] == "hbm":
+            ach = mdl["bytes"] / t / 1e9
+            roof = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=ach / HBM_PEAK_GBS, algorithmic_bytes=mdl["bytes"])
+        else:
+            ach = mdl["flops"] / t / 1e12
+            roof = dict(kernel=dom, bound="alu", achieved=ach, peak=mdl["peak"], unit="TFLOP/s",
+                        frac=ach / mdl["peak"], algorithmic_flops=mdl["flops"])
+        roof["avg_us"] = ph[dom]
+        roof["traffic"] = None
+        tf = os.path.join(ROOT, "profiles", "traffic.json")
+        if os.path.exists(tf):
+            with open(tf) as fh:
+                tr = json.load(fh)
+            ent = tr.get(dom)
+            if ent and ent.get("source_hash") == source_hash(ent.get("sources", [])):
+                roof["traffic"] = ent.get("bytes_per_launch")
+    else:
+        roof = dict(kernel=dom, bound="alu", achieved=None, peak=None, unit=None, frac=None, traffic=None,
+                    avg_us=ph[dom])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:
+            threads = os.cpu_count() or 1
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            orc.deblur(c["B1"], c["B2"], m, n, S, lam)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds:
+                break
+        cpu = dict(value=reps * mpix / el, unit="Mpixel/s", cores=int(threads), kind="oracle",
+                   sample=f"{reps} repetitions of the same 480x640 frame (FP64 NumPy/SciPy oracle, {el:.1f} s)")
+
+    if args.copy_calibration:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    line = {
+        "metric": "deblurred Mpixel/s (kernel recovery + deconv), mixed form, PSNR vs FP64 oracle reported",
+        "value": value,
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_form["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (frames, FFT, division) + f64 (evaluation, Gram, eigen-solves, scale fix)",
+        "data": "synthetic",
+        "config": {"workload": "480x640 grayscale frame, coprime 9x9/11x11 kernels, noise 1e-3, lambda 1e-4, S=11",
+                   "frames_per_step": 1, "blurred": [[H1, W1], [H2, W2]], "fft_grid": [Py, Px]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "psnr_vs_oracle_db": main_form["psnr_vs_oracle"],
+        "psnr_vs_truth_db": main_form["psnr_vs_truth"],
+        "kernel_rel_l2_vs_oracle": main_form["kernel_rel_l2_vs_oracle"],
+        "phases_us": main_form["phases_us"],
+        "plain_fp64": {"value": mpix / (results["fp64"]["ms"] / 1e3), "ms_per_step": results["fp64"]["ms"],
+                       "psnr_vs_oracle_db": results["fp64"]["psnr_vs_oracle"],
+                       "kernel_rel_l2_vs_oracle": results["fp64"]["kernel_rel_l2_vs_oracle"],
+                       "phases_us": results["fp64"]["phases_us"]},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -123,6 +123,10 @@ const char* cbp_status_string(cbp_status s);
 /* Library version, "major.minor.patch" (static string). */
 const char* cbp_version(void);
 
+/* sizeof(cbp_diag), for callers that allocate diag records from another
+ * language. */
+size_t cbp_diag_size(void);
+
 /* Bytes of workspace needed by one call on frames of at most maxH x maxW
  * pixels with kernels of at most maxk, for `channels` channels and `batch`
  * frames in flight (the batch call).  Returns 0 for invalid sizes.

@@ -1,0 +1,350 @@
+"""Python binding of the MI355X coprime-blurred-pair (CBP) deblurring library.
+
+Thin ctypes marshalling over the C ABI in include/cbp.h: every step of the
+method (unit-circle evaluation, per-sample Gram eigen-solves, scale fix,
+assembly, Fourier division) runs in the HIP kernels of libcbp.so.  PyTorch
+only provides device memory and the stream.  If libcbp.so has not been built,
+every call raises -- there is no CPU fallback.
+
+Tensors: blurred frames are CUDA (HIP) tensors of shape (H, W) or (C, H, W),
+float32 (mixed precision form) or float64 (FP64 form).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "lib", "library_path", "CbpError", "Precision", "workspace_size", "eval_unit_circle",
+    "recover_kernels", "deblur", "deblur_batch", "Deblurrer", "decode_diag", "profile",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libcbp.so")
+
+CBP_MAX_K = 32
+CBP_MAX_S = 32
+CBP_MAX_N = 64
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "inconsistent or unsupported shape", 3: "degenerate input",
+          4: "device error", 5: "workspace too small", 6: "unsupported option"}
+
+
+class Precision:
+    FP64 = 0
+    MIXED = 1
+    MFMA32 = 2
+    BF16 = 3
+
+
+class CbpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} (status {status})")
+
+
+class CbpImage(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("channels", ctypes.c_int32), ("pitch", ctypes.c_int64),
+                ("channel_stride", ctypes.c_int64)]
+
+
+class CbpOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("samples", ctypes.c_int32), ("lambda_", ctypes.c_double),
+                ("tau", ctypes.c_double), ("learned", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("mlp_blob", ctypes.c_void_p), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("diag", ctypes.c_void_p)]
+
+
+class CbpDiag(ctypes.Structure):
+    _fields_ = [("k1", ctypes.c_int32), ("k2", ctypes.c_int32), ("S", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sample_lambda0", ctypes.c_double * CBP_MAX_S * 2),
+                ("sample_scale", ctypes.c_double * CBP_MAX_S * 2),
+                ("scale_lambda0", ctypes.c_double), ("scale_scale", ctypes.c_double),
+                ("kernel_imag", ctypes.c_double * 2), ("kernel_outside", ctypes.c_double * 2),
+                ("sample_vec", ctypes.c_double * 2 * CBP_MAX_N * CBP_MAX_S * 2),
+                ("scale_vec", ctypes.c_double * 2 * (2 * CBP_MAX_S)),
+                ("khat", ctypes.c_double * 2 * CBP_MAX_S * CBP_MAX_S * 2)]
+
+
+_LIB = None
+
+# every entry point declared in include/cbp.h with (restype, argtypes)
+_P = ctypes.c_void_p
+_SIGS = {
+    "cbp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "cbp_version": (ctypes.c_char_p, []),
+    "cbp_diag_size": (ctypes.c_size_t, []),
+    "cbp_workspace_size": (ctypes.c_size_t, [ctypes.c_int32] * 5 + [ctypes.POINTER(CbpOptions)]),
+    "cbp_eval_unit_circle": (ctypes.c_int, [ctypes.POINTER(CbpImage), ctypes.c_int32, _P, _P,
+                                            ctypes.POINTER(CbpOptions)]),
+    "cbp_recover_kernels": (ctypes.c_int, [ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage), ctypes.c_int32,
+                                           ctypes.c_int32, _P, _P, ctypes.POINTER(CbpOptions)]),
+    "cbp_deblur": (ctypes.c_int, [ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage),
+                                  _P, _P, ctypes.POINTER(CbpOptions)]),
+    "cbp_deblur_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage),
+                                        ctypes.POINTER(CbpImage), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(CbpOptions)]),
+    "cbp_profile_enable": (None, [ctypes.c_int32]),
+    "cbp_profile_reset": (None, []),
+    "cbp_profile_read": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.c_int32]),
+    "cbp_profile_phase_name": (ctypes.c_char_p, [ctypes.c_int32]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcbp.so (built in-tree by paper_1203_4874_amd.build)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(library_path):
+            raise RuntimeError(f"HIP library not built ({library_path}); run: python -m paper_1203_4874_amd.build")
+        L = ctypes.CDLL(library_path)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+# ---------------------------------------------------------------- marshalling helpers
+
+def _torch():
+    import torch
+    return torch
+
+
+def _image(t) -> CbpImage:
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError("CBP frames must be device tensors")
+    if t.dtype not in (torch.float32, torch.float64):
+        raise ValueError("CBP frames must be float32 or float64")
+    if t.dim() == 2:
+        C, (H, W) = 1, t.shape
+        sc, sy, sx = t.shape[0] * t.stride(0), t.stride(0), t.stride(1)
+    elif t.dim() == 3:
+        C, H, W = t.shape
+        sc, sy, sx = t.stride(0), t.stride(1), t.stride(2)
+    else:
+        raise ValueError("frames must be (H, W) or (C, H, W)")
+    if sx != 1:
+        raise ValueError("frames must have unit stride along x")
+    return CbpImage(t.data_ptr(), 0 if t.dtype == torch.float32 else 1, H, W, C, sy, sc)
+
+
+def _precision_of(t) -> int:
+    torch = _torch()
+    return Precision.MIXED if t.dtype == torch.float32 else Precision.FP64
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise CbpError(status, where)
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace_size(maxH: int, maxW: int, maxk: int, channels: int = 1, batch: int = 1,
+                   precision: int = Precision.FP64, samples: int = 0) -> int:
+    o = CbpOptions()
+    o.precision = precision
+    o.samples = samples
+    return int(lib().cbp_workspace_size(maxH, maxW, maxk, channels, batch, ctypes.byref(o)))
+
+
+def diag_size() -> int:
+    return int(lib().cbp_diag_size())
+
+
+def decode_diag(buf: np.ndarray) -> dict:
+    """Decode one cbp_diag record (bytes copied from the device) to numpy."""
+    d = CbpDiag.from_buffer_copy(bytes(buf[:ctypes.sizeof(CbpDiag)]))
+    S, n = d.S, d.n
+    sv = np.ctypeslib.as_array(d.sample_vec).reshape(2, CBP_MAX_S, CBP_MAX_N, 2)
+    kh = np.ctypeslib.as_array(d.khat).reshape(2, CBP_MAX_S, CBP_MAX_S, 2)
+    scv = np.ctypeslib.as_array(d.scale_vec).reshape(2 * CBP_MAX_S, 2)
+    return dict(k1=d.k1, k2=d.k2, S=S, n=n, flags=d.flags,
+                sample_lambda0=np.ctypeslib.as_array(d.sample_lambda0).reshape(2, CBP_MAX_S)[:, :S].copy(),
+                sample_scale=np.ctypeslib.as_array(d.sample_scale).reshape(2, CBP_MAX_S)[:, :S].copy(),
+                scale_lambda0=d.scale_lambda0, scale_scale=d.scale_scale,
+                kernel_imag=list(d.kernel_imag), kernel_outside=list(d.kernel_outside),
+                sample_vec=(sv[:, :S, :n, 0] + 1j * sv[:, :S, :n, 1]).copy(),
+                scale_vec=(scv[:2 * S, 0] + 1j * scv[:2 * S, 1]).copy(),
+                khat=(kh[:, :S, :S, 0] + 1j * kh[:, :S, :S, 1]).copy())
+
+
+@dataclass
+class _Buffers:
+    ws: object
+    diag: object
+
+
+class Deblurrer:
+    """Holds a workspace (and optional diag buffer) for repeated calls on
+    frames up to a maximum size, so steady-state calls allocate nothing."""
+
+    def __init__(self, maxH: int, maxW: int, maxk: int, channels: int = 1, batch: int = 1,
+                 precision: int = Precision.FP64, samples: int = 0, device="cuda", diag: bool = False):
+        torch = _torch()
+        self.precision = precision
+        self.samples = samples
+        nbytes = workspace_size(maxH, maxW, maxk, channels, batch, precision, samples)
+        if nbytes == 0:
+            raise CbpError(2, "workspace_size")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.diag = torch.zeros(diag_size() * batch, dtype=torch.uint8, device=device) if diag else None
+        self.batch = batch
+
+    def options(self, lam: float = 0.0, stream=None, precision=None) -> CbpOptions:
+        o = CbpOptions()
+        o.precision = self.precision if precision is None else precision
+        o.samples = self.samples
+        o.lambda_ = lam
+        o.stream = _stream_ptr(stream)
+        o.workspace = self.ws.data_ptr()
+        o.workspace_bytes = self.ws.numel()
+        o.diag = self.diag.data_ptr() if self.diag is not None else None
+        return o
+
+    def read_diag(self, index: int = 0) -> dict:
+        torch = _torch()
+        torch.cuda.synchronize()
+        raw = self.diag.cpu().numpy()
+        sz = diag_size()
+        return decode_diag(raw[index * sz:(index + 1) * sz])
+
+    def recover_kernels(self, b1, b2, m: int, n: int, K1=None, K2=None, stream=None):
+        torch = _torch()
+        i1, i2 = _image(b1), _image(b2)
+        k1, k2 = i1.height - m + 1, i2.height - m + 1
+        if K1 is None:
+            K1 = torch.empty((max(k1, 1), max(k1, 1)), dtype=torch.float64, device=b1.device)
+        if K2 is None:
+            K2 = torch.empty((max(k2, 1), max(k2, 1)), dtype=torch.float64, device=b1.device)
+        o = self.options(0.0, stream, _precision_of(b1))
+        _check(lib().cbp_recover_kernels(ctypes.byref(i1), ctypes.byref(i2), m, n, K1.data_ptr(), K2.data_ptr(),
+                                         ctypes.byref(o)), "cbp_recover_kernels")
+        return K1, K2
+
+    def deblur(self, b1, b2, m: int, n: int, lam: float = 0.0, out=None, K1=None, K2=None, stream=None):
+        torch = _torch()
+        i1, i2 = _image(b1), _image(b2)
+        k1, k2 = i1.height - m + 1, i2.height - m + 1
+        if out is None:
+            shape = (m, n) if b1.dim() == 2 else (b1.shape[0], m, n)
+            out = torch.empty(shape, dtype=b1.dtype, device=b1.device)
+        if K1 is None:
+            K1 = torch.empty((max(k1, 1), max(k1, 1)), dtype=torch.float64, device=b1.device)
+        if K2 is None:
+            K2 = torch.empty((max(k2, 1), max(k2, 1)), dtype=torch.float64, device=b1.device)
+        io = _image(out)
+        o = self.options(lam, stream, _precision_of(b1))
+        _check(lib().cbp_deblur(ctypes.byref(i1), ctypes.byref(i2), ctypes.byref(io), K1.data_ptr(),
+                                K2.data_ptr(), ctypes.byref(o)), "cbp_deblur")
+        return out, K1, K2
+
+    def deblur_batch(self, pairs, lam: float = 0.0, outs=None, stream=None):
+        """pairs: list of (b1, b2, m, n).  Returns (latents, K1s, K2s, statuses)."""
+        torch = _torch()
+        nf = len(pairs)
+        I1 = (CbpImage * nf)()
+        I2 = (CbpImage * nf)()
+        IO = (CbpImage * nf)()
+        k1p = (ctypes.c_void_p * nf)()
+        k2p = (ctypes.c_void_p * nf)()
+        st = (ctypes.c_int * nf)()
+        latents, K1s, K2s = [], [], []
+        for f, (b1, b2, m, n) in enumerate(pairs):
+            I1[f], I2[f] = _image(b1), _image(b2)
+            k1, k2 = I1[f].height - m + 1, I2[f].height - m + 1
+            out = outs[f] if outs is not None else torch.empty(
+                (m, n) if b1.dim() == 2 else (b1.shape[0], m, n), dtype=b1.dtype, device=b1.device)
+            K1 = torch.empty((max(k1, 1), max(k1, 1)), dtype=torch.float64, device=b1.device)
+            K2 = torch.empty((max(k2, 1), max(k2, 1)), dtype=torch.float64, device=b1.device)
+            IO[f] = _image(out)
+            k1p[f], k2p[f] = K1.data_ptr(), K2.data_ptr()
+            latents.append(out); K1s.append(K1); K2s.append(K2)
+        o = self.options(lam, stream, _precision_of(pairs[0][0]))
+        s = lib().cbp_deblur_batch(nf, I1, I2, IO, k1p, k2p, st, ctypes.byref(o))
+        _check(s, "cbp_deblur_batch")
+        return latents, K1s, K2s, list(st)
+
+
+def _one_shot(b1, b2, m, n, samples, diag):
+    H = max(b1.shape[-2], b2.shape[-2])
+    W = max(b1.shape[-1], b2.shape[-1])
+    k = max(b1.shape[-2], b2.shape[-2]) - m + 1
+    ch = 1 if b1.dim() == 2 else b1.shape[0]
+    return Deblurrer(H, W, max(1, min(k, CBP_MAX_K)), ch, 1, _precision_of(b1), samples, b1.device, diag)
+
+
+def eval_unit_circle(b, S: int, stream=None):
+    """(EX, EY) complex128 device tensors of shapes (S, W) and (S, H)."""
+    torch = _torch()
+    im = _image(b)
+    ex = torch.empty((S, im.width), dtype=torch.complex128, device=b.device)
+    ey = torch.empty((S, im.height), dtype=torch.complex128, device=b.device)
+    need = workspace_size(im.height, im.width, max(1, min(S, CBP_MAX_K)), 1, 1, Precision.FP64, S)
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=b.device)
+    o = CbpOptions()
+    o.precision = _precision_of(b)
+    o.stream = _stream_ptr(stream)
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = ws.numel()
+    _check(lib().cbp_eval_unit_circle(ctypes.byref(im), S, ex.data_ptr(), ey.data_ptr(), ctypes.byref(o)),
+           "cbp_eval_unit_circle")
+    return ex, ey
+
+
+def recover_kernels(b1, b2, m: int, n: int, samples: int = 0, diag: bool = False):
+    d = _one_shot(b1, b2, m, n, samples, diag)
+    K1, K2 = d.recover_kernels(b1, b2, m, n)
+    return (K1, K2, d.read_diag()) if diag else (K1, K2)
+
+
+def deblur(b1, b2, m: int, n: int, samples: int = 0, lam: float = 0.0, diag: bool = False):
+    d = _one_shot(b1, b2, m, n, samples, diag)
+    L, K1, K2 = d.deblur(b1, b2, m, n, lam)
+    return (L, K1, K2, d.read_diag()) if diag else (L, K1, K2)
+
+
+def deblur_batch(pairs, samples: int = 0, lam: float = 0.0):
+    torch = _torch()
+    H = max(max(p[0].shape[-2], p[1].shape[-2]) for p in pairs)
+    W = max(max(p[0].shape[-1], p[1].shape[-1]) for p in pairs)
+    k = max(max(p[0].shape[-2], p[1].shape[-2]) - p[2] + 1 for p in pairs)
+    ch = 1 if pairs[0][0].dim() == 2 else pairs[0][0].shape[0]
+    d = Deblurrer(H, W, max(1, min(k, CBP_MAX_K)), ch, len(pairs), _precision_of(pairs[0][0]), samples,
+                  pairs[0][0].device)
+    return d.deblur_batch(pairs, lam)
+
+
+class profile:
+    """Context manager: per-phase GPU time (ms) of the calls made inside it."""
+
+    def __enter__(self):
+        lib().cbp_profile_reset()
+        lib().cbp_profile_enable(1)
+        self.result = {}
+        return self
+
+    def __exit__(self, *exc):
+        L = lib()
+        n = 16
+        tot = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        k = L.cbp_profile_read(tot, cnt, n)
+        L.cbp_profile_enable(0)
+        self.result = {L.cbp_profile_phase_name(i).decode(): (tot[i], cnt[i]) for i in range(k)}
+        return False

@@ -1,0 +1,198 @@
+// Mixed-radix (2, 3, 4, 5, 7, 8) Stockham autosort FFT passes.
+//
+// A length-N transform (N a product of the radices) runs as one pass per
+// radix factor R.  Pass s with stride Ns (the product of the radices already
+// applied) performs N/R butterflies; butterfly j reads the R inputs
+// src[j + r*N/R], multiplies input r by the twiddle w_N^{r*k*N/(Ns*R)}
+// (k = j mod Ns), applies an R-point DFT and writes its R outputs to
+// dst[(j - k)*R + k + r*Ns].  After the last pass the result is in natural
+// order (Stockham's autosort formulation; see Van Loan, "Computational
+// Frameworks for the Fast Fourier Transform", SIAM 1992).
+//
+// DIR = -1 computes X[m] = sum_t x[t] exp(-2 pi i m t / N) (forward),
+// DIR = +1 the same with +i (unnormalised inverse).  Twiddles come from a
+// table tw[t] = exp(-2 pi i t / N), t in [0, N).
+//
+// Everything here is host+device so the same butterfly code can be checked
+// on the CPU.
+#pragma once
+
+#include "common.h"
+
+namespace cbp {
+
+// ---------------------------------------------------------------- R-point DFTs
+template <int DIR, typename T>
+CBP_HD void dft2(cplx<T>* v) {
+  cplx<T> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <int DIR, typename T>
+CBP_HD void dft4(cplx<T>& v0, cplx<T>& v1, cplx<T>& v2, cplx<T>& v3) {
+  cplx<T> a = v0 + v2, b = v0 - v2, c = v1 + v3, d = v1 - v3;
+  cplx<T> id = mul_i(d, DIR);  // DIR * i * d
+  v0 = a + c;
+  v2 = a - c;
+  v1 = b + id;
+  v3 = b - id;
+}
+
+template <int DIR, typename T>
+CBP_HD void dft8(cplx<T>* v) {
+  // even / odd split: X_k = E_k + w^k O_k, X_{k+4} = E_k - w^k O_k, w = exp(DIR 2 pi i / 8)
+  cplx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cplx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
+  const T h = T(radix_consts::r2_2);
+  cplx<T> w1 = {h, T(DIR) * h};    // exp(DIR i pi/4)
+  cplx<T> w3 = {-h, T(DIR) * h};   // exp(DIR 3 i pi/4)
+  o1 = o1 * w1;
+  o2 = mul_i(o2, DIR);
+  o3 = o3 * w3;
+  v[0] = e0 + o0; v[4] = e0 - o0;
+  v[1] = e1 + o1; v[5] = e1 - o1;
+  v[2] = e2 + o2; v[6] = e2 - o2;
+  v[3] = e3 + o3; v[7] = e3 - o3;
+}
+
+// Odd prime radix: with a_k = v_k + v_{R-k}, b_k = v_k - v_{R-k},
+//   X_m = v_0 + sum_k a_k cos(2 pi mk/R) + DIR i sum_k b_k sin(2 pi mk/R),
+//   X_{R-m} = the same with -DIR.
+template <int DIR, typename T>
+CBP_HD void dft3(cplx<T>* v) {
+  const T c1 = T(radix_consts::c3_1), s1 = T(radix_consts::s3_1);
+  cplx<T> a = v[1] + v[2], b = v[1] - v[2];
+  cplx<T> A = v[0] + c1 * a;
+  cplx<T> B = mul_i(s1 * b, DIR);
+  v[0] = v[0] + a;
+  v[1] = A + B;
+  v[2] = A - B;
+}
+
+template <int DIR, typename T>
+CBP_HD void dft5(cplx<T>* v) {
+  const T c1 = T(radix_consts::c5_1), s1 = T(radix_consts::s5_1);
+  const T c2 = T(radix_consts::c5_2), s2 = T(radix_consts::s5_2);
+  cplx<T> a1 = v[1] + v[4], b1 = v[1] - v[4];
+  cplx<T> a2 = v[2] + v[3], b2 = v[2] - v[3];
+  cplx<T> A1 = v[0] + c1 * a1 + c2 * a2;
+  cplx<T> A2 = v[0] + c2 * a1 + c1 * a2;
+  cplx<T> B1 = mul_i(s1 * b1 + s2 * b2, DIR);
+  cplx<T> B2 = mul_i(s2 * b1 - s1 * b2, DIR);
+  v[0] = v[0] + a1 + a2;
+  v[1] = A1 + B1;
+  v[4] = A1 - B1;
+  v[2] = A2 + B2;
+  v[3] = A2 - B2;
+}
+
+template <int DIR, typename T>
+CBP_HD void dft7(cplx<T>* v) {
+  const T c1 = T(radix_consts::c7_1), s1 = T(radix_consts::s7_1);
+  const T c2 = T(radix_consts::c7_2), s2 = T(radix_consts::s7_2);
+  const T c3 = T(radix_consts::c7_3), s3 = T(radix_consts::s7_3);
+  cplx<T> a1 = v[1] + v[6], b1 = v[1] - v[6];
+  cplx<T> a2 = v[2] + v[5], b2 = v[2] - v[5];
+  cplx<T> a3 = v[3] + v[4], b3 = v[3] - v[4];
+  cplx<T> A1 = v[0] + c1 * a1 + c2 * a2 + c3 * a3;
+  cplx<T> A2 = v[0] + c2 * a1 + c3 * a2 + c1 * a3;
+  cplx<T> A3 = v[0] + c3 * a1 + c1 * a2 + c2 * a3;
+  cplx<T> B1 = mul_i(s1 * b1 + s2 * b2 + s3 * b3, DIR);
+  cplx<T> B2 = mul_i(s2 * b1 - s3 * b2 - s1 * b3, DIR);
+  cplx<T> B3 = mul_i(s3 * b1 - s1 * b2 + s2 * b3, DIR);
+  v[0] = v[0] + a1 + a2 + a3;
+  v[1] = A1 + B1; v[6] = A1 - B1;
+  v[2] = A2 + B2; v[5] = A2 - B2;
+  v[3] = A3 + B3; v[4] = A3 - B3;
+}
+
+template <int R, int DIR, typename T>
+CBP_HD void dft_small(cplx<T>* v) {
+  if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 3) dft3<DIR>(v);
+  else if constexpr (R == 4) dft4<DIR>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 5) dft5<DIR>(v);
+  else if constexpr (R == 7) dft7<DIR>(v);
+  else if constexpr (R == 8) dft8<DIR>(v);
+}
+
+// ---------------------------------------------------------------- one butterfly
+template <int R, int DIR, typename T>
+CBP_HD void stockham_bfly(const cplx<T>* src, cplx<T>* dst, int N, int Ns, int twstep,
+                          const cplx<T>* tw, int j) {
+  const int NR = N / R;
+  const int k = j % Ns;
+  cplx<T> v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = src[j + r * NR];
+  if (Ns > 1) {
+    const int step = k * twstep;  // twstep = N / (Ns * R); r * step < N
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      cplx<T> w = tw[r * step];
+      if (DIR > 0) w.im = -w.im;
+      v[r] = v[r] * w;
+    }
+  }
+  dft_small<R, DIR>(v);
+  const int out = (j - k) * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[out + r * Ns] = v[r];
+}
+
+// ---------------------------------------------------------------- plans
+constexpr int FFT_MAX_PASSES = 16;
+
+struct fft_plan {
+  int N;
+  int npass;
+  int radix[FFT_MAX_PASSES];
+};
+
+// Factor N into the supported radices (8 first, then 4, 2, 3, 5, 7).
+// Returns false when N has another prime factor or too many passes.
+inline bool make_fft_plan(int N, fft_plan* p) {
+  if (N < 1) return false;
+  p->N = N;
+  p->npass = 0;
+  int r = N;
+  const int order[6] = {8, 4, 2, 3, 5, 7};
+  for (int t = 0; t < 6; ++t) {
+    while (r % order[t] == 0) {
+      if (p->npass >= FFT_MAX_PASSES) return false;
+      p->radix[p->npass++] = order[t];
+      r /= order[t];
+    }
+  }
+  return r == 1;
+}
+
+// One pass over `nbatch` transforms stored at src + f*bstride (f < nbatch),
+// butterflies distributed over threads tid, tid+nthr, ...  Returns nothing;
+// the caller synchronises between passes.
+template <int DIR, typename T>
+CBP_HD void fft_pass(const cplx<T>* src, cplx<T>* dst, int N, int R, int Ns, const cplx<T>* tw,
+                     int nbatch, int bstride, int tid, int nthr) {
+  const int nb = N / R;
+  const int total = nb * nbatch;
+  const int twstep = N / (Ns * R);
+  for (int t = tid; t < total; t += nthr) {
+    const int f = t / nb;
+    const int j = t - f * nb;
+    const cplx<T>* s = src + (size_t)f * bstride;
+    cplx<T>* d = dst + (size_t)f * bstride;
+    switch (R) {
+      case 2: stockham_bfly<2, DIR>(s, d, N, Ns, twstep, tw, j); break;
+      case 3: stockham_bfly<3, DIR>(s, d, N, Ns, twstep, tw, j); break;
+      case 4: stockham_bfly<4, DIR>(s, d, N, Ns, twstep, tw, j); break;
+      case 5: stockham_bfly<5, DIR>(s, d, N, Ns, twstep, tw, j); break;
+      case 7: stockham_bfly<7, DIR>(s, d, N, Ns, twstep, tw, j); break;
+      default: stockham_bfly<8, DIR>(s, d, N, Ns, twstep, tw, j); break;
+    }
+  }
+}
+
+}  // namespace cbp

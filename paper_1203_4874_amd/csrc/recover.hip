@@ -1,0 +1,393 @@
+// Kernel recovery on the GPU: per-sample Gram matrices, their smallest
+// eigenvectors (the 1-D cofactors), the two-order scale fix and the assembly
+// of the kernels (Sec. 4 and Sec. 5).
+//
+// Per sample j of pass X (and i of pass Y) the 1-D cofactors solve
+//   b1(w_j, .) (x) u = b2(w_j, .) (x) v,   u: k2 taps, v: k1 taps,
+// since b1 k2 = l k1 k2 = b2 k1 (eq. 4).  With A = [C_k2(e1) | -C_k1(e2)]
+// (C_k(e) the full-convolution matrix of e), the Gram G = A^H A is block
+// Toeplitz:
+//   G11[p][q] = rho11(p - q),  G22[p][q] = rho22(p - q),  G12[p][q] = -rho12(p - q),
+//   rho_ab(l) = sum_t conj(a[t]) b[t + l],
+// so only 2(k1+k2)-1 correlations are formed, each accumulated in
+// double-double (Dot2).  The null vector x = (u, v) is the eigenvector of the
+// smallest eigenvalue of G (eig.h).
+//
+// Scale fix (Sec. 4: combine the two evaluation orders by least squares;
+// Sec. 5: 2t unknowns over t x t equations): with the cofactors evaluated on
+// the other axis,
+//   P_c[i][j] = sum_x v_j^{(c)}[x] w_i^x   (pass X slice j),
+//   Q_c[i][j] = sum_y v_i'^{(c)}[y] w_j^y  (pass Y slice i),
+// the scales z = (a, b) minimise sum_{c,i,j} |a_j P_c[i][j] - b_i Q_c[i][j]|^2
+// with ||z|| = 1: the smallest eigenvector of
+//   H = [[diag(sum |P|^2), -C], [-C^H, diag(sum |Q|^2)]],  C[j][i] = sum_c conj(P_c[i][j]) Q_c[i][j].
+// Assembly (Sec. 5, abstract): Khat_c = (a_j P_c + b_i Q_c) / 2, inverse
+// S x S DFT, crop to the k_c x k_c support, divide by the complex sum over
+// the support and keep the real part.
+#include "eig.h"
+#include "internal.h"
+
+namespace cbp {
+
+namespace {
+
+// G of one sample from its correlations rho (stored: rho11[0..k2),
+// rho22[0..k1), rho12[-(k1-1)..k2-1]).
+struct gram_acc {
+  const cdd* rho;
+  int k1, k2;
+  __device__ cdd get(int i, int j) const {
+    if (i < k2) {
+      if (j < k2) {
+        const int l = i - j;
+        return l >= 0 ? rho[l] : cdd_conj(rho[-l]);
+      }
+      const int q = j - k2;
+      return cdd_neg(rho[k2 + k1 + (i - q) + (k1 - 1)]);
+    }
+    const int p = i - k2;
+    if (j >= k2) {
+      const int l = p - (j - k2);
+      return l >= 0 ? rho[k2 + l] : cdd_conj(rho[k2 - l]);
+    }
+    return cdd_conj(cdd_neg(rho[k2 + k1 + (j - p) + (k1 - 1)]));
+  }
+};
+
+// Scale system H from its diagonal blocks (Da, Db) and coupling C.
+struct scale_acc {
+  const dd* Da;
+  const dd* Db;
+  const cdd* C;
+  int S;
+  __device__ cdd get(int r, int c) const {
+    const dd z = {0.0, 0.0};
+    if (r < S && c < S) return r == c ? cdd{Da[r], z} : cdd{z, z};
+    if (r >= S && c >= S) return r == c ? cdd{Db[r - S], z} : cdd{z, z};
+    if (r < S) return C[r * S + (c - S)];
+    return cdd_conj(C[c * S + (r - S)]);
+  }
+};
+
+__device__ inline void unit_twiddles(c64* tw, int S) {
+  for (int t = threadIdx.x; t < S; t += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * (double)t / (double)S, &s, &c);
+    tw[t] = {c, s};
+  }
+}
+
+__device__ inline bool finite_c(c64 v) { return isfinite(v.re) && isfinite(v.im); }
+
+// Correlations rho for every (pass, sample, lag), summed over channels.
+// grid (2N-1, S, 2), 256 threads.
+__global__ __launch_bounds__(256) void k_gram(const c64* ex, const c64* ey, int Wmax, int Hmax, int W1, int W2,
+                                              int H1, int H2, int S, int k1, int k2, int nch, cdd* corr) {
+  __shared__ dd rre[256], rim[256];
+  const int li = blockIdx.x, j = blockIdx.y, pass = blockIdx.z;
+  const int N = k1 + k2, NL = 2 * N - 1;
+  int fa, fb, l;
+  if (li < k2) { fa = 0; fb = 0; l = li; }
+  else if (li < k2 + k1) { fa = 1; fb = 1; l = li - k2; }
+  else { fa = 0; fb = 1; l = li - (k1 + k2) - (k1 - 1); }
+  const int la = pass == 0 ? (fa ? W2 : W1) : (fa ? H2 : H1);
+  const int lb = pass == 0 ? (fb ? W2 : W1) : (fb ? H2 : H1);
+  const int stride = pass == 0 ? Wmax : Hmax;
+  const c64* base = pass == 0 ? ex : ey;
+  const int t0 = max(0, -l), t1 = min(la, lb - l);
+  dot2 sre, sim;
+  sre.init();
+  sim.init();
+  for (int ch = 0; ch < nch; ++ch) {
+    const c64* a = base + ((size_t)(ch * 2 + fa) * S + j) * stride;
+    const c64* b = base + ((size_t)(ch * 2 + fb) * S + j) * stride;
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += 256) {
+      const c64 av = a[t], bv = b[t + l];
+      sre.add_prod(av.re, bv.re);
+      sre.add_prod(av.im, bv.im);
+      sim.add_prod(av.re, bv.im);
+      sim.add_prod(-av.im, bv.re);
+    }
+  }
+  const int tid = threadIdx.x;
+  rre[tid] = sre.result();
+  rim[tid] = sim.result();
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      rre[tid] = dd_add(rre[tid], rre[tid + s]);
+      rim[tid] = dd_add(rim[tid], rim[tid + s]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) corr[((size_t)pass * S + j) * NL + li] = cdd{rre[0], rim[0]};
+}
+
+// Smallest eigenvector of every per-sample Gram.  grid (S, 2), 256 threads.
+__global__ __launch_bounds__(EIG_NT) void k_sample(const cdd* corr, int S, int k1, int k2, c64* xout,
+                                                   double* lam0, cbp_diag* diag) {
+  extern __shared__ __attribute__((aligned(16))) char sm_sample[];
+  const int N = k1 + k2, NL = 2 * N - 1;
+  const int j = blockIdx.x, pass = blockIdx.y;
+  const int tid = threadIdx.x;
+  cdd* rho = (cdd*)sm_sample;
+  eig_ws w = eig_carve(sm_sample + (((size_t)NL * sizeof(cdd) + 15) & ~(size_t)15), N);
+  for (int l = tid; l < NL; l += EIG_NT) rho[l] = corr[((size_t)pass * S + j) * NL + l];
+  __syncthreads();
+  const gram_acc G{rho, k1, k2};
+  for (int e = tid; e < N * N; e += EIG_NT) {
+    const int i = e / N, c = e - i * N;
+    const cdd g = G.get(i, c);
+    w.A[e] = {g.re.hi, g.im.hi};
+  }
+  __syncthreads();
+  double gmax = 0.0;
+  if (tid == 0)
+    for (int i = 0; i < N; ++i) gmax = fmax(gmax, w.A[i * N + i].re);
+  jacobi_eig(w, N);
+  double second;
+  const int im = eig_argmin(w, N, &second);
+  const dd mu = eig_refine(w, G, N, im);
+  const size_t base = ((size_t)pass * S + j) * N;
+  bool bad = false;
+  for (int i = tid; i < N; i += EIG_NT) {
+    const c64 xi = w.x[i];
+    xout[base + i] = xi;
+    if (!finite_c(xi)) bad = true;
+    if (diag) {
+      diag->sample_vec[pass][j][i][0] = xi.re;
+      diag->sample_vec[pass][j][i][1] = xi.im;
+    }
+  }
+  if (bad && diag) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
+  if (tid == 0) {
+    const double l0 = dd_val(mu);
+    lam0[pass * S + j] = l0;
+    if (diag) {
+      diag->sample_lambda0[pass][j] = l0;
+      diag->sample_scale[pass][j] = gmax;
+      if (!(second - l0 > 1e-13 * gmax)) atomicOr(&diag->flags, CBP_DIAG_SAMPLE_WEAK);
+    }
+  }
+}
+
+// Scale fix, assembly, inverse DFT and normalisation.  One workgroup.
+__global__ __launch_bounds__(EIG_NT) void k_finalize(const c64* xvec, int S, int k1, int k2, c64* pq, cdd* cbuf,
+                                                     double* K1, double* K2, cbp_diag* diag) {
+  extern __shared__ __attribute__((aligned(16))) char sm_fin[];
+  const int N = k1 + k2, n2 = 2 * S, SS = S * S;
+  const int tid = threadIdx.x;
+  c64* tw = (c64*)sm_fin;                        // S
+  dd* Da = (dd*)(tw + CBP_MAX_S);                // S
+  dd* Db = Da + CBP_MAX_S;                       // S
+  c64* sums = (c64*)(Db + CBP_MAX_S);            // 2
+  eig_ws w = eig_carve((char*)(sums + 4), n2);
+  unit_twiddles(tw, S);
+  __syncthreads();
+  // cofactors evaluated on the other axis: pq = [P1, P2, Q1, Q2], each [i][j]
+  for (int e = tid; e < 4 * SS; e += EIG_NT) {
+    const int which = e / SS, ij = e - which * SS;
+    const int i = ij / S, jj = ij - i * S;
+    const c64* xs;
+    int len, f;
+    if (which == 0) { xs = xvec + ((size_t)jj) * N + k2; len = k1; f = i; }          // P1: v of pass X sample jj
+    else if (which == 1) { xs = xvec + ((size_t)jj) * N; len = k2; f = i; }          // P2: u of pass X sample jj
+    else if (which == 2) { xs = xvec + ((size_t)S + i) * N + k2; len = k1; f = jj; } // Q1: v of pass Y sample i
+    else { xs = xvec + ((size_t)S + i) * N; len = k2; f = jj; }                      // Q2: u of pass Y sample i
+    c64 acc = {0.0, 0.0};
+    int t = 0;
+    for (int x = 0; x < len; ++x) {
+      acc = acc + xs[x] * tw[t];
+      t += f;
+      if (t >= S) t -= S;
+    }
+    pq[e] = acc;
+  }
+  __threadfence_block();
+  __syncthreads();
+  // H blocks in double-double
+  for (int e = tid; e < SS; e += EIG_NT) {
+    const int jj = e / S, i = e - jj * S;
+    dot2 re, im;
+    re.init();
+    im.init();
+    for (int c = 0; c < 2; ++c) {
+      const c64 P = pq[(size_t)c * SS + i * S + jj], Q = pq[(size_t)(2 + c) * SS + i * S + jj];
+      re.add_prod(-P.re, Q.re); re.add_prod(-P.im, Q.im);
+      im.add_prod(-P.re, Q.im); im.add_prod(P.im, Q.re);
+    }
+    cbuf[e] = cdd{re.result(), im.result()};
+  }
+  for (int t = tid; t < n2; t += EIG_NT) {
+    dot2 d;
+    d.init();
+    if (t < S) {
+      for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < S; ++i) {
+          const c64 P = pq[(size_t)c * SS + i * S + t];
+          d.add_prod(P.re, P.re); d.add_prod(P.im, P.im);
+        }
+      Da[t] = d.result();
+    } else {
+      const int i = t - S;
+      for (int c = 0; c < 2; ++c)
+        for (int jj = 0; jj < S; ++jj) {
+          const c64 Q = pq[(size_t)(2 + c) * SS + i * S + jj];
+          d.add_prod(Q.re, Q.re); d.add_prod(Q.im, Q.im);
+        }
+      Db[i] = d.result();
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  const scale_acc H{Da, Db, cbuf, S};
+  for (int e = tid; e < n2 * n2; e += EIG_NT) {
+    const int r = e / n2, c = e - r * n2;
+    const cdd h = H.get(r, c);
+    w.A[e] = {h.re.hi, h.im.hi};
+  }
+  __syncthreads();
+  double hmax = 0.0;
+  if (tid == 0)
+    for (int i = 0; i < n2; ++i) hmax = fmax(hmax, w.A[i * n2 + i].re);
+  jacobi_eig(w, n2);
+  double second;
+  const int im = eig_argmin(w, n2, &second);
+  const dd mu = eig_refine(w, H, n2, im);
+  if (tid == 0 && diag) {
+    diag->k1 = k1; diag->k2 = k2; diag->S = S; diag->n = N;
+    diag->scale_lambda0 = dd_val(mu);
+    diag->scale_scale = hmax;
+    if (!(second - dd_val(mu) > 1e-13 * hmax)) atomicOr(&diag->flags, CBP_DIAG_SCALE_WEAK);
+  }
+  if (diag)
+    for (int t = tid; t < n2; t += EIG_NT) {
+      diag->scale_vec[t][0] = w.x[t].re;
+      diag->scale_vec[t][1] = w.x[t].im;
+    }
+  // averaged spectra Kh[c][i][j] (into w.A, 2 S^2 <= n2^2 entries)
+  c64* Kh = w.A;
+  c64* Tm = w.V;
+  for (int e = tid; e < 2 * SS; e += EIG_NT) {
+    const int c = e / SS, ij = e - c * SS;
+    const int i = ij / S, jj = ij - i * S;
+    const c64 P = pq[(size_t)c * SS + ij], Q = pq[(size_t)(2 + c) * SS + ij];
+    const c64 v = w.x[jj] * P + w.x[S + i] * Q;
+    Kh[e] = {0.5 * v.re, 0.5 * v.im};
+    if (diag) {
+      diag->khat[c][i][jj][0] = 0.5 * v.re;
+      diag->khat[c][i][jj][1] = 0.5 * v.im;
+    }
+  }
+  __syncthreads();
+  // inverse DFT along x: Tm[c][j][x] = sum_i Kh[c][i][j] w_i^{-x}
+  for (int e = tid; e < 2 * SS; e += EIG_NT) {
+    const int c = e / SS, jx = e - c * SS;
+    const int jj = jx / S, x = jx - jj * S;
+    c64 acc = {0.0, 0.0};
+    int t = 0;
+    for (int i = 0; i < S; ++i) {
+      acc = acc + Kh[(size_t)c * SS + i * S + jj] * conj(tw[t]);
+      t += x;
+      if (t >= S) t -= S;
+    }
+    Tm[e] = acc;
+  }
+  __syncthreads();
+  // inverse DFT along y: Kf[c][y][x] = sum_j w_j^{-y} Tm[c][j][x]   (into Kh)
+  for (int e = tid; e < 2 * SS; e += EIG_NT) {
+    const int c = e / SS, yx = e - c * SS;
+    const int y = yx / S, x = yx - y * S;
+    c64 acc = {0.0, 0.0};
+    int t = 0;
+    for (int jj = 0; jj < S; ++jj) {
+      acc = acc + Tm[(size_t)c * SS + jj * S + x] * conj(tw[t]);
+      t += y;
+      if (t >= S) t -= S;
+    }
+    Kh[e] = acc;
+  }
+  __syncthreads();
+  for (int c = 0; c < 2; ++c) {
+    const int k = c == 0 ? k1 : k2;
+    double sr = 0.0, si = 0.0, ein = 0.0, eall = 0.0;
+    for (int e = tid; e < SS; e += EIG_NT) {
+      const int y = e / S, x = e - y * S;
+      const c64 v = Kh[(size_t)c * SS + e];
+      const double p = norm2(v);
+      eall += p;
+      if (y < k && x < k) { sr += v.re; si += v.im; ein += p; }
+    }
+    sr = block_sum(sr, w.red);
+    si = block_sum(si, w.red);
+    ein = block_sum(ein, w.red);
+    eall = block_sum(eall, w.red);
+    const double s2 = sr * sr + si * si;
+    double* K = c == 0 ? K1 : K2;
+    double re2 = 0.0, im2 = 0.0;
+    for (int e = tid; e < k * k; e += EIG_NT) {
+      const int y = e / k, x = e - y * k;
+      const c64 v = Kh[(size_t)c * SS + y * S + x];
+      const double kr = (v.re * sr + v.im * si) / s2;
+      const double ki = (v.im * sr - v.re * si) / s2;
+      K[e] = kr;
+      re2 += kr * kr;
+      im2 += ki * ki;
+    }
+    re2 = block_sum(re2, w.red);
+    im2 = block_sum(im2, w.red);
+    if (tid == 0 && diag) {
+      diag->kernel_imag[c] = sqrt(im2) / fmax(sqrt(re2), 1e-300);
+      diag->kernel_outside[c] = (eall - ein) / fmax(eall, 1e-300);
+      if (!(s2 > 0.0) || !isfinite(s2)) atomicOr(&diag->flags, CBP_DIAG_KERNEL_ZERO);
+      if (!isfinite(re2)) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
+    }
+  }
+}
+
+__global__ void k_diag_init(cbp_diag* diag) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) diag->flags = 0;
+}
+
+}  // namespace
+
+size_t finalize_lds_bytes(int S) {
+  return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) + 4 * sizeof(c64) +
+         eig_lds_bytes(2 * S);
+}
+
+size_t sample_lds_bytes(int N) {
+  return ((((size_t)(2 * N - 1) * sizeof(cdd)) + 15) & ~(size_t)15) + eig_lds_bytes(N);
+}
+
+hipError_t launch_recover(const frame_plan& fp, char* ws, double* K1, double* K2, void* diagp, hipStream_t st) {
+  static bool attrs_set = false;
+  if (!attrs_set) {
+    hipFuncSetAttribute((const void*)k_sample, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipFuncSetAttribute((const void*)k_finalize, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attrs_set = true;
+  }
+  cbp_diag* diag = (cbp_diag*)diagp;
+  const int S = fp.S, N = fp.N;
+  const c64* ex = (const c64*)(ws + fp.off_ex);
+  const c64* ey = (const c64*)(ws + fp.off_ey);
+  cdd* corr = (cdd*)(ws + fp.off_corr);
+  c64* xvec = (c64*)(ws + fp.off_xvec);
+  double* lam0 = (double*)(ws + fp.off_lam0);
+  if (diag) hipLaunchKernelGGL(k_diag_init, dim3(1), dim3(64), 0, st, diag);
+  prof_begin(PH_GRAM, st);
+  hipLaunchKernelGGL(k_gram, dim3(2 * N - 1, S, 2), dim3(256), 0, st, ex, ey, fp.Wmax, fp.Hmax, fp.W1, fp.W2, fp.H1,
+                     fp.H2, S, fp.k1, fp.k2, fp.nch, corr);
+  prof_end(PH_GRAM, st);
+  prof_begin(PH_SAMPLE, st);
+  hipLaunchKernelGGL(k_sample, dim3(S, 2), dim3(EIG_NT), sample_lds_bytes(N), st, corr, S, fp.k1, fp.k2, xvec,
+                     lam0, diag);
+  prof_end(PH_SAMPLE, st);
+  prof_begin(PH_FINALIZE, st);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(EIG_NT), finalize_lds_bytes(S), st, xvec, S, fp.k1, fp.k2,
+                     (c64*)(ws + fp.off_pq), (cdd*)(ws + fp.off_cbuf), K1, K2, diag);
+  prof_end(PH_FINALIZE, st);
+  return hipGetLastError();
+}
+
+}  // namespace cbp

@@ -1,0 +1,218 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (stated for the method's outputs):
+  * kernels, FP64 form: relative L2 <= 1e-6;
+  * kernels, mixed form (FP32 frames, FP64 recovery): relative L2 <= 1e-3;
+  * noiseless latent: PSNR >= 60 dB against the oracle's latent (peak 1);
+  * unit-circle evaluation (always FP64-accumulated): max |diff| <= 1e-12 x max |E|.
+Per-sample null vectors are unique only up to a complex scale, so they are
+compared through |<x_gpu, x_oracle>| (unit vectors).  Both sides read the same
+seeded inputs (synth); for the mixed form the oracle reads the float32 frame
+values promoted to float64.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cbp as orc
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def psnr(a, b, peak=1.0):
+    mse = float(np.mean((np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)) ** 2))
+    return float("inf") if mse == 0 else 10 * np.log10(peak * peak / mse)
+
+
+def to_dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=_dev())
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1203_4874_amd as P
+    P.lib()
+    return P
+
+
+# ---------------------------------------------------------------- a1 evaluation
+
+@pytest.mark.parametrize("dtype,shape,S", [(torch.float64, (68, 68), 5), (torch.float32, (490, 650), 11),
+                                           (torch.float64, (37, 301), 32), (torch.float32, (1, 1), 1),
+                                           (torch.float64, (257, 3), 7)])
+def test_eval_unit_circle_matches_oracle(P, dtype, shape, S):
+    r = np.random.default_rng(11)
+    B = r.random(shape)
+    Bd = to_dev(B, dtype)
+    ex, ey = P.eval_unit_circle(Bd, S)
+    torch.cuda.synchronize()
+    Bref = Bd.double().cpu().numpy()
+    EX, EY = orc.unit_circle_eval(Bref, S)
+    scale = max(np.abs(EX).max(), 1e-300)
+    assert np.abs(ex.cpu().numpy() - EX).max() <= 1e-12 * scale
+    assert np.abs(ey.cpu().numpy() - EY).max() <= 1e-12 * scale
+
+
+# ---------------------------------------------------------------- a2-a5 kernels
+
+def _check_samples(diag, full, tol=1e-10):
+    S, n = diag["S"], diag["n"]
+    for p, (U, V) in enumerate(((full["XU"], full["XV"]), (full["YU"], full["YV"]))):
+        for j in range(S):
+            xo = np.concatenate([U[j], V[j]])
+            xg = diag["sample_vec"][p, j]
+            c = abs(np.vdot(xo, xg)) / (np.linalg.norm(xo) * np.linalg.norm(xg))
+            assert c >= 1.0 - tol, (p, j, c)
+
+
+def test_recover_config1_fp64(P):
+    c = synth.config1()
+    b1, b2 = to_dev(c["B1"], torch.float64), to_dev(c["B2"], torch.float64)
+    K1, K2, diag = P.recover_kernels(b1, b2, c["m"], c["n"], diag=True)
+    R1, R2, full = orc.recover_kernels(c["B1"], c["B2"], c["m"], c["n"], full=True)
+    K1, K2 = K1.cpu().numpy(), K2.cpu().numpy()
+    assert rel(K1, R1) <= 1e-10 and rel(K2, R2) <= 1e-10
+    assert rel(K1, c["K1"]) <= 1e-10
+    assert diag["flags"] == 0
+    _check_samples(diag, full)
+
+
+@pytest.mark.parametrize("noise", [0.0, 1e-3])
+def test_recover_config2_fp64(P, noise):
+    c = synth.config2(noise=noise)
+    b1, b2 = to_dev(c["B1"], torch.float64), to_dev(c["B2"], torch.float64)
+    K1, K2, diag = P.recover_kernels(b1, b2, c["m"], c["n"], diag=True)
+    R1, R2, full = orc.recover_kernels(c["B1"], c["B2"], c["m"], c["n"], full=True)
+    e1, e2 = rel(K1.cpu().numpy(), R1), rel(K2.cpu().numpy(), R2)
+    print(f"config2 fp64 noise={noise}: kernel rel-L2 vs oracle {e1:.2e} {e2:.2e}")
+    assert e1 <= 1e-6 and e2 <= 1e-6
+
+
+@pytest.mark.parametrize("noise", [0.0, 1e-3])
+def test_recover_config2_mixed(P, noise):
+    c = synth.config2(noise=noise)
+    B1 = c["B1"].astype(np.float32)
+    B2 = c["B2"].astype(np.float32)
+    K1, K2 = P.recover_kernels(to_dev(B1, torch.float32), to_dev(B2, torch.float32), c["m"], c["n"])
+    R1, R2 = orc.recover_kernels(B1.astype(np.float64), B2.astype(np.float64), c["m"], c["n"])
+    e1, e2 = rel(K1.cpu().numpy(), R1), rel(K2.cpu().numpy(), R2)
+    print(f"config2 mixed noise={noise}: kernel rel-L2 vs oracle {e1:.2e} {e2:.2e}")
+    assert e1 <= 1e-3 and e2 <= 1e-3
+
+
+@pytest.mark.parametrize("k1,k2,S,m,n", [(3, 5, 0, 40, 53), (5, 3, 10, 61, 33), (1, 3, 0, 30, 30),
+                                         (4, 4, 4, 25, 41), (7, 6, 9, 50, 47), (31, 32, 32, 90, 70)])
+def test_recover_uneven_and_extreme_sizes(P, k1, k2, S, m, n):
+    r = synth.rng_for(123, k1, k2, S)
+    L = r.random((m, n))
+    K1, K2 = synth.draw_coprime_pair(r, k1, k2, "uniform", sample_counts=(S or None,))
+    B1, B2 = synth.full_conv2d(L, K1), synth.full_conv2d(L, K2)
+    G1, G2 = P.recover_kernels(to_dev(B1, torch.float64), to_dev(B2, torch.float64), m, n, samples=S)
+    R1, R2 = orc.recover_kernels(B1, B2, m, n, S)
+    assert rel(G1.cpu().numpy(), R1) <= 1e-6 and rel(G2.cpu().numpy(), R2) <= 1e-6
+
+
+# ---------------------------------------------------------------- a6 deconvolution
+
+def test_deblur_config1_fp64(P):
+    c = synth.config1()
+    L, K1, K2 = P.deblur(to_dev(c["B1"], torch.float64), to_dev(c["B2"], torch.float64), c["m"], c["n"])
+    Lo, R1, R2 = orc.deblur(c["B1"], c["B2"], c["m"], c["n"], 0, 0.0)
+    Lg = L.cpu().numpy()
+    assert np.abs(Lg - Lo).max() <= 1e-9
+    assert psnr(Lg, Lo) >= 60
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_deblur_config2_noiseless(P, dtype):
+    c = synth.config2(noise=0.0)
+    npd = np.float64 if dtype == torch.float64 else np.float32
+    B1, B2 = c["B1"].astype(npd), c["B2"].astype(npd)
+    L, K1, K2 = P.deblur(to_dev(B1, dtype), to_dev(B2, dtype), c["m"], c["n"])
+    Lo, R1, R2 = orc.deblur(B1.astype(np.float64), B2.astype(np.float64), c["m"], c["n"], 0, 0.0)
+    p = psnr(L.cpu().numpy(), Lo)
+    print(f"config2 noiseless {dtype}: latent PSNR vs oracle {p:.1f} dB, vs truth {psnr(L.cpu().numpy(), c['L']):.1f} dB")
+    assert p >= 60
+
+
+@pytest.mark.parametrize("m,n,k1,k2", [(33, 45, 3, 4), (20, 61, 5, 2), (64, 63, 9, 9)])
+def test_deblur_ragged_grids_fp64(P, m, n, k1, k2):
+    r = synth.rng_for(321, m, n)
+    L = r.random((m, n))
+    K1, K2 = synth.draw_coprime_pair(r, k1, k2, "uniform")
+    B1, B2 = synth.full_conv2d(L, K1), synth.full_conv2d(L, K2)
+    G, G1, G2 = P.deblur(to_dev(B1, torch.float64), to_dev(B2, torch.float64), m, n)
+    Lo, _, _ = orc.deblur(B1, B2, m, n, 0, 0.0)
+    assert np.abs(G.cpu().numpy() - Lo).max() <= 1e-8
+
+
+def test_deblur_bench_workload(P):
+    """The benchmark's workload and launch configuration: 480x640, kernels
+    9 / 11, noise 1e-3, lambda 1e-4, FP32 frames (mixed form) and FP64."""
+    c = synth.config2()
+    for dtype, npd, ktol in ((torch.float32, np.float32, 1e-3), (torch.float64, np.float64, 1e-6)):
+        B1, B2 = c["B1"].astype(npd), c["B2"].astype(npd)
+        d = P.Deblurrer(490, 650, 11, precision=P.Precision.MIXED if npd is np.float32 else P.Precision.FP64)
+        L, K1, K2 = d.deblur(to_dev(B1, dtype), to_dev(B2, dtype), c["m"], c["n"], lam=c["lam"])
+        torch.cuda.synchronize()
+        Lo, R1, R2 = orc.deblur(B1.astype(np.float64), B2.astype(np.float64), c["m"], c["n"], 0, c["lam"])
+        e1 = rel(K1.cpu().numpy(), R1)
+        p = psnr(L.cpu().numpy(), Lo)
+        print(f"bench workload {dtype}: kernel rel-L2 {e1:.2e}, latent PSNR vs oracle {p:.1f} dB")
+        assert e1 <= ktol and rel(K2.cpu().numpy(), R2) <= ktol
+        assert p >= 60
+
+
+def test_batch_matches_single_calls(P):
+    frames = []
+    for f, (m, n, k1, k2) in enumerate([(40, 50, 3, 5), (64, 64, 5, 5), (31, 77, 7, 4)]):
+        r = synth.rng_for(555, f)
+        L = r.random((m, n))
+        K1, K2 = synth.draw_coprime_pair(r, k1, k2, "uniform")
+        frames.append((to_dev(synth.full_conv2d(L, K1), torch.float64),
+                       to_dev(synth.full_conv2d(L, K2), torch.float64), m, n))
+    Ls, K1s, K2s, st = P.deblur_batch(frames)
+    torch.cuda.synchronize()
+    assert st == [0, 0, 0]
+    for (b1, b2, m, n), L, K1 in zip(frames, Ls, K1s):
+        L1, J1, J2 = P.deblur(b1, b2, m, n)
+        assert torch.equal(L1, L) and torch.equal(J1, K1)
+
+
+def test_repeated_calls_are_bitwise_identical(P):
+    c = synth.config2(noise=1e-3)
+    b1 = to_dev(c["B1"].astype(np.float32), torch.float32)
+    b2 = to_dev(c["B2"].astype(np.float32), torch.float32)
+    d = P.Deblurrer(490, 650, 11, precision=P.Precision.MIXED)
+    La, K1a, _ = d.deblur(b1, b2, 480, 640, lam=1e-4)
+    La = La.clone(); K1a = K1a.clone()
+    Lb, K1b, _ = d.deblur(b1, b2, 480, 640, lam=1e-4)
+    torch.cuda.synchronize()
+    assert torch.equal(La, Lb) and torch.equal(K1a, K1b)
+
+
+def test_host_validation_errors_on_device(P):
+    c = synth.config1()
+    b1, b2 = to_dev(c["B1"], torch.float64), to_dev(c["B2"], torch.float64)
+    d = P.Deblurrer(68, 68, 5)
+    with pytest.raises(P.CbpError) as e:
+        d.deblur(b1, b2, 65, 64)            # latent inconsistent with the frames
+    assert e.value.status == 2
+    with pytest.raises(P.CbpError) as e:
+        d.deblur(b1, b2[:, :-1], 64, 64)    # W1 - W2 != H1 - H2
+    assert e.value.status == 2
+    small = P.Deblurrer(20, 20, 3)
+    with pytest.raises(P.CbpError) as e:
+        small.deblur(b1, b2, 64, 64)        # workspace too small
+    assert e.value.status == 5
