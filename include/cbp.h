@@ -106,10 +106,13 @@ typedef struct cbp_options {
 typedef struct cbp_diag {
   int32_t k1, k2, S, n;                      /* sizes used: n = k1 + k2 */
   int32_t flags;                             /* CBP_DIAG_* */
+  int32_t refine_sample;                     /* most Newton refinement steps over the per-sample eigen-solves */
+  int32_t refine_scale;                      /* Newton refinement steps of the scale-system eigen-solve */
   int32_t reserved;
   double  sample_lambda0[2][CBP_MAX_S];      /* Rayleigh quotient of each null vector (pass X, pass Y) */
+  double  sample_lambda1[2][CBP_MAX_S];      /* second smallest eigenvalue of each per-sample Gram */
   double  sample_scale[2][CBP_MAX_S];        /* largest Gram diagonal entry of each sample */
-  double  scale_lambda0, scale_scale;        /* same two figures for the scale system */
+  double  scale_lambda0, scale_lambda1, scale_scale;  /* the same three figures for the scale system */
   double  kernel_imag[2];                    /* ||Im K|| / ||Re K|| after normalisation */
   double  kernel_outside[2];                 /* energy fraction of the S x S inverse DFT outside the k x k support */
   double  sample_vec[2][CBP_MAX_S][CBP_MAX_N][2];  /* unit null vectors x = (u: k2 entries, v: k1 entries) */

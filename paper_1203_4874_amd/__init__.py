@@ -62,10 +62,13 @@ class CbpOptions(ctypes.Structure):
 
 class CbpDiag(ctypes.Structure):
     _fields_ = [("k1", ctypes.c_int32), ("k2", ctypes.c_int32), ("S", ctypes.c_int32), ("n", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("refine_sample", ctypes.c_int32),
+                ("refine_scale", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("sample_lambda0", ctypes.c_double * CBP_MAX_S * 2),
+                ("sample_lambda1", ctypes.c_double * CBP_MAX_S * 2),
                 ("sample_scale", ctypes.c_double * CBP_MAX_S * 2),
-                ("scale_lambda0", ctypes.c_double), ("scale_scale", ctypes.c_double),
+                ("scale_lambda0", ctypes.c_double), ("scale_lambda1", ctypes.c_double),
+                ("scale_scale", ctypes.c_double),
                 ("kernel_imag", ctypes.c_double * 2), ("kernel_outside", ctypes.c_double * 2),
                 ("sample_vec", ctypes.c_double * 2 * CBP_MAX_N * CBP_MAX_S * 2),
                 ("scale_vec", ctypes.c_double * 2 * (2 * CBP_MAX_S)),
@@ -174,10 +177,12 @@ def decode_diag(buf: np.ndarray) -> dict:
     sv = np.ctypeslib.as_array(d.sample_vec).reshape(2, CBP_MAX_S, CBP_MAX_N, 2)
     kh = np.ctypeslib.as_array(d.khat).reshape(2, CBP_MAX_S, CBP_MAX_S, 2)
     scv = np.ctypeslib.as_array(d.scale_vec).reshape(2 * CBP_MAX_S, 2)
-    return dict(k1=d.k1, k2=d.k2, S=S, n=n, flags=d.flags,
+    return dict(k1=d.k1, k2=d.k2, S=S, n=n, flags=d.flags, refine_sample=d.refine_sample,
+                refine_scale=d.refine_scale,
                 sample_lambda0=np.ctypeslib.as_array(d.sample_lambda0).reshape(2, CBP_MAX_S)[:, :S].copy(),
+                sample_lambda1=np.ctypeslib.as_array(d.sample_lambda1).reshape(2, CBP_MAX_S)[:, :S].copy(),
                 sample_scale=np.ctypeslib.as_array(d.sample_scale).reshape(2, CBP_MAX_S)[:, :S].copy(),
-                scale_lambda0=d.scale_lambda0, scale_scale=d.scale_scale,
+                scale_lambda0=d.scale_lambda0, scale_lambda1=d.scale_lambda1, scale_scale=d.scale_scale,
                 kernel_imag=list(d.kernel_imag), kernel_outside=list(d.kernel_outside),
                 sample_vec=(sv[:, :S, :n, 0] + 1j * sv[:, :S, :n, 1]).copy(),
                 scale_vec=(scv[:2 * S, 0] + 1j * scv[:2 * S, 1]).copy(),

@@ -11,7 +11,7 @@
 //   rho_ab(l) = sum_t conj(a[t]) b[t + l],
 // so only 2(k1+k2)-1 correlations are formed, each accumulated in
 // double-double (Dot2).  The null vector x = (u, v) is the eigenvector of the
-// smallest eigenvalue of G (eig.h).
+// smallest eigenvalue of G (eigsmall.h).
 //
 // Scale fix (Sec. 4: combine the two evaluation orders by least squares;
 // Sec. 5: 2t unknowns over t x t equations): with the cofactors evaluated on
@@ -24,7 +24,7 @@
 // Assembly (Sec. 5, abstract): Khat_c = (a_j P_c + b_i Q_c) / 2, inverse
 // S x S DFT, crop to the k_c x k_c support, divide by the complex sum over
 // the support and keep the real part.
-#include "eig.h"
+#include "eigsmall.h"
 #include "internal.h"
 
 namespace cbp {
@@ -123,69 +123,68 @@ __global__ __launch_bounds__(256) void k_gram(const c64* ex, const c64* ey, int 
   if (tid == 0) corr[((size_t)pass * S + j) * NL + li] = cdd{rre[0], rim[0]};
 }
 
-// Smallest eigenvector of every per-sample Gram.  grid (S, 2), 256 threads.
-__global__ __launch_bounds__(EIG_NT) void k_sample(const cdd* corr, int S, int k1, int k2, c64* xout,
-                                                   double* lam0, cbp_diag* diag) {
+// Smallest eigenvector of every per-sample Gram.  grid (S, 2), one wave each.
+__global__ __launch_bounds__(SMALL_NT) void k_sample(const cdd* corr, int S, int k1, int k2, c64* xout,
+                                                     double* lam0, cbp_diag* diag) {
   extern __shared__ __attribute__((aligned(16))) char sm_sample[];
   const int N = k1 + k2, NL = 2 * N - 1;
   const int j = blockIdx.x, pass = blockIdx.y;
-  const int tid = threadIdx.x;
+  const int l = threadIdx.x;
   cdd* rho = (cdd*)sm_sample;
-  eig_ws w = eig_carve(sm_sample + (((size_t)NL * sizeof(cdd) + 15) & ~(size_t)15), N);
-  for (int l = tid; l < NL; l += EIG_NT) rho[l] = corr[((size_t)pass * S + j) * NL + l];
+  small_ws w = small_carve(sm_sample + (((size_t)NL * sizeof(cdd) + 15) & ~(size_t)15), N);
+  for (int t = l; t < NL; t += SMALL_NT) rho[t] = corr[((size_t)pass * S + j) * NL + t];
   __syncthreads();
   const gram_acc G{rho, k1, k2};
-  for (int e = tid; e < N * N; e += EIG_NT) {
+  for (int e = l; e < N * N; e += SMALL_NT) {
     const int i = e / N, c = e - i * N;
     const cdd g = G.get(i, c);
     w.A[e] = {g.re.hi, g.im.hi};
   }
+  const double gmax = wmax(l < N ? dd_val(G.get(l, l).re) : 0.0);
   __syncthreads();
-  double gmax = 0.0;
-  if (tid == 0)
-    for (int i = 0; i < N; ++i) gmax = fmax(gmax, w.A[i * N + i].re);
-  jacobi_eig(w, N);
-  double second;
-  const int im = eig_argmin(w, N, &second);
-  const dd mu = eig_refine(w, G, N, im);
+  double lam1;
+  int steps;
+  const dd mu = small_eig(w, G, N, &lam1, &steps);
   const size_t base = ((size_t)pass * S + j) * N;
-  bool bad = false;
-  for (int i = tid; i < N; i += EIG_NT) {
-    const c64 xi = w.x[i];
-    xout[base + i] = xi;
-    if (!finite_c(xi)) bad = true;
+  const c64 xi = l < N ? w.x[l] : c64{0.0, 0.0};
+  if (l < N) {
+    xout[base + l] = xi;
     if (diag) {
-      diag->sample_vec[pass][j][i][0] = xi.re;
-      diag->sample_vec[pass][j][i][1] = xi.im;
+      diag->sample_vec[pass][j][l][0] = xi.re;
+      diag->sample_vec[pass][j][l][1] = xi.im;
     }
   }
-  if (bad && diag) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
-  if (tid == 0) {
+  const bool bad = wmax(l < N && !finite_c(xi) ? 1.0 : 0.0) > 0.0;
+  if (l == 0) {
     const double l0 = dd_val(mu);
     lam0[pass * S + j] = l0;
     if (diag) {
       diag->sample_lambda0[pass][j] = l0;
+      diag->sample_lambda1[pass][j] = lam1;
       diag->sample_scale[pass][j] = gmax;
-      if (!(second - l0 > 1e-13 * gmax)) atomicOr(&diag->flags, CBP_DIAG_SAMPLE_WEAK);
+      atomicMax(&diag->refine_sample, steps);
+      if (!(lam1 - l0 > 1e-13 * gmax)) atomicOr(&diag->flags, CBP_DIAG_SAMPLE_WEAK);
+      if (bad || !isfinite(l0)) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
     }
   }
 }
 
-// Scale fix, assembly, inverse DFT and normalisation.  One workgroup.
-__global__ __launch_bounds__(EIG_NT) void k_finalize(const c64* xvec, int S, int k1, int k2, c64* pq, cdd* cbuf,
-                                                     double* K1, double* K2, cbp_diag* diag) {
+// Scale fix, assembly, inverse DFT and normalisation.  One wave.
+__global__ __launch_bounds__(SMALL_NT) void k_finalize(const c64* xvec, int S, int k1, int k2, c64* pq, cdd* cbuf,
+                                                       double* K1, double* K2, cbp_diag* diag) {
   extern __shared__ __attribute__((aligned(16))) char sm_fin[];
   const int N = k1 + k2, n2 = 2 * S, SS = S * S;
   const int tid = threadIdx.x;
   c64* tw = (c64*)sm_fin;                        // S
   dd* Da = (dd*)(tw + CBP_MAX_S);                // S
   dd* Db = Da + CBP_MAX_S;                       // S
-  c64* sums = (c64*)(Db + CBP_MAX_S);            // 2
-  eig_ws w = eig_carve((char*)(sums + 4), n2);
+  c64* kbuf = (c64*)(Db + CBP_MAX_S);            // 2 S^2: averaged spectra, then the S x S inverse DFTs
+  c64* tbuf = kbuf + 2 * CBP_MAX_S * CBP_MAX_S;  // 2 S^2: half-transformed spectra
+  small_ws w = small_carve((char*)(tbuf + 2 * CBP_MAX_S * CBP_MAX_S), n2);
   unit_twiddles(tw, S);
   __syncthreads();
   // cofactors evaluated on the other axis: pq = [P1, P2, Q1, Q2], each [i][j]
-  for (int e = tid; e < 4 * SS; e += EIG_NT) {
+  for (int e = tid; e < 4 * SS; e += SMALL_NT) {
     const int which = e / SS, ij = e - which * SS;
     const int i = ij / S, jj = ij - i * S;
     const c64* xs;
@@ -206,7 +205,7 @@ __global__ __launch_bounds__(EIG_NT) void k_finalize(const c64* xvec, int S, int
   __threadfence_block();
   __syncthreads();
   // H blocks in double-double
-  for (int e = tid; e < SS; e += EIG_NT) {
+  for (int e = tid; e < SS; e += SMALL_NT) {
     const int jj = e / S, i = e - jj * S;
     dot2 re, im;
     re.init();
@@ -218,7 +217,7 @@ __global__ __launch_bounds__(EIG_NT) void k_finalize(const c64* xvec, int S, int
     }
     cbuf[e] = cdd{re.result(), im.result()};
   }
-  for (int t = tid; t < n2; t += EIG_NT) {
+  for (int t = tid; t < n2; t += SMALL_NT) {
     dot2 d;
     d.init();
     if (t < S) {
@@ -241,34 +240,33 @@ __global__ __launch_bounds__(EIG_NT) void k_finalize(const c64* xvec, int S, int
   __threadfence_block();
   __syncthreads();
   const scale_acc H{Da, Db, cbuf, S};
-  for (int e = tid; e < n2 * n2; e += EIG_NT) {
+  for (int e = tid; e < n2 * n2; e += SMALL_NT) {
     const int r = e / n2, c = e - r * n2;
     const cdd h = H.get(r, c);
     w.A[e] = {h.re.hi, h.im.hi};
   }
+  const double hmax = wmax(tid < n2 ? dd_val(H.get(tid, tid).re) : 0.0);
   __syncthreads();
-  double hmax = 0.0;
-  if (tid == 0)
-    for (int i = 0; i < n2; ++i) hmax = fmax(hmax, w.A[i * n2 + i].re);
-  jacobi_eig(w, n2);
-  double second;
-  const int im = eig_argmin(w, n2, &second);
-  const dd mu = eig_refine(w, H, n2, im);
+  double lam1;
+  int steps;
+  const dd mu = small_eig(w, H, n2, &lam1, &steps);
   if (tid == 0 && diag) {
     diag->k1 = k1; diag->k2 = k2; diag->S = S; diag->n = N;
     diag->scale_lambda0 = dd_val(mu);
+    diag->scale_lambda1 = lam1;
     diag->scale_scale = hmax;
-    if (!(second - dd_val(mu) > 1e-13 * hmax)) atomicOr(&diag->flags, CBP_DIAG_SCALE_WEAK);
+    diag->refine_scale = steps;
+    if (!(lam1 - dd_val(mu) > 1e-13 * hmax)) atomicOr(&diag->flags, CBP_DIAG_SCALE_WEAK);
   }
   if (diag)
-    for (int t = tid; t < n2; t += EIG_NT) {
+    for (int t = tid; t < n2; t += SMALL_NT) {
       diag->scale_vec[t][0] = w.x[t].re;
       diag->scale_vec[t][1] = w.x[t].im;
     }
-  // averaged spectra Kh[c][i][j] (into w.A, 2 S^2 <= n2^2 entries)
-  c64* Kh = w.A;
-  c64* Tm = w.V;
-  for (int e = tid; e < 2 * SS; e += EIG_NT) {
+  // averaged spectra Kh[c][i][j]
+  c64* Kh = kbuf;
+  c64* Tm = tbuf;
+  for (int e = tid; e < 2 * SS; e += SMALL_NT) {
     const int c = e / SS, ij = e - c * SS;
     const int i = ij / S, jj = ij - i * S;
     const c64 P = pq[(size_t)c * SS + ij], Q = pq[(size_t)(2 + c) * SS + ij];
@@ -281,7 +279,7 @@ __global__ __launch_bounds__(EIG_NT) void k_finalize(const c64* xvec, int S, int
   }
   __syncthreads();
   // inverse DFT along x: Tm[c][j][x] = sum_i Kh[c][i][j] w_i^{-x}
-  for (int e = tid; e < 2 * SS; e += EIG_NT) {
+  for (int e = tid; e < 2 * SS; e += SMALL_NT) {
     const int c = e / SS, jx = e - c * SS;
     const int jj = jx / S, x = jx - jj * S;
     c64 acc = {0.0, 0.0};
@@ -295,7 +293,7 @@ __global__ __launch_bounds__(EIG_NT) void k_finalize(const c64* xvec, int S, int
   }
   __syncthreads();
   // inverse DFT along y: Kf[c][y][x] = sum_j w_j^{-y} Tm[c][j][x]   (into Kh)
-  for (int e = tid; e < 2 * SS; e += EIG_NT) {
+  for (int e = tid; e < 2 * SS; e += SMALL_NT) {
     const int c = e / SS, yx = e - c * SS;
     const int y = yx / S, x = yx - y * S;
     c64 acc = {0.0, 0.0};
@@ -311,21 +309,21 @@ __global__ __launch_bounds__(EIG_NT) void k_finalize(const c64* xvec, int S, int
   for (int c = 0; c < 2; ++c) {
     const int k = c == 0 ? k1 : k2;
     double sr = 0.0, si = 0.0, ein = 0.0, eall = 0.0;
-    for (int e = tid; e < SS; e += EIG_NT) {
+    for (int e = tid; e < SS; e += SMALL_NT) {
       const int y = e / S, x = e - y * S;
       const c64 v = Kh[(size_t)c * SS + e];
       const double p = norm2(v);
       eall += p;
       if (y < k && x < k) { sr += v.re; si += v.im; ein += p; }
     }
-    sr = block_sum(sr, w.red);
-    si = block_sum(si, w.red);
-    ein = block_sum(ein, w.red);
-    eall = block_sum(eall, w.red);
+    sr = wsum(sr);
+    si = wsum(si);
+    ein = wsum(ein);
+    eall = wsum(eall);
     const double s2 = sr * sr + si * si;
     double* K = c == 0 ? K1 : K2;
     double re2 = 0.0, im2 = 0.0;
-    for (int e = tid; e < k * k; e += EIG_NT) {
+    for (int e = tid; e < k * k; e += SMALL_NT) {
       const int y = e / k, x = e - y * k;
       const c64 v = Kh[(size_t)c * SS + y * S + x];
       const double kr = (v.re * sr + v.im * si) / s2;
@@ -334,8 +332,8 @@ __global__ __launch_bounds__(EIG_NT) void k_finalize(const c64* xvec, int S, int
       re2 += kr * kr;
       im2 += ki * ki;
     }
-    re2 = block_sum(re2, w.red);
-    im2 = block_sum(im2, w.red);
+    re2 = wsum(re2);
+    im2 = wsum(im2);
     if (tid == 0 && diag) {
       diag->kernel_imag[c] = sqrt(im2) / fmax(sqrt(re2), 1e-300);
       diag->kernel_outside[c] = (eall - ein) / fmax(eall, 1e-300);
@@ -346,18 +344,22 @@ __global__ __launch_bounds__(EIG_NT) void k_finalize(const c64* xvec, int S, int
 }
 
 __global__ void k_diag_init(cbp_diag* diag) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) diag->flags = 0;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    diag->flags = 0;
+    diag->refine_sample = 0;
+    diag->refine_scale = 0;
+  }
 }
 
 }  // namespace
 
 size_t finalize_lds_bytes(int S) {
-  return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) + 4 * sizeof(c64) +
-         eig_lds_bytes(2 * S);
+  return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) +
+         4 * (size_t)CBP_MAX_S * CBP_MAX_S * sizeof(c64) + small_lds_bytes(2 * S);
 }
 
 size_t sample_lds_bytes(int N) {
-  return ((((size_t)(2 * N - 1) * sizeof(cdd)) + 15) & ~(size_t)15) + eig_lds_bytes(N);
+  return ((((size_t)(2 * N - 1) * sizeof(cdd)) + 15) & ~(size_t)15) + small_lds_bytes(N);
 }
 
 hipError_t launch_recover(const frame_plan& fp, char* ws, double* K1, double* K2, void* diagp, hipStream_t st) {
@@ -374,17 +376,17 @@ hipError_t launch_recover(const frame_plan& fp, char* ws, double* K1, double* K2
   cdd* corr = (cdd*)(ws + fp.off_corr);
   c64* xvec = (c64*)(ws + fp.off_xvec);
   double* lam0 = (double*)(ws + fp.off_lam0);
-  if (diag) hipLaunchKernelGGL(k_diag_init, dim3(1), dim3(64), 0, st, diag);
+  if (diag) hipLaunchKernelGGL(k_diag_init, dim3(1), dim3(256), 0, st, diag);
   prof_begin(PH_GRAM, st);
   hipLaunchKernelGGL(k_gram, dim3(2 * N - 1, S, 2), dim3(256), 0, st, ex, ey, fp.Wmax, fp.Hmax, fp.W1, fp.W2, fp.H1,
                      fp.H2, S, fp.k1, fp.k2, fp.nch, corr);
   prof_end(PH_GRAM, st);
   prof_begin(PH_SAMPLE, st);
-  hipLaunchKernelGGL(k_sample, dim3(S, 2), dim3(EIG_NT), sample_lds_bytes(N), st, corr, S, fp.k1, fp.k2, xvec,
+  hipLaunchKernelGGL(k_sample, dim3(S, 2), dim3(SMALL_NT), sample_lds_bytes(N), st, corr, S, fp.k1, fp.k2, xvec,
                      lam0, diag);
   prof_end(PH_SAMPLE, st);
   prof_begin(PH_FINALIZE, st);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(EIG_NT), finalize_lds_bytes(S), st, xvec, S, fp.k1, fp.k2,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(SMALL_NT), finalize_lds_bytes(S), st, xvec, S, fp.k1, fp.k2,
                      (c64*)(ws + fp.off_pq), (cdd*)(ws + fp.off_cbuf), K1, K2, diag);
   prof_end(PH_FINALIZE, st);
   return hipGetLastError();

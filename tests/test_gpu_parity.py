@@ -95,8 +95,10 @@ def test_recover_config2_fp64(P, noise):
     K1, K2, diag = P.recover_kernels(b1, b2, c["m"], c["n"], diag=True)
     R1, R2, full = orc.recover_kernels(c["B1"], c["B2"], c["m"], c["n"], full=True)
     e1, e2 = rel(K1.cpu().numpy(), R1), rel(K2.cpu().numpy(), R2)
-    print(f"config2 fp64 noise={noise}: kernel rel-L2 vs oracle {e1:.2e} {e2:.2e}")
+    print(f"config2 fp64 noise={noise}: kernel rel-L2 vs oracle {e1:.2e} {e2:.2e}; refinement steps "
+          f"{diag['refine_sample']}/{diag['refine_scale']}")
     assert e1 <= 1e-6 and e2 <= 1e-6
+    _check_samples(diag, full, tol=1e-9)
 
 
 @pytest.mark.parametrize("noise", [0.0, 1e-3])
