@@ -1,0 +1,91 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+entry point declared in include/cbp.h, the diag record layout matches the
+binding, the workspace size is monotone, and host-side validation returns
+its error codes before any device work (the pointers passed here are never
+dereferenced)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1203_4874_amd as P
+    if not os.path.exists(P.library_path):
+        pytest.fail("libcbp.so is not built (run python -m paper_1203_4874_amd.build)")
+    return P
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "cbp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cbp_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(P):
+    L = P.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(P._SIGS), "binding signatures must cover exactly the header"
+
+
+def test_version_status_and_diag_layout(P):
+    L = P.lib()
+    assert L.cbp_version().decode().count(".") == 2
+    assert L.cbp_status_string(0) == b"ok"
+    assert L.cbp_status_string(5) == b"workspace too small"
+    assert L.cbp_diag_size() == ctypes.sizeof(P.CbpDiag)
+
+
+def test_workspace_size_monotone_and_invalid(P):
+    a = P.workspace_size(490, 650, 11)
+    assert a > 0
+    assert P.workspace_size(720, 1300, 15) > a
+    assert P.workspace_size(490, 650, 11, batch=4) == 4 * a
+    assert P.workspace_size(490, 650, 33) == 0
+    assert P.workspace_size(0, 650, 11) == 0
+
+
+def _img(ptr, dtype, h, w, c=1):
+    return P_.CbpImage(ptr, dtype, h, w, c, w, h * w)
+
+
+def test_host_validation_codes(P):
+    global P_
+    P_ = P
+    L = P.lib()
+    i1, i2 = _img(0x1000, 0, 488, 648), _img(0x2000, 0, 490, 650)
+    lat = _img(0x3000, 0, 480, 640)
+    o = P.CbpOptions()
+    o.precision = P.Precision.MIXED
+    call = lambda a, b, c, opts: L.cbp_deblur(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), None, None,
+                                              ctypes.byref(opts))
+    assert call(i1, i2, lat, o) == 5                       # no workspace
+    assert call(i1, i2, _img(0x3000, 0, 481, 640), o) == 2  # latent inconsistent with frames
+    assert call(i1, _img(0x2000, 0, 490, 651), lat, o) == 2  # H1-H2 != W1-W2
+    assert call(i1, i2, _img(0x3000, 1, 480, 640), o) == 1  # latent dtype differs
+    o.samples = 5                                           # S < max k
+    assert call(i1, i2, lat, o) == 1
+    o.samples = 0
+    o.lambda_ = -1.0
+    assert call(i1, i2, lat, o) == 1
+    o.lambda_ = 0.0
+    o.precision = P.Precision.FP64                          # FP64 form needs FP64 frames
+    assert call(i1, i2, lat, o) == 1
+    o.precision = P.Precision.BF16
+    assert call(i1, i2, lat, o) == 6
+    o.precision = P.Precision.MIXED
+    o.learned = 1
+    assert call(i1, i2, lat, o) == 6
+    o.learned = 0
+    big = _img(0x1000, 0, 488 + 40, 648 + 40)               # k = 41 > 32
+    assert call(big, _img(0x2000, 0, 490 + 40, 650 + 40), _img(0x3000, 0, 480, 640), o) == 2
+    assert call(_img(0, 0, 488, 648), i2, lat, o) == 1      # null data pointer
+    assert L.cbp_deblur(None, ctypes.byref(i2), ctypes.byref(lat), None, None, ctypes.byref(o)) == 1

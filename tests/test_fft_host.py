@@ -1,0 +1,61 @@
+"""The HIP path's Stockham FFT passes (csrc/fft_core.h), compiled for the host
+with g++ and run through tests/host/fft_driver.cpp, against numpy.fft."""
+
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("fft") / "fft_driver")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_1203_4874_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "fft_driver.cpp"), "-o", exe], check=True)
+    return exe
+
+
+def run(exe, x, direction):
+    inp = f"{len(x)} {direction}\n" + "\n".join(f"{float(v.real)!r} {float(v.imag)!r}" for v in x)
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    return np.array([complex(*map(float, line.split())) for line in out.strip().split("\n")])
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 7, 8, 12, 35, 49, 64, 490, 672, 1120, 1792, 1944, 2048])
+def test_stockham_matches_numpy(driver, N):
+    r = np.random.default_rng(N)
+    x = r.standard_normal(N) + 1j * r.standard_normal(N)
+    y = run(driver, x, -1)
+    assert np.abs(y - np.fft.fft(x)).max() <= 1e-14 * max(1.0, np.abs(np.fft.fft(x)).max())
+    z = run(driver, x, +1)
+    assert np.abs(z - N * np.fft.ifft(x)).max() <= 1e-14 * max(1.0, np.abs(N * np.fft.ifft(x)).max())
+
+
+def test_non_smooth_size_has_no_plan(driver):
+    out = subprocess.run([driver], input="11 -1\n" + "0 0\n" * 11, capture_output=True, text=True)
+    assert "BADPLAN" in out.stdout
+
+
+def test_radix_constants():
+    """The odd-radix cosines / sines written in csrc/common.h."""
+    import re
+    import mpmath as mp
+    mp.mp.dps = 30
+    src = open(os.path.join(ROOT, "paper_1203_4874_amd", "csrc", "common.h")).read()
+    vals = dict(re.findall(r"static constexpr double (\w+) = (-?[0-9.]+);", src))
+    for R in (3, 5, 7):
+        for k in range(1, (R - 1) // 2 + 1):
+            c = vals.get(f"c{R}_{k}")
+            s = vals.get(f"s{R}_{k}")
+            if c is not None:
+                assert abs(mp.mpf(c) - mp.cos(2 * mp.pi * k / R)) < 1e-19
+            if s is not None:
+                assert abs(mp.mpf(s) - mp.sin(2 * mp.pi * k / R)) < 1e-19
+    assert abs(mp.mpf(vals["r2_2"]) - mp.sqrt(0.5)) < 1e-19
