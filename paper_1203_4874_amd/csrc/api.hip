@@ -45,7 +45,7 @@ region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
   const int Px = smooth7(Wmax);
   const size_t hx = (size_t)Px / 2 + 1;
   const size_t ncf = 2 * (size_t)nch;
-  r.fpart = ((size_t)(Hmax + 63) / 64 + 1) * ncf * S * (size_t)Wmax * sizeof(double);
+  r.fpart = ((size_t)(Hmax + 31) / 32 + 1) * ncf * S * (size_t)Wmax * sizeof(double);
   r.ex = ncf * S * (size_t)Wmax * sizeof(c64);
   r.ey = ncf * S * (size_t)Hmax * sizeof(c64);
   r.corr = 2 * (size_t)S * (4 * (size_t)kmax - 1) * sizeof(cdd);
@@ -81,10 +81,10 @@ size_t layout(frame_plan* fp, const region_sizes& r) {
 int max_fft(int esize) { return esize == 4 ? CBP_MAX_FFT_F32 : CBP_MAX_FFT_F64; }
 
 // Choose the column-pass strip width: as wide as LDS allows, but keep at
-// least ~256 workgroups per channel when the spectrum is narrow.
+// least ~128 workgroups per channel when the spectrum is narrow.
 int choose_cw(int Py, int hx, int esize) {
   int cw = 4;
-  while (cw > 1 && (col_lds_bytes(Py, cw, esize) > kLdsLimit - 4096 || (hx + cw - 1) / cw < 256)) cw >>= 1;
+  while (cw > 1 && (col_lds_bytes(Py, cw, esize) > kLdsLimit - 4096 || (hx + cw - 1) / cw < 128)) cw >>= 1;
   return cw;
 }
 
@@ -127,7 +127,7 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
   fp->Wmax = fp->W1 > fp->W2 ? fp->W1 : fp->W2;
   fp->m = m; fp->n = n; fp->k1 = k1; fp->k2 = k2; fp->S = S; fp->N = k1 + k2;
   fp->nch = b1->channels;
-  fp->rpg = S * ((64 + S - 1) / S);
+  fp->rpg = S * ((32 + S - 1) / S);
   fp->RG = (fp->Hmax + fp->rpg - 1) / fp->rpg;
   fp->Py = smooth7(fp->Hmax);
   fp->Px = smooth7(fp->Wmax);
@@ -186,6 +186,34 @@ profiler& prof() {
 const char* kPhaseNames[PH_COUNT] = {"fold_cols", "eval_cols", "eval_rows", "gram", "sample_eig",
                                      "scale_assemble", "row_fft_fwd", "col_fft_filter", "row_fft_inv"};
 
+// Side stream and fork/join events of one device (created once; default
+// priority).  The row fold and the row FFT depend only on the input frames,
+// so they run on the side stream beside the column fold -> Gram ->
+// eigen-solve chain, which occupies few compute units.
+struct fork_state {
+  std::mutex launch_mu;   // one launch sequence at a time per device (the events are shared)
+  bool ready = false;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_rows = nullptr, ev_fft = nullptr;
+};
+
+fork_state* get_fork() {
+  static std::mutex mu;
+  static fork_state states[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  fork_state& f = states[dev];
+  if (!f.ready) {
+    if (hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&f.ev_fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&f.ev_rows, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&f.ev_fft, hipEventDisableTiming) != hipSuccess) return nullptr;
+    f.ready = true;
+  }
+  return &f;
+}
+
 template <typename T>
 cbp_status run_frame(const cbp_image* b1, const cbp_image* b2, const frame_plan& fp, char* ws, double* K1,
                      double* K2, cbp_image* latent, const cbp_options* o, void* diag) {
@@ -193,11 +221,26 @@ cbp_status run_frame(const cbp_image* b1, const cbp_image* b2, const frame_plan&
   const pair_view<T> v = view_of<T>(b1, b2);
   double* k1 = K1 ? K1 : (double*)(ws + fp.off_kern);
   double* k2 = K2 ? K2 : (double*)(ws + fp.off_kern) + CBP_MAX_K * CBP_MAX_K;
-  if (launch_eval<T>(v, fp, ws, st) != hipSuccess) return CBP_E_DEVICE;
+  fork_state* f = get_fork();
+  if (!f) return CBP_E_DEVICE;
+  std::lock_guard<std::mutex> launch_lock(f->launch_mu);
+  hipStream_t side = f->side;
+  // fork
+  if (hipEventRecord(f->ev_fork, st) != hipSuccess) return CBP_E_DEVICE;
+  if (hipStreamWaitEvent(side, f->ev_fork, 0) != hipSuccess) return CBP_E_DEVICE;
+  if (launch_eval_rows<T>(v, fp, ws, side) != hipSuccess) return CBP_E_DEVICE;
+  if (hipEventRecord(f->ev_rows, side) != hipSuccess) return CBP_E_DEVICE;
+  if (latent && launch_row_fwd<T>(v, fp, ws, side) != hipSuccess) return CBP_E_DEVICE;
+  if (hipEventRecord(f->ev_fft, side) != hipSuccess) return CBP_E_DEVICE;
+  // main chain
+  if (launch_eval_cols<T>(v, fp, ws, st) != hipSuccess) return CBP_E_DEVICE;
+  if (hipStreamWaitEvent(st, f->ev_rows, 0) != hipSuccess) return CBP_E_DEVICE;
   if (launch_recover(fp, ws, k1, k2, diag, st) != hipSuccess) return CBP_E_DEVICE;
+  // join (also when no latent is produced, so the side stream never runs ahead of the next call)
+  if (hipStreamWaitEvent(st, f->ev_fft, 0) != hipSuccess) return CBP_E_DEVICE;
   if (latent) {
     const int64_t ocs = latent->channels > 1 ? latent->channel_stride : 0;
-    if (launch_deconv<T>(v, fp, ws, k1, k2, (T*)latent->data, latent->pitch, ocs, o->lambda, st) != hipSuccess)
+    if (launch_col_inv<T>(v, fp, ws, k1, k2, (T*)latent->data, latent->pitch, ocs, o->lambda, st) != hipSuccess)
       return CBP_E_DEVICE;
   }
   return CBP_OK;
@@ -282,7 +325,7 @@ size_t cbp_workspace_size(int32_t maxH, int32_t maxW, int32_t maxk, int32_t chan
 cbp_status cbp_eval_unit_circle(const cbp_image* b, int32_t S, double* ex, double* ey, const cbp_options* opts) {
   if (!valid_image(b) || !ex || !ey || !opts) return CBP_E_INVALID;
   if (S < 1 || S > CBP_MAX_S) return CBP_E_INVALID;
-  const size_t need = ((size_t)(b->height + 63) / 64 + 1) * (size_t)S * b->width * sizeof(double);
+  const size_t need = ((size_t)(b->height + 31) / 32 + 1) * (size_t)S * b->width * sizeof(double);
   if (!opts->workspace || opts->workspace_bytes < need) return CBP_E_NOMEM;
   const hipError_t e = launch_eval_single(b->data, b->dtype, b->pitch, b->height, b->width, S,
                                           (char*)opts->workspace, ex, ey, (hipStream_t)opts->stream);

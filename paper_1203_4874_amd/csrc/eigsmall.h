@@ -1,26 +1,31 @@
 // Smallest eigenpair of a small Hermitian matrix (n <= 64) in one wave.
 //
 //  1. Householder reduction of the FP64 matrix to a Hermitian tridiagonal
-//     Q^H G Q, then a diagonal unitary D that makes it real: T = D^H Q^H G Q D
-//     with diagonal a_k and off-diagonal b_k = |e_k| >= 0 (Golub & Van Loan,
-//     "Matrix Computations", Sec. 8.3.1).
-//  2. The two smallest eigenvalues of T by Sturm-count multisection: the
-//     number of negative pivots of the LDL^T factorisation of T - s I is the
-//     number of eigenvalues below s (Sylvester's law of inertia); 32 lanes
-//     each probe one point of the current bracket per round, 12 rounds.
-//  3. sigma = lam0 - max(1e-3 (lam1 - lam0), 16 n eps ||T||), so that
-//     G - sigma I is positive definite with its smallest eigenvalue well
-//     separated; its inverse M by Gauss-Jordan elimination (no pivoting is
-//     needed for a positive definite matrix).
-//  4. Shifted inverse iteration x <- M x / ||M x|| (error shrinks by
+//     (Golub & Van Loan, "Matrix Computations", Sec. 8.3.1); with a diagonal
+//     unitary it becomes the real tridiagonal T (diagonal a_k, off-diagonal
+//     b_k = |e_k|), which has the same eigenvalues.
+//  2. The smallest eigenvalue of T by Sturm-count multisection: the number of
+//     negative pivots of the LDL^T factorisation of T - s I is the number of
+//     eigenvalues below s (Sylvester's law of inertia).  64 probes per round,
+//     8 rounds, leave a bracket [lo, hi] of width ~6e-15 ||T||.
+//  3. sigma = lo - 16 n eps ||T|| < lam0, so B = G - sigma I is positive
+//     definite with its smallest eigenvalue well separated from the rest;
+//     M = B^{-1} by Gauss-Jordan elimination (no pivoting is needed for a
+//     positive definite matrix).
+//  4. Inverse iteration x <- M x / ||M x|| (error shrinks by
 //     (lam0 - sigma) / (lam1 - sigma) per step).
 //  5. Newton refinement against G held in double-double:
 //       r = G x - mu x (mu = x^H G x, both double-double),
 //       x <- (x - M r) / ||x - M r||,
-//     until ||M r|| < 1e-15; M r approximates the exact Newton correction
-//     sum_k v_k (v_k^H r) / (lam_k - mu) with relative error
-//     (mu - sigma) / (lam_k - sigma) ~ 1e-3.
-// Everything runs in one wave of 64 lanes; matrices live in LDS.
+//     until the correction is below 4e-15; M r approximates the exact Newton
+//     step sum_k v_k (v_k^H r) / (lam_k - mu) with relative error
+//     (mu - sigma) / (lam_k - sigma).
+//
+// One lane holds one vector entry (n <= 64); matrices live in LDS.  Wave
+// reductions use DPP lane permutations (quad_perm, half-row and row mirrors,
+// row broadcasts of lanes 15 and 31) and a read of lane 63, which keeps them
+// in the vector ALU instead of the LDS permute path.  LDS loads of a loop are
+// issued in batches before their uses so their latency overlaps.
 #pragma once
 
 #include "common.h"
@@ -29,36 +34,34 @@ namespace cbp {
 
 constexpr int SMALL_NT = 64;
 constexpr int SMALL_REFINE_MAX = 4;
-constexpr int SMALL_INVIT = 5;
-constexpr int SMALL_BISECT_ROUNDS = 12;
+constexpr int SMALL_INVIT = 4;
+constexpr int SMALL_BISECT_ROUNDS = 8;
 
 struct small_ws {
-  c64* A;       // n*n: Householder work matrix, then (G - sigma I)^{-1}
+  c64* A;       // n*n: matrix being reduced, then B, then M = B^{-1}
+  c64* e;       // n: complex off-diagonal of the Hermitian tridiagonal
+  c64* w;       // n: scratch (Householder vector / GJ column)
+  c64* u;       // n: scratch (Householder w / GJ row)
+  c64* x;       // n: result vector
   double* a;    // n: diagonal of T
   double* b;    // n: off-diagonal of T, b[k] = T[k+1][k]
-  c64* e;       // n: complex off-diagonal before the phase fix
-  c64* x;       // n: eigenvector estimate
-  c64* y;       // n: scratch vector
-  c64* r;       // n: scratch vector
-  double* red;  // 8 doubles
 };
 
 __host__ __device__ inline size_t small_lds_bytes(int n) {
-  return (size_t)n * n * sizeof(c64) + (size_t)n * (2 * sizeof(double) + 4 * sizeof(c64)) + 8 * sizeof(double) + 64;
+  return (size_t)n * n * sizeof(c64) + (size_t)n * (4 * sizeof(c64) + 2 * sizeof(double)) + 64;
 }
 
 __device__ inline small_ws small_carve(char* base, int n) {
-  small_ws w;
+  small_ws s;
   char* p = base;
-  w.A = (c64*)p; p += (size_t)n * n * sizeof(c64);
-  w.e = (c64*)p; p += n * sizeof(c64);
-  w.x = (c64*)p; p += n * sizeof(c64);
-  w.y = (c64*)p; p += n * sizeof(c64);
-  w.r = (c64*)p; p += n * sizeof(c64);
-  w.a = (double*)p; p += n * sizeof(double);
-  w.b = (double*)p; p += n * sizeof(double);
-  w.red = (double*)p;
-  return w;
+  s.A = (c64*)p; p += (size_t)n * n * sizeof(c64);
+  s.e = (c64*)p; p += n * sizeof(c64);
+  s.w = (c64*)p; p += n * sizeof(c64);
+  s.u = (c64*)p; p += n * sizeof(c64);
+  s.x = (c64*)p; p += n * sizeof(c64);
+  s.a = (double*)p; p += n * sizeof(double);
+  s.b = (double*)p;
+  return s;
 }
 
 // Reciprocal and reciprocal square root: hardware estimate + two Newton steps.
@@ -77,6 +80,70 @@ __device__ inline double rsq_nr(double x) {
   return y;
 }
 
+// ---------------------------------------------------------------- wave primitives
+template <int CTRL, int ROWMASK = 0xf>
+__device__ inline double dpp_d(double v, double old) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes (fixed order; the result is wave-uniform).
+__device__ inline double wsum(double v) {
+  v += dpp_d<0xB1>(v, 0.0);        // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v, 0.0);        // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v, 0.0);       // row_half_mirror
+  v += dpp_d<0x140>(v, 0.0);       // row_mirror
+  v += dpp_d<0x142, 0xa>(v, 0.0);  // row_bcast:15 into rows 1, 3
+  v += dpp_d<0x143, 0xc>(v, 0.0);  // row_bcast:31 into rows 2, 3
+  return readlane_d(v, 63);
+}
+
+__device__ inline double wmin(double v) {
+  const double inf = __builtin_inf();
+  v = fmin(v, dpp_d<0xB1>(v, inf));
+  v = fmin(v, dpp_d<0x4E>(v, inf));
+  v = fmin(v, dpp_d<0x141>(v, inf));
+  v = fmin(v, dpp_d<0x140>(v, inf));
+  v = fmin(v, dpp_d<0x142, 0xa>(v, inf));
+  v = fmin(v, dpp_d<0x143, 0xc>(v, inf));
+  return readlane_d(v, 63);
+}
+
+__device__ inline double wmax(double v) { return -wmin(-v); }
+
+__device__ inline c64 wsum_c(c64 v) {
+  v.re += dpp_d<0xB1>(v.re, 0.0);       v.im += dpp_d<0xB1>(v.im, 0.0);
+  v.re += dpp_d<0x4E>(v.re, 0.0);       v.im += dpp_d<0x4E>(v.im, 0.0);
+  v.re += dpp_d<0x141>(v.re, 0.0);      v.im += dpp_d<0x141>(v.im, 0.0);
+  v.re += dpp_d<0x140>(v.re, 0.0);      v.im += dpp_d<0x140>(v.im, 0.0);
+  v.re += dpp_d<0x142, 0xa>(v.re, 0.0); v.im += dpp_d<0x142, 0xa>(v.im, 0.0);
+  v.re += dpp_d<0x143, 0xc>(v.re, 0.0); v.im += dpp_d<0x143, 0xc>(v.im, 0.0);
+  return {readlane_d(v.re, 63), readlane_d(v.im, 63)};
+}
+
+template <int CTRL, int ROWMASK = 0xf>
+__device__ inline dd dpp_dd(dd v) {
+  return {dpp_d<CTRL, ROWMASK>(v.hi, 0.0), dpp_d<CTRL, ROWMASK>(v.lo, 0.0)};
+}
+
+// Double-double sum over the 64 lanes (dd_add at each level).
+__device__ inline dd wsum_dd(dd v) {
+  v = dd_add(v, dpp_dd<0xB1>(v));
+  v = dd_add(v, dpp_dd<0x4E>(v));
+  v = dd_add(v, dpp_dd<0x141>(v));
+  v = dd_add(v, dpp_dd<0x140>(v));
+  v = dd_add(v, dpp_dd<0x142, 0xa>(v));
+  v = dd_add(v, dpp_dd<0x143, 0xc>(v));
+  return {readlane_d(v.hi, 63), readlane_d(v.lo, 63)};
+}
+
 // (e / n, e % n) without an integer division (float estimate, corrected).
 __device__ inline void split_index(int e, int n, float rn, int& i, int& j) {
   i = (int)((float)e * rn);
@@ -85,110 +152,115 @@ __device__ inline void split_index(int e, int n, float rn, int& i, int& j) {
   else if (j < 0) { --i; j += n; }
 }
 
-// Wave-wide reductions (xor butterflies: every lane gets the same value).
-__device__ inline double wsum(double v) {
-  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
-__device__ inline double wmin(double v) {
-  for (int m = 32; m > 0; m >>= 1) v = fmin(v, __shfl_xor(v, m, 64));
-  return v;
-}
-__device__ inline double wmax(double v) {
-  for (int m = 32; m > 0; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
-  return v;
-}
-__device__ inline c64 wsum_c(c64 v) { return {wsum(v.re), wsum(v.im)}; }
-__device__ inline c64 shfl_c(c64 v, int src) { return {__shfl(v.re, src, 64), __shfl(v.im, src, 64)}; }
-
-__device__ inline dd wsum_dd(dd v) {
-  for (int m = 32; m > 0; m >>= 1) {
-    dd o;
-    o.hi = __shfl_xor(v.hi, m, 64);
-    o.lo = __shfl_xor(v.lo, m, 64);
-    v = dd_add(v, o);
-  }
-  return v;
-}
-
-// 1. Householder tridiagonalisation of w.A (n x n Hermitian, destroyed);
-//    leaves T in w.a, w.b.
-__device__ inline void small_tridiag(small_ws& w, int n) {
+// ---------------------------------------------------------------- 1. tridiagonal
+// Householder reduction of s.A (destroyed); T in s.a, s.b.
+__device__ inline void small_tridiag(small_ws& s, int n) {
   const int l = threadIdx.x;
+  c64* __restrict__ A = s.A;
+  c64* __restrict__ V = s.w;
+  c64* __restrict__ W = s.u;
   for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;       // length of the column below the diagonal
+    const int m = n - k - 1;
     const int o = k + 1;
     c64 xl = {0.0, 0.0};
-    if (l < m) xl = conj(w.A[k * n + o + l]);   // A[o+l][k] = conj(A[k][o+l])
+    if (l < m) xl = conj(A[k * n + o + l]);     // A[o+l][k]
     const double s2 = wsum(norm2(xl));
+    const double x0r = readlane_d(xl.re, 0), x0i = readlane_d(xl.im, 0);
+    const double ax0sq = x0r * x0r + x0i * x0i;
     const double tail = wsum(l >= 1 ? norm2(xl) : 0.0);
-    const c64 x0 = shfl_c(xl, 0);
-    if (!(tail > 0.0)) {                         // column already reduced
-      if (l == 0) w.e[k] = x0;
-      __syncthreads();
+    if (!(tail > 0.0)) {                        // column already reduced
+      if (l == 0) s.e[k] = {x0r, x0i};
       continue;
     }
-    const double nx = s2 * rsq_nr(s2);          // ||x||
-    const double ax0 = sqrt(norm2(x0));
-    const c64 ph = ax0 > 0.0 ? c64{x0.re / ax0, x0.im / ax0} : c64{1.0, 0.0};
+    const double nx = s2 * rsq_nr(s2);
+    const double ax0 = ax0sq > 0.0 ? ax0sq * rsq_nr(ax0sq) : 0.0;
+    const c64 ph = ax0 > 0.0 ? c64{x0r / ax0, x0i / ax0} : c64{1.0, 0.0};
     const c64 alpha = {-ph.re * nx, -ph.im * nx};
-    // v = sqrt(2) u / ||u||, u = x - alpha e_0, ||u||^2 = 2 ||x|| (||x|| + |x_0|)
-    const double sc = rsq_nr(nx * (nx + ax0));
+    const double sc = rsq_nr(nx * (nx + ax0));  // sqrt(2) / ||x - alpha e_0||
     c64 vl = {0.0, 0.0};
     if (l < m) {
       const c64 ul = (l == 0) ? c64{xl.re - alpha.re, xl.im - alpha.im} : xl;
       vl = {ul.re * sc, ul.im * sc};
-      w.x[l] = vl;
+      V[l] = vl;
     }
     __syncthreads();
-    // p = A' v with A' the trailing m x m block (read by columns: A'[l][j] = conj(A'[j][l]))
-    c64 pl = {0.0, 0.0};
-    if (l < m)
-      for (int j = 0; j < m; ++j) pl = pl + cmulc(w.A[(o + j) * n + o + l], w.x[j]);
+    // p = A' v (A' trailing m x m block; A'[l][j] = conj(A'[j][l]) read by column)
+    c64 p0 = {0.0, 0.0}, p1 = {0.0, 0.0};
+    if (l < m) {
+      const c64* col = A + (size_t)o * n + o + l;
+      int j = 0;
+      for (; j + 4 <= m; j += 4) {
+        const c64 a0 = col[(size_t)j * n], a1 = col[(size_t)(j + 1) * n];
+        const c64 a2 = col[(size_t)(j + 2) * n], a3 = col[(size_t)(j + 3) * n];
+        const c64 v0 = V[j], v1 = V[j + 1], v2 = V[j + 2], v3 = V[j + 3];
+        p0 = p0 + cmulc(a0, v0) + cmulc(a2, v2);
+        p1 = p1 + cmulc(a1, v1) + cmulc(a3, v3);
+      }
+      for (; j < m; ++j) p0 = p0 + cmulc(col[(size_t)j * n], V[j]);
+    }
+    const c64 pl = p0 + p1;
     const double K = 0.5 * wsum(l < m ? (vl.re * pl.re + vl.im * pl.im) : 0.0);  // Re(v^H p) / 2
     const c64 wl = {pl.re - K * vl.re, pl.im - K * vl.im};
-    if (l < m) w.y[l] = wl;
+    if (l < m) W[l] = wl;
     __syncthreads();
-    // A' -= v w^H + w v^H   (lane l rewrites column l)
+    // A' -= v w^H + w v^H   (lane l rewrites column l, four rows at a time)
     if (l < m) {
       const c64 cw = conj(wl), cv = conj(vl);
-      for (int j = 0; j < m; ++j) {
-        const c64 vj = w.x[j], wj = w.y[j];
-        const size_t id = (size_t)(o + j) * n + o + l;
-        w.A[id] = w.A[id] - vj * cw - wj * cv;
+      c64* col = A + (size_t)o * n + o + l;
+      int j = 0;
+      for (; j + 4 <= m; j += 4) {
+        c64 a0 = col[(size_t)j * n], a1 = col[(size_t)(j + 1) * n];
+        c64 a2 = col[(size_t)(j + 2) * n], a3 = col[(size_t)(j + 3) * n];
+        const c64 v0 = V[j], v1 = V[j + 1], v2 = V[j + 2], v3 = V[j + 3];
+        const c64 w0 = W[j], w1 = W[j + 1], w2 = W[j + 2], w3 = W[j + 3];
+        a0 = a0 - v0 * cw - w0 * cv;
+        a1 = a1 - v1 * cw - w1 * cv;
+        a2 = a2 - v2 * cw - w2 * cv;
+        a3 = a3 - v3 * cw - w3 * cv;
+        col[(size_t)j * n] = a0;
+        col[(size_t)(j + 1) * n] = a1;
+        col[(size_t)(j + 2) * n] = a2;
+        col[(size_t)(j + 3) * n] = a3;
+      }
+      for (; j < m; ++j) {
+        const c64 a0 = col[(size_t)j * n];
+        col[(size_t)j * n] = a0 - V[j] * cw - W[j] * cv;
       }
     }
-    if (l == 0) w.e[k] = alpha;
+    if (l == 0) s.e[k] = alpha;
     __syncthreads();
   }
-  if (l < n) w.a[l] = w.A[l * n + l].re;
-  if (l == 0 && n >= 2) w.e[n - 2] = w.A[(n - 1) * n + n - 2];
+  if (l < n) s.a[l] = A[l * n + l].re;
+  if (l == 0 && n >= 2) s.e[n - 2] = A[(n - 1) * n + n - 2];
   __syncthreads();
-  if (l < n - 1) w.b[l] = sqrt(norm2(w.e[l]));
-  if (l == n - 1) w.b[l] = 0.0;
+  if (l < n - 1) s.b[l] = sqrt(norm2(s.e[l]));
+  if (l == n - 1) s.b[l] = 0.0;
   __syncthreads();
 }
 
-// Number of eigenvalues of T below s (Sturm count).
-__device__ inline int sturm_count(const double* a, const double* b, int n, double s, double pivmin) {
-  double q = a[0] - s;
+// ---------------------------------------------------------------- 2. bisection
+// Number of eigenvalues of T below t (Sturm count).
+__device__ inline int sturm_count(const double* a, const double* b, int n, double t, double pivmin) {
+  double q = a[0] - t;
   int c = q < 0.0;
   for (int k = 1; k < n; ++k) {
     if (fabs(q) < pivmin) q = -pivmin;
-    q = a[k] - s - b[k - 1] * b[k - 1] * rcp_nr(q);
+    q = a[k] - t - b[k - 1] * b[k - 1] * rcp_nr(q);
     c += q < 0.0;
   }
   return c;
 }
 
-// 2. Two smallest eigenvalues of T (n >= 2; lanes 0-31 bracket lam0, 32-63 lam1).
-__device__ inline void small_bisect(small_ws& w, int n, double* lam0, double* lam1, double* tnorm) {
+// Bracket of the (target-1)-th smallest eigenvalue of T (target 1 or 2),
+// 64 probes per round.  Returns ||T|| (Gershgorin bound) in *tn.
+__device__ inline void small_bisect(const small_ws& s, int n, int target, double* lo_out, double* hi_out,
+                                    double* tn_out) {
   const int l = threadIdx.x;
   double glo = 1.7976931348623157e308, ghi = -1.7976931348623157e308, bmax = 0.0;
   if (l < n) {
-    const double bl = l > 0 ? w.b[l - 1] : 0.0, br = w.b[l];
-    glo = w.a[l] - bl - br;
-    ghi = w.a[l] + bl + br;
+    const double bl = l > 0 ? s.b[l - 1] : 0.0, br = s.b[l];
+    glo = s.a[l] - bl - br;
+    ghi = s.a[l] + bl + br;
     bmax = br;
   }
   glo = wmin(glo);
@@ -196,98 +268,138 @@ __device__ inline void small_bisect(small_ws& w, int n, double* lam0, double* la
   bmax = wmax(bmax);
   const double tn = fmax(fabs(glo), fabs(ghi));
   const double pivmin = fmax(bmax * bmax, 1e-280) * 1e-290 + 1e-300;
-  const int g = l >> 5, j = l & 31;
-  const int target = g + 1;                       // need count >= target
   double lo = glo - 2.2e-16 * tn - 1e-300, hi = ghi + 2.2e-16 * tn + 1e-300;
   for (int it = 0; it < SMALL_BISECT_ROUNDS; ++it) {
-    const double h = (hi - lo) * (1.0 / 33.0);
-    const double s = lo + h * (double)(j + 1);
-    const bool hit = sturm_count(w.a, w.b, n, s, pivmin) >= target;
+    const double h = (hi - lo) * (1.0 / 65.0);
+    const bool hit = sturm_count(s.a, s.b, n, lo + h * (double)(l + 1), pivmin) >= target;
     const unsigned long long mask = __ballot(hit);
-    const unsigned int gm = (unsigned int)(mask >> (32 * g));
-    const int js = gm ? __builtin_ctz(gm) : 32;   // first probe at or above the eigenvalue
+    const int js = mask ? __builtin_ctzll(mask) : 64;   // first probe above the eigenvalue
     const double nlo = js == 0 ? lo : lo + h * (double)js;
-    const double nhi = js == 32 ? hi : lo + h * (double)(js + 1);
+    const double nhi = js == 64 ? hi : lo + h * (double)(js + 1);
     lo = nlo;
     hi = nhi;
   }
-  const double mid = 0.5 * (lo + hi);
-  *lam0 = __shfl(mid, 0, 64);
-  *lam1 = n >= 2 ? __shfl(mid, 32, 64) : *lam0;
-  *tnorm = tn;
+  *lo_out = lo;
+  *hi_out = hi;
+  *tn_out = tn;
 }
 
-// 3. w.A <- (B)^{-1} for the Hermitian positive definite B already in w.A
-//    (Gauss-Jordan, no pivoting; row and column k are staged in w.y / w.r).
-__device__ inline void small_gj_inverse(small_ws& w, int n) {
+// ---------------------------------------------------------------- 3. inverse
+// s.A <- s.A^{-1} for a Hermitian positive definite matrix (Gauss-Jordan, no
+// pivoting; row and column k are staged in s.u / s.w before the update).
+__device__ inline void small_gj_inverse(small_ws& s, int n) {
   const int l = threadIdx.x;
   const float rn = 1.0f / (float)n;
+  const int nn = n * n;
+  c64* __restrict__ A = s.A;
+  c64* __restrict__ col = s.w;
+  c64* __restrict__ row = s.u;
   for (int k = 0; k < n; ++k) {
     if (l < n) {
-      w.y[l] = w.A[l * n + k];
-      w.r[l] = w.A[k * n + l];
+      col[l] = A[l * n + k];
+      row[l] = A[k * n + l];
     }
     __syncthreads();
-    const double ip = rcp_nr(w.r[k].re);
-    for (int e = l; e < n * n; e += SMALL_NT) {
-      int i, jj;
-      split_index(e, n, rn, i, jj);
-      c64 v;
-      if (i == k && jj == k) v = {ip, 0.0};
-      else if (i == k) v = ip * w.r[jj];
-      else if (jj == k) v = -ip * w.y[i];
-      else v = w.A[e] - ip * (w.y[i] * w.r[jj]);
-      w.A[e] = v;
+    const double ip = rcp_nr(row[k].re);
+    for (int e0 = 0; e0 < nn; e0 += 8 * SMALL_NT) {
+      c64 av[8], cv[8], rv[8];
+      int ii[8], jj[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int e = e0 + l + t * SMALL_NT;
+        split_index(e, n, rn, ii[t], jj[t]);
+        if (e < nn) {
+          av[t] = A[e];
+          cv[t] = col[ii[t]];
+          rv[t] = row[jj[t]];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int e = e0 + l + t * SMALL_NT;
+        if (e < nn) {
+          c64 v;
+          if (ii[t] == k && jj[t] == k) v = {ip, 0.0};
+          else if (ii[t] == k) v = ip * rv[t];
+          else if (jj[t] == k) v = -ip * cv[t];
+          else v = av[t] - ip * (cv[t] * rv[t]);
+          A[e] = v;
+        }
+      }
     }
     __syncthreads();
   }
 }
 
-// y = M x with M = w.A Hermitian (lane l reads column l: M[l][j] = conj(M[j][l])).
-__device__ inline c64 small_matvec(const small_ws& w, int n, const c64* x) {
+// y = M x for Hermitian M = s.A (lane l reads column l: M[l][j] = conj(M[j][l])).
+__device__ inline c64 small_matvec(const small_ws& s, int n, const c64* __restrict__ x) {
   const int l = threadIdx.x;
-  c64 s = {0.0, 0.0};
-  if (l < n)
-    for (int j = 0; j < n; ++j) s = s + cmulc(w.A[j * n + l], x[j]);
-  return s;
+  c64 s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
+  if (l < n) {
+    const c64* colp = s.A + l;
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
+      const c64 a0 = colp[(size_t)j * n], a1 = colp[(size_t)(j + 1) * n];
+      const c64 a2 = colp[(size_t)(j + 2) * n], a3 = colp[(size_t)(j + 3) * n];
+      const c64 x0 = x[j], x1 = x[j + 1], x2 = x[j + 2], x3 = x[j + 3];
+      s0 = s0 + cmulc(a0, x0) + cmulc(a2, x2);
+      s1 = s1 + cmulc(a1, x1) + cmulc(a3, x3);
+    }
+    for (; j < n; ++j) s0 = s0 + cmulc(colp[(size_t)j * n], x[j]);
+  }
+  return s0 + s1;
 }
 
-// The whole solver.  acc.get(i, j) gives G in double-double; G's rounded
-// value must already be in w.A.  Returns mu = x^H G x (dd); x is left in w.x
-// (unit norm).  *lam1 receives the second smallest eigenvalue of the FP64
-// matrix and *steps the number of refinement steps.
+// ---------------------------------------------------------------- the solver
+// acc.get(i, j) gives G in double-double; G's rounded value must already be
+// in s.A (destroyed).  Leaves the unit eigenvector in s.x (lane l also keeps
+// entry l) and returns mu = x^H G x (dd).  *lam1 receives the second
+// smallest eigenvalue when want_lam1 (else NaN); *steps the number of
+// refinement steps.
 template <class Acc>
-__device__ inline dd small_eig(small_ws& w, const Acc& acc, int n, double* lam1, int* steps) {
+__device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_lam1, double* lam1, int* steps) {
   const int l = threadIdx.x;
   if (n == 1) {
-    if (l == 0) w.x[0] = {1.0, 0.0};
+    if (l == 0) s.x[0] = {1.0, 0.0};
     __syncthreads();
-    *lam1 = dd_val(acc.get(0, 0).re);
+    *lam1 = __builtin_nan("");
     *steps = 0;
     return acc.get(0, 0).re;
   }
-  small_tridiag(w, n);
-  double l0, l1, tn;
-  small_bisect(w, n, &l0, &l1, &tn);
-  *lam1 = l1;
-  const double shift = fmax(1e-3 * (l1 - l0), 16.0 * n * 2.2e-16 * tn);
-  const double sigma = l0 - shift;
+  small_tridiag(s, n);
+  double lo0, hi0, tn;
+  small_bisect(s, n, 1, &lo0, &hi0, &tn);
+  if (want_lam1) {
+    double lo1, hi1, tn1;
+    small_bisect(s, n, 2, &lo1, &hi1, &tn1);
+    *lam1 = 0.5 * (lo1 + hi1);
+  } else {
+    *lam1 = __builtin_nan("");
+  }
+  const double sigma = lo0 - 16.0 * n * 2.2e-16 * tn;
   // B = G - sigma I (rounded G), inverted in place
-  for (int e = l; e < n * n; e += SMALL_NT) {
-    const int i = e / n, jj = e - i * n;
-    const cdd g = acc.get(i, jj);
-    w.A[e] = {g.re.hi - (i == jj ? sigma : 0.0), g.im.hi};
+  {
+    const float rn = 1.0f / (float)n;
+    for (int e = l; e < n * n; e += SMALL_NT) {
+      int i, jj;
+      split_index(e, n, rn, i, jj);
+      const cdd g = acc.get(i, jj);
+      s.A[e] = {g.re.hi - (i == jj ? sigma : 0.0), g.im.hi};
+    }
   }
   __syncthreads();
-  small_gj_inverse(w, n);
+  small_gj_inverse(s, n);
   // inverse iteration from a fixed, generic start vector
-  if (l < n) w.x[l] = {1.0 + 0.6180339887 * (double)l, 0.5 - 0.4142135624 * (double)((l * 7) % 5)};
+  c64 xl = l < n ? c64{1.0 + 0.6180339887 * (double)l, 0.5 - 0.4142135624 * (double)((l * 7) % 5)}
+                 : c64{0.0, 0.0};
+  if (l < n) s.x[l] = xl;
   __syncthreads();
   for (int it = 0; it < SMALL_INVIT; ++it) {
-    const c64 y = small_matvec(w, n, w.x);
+    const c64 y = small_matvec(s, n, s.x);
     const double nr = sqrt(wsum(l < n ? norm2(y) : 0.0));
+    xl = l < n ? c64{y.re / nr, y.im / nr} : c64{0.0, 0.0};
     __syncthreads();
-    if (l < n) w.x[l] = {y.re / nr, y.im / nr};
+    if (l < n) s.x[l] = xl;
     __syncthreads();
   }
   // Newton refinement against the double-double matrix
@@ -296,15 +408,13 @@ __device__ inline dd small_eig(small_ws& w, const Acc& acc, int n, double* lam1,
   bool done = false;
   for (;; ++it) {
     dd yre = {0.0, 0.0}, yim = {0.0, 0.0};
-    c64 xi = {0.0, 0.0};
     if (l < n) {
-      xi = w.x[l];
       dot2 ar, ai;
       ar.init();
       ai.init();
       for (int j = 0; j < n; ++j) {
         const cdd g = acc.get(l, j);
-        const c64 xj = w.x[j];
+        const c64 xj = s.x[j];
         ar.add_prod(g.re.hi, xj.re); ar.add(g.re.lo * xj.re);
         ar.add_prod(-g.im.hi, xj.im); ar.add(-g.im.lo * xj.im);
         ai.add_prod(g.re.hi, xj.im); ai.add(g.re.lo * xj.im);
@@ -315,26 +425,27 @@ __device__ inline dd small_eig(small_ws& w, const Acc& acc, int n, double* lam1,
     }
     dot2 t;
     t.init();
-    t.add_prod(xi.re, yre.hi); t.add(xi.re * yre.lo);
-    t.add_prod(xi.im, yim.hi); t.add(xi.im * yim.lo);
+    t.add_prod(xl.re, yre.hi); t.add(xl.re * yre.lo);
+    t.add_prod(xl.im, yim.hi); t.add(xl.im * yim.lo);
     mu = wsum_dd(t.result());
     if (done || it == SMALL_REFINE_MAX) break;
     if (l < n) {
       dot2 qr, qi;
       qr.init(); qi.init();
-      qr.add_dd(yre); qr.add_prod(-mu.hi, xi.re); qr.add(-mu.lo * xi.re);
-      qi.add_dd(yim); qi.add_prod(-mu.hi, xi.im); qi.add(-mu.lo * xi.im);
-      w.r[l] = {dd_val(qr.result()), dd_val(qi.result())};
+      qr.add_dd(yre); qr.add_prod(-mu.hi, xl.re); qr.add(-mu.lo * xl.re);
+      qi.add_dd(yim); qi.add_prod(-mu.hi, xl.im); qi.add(-mu.lo * xl.im);
+      s.u[l] = {dd_val(qr.result()), dd_val(qi.result())};
     }
     __syncthreads();
-    const c64 d = small_matvec(w, n, w.r);
-    const c64 xn = l < n ? xi - d : c64{0.0, 0.0};
+    const c64 cl = small_matvec(s, n, s.u);
+    const c64 xn = l < n ? xl - cl : c64{0.0, 0.0};
     const double nrm = sqrt(wsum(norm2(xn)));
-    const double dn = sqrt(wsum(l < n ? norm2(d) : 0.0));
+    const double dn = sqrt(wsum(l < n ? norm2(cl) : 0.0));
+    xl = {xn.re / nrm, xn.im / nrm};
     __syncthreads();
-    if (l < n) w.x[l] = {xn.re / nrm, xn.im / nrm};
+    if (l < n) s.x[l] = xl;
     __syncthreads();
-    done = !(dn > 1e-15);
+    done = !(dn > 4e-15);
   }
   *steps = it;
   return mu;

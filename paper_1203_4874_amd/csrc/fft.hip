@@ -216,26 +216,41 @@ size_t col_lds_bytes(int N, int cw, int esize) {
   return ((size_t)(4 * cw + 1) * N + (size_t)cw * 2 * CBP_MAX_K) * 2 * esize;
 }
 
+namespace {
+void set_fft_attrs_once() {
+  static bool done = false;
+  if (done) return;
+  const void* fns[6] = {(const void*)k_row_fwd<float>, (const void*)k_col_filter<float>, (const void*)k_row_inv<float>,
+                        (const void*)k_row_fwd<double>, (const void*)k_col_filter<double>,
+                        (const void*)k_row_inv<double>};
+  for (const void* f : fns) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  done = true;
+}
+}  // namespace
+
 template <typename T>
-hipError_t launch_deconv(const pair_view<T>& v, const frame_plan& fp, char* ws, const double* K1, const double* K2,
-                         T* out, int64_t opitch, int64_t ocs, double lambda, hipStream_t st) {
-  static bool attrs_set = false;
-  if (!attrs_set) {
-    hipFuncSetAttribute((const void*)k_row_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    hipFuncSetAttribute((const void*)k_col_filter<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    hipFuncSetAttribute((const void*)k_row_inv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attrs_set = true;
-  }
+hipError_t launch_row_fwd(const pair_view<T>& v, const frame_plan& fp, char* ws, hipStream_t st) {
+  set_fft_attrs_once();
+  cplx<T>* t1 = (cplx<T>*)(ws + fp.off_t1);
+  cplx<T>* t2 = (cplx<T>*)(ws + fp.off_t2);
+  const int64_t tpc = (int64_t)fp.Hmax * fp.hx;
+  prof_begin(PH_ROW_FWD, st);
+  hipLaunchKernelGGL(k_row_fwd<T>, dim3(fp.Hmax, v.nch), dim3(256), row_lds_bytes(fp.Px, (int)sizeof(T)), st, v,
+                     fp.fx, fp.hx, t1, t2, tpc);
+  prof_end(PH_ROW_FWD, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_col_inv(const pair_view<T>& v, const frame_plan& fp, char* ws, const double* K1, const double* K2,
+                          T* out, int64_t opitch, int64_t ocs, double lambda, hipStream_t st) {
+  set_fft_attrs_once();
   cplx<T>* t1 = (cplx<T>*)(ws + fp.off_t1);
   cplx<T>* t2 = (cplx<T>*)(ws + fp.off_t2);
   cplx<T>* u = (cplx<T>*)(ws + fp.off_u);
   const int64_t tpc = (int64_t)fp.Hmax * fp.hx;
   const int64_t upc = (int64_t)fp.m * fp.hx;
   const int es = (int)sizeof(T);
-  prof_begin(PH_ROW_FWD, st);
-  hipLaunchKernelGGL(k_row_fwd<T>, dim3(fp.Hmax, v.nch), dim3(256), row_lds_bytes(fp.Px, es), st, v, fp.fx, fp.hx,
-                     t1, t2, tpc);
-  prof_end(PH_ROW_FWD, st);
   prof_begin(PH_COL_FILTER, st);
   hipLaunchKernelGGL(k_col_filter<T>, dim3((fp.hx + fp.cw - 1) / fp.cw, v.nch), dim3(256),
                      col_lds_bytes(fp.Py, fp.cw, es), st, t1, t2, fp.H1, fp.H2, fp.hx, tpc, u, fp.m, upc, K1, fp.k1,
@@ -249,9 +264,11 @@ hipError_t launch_deconv(const pair_view<T>& v, const frame_plan& fp, char* ws, 
   return hipGetLastError();
 }
 
-template hipError_t launch_deconv<float>(const pair_view<float>&, const frame_plan&, char*, const double*,
-                                         const double*, float*, int64_t, int64_t, double, hipStream_t);
-template hipError_t launch_deconv<double>(const pair_view<double>&, const frame_plan&, char*, const double*,
-                                          const double*, double*, int64_t, int64_t, double, hipStream_t);
+template hipError_t launch_row_fwd<float>(const pair_view<float>&, const frame_plan&, char*, hipStream_t);
+template hipError_t launch_row_fwd<double>(const pair_view<double>&, const frame_plan&, char*, hipStream_t);
+template hipError_t launch_col_inv<float>(const pair_view<float>&, const frame_plan&, char*, const double*,
+                                          const double*, float*, int64_t, int64_t, double, hipStream_t);
+template hipError_t launch_col_inv<double>(const pair_view<double>&, const frame_plan&, char*, const double*,
+                                           const double*, double*, int64_t, int64_t, double, hipStream_t);
 
 }  // namespace cbp

@@ -54,7 +54,9 @@ void prof_end(int phase, hipStream_t st);
 // ---------------------------------------------------------------- launchers
 // eval.hip
 template <typename T>
-hipError_t launch_eval(const pair_view<T>& v, const frame_plan& fp, char* ws, hipStream_t st);
+hipError_t launch_eval_cols(const pair_view<T>& v, const frame_plan& fp, char* ws, hipStream_t st);
+template <typename T>
+hipError_t launch_eval_rows(const pair_view<T>& v, const frame_plan& fp, char* ws, hipStream_t st);
 hipError_t launch_eval_single(const void* b, int dtype, int64_t pitch, int H, int W, int S,
                               char* ws, double* ex, double* ey, hipStream_t st);
 
@@ -64,8 +66,10 @@ hipError_t launch_recover(const frame_plan& fp, char* ws, double* K1, double* K2
 
 // fft.hip
 template <typename T>
-hipError_t launch_deconv(const pair_view<T>& v, const frame_plan& fp, char* ws, const double* K1,
-                         const double* K2, T* out, int64_t opitch, int64_t ocs, double lambda,
-                         hipStream_t st);
+hipError_t launch_row_fwd(const pair_view<T>& v, const frame_plan& fp, char* ws, hipStream_t st);
+template <typename T>
+hipError_t launch_col_inv(const pair_view<T>& v, const frame_plan& fp, char* ws, const double* K1,
+                          const double* K2, T* out, int64_t opitch, int64_t ocs, double lambda,
+                          hipStream_t st);
 
 }  // namespace cbp

@@ -80,10 +80,10 @@ __device__ inline void unit_twiddles(c64* tw, int S) {
 __device__ inline bool finite_c(c64 v) { return isfinite(v.re) && isfinite(v.im); }
 
 // Correlations rho for every (pass, sample, lag), summed over channels.
-// grid (2N-1, S, 2), 256 threads.
-__global__ __launch_bounds__(256) void k_gram(const c64* ex, const c64* ey, int Wmax, int Hmax, int W1, int W2,
-                                              int H1, int H2, int S, int k1, int k2, int nch, cdd* corr) {
-  __shared__ dd rre[256], rim[256];
+// grid (2N-1, S, 2), one wave each; Dot2 accumulation per lane, then a
+// fixed-order double-double wave reduction.
+__global__ __launch_bounds__(64) void k_gram(const c64* ex, const c64* ey, int Wmax, int Hmax, int W1, int W2,
+                                             int H1, int H2, int S, int k1, int k2, int nch, cdd* corr) {
   const int li = blockIdx.x, j = blockIdx.y, pass = blockIdx.z;
   const int N = k1 + k2, NL = 2 * N - 1;
   int fa, fb, l;
@@ -101,26 +101,23 @@ __global__ __launch_bounds__(256) void k_gram(const c64* ex, const c64* ey, int 
   for (int ch = 0; ch < nch; ++ch) {
     const c64* a = base + ((size_t)(ch * 2 + fa) * S + j) * stride;
     const c64* b = base + ((size_t)(ch * 2 + fb) * S + j) * stride;
-    for (int t = t0 + (int)threadIdx.x; t < t1; t += 256) {
-      const c64 av = a[t], bv = b[t + l];
-      sre.add_prod(av.re, bv.re);
-      sre.add_prod(av.im, bv.im);
-      sim.add_prod(av.re, bv.im);
-      sim.add_prod(-av.im, bv.re);
+    int t = t0 + (int)threadIdx.x;
+    for (; t + 64 < t1; t += 128) {
+      const c64 a0 = a[t], b0 = b[t + l], a1 = a[t + 64], b1 = b[t + 64 + l];
+      sre.add_prod(a0.re, b0.re); sre.add_prod(a0.im, b0.im);
+      sim.add_prod(a0.re, b0.im); sim.add_prod(-a0.im, b0.re);
+      sre.add_prod(a1.re, b1.re); sre.add_prod(a1.im, b1.im);
+      sim.add_prod(a1.re, b1.im); sim.add_prod(-a1.im, b1.re);
+    }
+    if (t < t1) {
+      const c64 a0 = a[t], b0 = b[t + l];
+      sre.add_prod(a0.re, b0.re); sre.add_prod(a0.im, b0.im);
+      sim.add_prod(a0.re, b0.im); sim.add_prod(-a0.im, b0.re);
     }
   }
-  const int tid = threadIdx.x;
-  rre[tid] = sre.result();
-  rim[tid] = sim.result();
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) {
-      rre[tid] = dd_add(rre[tid], rre[tid + s]);
-      rim[tid] = dd_add(rim[tid], rim[tid + s]);
-    }
-    __syncthreads();
-  }
-  if (tid == 0) corr[((size_t)pass * S + j) * NL + li] = cdd{rre[0], rim[0]};
+  const dd re = wsum_dd(sre.result());
+  const dd im = wsum_dd(sim.result());
+  if (threadIdx.x == 0) corr[((size_t)pass * S + j) * NL + li] = cdd{re, im};
 }
 
 // Smallest eigenvector of every per-sample Gram.  grid (S, 2), one wave each.
@@ -144,7 +141,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_sample(const cdd* corr, int S, int
   __syncthreads();
   double lam1;
   int steps;
-  const dd mu = small_eig(w, G, N, &lam1, &steps);
+  const dd mu = small_eig(w, G, N, diag != nullptr, &lam1, &steps);
   const size_t base = ((size_t)pass * S + j) * N;
   const c64 xi = l < N ? w.x[l] : c64{0.0, 0.0};
   if (l < N) {
@@ -163,7 +160,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_sample(const cdd* corr, int S, int
       diag->sample_lambda1[pass][j] = lam1;
       diag->sample_scale[pass][j] = gmax;
       atomicMax(&diag->refine_sample, steps);
-      if (!(lam1 - l0 > 1e-13 * gmax)) atomicOr(&diag->flags, CBP_DIAG_SAMPLE_WEAK);
+      if (!(lam1 - l0 > 1e-13 * gmax)) atomicOr(&diag->flags, CBP_DIAG_SAMPLE_WEAK);  // NaN-safe: flags NaN too
       if (bad || !isfinite(l0)) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
     }
   }
@@ -178,9 +175,11 @@ __global__ __launch_bounds__(SMALL_NT) void k_finalize(const c64* xvec, int S, i
   c64* tw = (c64*)sm_fin;                        // S
   dd* Da = (dd*)(tw + CBP_MAX_S);                // S
   dd* Db = Da + CBP_MAX_S;                       // S
-  c64* kbuf = (c64*)(Db + CBP_MAX_S);            // 2 S^2: averaged spectra, then the S x S inverse DFTs
-  c64* tbuf = kbuf + 2 * CBP_MAX_S * CBP_MAX_S;  // 2 S^2: half-transformed spectra
-  small_ws w = small_carve((char*)(tbuf + 2 * CBP_MAX_S * CBP_MAX_S), n2);
+  small_ws w = small_carve((char*)(Db + CBP_MAX_S), n2);
+  // after the scale solve, its matrix region (4 S^2 entries) holds the
+  // averaged spectra / inverse DFTs (2 S^2) and the half-transformed ones (2 S^2)
+  c64* kbuf = w.A;
+  c64* tbuf = w.A + 2 * SS;
   unit_twiddles(tw, S);
   __syncthreads();
   // cofactors evaluated on the other axis: pq = [P1, P2, Q1, Q2], each [i][j]
@@ -249,7 +248,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_finalize(const c64* xvec, int S, i
   __syncthreads();
   double lam1;
   int steps;
-  const dd mu = small_eig(w, H, n2, &lam1, &steps);
+  const dd mu = small_eig(w, H, n2, diag != nullptr, &lam1, &steps);
   if (tid == 0 && diag) {
     diag->k1 = k1; diag->k2 = k2; diag->S = S; diag->n = N;
     diag->scale_lambda0 = dd_val(mu);
@@ -354,8 +353,7 @@ __global__ void k_diag_init(cbp_diag* diag) {
 }  // namespace
 
 size_t finalize_lds_bytes(int S) {
-  return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) +
-         4 * (size_t)CBP_MAX_S * CBP_MAX_S * sizeof(c64) + small_lds_bytes(2 * S);
+  return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) + small_lds_bytes(2 * S);
 }
 
 size_t sample_lds_bytes(int N) {
@@ -378,7 +376,7 @@ hipError_t launch_recover(const frame_plan& fp, char* ws, double* K1, double* K2
   double* lam0 = (double*)(ws + fp.off_lam0);
   if (diag) hipLaunchKernelGGL(k_diag_init, dim3(1), dim3(256), 0, st, diag);
   prof_begin(PH_GRAM, st);
-  hipLaunchKernelGGL(k_gram, dim3(2 * N - 1, S, 2), dim3(256), 0, st, ex, ey, fp.Wmax, fp.Hmax, fp.W1, fp.W2, fp.H1,
+  hipLaunchKernelGGL(k_gram, dim3(2 * N - 1, S, 2), dim3(64), 0, st, ex, ey, fp.Wmax, fp.Hmax, fp.W1, fp.W2, fp.H1,
                      fp.H2, S, fp.k1, fp.k2, fp.nch, corr);
   prof_end(PH_GRAM, st);
   prof_begin(PH_SAMPLE, st);
