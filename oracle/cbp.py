@@ -127,18 +127,49 @@ def null_vector(A: np.ndarray):
     return x, (s[::-1] ** 2)
 
 
-def sample_cofactors(E1: np.ndarray, E2: np.ndarray, k1: int, k2: int):
+def round_operands(e: np.ndarray, fmt):
+    """The matrix-core operand precision of the MFMA32 / BF16 forms: each real
+    and imaginary part of the FP64 evaluation rounded to FP32 (round to
+    nearest even), and for "bf16" then to bfloat16 (round to nearest even on
+    the 16 dropped bits) -- the two roundings the GPU applies.  fmt None
+    leaves e unchanged."""
+    if fmt is None:
+        return e
+    def r(x):
+        f = np.asarray(x, dtype=np.float64).astype(np.float32)
+        if fmt == "bf16":
+            u = f.view(np.uint32).astype(np.uint64)
+            u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+            f = u.astype(np.uint32).view(np.float32)
+        elif fmt != "f32":
+            raise ValueError(fmt)
+        return f.astype(np.float64)
+    return r(e.real) + 1j * r(e.imag)
+
+
+def sample_gram(e1: np.ndarray, e2: np.ndarray, k1: int, k2: int, fmt=None) -> np.ndarray:
+    """G = A^H A for A = [C_k2(e1) | -C_k1(e2)] built from the (rounded)
+    evaluations, accumulated in FP64."""
+    A = sample_matrix(round_operands(e1, fmt), round_operands(e2, fmt), k1, k2)
+    return A.conj().T @ A
+
+
+def sample_cofactors(E1: np.ndarray, E2: np.ndarray, k1: int, k2: int, fmt=None):
     """Null vectors for every sample of one pass.
 
     Returns U (S x k2: cofactor slices of kernel 2), V (S x k1: slices of
-    kernel 1), spectra (S x (k1+k2), ascending Gram eigenvalues).
+    kernel 1), spectra (S x (k1+k2), ascending Gram eigenvalues).  With fmt
+    ("f32" / "bf16") the stacked matrix is built from operands rounded as the
+    matrix-core forms round them (round_operands); the null vector is then
+    exact for those operands.
     """
     S = E1.shape[0]
     U = np.zeros((S, k2), dtype=np.complex128)
     V = np.zeros((S, k1), dtype=np.complex128)
     spec = np.zeros((S, k1 + k2))
     for j in range(S):
-        x, sp = null_vector(sample_matrix(E1[j], E2[j], k1, k2))
+        A = sample_matrix(round_operands(E1[j], fmt), round_operands(E2[j], fmt), k1, k2)
+        x, sp = null_vector(A)
         U[j], V[j], spec[j] = x[:k2], x[k2:], sp
     return U, V, spec
 
@@ -249,17 +280,18 @@ def deconvolve(B1, B2, K1, K2, m: int, n: int, lam: float = 0.0):
 # whole method
 # --------------------------------------------------------------------------
 
-def recover_kernels(B1, B2, m: int, n: int, S: int = 0, full: bool = False):
+def recover_kernels(B1, B2, m: int, n: int, S: int = 0, full: bool = False, gram_fmt=None):
     """Kernels K1, K2 from the blurred pair (O1-O6).  With ``full`` also
-    returns every intermediate in a dict."""
+    returns every intermediate in a dict.  gram_fmt ("f32" / "bf16") rounds
+    the per-sample operands as the matrix-core precision forms do."""
     k1, k2 = kernel_sizes(B1.shape, B2.shape, m, n)
     S = S or max(k1, k2)
     if S < max(k1, k2):
         raise ValueError("S must be >= max kernel size")
     EX1, EY1 = unit_circle_eval(B1, S)
     EX2, EY2 = unit_circle_eval(B2, S)
-    XU, XV, Xspec = sample_cofactors(EX1, EX2, k1, k2)
-    YU, YV, Yspec = sample_cofactors(EY1, EY2, k1, k2)
+    XU, XV, Xspec = sample_cofactors(EX1, EX2, k1, k2, gram_fmt)
+    YU, YV, Yspec = sample_cofactors(EY1, EY2, k1, k2, gram_fmt)
     P, Q = cofactor_grids(XU, XV, YU, YV, S)
     a, b, Hspec = scale_fix(P, Q)
     K1, d1 = assemble_kernel(P[0], Q[0], a, b, k1)
@@ -271,7 +303,7 @@ def recover_kernels(B1, B2, m: int, n: int, S: int = 0, full: bool = False):
                         P=P, Q=Q, a=a, b=b, Hspec=Hspec, diag=(d1, d2))
 
 
-def deblur(B1, B2, m: int, n: int, S: int = 0, lam: float = 0.0):
+def deblur(B1, B2, m: int, n: int, S: int = 0, lam: float = 0.0, gram_fmt=None):
     """Latent frame and kernels from the blurred pair (O1-O7)."""
-    K1, K2 = recover_kernels(B1, B2, m, n, S)
+    K1, K2 = recover_kernels(B1, B2, m, n, S, gram_fmt=gram_fmt)
     return deconvolve(B1, B2, K1, K2, m, n, lam), K1, K2

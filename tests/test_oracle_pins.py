@@ -234,3 +234,46 @@ def test_config2_noiseless_recovers_truth():
     c = synth.config2(noise=0.0, m=120, n=160)
     K1, K2 = cbp.recover_kernels(c["B1"], c["B2"], 120, 160)
     assert rel(K1, c["K1"]) < 1e-9 and rel(K2, c["K2"]) < 1e-9
+
+
+# ---------------------------------------------------------------- operand rounding of the matrix-core forms
+
+def test_bf16_rounding_ties_and_library():
+    """round_operands('bf16'): FP64 -> FP32 -> bfloat16, each round to nearest
+    even.  Pinned by hand-worked ties and by torch's own float32 -> bfloat16
+    conversion (a library routine) on random values."""
+    r = lambda v: cbp.round_operands(np.array([v], dtype=np.complex128), "bf16")[0].real
+    assert r(1.0) == 1.0
+    assert r(1.0 + 2.0 ** -8) == 1.0                     # tie -> even (mantissa 0)
+    assert r(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6     # tie -> even (mantissa 2)
+    assert r(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7   # above the tie
+    assert r(-(1.0 + 3 * 2.0 ** -8)) == -(1.0 + 2.0 ** -6)
+    assert r(0.0) == 0.0
+    torch = pytest.importorskip("torch")
+    x = np.random.default_rng(5).standard_normal(4096) * 10.0 ** np.random.default_rng(6).uniform(-8, 8, 4096)
+    want = torch.tensor(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    got = cbp.round_operands(x + 0j, "bf16").real
+    assert np.array_equal(got, want)
+    got32 = cbp.round_operands(x + 1j * x, "f32")
+    assert np.array_equal(got32.real, x.astype(np.float32).astype(np.float64))
+    assert np.array_equal(got32.imag, got32.real)
+
+
+def test_rounded_gram_reduces_to_plain_and_is_block_toeplitz():
+    """fmt None is the plain Gram; any format gives a Hermitian block-Toeplitz
+    G whose null vector is the rounded problem's (checked against svd)."""
+    r = np.random.default_rng(8)
+    e1 = r.standard_normal(40) + 1j * r.standard_normal(40)
+    e2 = r.standard_normal(38) + 1j * r.standard_normal(38)   # len(e1) + k2 = len(e2) + k1
+    k1, k2 = 5, 3
+    A = cbp.sample_matrix(e1, e2, k1, k2)
+    assert np.array_equal(cbp.sample_gram(e1, e2, k1, k2), A.conj().T @ A)
+    for fmt in ("f32", "bf16"):
+        G = cbp.sample_gram(e1, e2, k1, k2, fmt)
+        assert np.allclose(G, G.conj().T, rtol=0, atol=1e-12 * np.abs(G).max())
+        for p in range(k2 - 1):      # G11 is Toeplitz: G[p + 1, 1] = G[p, 0]
+            assert abs(G[p + 1, 1] - G[p, 0]) <= 1e-12 * np.abs(G).max()
+        x, _ = cbp.null_vector(cbp.sample_matrix(cbp.round_operands(e1, fmt), cbp.round_operands(e2, fmt), k1, k2))
+        w, V = np.linalg.eigh(G)
+        assert abs(abs(np.vdot(V[:, 0], x)) - 1.0) <= 1e-8
+        assert np.abs(G - cbp.sample_gram(e1, e2, k1, k2)).max() > 0   # the rounding is seen
