@@ -13,6 +13,9 @@ Modules
             B1 (x) U = B2 (x) V by brute force.
   exact  -- exact rational / Gaussian-rational arithmetic (SymPy) on tiny
             integer inputs: GCD, resultants, exact null spaces.
+  learned -- the learned form: spectrum features, the MLP (forward, backward,
+            loss), the weighted scale fix and the weighted, regularised
+            assembly; it reduces to cbp's steps at unit weights.
 """
 
-from . import cbp, tls2d, exact  # noqa: F401
+from . import cbp, tls2d, exact, learned  # noqa: F401

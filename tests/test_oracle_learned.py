@@ -1,0 +1,128 @@
+"""Pins of the learned form's oracle (oracle/learned.py) against things other
+than itself: central differences for the MLP gradients, a dense
+least-squares solve for the separable weighted assembly, an explicit
+weighted row system for the weighted scale fix, closed-form features, and
+the reductions to the plain method."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cbp, learned
+
+
+def test_features_closed_form():
+    f = learned.spectrum_features(np.array([1e-10, 1e-5, 1.0]))
+    assert f.shape == (32,)
+    assert np.allclose(f[:3], [-1.0, -0.5, 0.0], atol=1e-15)
+    assert np.all(f[3:] == learned.PAD)
+    g = learned.spectrum_features(np.array([0.0, 2.0]))     # a zero eigenvalue hits the floor
+    assert np.isclose(g[0], -3.0) and g[1] == 0.0
+
+
+def test_mlp_gradients_match_central_differences():
+    rng = np.random.default_rng(3)
+    p = learned.init_params(rng)
+    p = {k: v + 0.05 * rng.standard_normal(v.shape) for k, v in p.items()}
+    X = rng.standard_normal((7, 32))
+    tw = rng.standard_normal(7)
+    tt = rng.standard_normal(7)
+    loss, g = learned.loss_and_grad(p, X, tw, tt)
+    h = 1e-6
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        idx = [tuple(rng.integers(0, s) for s in p[name].shape) for _ in range(6)]
+        for ix in idx:
+            q = {k: v.copy() for k, v in p.items()}
+            q[name][ix] += h
+            lp, _ = learned.loss_and_grad(q, X, tw, tt)
+            q[name][ix] -= 2 * h
+            lm, _ = learned.loss_and_grad(q, X, tw, tt)
+            num = (lp - lm) / (2 * h)
+            assert abs(num - g[name][ix]) <= 1e-6 * max(1.0, abs(num)), (name, ix, num, g[name][ix])
+
+
+def _grids(seed, k1, k2, S, noise=0.0):
+    r = synth.rng_for(seed)
+    L = r.random((40, 44))
+    K1, K2 = synth.draw_coprime_pair(r, k1, k2, "uniform")
+    B1, B2 = synth.blur_pair(synth.rng_for(seed, 1), L, K1, K2, noise)
+    _, _, f = cbp.recover_kernels(B1, B2, 40, 44, S, full=True)
+    return f, K1, K2
+
+
+def test_weighted_scale_fix_against_row_system():
+    f, _, _ = _grids(11, 4, 5, 6, noise=1e-3)
+    P, Q = f["P"], f["Q"]
+    S = P[0].shape[0]
+    rng = np.random.default_rng(4)
+    wX, wY = rng.uniform(0.2, 3.0, S), rng.uniform(0.2, 3.0, S)
+    a, b, _ = learned.weighted_scale_core(P, Q, wX, wY)
+    rows = []
+    for Pc, Qc in zip(P, Q):
+        for i in range(S):
+            for j in range(S):
+                r = np.zeros(2 * S, dtype=np.complex128)
+                sw = np.sqrt(wX[j] * wY[i])
+                r[j] = sw * Pc[i, j]
+                r[S + i] = -sw * Qc[i, j]
+                rows.append(r)
+    _, _, Vh = np.linalg.svd(np.array(rows))
+    z = Vh[-1].conj()
+    zz = np.concatenate([a, b])
+    assert abs(abs(np.vdot(z, zz)) - 1.0) <= 1e-10
+    # unit weights through the weighted route equal the plain scale fix
+    a1, b1, _ = learned.weighted_scale_core(P, Q, np.ones(S), np.ones(S))
+    a0, b0, _ = cbp.scale_fix(P, Q)
+    assert abs(abs(np.vdot(np.concatenate([a0, b0]), np.concatenate([a1, b1]))) - 1.0) <= 1e-12
+
+
+def test_weighted_assembly_against_dense_lstsq_and_plain():
+    f, K1, K2 = _grids(12, 4, 3, 5, noise=1e-3)
+    P, Q = f["P"], f["Q"]
+    S = P[0].shape[0]
+    a, b, _ = cbp.scale_fix(P, Q)
+    rng = np.random.default_rng(5)
+    wX, wY = rng.uniform(0.2, 3.0, S), rng.uniform(0.2, 3.0, S)
+    k = 4
+    K, _ = learned.weighted_assembly_core(P[0], Q[0], a, b, k, wX, wY, 0.0)
+    # dense weighted least squares over the k*k complex unknowns Z[x][y]
+    Kh = (wX[None, :] * a[None, :] * P[0] + wY[:, None] * b[:, None] * Q[0]) / (wX[None, :] + wY[:, None])
+    F = cbp.unit_roots_matrix(S, k)
+    A = np.zeros((S * S, k * k), dtype=np.complex128)
+    rhs = np.zeros(S * S, dtype=np.complex128)
+    for i in range(S):
+        for j in range(S):
+            sw = np.sqrt(wY[i] * wX[j])
+            A[i * S + j] = sw * np.outer(F[i], F[j]).ravel()     # Z[x][y] coefficient F[i][x] F[j][y]
+            rhs[i * S + j] = sw * Kh[i, j]
+    Z = np.linalg.lstsq(A, rhs, rcond=None)[0].reshape(k, k)
+    Kd = Z.T / Z.sum()
+    assert np.abs(K - Kd.real).max() <= 1e-10 * np.abs(Kd).max()
+    # unit weights, tau = 0 through the weighted route: the plain assembly
+    Ku, _ = learned.weighted_assembly_core(P[0], Q[0], a, b, k, np.ones(S), np.ones(S), 0.0)
+    Kp, _ = cbp.assemble_kernel(P[0], Q[0], a, b, k)
+    assert np.abs(Ku - Kp).max() <= 1e-12
+    # uniform weights: tau only rescales Z, which the normalisation removes
+    Kt, _ = learned.weighted_assembly_core(P[0], Q[0], a, b, k, 2 * np.ones(S), 2 * np.ones(S), 3.0)
+    assert np.abs(Kt - Kp).max() <= 1e-12
+    # tau -> infinity: Z -> C / tau^2, the weighted adjoint of Khat
+    Kinf, _ = learned.weighted_assembly_core(P[0], Q[0], a, b, k, wX, wY, 1e9)
+    C = F.conj().T @ np.diag(wY) @ Kh @ np.diag(wX) @ F.conj()
+    Kc = C.T / C.sum()
+    assert np.abs(Kinf - Kc.real).max() <= 1e-6 * np.abs(Kc).max()
+
+
+def test_constant_network_output_reduces_to_plain():
+    """A network with zero last-layer weights outputs constants: constant
+    weights and tau ~ e^-30 give the plain kernels."""
+    r = synth.rng_for(77)
+    L = r.random((48, 50))
+    K1, K2 = synth.draw_coprime_pair(r, 5, 4, "uniform")
+    B1, B2 = synth.blur_pair(synth.rng_for(77, 1), L, K1, K2, 1e-3)
+    p = learned.init_params(np.random.default_rng(1))
+    p["W3"][:] = 0.0
+    p["b3"][:] = [4.0, -40.0]
+    Q1, Q2, info = learned.recover_kernels_learned(B1, B2, 48, 50, p, full=True)
+    P1, P2 = info["plain"]
+    assert np.allclose(info["wX"], info["wX"][0]) and info["tau"] <= 1e-12
+    assert np.abs(Q1 - P1).max() <= 1e-9 and np.abs(Q2 - P2).max() <= 1e-9
