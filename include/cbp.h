@@ -29,7 +29,11 @@
  *     gives H_c = m + k_c - 1 and W_c = n + k_c - 1, so k_c = H_c - m + 1.
  *   - Kernels are FP64, row-major k_c x k_c, in DEVICE memory.
  *   - The caller owns every buffer, including the workspace, whose size comes
- *     from cbp_workspace_size().  The library allocates no device memory.
+ *     from cbp_workspace_size().  The library allocates no device memory for
+ *     data; it keeps per device a side stream, events, a small ring of pinned
+ *     host staging buffers (frame descriptors of batched calls), the HIP
+ *     graphs of CBP_FLAG_GRAPH calls and the autotuner's choices, until the
+ *     process ends.
  *   - Calls are asynchronous on options->stream (a hipStream_t; NULL = the
  *     default stream).  The returned status covers HOST-side validation only;
  *     numerical outcomes are written to options->diag (device, nullable) and
@@ -66,10 +70,16 @@ typedef enum {
 typedef enum { CBP_F32 = 0, CBP_F64 = 1 } cbp_dtype;
 
 /* Precision form.
- *   FP64  : FP64 frames; evaluation, Gram (double-double accumulated), the
- *           eigen-solves, scale fix and Fourier division all in FP64.
- *   MIXED : FP32 frames; evaluation accumulated in FP64, Gram double-double,
- *           eigen-solves and scale fix FP64, FFT and division in FP32. */
+ *   FP64   : FP64 frames; evaluation, Gram (double-double accumulated), the
+ *            eigen-solves, scale fix and Fourier division all in FP64.
+ *   MIXED  : FP32 frames; evaluation accumulated in FP64, Gram double-double,
+ *            eigen-solves and scale fix FP64, FFT and division in FP32.
+ *   MFMA32 : as MIXED, but the per-sample Gram is A^H A on the matrix cores
+ *            from FP32-rounded operands, FP32 accumulation (k1 + k2 <= 32).
+ *   BF16   : as MFMA32 with bfloat16 operands (FP32 accumulation).
+ * The two matrix-core forms square the conditioning of the per-sample
+ * problems in FP32: their kernel error against the FP64 method is reported,
+ * not bounded (see cbp_sample_grams). */
 typedef enum { CBP_PREC_FP64 = 0, CBP_PREC_MIXED = 1, CBP_PREC_MFMA32 = 2, CBP_PREC_BF16 = 3 } cbp_precision;
 
 typedef struct cbp_image {
@@ -85,15 +95,32 @@ typedef struct cbp_options {
   int32_t     precision;        /* cbp_precision */
   int32_t     samples;          /* S per axis; 0 = max(k1, k2); must be >= max(k1, k2) and <= CBP_MAX_S */
   double      lambda;           /* Tikhonov term of the Fourier division, >= 0 */
-  double      tau;              /* reserved (learned form), must be 0 */
-  int32_t     learned;          /* reserved (learned form), must be 0 */
-  int32_t     flags;            /* reserved, must be 0 */
-  const void* mlp_blob;         /* reserved, must be NULL */
+  double      tau;              /* reserved, must be 0 (the learned form predicts its own) */
+  int32_t     learned;          /* 1 = learned form: weights from the network in mlp_blob (k1 + k2 <= 32) */
+  int32_t     flags;            /* CBP_FLAG_* bits; 0 = eager launches with default launch shapes */
+  const void* mlp_blob;         /* device network blob (cbp_mlp_export) when learned = 1, else NULL */
   void*       stream;           /* hipStream_t */
   void*       workspace;        /* device scratch owned by the caller */
   size_t      workspace_bytes;  /* its size in bytes */
   void*       diag;             /* device cbp_diag (one per frame for the batch call), or NULL */
 } cbp_options;
+
+/* Option flags (cbp_options.flags).
+ *   CBP_FLAG_GRAPH    : the call's launches are captured once into a HIP graph
+ *                       (keyed by every pointer, size and option the launches
+ *                       bake in) and replayed with one hipGraphLaunch on later
+ *                       calls with the same key.  Up to 32 graphs are cached
+ *                       per device; evicting one synchronises the device.
+ *   CBP_FLAG_AUTOTUNE : on the first call of a batch class (dtype, frame count,
+ *                       largest frame, kernel and channel count, S, precision)
+ *                       the launch shapes -- FFT radix order, rows per fold
+ *                       group, columns per column-pass strip, workgroups per
+ *                       CU of the streaming launches -- are searched by timing
+ *                       the call itself on its stream (the call then blocks
+ *                       until the search ends); later calls of that class use
+ *                       the choice, with or without the flag. */
+#define CBP_FLAG_GRAPH     1
+#define CBP_FLAG_AUTOTUNE  2
 
 /* Diagnostic flags (cbp_diag.flags). */
 #define CBP_DIAG_NONFINITE      1  /* a non-finite value reached the kernels */
@@ -118,10 +145,16 @@ typedef struct cbp_diag {
   double  sample_vec[2][CBP_MAX_S][CBP_MAX_N][2];  /* unit null vectors x = (u: k2 entries, v: k1 entries) */
   double  scale_vec[2 * CBP_MAX_S][2];             /* unit (a_0..a_{S-1}, b_0..b_{S-1}) */
   double  khat[2][CBP_MAX_S][CBP_MAX_S][2];        /* averaged kernel spectra [kernel][i (x freq)][j (y freq)] */
+  float   sample_features[2][CBP_MAX_S][32];         /* the learned form's spectrum features of each sample */
+  double  sample_weights[2 * CBP_MAX_S + 1];          /* learned form: wX_0.., wY_0.., tau (unused otherwise) */
 } cbp_diag;
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char* cbp_status_string(cbp_status s);
+
+/* The HIP call behind the last CBP_E_DEVICE returned on this thread and its
+ * HIP error string ("" if none); valid until the thread's next failing call. */
+const char* cbp_last_error(void);
 
 /* Library version, "major.minor.patch" (static string). */
 const char* cbp_version(void);
@@ -146,6 +179,18 @@ size_t cbp_workspace_size(int32_t maxH, int32_t maxW, int32_t maxk,
 cbp_status cbp_eval_unit_circle(const cbp_image* b, int32_t S, double* ex, double* ey,
                                 const cbp_options* opts);
 
+/* The per-sample Gram matrices of step 2 (Sec. 5: one small factorisation
+ * per sample and direction), as the chosen precision form computes them:
+ * FP64 / MIXED accumulate the block-Toeplitz correlations in double-double;
+ * MFMA32 / BF16 form A^H A on the matrix cores from FP32 / bfloat16 operands
+ * with FP32 accumulation.  grams (device) receives 2 * S * N * N complex
+ * FP64 values (re, im interleaved), N = k1 + k2, laid out
+ * [pass (0: X, 1: Y)][sample][p][q], each the Hermitian
+ *   G = A^H A,  A = [C_k2(e1) | -C_k1(e2)]  (unknowns ordered (u: k2, v: k1)),
+ * rounded to FP64.  Multi-channel frames: summed over channels. */
+cbp_status cbp_sample_grams(const cbp_image* b1, const cbp_image* b2, int32_t m, int32_t n,
+                            double* grams, const cbp_options* opts);
+
 /* Kernel recovery (steps 1-4).  b1, b2: the blurred pair (same dtype and
  * channel count); m, n: latent size.  K1 (k1*k1 doubles) and K2 (k2*k2)
  * receive the kernels normalised to sum 1.  Multi-channel frames: the
@@ -161,15 +206,71 @@ cbp_status cbp_deblur(const cbp_image* b1, const cbp_image* b2, cbp_image* laten
                       double* K1, double* K2, const cbp_options* opts);
 
 /* cbp_deblur over `nframes` independent frames (each with its own kernel
- * pair and sizes).  b1s, b2s, latents, K1s, K2s are HOST arrays of nframes
- * entries (K1s / K2s entries may be NULL).  per_frame (host, nullable)
- * receives each frame's validation status; the call returns the first
- * failure or CBP_OK.  The workspace must hold `nframes` frames of the
- * largest size (cbp_workspace_size(..., batch = nframes, ...)).
- * opts->diag, when set, points to nframes cbp_diag records. */
+ * pair and sizes; one dtype).  b1s, b2s, latents, K1s, K2s are HOST arrays of
+ * nframes entries (K1s / K2s entries may be NULL).  Every phase of the path
+ * is ONE launch over the work items of all frames (up to 256 frames per
+ * launch; larger batches are split), reading per-frame descriptors that the
+ * call stages into the head of the workspace.  per_frame (host, nullable)
+ * receives each frame's validation status; invalid frames are skipped, the
+ * others run, and the call returns the first failure or CBP_OK.  The
+ * workspace must hold `nframes` frames of the largest size
+ * (cbp_workspace_size(..., batch = nframes, ...)).  opts->diag, when set,
+ * points to nframes cbp_diag records.  With the default launch shapes (no
+ * autotuned choice stored for the batch class) per-frame results are
+ * identical, bit for bit, to cbp_deblur on that frame alone. */
 cbp_status cbp_deblur_batch(int32_t nframes, const cbp_image* b1s, const cbp_image* b2s,
                             cbp_image* latents, double* const* K1s, double* const* K2s,
                             cbp_status* per_frame, const cbp_options* opts);
+
+/* Launch shapes chosen by the last CBP_FLAG_AUTOTUNE search on the current
+ * device, with the time of one batch call under them. */
+typedef struct cbp_tuning {
+  int32_t fold_rows;          /* rows per column-fold group (before rounding up to a multiple of S) */
+  int32_t strip_columns;      /* columns per column-pass strip (0 = automatic) */
+  int32_t workgroups_per_cu;  /* persistent-grid cap of the streaming launches (0 = one workgroup per item) */
+  int32_t fft_order;          /* radix pass order: 0 = 8,4,2,3,5,7; 1 = 4,8,2,3,5,7; 2 = 7,5,3,8,4,2 */
+  double  ms;                 /* measured time of the batch call, ms */
+} cbp_tuning;
+
+/* CBP_E_INVALID when no search has run on this device. */
+cbp_status cbp_last_tuning(cbp_tuning* out);
+
+/* ------------------------------------------------------------------------
+ * The learned form (no counterpart in the paper).  A 32 -> 128 -> 128 -> 2
+ * ReLU network reads each sample's Gram spectrum as 32 features
+ *   f_i = log10(max(lambda_i, 1e-14 lambda_max) / lambda_max) / 10  (i < k1+k2), +1 after,
+ * and predicts w = clip(softplus(o1), 1e-3, 1e3) and tau_j = exp(clip(o2, -30, 5)).
+ * The weights enter the scale fix (rows weighted by sqrt(wX_j wY_i)) and the
+ * assembly (spectra averaged with weights wX_j, wY_i; the kernel is the
+ * separable weighted fit to them with per-axis Tikhonov strength tau =
+ * median of tau_j).  Unit weights and tau = 0 reduce it to the plain method.
+ * Layers 1 and 2 run on the matrix cores in bfloat16 with FP32 accumulation;
+ * the 2-output head, the biases, the master weights and Adam are FP32.
+ *
+ * Parameters (FP32, device, packed): W1 [128][32], b1 [128], W2 [128][128],
+ * b2 [128], W3 [2][128], b3 [2] -- cbp_mlp_param_count() floats.
+ * Training state (device, cbp_mlp_state_size(max_rows) bytes, caller-owned):
+ * master weights, Adam moments, bf16 copies and the activations of up to
+ * max_rows rows.  Features X: device FP32 [n][32]; targets T: device FP32
+ * [n][2] = (log w*, log tau*); loss: device FP32, the mean over rows of
+ * (log softplus(o1) - log w*)^2 + (o2 - log tau*)^2.  All calls are
+ * asynchronous on `stream`. */
+int32_t    cbp_mlp_param_count(void);
+size_t     cbp_mlp_blob_size(void);
+size_t     cbp_mlp_state_size(int32_t max_rows);
+/* Load parameters into a state and reset its Adam moments. */
+cbp_status cbp_mlp_set_params(void* state, int32_t max_rows, const float* params, void* stream);
+cbp_status cbp_mlp_get_params(const void* state, int32_t max_rows, float* params, void* stream);
+/* Loss and gradient (packed like the parameters; grads may be NULL) of n <= max_rows rows. */
+cbp_status cbp_mlp_gradients(void* state, int32_t max_rows, const float* X, const float* T, int32_t n,
+                             float* loss, float* grads, void* stream);
+/* cbp_mlp_gradients followed by one Adam step (beta 0.9 / 0.999, eps 1e-8; step counts from 1). */
+cbp_status cbp_mlp_train_step(void* state, int32_t max_rows, const float* X, const float* T, int32_t n,
+                              float lr, int32_t step, float* loss, void* stream);
+/* The inference blob (cbp_mlp_blob_size() bytes, device) from a state. */
+cbp_status cbp_mlp_export(const void* state, int32_t max_rows, void* blob, void* stream);
+/* Network outputs (o1, o2) for n feature rows: out device FP32 [n][2]. */
+cbp_status cbp_mlp_forward(const void* blob, const float* X, int32_t n, float* out, void* stream);
 
 /* Phase timing.  While enabled, every call records a HIP event pair around
  * each phase on its stream; cbp_profile_read() waits for the recorded events,

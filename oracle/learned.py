@@ -10,9 +10,11 @@ call in that case, so the reduction is exact by construction.
 Readings (no paper text covers this form; these are this implementation's
 definitions):
   * features: the sample's ascending Gram eigenvalues as
-    f_i = log10(max(lambda_i, 1e-30 lambda_max) / lambda_max) / 10 for
+    f_i = log10(max(lambda_i, 1e-14 lambda_max) / lambda_max) / 10 for
     i < N = k1 + k2, and the sentinel +1 for i = N .. 31 (real features are
-    <= 0, so the sentinel marks the padding);
+    <= 0, so the sentinel marks the padding).  The floor 1e-14 sits above the
+    rounding level of an FP64 Gram's eigenvalues (about 1e-16 lambda_max), so
+    eigenvalues below it, which no FP64 route resolves, all read as -1.4;
   * MLP 32 -> 128 -> 128 -> 2 with ReLU, outputs o = (o1, o2):
     w = clip(softplus(o1), 1e-3, 1e3), tau_j = exp(clip(o2, -30, 5));
     the frame's tau is the median of its samples' tau_j;
@@ -39,7 +41,7 @@ from . import cbp
 FEAT = 32
 HIDDEN = 128
 PAD = 1.0
-LOG_FLOOR = 1e-30
+LOG_FLOOR = 1e-14
 
 
 # --------------------------------------------------------------------------
@@ -184,14 +186,20 @@ def weighted_assembly_core(Pc, Qc, a, b, k, wX, wY, tau):
     return Kn.real, dict(imag=float(np.linalg.norm(Kn.imag) / np.linalg.norm(Kn.real)), sum=s)
 
 
-def recover_kernels_learned(B1, B2, m: int, n: int, params, S: int = 0, full: bool = False):
-    """Kernels with MLP weights (O1-O6 with the weighted O5 / O6)."""
+def recover_kernels_learned(B1, B2, m: int, n: int, params, S: int = 0, full: bool = False,
+                            bf16: bool = False):
+    """Kernels with MLP weights (O1-O6 with the weighted O5 / O6).  bf16 runs
+    the network with the GPU kernels' roundings (mlp_forward_bf16) and takes
+    the features in FP32, as the GPU stores them."""
     K1p, K2p, f = cbp.recover_kernels(B1, B2, m, n, S, full=True)
     k1, k2, S = f["k1"], f["k2"], f["S"]
     XF = spectrum_features(f["Xspec"])
     YF = spectrum_features(f["Yspec"])
-    oX, _ = mlp_forward(params, XF)
-    oY, _ = mlp_forward(params, YF)
+    fwd = mlp_forward
+    if bf16:
+        XF, YF, fwd = _f32(XF), _f32(YF), mlp_forward_bf16
+    oX, _ = fwd(params, XF)
+    oY, _ = fwd(params, YF)
     wX, tX = weights_from_outputs(oX)
     wY, tY = weights_from_outputs(oY)
     tau = float(np.median(np.concatenate([tX, tY])))
@@ -201,3 +209,75 @@ def recover_kernels_learned(B1, B2, m: int, n: int, params, S: int = 0, full: bo
     if not full:
         return K1, K2
     return K1, K2, dict(plain=(K1p, K2p), wX=wX, wY=wY, tau=tau, features=(XF, YF), base=f)
+
+
+# --------------------------------------------------------------------------
+# the network in the kernels' precision (for parity of the GPU network)
+# --------------------------------------------------------------------------
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round to float32 (nearest even), then to bfloat16 (nearest even)."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def mlp_forward_bf16(p, X: np.ndarray):
+    """The forward pass with the roundings the GPU kernels make: inputs, W1,
+    W2 and both hidden activations in bfloat16; biases and the head W3 in
+    FP32; every sum exact (FP64) here."""
+    Xb = round_bf16(X)
+    z1 = Xb @ round_bf16(p["W1"]).T + _f32(p["b1"])
+    h1 = round_bf16(np.maximum(z1, 0.0))
+    z2 = h1 @ round_bf16(p["W2"]).T + _f32(p["b2"])
+    h2 = round_bf16(np.maximum(z2, 0.0))
+    o = h2 @ _f32(p["W3"]).T + _f32(p["b3"])
+    return o, dict(X=Xb, h1=h1, h2=h2)
+
+
+def loss_and_grad_bf16(p, X, logw_target, logtau_target):
+    """loss_and_grad with the GPU's roundings: the backpropagated signals into
+    the hidden layers (dZ2, dZ1) are rounded to bfloat16, as the kernels
+    store them."""
+    o, c = mlp_forward_bf16(p, X)
+    n = X.shape[0]
+    sp = softplus(o[:, 0])
+    r1 = np.log(sp) - logw_target
+    r2 = o[:, 1] - logtau_target
+    loss = float(np.mean(r1 ** 2 + r2 ** 2))
+    dO = np.zeros_like(o)
+    sig = 1.0 / (1.0 + np.exp(-o[:, 0]))
+    dO[:, 0] = 2.0 * r1 / n * sig / sp
+    dO[:, 1] = 2.0 * r2 / n
+    g = {}
+    g["W3"] = dO.T @ c["h2"]
+    g["b3"] = dO.sum(0)
+    dZ2 = round_bf16((dO @ _f32(p["W3"])) * (c["h2"] > 0))
+    g["W2"] = dZ2.T @ c["h1"]
+    g["b2"] = dZ2.sum(0)
+    dZ1 = round_bf16((dZ2 @ round_bf16(p["W2"])) * (c["h1"] > 0))
+    g["W1"] = dZ1.T @ c["X"]
+    g["b1"] = dZ1.sum(0)
+    return loss, g
+
+
+def pack(p) -> np.ndarray:
+    """Parameters in the packed order W1, b1, W2, b2, W3, b3 (FP64)."""
+    return np.concatenate([p["W1"].ravel(), p["b1"], p["W2"].ravel(), p["b2"], p["W3"].ravel(), p["b3"]])
+
+
+def unpack(v: np.ndarray):
+    v = np.asarray(v, dtype=np.float64)
+    o = 0
+    out = {}
+    for name, shape in (("W1", (HIDDEN, FEAT)), ("b1", (HIDDEN,)), ("W2", (HIDDEN, HIDDEN)), ("b2", (HIDDEN,)),
+                        ("W3", (2, HIDDEN)), ("b3", (2,))):
+        size = int(np.prod(shape))
+        out[name] = v[o:o + size].reshape(shape).copy()
+        o += size
+    return out

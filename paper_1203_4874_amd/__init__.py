@@ -20,7 +20,8 @@ import numpy as np
 
 __all__ = [
     "lib", "library_path", "CbpError", "Precision", "workspace_size", "eval_unit_circle",
-    "recover_kernels", "deblur", "deblur_batch", "Deblurrer", "decode_diag", "profile",
+    "recover_kernels", "deblur", "deblur_batch", "Deblurrer", "PreparedBatch", "decode_diag", "profile",
+    "Flags", "last_tuning", "sample_grams", "MlpState", "mlp_forward", "mlp_blob_from_params",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,6 +40,11 @@ class Precision:
     MIXED = 1
     MFMA32 = 2
     BF16 = 3
+
+
+class Flags:
+    GRAPH = 1      # capture the call's launches in a HIP graph, replay on later identical calls
+    AUTOTUNE = 2   # search the launch shapes of this batch class on its first call
 
 
 class CbpError(RuntimeError):
@@ -60,6 +66,11 @@ class CbpOptions(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("diag", ctypes.c_void_p)]
 
 
+class CbpTuning(ctypes.Structure):
+    _fields_ = [("fold_rows", ctypes.c_int32), ("strip_columns", ctypes.c_int32),
+                ("workgroups_per_cu", ctypes.c_int32), ("fft_order", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
 class CbpDiag(ctypes.Structure):
     _fields_ = [("k1", ctypes.c_int32), ("k2", ctypes.c_int32), ("S", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("refine_sample", ctypes.c_int32),
@@ -72,7 +83,9 @@ class CbpDiag(ctypes.Structure):
                 ("kernel_imag", ctypes.c_double * 2), ("kernel_outside", ctypes.c_double * 2),
                 ("sample_vec", ctypes.c_double * 2 * CBP_MAX_N * CBP_MAX_S * 2),
                 ("scale_vec", ctypes.c_double * 2 * (2 * CBP_MAX_S)),
-                ("khat", ctypes.c_double * 2 * CBP_MAX_S * CBP_MAX_S * 2)]
+                ("khat", ctypes.c_double * 2 * CBP_MAX_S * CBP_MAX_S * 2),
+                ("sample_features", ctypes.c_float * 32 * CBP_MAX_S * 2),
+                ("sample_weights", ctypes.c_double * (2 * CBP_MAX_S + 1))]
 
 
 _LIB = None
@@ -93,6 +106,23 @@ _SIGS = {
     "cbp_deblur_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage),
                                         ctypes.POINTER(CbpImage), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(CbpOptions)]),
+    "cbp_last_tuning": (ctypes.c_int, [ctypes.c_void_p]),
+    "cbp_sample_grams": (ctypes.c_int, [ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage), ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(CbpOptions)]),
+    "cbp_last_error": (ctypes.c_char_p, []),
+    "cbp_mlp_param_count": (ctypes.c_int32, []),
+    "cbp_mlp_blob_size": (ctypes.c_size_t, []),
+    "cbp_mlp_state_size": (ctypes.c_size_t, [ctypes.c_int32]),
+    "cbp_mlp_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "cbp_mlp_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "cbp_mlp_gradients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cbp_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int32, ctypes.c_float, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
+    "cbp_mlp_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "cbp_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "cbp_profile_enable": (None, [ctypes.c_int32]),
     "cbp_profile_reset": (None, []),
     "cbp_profile_read": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
@@ -149,6 +179,8 @@ def _precision_of(t) -> int:
 
 def _check(status: int, where: str):
     if status != 0:
+        if status == 4:
+            where = f"{where} [{lib().cbp_last_error().decode()}]"
         raise CbpError(status, where)
 
 
@@ -186,7 +218,9 @@ def decode_diag(buf: np.ndarray) -> dict:
                 kernel_imag=list(d.kernel_imag), kernel_outside=list(d.kernel_outside),
                 sample_vec=(sv[:, :S, :n, 0] + 1j * sv[:, :S, :n, 1]).copy(),
                 scale_vec=(scv[:2 * S, 0] + 1j * scv[:2 * S, 1]).copy(),
-                khat=(kh[:, :S, :S, 0] + 1j * kh[:, :S, :S, 1]).copy())
+                khat=(kh[:, :S, :S, 0] + 1j * kh[:, :S, :S, 1]).copy(),
+                sample_features=np.ctypeslib.as_array(d.sample_features).reshape(2, CBP_MAX_S, 32)[:, :S].copy(),
+                sample_weights=np.ctypeslib.as_array(d.sample_weights)[:2 * S + 1].copy())
 
 
 @dataclass
@@ -211,11 +245,15 @@ class Deblurrer:
         self.diag = torch.zeros(diag_size() * batch, dtype=torch.uint8, device=device) if diag else None
         self.batch = batch
 
-    def options(self, lam: float = 0.0, stream=None, precision=None) -> CbpOptions:
+    def options(self, lam: float = 0.0, stream=None, precision=None, flags: int = 0, mlp=None) -> CbpOptions:
         o = CbpOptions()
         o.precision = self.precision if precision is None else precision
         o.samples = self.samples
         o.lambda_ = lam
+        o.flags = flags
+        if mlp is not None:
+            o.learned = 1
+            o.mlp_blob = mlp.data_ptr()
         o.stream = _stream_ptr(stream)
         o.workspace = self.ws.data_ptr()
         o.workspace_bytes = self.ws.numel()
@@ -242,7 +280,9 @@ class Deblurrer:
                                          ctypes.byref(o)), "cbp_recover_kernels")
         return K1, K2
 
-    def deblur(self, b1, b2, m: int, n: int, lam: float = 0.0, out=None, K1=None, K2=None, stream=None):
+    def deblur(self, b1, b2, m: int, n: int, lam: float = 0.0, out=None, K1=None, K2=None, stream=None,
+               flags: int = 0, mlp=None):
+        """mlp: a device network blob (uint8 tensor, MlpState.export()) selects the learned form."""
         torch = _torch()
         i1, i2 = _image(b1), _image(b2)
         k1, k2 = i1.height - m + 1, i2.height - m + 1
@@ -254,36 +294,140 @@ class Deblurrer:
         if K2 is None:
             K2 = torch.empty((max(k2, 1), max(k2, 1)), dtype=torch.float64, device=b1.device)
         io = _image(out)
-        o = self.options(lam, stream, _precision_of(b1))
+        o = self.options(lam, stream, self.precision if self.precision >= 2 else _precision_of(b1), flags, mlp)
         _check(lib().cbp_deblur(ctypes.byref(i1), ctypes.byref(i2), ctypes.byref(io), K1.data_ptr(),
                                 K2.data_ptr(), ctypes.byref(o)), "cbp_deblur")
         return out, K1, K2
 
-    def deblur_batch(self, pairs, lam: float = 0.0, outs=None, stream=None):
+    def prepare_batch(self, pairs, lam: float = 0.0, outs=None, flags: int = 0, mlp=None) -> "PreparedBatch":
+        """pairs: list of (b1, b2, m, n).  Allocates the latents and kernels
+        once and marshals the argument arrays once; PreparedBatch.run() then
+        makes one cbp_deblur_batch call per invocation."""
+        return PreparedBatch(self, pairs, lam, outs, flags, mlp)
+
+    def deblur_batch(self, pairs, lam: float = 0.0, outs=None, stream=None, flags: int = 0):
         """pairs: list of (b1, b2, m, n).  Returns (latents, K1s, K2s, statuses)."""
+        pb = self.prepare_batch(pairs, lam, outs, flags)
+        st = pb.run(stream, check=True)
+        return pb.latents, pb.K1s, pb.K2s, st
+
+
+class PreparedBatch:
+    """Marshalled arguments of one cbp_deblur_batch call (see Deblurrer.prepare_batch)."""
+
+    def __init__(self, d: Deblurrer, pairs, lam, outs, flags, mlp=None):
         torch = _torch()
         nf = len(pairs)
-        I1 = (CbpImage * nf)()
-        I2 = (CbpImage * nf)()
-        IO = (CbpImage * nf)()
-        k1p = (ctypes.c_void_p * nf)()
-        k2p = (ctypes.c_void_p * nf)()
-        st = (ctypes.c_int * nf)()
-        latents, K1s, K2s = [], [], []
+        self.d, self.nf, self.lam, self.flags, self.mlp = d, nf, lam, flags, mlp
+        self.I1 = (CbpImage * nf)()
+        self.I2 = (CbpImage * nf)()
+        self.IO = (CbpImage * nf)()
+        self.k1p = (ctypes.c_void_p * nf)()
+        self.k2p = (ctypes.c_void_p * nf)()
+        self.st = (ctypes.c_int * nf)()
+        self.latents, self.K1s, self.K2s = [], [], []
+        self.pairs = pairs
         for f, (b1, b2, m, n) in enumerate(pairs):
-            I1[f], I2[f] = _image(b1), _image(b2)
-            k1, k2 = I1[f].height - m + 1, I2[f].height - m + 1
+            self.I1[f], self.I2[f] = _image(b1), _image(b2)
+            k1, k2 = self.I1[f].height - m + 1, self.I2[f].height - m + 1
             out = outs[f] if outs is not None else torch.empty(
                 (m, n) if b1.dim() == 2 else (b1.shape[0], m, n), dtype=b1.dtype, device=b1.device)
             K1 = torch.empty((max(k1, 1), max(k1, 1)), dtype=torch.float64, device=b1.device)
             K2 = torch.empty((max(k2, 1), max(k2, 1)), dtype=torch.float64, device=b1.device)
-            IO[f] = _image(out)
-            k1p[f], k2p[f] = K1.data_ptr(), K2.data_ptr()
-            latents.append(out); K1s.append(K1); K2s.append(K2)
-        o = self.options(lam, stream, _precision_of(pairs[0][0]))
-        s = lib().cbp_deblur_batch(nf, I1, I2, IO, k1p, k2p, st, ctypes.byref(o))
-        _check(s, "cbp_deblur_batch")
-        return latents, K1s, K2s, list(st)
+            self.IO[f] = _image(out)
+            self.k1p[f], self.k2p[f] = K1.data_ptr(), K2.data_ptr()
+            self.latents.append(out)
+            self.K1s.append(K1)
+            self.K2s.append(K2)
+        self.precision = d.precision if d.precision >= 2 else _precision_of(pairs[0][0])
+
+    def run(self, stream=None, check: bool = True):
+        o = self.d.options(self.lam, stream, self.precision, self.flags, self.mlp)
+        s = lib().cbp_deblur_batch(self.nf, self.I1, self.I2, self.IO, self.k1p, self.k2p, self.st,
+                                   ctypes.byref(o))
+        if check:
+            _check(s, "cbp_deblur_batch")
+        return list(self.st)
+
+
+class MlpState:
+    """Training state of the learned form's network (device memory owned
+    here): FP32 master weights, Adam moments, bf16 copies and the activations
+    of up to max_rows rows.  Every step runs in the library's kernels."""
+
+    def __init__(self, max_rows: int, device="cuda"):
+        torch = _torch()
+        self.rows = int(max_rows)
+        nbytes = int(lib().cbp_mlp_state_size(self.rows))
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.device = device
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib().cbp_mlp_param_count())
+
+    def set_params(self, params, stream=None):
+        torch = _torch()
+        p = torch.as_tensor(params, dtype=torch.float32, device=self.device).contiguous()
+        _check(lib().cbp_mlp_set_params(self.buf.data_ptr(), self.rows, p.data_ptr(), _stream_ptr(stream)),
+               "cbp_mlp_set_params")
+        self._keep = p
+
+    def get_params(self, stream=None):
+        torch = _torch()
+        p = torch.empty(self.param_count(), dtype=torch.float32, device=self.device)
+        _check(lib().cbp_mlp_get_params(self.buf.data_ptr(), self.rows, p.data_ptr(), _stream_ptr(stream)),
+               "cbp_mlp_get_params")
+        return p
+
+    def gradients(self, X, T, stream=None):
+        """(loss, grads) of the mean loss on rows X [n][32], targets T [n][2]."""
+        torch = _torch()
+        g = torch.empty(self.param_count(), dtype=torch.float32, device=self.device)
+        _check(lib().cbp_mlp_gradients(self.buf.data_ptr(), self.rows, X.data_ptr(), T.data_ptr(), X.shape[0],
+                                       self.loss.data_ptr(), g.data_ptr(), _stream_ptr(stream)),
+               "cbp_mlp_gradients")
+        return self.loss, g
+
+    def train_step(self, X, T, lr: float, step: int, stream=None):
+        _check(lib().cbp_mlp_train_step(self.buf.data_ptr(), self.rows, X.data_ptr(), T.data_ptr(), X.shape[0],
+                                        float(lr), int(step), self.loss.data_ptr(), _stream_ptr(stream)),
+               "cbp_mlp_train_step")
+        return self.loss
+
+    def export(self, stream=None):
+        """The inference blob (uint8 device tensor) for the learned form."""
+        torch = _torch()
+        blob = torch.zeros(int(lib().cbp_mlp_blob_size()), dtype=torch.uint8, device=self.device)
+        _check(lib().cbp_mlp_export(self.buf.data_ptr(), self.rows, blob.data_ptr(), _stream_ptr(stream)),
+               "cbp_mlp_export")
+        return blob
+
+
+def mlp_forward(blob, X, stream=None):
+    """Network outputs (o1, o2) [n][2] FP32 for feature rows X [n][32] (FP32 device)."""
+    torch = _torch()
+    out = torch.empty((X.shape[0], 2), dtype=torch.float32, device=X.device)
+    _check(lib().cbp_mlp_forward(blob.data_ptr(), X.data_ptr(), X.shape[0], out.data_ptr(), _stream_ptr(stream)),
+           "cbp_mlp_forward")
+    return out
+
+
+def mlp_blob_from_params(params, device="cuda"):
+    """Inference blob from packed FP32 parameters (through a one-row state)."""
+    st = MlpState(1, device)
+    st.set_params(params)
+    return st.export()
+
+
+def last_tuning():
+    """Launch shapes of the last autotune search on the current device, or None."""
+    t = CbpTuning()
+    if lib().cbp_last_tuning(ctypes.byref(t)) != 0:
+        return None
+    return dict(fold_rows=t.fold_rows, strip_columns=t.strip_columns,
+                workgroups_per_cu=t.workgroups_per_cu, fft_order=t.fft_order, ms=t.ms)
 
 
 def _one_shot(b1, b2, m, n, samples, diag):
@@ -312,6 +456,24 @@ def eval_unit_circle(b, S: int, stream=None):
     return ex, ey
 
 
+def sample_grams(b1, b2, m: int, n: int, precision=None, samples: int = 0, stream=None):
+    """Per-sample Gram matrices, complex128 device tensor (2, S, N, N):
+    [pass][sample][p][q] with unknowns ordered (u: k2 entries, v: k1)."""
+    torch = _torch()
+    i1, i2 = _image(b1), _image(b2)
+    k1, k2 = i1.height - m + 1, i2.height - m + 1
+    S = samples or max(k1, k2)
+    N = k1 + k2
+    prec = _precision_of(b1) if precision is None else precision
+    d = Deblurrer(max(i1.height, i2.height), max(i1.width, i2.width), max(1, min(max(k1, k2), CBP_MAX_K)),
+                  i1.channels, 1, prec, samples, b1.device)
+    G = torch.empty((2, S, N, N), dtype=torch.complex128, device=b1.device)
+    o = d.options(0.0, stream, prec)
+    _check(lib().cbp_sample_grams(ctypes.byref(i1), ctypes.byref(i2), m, n, G.data_ptr(), ctypes.byref(o)),
+           "cbp_sample_grams")
+    return G
+
+
 def recover_kernels(b1, b2, m: int, n: int, samples: int = 0, diag: bool = False):
     d = _one_shot(b1, b2, m, n, samples, diag)
     K1, K2 = d.recover_kernels(b1, b2, m, n)
@@ -324,7 +486,7 @@ def deblur(b1, b2, m: int, n: int, samples: int = 0, lam: float = 0.0, diag: boo
     return (L, K1, K2, d.read_diag()) if diag else (L, K1, K2)
 
 
-def deblur_batch(pairs, samples: int = 0, lam: float = 0.0):
+def deblur_batch(pairs, samples: int = 0, lam: float = 0.0, flags: int = 0):
     torch = _torch()
     H = max(max(p[0].shape[-2], p[1].shape[-2]) for p in pairs)
     W = max(max(p[0].shape[-1], p[1].shape[-1]) for p in pairs)
@@ -332,7 +494,7 @@ def deblur_batch(pairs, samples: int = 0, lam: float = 0.0):
     ch = 1 if pairs[0][0].dim() == 2 else pairs[0][0].shape[0]
     d = Deblurrer(H, W, max(1, min(k, CBP_MAX_K)), ch, len(pairs), _precision_of(pairs[0][0]), samples,
                   pairs[0][0].device)
-    return d.deblur_batch(pairs, lam)
+    return d.deblur_batch(pairs, lam, flags=flags)
 
 
 class profile:

@@ -1,25 +1,30 @@
 // C ABI of the CBP library (declared in include/cbp.h): host-side validation,
-// frame plans and workspace layout, the launch chain, and phase timing.
+// frame plans and workspace layout, the launch chains (one frame; a batch of
+// frames through work-list launches; a batch captured as a HIP graph), the
+// batch autotuner, and phase timing.
 //
 // Every status returned here comes from host-side checks made before the
 // first HIP call of the entry point, so invalid arguments never reach a
 // kernel.  Launch failures are reported as CBP_E_DEVICE.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "internal.h"
+#include "mlp.h"
 
 namespace cbp {
-
-size_t finalize_lds_bytes(int S);
-size_t sample_lds_bytes(int N);
-size_t row_lds_bytes(int N, int esize);
-size_t col_lds_bytes(int N, int cw, int esize);
 
 namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsLimit = 160 * 1024;
+constexpr int kComputeUnits = 256;
+constexpr int32_t kKnownFlags = CBP_FLAG_GRAPH | CBP_FLAG_AUTOTUNE;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
@@ -37,7 +42,7 @@ int smooth7(int n) {
 // for any frame within (maxH, maxW, maxk, S, nch) fits the size that
 // cbp_workspace_size() reports for those bounds.
 struct region_sizes {
-  size_t fpart, ex, ey, corr, xvec, lam0, pq, cbuf, kern, t, u;
+  size_t fpart, ex, ey, corr, xvec, lam0, pq, cbuf, kern, t, u, feat, wts;
 };
 
 region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
@@ -56,6 +61,8 @@ region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
   r.kern = 2 * (size_t)CBP_MAX_K * CBP_MAX_K * sizeof(double);
   r.t = (size_t)nch * Hmax * hx * 2 * esize;
   r.u = (size_t)nch * Hmax * hx * 2 * esize;
+  r.feat = 2 * (size_t)S * 32 * sizeof(float);
+  r.wts = (2 * (size_t)S + 1) * sizeof(double);
   return r;
 }
 
@@ -74,17 +81,38 @@ size_t layout(frame_plan* fp, const region_sizes& r) {
   fp->off_t1 = take(r.t);
   fp->off_t2 = take(r.t);
   fp->off_u = take(r.u);
+  fp->off_feat = take(r.feat);
+  fp->off_wts = take(r.wts);
   fp->total = o;
   return o;
 }
 
+int nchunks(int nframes) { return (nframes + BATCH_CHUNK - 1) / BATCH_CHUNK; }
+
+// Workspace head: the frame descriptors and per-queue item prefix sums of a
+// batched call (frames follow it).
+size_t head_desc_bytes(int nframes) { return align_up((size_t)nframes * sizeof(frame_desc)); }
+size_t head_bytes(int nframes) {
+  return head_desc_bytes(nframes) +
+         align_up((size_t)nchunks(nframes) * Q_COUNT * (BATCH_CHUNK + 1) * sizeof(int));
+}
+
 int max_fft(int esize) { return esize == 4 ? CBP_MAX_FFT_F32 : CBP_MAX_FFT_F64; }
 
-// Choose the column-pass strip width: as wide as LDS allows, but keep at
-// least ~128 workgroups per channel when the spectrum is narrow.
-int choose_cw(int Py, int hx, int esize) {
-  int cw = 4;
-  while (cw > 1 && (col_lds_bytes(Py, cw, esize) > kLdsLimit - 4096 || (hx + cw - 1) / cw < 128)) cw >>= 1;
+// ---------------------------------------------------------------- tuning
+// Launch-shape knobs of one batch class, chosen by the autotuner.
+struct tuning {
+  int fold_rows;   // target rows per column-fold group (rounded up to a multiple of S; >= 32)
+  int cw;          // columns per column-pass strip (0: widest that fits and keeps >= 128 strips)
+  int wg_per_cu;   // persistent-grid cap of the streaming queues, workgroups per CU (0: one per item)
+  int fft_order;   // radix pass order of the row and column FFTs
+};
+constexpr tuning kDefaultTuning = {32, 0, 0, 0};
+
+int choose_cw(int Py, int hx, int esize, int want) {
+  int cw = want > 0 ? want : 4;
+  while (cw > 1 && (col_lds_bytes(Py, cw, esize) > kLdsLimit - 4096 || (want <= 0 && (hx + cw - 1) / cw < 128)))
+    cw >>= 1;
   return cw;
 }
 
@@ -99,17 +127,23 @@ bool valid_image(const cbp_image* im) {
 
 cbp_status check_options(const cbp_options* o, int dtype) {
   if (!o) return CBP_E_INVALID;
-  if (!(o->lambda >= 0.0) || o->tau != 0.0 || o->learned != 0 || o->flags != 0 || o->mlp_blob != nullptr)
-    return o->learned != 0 || o->mlp_blob != nullptr ? CBP_E_UNSUPPORTED : CBP_E_INVALID;
+  if ((o->learned != 0) != (o->mlp_blob != nullptr)) return CBP_E_INVALID;   // the learned form needs its network
+  if (!(o->lambda >= 0.0) || o->tau != 0.0 || (o->flags & ~kKnownFlags) != 0) return CBP_E_INVALID;
   if (o->precision == CBP_PREC_FP64) return dtype == CBP_F64 ? CBP_OK : CBP_E_INVALID;
-  if (o->precision == CBP_PREC_MIXED) return dtype == CBP_F32 ? CBP_OK : CBP_E_INVALID;
-  if (o->precision == CBP_PREC_MFMA32 || o->precision == CBP_PREC_BF16) return CBP_E_UNSUPPORTED;
+  if (o->precision == CBP_PREC_MIXED || o->precision == CBP_PREC_MFMA32 || o->precision == CBP_PREC_BF16)
+    return dtype == CBP_F32 ? CBP_OK : CBP_E_INVALID;
   return CBP_E_INVALID;
+}
+
+// Gram route of a precision form: -1 = double-double correlations (FP64,
+// MIXED), 0 = matrix cores on FP32 operands (MFMA32), 1 = on bfloat16 (BF16).
+int gram_format(int precision) {
+  return precision == CBP_PREC_MFMA32 ? 0 : precision == CBP_PREC_BF16 ? 1 : -1;
 }
 
 // Shapes -> plan.  All checks are host-side.
 cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, const cbp_options* o,
-                     frame_plan* fp) {
+                     const tuning& tn, frame_plan* fp) {
   if (!valid_image(b1) || !valid_image(b2)) return CBP_E_INVALID;
   if (b1->dtype != b2->dtype || b1->channels != b2->channels) return CBP_E_INVALID;
   const cbp_status so = check_options(o, b1->dtype);
@@ -127,32 +161,67 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
   fp->Wmax = fp->W1 > fp->W2 ? fp->W1 : fp->W2;
   fp->m = m; fp->n = n; fp->k1 = k1; fp->k2 = k2; fp->S = S; fp->N = k1 + k2;
   fp->nch = b1->channels;
-  fp->rpg = S * ((32 + S - 1) / S);
+  const int rows = tn.fold_rows > 32 ? tn.fold_rows : 32;
+  fp->rpg = S * ((rows + S - 1) / S);
   fp->RG = (fp->Hmax + fp->rpg - 1) / fp->rpg;
   fp->Py = smooth7(fp->Hmax);
   fp->Px = smooth7(fp->Wmax);
   if (fp->Py > max_fft(esize) || fp->Px > max_fft(esize)) return CBP_E_SHAPE;
-  if (!make_fft_plan(fp->Py, &fp->fy) || !make_fft_plan(fp->Px, &fp->fx)) return CBP_E_SHAPE;
+  if (!make_fft_plan(fp->Py, &fp->fy, tn.fft_order) || !make_fft_plan(fp->Px, &fp->fx, tn.fft_order))
+    return CBP_E_SHAPE;
   fp->hx = fp->Px / 2 + 1;
-  fp->cw = choose_cw(fp->Py, fp->hx, esize);
-  if (sample_lds_bytes(fp->N) > kLdsLimit || finalize_lds_bytes(S) > kLdsLimit ||
-      row_lds_bytes(fp->Px, esize) > kLdsLimit || col_lds_bytes(fp->Py, fp->cw, esize) > kLdsLimit)
+  fp->cw = choose_cw(fp->Py, fp->hx, esize, tn.cw);
+  const int gfmt = gram_format(o->precision);
+  if (gfmt >= 0 && (fp->N > 32 || gram_mfma_lds_bytes(std::max(fp->Hmax, fp->Wmax), gfmt) > kLdsLimit - 2048))
+    return CBP_E_UNSUPPORTED;
+  if (o->learned && fp->N > 32) return CBP_E_UNSUPPORTED;   // 32 spectrum features per sample
+  if (sample_lds_bytes(fp->N) > kLdsLimit - 2048 || finalize_lds_bytes(S, o->learned != 0) > kLdsLimit - 2048 ||
+      row_lds_bytes(fp->Px, esize) > kLdsLimit - 2048 || col_lds_bytes(fp->Py, fp->cw, esize) > kLdsLimit - 2048)
     return CBP_E_SHAPE;
   layout(fp, regions(fp->Hmax, fp->Wmax, kmax, S, fp->nch, esize));
   return CBP_OK;
 }
 
-template <typename T>
-pair_view<T> view_of(const cbp_image* b1, const cbp_image* b2) {
-  pair_view<T> v;
-  v.b1 = (const T*)b1->data;
-  v.b2 = (const T*)b2->data;
-  v.p1 = b1->pitch; v.p2 = b2->pitch;
-  v.cs1 = b1->channels > 1 ? b1->channel_stride : 0;
-  v.cs2 = b2->channels > 1 ? b2->channel_stride : 0;
-  v.H1 = b1->height; v.W1 = b1->width; v.H2 = b2->height; v.W2 = b2->width;
-  v.nch = b1->channels;
-  return v;
+frame_desc make_desc(const frame_plan& fp, const cbp_image* b1, const cbp_image* b2, char* ws, double* K1,
+                     double* K2, const cbp_image* latent, double lambda, void* diag, bool learned) {
+  frame_desc d;
+  std::memset(&d, 0, sizeof d);
+  d.b1 = b1->data;
+  d.b2 = b2->data;
+  d.p1 = b1->pitch;
+  d.p2 = b2->pitch;
+  d.cs1 = b1->channels > 1 ? b1->channel_stride : 0;
+  d.cs2 = b2->channels > 1 ? b2->channel_stride : 0;
+  d.H1 = fp.H1; d.W1 = fp.W1; d.H2 = fp.H2; d.W2 = fp.W2; d.Hmax = fp.Hmax; d.Wmax = fp.Wmax;
+  d.nch = fp.nch;
+  d.ncf = 2 * fp.nch;
+  d.m = fp.m; d.n = fp.n; d.k1 = fp.k1; d.k2 = fp.k2; d.S = fp.S; d.N = fp.N;
+  d.rpg = fp.rpg; d.RG = fp.RG; d.Py = fp.Py; d.Px = fp.Px; d.hx = fp.hx; d.cw = fp.cw;
+  d.fy = fp.fy;
+  d.fx = fp.fx;
+  d.fpart = (double*)(ws + fp.off_fpart);
+  d.ex = (c64*)(ws + fp.off_ex);
+  d.ey = (c64*)(ws + fp.off_ey);
+  d.corr = (cdd*)(ws + fp.off_corr);
+  d.xvec = (c64*)(ws + fp.off_xvec);
+  d.lam0 = (double*)(ws + fp.off_lam0);
+  d.pq = (c64*)(ws + fp.off_pq);
+  d.cbuf = (cdd*)(ws + fp.off_cbuf);
+  d.t1 = ws + fp.off_t1;
+  d.t2 = ws + fp.off_t2;
+  d.u = ws + fp.off_u;
+  d.K1 = K1 ? K1 : (double*)(ws + fp.off_kern);
+  d.K2 = K2 ? K2 : (double*)(ws + fp.off_kern) + CBP_MAX_K * CBP_MAX_K;
+  if (latent) {
+    d.out = latent->data;
+    d.opitch = latent->pitch;
+    d.ocs = latent->channels > 1 ? latent->channel_stride : 0;
+  }
+  d.lambda = lambda;
+  d.diag = (cbp_diag*)diag;
+  d.feat = (learned || diag) ? (float*)(ws + fp.off_feat) : nullptr;
+  d.wts = learned ? (double*)(ws + fp.off_wts) : nullptr;
+  return d;
 }
 
 // ---------------------------------------------------------------- phase timing state
@@ -183,87 +252,490 @@ profiler& prof() {
   return p;
 }
 
+thread_local bool t_capturing = false;  // no timing events inside a graph capture
+
+// The HIP call that made the last CBP_E_DEVICE of this thread (cbp_last_error).
+thread_local char t_error[256] = "";
+
+hipError_t note(const char* what, hipError_t e) {
+  if (e != hipSuccess) std::snprintf(t_error, sizeof t_error, "%s: %s", what, hipGetErrorString(e));
+  return e;
+}
+#define CBP_TRY(expr)                                     \
+  do {                                                    \
+    const hipError_t e_ = note(#expr, (expr));            \
+    if (e_ != hipSuccess) return e_;                      \
+  } while (0)
+
 const char* kPhaseNames[PH_COUNT] = {"fold_cols", "eval_cols", "eval_rows", "gram", "sample_eig",
                                      "scale_assemble", "row_fft_fwd", "col_fft_filter", "row_fft_inv"};
 
-// Side stream and fork/join events of one device (created once; default
-// priority).  The row fold and the row FFT depend only on the input frames,
-// so they run on the side stream beside the column fold -> Gram ->
-// eigen-solve chain, which occupies few compute units.
-struct fork_state {
-  std::mutex launch_mu;   // one launch sequence at a time per device (the events are shared)
+// ---------------------------------------------------------------- per-device state
+// Pinned host staging for the descriptor upload of an eager batched call;
+// a slot is reused only after the copy recorded on it has completed.
+struct pinned_slot {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool recorded = false;
+};
+constexpr int kRing = 16;
+
+struct graph_entry {
+  hipGraphExec_t exec = nullptr;
+  void* host = nullptr;  // pinned copy of the workspace head the graph uploads on every replay
+  uint64_t last_use = 0;
+};
+constexpr size_t kMaxGraphs = 32;
+
+// Side stream, events, staging ring, graph and tuning caches of one device
+// (created once; every stream at the default priority).  The row pass
+// depends only on the input frames, so it runs on the side stream beside the
+// column fold -> Gram -> eigen-solve chain, which occupies few compute units.
+struct dev_state {
+  std::mutex launch_mu;  // one launch sequence at a time per device (the events are shared)
   bool ready = false;
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_rows = nullptr, ev_fft = nullptr;
+  hipStream_t side = nullptr, cap = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_side = nullptr, t0 = nullptr, t1 = nullptr;
+  pinned_slot ring[kRing];
+  int next = 0;
+  std::map<std::string, graph_entry> graphs;
+  uint64_t tick = 0;
+  std::map<std::string, tuning> tuned;
+  bool have_last = false;
+  cbp_tuning last = {};
 };
 
-fork_state* get_fork() {
+dev_state* get_dev() {
   static std::mutex mu;
-  static fork_state states[64];
+  static dev_state states[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
   std::lock_guard<std::mutex> g(mu);
-  fork_state& f = states[dev];
+  dev_state& f = states[dev];
   if (!f.ready) {
-    if (hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&f.ev_fork, hipEventDisableTiming) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&f.ev_rows, hipEventDisableTiming) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&f.ev_fft, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (note("hipStreamCreateWithFlags", hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking)) != hipSuccess ||
+        note("hipStreamCreateWithFlags", hipStreamCreateWithFlags(&f.cap, hipStreamNonBlocking)) != hipSuccess ||
+        note("hipEventCreateWithFlags", hipEventCreateWithFlags(&f.ev_fork, hipEventDisableTiming)) != hipSuccess ||
+        note("hipEventCreateWithFlags", hipEventCreateWithFlags(&f.ev_side, hipEventDisableTiming)) != hipSuccess ||
+        note("hipEventCreate", hipEventCreate(&f.t0)) != hipSuccess ||
+        note("hipEventCreate", hipEventCreate(&f.t1)) != hipSuccess)
+      return nullptr;
+    for (pinned_slot& s : f.ring)
+      if (note("hipEventCreateWithFlags", hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess)
+        return nullptr;
+    set_recover_attrs();
+    set_fft_attrs();
+    set_gram_mfma_attrs();
     f.ready = true;
   }
   return &f;
 }
 
-template <typename T>
-cbp_status run_frame(const cbp_image* b1, const cbp_image* b2, const frame_plan& fp, char* ws, double* K1,
-                     double* K2, cbp_image* latent, const cbp_options* o, void* diag) {
-  hipStream_t st = (hipStream_t)o->stream;
-  const pair_view<T> v = view_of<T>(b1, b2);
-  double* k1 = K1 ? K1 : (double*)(ws + fp.off_kern);
-  double* k2 = K2 ? K2 : (double*)(ws + fp.off_kern) + CBP_MAX_K * CBP_MAX_K;
-  fork_state* f = get_fork();
-  if (!f) return CBP_E_DEVICE;
-  std::lock_guard<std::mutex> launch_lock(f->launch_mu);
-  hipStream_t side = f->side;
-  // fork
-  if (hipEventRecord(f->ev_fork, st) != hipSuccess) return CBP_E_DEVICE;
-  if (hipStreamWaitEvent(side, f->ev_fork, 0) != hipSuccess) return CBP_E_DEVICE;
-  if (launch_eval_rows<T>(v, fp, ws, side) != hipSuccess) return CBP_E_DEVICE;
-  if (hipEventRecord(f->ev_rows, side) != hipSuccess) return CBP_E_DEVICE;
-  if (latent && launch_row_fwd<T>(v, fp, ws, side) != hipSuccess) return CBP_E_DEVICE;
-  if (hipEventRecord(f->ev_fft, side) != hipSuccess) return CBP_E_DEVICE;
-  // main chain
-  if (launch_eval_cols<T>(v, fp, ws, st) != hipSuccess) return CBP_E_DEVICE;
-  if (hipStreamWaitEvent(st, f->ev_rows, 0) != hipSuccess) return CBP_E_DEVICE;
-  if (launch_recover(fp, ws, k1, k2, diag, st) != hipSuccess) return CBP_E_DEVICE;
-  // join (also when no latent is produced, so the side stream never runs ahead of the next call)
-  if (hipStreamWaitEvent(st, f->ev_fft, 0) != hipSuccess) return CBP_E_DEVICE;
-  if (latent) {
-    const int64_t ocs = latent->channels > 1 ? latent->channel_stride : 0;
-    if (launch_col_inv<T>(v, fp, ws, k1, k2, (T*)latent->data, latent->pitch, ocs, o->lambda, st) != hipSuccess)
-      return CBP_E_DEVICE;
-  }
-  return CBP_OK;
+// ---------------------------------------------------------------- launch chain
+// One launch of every queue over a set of frames: either one frame (one !=
+// nullptr, descs == nullptr) or a chunk of a batch.
+struct chunk_view {
+  const frame_desc* one;
+  const frame_desc* descs;  // device
+  const int* starts;        // device
+  int nf;
+  int items[Q_COUNT];
+  int grid[Q_COUNT];
+  int maxN, maxS, maxPx, maxPy, maxcw;
+  int gram_fmt;   // gram_format() of the call's precision
+  int maxStride;  // largest Hmax / Wmax (matrix-core Gram staging)
+  const void* mlp;  // the learned form's network (device mlp blob) or NULL
+};
+
+int grid_for(int items, int cap) {
+  int g = items;
+  if (cap > 0 && g > cap) g = cap;
+  if (g >= 64) g = (g + 7) & ~7;  // a multiple of 8: XCD-aware item ranges
+  return g < 1 ? 1 : g;
 }
 
+template <typename T>
+hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool diag, hipStream_t st) {
+  static const frame_desc zero = {};
+  const frame_desc& one = cv.one ? *cv.one : zero;
+  auto br = [&](int q) {
+    return cv.descs ? batch_ref{cv.descs, cv.starts, cv.nf} : batch_ref{nullptr, nullptr, cv.items[q]};
+  };
+  hipStream_t side = ds.side;
+  CBP_TRY(hipEventRecord(ds.ev_fork, st));
+  CBP_TRY(hipStreamWaitEvent(side, ds.ev_fork, 0));
+  if (latent) CBP_TRY(launch_row_fwd<T>(one, br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, side));
+  else CBP_TRY(launch_eval_rows<T>(one, br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], side));
+  CBP_TRY(hipEventRecord(ds.ev_side, side));
+  if (diag) CBP_TRY(launch_diag_init(one, br(Q_DIAG), cv.grid[Q_DIAG], st));
+  CBP_TRY(launch_fold<T>(one, br(Q_FOLD), cv.grid[Q_FOLD], st));
+  CBP_TRY(launch_eval_cols(one, br(Q_EVAL_COLS), cv.grid[Q_EVAL_COLS], st));
+  // join: the Gram needs the row evaluation (and the column pass the row spectra)
+  CBP_TRY(hipStreamWaitEvent(st, ds.ev_side, 0));
+  if (cv.gram_fmt < 0) CBP_TRY(launch_gram(one, br(Q_GRAM), cv.grid[Q_GRAM], st));
+  else CBP_TRY(launch_gram_mfma(one, br(Q_GRAMM), cv.grid[Q_GRAMM], cv.gram_fmt, cv.maxStride, st));
+  CBP_TRY(launch_sample(one, br(Q_SAMPLE), cv.grid[Q_SAMPLE], cv.maxN, st));
+  if (cv.mlp) CBP_TRY(launch_mlp_frames(one, br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.mlp, st));
+  CBP_TRY(launch_finalize(one, br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, cv.mlp != nullptr, st));
+  if (latent) {
+    CBP_TRY(launch_col<T>(one, br(Q_COL), cv.grid[Q_COL], cv.maxPy, cv.maxcw, st));
+    CBP_TRY(launch_row_inv<T>(one, br(Q_ROW_INV), cv.grid[Q_ROW_INV], cv.maxPx, st));
+  }
+  return hipSuccess;
+}
+
+hipError_t enqueue(dev_state& ds, int dtype, const chunk_view& cv, bool latent, bool diag, hipStream_t st) {
+  return dtype == CBP_F32 ? enqueue_chunk<float>(ds, cv, latent, diag, st)
+                          : enqueue_chunk<double>(ds, cv, latent, diag, st);
+}
+
+// ---------------------------------------------------------------- one frame
 cbp_status frame_call(const cbp_image* b1, const cbp_image* b2, cbp_image* latent, int m, int n, double* K1,
                       double* K2, const cbp_options* o, char* ws, size_t ws_bytes, void* diag) {
   frame_plan fp;
-  const cbp_status s = make_plan(b1, b2, m, n, o, &fp);
+  const cbp_status s = make_plan(b1, b2, m, n, o, kDefaultTuning, &fp);
   if (s != CBP_OK) return s;
   if (latent) {
     if (!valid_image(latent) || latent->dtype != b1->dtype || latent->channels != b1->channels) return CBP_E_INVALID;
   }
-  if (!ws || ws_bytes < fp.total) return CBP_E_NOMEM;
-  if (b1->dtype == CBP_F32) return run_frame<float>(b1, b2, fp, ws, K1, K2, latent, o, diag);
-  return run_frame<double>(b1, b2, fp, ws, K1, K2, latent, o, diag);
+  const size_t head = head_bytes(1);
+  if (!ws || ws_bytes < head + fp.total) return CBP_E_NOMEM;
+  dev_state* ds = get_dev();
+  if (!ds) return CBP_E_DEVICE;
+  const frame_desc d = make_desc(fp, b1, b2, ws + head, K1, K2, latent, o->lambda, diag, o->learned != 0);
+  chunk_view cv = {};
+  cv.one = &d;
+  for (int q = 0; q < Q_COUNT; ++q) {
+    cv.items[q] = queue_items(q, fp);
+    cv.grid[q] = grid_for(cv.items[q], 0);
+  }
+  cv.maxN = fp.N; cv.maxS = fp.S; cv.maxPx = fp.Px; cv.maxPy = fp.Py; cv.maxcw = fp.cw;
+  cv.gram_fmt = gram_format(o->precision);
+  cv.maxStride = std::max(fp.Hmax, fp.Wmax);
+  cv.mlp = o->learned ? o->mlp_blob : nullptr;
+  std::lock_guard<std::mutex> lk(ds->launch_mu);
+  (void)hipGetLastError();  // launch errors below are read with hipGetLastError: start clean
+  return enqueue(*ds, b1->dtype, cv, latent != nullptr, diag != nullptr, (hipStream_t)o->stream) == hipSuccess
+             ? CBP_OK
+             : CBP_E_DEVICE;
+}
+
+// ---------------------------------------------------------------- batches
+struct frame_req {
+  const cbp_image* b1;
+  const cbp_image* b2;
+  cbp_image* latent;
+  int m, n;
+  double* K1;
+  double* K2;
+  void* diag;
+};
+
+// Plans, descriptors and launch shapes of the valid frames of one batch.
+struct batch_build {
+  int dtype = CBP_F32;
+  bool latent = false, diag = false;
+  std::vector<int> idx;            // request index of each valid frame
+  std::vector<frame_plan> plans;
+  std::vector<char> head;          // bytes uploaded to the workspace head
+  std::vector<chunk_view> chunks;  // device pointers into the head
+  char* head_dev = nullptr;
+};
+
+// Class of a batch for the tuning cache: dtype, frame count, latent, and the
+// largest frame, kernel and channel count.
+std::string class_key(const std::vector<frame_req>& reqs, const cbp_options* o) {
+  int H = 0, W = 0, k = 0, ch = 0, dt = reqs.empty() ? 0 : reqs[0].b1->dtype;
+  for (const frame_req& r : reqs) {
+    H = std::max({H, r.b1->height, r.b2->height});
+    W = std::max({W, r.b1->width, r.b2->width});
+    k = std::max({k, r.b1->height - r.m + 1, r.b2->height - r.m + 1});
+    ch = std::max(ch, r.b1->channels);
+  }
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%d/%zu/%d/%d/%d/%d/%d/%d/%d", dt, reqs.size(), reqs.empty() ? 0 : reqs[0].latent != nullptr,
+                H, W, k, ch, o->samples, o->precision);
+  return buf;
+}
+
+// Validate and plan every frame; statuses go to `status` (one per request).
+// Returns CBP_E_NOMEM when the valid frames do not fit the workspace.
+cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o, const tuning& tn,
+                       std::vector<cbp_status>& status, batch_build* bb) {
+  const int nreq = (int)reqs.size();
+  status.assign(nreq, CBP_OK);
+  bb->idx.clear();
+  bb->plans.clear();
+  bb->chunks.clear();
+  const int dtype = reqs[0].b1 ? reqs[0].b1->dtype : -1;
+  const bool latent = reqs[0].latent != nullptr;
+  for (int f = 0; f < nreq; ++f) {
+    const frame_req& r = reqs[f];
+    frame_plan fp;
+    cbp_status s = make_plan(r.b1, r.b2, r.m, r.n, o, tn, &fp);
+    if (s == CBP_OK && r.b1->dtype != dtype) s = CBP_E_INVALID;
+    if (s == CBP_OK && (r.latent != nullptr) != latent) s = CBP_E_INVALID;
+    if (s == CBP_OK && latent &&
+        (!valid_image(r.latent) || r.latent->dtype != dtype || r.latent->channels != r.b1->channels ||
+         r.latent->height != r.m || r.latent->width != r.n))
+      s = CBP_E_INVALID;
+    status[f] = s;
+    if (s == CBP_OK) {
+      bb->idx.push_back(f);
+      bb->plans.push_back(fp);
+    }
+  }
+  const int nf = (int)bb->idx.size();
+  bb->dtype = dtype;
+  bb->latent = latent;
+  bb->diag = o->diag != nullptr;
+  if (nf == 0) return CBP_OK;
+  const size_t head = head_bytes(nf);
+  size_t need = head;
+  for (const frame_plan& fp : bb->plans) need += fp.total;
+  if (!o->workspace || o->workspace_bytes < need) {
+    for (int f : bb->idx) status[f] = CBP_E_NOMEM;
+    return CBP_E_NOMEM;
+  }
+  char* ws = (char*)o->workspace;
+  bb->head_dev = ws;
+  bb->head.assign(head, 0);
+  frame_desc* descs = (frame_desc*)bb->head.data();
+  int* starts = (int*)(bb->head.data() + head_desc_bytes(nf));
+  size_t off = head;
+  for (int i = 0; i < nf; ++i) {
+    const frame_req& r = reqs[bb->idx[i]];
+    descs[i] = make_desc(bb->plans[i], r.b1, r.b2, ws + off, r.K1, r.K2, r.latent, o->lambda, r.diag,
+                         o->learned != 0);
+    off += bb->plans[i].total;
+  }
+  const int cap = tn.wg_per_cu > 0 ? tn.wg_per_cu * kComputeUnits : 0;
+  for (int c = 0; c < nchunks(nf); ++c) {
+    const int f0 = c * BATCH_CHUNK, cnt = std::min(BATCH_CHUNK, nf - f0);
+    int* st = starts + (size_t)c * Q_COUNT * (BATCH_CHUNK + 1);
+    chunk_view cv = {};
+    cv.one = nullptr;
+    cv.descs = (const frame_desc*)bb->head_dev + f0;
+    cv.starts = (const int*)(bb->head_dev + head_desc_bytes(nf)) + (size_t)c * Q_COUNT * (BATCH_CHUNK + 1);
+    cv.nf = cnt;
+    for (int q = 0; q < Q_COUNT; ++q) {
+      // layout of one chunk's prefix sums: [Q][cnt + 1]
+      int* sq = st + (size_t)q * (cnt + 1);
+      sq[0] = 0;
+      for (int i = 0; i < cnt; ++i) sq[i + 1] = sq[i] + queue_items(q, bb->plans[f0 + i]);
+      cv.items[q] = sq[cnt];
+      const bool streaming = q != Q_SAMPLE && q != Q_FINALIZE && q != Q_DIAG && q != Q_GRAMM;
+      cv.grid[q] = grid_for(cv.items[q], streaming ? cap : 0);
+    }
+    cv.maxN = cv.maxS = cv.maxPx = cv.maxPy = cv.maxcw = cv.maxStride = 1;
+    cv.gram_fmt = gram_format(o->precision);
+    cv.mlp = o->learned ? o->mlp_blob : nullptr;
+    for (int i = 0; i < cnt; ++i) {
+      const frame_plan& p = bb->plans[f0 + i];
+      cv.maxStride = std::max({cv.maxStride, p.Hmax, p.Wmax});
+      cv.maxN = std::max(cv.maxN, p.N);
+      cv.maxS = std::max(cv.maxS, p.S);
+      cv.maxPx = std::max(cv.maxPx, p.Px);
+      cv.maxPy = std::max(cv.maxPy, p.Py);
+      cv.maxcw = std::max(cv.maxcw, p.cw);
+    }
+    const int esize = dtype == CBP_F32 ? 4 : 8;
+    // the widest strip and the tallest column share one allocation; keep it in LDS
+    while (cv.maxcw > 1 && col_lds_bytes(cv.maxPy, cv.maxcw, esize) > kLdsLimit - 2048) {
+      cv.maxcw >>= 1;
+      for (int i = 0; i < cnt; ++i) {
+        frame_plan& p = bb->plans[f0 + i];
+        if (p.cw > cv.maxcw) {
+          p.cw = cv.maxcw;
+          descs[f0 + i].cw = p.cw;
+        }
+      }
+      int* sq = st + (size_t)Q_COL * (cnt + 1);
+      for (int i = 0; i < cnt; ++i) sq[i + 1] = sq[i] + queue_items(Q_COL, bb->plans[f0 + i]);
+      cv.items[Q_COL] = sq[cnt];
+      cv.grid[Q_COL] = grid_for(cv.items[Q_COL], cap);
+    }
+    bb->chunks.push_back(cv);
+  }
+  return CBP_OK;
+}
+
+// Copy the workspace head from a pinned staging slot (asynchronous on st).
+hipError_t upload_head(dev_state& ds, const batch_build& bb, hipStream_t st) {
+  pinned_slot& s = ds.ring[ds.next];
+  ds.next = (ds.next + 1) % kRing;
+  if (s.recorded) CBP_TRY(hipEventSynchronize(s.done));
+  if (s.cap < bb.head.size()) {
+    if (s.host) hipHostFree(s.host);
+    s.host = nullptr;
+    s.cap = 0;
+    CBP_TRY(hipHostMalloc(&s.host, bb.head.size(), hipHostMallocDefault));
+    s.cap = bb.head.size();
+  }
+  std::memcpy(s.host, bb.head.data(), bb.head.size());
+  CBP_TRY(hipMemcpyAsync(bb.head_dev, s.host, bb.head.size(), hipMemcpyHostToDevice, st));
+  CBP_TRY(hipEventRecord(s.done, st));
+  s.recorded = true;
+  return hipSuccess;
+}
+
+hipError_t enqueue_batch(dev_state& ds, const batch_build& bb, hipStream_t st) {
+  for (const chunk_view& cv : bb.chunks) {
+    const hipError_t e = enqueue(ds, bb.dtype, cv, bb.latent, bb.diag, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Key of a captured graph: everything its nodes bake in.
+std::string graph_key(const batch_build& bb) {
+  std::string k(bb.head.begin(), bb.head.end());
+  for (const chunk_view& cv : bb.chunks) k.append((const char*)&cv, sizeof cv);
+  k.append((const char*)&bb.head_dev, sizeof bb.head_dev);
+  k.push_back((char)bb.dtype);
+  k.push_back((char)bb.latent);
+  k.push_back((char)bb.diag);
+  return k;   // the chunk views carry the network pointer
+}
+
+hipError_t run_graph(dev_state& ds, const batch_build& bb, hipStream_t st) {
+  const std::string key = graph_key(bb);
+  auto it = ds.graphs.find(key);
+  hipError_t e;
+  if (it == ds.graphs.end()) {
+    if (ds.graphs.size() >= kMaxGraphs) {
+      // evict the least recently used graph once the caller's work has drained
+      auto lru = ds.graphs.begin();
+      for (auto g = ds.graphs.begin(); g != ds.graphs.end(); ++g)
+        if (g->second.last_use < lru->second.last_use) lru = g;
+      if ((e = note("hipDeviceSynchronize", hipDeviceSynchronize())) != hipSuccess) return e;
+      hipGraphExecDestroy(lru->second.exec);
+      hipHostFree(lru->second.host);
+      ds.graphs.erase(lru);
+    }
+    graph_entry ent;
+    if ((e = note("hipHostMalloc", hipHostMalloc(&ent.host, bb.head.size(), hipHostMallocDefault))) != hipSuccess)
+      return e;
+    std::memcpy(ent.host, bb.head.data(), bb.head.size());
+    hipGraph_t g = nullptr;
+    if ((e = note("hipStreamBeginCapture", hipStreamBeginCapture(ds.cap, hipStreamCaptureModeRelaxed))) !=
+        hipSuccess) {
+      hipHostFree(ent.host);
+      return e;
+    }
+    t_capturing = true;
+    hipError_t ce = note("hipMemcpyAsync (capture)",
+                         hipMemcpyAsync(bb.head_dev, ent.host, bb.head.size(), hipMemcpyHostToDevice, ds.cap));
+    if (ce == hipSuccess) ce = enqueue_batch(ds, bb, ds.cap);
+    t_capturing = false;
+    e = note("hipStreamEndCapture", hipStreamEndCapture(ds.cap, &g));
+    if (ce == hipSuccess && e == hipSuccess)
+      e = note("hipGraphInstantiate", hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0));
+    if (g) hipGraphDestroy(g);
+    if (ce != hipSuccess || e != hipSuccess) {
+      hipHostFree(ent.host);
+      return ce != hipSuccess ? ce : e;
+    }
+    it = ds.graphs.emplace(key, ent).first;
+  }
+  it->second.last_use = ++ds.tick;
+  return note("hipGraphLaunch", hipGraphLaunch(it->second.exec, st));
+}
+
+// Time one eager run of a batch with tuning tn (ms; < 0 on failure).
+float time_tuning(dev_state& ds, const std::vector<frame_req>& reqs, const cbp_options* o, const tuning& tn,
+                  hipStream_t st) {
+  std::vector<cbp_status> status;
+  batch_build bb;
+  if (build_batch(reqs, o, tn, status, &bb) != CBP_OK || bb.idx.empty()) return -1.0f;
+  if (upload_head(ds, bb, st) != hipSuccess) return -1.0f;
+  if (enqueue_batch(ds, bb, st) != hipSuccess) return -1.0f;  // warm-up
+  float best = -1.0f;
+  for (int rep = 0; rep < 3; ++rep) {
+    if (hipEventRecord(ds.t0, st) != hipSuccess) return -1.0f;
+    if (enqueue_batch(ds, bb, st) != hipSuccess) return -1.0f;
+    if (hipEventRecord(ds.t1, st) != hipSuccess) return -1.0f;
+    float ms = 0.0f;
+    if (hipEventSynchronize(ds.t1) != hipSuccess || hipEventElapsedTime(&ms, ds.t0, ds.t1) != hipSuccess)
+      return -1.0f;
+    if (best < 0.0f || ms < best) best = ms;
+  }
+  return best;
+}
+
+// Coordinate search over the knobs, one at a time, from the defaults.
+tuning autotune(dev_state& ds, const std::vector<frame_req>& reqs, const cbp_options* o, hipStream_t st,
+                float* best_ms) {
+  tuning best = kDefaultTuning;
+  float bms = time_tuning(ds, reqs, o, best, st);
+  auto consider = [&](tuning t) {
+    const float ms = time_tuning(ds, reqs, o, t, st);
+    if (ms > 0.0f && (bms < 0.0f || ms < bms)) {
+      bms = ms;
+      best = t;
+    }
+  };
+  for (int order = 1; order < FFT_ORDERS; ++order) { tuning t = best; t.fft_order = order; consider(t); }
+  for (int rows : {64, 128, 256}) { tuning t = best; t.fold_rows = rows; consider(t); }
+  for (int cw : {1, 2, 4, 8}) { tuning t = best; t.cw = cw; consider(t); }
+  for (int wpc : {2, 4, 8, 16}) { tuning t = best; t.wg_per_cu = wpc; consider(t); }
+  *best_ms = bms;
+  return best;
+}
+
+cbp_status batch_call(const std::vector<frame_req>& reqs, cbp_status* per_frame, const cbp_options* o) {
+  if (reqs.empty() || !o) return CBP_E_INVALID;
+  for (const frame_req& r : reqs)
+    if (!r.b1 || !r.b2) return CBP_E_INVALID;
+  // host validation first (no HIP call when every frame is invalid)
+  std::vector<cbp_status> status;
+  batch_build bb;
+  cbp_status s = build_batch(reqs, o, kDefaultTuning, status, &bb);
+  if (per_frame)
+    for (size_t f = 0; f < reqs.size(); ++f) per_frame[f] = status[f];
+  cbp_status first = CBP_OK;
+  for (cbp_status x : status)
+    if (x != CBP_OK) { first = x; break; }
+  if (s != CBP_OK || bb.idx.empty()) return s != CBP_OK ? s : first;
+  dev_state* ds = get_dev();
+  if (!ds) return CBP_E_DEVICE;
+  hipStream_t st = (hipStream_t)o->stream;
+  std::lock_guard<std::mutex> lk(ds->launch_mu);
+  (void)hipGetLastError();  // launch errors below are read with hipGetLastError: start clean
+  const std::string ck = class_key(reqs, o);
+  auto tt = ds->tuned.find(ck);
+  tuning tn = kDefaultTuning;
+  if (tt != ds->tuned.end()) {
+    tn = tt->second;
+  } else if ((o->flags & CBP_FLAG_AUTOTUNE) && bb.idx.size() == reqs.size()) {
+    // the search runs only on batches that are valid as given
+    float ms = -1.0f;
+    tn = autotune(*ds, reqs, o, st, &ms);
+    ds->tuned[ck] = tn;
+    ds->have_last = true;
+    ds->last = cbp_tuning{tn.fold_rows, tn.cw, tn.wg_per_cu, tn.fft_order, (double)ms};
+  }
+  if (std::memcmp(&tn, &kDefaultTuning, sizeof tn) != 0) {
+    s = build_batch(reqs, o, tn, status, &bb);
+    if (s != CBP_OK) return s;
+  }
+  hipError_t e;
+  if (o->flags & CBP_FLAG_GRAPH) {
+    e = run_graph(*ds, bb, st);
+  } else {
+    e = upload_head(*ds, bb, st);
+    if (e == hipSuccess) e = enqueue_batch(*ds, bb, st);
+  }
+  if (e != hipSuccess) return CBP_E_DEVICE;
+  return first;
 }
 
 }  // namespace
 
 void prof_begin(int phase, hipStream_t st) {
   profiler& p = prof();
-  if (!p.on) return;
+  if (!p.on || t_capturing) return;
   std::lock_guard<std::mutex> g(p.mu);
   hipEvent_t e = p.get();
   if (!e) return;
@@ -273,7 +745,7 @@ void prof_begin(int phase, hipStream_t st) {
 
 void prof_end(int phase, hipStream_t st) {
   profiler& p = prof();
-  if (!p.on) return;
+  if (!p.on || t_capturing) return;
   std::lock_guard<std::mutex> g(p.mu);
   hipEvent_t a = p.open[phase];
   if (!a) return;
@@ -303,7 +775,7 @@ const char* cbp_status_string(cbp_status s) {
   return "unknown status";
 }
 
-const char* cbp_version(void) { return "0.1.0"; }
+const char* cbp_version(void) { return "0.2.0"; }
 
 size_t cbp_diag_size(void) { return sizeof(cbp_diag); }
 
@@ -314,12 +786,12 @@ size_t cbp_workspace_size(int32_t maxH, int32_t maxW, int32_t maxk, int32_t chan
   int esize = 8;
   if (opts) {
     if (opts->samples > S) S = opts->samples;
-    if (opts->precision == CBP_PREC_MIXED) esize = 4;
+    if (opts->precision != CBP_PREC_FP64) esize = 4;
   }
   if (S > CBP_MAX_S) return 0;
   frame_plan fp;
   const size_t one = layout(&fp, regions(maxH, maxW, maxk, S, channels, esize));
-  return one * (size_t)batch;
+  return head_bytes(batch) + one * (size_t)batch;
 }
 
 cbp_status cbp_eval_unit_circle(const cbp_image* b, int32_t S, double* ex, double* ey, const cbp_options* opts) {
@@ -334,32 +806,133 @@ cbp_status cbp_eval_unit_circle(const cbp_image* b, int32_t S, double* ex, doubl
 
 cbp_status cbp_recover_kernels(const cbp_image* b1, const cbp_image* b2, int32_t m, int32_t n, double* K1,
                                double* K2, const cbp_options* opts) {
-  if (!K1 || !K2 || !opts) return CBP_E_INVALID;
+  if (!K1 || !K2 || !opts || !b1 || !b2) return CBP_E_INVALID;
+  if (opts->flags & (CBP_FLAG_GRAPH | CBP_FLAG_AUTOTUNE)) {
+    const std::vector<frame_req> reqs = {frame_req{b1, b2, nullptr, m, n, K1, K2, opts->diag}};
+    return batch_call(reqs, nullptr, opts);
+  }
   return frame_call(b1, b2, nullptr, m, n, K1, K2, opts, (char*)opts->workspace, opts->workspace_bytes,
                     opts->diag);
 }
 
 cbp_status cbp_deblur(const cbp_image* b1, const cbp_image* b2, cbp_image* latent, double* K1, double* K2,
                       const cbp_options* opts) {
-  if (!opts || !latent) return CBP_E_INVALID;
+  if (!opts || !latent || !b1 || !b2) return CBP_E_INVALID;
+  if (opts->flags & (CBP_FLAG_GRAPH | CBP_FLAG_AUTOTUNE)) {
+    const std::vector<frame_req> reqs = {
+        frame_req{b1, b2, latent, latent->height, latent->width, K1, K2, opts->diag}};
+    return batch_call(reqs, nullptr, opts);
+  }
   return frame_call(b1, b2, latent, latent->height, latent->width, K1, K2, opts, (char*)opts->workspace,
                     opts->workspace_bytes, opts->diag);
+}
+
+cbp_status cbp_sample_grams(const cbp_image* b1, const cbp_image* b2, int32_t m, int32_t n, double* grams,
+                            const cbp_options* opts) {
+  if (!grams || !opts || !b1 || !b2) return CBP_E_INVALID;
+  frame_plan fp;
+  const cbp_status s = make_plan(b1, b2, m, n, opts, kDefaultTuning, &fp);
+  if (s != CBP_OK) return s;
+  const size_t head = head_bytes(1);
+  char* ws = (char*)opts->workspace;
+  if (!ws || opts->workspace_bytes < head + fp.total) return CBP_E_NOMEM;
+  dev_state* ds = get_dev();
+  if (!ds) return CBP_E_DEVICE;
+  const frame_desc d = make_desc(fp, b1, b2, ws + head, nullptr, nullptr, nullptr, opts->lambda, nullptr, false);
+  auto br = [&](int q) { return batch_ref{nullptr, nullptr, queue_items(q, fp)}; };
+  auto grid = [&](int q) { return grid_for(queue_items(q, fp), 0); };
+  hipStream_t st = (hipStream_t)opts->stream;
+  const int gfmt = gram_format(opts->precision);
+  std::lock_guard<std::mutex> lk(ds->launch_mu);
+  (void)hipGetLastError();
+  auto run = [&]() -> hipError_t {
+    if (b1->dtype == CBP_F32) {
+      CBP_TRY(launch_fold<float>(d, br(Q_FOLD), grid(Q_FOLD), st));
+      CBP_TRY(launch_eval_rows<float>(d, br(Q_EVAL_ROWS), grid(Q_EVAL_ROWS), st));
+    } else {
+      CBP_TRY(launch_fold<double>(d, br(Q_FOLD), grid(Q_FOLD), st));
+      CBP_TRY(launch_eval_rows<double>(d, br(Q_EVAL_ROWS), grid(Q_EVAL_ROWS), st));
+    }
+    CBP_TRY(launch_eval_cols(d, br(Q_EVAL_COLS), grid(Q_EVAL_COLS), st));
+    if (gfmt < 0) CBP_TRY(launch_gram(d, br(Q_GRAM), grid(Q_GRAM), st));
+    else CBP_TRY(launch_gram_mfma(d, br(Q_GRAMM), grid(Q_GRAMM), gfmt, std::max(fp.Hmax, fp.Wmax), st));
+    CBP_TRY(launch_gram_expand(d, br(Q_GRAMM), grid(Q_GRAMM), grams, st));
+    return hipSuccess;
+  };
+  return run() == hipSuccess ? CBP_OK : CBP_E_DEVICE;
 }
 
 cbp_status cbp_deblur_batch(int32_t nframes, const cbp_image* b1s, const cbp_image* b2s, cbp_image* latents,
                             double* const* K1s, double* const* K2s, cbp_status* per_frame, const cbp_options* opts) {
   if (nframes < 1 || !b1s || !b2s || !latents || !opts) return CBP_E_INVALID;
-  const size_t slice = (opts->workspace_bytes / (size_t)nframes) & ~(kAlign - 1);
-  cbp_status first = CBP_OK;
-  for (int f = 0; f < nframes; ++f) {
-    char* ws = opts->workspace ? (char*)opts->workspace + (size_t)f * slice : nullptr;
-    void* diag = opts->diag ? (void*)((cbp_diag*)opts->diag + f) : nullptr;
-    const cbp_status s = frame_call(&b1s[f], &b2s[f], &latents[f], latents[f].height, latents[f].width,
-                                    K1s ? K1s[f] : nullptr, K2s ? K2s[f] : nullptr, opts, ws, slice, diag);
-    if (per_frame) per_frame[f] = s;
-    if (s != CBP_OK && first == CBP_OK) first = s;
-  }
-  return first;
+  std::vector<frame_req> reqs(nframes);
+  for (int f = 0; f < nframes; ++f)
+    reqs[f] = frame_req{&b1s[f], &b2s[f], &latents[f], latents[f].height, latents[f].width,
+                        K1s ? K1s[f] : nullptr, K2s ? K2s[f] : nullptr,
+                        opts->diag ? (void*)((cbp_diag*)opts->diag + f) : nullptr};
+  return batch_call(reqs, per_frame, opts);
+}
+
+const char* cbp_last_error(void) { return t_error; }
+
+// ------------------------------------------------------------------ the learned form's network
+int32_t cbp_mlp_param_count(void) { return MLP_NPARAM; }
+size_t cbp_mlp_blob_size(void) { return sizeof(mlp_blob); }
+size_t cbp_mlp_state_size(int32_t max_rows) { return max_rows >= 1 ? mlp_state_bytes(max_rows) : 0; }
+
+cbp_status cbp_mlp_set_params(void* state, int32_t max_rows, const float* params, void* stream) {
+  if (!state || !params || max_rows < 1) return CBP_E_INVALID;
+  (void)hipGetLastError();
+  return note("mlp_set_params", mlp_set_params(state, max_rows, params, (hipStream_t)stream)) == hipSuccess
+             ? CBP_OK : CBP_E_DEVICE;
+}
+
+cbp_status cbp_mlp_get_params(const void* state, int32_t max_rows, float* params, void* stream) {
+  if (!state || !params || max_rows < 1) return CBP_E_INVALID;
+  return note("mlp_get_params", mlp_get_params(state, max_rows, params, (hipStream_t)stream)) == hipSuccess
+             ? CBP_OK : CBP_E_DEVICE;
+}
+
+cbp_status cbp_mlp_gradients(void* state, int32_t max_rows, const float* X, const float* T, int32_t n,
+                             float* loss, float* grads, void* stream) {
+  if (!state || !X || !T || !loss || n < 1 || n > max_rows) return CBP_E_INVALID;
+  (void)hipGetLastError();
+  return note("mlp_gradients", mlp_gradients(state, max_rows, X, T, n, loss, grads, (hipStream_t)stream)) ==
+                 hipSuccess ? CBP_OK : CBP_E_DEVICE;
+}
+
+cbp_status cbp_mlp_train_step(void* state, int32_t max_rows, const float* X, const float* T, int32_t n, float lr,
+                              int32_t step, float* loss, void* stream) {
+  if (!state || !X || !T || !loss || n < 1 || n > max_rows || step < 1 || !(lr > 0.0f)) return CBP_E_INVALID;
+  (void)hipGetLastError();
+  hipStream_t st = (hipStream_t)stream;
+  if (note("mlp_gradients", mlp_gradients(state, max_rows, X, T, n, loss, nullptr, st)) != hipSuccess)
+    return CBP_E_DEVICE;
+  return note("mlp_adam_step", mlp_adam_step(state, max_rows, lr, step, st)) == hipSuccess ? CBP_OK : CBP_E_DEVICE;
+}
+
+cbp_status cbp_mlp_export(const void* state, int32_t max_rows, void* blob, void* stream) {
+  if (!state || !blob || max_rows < 1) return CBP_E_INVALID;
+  (void)hipGetLastError();
+  return note("mlp_export", mlp_export(state, max_rows, blob, (hipStream_t)stream)) == hipSuccess ? CBP_OK
+                                                                                              : CBP_E_DEVICE;
+}
+
+cbp_status cbp_mlp_forward(const void* blob, const float* X, int32_t n, float* out, void* stream) {
+  if (!blob || !X || !out || n < 1) return CBP_E_INVALID;
+  (void)hipGetLastError();
+  return note("mlp_forward", mlp_forward_blob(blob, X, n, out, (hipStream_t)stream)) == hipSuccess ? CBP_OK
+                                                                                                 : CBP_E_DEVICE;
+}
+
+cbp_status cbp_last_tuning(cbp_tuning* out) {
+  if (!out) return CBP_E_INVALID;
+  dev_state* ds = get_dev();
+  if (!ds) return CBP_E_DEVICE;
+  std::lock_guard<std::mutex> lk(ds->launch_mu);
+  if (!ds->have_last) return CBP_E_INVALID;
+  *out = ds->last;
+  return CBP_OK;
 }
 
 void cbp_profile_enable(int32_t on) {

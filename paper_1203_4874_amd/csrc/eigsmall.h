@@ -284,6 +284,36 @@ __device__ inline void small_bisect(const small_ws& s, int n, int target, double
   *tn_out = tn;
 }
 
+// Every eigenvalue of T on a log scale: lane l < n returns its (l+1)-th
+// smallest eigenvalue, bisected in log10 over [1e-15 ||T||, ||T||] to
+// SPECTRUM_ITERS steps (values below the range return its bottom).  Used for
+// the learned form's features, which floor at 1e-14 of the largest
+// eigenvalue.
+constexpr int SPECTRUM_ITERS = 28;
+
+__device__ inline double small_spectrum(const small_ws& s, int n) {
+  const int l = threadIdx.x;
+  double ghi = -1.7976931348623157e308, bmax = 0.0;
+  if (l < n) {
+    const double bl = l > 0 ? s.b[l - 1] : 0.0, br = s.b[l];
+    ghi = s.a[l] + bl + br;
+    bmax = br;
+  }
+  ghi = wmax(ghi);
+  bmax = wmax(bmax);
+  const double pivmin = fmax(bmax * bmax, 1e-280) * 1e-290 + 1e-300;
+  const double top = log10(fmax(ghi, 1e-300));
+  double lo = top - 15.0, hi = top;
+  if (l < n) {
+    for (int it = 0; it < SPECTRUM_ITERS; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (sturm_count(s.a, s.b, n, exp10(mid), pivmin) >= l + 1) hi = mid;
+      else lo = mid;
+    }
+  }
+  return exp10(0.5 * (lo + hi));
+}
+
 // ---------------------------------------------------------------- 3. inverse
 // s.A <- s.A^{-1} for a Hermitian positive definite matrix (Gauss-Jordan, no
 // pivoting; row and column k are staged in s.u / s.w before the update).

@@ -11,6 +11,9 @@
 //
 // Layouts (cf = 2*channel + frame):
 //   fpart [RG][ncf][S][Wmax] double, EX [ncf][S][Wmax] c64, EY [ncf][S][Hmax] c64.
+// The row evaluation of a deblurring call is done by the forward row FFT
+// kernel (same arithmetic, same order) from the rows it loads anyway;
+// k_eval_rows serves kernel-only calls and the one-frame evaluation.
 #include "eigsmall.h"
 #include "internal.h"
 
@@ -19,10 +22,10 @@ namespace cbp {
 namespace {
 
 template <typename T>
-__device__ inline void pick(const pair_view<T>& v, int cf, const T*& b, int64_t& pitch, int& H, int& W) {
+__device__ inline void pick(const frame_desc& d, int cf, const T*& b, int64_t& pitch, int& H, int& W) {
   const int ch = cf >> 1;
-  if ((cf & 1) == 0) { b = v.b1 + ch * v.cs1; pitch = v.p1; H = v.H1; W = v.W1; }
-  else { b = v.b2 + ch * v.cs2; pitch = v.p2; H = v.H2; W = v.W2; }
+  if ((cf & 1) == 0) { b = (const T*)d.b1 + ch * d.cs1; pitch = d.p1; H = d.H1; W = d.W1; }
+  else { b = (const T*)d.b2 + ch * d.cs2; pitch = d.p2; H = d.H2; W = d.W2; }
 }
 
 __device__ inline void unit_twiddles(c64* tw, int S) {
@@ -34,171 +37,196 @@ __device__ inline void unit_twiddles(c64* tw, int S) {
 }
 
 // Column fold over rows [g*rpg, (g+1)*rpg) of one (channel, frame): one
-// thread per column, S independent accumulators, 64 columns per workgroup.
+// thread per column, S independent accumulators, 64 columns per item.
+// Items: (column block, row group, cf).
 template <typename T>
-__global__ __launch_bounds__(64) void k_fold_cols(pair_view<T> v, int S, int rpg, double* fpart, int Wmax) {
-  const int cf = blockIdx.z, ncf = gridDim.z;
-  const T* b;
-  int64_t pitch;
-  int H, W;
-  pick(v, cf, b, pitch, H, W);
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  if (x >= W) return;
-  const int y0 = blockIdx.y * rpg;
-  const int y1 = min(y0 + rpg, H);
-  double acc[CBP_MAX_S];
+__global__ __launch_bounds__(64) void k_fold_cols(frame_desc one, batch_ref br) {
+  for_items<Q_FOLD>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+    const int nx = (d.Wmax + 63) / 64;
+    const int bx = item % nx, rest = item / nx;
+    const int g = rest % d.RG, cf = rest / d.RG;
+    const T* b;
+    int64_t pitch;
+    int H, W;
+    pick(d, cf, b, pitch, H, W);
+    const int x = bx * 64 + threadIdx.x;
+    if (x >= W) return;
+    const int S = d.S;
+    const int y0 = g * d.rpg;
+    const int y1 = min(y0 + d.rpg, H);
+    double acc[CBP_MAX_S];
 #pragma unroll
-  for (int r = 0; r < CBP_MAX_S; ++r) acc[r] = 0.0;
-  for (int yb = y0; yb < y1; yb += S) {
-    const T* col = b + (int64_t)yb * pitch + x;
+    for (int r = 0; r < CBP_MAX_S; ++r) acc[r] = 0.0;
+    for (int yb = y0; yb < y1; yb += S) {
+      const T* col = b + (int64_t)yb * pitch + x;
+#pragma unroll
+      for (int r = 0; r < CBP_MAX_S; ++r)
+        if (r < S && yb + r < y1) acc[r] += (double)col[(int64_t)r * pitch];
+    }
+    double* out = d.fpart + ((size_t)g * d.ncf + cf) * S * (size_t)d.Wmax + x;
 #pragma unroll
     for (int r = 0; r < CBP_MAX_S; ++r)
-      if (r < S && yb + r < y1) acc[r] += (double)col[(int64_t)r * pitch];
-  }
-  double* out = fpart + ((size_t)blockIdx.y * ncf + cf) * S * (size_t)Wmax + x;
-#pragma unroll
-  for (int r = 0; r < CBP_MAX_S; ++r)
-    if (r < S) out[(size_t)r * Wmax] = acc[r];
+      if (r < S) out[(size_t)r * d.Wmax] = acc[r];
+  });
 }
 
 // Sum the row-group partials of the column fold and apply the S-point DFT;
-// 16 columns per workgroup, 16 residues / frequencies in flight per column.
-__global__ __launch_bounds__(256) void k_eval_cols(const double* fpart, int RG, int S, int Wmax, int W1, int W2,
-                                                   c64* ex, int exW) {
+// 16 columns per item, 16 residues / frequencies in flight per column.
+// Items: (column block, cf).
+__global__ __launch_bounds__(256) void k_eval_cols(frame_desc one, batch_ref br) {
   __shared__ double F[CBP_MAX_S][16];
   __shared__ c64 tw[CBP_MAX_S];
-  const int cf = blockIdx.y, ncf = gridDim.y;
-  const int W = (cf & 1) ? W2 : W1;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int x = blockIdx.x * 16 + tx;
-  unit_twiddles(tw, S);
-  for (int r = ty; r < S; r += 16) {
-    double s0 = 0.0, s1 = 0.0;
-    if (x < W) {
-      const double* p = fpart + ((size_t)cf * S + r) * Wmax + x;
-      const size_t gs = (size_t)ncf * S * Wmax;
-      int g = 0;
-      for (; g + 2 <= RG; g += 2) {
-        s0 += p[(size_t)g * gs];
-        s1 += p[(size_t)(g + 1) * gs];
+  for_items<Q_EVAL_COLS>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+    const int nx = (d.Wmax + 15) / 16;
+    const int bx = item % nx, cf = item / nx;
+    const int S = d.S, Wmax = d.Wmax, RG = d.RG;
+    const int W = (cf & 1) ? d.W2 : d.W1;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int x = bx * 16 + tx;
+    unit_twiddles(tw, S);
+    for (int r = ty; r < S; r += 16) {
+      double s0 = 0.0, s1 = 0.0;
+      if (x < W) {
+        const double* p = d.fpart + ((size_t)cf * S + r) * Wmax + x;
+        const size_t gs = (size_t)d.ncf * S * Wmax;
+        int g = 0;
+        for (; g + 2 <= RG; g += 2) {
+          s0 += p[(size_t)g * gs];
+          s1 += p[(size_t)(g + 1) * gs];
+        }
+        if (g < RG) s0 += p[(size_t)g * gs];
       }
-      if (g < RG) s0 += p[(size_t)g * gs];
+      F[r][tx] = s0 + s1;
     }
-    F[r][tx] = s0 + s1;
-  }
-  __syncthreads();
-  if (x >= W) return;
-  for (int j = ty; j < S; j += 16) {
-    c64 acc = {0.0, 0.0};
-    int t = 0;
-    for (int r = 0; r < S; ++r) {
-      const double f = F[r][tx];
-      acc.re += f * tw[t].re;
-      acc.im += f * tw[t].im;
-      t += j;
-      if (t >= S) t -= S;
+    __syncthreads();
+    if (x >= W) return;
+    for (int j = ty; j < S; j += 16) {
+      c64 acc = {0.0, 0.0};
+      int t = 0;
+      for (int r = 0; r < S; ++r) {
+        const double f = F[r][tx];
+        acc.re += f * tw[t].re;
+        acc.im += f * tw[t].im;
+        t += j;
+        if (t >= S) t -= S;
+      }
+      d.ex[((size_t)cf * S + j) * Wmax + x] = acc;
     }
-    ex[((size_t)cf * S + j) * exW + x] = acc;
-  }
+  });
 }
 
 // Row fold and S-point DFT: one wave per row; lane l folds the chunks
-// x in [q S, q S + S), q = l, l + 64, ...; wave shuffles sum the lanes.
+// x in [q S, q S + S), q = l, l + 64, ...; wave reductions sum the lanes.
+// Items: (block of 4 rows, cf).
 template <typename T>
-__global__ __launch_bounds__(256) void k_eval_rows(pair_view<T> v, int S, c64* ey, int eyH) {
+__global__ __launch_bounds__(256) void k_eval_rows(frame_desc one, batch_ref br) {
   __shared__ double g[4][CBP_MAX_S];
   __shared__ c64 tw[CBP_MAX_S];
-  const int cf = blockIdx.y;
-  const T* b;
-  int64_t pitch;
-  int H, W;
-  pick(v, cf, b, pitch, H, W);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int y = blockIdx.x * 4 + w;
-  unit_twiddles(tw, S);
-  double acc[CBP_MAX_S];
+  for_items<Q_EVAL_ROWS>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+    const int ny = (d.Hmax + 3) / 4;
+    const int by = item % ny, cf = item / ny;
+    const int S = d.S;
+    const T* b;
+    int64_t pitch;
+    int H, W;
+    pick(d, cf, b, pitch, H, W);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int y = by * 4 + w;
+    unit_twiddles(tw, S);
+    double acc[CBP_MAX_S];
 #pragma unroll
-  for (int r = 0; r < CBP_MAX_S; ++r) acc[r] = 0.0;
-  if (y < H) {
-    const T* row = b + (int64_t)y * pitch;
-    for (int x0 = l * S; x0 < W; x0 += 64 * S) {
+    for (int r = 0; r < CBP_MAX_S; ++r) acc[r] = 0.0;
+    if (y < H) {
+      const T* row = b + (int64_t)y * pitch;
+      for (int x0 = l * S; x0 < W; x0 += 64 * S) {
 #pragma unroll
-      for (int r = 0; r < CBP_MAX_S; ++r)
-        if (r < S && x0 + r < W) acc[r] += (double)row[x0 + r];
+        for (int r = 0; r < CBP_MAX_S; ++r)
+          if (r < S && x0 + r < W) acc[r] += (double)row[x0 + r];
+      }
     }
-  }
 #pragma unroll
-  for (int r = 0; r < CBP_MAX_S; ++r) {
-    if (r < S) {
-      const double s = wsum(acc[r]);
-      if (l == 0) g[w][r] = s;
+    for (int r = 0; r < CBP_MAX_S; ++r) {
+      if (r < S) {
+        const double s = wsum(acc[r]);
+        if (l == 0) g[w][r] = s;
+      }
     }
-  }
-  __syncthreads();
-  if (y < H && l < S) {
-    c64 e = {0.0, 0.0};
-    int t = 0;
-    for (int r = 0; r < S; ++r) {
-      const double f = g[w][r];
-      e.re += f * tw[t].re;
-      e.im += f * tw[t].im;
-      t += l;
-      if (t >= S) t -= S;
+    __syncthreads();
+    if (y < H && l < S) {
+      c64 e = {0.0, 0.0};
+      int t = 0;
+      for (int r = 0; r < S; ++r) {
+        const double f = g[w][r];
+        e.re += f * tw[t].re;
+        e.im += f * tw[t].im;
+        t += l;
+        if (t >= S) t -= S;
+      }
+      d.ey[((size_t)cf * S + l) * d.Hmax + y] = e;
     }
-    ey[((size_t)cf * S + l) * eyH + y] = e;
-  }
+  });
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_eval_cols(const pair_view<T>& v, const frame_plan& fp, char* ws, hipStream_t st) {
-  const int ncf = 2 * v.nch;
-  double* fpart = (double*)(ws + fp.off_fpart);
-  c64* ex = (c64*)(ws + fp.off_ex);
-  const int S = fp.S;
+hipError_t launch_fold(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st) {
   prof_begin(PH_FOLD, st);
-  hipLaunchKernelGGL(k_fold_cols<T>, dim3((fp.Wmax + 63) / 64, fp.RG, ncf), dim3(64), 0, st, v, S, fp.rpg,
-                     fpart, fp.Wmax);
+  hipLaunchKernelGGL(k_fold_cols<T>, dim3(grid), dim3(64), 0, st, one, br);
   prof_end(PH_FOLD, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_cols(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st) {
   prof_begin(PH_EVAL_COLS, st);
-  hipLaunchKernelGGL(k_eval_cols, dim3((fp.Wmax + 15) / 16, ncf), dim3(256), 0, st, fpart, fp.RG, S, fp.Wmax,
-                     v.W1, v.W2, ex, fp.Wmax);
+  hipLaunchKernelGGL(k_eval_cols, dim3(grid), dim3(256), 0, st, one, br);
   prof_end(PH_EVAL_COLS, st);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_eval_rows(const pair_view<T>& v, const frame_plan& fp, char* ws, hipStream_t st) {
-  const int ncf = 2 * v.nch;
-  c64* ey = (c64*)(ws + fp.off_ey);
+hipError_t launch_eval_rows(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st) {
   prof_begin(PH_EVAL_ROWS, st);
-  hipLaunchKernelGGL(k_eval_rows<T>, dim3((fp.Hmax + 3) / 4, ncf), dim3(256), 0, st, v, fp.S, ey, fp.Hmax);
+  hipLaunchKernelGGL(k_eval_rows<T>, dim3(grid), dim3(256), 0, st, one, br);
   prof_end(PH_EVAL_ROWS, st);
   return hipGetLastError();
 }
 
-template hipError_t launch_eval_cols<float>(const pair_view<float>&, const frame_plan&, char*, hipStream_t);
-template hipError_t launch_eval_cols<double>(const pair_view<double>&, const frame_plan&, char*, hipStream_t);
-template hipError_t launch_eval_rows<float>(const pair_view<float>&, const frame_plan&, char*, hipStream_t);
-template hipError_t launch_eval_rows<double>(const pair_view<double>&, const frame_plan&, char*, hipStream_t);
+template hipError_t launch_fold<float>(const frame_desc&, const batch_ref&, int, hipStream_t);
+template hipError_t launch_fold<double>(const frame_desc&, const batch_ref&, int, hipStream_t);
+template hipError_t launch_eval_rows<float>(const frame_desc&, const batch_ref&, int, hipStream_t);
+template hipError_t launch_eval_rows<double>(const frame_desc&, const batch_ref&, int, hipStream_t);
 
-// One frame, channel 0, written straight to the caller's EX (S x W) and EY (S x H).
+// One frame, channel 0, written straight to the caller's EX (S x W) and EY
+// (S x H): a one-slot (ncf = 1) frame descriptor over the same kernels.
 hipError_t launch_eval_single(const void* b, int dtype, int64_t pitch, int H, int W, int S, char* ws, double* ex,
                               double* ey, hipStream_t st) {
-  const int rpg = S * ((32 + S - 1) / S);
-  const int RG = (H + rpg - 1) / rpg;
-  double* fpart = (double*)ws;
-  auto run = [&](auto* ptr) -> hipError_t {
-    using T = typename std::remove_const<typename std::remove_pointer<decltype(ptr)>::type>::type;
-    pair_view<T> v{ptr, ptr, pitch, pitch, 0, 0, H, W, H, W, 1};
-    hipLaunchKernelGGL(k_fold_cols<T>, dim3((W + 63) / 64, RG, 1), dim3(64), 0, st, v, S, rpg, fpart, W);
-    hipLaunchKernelGGL(k_eval_cols, dim3((W + 15) / 16, 1), dim3(256), 0, st, fpart, RG, S, W, W, W, (c64*)ex, W);
-    hipLaunchKernelGGL(k_eval_rows<T>, dim3((H + 3) / 4, 1), dim3(256), 0, st, v, S, (c64*)ey, H);
-    return hipGetLastError();
-  };
-  if (dtype == 0) return run((const float*)b);
-  return run((const double*)b);
+  frame_desc d = {};
+  d.b1 = b;
+  d.b2 = b;
+  d.p1 = d.p2 = pitch;
+  d.H1 = d.H2 = d.Hmax = H;
+  d.W1 = d.W2 = d.Wmax = W;
+  d.nch = 1;
+  d.ncf = 1;
+  d.S = S;
+  d.rpg = S * ((32 + S - 1) / S);
+  d.RG = (H + d.rpg - 1) / d.rpg;
+  d.fpart = (double*)ws;
+  d.ex = (c64*)ex;
+  d.ey = (c64*)ey;
+  const batch_ref none = {nullptr, nullptr, 0};
+  const int gf = ((W + 63) / 64) * d.RG, gc = (W + 15) / 16, gr = (H + 3) / 4;
+  if (dtype == CBP_F32) {
+    hipLaunchKernelGGL(k_fold_cols<float>, dim3(gf), dim3(64), 0, st, d, none);
+    hipLaunchKernelGGL(k_eval_cols, dim3(gc), dim3(256), 0, st, d, none);
+    hipLaunchKernelGGL(k_eval_rows<float>, dim3(gr), dim3(256), 0, st, d, none);
+  } else {
+    hipLaunchKernelGGL(k_fold_cols<double>, dim3(gf), dim3(64), 0, st, d, none);
+    hipLaunchKernelGGL(k_eval_cols, dim3(gc), dim3(256), 0, st, d, none);
+    hipLaunchKernelGGL(k_eval_rows<double>, dim3(gr), dim3(256), 0, st, d, none);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace cbp

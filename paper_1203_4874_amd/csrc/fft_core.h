@@ -152,19 +152,26 @@ struct fft_plan {
   int radix[FFT_MAX_PASSES];
 };
 
-// Factor N into the supported radices (8 first, then 4, 2, 3, 5, 7).
-// Returns false when N has another prime factor or too many passes.
-inline bool make_fft_plan(int N, fft_plan* p) {
-  if (N < 1) return false;
+// Factor N into the supported radices.  `order` picks the pass order:
+//   0: radix 8 first, then 4, 2, 3, 5, 7 (fewest passes);
+//   1: radix 4 first, then 8, 2, 3, 5, 7;
+//   2: odd radices first: 7, 5, 3, then 8, 4, 2.
+// Returns false when N has another prime factor, too many passes, or an
+// unknown order.
+constexpr int FFT_ORDERS = 3;
+
+inline bool make_fft_plan(int N, fft_plan* p, int order = 0) {
+  static const int orders[FFT_ORDERS][6] = {{8, 4, 2, 3, 5, 7}, {4, 8, 2, 3, 5, 7}, {7, 5, 3, 8, 4, 2}};
+  if (N < 1 || order < 0 || order >= FFT_ORDERS) return false;
   p->N = N;
   p->npass = 0;
   int r = N;
-  const int order[6] = {8, 4, 2, 3, 5, 7};
   for (int t = 0; t < 6; ++t) {
-    while (r % order[t] == 0) {
+    const int R = orders[order][t];
+    while (r % R == 0) {
       if (p->npass >= FFT_MAX_PASSES) return false;
-      p->radix[p->npass++] = order[t];
-      r /= order[t];
+      p->radix[p->npass++] = R;
+      r /= R;
     }
   }
   return r == 1;

@@ -1,5 +1,12 @@
 // Internal launch interface between the C ABI (api.hip) and the kernel
 // translation units.  Not part of the public ABI.
+//
+// Every kernel works on "work items" of one queue (a phase of the path).  A
+// launch covers either one frame, whose descriptor is a kernel argument and
+// whose items are the workgroups of the grid, or a batch of frames, whose
+// descriptors and per-queue item prefix sums sit in device memory; there the
+// grid may be smaller than the item count and each workgroup loops over
+// items (a persistent launch), finding each item's frame by binary search.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,19 +21,17 @@
 
 namespace cbp {
 
-// One blurred pair as the kernels see it (device pointers, element pitches).
-template <typename T>
-struct pair_view {
-  const T* b1;
-  const T* b2;
-  int64_t p1, p2;    // row pitch (elements)
-  int64_t cs1, cs2;  // channel stride (elements)
-  int H1, W1, H2, W2;
-  int nch;
+// Work queues, one per kernel.
+enum queue_id {
+  Q_DIAG = 0, Q_FOLD, Q_EVAL_COLS, Q_EVAL_ROWS, Q_ROW_FWD, Q_GRAM, Q_GRAMM, Q_SAMPLE, Q_FINALIZE, Q_COL,
+  Q_ROW_INV, Q_COUNT
 };
 
-// Geometry and workspace offsets of one frame (all offsets in bytes from the
-// frame's workspace base).
+// Frames per batched launch (the item prefix sums of one launch sit in LDS).
+constexpr int BATCH_CHUNK = 256;
+
+// Geometry and workspace offsets of one frame (host side; offsets in bytes
+// from the frame's workspace base).
 struct frame_plan {
   int H1, W1, H2, W2, Hmax, Wmax;
   int m, n, k1, k2, S, N;  // N = k1 + k2
@@ -36,8 +41,125 @@ struct frame_plan {
   int cw;                  // columns per workgroup in the column pass
   fft_plan fy, fx;
   size_t off_fpart, off_ex, off_ey, off_corr, off_xvec, off_lam0, off_pq, off_cbuf, off_kern,
-      off_t1, off_t2, off_u, total;
+      off_t1, off_t2, off_u, off_feat, off_wts, total;
 };
+
+// Everything a kernel needs about one frame (device pointers).
+struct frame_desc {
+  const void* b1;
+  const void* b2;
+  int64_t p1, p2;    // row pitch (elements)
+  int64_t cs1, cs2;  // channel stride (elements; 0 for one channel)
+  int H1, W1, H2, W2, Hmax, Wmax, nch;
+  int ncf;           // evaluated (channel, frame) slots: 2 nch (1 for the one-frame evaluation entry point)
+  int m, n, k1, k2, S, N;
+  int rpg, RG, Py, Px, hx, cw;
+  fft_plan fy, fx;
+  // workspace regions
+  double* fpart;
+  c64* ex;
+  c64* ey;
+  cdd* corr;
+  c64* xvec;
+  double* lam0;
+  c64* pq;
+  cdd* cbuf;
+  void* t1;
+  void* t2;
+  void* u;
+  // outputs
+  double* K1;
+  double* K2;
+  void* out;
+  int64_t opitch, ocs;
+  double lambda;
+  cbp_diag* diag;
+  // learned form (NULL otherwise): per-sample features [2S][32] (written by
+  // the eigen-solves) and the network's weights [2S] + tau (read by the
+  // assembly)
+  float* feat;
+  double* wts;
+};
+
+// Work items of each queue for one frame (the grid of a one-frame launch).
+inline int queue_items(int q, const frame_plan& p) {
+  const int ncf = 2 * p.nch;
+  switch (q) {
+    case Q_DIAG: return 1;
+    case Q_FOLD: return ((p.Wmax + 63) / 64) * p.RG * ncf;
+    case Q_EVAL_COLS: return ((p.Wmax + 15) / 16) * ncf;
+    case Q_EVAL_ROWS: return ((p.Hmax + 3) / 4) * ncf;
+    case Q_ROW_FWD: return p.Hmax * p.nch;
+    case Q_GRAM: return (2 * p.N - 1) * p.S * 2;
+    case Q_GRAMM: return p.S * 2;
+    case Q_SAMPLE: return p.S * 2;
+    case Q_FINALIZE: return 1;
+    case Q_COL: return ((p.hx + p.cw - 1) / p.cw) * p.nch;
+    case Q_ROW_INV: return ((p.m + 1) / 2) * p.nch;
+  }
+  return 0;
+}
+
+// A batch as the kernels see it.  descs == nullptr means a one-frame launch
+// whose descriptor is the kernel argument; nframes then holds the item count
+// of the launched queue.
+struct batch_ref {
+  const frame_desc* descs;  // nframes descriptors
+  const int* starts;        // [Q_COUNT][nframes + 1] item prefix sums
+  int nframes;
+};
+
+#if defined(__HIPCC__)
+// Items [first, end) step `step` of this workgroup.  Workgroups are
+// dispatched to the 8 XCDs round robin (workgroup b on XCD b mod 8); with a
+// grid that is a multiple of 8, XCD x takes the contiguous item range
+// [x T / 8, (x + 1) T / 8), so neighbouring items (the lags of one sample,
+// adjacent rows and strips of one frame) share their inputs in one XCD's L2.
+__device__ inline void xcd_items(int T, int& first, int& end, int& step) {
+  const int G = gridDim.x, b = blockIdx.x;
+  if (G < 8 || (G & 7) != 0) {
+    first = b;
+    end = T;
+    step = G;
+    return;
+  }
+  const int x = b & 7;
+  first = (int)(((int64_t)x * T) >> 3) + (b >> 3);
+  end = (int)(((int64_t)(x + 1) * T) >> 3);
+  step = G >> 3;
+}
+
+// Run body(frame, item) for every item of queue Q owned by this workgroup.
+// The body may use __syncthreads(); a barrier separates consecutive items.
+template <int Q, typename F>
+__device__ inline void for_items(const frame_desc& one, const batch_ref& br, F&& body) {
+  int first, end, step;
+  if (br.descs == nullptr) {
+    xcd_items(br.nframes, first, end, step);  // one frame: nframes holds its item count
+    for (int it = first; it < end; it += step) {
+      body(one, it);
+      __syncthreads();
+    }
+    return;
+  }
+  __shared__ int st[BATCH_CHUNK + 1];
+  const int nf = br.nframes;
+  const int* s = br.starts + (size_t)Q * (nf + 1);
+  for (int t = threadIdx.x; t <= nf; t += blockDim.x) st[t] = s[t];
+  __syncthreads();
+  xcd_items(st[nf], first, end, step);
+  for (int it = first; it < end; it += step) {
+    int lo = 0, hi = nf;  // st[lo] <= it < st[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (st[mid] <= it) lo = mid;
+      else hi = mid;
+    }
+    body(br.descs[lo], it - st[lo]);
+    __syncthreads();
+  }
+}
+#endif
 
 // ---------------------------------------------------------------- phase timing
 // Phases of one call, in launch order (also the names cbp_profile_phase_name
@@ -52,24 +174,53 @@ void prof_begin(int phase, hipStream_t st);
 void prof_end(int phase, hipStream_t st);
 
 // ---------------------------------------------------------------- launchers
+// Each launches one queue over `grid` workgroups (any grid >= 1 covers every
+// item; a multiple of 8 enables the XCD-aware item ranges).
 // eval.hip
 template <typename T>
-hipError_t launch_eval_cols(const pair_view<T>& v, const frame_plan& fp, char* ws, hipStream_t st);
+hipError_t launch_fold(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st);
+hipError_t launch_eval_cols(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st);
 template <typename T>
-hipError_t launch_eval_rows(const pair_view<T>& v, const frame_plan& fp, char* ws, hipStream_t st);
+hipError_t launch_eval_rows(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st);
 hipError_t launch_eval_single(const void* b, int dtype, int64_t pitch, int H, int W, int S,
                               char* ws, double* ex, double* ey, hipStream_t st);
 
 // recover.hip
-hipError_t launch_recover(const frame_plan& fp, char* ws, double* K1, double* K2, void* diag,
-                          hipStream_t st);
+hipError_t launch_diag_init(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st);
+hipError_t launch_gram(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st);
+// dense Gram matrices (2 S N N complex FP64, [pass][sample][p][q]); items of Q_GRAMM
+hipError_t launch_gram_expand(const frame_desc& one, const batch_ref& br, int grid, double* out, hipStream_t st);
+hipError_t launch_sample(const frame_desc& one, const batch_ref& br, int grid, int maxN, hipStream_t st);
+hipError_t launch_finalize(const frame_desc& one, const batch_ref& br, int grid, int maxS, int learned,
+                           hipStream_t st);
+size_t finalize_lds_bytes(int S, int learned);
+size_t sample_lds_bytes(int N);
 
-// fft.hip
+// gram_mfma.hip: the per-sample Gram on the matrix cores (fmt 0: FP32
+// operands, 1: bfloat16), N = k1 + k2 <= 32; maxStride = the largest Wmax /
+// Hmax of the launched frames.
+hipError_t launch_gram_mfma(const frame_desc& one, const batch_ref& br, int grid, int fmt, int maxStride,
+                            hipStream_t st);
+size_t gram_mfma_lds_bytes(int maxStride, int fmt);
+void set_gram_mfma_attrs();
+
+// fft.hip.  with_ey: the row pass also writes the row evaluation EY (the
+// k_eval_rows result, bit for bit) from the rows it already holds.
 template <typename T>
-hipError_t launch_row_fwd(const pair_view<T>& v, const frame_plan& fp, char* ws, hipStream_t st);
-template <typename T>
-hipError_t launch_col_inv(const pair_view<T>& v, const frame_plan& fp, char* ws, const double* K1,
-                          const double* K2, T* out, int64_t opitch, int64_t ocs, double lambda,
+hipError_t launch_row_fwd(const frame_desc& one, const batch_ref& br, int grid, int maxPx, int with_ey,
                           hipStream_t st);
+template <typename T>
+hipError_t launch_col(const frame_desc& one, const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st);
+template <typename T>
+hipError_t launch_row_inv(const frame_desc& one, const batch_ref& br, int grid, int maxPx, hipStream_t st);
+size_t row_lds_bytes(int N, int esize);
+size_t col_lds_bytes(int N, int cw, int esize);
+void set_recover_attrs();
+void set_fft_attrs();
+
+// mlp.hip: the learned form's network on every frame of the launch
+// (features -> weights and tau); blob is a device mlp_blob.
+hipError_t launch_mlp_frames(const frame_desc& one, const batch_ref& br, int grid, const void* blob,
+                             hipStream_t st);
 
 }  // namespace cbp

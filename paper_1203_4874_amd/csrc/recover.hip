@@ -80,96 +80,129 @@ __device__ inline void unit_twiddles(c64* tw, int S) {
 __device__ inline bool finite_c(c64 v) { return isfinite(v.re) && isfinite(v.im); }
 
 // Correlations rho for every (pass, sample, lag), summed over channels.
-// grid (2N-1, S, 2), one wave each; Dot2 accumulation per lane, then a
-// fixed-order double-double wave reduction.
-__global__ __launch_bounds__(64) void k_gram(const c64* ex, const c64* ey, int Wmax, int Hmax, int W1, int W2,
-                                             int H1, int H2, int S, int k1, int k2, int nch, cdd* corr) {
-  const int li = blockIdx.x, j = blockIdx.y, pass = blockIdx.z;
-  const int N = k1 + k2, NL = 2 * N - 1;
-  int fa, fb, l;
-  if (li < k2) { fa = 0; fb = 0; l = li; }
-  else if (li < k2 + k1) { fa = 1; fb = 1; l = li - k2; }
-  else { fa = 0; fb = 1; l = li - (k1 + k2) - (k1 - 1); }
-  const int la = pass == 0 ? (fa ? W2 : W1) : (fa ? H2 : H1);
-  const int lb = pass == 0 ? (fb ? W2 : W1) : (fb ? H2 : H1);
-  const int stride = pass == 0 ? Wmax : Hmax;
-  const c64* base = pass == 0 ? ex : ey;
-  const int t0 = max(0, -l), t1 = min(la, lb - l);
-  dot2 sre, sim;
-  sre.init();
-  sim.init();
-  for (int ch = 0; ch < nch; ++ch) {
-    const c64* a = base + ((size_t)(ch * 2 + fa) * S + j) * stride;
-    const c64* b = base + ((size_t)(ch * 2 + fb) * S + j) * stride;
-    int t = t0 + (int)threadIdx.x;
-    for (; t + 64 < t1; t += 128) {
-      const c64 a0 = a[t], b0 = b[t + l], a1 = a[t + 64], b1 = b[t + 64 + l];
-      sre.add_prod(a0.re, b0.re); sre.add_prod(a0.im, b0.im);
-      sim.add_prod(a0.re, b0.im); sim.add_prod(-a0.im, b0.re);
-      sre.add_prod(a1.re, b1.re); sre.add_prod(a1.im, b1.im);
-      sim.add_prod(a1.re, b1.im); sim.add_prod(-a1.im, b1.re);
+// Items: (lag, sample, pass), one wave each; Dot2 accumulation per lane,
+// then a fixed-order double-double wave reduction.
+__global__ __launch_bounds__(64) void k_gram(frame_desc one, batch_ref br) {
+  for_items<Q_GRAM>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+    const int k1 = d.k1, k2 = d.k2, S = d.S;
+    const int N = k1 + k2, NL = 2 * N - 1;
+    const int li = item % NL, rest = item / NL;
+    const int j = rest % S, pass = rest / S;
+    int fa, fb, l;
+    if (li < k2) { fa = 0; fb = 0; l = li; }
+    else if (li < k2 + k1) { fa = 1; fb = 1; l = li - k2; }
+    else { fa = 0; fb = 1; l = li - (k1 + k2) - (k1 - 1); }
+    const int la = pass == 0 ? (fa ? d.W2 : d.W1) : (fa ? d.H2 : d.H1);
+    const int lb = pass == 0 ? (fb ? d.W2 : d.W1) : (fb ? d.H2 : d.H1);
+    const int stride = pass == 0 ? d.Wmax : d.Hmax;
+    const c64* base = pass == 0 ? d.ex : d.ey;
+    const int t0 = max(0, -l), t1 = min(la, lb - l);
+    dot2 sre, sim;
+    sre.init();
+    sim.init();
+    for (int ch = 0; ch < d.nch; ++ch) {
+      const c64* a = base + ((size_t)(ch * 2 + fa) * S + j) * stride;
+      const c64* b = base + ((size_t)(ch * 2 + fb) * S + j) * stride;
+      int t = t0 + (int)threadIdx.x;
+      for (; t + 64 < t1; t += 128) {
+        const c64 a0 = a[t], b0 = b[t + l], a1 = a[t + 64], b1 = b[t + 64 + l];
+        sre.add_prod(a0.re, b0.re); sre.add_prod(a0.im, b0.im);
+        sim.add_prod(a0.re, b0.im); sim.add_prod(-a0.im, b0.re);
+        sre.add_prod(a1.re, b1.re); sre.add_prod(a1.im, b1.im);
+        sim.add_prod(a1.re, b1.im); sim.add_prod(-a1.im, b1.re);
+      }
+      if (t < t1) {
+        const c64 a0 = a[t], b0 = b[t + l];
+        sre.add_prod(a0.re, b0.re); sre.add_prod(a0.im, b0.im);
+        sim.add_prod(a0.re, b0.im); sim.add_prod(-a0.im, b0.re);
+      }
     }
-    if (t < t1) {
-      const c64 a0 = a[t], b0 = b[t + l];
-      sre.add_prod(a0.re, b0.re); sre.add_prod(a0.im, b0.im);
-      sim.add_prod(a0.re, b0.im); sim.add_prod(-a0.im, b0.re);
-    }
-  }
-  const dd re = wsum_dd(sre.result());
-  const dd im = wsum_dd(sim.result());
-  if (threadIdx.x == 0) corr[((size_t)pass * S + j) * NL + li] = cdd{re, im};
+    const dd re = wsum_dd(sre.result());
+    const dd im = wsum_dd(sim.result());
+    if (threadIdx.x == 0) d.corr[((size_t)pass * S + j) * NL + li] = cdd{re, im};
+  });
 }
 
-// Smallest eigenvector of every per-sample Gram.  grid (S, 2), one wave each.
-__global__ __launch_bounds__(SMALL_NT) void k_sample(const cdd* corr, int S, int k1, int k2, c64* xout,
-                                                     double* lam0, cbp_diag* diag) {
+// Smallest eigenvector of every per-sample Gram.  Items: (sample, pass),
+// one wave each.
+__global__ __launch_bounds__(SMALL_NT) void k_sample(frame_desc one, batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_sample[];
-  const int N = k1 + k2, NL = 2 * N - 1;
-  const int j = blockIdx.x, pass = blockIdx.y;
-  const int l = threadIdx.x;
-  cdd* rho = (cdd*)sm_sample;
-  small_ws w = small_carve(sm_sample + (((size_t)NL * sizeof(cdd) + 15) & ~(size_t)15), N);
-  for (int t = l; t < NL; t += SMALL_NT) rho[t] = corr[((size_t)pass * S + j) * NL + t];
-  __syncthreads();
-  const gram_acc G{rho, k1, k2};
-  for (int e = l; e < N * N; e += SMALL_NT) {
-    const int i = e / N, c = e - i * N;
-    const cdd g = G.get(i, c);
-    w.A[e] = {g.re.hi, g.im.hi};
-  }
-  const double gmax = wmax(l < N ? dd_val(G.get(l, l).re) : 0.0);
-  __syncthreads();
-  double lam1;
-  int steps;
-  const dd mu = small_eig(w, G, N, diag != nullptr, &lam1, &steps);
-  const size_t base = ((size_t)pass * S + j) * N;
-  const c64 xi = l < N ? w.x[l] : c64{0.0, 0.0};
-  if (l < N) {
-    xout[base + l] = xi;
-    if (diag) {
-      diag->sample_vec[pass][j][l][0] = xi.re;
-      diag->sample_vec[pass][j][l][1] = xi.im;
+  for_items<Q_SAMPLE>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+    const int k1 = d.k1, k2 = d.k2, S = d.S;
+    const int N = k1 + k2, NL = 2 * N - 1;
+    const int j = item % S, pass = item / S;
+    const int l = threadIdx.x;
+    cbp_diag* diag = d.diag;
+    cdd* rho = (cdd*)sm_sample;
+    small_ws w = small_carve(sm_sample + (((size_t)NL * sizeof(cdd) + 15) & ~(size_t)15), N);
+    for (int t = l; t < NL; t += SMALL_NT) rho[t] = d.corr[((size_t)pass * S + j) * NL + t];
+    __syncthreads();
+    const gram_acc G{rho, k1, k2};
+    for (int e = l; e < N * N; e += SMALL_NT) {
+      const int i = e / N, c = e - i * N;
+      const cdd g = G.get(i, c);
+      w.A[e] = {g.re.hi, g.im.hi};
     }
-  }
-  const bool bad = wmax(l < N && !finite_c(xi) ? 1.0 : 0.0) > 0.0;
-  if (l == 0) {
-    const double l0 = dd_val(mu);
-    lam0[pass * S + j] = l0;
-    if (diag) {
-      diag->sample_lambda0[pass][j] = l0;
-      diag->sample_lambda1[pass][j] = lam1;
-      diag->sample_scale[pass][j] = gmax;
-      atomicMax(&diag->refine_sample, steps);
-      if (!(lam1 - l0 > 1e-13 * gmax)) atomicOr(&diag->flags, CBP_DIAG_SAMPLE_WEAK);  // NaN-safe: flags NaN too
-      if (bad || !isfinite(l0)) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
+    const double gmax = wmax(l < N ? dd_val(G.get(l, l).re) : 0.0);
+    __syncthreads();
+    double lam1;
+    int steps;
+    const dd mu = small_eig(w, G, N, diag != nullptr, &lam1, &steps);
+    const size_t base = ((size_t)pass * S + j) * N;
+    const c64 xi = l < N ? w.x[l] : c64{0.0, 0.0};
+    if (l < N) {
+      d.xvec[base + l] = xi;
+      if (diag) {
+        diag->sample_vec[pass][j][l][0] = xi.re;
+        diag->sample_vec[pass][j][l][1] = xi.im;
+      }
     }
-  }
+    const bool bad = wmax(l < N && !finite_c(xi) ? 1.0 : 0.0) > 0.0;
+    if (d.feat) {
+      // learned form (and diagnostics): features of this sample's spectrum
+      // (the tridiagonal T of the solve is still in w.a / w.b):
+      //   f_i = log10(max(lambda_i, 1e-14 lambda_max) / lambda_max) / 10, i < N; +1 after
+      const double lam = small_spectrum(w, N);
+      const double lmax = readlane_d(lam, N - 1);
+      if (l < 32) {
+        const float f = l < N ? (float)(log10(fmax(lam, 1e-14 * lmax) / lmax) * 0.1) : 1.0f;
+        d.feat[((size_t)pass * S + j) * 32 + l] = f;
+        if (diag) diag->sample_features[pass][j][l] = f;
+      }
+    }
+    if (l == 0) {
+      const double l0 = dd_val(mu);
+      d.lam0[pass * S + j] = l0;
+      if (diag) {
+        diag->sample_lambda0[pass][j] = l0;
+        diag->sample_lambda1[pass][j] = lam1;
+        diag->sample_scale[pass][j] = gmax;
+        atomicMax(&diag->refine_sample, steps);
+        if (!(lam1 - l0 > 1e-13 * gmax)) atomicOr(&diag->flags, CBP_DIAG_SAMPLE_WEAK);  // NaN-safe: flags NaN too
+        if (bad || !isfinite(l0)) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
+      }
+    }
+  });
 }
 
 // Scale fix, assembly, inverse DFT and normalisation.  One wave.
-__global__ __launch_bounds__(SMALL_NT) void k_finalize(const c64* xvec, int S, int k1, int k2, c64* pq, cdd* cbuf,
-                                                       double* K1, double* K2, cbp_diag* diag) {
-  extern __shared__ __attribute__((aligned(16))) char sm_fin[];
+// Learned form (wts != NULL): wts[j] = wX_j (pass-X sample j), wts[S + i] =
+// wY_i, wts[2S] = tau.  The scale system's rows are weighted by
+// sqrt(wX_j wY_i); the spectra are averaged with weights wX_j, wY_i; each
+// kernel Z = K^T (k x k, [x][y]) solves (Ax + tau I) Z (By + tau I) = C with
+//   Ax = Fx^H D_u Fx, By = Fy^T D_v conj(Fy), C = Fx^H D_u Khat D_v conj(Fy),
+// u = wY, v = wX, F[i][x] = w_i^x (the separable weighted fit with per-axis
+// Tikhonov terms), then is divided by its complex sum (real part kept).
+__device__ inline void learned_assembly(const c64* tw, int S, int k, const double* wts, c64* Kh, c64* tb, c64* xt,
+                                        double* K, cbp_diag* diag, int c);
+
+// LDS of the plain finalize: twiddles, the two diagonal blocks, the solver.
+__host__ __device__ inline size_t fin_base_bytes(int S) {
+  return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) + small_lds_bytes(2 * S);
+}
+
+__device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c64* pq, cdd* cbuf, double* K1,
+                                      double* K2, cbp_diag* diag, char* sm_fin, const double* wts) {
   const int N = k1 + k2, n2 = 2 * S, SS = S * S;
   const int tid = threadIdx.x;
   c64* tw = (c64*)sm_fin;                        // S
@@ -209,8 +242,11 @@ __global__ __launch_bounds__(SMALL_NT) void k_finalize(const c64* xvec, int S, i
     dot2 re, im;
     re.init();
     im.init();
+    const double W = wts ? wts[jj] * wts[S + i] : 1.0;
     for (int c = 0; c < 2; ++c) {
-      const c64 P = pq[(size_t)c * SS + i * S + jj], Q = pq[(size_t)(2 + c) * SS + i * S + jj];
+      c64 P = pq[(size_t)c * SS + i * S + jj];
+      const c64 Q = pq[(size_t)(2 + c) * SS + i * S + jj];
+      if (wts) P = {W * P.re, W * P.im};
       re.add_prod(-P.re, Q.re); re.add_prod(-P.im, Q.im);
       im.add_prod(-P.re, Q.im); im.add_prod(P.im, Q.re);
     }
@@ -223,7 +259,9 @@ __global__ __launch_bounds__(SMALL_NT) void k_finalize(const c64* xvec, int S, i
       for (int c = 0; c < 2; ++c)
         for (int i = 0; i < S; ++i) {
           const c64 P = pq[(size_t)c * SS + i * S + t];
-          d.add_prod(P.re, P.re); d.add_prod(P.im, P.im);
+          const double W = wts ? wts[t] * wts[S + i] : 1.0;
+          if (wts) { d.add_prod(W * P.re, P.re); d.add_prod(W * P.im, P.im); }
+          else { d.add_prod(P.re, P.re); d.add_prod(P.im, P.im); }
         }
       Da[t] = d.result();
     } else {
@@ -231,7 +269,9 @@ __global__ __launch_bounds__(SMALL_NT) void k_finalize(const c64* xvec, int S, i
       for (int c = 0; c < 2; ++c)
         for (int jj = 0; jj < S; ++jj) {
           const c64 Q = pq[(size_t)(2 + c) * SS + i * S + jj];
-          d.add_prod(Q.re, Q.re); d.add_prod(Q.im, Q.im);
+          const double W = wts ? wts[jj] * wts[S + i] : 1.0;
+          if (wts) { d.add_prod(W * Q.re, Q.re); d.add_prod(W * Q.im, Q.im); }
+          else { d.add_prod(Q.re, Q.re); d.add_prod(Q.im, Q.im); }
         }
       Db[i] = d.result();
     }
@@ -269,14 +309,30 @@ __global__ __launch_bounds__(SMALL_NT) void k_finalize(const c64* xvec, int S, i
     const int c = e / SS, ij = e - c * SS;
     const int i = ij / S, jj = ij - i * S;
     const c64 P = pq[(size_t)c * SS + ij], Q = pq[(size_t)(2 + c) * SS + ij];
-    const c64 v = w.x[jj] * P + w.x[S + i] * Q;
-    Kh[e] = {0.5 * v.re, 0.5 * v.im};
+    c64 kv;
+    if (wts) {
+      const double wx = wts[jj], wy = wts[S + i], r = 1.0 / (wx + wy);
+      const c64 a = w.x[jj] * P, b = w.x[S + i] * Q;
+      kv = {(wx * a.re + wy * b.re) * r, (wx * a.im + wy * b.im) * r};
+    } else {
+      const c64 v = w.x[jj] * P + w.x[S + i] * Q;
+      kv = {0.5 * v.re, 0.5 * v.im};
+    }
+    Kh[e] = kv;
     if (diag) {
-      diag->khat[c][i][jj][0] = 0.5 * v.re;
-      diag->khat[c][i][jj][1] = 0.5 * v.im;
+      diag->khat[c][i][jj][0] = kv.re;
+      diag->khat[c][i][jj][1] = kv.im;
     }
   }
   __syncthreads();
+  if (wts) {
+    if (diag)
+      for (int t = tid; t <= n2; t += SMALL_NT) diag->sample_weights[t] = wts[t];
+    c64* xt = (c64*)((char*)sm_fin + fin_base_bytes(S));   // S^2 + 2 CBP_MAX_S extra entries
+    learned_assembly(tw, S, k1, wts, Kh, tbuf, xt, K1, diag, 0);
+    learned_assembly(tw, S, k2, wts, Kh + SS, tbuf, xt, K2, diag, 1);
+    return;
+  }
   // inverse DFT along x: Tm[c][j][x] = sum_i Kh[c][i][j] w_i^{-x}
   for (int e = tid; e < 2 * SS; e += SMALL_NT) {
     const int c = e / SS, jx = e - c * SS;
@@ -342,50 +398,181 @@ __global__ __launch_bounds__(SMALL_NT) void k_finalize(const c64* xvec, int S, i
   }
 }
 
-__global__ void k_diag_init(cbp_diag* diag) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    diag->flags = 0;
-    diag->refine_sample = 0;
-    diag->refine_scale = 0;
+__device__ inline void learned_assembly(const c64* tw, int S, int k, const double* wts, c64* Kh, c64* tb, c64* xt,
+                                        double* K, cbp_diag* diag, int c) {
+  const int tid = threadIdx.x, kk = k * k;
+  const double tau = wts[2 * S];
+  c64* Ax = tb;             // k x k
+  c64* By = tb + kk;        // k x k
+  c64* T1 = xt;             // k x S, later Z1 (k x k)
+  c64* Cm = Kh;             // k x k, over Khat once T1 is formed
+  // F[i][x] = w_i^x = tw[(i x) mod S];  u_i = wY_i,  v_j = wX_j
+  for (int e = tid; e < kk; e += SMALL_NT) {
+    const int p = e / k, q = e - p * k;
+    c64 a = {0.0, 0.0}, b = {0.0, 0.0};
+    for (int i = 0; i < S; ++i) {
+      const c64 fp = tw[(i * p) % S], fq = tw[(i * q) % S];
+      const c64 g = cmulc(fp, fq);            // conj(F[i][p]) F[i][q]
+      a = a + c64{wts[S + i] * g.re, wts[S + i] * g.im};
+      const c64 h = cmulc(fq, fp);            // F[j][p] conj(F[j][q])
+      b = b + c64{wts[i] * h.re, wts[i] * h.im};
+    }
+    if (p == q) { a.re += tau; b.re += tau; }
+    Ax[e] = a;
+    By[e] = b;
   }
+  // T1[x][j] = sum_i conj(F[i][x]) u_i Khat[i][j]
+  for (int e = tid; e < k * S; e += SMALL_NT) {
+    const int x = e / S, jj = e - x * S;
+    c64 acc = {0.0, 0.0};
+    for (int i = 0; i < S; ++i) {
+      const c64 g = cmulc(tw[(i * x) % S], Kh[i * S + jj]);
+      acc = acc + c64{wts[S + i] * g.re, wts[S + i] * g.im};
+    }
+    T1[e] = acc;
+  }
+  __syncthreads();
+  // C[x][y] = sum_j T1[x][j] v_j conj(F[j][y])
+  for (int e = tid; e < kk; e += SMALL_NT) {
+    const int x = e / k, y = e - x * k;
+    c64 acc = {0.0, 0.0};
+    for (int jj = 0; jj < S; ++jj) {
+      const c64 g = cmulc(tw[(jj * y) % S], T1[x * S + jj]);
+      acc = acc + c64{wts[jj] * g.re, wts[jj] * g.im};
+    }
+    Cm[e] = acc;
+  }
+  __syncthreads();
+  // (Ax + tau I)^{-1}, (By + tau I)^{-1} in place (Hermitian positive definite)
+  small_ws g;
+  g.w = xt + (size_t)S * S;
+  g.u = g.w + CBP_MAX_S;
+  g.A = Ax;
+  small_gj_inverse(g, k);
+  g.A = By;
+  small_gj_inverse(g, k);
+  // Z1 = Ax^{-1} C (into T1), Z = Z1 By^{-1} (into Cm)
+  for (int e = tid; e < kk; e += SMALL_NT) {
+    const int x = e / k, y = e - x * k;
+    c64 acc = {0.0, 0.0};
+    for (int t = 0; t < k; ++t) acc = acc + Ax[x * k + t] * Cm[t * k + y];
+    T1[e] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < kk; e += SMALL_NT) {
+    const int x = e / k, y = e - x * k;
+    c64 acc = {0.0, 0.0};
+    for (int t = 0; t < k; ++t) acc = acc + T1[x * k + t] * By[t * k + y];
+    Cm[e] = acc;
+  }
+  __syncthreads();
+  // K[y][x] = Z[x][y] / sum(Z), real part
+  double sr = 0.0, si = 0.0;
+  for (int e = tid; e < kk; e += SMALL_NT) { sr += Cm[e].re; si += Cm[e].im; }
+  sr = wsum(sr);
+  si = wsum(si);
+  const double s2 = sr * sr + si * si;
+  double re2 = 0.0, im2 = 0.0;
+  for (int e = tid; e < kk; e += SMALL_NT) {
+    const int y = e / k, x = e - y * k;
+    const c64 v = Cm[x * k + y];
+    const double kr = (v.re * sr + v.im * si) / s2;
+    const double ki = (v.im * sr - v.re * si) / s2;
+    K[e] = kr;
+    re2 += kr * kr;
+    im2 += ki * ki;
+  }
+  re2 = wsum(re2);
+  im2 = wsum(im2);
+  if (tid == 0 && diag) {
+    diag->kernel_imag[c] = sqrt(im2) / fmax(sqrt(re2), 1e-300);
+    diag->kernel_outside[c] = 0.0;
+    if (!(s2 > 0.0) || !isfinite(s2)) atomicOr(&diag->flags, CBP_DIAG_KERNEL_ZERO);
+    if (!isfinite(re2)) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
+  }
+  __syncthreads();
+}
+
+// Items: one per frame.
+__global__ __launch_bounds__(SMALL_NT) void k_finalize(frame_desc one, batch_ref br) {
+  extern __shared__ __attribute__((aligned(16))) char sm_fin[];
+  for_items<Q_FINALIZE>(one, br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
+    finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, d.cbuf, d.K1, d.K2, d.diag, sm_fin, d.wts);
+  });
+}
+
+// Dense per-sample Gram matrices from the correlations (the a2 output of
+// cbp_sample_grams): out[pass][j][p][q] = G(p, q) rounded to FP64.
+// Items: (sample, pass).
+__global__ __launch_bounds__(64) void k_gram_expand(frame_desc one, batch_ref br, c64* out) {
+  for_items<Q_GRAMM>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+    const int S = d.S, N = d.N, NL = 2 * N - 1;
+    const gram_acc G{d.corr + (size_t)item * NL, d.k1, d.k2};
+    c64* o = out + (size_t)item * N * N;
+    for (int e = threadIdx.x; e < N * N; e += 64) {
+      const cdd g = G.get(e / N, e % N);
+      o[e] = {dd_val(g.re), dd_val(g.im)};
+    }
+    (void)S;
+  });
+}
+
+// Clear the per-call diagnostic counters.  Items: one per frame.
+__global__ void k_diag_init(frame_desc one, batch_ref br) {
+  for_items<Q_DIAG>(one, br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
+    if (threadIdx.x == 0 && d.diag) {
+      d.diag->flags = 0;
+      d.diag->refine_sample = 0;
+      d.diag->refine_scale = 0;
+    }
+  });
 }
 
 }  // namespace
 
-size_t finalize_lds_bytes(int S) {
-  return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) + small_lds_bytes(2 * S);
+size_t finalize_lds_bytes(int S, int learned) {
+  const size_t base = fin_base_bytes(S);
+  // the learned assembly: T1 / Z1 (S^2) and the inversion's two vectors
+  return learned ? base + ((size_t)S * S + 2 * CBP_MAX_S) * sizeof(c64) : base;
 }
 
 size_t sample_lds_bytes(int N) {
   return ((((size_t)(2 * N - 1) * sizeof(cdd)) + 15) & ~(size_t)15) + small_lds_bytes(N);
 }
 
-hipError_t launch_recover(const frame_plan& fp, char* ws, double* K1, double* K2, void* diagp, hipStream_t st) {
-  static bool attrs_set = false;
-  if (!attrs_set) {
-    hipFuncSetAttribute((const void*)k_sample, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    hipFuncSetAttribute((const void*)k_finalize, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attrs_set = true;
-  }
-  cbp_diag* diag = (cbp_diag*)diagp;
-  const int S = fp.S, N = fp.N;
-  const c64* ex = (const c64*)(ws + fp.off_ex);
-  const c64* ey = (const c64*)(ws + fp.off_ey);
-  cdd* corr = (cdd*)(ws + fp.off_corr);
-  c64* xvec = (c64*)(ws + fp.off_xvec);
-  double* lam0 = (double*)(ws + fp.off_lam0);
-  if (diag) hipLaunchKernelGGL(k_diag_init, dim3(1), dim3(256), 0, st, diag);
+void set_recover_attrs() {
+  hipFuncSetAttribute((const void*)k_sample, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_finalize, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+hipError_t launch_diag_init(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_init, dim3(grid), dim3(64), 0, st, one, br);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_expand(const frame_desc& one, const batch_ref& br, int grid, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_expand, dim3(grid), dim3(64), 0, st, one, br, (c64*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st) {
   prof_begin(PH_GRAM, st);
-  hipLaunchKernelGGL(k_gram, dim3(2 * N - 1, S, 2), dim3(64), 0, st, ex, ey, fp.Wmax, fp.Hmax, fp.W1, fp.W2, fp.H1,
-                     fp.H2, S, fp.k1, fp.k2, fp.nch, corr);
+  hipLaunchKernelGGL(k_gram, dim3(grid), dim3(64), 0, st, one, br);
   prof_end(PH_GRAM, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(const frame_desc& one, const batch_ref& br, int grid, int maxN, hipStream_t st) {
   prof_begin(PH_SAMPLE, st);
-  hipLaunchKernelGGL(k_sample, dim3(S, 2), dim3(SMALL_NT), sample_lds_bytes(N), st, corr, S, fp.k1, fp.k2, xvec,
-                     lam0, diag);
+  hipLaunchKernelGGL(k_sample, dim3(grid), dim3(SMALL_NT), sample_lds_bytes(maxN), st, one, br);
   prof_end(PH_SAMPLE, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const frame_desc& one, const batch_ref& br, int grid, int maxS, int learned,
+                           hipStream_t st) {
   prof_begin(PH_FINALIZE, st);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(SMALL_NT), finalize_lds_bytes(S), st, xvec, S, fp.k1, fp.k2,
-                     (c64*)(ws + fp.off_pq), (cdd*)(ws + fp.off_cbuf), K1, K2, diag);
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(SMALL_NT), finalize_lds_bytes(maxS, learned), st, one, br);
   prof_end(PH_FINALIZE, st);
   return hipGetLastError();
 }

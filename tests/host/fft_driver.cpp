@@ -1,5 +1,5 @@
 // Host driver for the library's Stockham FFT passes (csrc/fft_core.h):
-// reads "N dir" then N complex values (re im) from stdin, runs every pass of
+// reads "N dir order" then N complex values (re im) from stdin, runs every pass of
 // the plan sequentially on the CPU and prints the transform.  Used by
 // tests/test_fft_host.py to check the butterflies against numpy.fft.
 #include <cmath>
@@ -11,10 +11,10 @@
 using namespace cbp;
 
 int main() {
-  int N, dir;
-  if (std::scanf("%d %d", &N, &dir) != 2) return 2;
+  int N, dir, order;
+  if (std::scanf("%d %d %d", &N, &dir, &order) != 3) return 2;
   fft_plan p;
-  if (!make_fft_plan(N, &p)) { std::printf("BADPLAN\n"); return 3; }
+  if (!make_fft_plan(N, &p, order)) { std::printf("BADPLAN\n"); return 3; }
   std::vector<cplx<double>> a(N), b(N), tw(N);
   for (int i = 0; i < N; ++i)
     if (std::scanf("%lf %lf", &a[i].re, &a[i].im) != 2) return 2;

@@ -48,7 +48,8 @@ def test_workspace_size_monotone_and_invalid(P):
     a = P.workspace_size(490, 650, 11)
     assert a > 0
     assert P.workspace_size(720, 1300, 15) > a
-    assert P.workspace_size(490, 650, 11, batch=4) == 4 * a
+    # a batch holds every frame plus a head of frame descriptors and item prefix sums
+    assert 3 * a < P.workspace_size(490, 650, 11, batch=4) <= 4 * a
     assert P.workspace_size(490, 650, 33) == 0
     assert P.workspace_size(0, 650, 11) == 0
 
@@ -79,13 +80,43 @@ def test_host_validation_codes(P):
     o.lambda_ = 0.0
     o.precision = P.Precision.FP64                          # FP64 form needs FP64 frames
     assert call(i1, i2, lat, o) == 1
-    o.precision = P.Precision.BF16
-    assert call(i1, i2, lat, o) == 6
+    o.precision = P.Precision.BF16                          # matrix-core forms take FP32 frames
+    assert call(i1, i2, lat, o) == 5                        # (accepted; no workspace)
+    assert call(_img(0x1000, 1, 488, 648), _img(0x2000, 1, 490, 650), _img(0x3000, 1, 480, 640), o) == 1
+    wide = (_img(0x1000, 0, 480 + 19, 640 + 19), _img(0x2000, 0, 480 + 15, 640 + 15))   # k1 + k2 = 36 > 32
+    assert call(wide[0], wide[1], lat, o) == 6
+    o.precision = P.Precision.MFMA32
+    assert call(wide[0], wide[1], lat, o) == 6
+    assert call(i1, i2, lat, o) == 5
     o.precision = P.Precision.MIXED
-    o.learned = 1
-    assert call(i1, i2, lat, o) == 6
+    o.learned = 1                                           # the learned form needs its network blob
+    assert call(i1, i2, lat, o) == 1
     o.learned = 0
     big = _img(0x1000, 0, 488 + 40, 648 + 40)               # k = 41 > 32
     assert call(big, _img(0x2000, 0, 490 + 40, 650 + 40), _img(0x3000, 0, 480, 640), o) == 2
     assert call(_img(0, 0, 488, 648), i2, lat, o) == 1      # null data pointer
     assert L.cbp_deblur(None, ctypes.byref(i2), ctypes.byref(lat), None, None, ctypes.byref(o)) == 1
+    o.flags = 64                                            # unknown option flag
+    assert call(i1, i2, lat, o) == 1
+    o.flags = 0
+
+
+def test_batch_host_validation(P):
+    """Per-frame statuses of cbp_deblur_batch come from host checks; a batch
+    whose every frame is invalid returns before any HIP call."""
+    global P_
+    P_ = P
+    L = P.lib()
+    o = P.CbpOptions()
+    o.precision = P.Precision.MIXED
+    n = 3
+    I1 = (P.CbpImage * n)(_img(0x1000, 0, 488, 648), _img(0x1000, 0, 488, 648), _img(0, 0, 488, 648))
+    I2 = (P.CbpImage * n)(_img(0x2000, 0, 490, 651), _img(0x2000, 1, 490, 650), _img(0x2000, 0, 490, 650))
+    IO = (P.CbpImage * n)(_img(0x3000, 0, 480, 640), _img(0x3000, 0, 480, 640), _img(0x3000, 0, 480, 640))
+    st = (ctypes.c_int * n)()
+    r = L.cbp_deblur_batch(n, I1, I2, IO, None, None, st, ctypes.byref(o))
+    assert list(st) == [2, 1, 1]      # H1-H2 != W1-W2; dtypes differ; null data pointer
+    assert r == 2                     # the first failure
+    assert L.cbp_deblur_batch(0, I1, I2, IO, None, None, st, ctypes.byref(o)) == 1
+    t = P.CbpTuning()
+    assert L.cbp_last_tuning(None) == 1

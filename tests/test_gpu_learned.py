@@ -1,0 +1,170 @@
+"""GPU parity of the learned form: the BF16 network's forward and gradients
+against the oracle network run with the kernels' roundings, Adam training
+lowering the loss, and the learned kernels against the oracle's learned
+route with the same (seeded, synthetic) parameters.
+
+Bars: network outputs within 2e-3 of the output scale and gradients within
+1e-2 (norm-wise, per parameter block) of the bf16-emulated oracle -- the
+residue is FP32 accumulation, which can move a bfloat16 rounding of a hidden
+activation by one unit (2^-8 relative); learned kernels within 1e-3 of the
+oracle's learned kernels (FP32 frames); constant network outputs (unit
+weights, tau ~ 0) give the plain kernels to 1e-9.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cbp as orc
+from oracle import learned as orl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1203_4874_amd as P
+    P.lib()
+    return P
+
+
+def _params(seed, scale=1.0):
+    p = orl.init_params(np.random.default_rng(seed))
+    r = np.random.default_rng(seed + 1)
+    p["b1"] = 0.1 * r.standard_normal(128)
+    p["b2"] = 0.1 * r.standard_normal(128)
+    p["W3"] = p["W3"] * scale
+    p["b3"] = np.array([0.5, -3.0])
+    return p
+
+
+def _features(seed, n):
+    """Feature rows shaped like real ones: N in 10..30 log-spectrum values in
+    [-1.4, 0] ascending, +1 padding."""
+    r = np.random.default_rng(seed)
+    X = np.ones((n, 32))
+    for i in range(n):
+        N = int(r.integers(10, 31))
+        X[i, :N] = np.sort(-1.4 * r.random(N) ** 2)
+        X[i, N - 1] = 0.0
+    return X
+
+
+def test_network_forward_matches_bf16_oracle(P):
+    p = _params(3)
+    blob = P.mlp_blob_from_params(orl.pack(p).astype(np.float32), _dev())
+    for n in (1, 37, 64, 300):
+        X = _features(n, n)
+        out = P.mlp_forward(blob, torch.as_tensor(X, dtype=torch.float32, device=_dev())).cpu().numpy()
+        # the oracle reads the same FP32 parameters and features the GPU reads
+        q = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+        o, _ = orl.mlp_forward_bf16(q, X.astype(np.float32).astype(np.float64))
+        err = np.abs(out - o).max() / np.abs(o).max()
+        print(f"forward n={n}: max |diff| / max |o| = {err:.2e}")
+        assert err <= 2e-3
+
+
+def test_network_gradients_match_bf16_oracle(P):
+    p = _params(5, scale=3.0)
+    q = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    n = 700
+    X = _features(11, n).astype(np.float32).astype(np.float64)
+    r = np.random.default_rng(12)
+    T = np.stack([r.standard_normal(n), -5.0 + r.standard_normal(n)], 1).astype(np.float32).astype(np.float64)
+    st = P.MlpState(1024, _dev())
+    st.set_params(orl.pack(q).astype(np.float32))
+    loss, g = st.gradients(torch.as_tensor(X, dtype=torch.float32, device=_dev()),
+                           torch.as_tensor(T, dtype=torch.float32, device=_dev()))
+    torch.cuda.synchronize()
+    lo, go = orl.loss_and_grad_bf16(q, X, T[:, 0], T[:, 1])
+    gg = orl.unpack(g.cpu().numpy())
+    print(f"loss gpu {float(loss.item()):.6f} oracle {lo:.6f}")
+    assert abs(float(loss.item()) - lo) <= 1e-3 * abs(lo)
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        e = rel(gg[k], go[k])
+        print(f"grad {k}: rel-L2 {e:.2e}")
+        assert e <= 1e-2, k
+    # and the bf16-emulated oracle gradient is close to the exact FP64 one
+    _, gx = orl.loss_and_grad(q, X, T[:, 0], T[:, 1])
+    assert rel(go["W2"], gx["W2"]) <= 5e-2
+
+
+def test_adam_training_lowers_the_loss(P):
+    """A synthetic regression (targets a smooth function of the features):
+    400 Adam steps on the GPU lower the loss by > 5x."""
+    n = 4096
+    X = _features(21, n)
+    T = np.stack([np.tanh(3 * X[:, 0]) + X[:, 5], -4.0 + 2 * X[:, 1] * X[:, 2]], 1)
+    Xd = torch.as_tensor(X, dtype=torch.float32, device=_dev())
+    Td = torch.as_tensor(T, dtype=torch.float32, device=_dev())
+    st = P.MlpState(n, _dev())
+    st.set_params(orl.pack(_params(7)).astype(np.float32))
+    l0 = float(st.gradients(Xd, Td)[0].item())
+    for step in range(1, 401):
+        st.train_step(Xd, Td, 3e-3, step)
+    torch.cuda.synchronize()
+    l1 = float(st.gradients(Xd, Td)[0].item())
+    print(f"loss {l0:.4f} -> {l1:.4f}")
+    assert l1 < l0 / 5
+
+
+def _noisy_pair(seed, m, n, k1, k2, noise):
+    r = synth.rng_for(seed, m, n)
+    L = synth.gaussian_scene(r, m, n)
+    K1, K2 = synth.draw_coprime_pair(r, k1, k2, "uniform")
+    B1, B2 = synth.blur_pair(synth.rng_for(seed, 9), L, K1, K2, noise)
+    return B1.astype(np.float32).astype(np.float64), B2.astype(np.float32).astype(np.float64), K1, K2
+
+
+@pytest.mark.parametrize("k1,k2,noise", [(5, 7, 1e-3), (9, 11, 1e-2), (7, 7, 0.0)])
+def test_learned_kernels_match_oracle(P, k1, k2, noise):
+    m, n = 96, 128
+    B1, B2, K1t, K2t = _noisy_pair(31, m, n, k1, k2, noise)
+    p = _params(13, scale=2.0)
+    q = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    blob = P.mlp_blob_from_params(orl.pack(q).astype(np.float32), _dev())
+    b1 = torch.as_tensor(B1, dtype=torch.float32, device=_dev())
+    b2 = torch.as_tensor(B2, dtype=torch.float32, device=_dev())
+    d = P.Deblurrer(m + max(k1, k2) - 1, n + max(k1, k2) - 1, max(k1, k2), precision=P.Precision.MIXED, diag=True)
+    L, G1, G2 = d.deblur(b1, b2, m, n, lam=1e-4, mlp=blob)
+    torch.cuda.synchronize()
+    dg = d.read_diag()
+    R1, R2, info = orl.recover_kernels_learned(B1, B2, m, n, q, full=True, bf16=True)
+    S = dg["S"]
+    wg = dg["sample_weights"]
+    print(f"k=({k1},{k2}) noise {noise}: weights gpu vs oracle max rel "
+          f"{np.abs(wg[:S] - info['wX']).max() / info['wX'].max():.2e}, tau {wg[2 * S]:.3e} vs {info['tau']:.3e}")
+    e = max(rel(G1.cpu().numpy(), R1), rel(G2.cpu().numpy(), R2))
+    P1, P2 = info["plain"]
+    ep = max(rel(R1, K1t), rel(R2, K2t))
+    el = max(rel(P1, K1t), rel(P2, K2t))
+    print(f"  learned kernels gpu vs oracle {e:.2e}; oracle vs truth: learned {ep:.3e}, plain {el:.3e}")
+    assert e <= 1e-3
+
+
+def test_constant_network_gives_plain_kernels(P):
+    m, n, k1, k2 = 80, 90, 6, 5
+    B1, B2, _, _ = _noisy_pair(41, m, n, k1, k2, 1e-3)
+    p = _params(17)
+    p["W3"][:] = 0.0
+    p["b3"][:] = [np.log(np.e - 1.0), -30.0]      # w = softplus(o1) = 1, tau = e^-30
+    blob = P.mlp_blob_from_params(orl.pack(p).astype(np.float32), _dev())
+    b1 = torch.as_tensor(B1, dtype=torch.float32, device=_dev())
+    b2 = torch.as_tensor(B2, dtype=torch.float32, device=_dev())
+    d = P.Deblurrer(m + k1 - 1, n + k1 - 1, k1, precision=P.Precision.MIXED)
+    _, A1, A2 = d.deblur(b1, b2, m, n, lam=1e-4)
+    A1, A2 = A1.clone(), A2.clone()
+    _, L1, L2 = d.deblur(b1, b2, m, n, lam=1e-4, mlp=blob)
+    torch.cuda.synchronize()
+    assert rel(L1.cpu().numpy(), A1.cpu().numpy()) <= 1e-9
+    assert rel(L2.cpu().numpy(), A2.cpu().numpy()) <= 1e-9

@@ -16,8 +16,8 @@ def test_features_closed_form():
     assert f.shape == (32,)
     assert np.allclose(f[:3], [-1.0, -0.5, 0.0], atol=1e-15)
     assert np.all(f[3:] == learned.PAD)
-    g = learned.spectrum_features(np.array([0.0, 2.0]))     # a zero eigenvalue hits the floor
-    assert np.isclose(g[0], -3.0) and g[1] == 0.0
+    g = learned.spectrum_features(np.array([0.0, 1e-20, 2.0]))  # below 1e-14 lambda_max: the floor
+    assert np.allclose(g[:2], -1.4) and g[2] == 0.0
 
 
 def test_mlp_gradients_match_central_differences():
@@ -126,3 +126,21 @@ def test_constant_network_output_reduces_to_plain():
     P1, P2 = info["plain"]
     assert np.allclose(info["wX"], info["wX"][0]) and info["tau"] <= 1e-12
     assert np.abs(Q1 - P1).max() <= 1e-9 and np.abs(Q2 - P2).max() <= 1e-9
+
+
+def test_bf16_network_emulation_reduces_to_fp64_on_representable_values():
+    """With parameters and inputs that bfloat16 holds exactly and activations
+    that stay exact, the emulated forward equals the FP64 forward; the
+    rounding itself matches the operand rounding of the Gram forms."""
+    rng = np.random.default_rng(9)
+    p = learned.init_params(rng)
+    p = {k: learned.round_bf16(v) for k, v in p.items()}
+    X = learned.round_bf16(rng.standard_normal((5, 32)))
+    o1, _ = learned.mlp_forward_bf16(p, X)
+    o0, _ = learned.mlp_forward(p, X)
+    assert np.abs(o1 - o0).max() <= 2e-2 * np.abs(o0).max()     # only the hidden roundings differ
+    x = rng.standard_normal(1000)
+    assert np.array_equal(learned.round_bf16(x), cbp.round_operands(x + 0j, "bf16").real)
+    v = learned.pack(p)
+    q = learned.unpack(v)
+    assert all(np.array_equal(p[k], q[k]) for k in p) and v.size == 20994
