@@ -336,7 +336,6 @@ dev_state* get_dev() {
 // One launch of every queue over a set of frames: either one frame (one !=
 // nullptr, descs == nullptr) or a chunk of a batch.
 struct chunk_view {
-  const frame_desc* one;
   const frame_desc* descs;  // device
   const int* starts;        // device
   int nf;
@@ -357,30 +356,27 @@ int grid_for(int items, int cap) {
 
 template <typename T>
 hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool diag, hipStream_t st) {
-  static const frame_desc zero = {};
-  const frame_desc& one = cv.one ? *cv.one : zero;
-  auto br = [&](int q) {
-    return cv.descs ? batch_ref{cv.descs, cv.starts, cv.nf} : batch_ref{nullptr, nullptr, cv.items[q]};
-  };
+  const batch_ref b = {cv.descs, cv.starts, cv.nf};
+  auto br = [&](int) { return b; };
   hipStream_t side = ds.side;
   CBP_TRY(hipEventRecord(ds.ev_fork, st));
   CBP_TRY(hipStreamWaitEvent(side, ds.ev_fork, 0));
-  if (latent) CBP_TRY(launch_row_fwd<T>(one, br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, side));
-  else CBP_TRY(launch_eval_rows<T>(one, br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], side));
+  if (latent) CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, side));
+  else CBP_TRY(launch_eval_rows<T>(br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], side));
   CBP_TRY(hipEventRecord(ds.ev_side, side));
-  if (diag) CBP_TRY(launch_diag_init(one, br(Q_DIAG), cv.grid[Q_DIAG], st));
-  CBP_TRY(launch_fold<T>(one, br(Q_FOLD), cv.grid[Q_FOLD], st));
-  CBP_TRY(launch_eval_cols(one, br(Q_EVAL_COLS), cv.grid[Q_EVAL_COLS], st));
+  if (diag) CBP_TRY(launch_diag_init(br(Q_DIAG), cv.grid[Q_DIAG], st));
+  CBP_TRY(launch_fold<T>(br(Q_FOLD), cv.grid[Q_FOLD], st));
+  CBP_TRY(launch_eval_cols(br(Q_EVAL_COLS), cv.grid[Q_EVAL_COLS], st));
   // join: the Gram needs the row evaluation (and the column pass the row spectra)
   CBP_TRY(hipStreamWaitEvent(st, ds.ev_side, 0));
-  if (cv.gram_fmt < 0) CBP_TRY(launch_gram(one, br(Q_GRAM), cv.grid[Q_GRAM], st));
-  else CBP_TRY(launch_gram_mfma(one, br(Q_GRAMM), cv.grid[Q_GRAMM], cv.gram_fmt, cv.maxStride, st));
-  CBP_TRY(launch_sample(one, br(Q_SAMPLE), cv.grid[Q_SAMPLE], cv.maxN, st));
-  if (cv.mlp) CBP_TRY(launch_mlp_frames(one, br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.mlp, st));
-  CBP_TRY(launch_finalize(one, br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, cv.mlp != nullptr, st));
+  if (cv.gram_fmt < 0) CBP_TRY(launch_gram(br(Q_GRAM), cv.grid[Q_GRAM], st));
+  else CBP_TRY(launch_gram_mfma(br(Q_GRAMM), cv.grid[Q_GRAMM], cv.gram_fmt, cv.maxStride, st));
+  CBP_TRY(launch_sample(br(Q_SAMPLE), cv.grid[Q_SAMPLE], cv.maxN, st));
+  if (cv.mlp) CBP_TRY(launch_mlp_frames(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.mlp, st));
+  CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, cv.mlp != nullptr, st));
   if (latent) {
-    CBP_TRY(launch_col<T>(one, br(Q_COL), cv.grid[Q_COL], cv.maxPy, cv.maxcw, st));
-    CBP_TRY(launch_row_inv<T>(one, br(Q_ROW_INV), cv.grid[Q_ROW_INV], cv.maxPx, st));
+    CBP_TRY(launch_col<T>(br(Q_COL), cv.grid[Q_COL], cv.maxPy, cv.maxcw, st));
+    CBP_TRY(launch_row_inv<T>(br(Q_ROW_INV), cv.grid[Q_ROW_INV], cv.maxPx, st));
   }
   return hipSuccess;
 }
@@ -388,37 +384,6 @@ hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool 
 hipError_t enqueue(dev_state& ds, int dtype, const chunk_view& cv, bool latent, bool diag, hipStream_t st) {
   return dtype == CBP_F32 ? enqueue_chunk<float>(ds, cv, latent, diag, st)
                           : enqueue_chunk<double>(ds, cv, latent, diag, st);
-}
-
-// ---------------------------------------------------------------- one frame
-cbp_status frame_call(const cbp_image* b1, const cbp_image* b2, cbp_image* latent, int m, int n, double* K1,
-                      double* K2, const cbp_options* o, char* ws, size_t ws_bytes, void* diag) {
-  frame_plan fp;
-  const cbp_status s = make_plan(b1, b2, m, n, o, kDefaultTuning, &fp);
-  if (s != CBP_OK) return s;
-  if (latent) {
-    if (!valid_image(latent) || latent->dtype != b1->dtype || latent->channels != b1->channels) return CBP_E_INVALID;
-  }
-  const size_t head = head_bytes(1);
-  if (!ws || ws_bytes < head + fp.total) return CBP_E_NOMEM;
-  dev_state* ds = get_dev();
-  if (!ds) return CBP_E_DEVICE;
-  const frame_desc d = make_desc(fp, b1, b2, ws + head, K1, K2, latent, o->lambda, diag, o->learned != 0);
-  chunk_view cv = {};
-  cv.one = &d;
-  for (int q = 0; q < Q_COUNT; ++q) {
-    cv.items[q] = queue_items(q, fp);
-    cv.grid[q] = grid_for(cv.items[q], 0);
-  }
-  cv.maxN = fp.N; cv.maxS = fp.S; cv.maxPx = fp.Px; cv.maxPy = fp.Py; cv.maxcw = fp.cw;
-  cv.gram_fmt = gram_format(o->precision);
-  cv.maxStride = std::max(fp.Hmax, fp.Wmax);
-  cv.mlp = o->learned ? o->mlp_blob : nullptr;
-  std::lock_guard<std::mutex> lk(ds->launch_mu);
-  (void)hipGetLastError();  // launch errors below are read with hipGetLastError: start clean
-  return enqueue(*ds, b1->dtype, cv, latent != nullptr, diag != nullptr, (hipStream_t)o->stream) == hipSuccess
-             ? CBP_OK
-             : CBP_E_DEVICE;
 }
 
 // ---------------------------------------------------------------- batches
@@ -515,7 +480,6 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
     const int f0 = c * BATCH_CHUNK, cnt = std::min(BATCH_CHUNK, nf - f0);
     int* st = starts + (size_t)c * Q_COUNT * (BATCH_CHUNK + 1);
     chunk_view cv = {};
-    cv.one = nullptr;
     cv.descs = (const frame_desc*)bb->head_dev + f0;
     cv.starts = (const int*)(bb->head_dev + head_desc_bytes(nf)) + (size_t)c * Q_COUNT * (BATCH_CHUNK + 1);
     cv.nf = cnt;
@@ -562,22 +526,26 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
 }
 
 // Copy the workspace head from a pinned staging slot (asynchronous on st).
-hipError_t upload_head(dev_state& ds, const batch_build& bb, hipStream_t st) {
+hipError_t upload_bytes(dev_state& ds, void* dst, const std::vector<char>& bytes, hipStream_t st) {
   pinned_slot& s = ds.ring[ds.next];
   ds.next = (ds.next + 1) % kRing;
   if (s.recorded) CBP_TRY(hipEventSynchronize(s.done));
-  if (s.cap < bb.head.size()) {
-    if (s.host) hipHostFree(s.host);
+  if (s.cap < bytes.size()) {
+    if (s.host) (void)hipHostFree(s.host);
     s.host = nullptr;
     s.cap = 0;
-    CBP_TRY(hipHostMalloc(&s.host, bb.head.size(), hipHostMallocDefault));
-    s.cap = bb.head.size();
+    CBP_TRY(hipHostMalloc(&s.host, bytes.size(), hipHostMallocDefault));
+    s.cap = bytes.size();
   }
-  std::memcpy(s.host, bb.head.data(), bb.head.size());
-  CBP_TRY(hipMemcpyAsync(bb.head_dev, s.host, bb.head.size(), hipMemcpyHostToDevice, st));
+  std::memcpy(s.host, bytes.data(), bytes.size());
+  CBP_TRY(hipMemcpyAsync(dst, s.host, bytes.size(), hipMemcpyHostToDevice, st));
   CBP_TRY(hipEventRecord(s.done, st));
   s.recorded = true;
   return hipSuccess;
+}
+
+hipError_t upload_head(dev_state& ds, const batch_build& bb, hipStream_t st) {
+  return upload_bytes(ds, bb.head_dev, bb.head, st);
 }
 
 hipError_t enqueue_batch(dev_state& ds, const batch_build& bb, hipStream_t st) {
@@ -797,66 +765,95 @@ size_t cbp_workspace_size(int32_t maxH, int32_t maxW, int32_t maxk, int32_t chan
 cbp_status cbp_eval_unit_circle(const cbp_image* b, int32_t S, double* ex, double* ey, const cbp_options* opts) {
   if (!valid_image(b) || !ex || !ey || !opts) return CBP_E_INVALID;
   if (S < 1 || S > CBP_MAX_S) return CBP_E_INVALID;
-  const size_t need = ((size_t)(b->height + 31) / 32 + 1) * (size_t)S * b->width * sizeof(double);
+  // one frame through the evaluation kernels: a one-slot (ncf = 1) descriptor
+  // whose EX / EY are the caller's buffers; its fold partials follow the head
+  frame_desc d;
+  std::memset(&d, 0, sizeof d);
+  d.b1 = d.b2 = b->data;
+  d.p1 = d.p2 = b->pitch;
+  d.H1 = d.H2 = d.Hmax = b->height;
+  d.W1 = d.W2 = d.Wmax = b->width;
+  d.nch = 1;
+  d.ncf = 1;
+  d.S = S;
+  d.rpg = S * ((32 + S - 1) / S);
+  d.RG = (b->height + d.rpg - 1) / d.rpg;
+  const size_t head = head_bytes(1);
+  const size_t need = head + ((size_t)(b->height + 31) / 32 + 1) * (size_t)S * b->width * sizeof(double);
   if (!opts->workspace || opts->workspace_bytes < need) return CBP_E_NOMEM;
-  const hipError_t e = launch_eval_single(b->data, b->dtype, b->pitch, b->height, b->width, S,
-                                          (char*)opts->workspace, ex, ey, (hipStream_t)opts->stream);
-  return e == hipSuccess ? CBP_OK : CBP_E_DEVICE;
+  char* ws = (char*)opts->workspace;
+  d.fpart = (double*)(ws + head);
+  d.ex = (c64*)ex;
+  d.ey = (c64*)ey;
+  int items[Q_COUNT] = {};
+  items[Q_FOLD] = ((d.Wmax + 63) / 64) * d.RG;
+  items[Q_EVAL_COLS] = (d.Wmax + 15) / 16;
+  items[Q_EVAL_ROWS] = (d.Hmax + 3) / 4;
+  std::vector<char> hb(head, 0);
+  std::memcpy(hb.data(), &d, sizeof d);
+  int* starts = (int*)(hb.data() + head_desc_bytes(1));
+  for (int q = 0; q < Q_COUNT; ++q) { starts[q * 2] = 0; starts[q * 2 + 1] = items[q]; }
+  dev_state* ds = get_dev();
+  if (!ds) return CBP_E_DEVICE;
+  hipStream_t st = (hipStream_t)opts->stream;
+  const batch_ref br = {(const frame_desc*)ws, (const int*)(ws + head_desc_bytes(1)), 1};
+  std::lock_guard<std::mutex> lk(ds->launch_mu);
+  (void)hipGetLastError();
+  auto run = [&]() -> hipError_t {
+    CBP_TRY(upload_bytes(*ds, ws, hb, st));
+    if (b->dtype == CBP_F32) CBP_TRY(launch_fold<float>(br, grid_for(items[Q_FOLD], 0), st));
+    else CBP_TRY(launch_fold<double>(br, grid_for(items[Q_FOLD], 0), st));
+    CBP_TRY(launch_eval_cols(br, grid_for(items[Q_EVAL_COLS], 0), st));
+    if (b->dtype == CBP_F32) CBP_TRY(launch_eval_rows<float>(br, grid_for(items[Q_EVAL_ROWS], 0), st));
+    else CBP_TRY(launch_eval_rows<double>(br, grid_for(items[Q_EVAL_ROWS], 0), st));
+    return hipSuccess;
+  };
+  return run() == hipSuccess ? CBP_OK : CBP_E_DEVICE;
 }
 
 cbp_status cbp_recover_kernels(const cbp_image* b1, const cbp_image* b2, int32_t m, int32_t n, double* K1,
                                double* K2, const cbp_options* opts) {
   if (!K1 || !K2 || !opts || !b1 || !b2) return CBP_E_INVALID;
-  if (opts->flags & (CBP_FLAG_GRAPH | CBP_FLAG_AUTOTUNE)) {
-    const std::vector<frame_req> reqs = {frame_req{b1, b2, nullptr, m, n, K1, K2, opts->diag}};
-    return batch_call(reqs, nullptr, opts);
-  }
-  return frame_call(b1, b2, nullptr, m, n, K1, K2, opts, (char*)opts->workspace, opts->workspace_bytes,
-                    opts->diag);
+  const std::vector<frame_req> reqs = {frame_req{b1, b2, nullptr, m, n, K1, K2, opts->diag}};
+  return batch_call(reqs, nullptr, opts);
 }
 
 cbp_status cbp_deblur(const cbp_image* b1, const cbp_image* b2, cbp_image* latent, double* K1, double* K2,
                       const cbp_options* opts) {
   if (!opts || !latent || !b1 || !b2) return CBP_E_INVALID;
-  if (opts->flags & (CBP_FLAG_GRAPH | CBP_FLAG_AUTOTUNE)) {
-    const std::vector<frame_req> reqs = {
-        frame_req{b1, b2, latent, latent->height, latent->width, K1, K2, opts->diag}};
-    return batch_call(reqs, nullptr, opts);
-  }
-  return frame_call(b1, b2, latent, latent->height, latent->width, K1, K2, opts, (char*)opts->workspace,
-                    opts->workspace_bytes, opts->diag);
+  const std::vector<frame_req> reqs = {frame_req{b1, b2, latent, latent->height, latent->width, K1, K2, opts->diag}};
+  return batch_call(reqs, nullptr, opts);
 }
 
 cbp_status cbp_sample_grams(const cbp_image* b1, const cbp_image* b2, int32_t m, int32_t n, double* grams,
                             const cbp_options* opts) {
   if (!grams || !opts || !b1 || !b2) return CBP_E_INVALID;
-  frame_plan fp;
-  const cbp_status s = make_plan(b1, b2, m, n, opts, kDefaultTuning, &fp);
+  const std::vector<frame_req> reqs = {frame_req{b1, b2, nullptr, m, n, nullptr, nullptr, nullptr}};
+  std::vector<cbp_status> status;
+  batch_build bb;
+  const cbp_status s = build_batch(reqs, opts, kDefaultTuning, status, &bb);
   if (s != CBP_OK) return s;
-  const size_t head = head_bytes(1);
-  char* ws = (char*)opts->workspace;
-  if (!ws || opts->workspace_bytes < head + fp.total) return CBP_E_NOMEM;
+  if (status[0] != CBP_OK) return status[0];
   dev_state* ds = get_dev();
   if (!ds) return CBP_E_DEVICE;
-  const frame_desc d = make_desc(fp, b1, b2, ws + head, nullptr, nullptr, nullptr, opts->lambda, nullptr, false);
-  auto br = [&](int q) { return batch_ref{nullptr, nullptr, queue_items(q, fp)}; };
-  auto grid = [&](int q) { return grid_for(queue_items(q, fp), 0); };
+  const chunk_view& cv = bb.chunks[0];
+  const batch_ref br = {cv.descs, cv.starts, cv.nf};
   hipStream_t st = (hipStream_t)opts->stream;
-  const int gfmt = gram_format(opts->precision);
   std::lock_guard<std::mutex> lk(ds->launch_mu);
   (void)hipGetLastError();
   auto run = [&]() -> hipError_t {
+    CBP_TRY(upload_head(*ds, bb, st));
     if (b1->dtype == CBP_F32) {
-      CBP_TRY(launch_fold<float>(d, br(Q_FOLD), grid(Q_FOLD), st));
-      CBP_TRY(launch_eval_rows<float>(d, br(Q_EVAL_ROWS), grid(Q_EVAL_ROWS), st));
+      CBP_TRY(launch_fold<float>(br, cv.grid[Q_FOLD], st));
+      CBP_TRY(launch_eval_rows<float>(br, cv.grid[Q_EVAL_ROWS], st));
     } else {
-      CBP_TRY(launch_fold<double>(d, br(Q_FOLD), grid(Q_FOLD), st));
-      CBP_TRY(launch_eval_rows<double>(d, br(Q_EVAL_ROWS), grid(Q_EVAL_ROWS), st));
+      CBP_TRY(launch_fold<double>(br, cv.grid[Q_FOLD], st));
+      CBP_TRY(launch_eval_rows<double>(br, cv.grid[Q_EVAL_ROWS], st));
     }
-    CBP_TRY(launch_eval_cols(d, br(Q_EVAL_COLS), grid(Q_EVAL_COLS), st));
-    if (gfmt < 0) CBP_TRY(launch_gram(d, br(Q_GRAM), grid(Q_GRAM), st));
-    else CBP_TRY(launch_gram_mfma(d, br(Q_GRAMM), grid(Q_GRAMM), gfmt, std::max(fp.Hmax, fp.Wmax), st));
-    CBP_TRY(launch_gram_expand(d, br(Q_GRAMM), grid(Q_GRAMM), grams, st));
+    CBP_TRY(launch_eval_cols(br, cv.grid[Q_EVAL_COLS], st));
+    if (cv.gram_fmt < 0) CBP_TRY(launch_gram(br, cv.grid[Q_GRAM], st));
+    else CBP_TRY(launch_gram_mfma(br, cv.grid[Q_GRAMM], cv.gram_fmt, cv.maxStride, st));
+    CBP_TRY(launch_gram_expand(br, cv.grid[Q_GRAMM], grams, st));
     return hipSuccess;
   };
   return run() == hipSuccess ? CBP_OK : CBP_E_DEVICE;

@@ -40,8 +40,8 @@ __device__ inline void unit_twiddles(c64* tw, int S) {
 // thread per column, S independent accumulators, 64 columns per item.
 // Items: (column block, row group, cf).
 template <typename T>
-__global__ __launch_bounds__(64) void k_fold_cols(frame_desc one, batch_ref br) {
-  for_items<Q_FOLD>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+__global__ __launch_bounds__(64) void k_fold_cols(batch_ref br) {
+  for_items<Q_FOLD>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const int nx = (d.Wmax + 63) / 64;
     const int bx = item % nx, rest = item / nx;
     const int g = rest % d.RG, cf = rest / d.RG;
@@ -73,10 +73,10 @@ __global__ __launch_bounds__(64) void k_fold_cols(frame_desc one, batch_ref br) 
 // Sum the row-group partials of the column fold and apply the S-point DFT;
 // 16 columns per item, 16 residues / frequencies in flight per column.
 // Items: (column block, cf).
-__global__ __launch_bounds__(256) void k_eval_cols(frame_desc one, batch_ref br) {
+__global__ __launch_bounds__(256) void k_eval_cols(batch_ref br) {
   __shared__ double F[CBP_MAX_S][16];
   __shared__ c64 tw[CBP_MAX_S];
-  for_items<Q_EVAL_COLS>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+  for_items<Q_EVAL_COLS>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const int nx = (d.Wmax + 15) / 16;
     const int bx = item % nx, cf = item / nx;
     const int S = d.S, Wmax = d.Wmax, RG = d.RG;
@@ -119,10 +119,10 @@ __global__ __launch_bounds__(256) void k_eval_cols(frame_desc one, batch_ref br)
 // x in [q S, q S + S), q = l, l + 64, ...; wave reductions sum the lanes.
 // Items: (block of 4 rows, cf).
 template <typename T>
-__global__ __launch_bounds__(256) void k_eval_rows(frame_desc one, batch_ref br) {
+__global__ __launch_bounds__(256) void k_eval_rows(batch_ref br) {
   __shared__ double g[4][CBP_MAX_S];
   __shared__ c64 tw[CBP_MAX_S];
-  for_items<Q_EVAL_ROWS>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+  for_items<Q_EVAL_ROWS>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const int ny = (d.Hmax + 3) / 4;
     const int by = item % ny, cf = item / ny;
     const int S = d.S;
@@ -170,63 +170,31 @@ __global__ __launch_bounds__(256) void k_eval_rows(frame_desc one, batch_ref br)
 }  // namespace
 
 template <typename T>
-hipError_t launch_fold(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st) {
+hipError_t launch_fold(const batch_ref& br, int grid, hipStream_t st) {
   prof_begin(PH_FOLD, st);
-  hipLaunchKernelGGL(k_fold_cols<T>, dim3(grid), dim3(64), 0, st, one, br);
+  hipLaunchKernelGGL(k_fold_cols<T>, dim3(grid), dim3(64), 0, st, br);
   prof_end(PH_FOLD, st);
   return hipGetLastError();
 }
 
-hipError_t launch_eval_cols(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st) {
+hipError_t launch_eval_cols(const batch_ref& br, int grid, hipStream_t st) {
   prof_begin(PH_EVAL_COLS, st);
-  hipLaunchKernelGGL(k_eval_cols, dim3(grid), dim3(256), 0, st, one, br);
+  hipLaunchKernelGGL(k_eval_cols, dim3(grid), dim3(256), 0, st, br);
   prof_end(PH_EVAL_COLS, st);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_eval_rows(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st) {
+hipError_t launch_eval_rows(const batch_ref& br, int grid, hipStream_t st) {
   prof_begin(PH_EVAL_ROWS, st);
-  hipLaunchKernelGGL(k_eval_rows<T>, dim3(grid), dim3(256), 0, st, one, br);
+  hipLaunchKernelGGL(k_eval_rows<T>, dim3(grid), dim3(256), 0, st, br);
   prof_end(PH_EVAL_ROWS, st);
   return hipGetLastError();
 }
 
-template hipError_t launch_fold<float>(const frame_desc&, const batch_ref&, int, hipStream_t);
-template hipError_t launch_fold<double>(const frame_desc&, const batch_ref&, int, hipStream_t);
-template hipError_t launch_eval_rows<float>(const frame_desc&, const batch_ref&, int, hipStream_t);
-template hipError_t launch_eval_rows<double>(const frame_desc&, const batch_ref&, int, hipStream_t);
-
-// One frame, channel 0, written straight to the caller's EX (S x W) and EY
-// (S x H): a one-slot (ncf = 1) frame descriptor over the same kernels.
-hipError_t launch_eval_single(const void* b, int dtype, int64_t pitch, int H, int W, int S, char* ws, double* ex,
-                              double* ey, hipStream_t st) {
-  frame_desc d = {};
-  d.b1 = b;
-  d.b2 = b;
-  d.p1 = d.p2 = pitch;
-  d.H1 = d.H2 = d.Hmax = H;
-  d.W1 = d.W2 = d.Wmax = W;
-  d.nch = 1;
-  d.ncf = 1;
-  d.S = S;
-  d.rpg = S * ((32 + S - 1) / S);
-  d.RG = (H + d.rpg - 1) / d.rpg;
-  d.fpart = (double*)ws;
-  d.ex = (c64*)ex;
-  d.ey = (c64*)ey;
-  const batch_ref none = {nullptr, nullptr, 0};
-  const int gf = ((W + 63) / 64) * d.RG, gc = (W + 15) / 16, gr = (H + 3) / 4;
-  if (dtype == CBP_F32) {
-    hipLaunchKernelGGL(k_fold_cols<float>, dim3(gf), dim3(64), 0, st, d, none);
-    hipLaunchKernelGGL(k_eval_cols, dim3(gc), dim3(256), 0, st, d, none);
-    hipLaunchKernelGGL(k_eval_rows<float>, dim3(gr), dim3(256), 0, st, d, none);
-  } else {
-    hipLaunchKernelGGL(k_fold_cols<double>, dim3(gf), dim3(64), 0, st, d, none);
-    hipLaunchKernelGGL(k_eval_cols, dim3(gc), dim3(256), 0, st, d, none);
-    hipLaunchKernelGGL(k_eval_rows<double>, dim3(gr), dim3(256), 0, st, d, none);
-  }
-  return hipGetLastError();
-}
+template hipError_t launch_fold<float>(const batch_ref&, int, hipStream_t);
+template hipError_t launch_fold<double>(const batch_ref&, int, hipStream_t);
+template hipError_t launch_eval_rows<float>(const batch_ref&, int, hipStream_t);
+template hipError_t launch_eval_rows<double>(const batch_ref&, int, hipStream_t);
 
 }  // namespace cbp

@@ -59,11 +59,11 @@ __device__ __attribute__((always_inline)) inline cplx<T>* fft_lds(cplx<T>* a, cp
 // same order, hence the same bits) is taken from the row in LDS; waves 0-3
 // fold (frame, residue parity) = (w & 1, w >> 1).
 template <typename T>
-__global__ __launch_bounds__(256) void k_row_fwd(frame_desc one, batch_ref br, int with_ey) {
+__global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
   extern __shared__ __attribute__((aligned(16))) char sm_rf[];
   __shared__ double gy[2][CBP_MAX_S];
   __shared__ c64 twS[CBP_MAX_S];
-  for_items<Q_ROW_FWD>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+  for_items<Q_ROW_FWD>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const fft_plan& px = d.fx;
     const int N = px.N, hx = d.hx;
     cplx<T>* a = (cplx<T>*)sm_rf;
@@ -138,9 +138,9 @@ __global__ __launch_bounds__(256) void k_row_fwd(frame_desc one, batch_ref br, i
 // ---------------------------------------------------------------- pass 2
 // Items: (strip of cw columns, channel).
 template <typename T>
-__global__ __launch_bounds__(256) void k_col_filter(frame_desc one, batch_ref br) {
+__global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_cf[];
-  for_items<Q_COL>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+  for_items<Q_COL>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const fft_plan& py = d.fy;
     const int N = py.N, cw = d.cw, hx = d.hx, m = d.m;
     const int k1 = d.k1, k2 = d.k2, Px = d.Px, H1 = d.H1, H2 = d.H2;
@@ -233,9 +233,9 @@ __global__ __launch_bounds__(256) void k_col_filter(frame_desc one, batch_ref br
 // ---------------------------------------------------------------- pass 3
 // Items: (pair of output rows, channel).
 template <typename T>
-__global__ __launch_bounds__(256) void k_row_inv(frame_desc one, batch_ref br) {
+__global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_ri[];
-  for_items<Q_ROW_INV>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+  for_items<Q_ROW_INV>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const fft_plan& px = d.fx;
     const int N = px.N, hx = d.hx, m = d.m, n = d.n;
     const T scale = (T)(1.0 / ((double)d.Py * (double)d.Px));
@@ -287,37 +287,36 @@ void set_fft_attrs() {
 }
 
 template <typename T>
-hipError_t launch_row_fwd(const frame_desc& one, const batch_ref& br, int grid, int maxPx, int with_ey,
+hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey,
                           hipStream_t st) {
   prof_begin(PH_ROW_FWD, st);
-  hipLaunchKernelGGL(k_row_fwd<T>, dim3(grid), dim3(256), row_lds_bytes(maxPx, (int)sizeof(T)), st, one, br,
+  hipLaunchKernelGGL(k_row_fwd<T>, dim3(grid), dim3(256), row_lds_bytes(maxPx, (int)sizeof(T)), st, br,
                      with_ey);
   prof_end(PH_ROW_FWD, st);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_col(const frame_desc& one, const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st) {
+hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st) {
   prof_begin(PH_COL_FILTER, st);
-  hipLaunchKernelGGL(k_col_filter<T>, dim3(grid), dim3(256), col_lds_bytes(maxPy, maxcw, (int)sizeof(T)), st, one,
-                     br);
+  hipLaunchKernelGGL(k_col_filter<T>, dim3(grid), dim3(256), col_lds_bytes(maxPy, maxcw, (int)sizeof(T)), st, br);
   prof_end(PH_COL_FILTER, st);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_row_inv(const frame_desc& one, const batch_ref& br, int grid, int maxPx, hipStream_t st) {
+hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t st) {
   prof_begin(PH_ROW_INV, st);
-  hipLaunchKernelGGL(k_row_inv<T>, dim3(grid), dim3(256), row_lds_bytes(maxPx, (int)sizeof(T)), st, one, br);
+  hipLaunchKernelGGL(k_row_inv<T>, dim3(grid), dim3(256), row_lds_bytes(maxPx, (int)sizeof(T)), st, br);
   prof_end(PH_ROW_INV, st);
   return hipGetLastError();
 }
 
-template hipError_t launch_row_fwd<float>(const frame_desc&, const batch_ref&, int, int, int, hipStream_t);
-template hipError_t launch_row_fwd<double>(const frame_desc&, const batch_ref&, int, int, int, hipStream_t);
-template hipError_t launch_col<float>(const frame_desc&, const batch_ref&, int, int, int, hipStream_t);
-template hipError_t launch_col<double>(const frame_desc&, const batch_ref&, int, int, int, hipStream_t);
-template hipError_t launch_row_inv<float>(const frame_desc&, const batch_ref&, int, int, hipStream_t);
-template hipError_t launch_row_inv<double>(const frame_desc&, const batch_ref&, int, int, hipStream_t);
+template hipError_t launch_row_fwd<float>(const batch_ref&, int, int, int, hipStream_t);
+template hipError_t launch_row_fwd<double>(const batch_ref&, int, int, int, hipStream_t);
+template hipError_t launch_col<float>(const batch_ref&, int, int, int, hipStream_t);
+template hipError_t launch_col<double>(const batch_ref&, int, int, int, hipStream_t);
+template hipError_t launch_row_inv<float>(const batch_ref&, int, int, hipStream_t);
+template hipError_t launch_row_inv<double>(const batch_ref&, int, int, hipStream_t);
 
 }  // namespace cbp

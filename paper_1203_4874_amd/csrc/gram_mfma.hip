@@ -54,9 +54,9 @@ __device__ inline mcol column_of(int c, int k2, int N) {
 
 // Items: (sample, pass).  FMT 0: FP32 operands; 1: bfloat16 operands.
 template <int FMT>
-__global__ __launch_bounds__(256) void k_gram_mfma(frame_desc one, batch_ref br) {
+__global__ __launch_bounds__(256) void k_gram_mfma(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_gm[];
-  for_items<Q_GRAMM>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+  for_items<Q_GRAMM>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const int S = d.S, k1 = d.k1, k2 = d.k2, N = k1 + k2, NL = 2 * N - 1;
     const int j = item % S, pass = item / S;
     const int len1 = pass ? d.H1 : d.W1, len2 = pass ? d.H2 : d.W2;
@@ -176,13 +176,13 @@ void set_gram_mfma_attrs() {
   hipFuncSetAttribute((const void*)k_gram_mfma<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-hipError_t launch_gram_mfma(const frame_desc& one, const batch_ref& br, int grid, int fmt, int maxStride,
+hipError_t launch_gram_mfma(const batch_ref& br, int grid, int fmt, int maxStride,
                             hipStream_t st) {
   prof_begin(PH_GRAM, st);
   if (fmt == 0)
-    hipLaunchKernelGGL(k_gram_mfma<0>, dim3(grid), dim3(256), gram_mfma_lds_bytes(maxStride, 0), st, one, br);
+    hipLaunchKernelGGL(k_gram_mfma<0>, dim3(grid), dim3(256), gram_mfma_lds_bytes(maxStride, 0), st, br);
   else
-    hipLaunchKernelGGL(k_gram_mfma<1>, dim3(grid), dim3(256), gram_mfma_lds_bytes(maxStride, 1), st, one, br);
+    hipLaunchKernelGGL(k_gram_mfma<1>, dim3(grid), dim3(256), gram_mfma_lds_bytes(maxStride, 1), st, br);
   prof_end(PH_GRAM, st);
   return hipGetLastError();
 }

@@ -2,11 +2,10 @@
 // translation units.  Not part of the public ABI.
 //
 // Every kernel works on "work items" of one queue (a phase of the path).  A
-// launch covers either one frame, whose descriptor is a kernel argument and
-// whose items are the workgroups of the grid, or a batch of frames, whose
-// descriptors and per-queue item prefix sums sit in device memory; there the
-// grid may be smaller than the item count and each workgroup loops over
-// items (a persistent launch), finding each item's frame by binary search.
+// launch covers the frames of a call (one or many): their descriptors and
+// per-queue item prefix sums sit in device memory (the workspace head); the
+// grid may be smaller than the item count, each workgroup then looping over
+// items (a persistent launch), and finds each item's frame by binary search.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -100,9 +99,7 @@ inline int queue_items(int q, const frame_plan& p) {
   return 0;
 }
 
-// A batch as the kernels see it.  descs == nullptr means a one-frame launch
-// whose descriptor is the kernel argument; nframes then holds the item count
-// of the launched queue.
+// The frames of a launch as the kernels see them (device memory).
 struct batch_ref {
   const frame_desc* descs;  // nframes descriptors
   const int* starts;        // [Q_COUNT][nframes + 1] item prefix sums
@@ -132,21 +129,13 @@ __device__ inline void xcd_items(int T, int& first, int& end, int& step) {
 // Run body(frame, item) for every item of queue Q owned by this workgroup.
 // The body may use __syncthreads(); a barrier separates consecutive items.
 template <int Q, typename F>
-__device__ inline void for_items(const frame_desc& one, const batch_ref& br, F&& body) {
-  int first, end, step;
-  if (br.descs == nullptr) {
-    xcd_items(br.nframes, first, end, step);  // one frame: nframes holds its item count
-    for (int it = first; it < end; it += step) {
-      body(one, it);
-      __syncthreads();
-    }
-    return;
-  }
+__device__ inline void for_items(const batch_ref& br, F&& body) {
   __shared__ int st[BATCH_CHUNK + 1];
   const int nf = br.nframes;
   const int* s = br.starts + (size_t)Q * (nf + 1);
   for (int t = threadIdx.x; t <= nf; t += blockDim.x) st[t] = s[t];
   __syncthreads();
+  int first, end, step;
   xcd_items(st[nf], first, end, step);
   for (int it = first; it < end; it += step) {
     int lo = 0, hi = nf;  // st[lo] <= it < st[hi]
@@ -178,20 +167,18 @@ void prof_end(int phase, hipStream_t st);
 // item; a multiple of 8 enables the XCD-aware item ranges).
 // eval.hip
 template <typename T>
-hipError_t launch_fold(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st);
-hipError_t launch_eval_cols(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st);
+hipError_t launch_fold(const batch_ref& br, int grid, hipStream_t st);
+hipError_t launch_eval_cols(const batch_ref& br, int grid, hipStream_t st);
 template <typename T>
-hipError_t launch_eval_rows(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st);
-hipError_t launch_eval_single(const void* b, int dtype, int64_t pitch, int H, int W, int S,
-                              char* ws, double* ex, double* ey, hipStream_t st);
+hipError_t launch_eval_rows(const batch_ref& br, int grid, hipStream_t st);
 
 // recover.hip
-hipError_t launch_diag_init(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st);
-hipError_t launch_gram(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st);
+hipError_t launch_diag_init(const batch_ref& br, int grid, hipStream_t st);
+hipError_t launch_gram(const batch_ref& br, int grid, hipStream_t st);
 // dense Gram matrices (2 S N N complex FP64, [pass][sample][p][q]); items of Q_GRAMM
-hipError_t launch_gram_expand(const frame_desc& one, const batch_ref& br, int grid, double* out, hipStream_t st);
-hipError_t launch_sample(const frame_desc& one, const batch_ref& br, int grid, int maxN, hipStream_t st);
-hipError_t launch_finalize(const frame_desc& one, const batch_ref& br, int grid, int maxS, int learned,
+hipError_t launch_gram_expand(const batch_ref& br, int grid, double* out, hipStream_t st);
+hipError_t launch_sample(const batch_ref& br, int grid, int maxN, hipStream_t st);
+hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned,
                            hipStream_t st);
 size_t finalize_lds_bytes(int S, int learned);
 size_t sample_lds_bytes(int N);
@@ -199,7 +186,7 @@ size_t sample_lds_bytes(int N);
 // gram_mfma.hip: the per-sample Gram on the matrix cores (fmt 0: FP32
 // operands, 1: bfloat16), N = k1 + k2 <= 32; maxStride = the largest Wmax /
 // Hmax of the launched frames.
-hipError_t launch_gram_mfma(const frame_desc& one, const batch_ref& br, int grid, int fmt, int maxStride,
+hipError_t launch_gram_mfma(const batch_ref& br, int grid, int fmt, int maxStride,
                             hipStream_t st);
 size_t gram_mfma_lds_bytes(int maxStride, int fmt);
 void set_gram_mfma_attrs();
@@ -207,12 +194,12 @@ void set_gram_mfma_attrs();
 // fft.hip.  with_ey: the row pass also writes the row evaluation EY (the
 // k_eval_rows result, bit for bit) from the rows it already holds.
 template <typename T>
-hipError_t launch_row_fwd(const frame_desc& one, const batch_ref& br, int grid, int maxPx, int with_ey,
+hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey,
                           hipStream_t st);
 template <typename T>
-hipError_t launch_col(const frame_desc& one, const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st);
+hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st);
 template <typename T>
-hipError_t launch_row_inv(const frame_desc& one, const batch_ref& br, int grid, int maxPx, hipStream_t st);
+hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t st);
 size_t row_lds_bytes(int N, int esize);
 size_t col_lds_bytes(int N, int cw, int esize);
 void set_recover_attrs();
@@ -220,7 +207,7 @@ void set_fft_attrs();
 
 // mlp.hip: the learned form's network on every frame of the launch
 // (features -> weights and tau); blob is a device mlp_blob.
-hipError_t launch_mlp_frames(const frame_desc& one, const batch_ref& br, int grid, const void* blob,
+hipError_t launch_mlp_frames(const batch_ref& br, int grid, const void* blob,
                              hipStream_t st);
 
 }  // namespace cbp

@@ -161,11 +161,11 @@ __global__ __launch_bounds__(256) void k_mlp_forward(fwd_args a) {
 //   wts[j] = w of pass-X sample j, wts[S + i] = w of pass-Y sample i,
 //   wts[2S] = tau = median of the 2S values tau_j (mean of the middle two).
 // Items: one per frame.
-__global__ __launch_bounds__(256) void k_mlp_frames(frame_desc one, batch_ref br, const mlp_blob* blob) {
+__global__ __launch_bounds__(256) void k_mlp_frames(batch_ref br, const mlp_blob* blob) {
   __shared__ __attribute__((aligned(16))) fwd_lds L;
   __shared__ double tj[64];
   __shared__ double mid[2];
-  for_items<Q_FINALIZE>(one, br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
+  for_items<Q_FINALIZE>(br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
     const int n = 2 * d.S;
     mlp_block(L, d.feat, n, blob->W1, blob->W2, blob->W3, blob->b1, blob->b2, blob->b3, nullptr, nullptr);
     const int t = threadIdx.x;
@@ -426,9 +426,9 @@ size_t carve_bytes(int rows) {
 
 size_t mlp_state_bytes(int rows) { return carve_bytes(rows); }
 
-hipError_t launch_mlp_frames(const frame_desc& one, const batch_ref& br, int grid, const void* blob,
+hipError_t launch_mlp_frames(const batch_ref& br, int grid, const void* blob,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_frames, dim3(grid), dim3(256), 0, st, one, br, (const mlp_blob*)blob);
+  hipLaunchKernelGGL(k_mlp_frames, dim3(grid), dim3(256), 0, st, br, (const mlp_blob*)blob);
   return hipGetLastError();
 }
 

@@ -82,8 +82,8 @@ __device__ inline bool finite_c(c64 v) { return isfinite(v.re) && isfinite(v.im)
 // Correlations rho for every (pass, sample, lag), summed over channels.
 // Items: (lag, sample, pass), one wave each; Dot2 accumulation per lane,
 // then a fixed-order double-double wave reduction.
-__global__ __launch_bounds__(64) void k_gram(frame_desc one, batch_ref br) {
-  for_items<Q_GRAM>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+__global__ __launch_bounds__(64) void k_gram(batch_ref br) {
+  for_items<Q_GRAM>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const int k1 = d.k1, k2 = d.k2, S = d.S;
     const int N = k1 + k2, NL = 2 * N - 1;
     const int li = item % NL, rest = item / NL;
@@ -125,9 +125,9 @@ __global__ __launch_bounds__(64) void k_gram(frame_desc one, batch_ref br) {
 
 // Smallest eigenvector of every per-sample Gram.  Items: (sample, pass),
 // one wave each.
-__global__ __launch_bounds__(SMALL_NT) void k_sample(frame_desc one, batch_ref br) {
+__global__ __launch_bounds__(SMALL_NT) void k_sample(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_sample[];
-  for_items<Q_SAMPLE>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+  for_items<Q_SAMPLE>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const int k1 = d.k1, k2 = d.k2, S = d.S;
     const int N = k1 + k2, NL = 2 * N - 1;
     const int j = item % S, pass = item / S;
@@ -494,9 +494,9 @@ __device__ inline void learned_assembly(const c64* tw, int S, int k, const doubl
 }
 
 // Items: one per frame.
-__global__ __launch_bounds__(SMALL_NT) void k_finalize(frame_desc one, batch_ref br) {
+__global__ __launch_bounds__(SMALL_NT) void k_finalize(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_fin[];
-  for_items<Q_FINALIZE>(one, br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
+  for_items<Q_FINALIZE>(br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
     finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, d.cbuf, d.K1, d.K2, d.diag, sm_fin, d.wts);
   });
 }
@@ -504,8 +504,8 @@ __global__ __launch_bounds__(SMALL_NT) void k_finalize(frame_desc one, batch_ref
 // Dense per-sample Gram matrices from the correlations (the a2 output of
 // cbp_sample_grams): out[pass][j][p][q] = G(p, q) rounded to FP64.
 // Items: (sample, pass).
-__global__ __launch_bounds__(64) void k_gram_expand(frame_desc one, batch_ref br, c64* out) {
-  for_items<Q_GRAMM>(one, br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+__global__ __launch_bounds__(64) void k_gram_expand(batch_ref br, c64* out) {
+  for_items<Q_GRAMM>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const int S = d.S, N = d.N, NL = 2 * N - 1;
     const gram_acc G{d.corr + (size_t)item * NL, d.k1, d.k2};
     c64* o = out + (size_t)item * N * N;
@@ -518,8 +518,8 @@ __global__ __launch_bounds__(64) void k_gram_expand(frame_desc one, batch_ref br
 }
 
 // Clear the per-call diagnostic counters.  Items: one per frame.
-__global__ void k_diag_init(frame_desc one, batch_ref br) {
-  for_items<Q_DIAG>(one, br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
+__global__ void k_diag_init(batch_ref br) {
+  for_items<Q_DIAG>(br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
     if (threadIdx.x == 0 && d.diag) {
       d.diag->flags = 0;
       d.diag->refine_sample = 0;
@@ -545,34 +545,34 @@ void set_recover_attrs() {
   hipFuncSetAttribute((const void*)k_finalize, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-hipError_t launch_diag_init(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_init, dim3(grid), dim3(64), 0, st, one, br);
+hipError_t launch_diag_init(const batch_ref& br, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_init, dim3(grid), dim3(64), 0, st, br);
   return hipGetLastError();
 }
 
-hipError_t launch_gram_expand(const frame_desc& one, const batch_ref& br, int grid, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_expand, dim3(grid), dim3(64), 0, st, one, br, (c64*)out);
+hipError_t launch_gram_expand(const batch_ref& br, int grid, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_expand, dim3(grid), dim3(64), 0, st, br, (c64*)out);
   return hipGetLastError();
 }
 
-hipError_t launch_gram(const frame_desc& one, const batch_ref& br, int grid, hipStream_t st) {
+hipError_t launch_gram(const batch_ref& br, int grid, hipStream_t st) {
   prof_begin(PH_GRAM, st);
-  hipLaunchKernelGGL(k_gram, dim3(grid), dim3(64), 0, st, one, br);
+  hipLaunchKernelGGL(k_gram, dim3(grid), dim3(64), 0, st, br);
   prof_end(PH_GRAM, st);
   return hipGetLastError();
 }
 
-hipError_t launch_sample(const frame_desc& one, const batch_ref& br, int grid, int maxN, hipStream_t st) {
+hipError_t launch_sample(const batch_ref& br, int grid, int maxN, hipStream_t st) {
   prof_begin(PH_SAMPLE, st);
-  hipLaunchKernelGGL(k_sample, dim3(grid), dim3(SMALL_NT), sample_lds_bytes(maxN), st, one, br);
+  hipLaunchKernelGGL(k_sample, dim3(grid), dim3(SMALL_NT), sample_lds_bytes(maxN), st, br);
   prof_end(PH_SAMPLE, st);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const frame_desc& one, const batch_ref& br, int grid, int maxS, int learned,
+hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned,
                            hipStream_t st) {
   prof_begin(PH_FINALIZE, st);
-  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(SMALL_NT), finalize_lds_bytes(maxS, learned), st, one, br);
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(SMALL_NT), finalize_lds_bytes(maxS, learned), st, br);
   prof_end(PH_FINALIZE, st);
   return hipGetLastError();
 }
