@@ -127,6 +127,7 @@ typedef struct cbp_options {
 #define CBP_DIAG_SAMPLE_WEAK    2  /* some per-sample Gram had no clear null direction */
 #define CBP_DIAG_SCALE_WEAK     4  /* the scale system had no clear null direction */
 #define CBP_DIAG_KERNEL_ZERO    8  /* a kernel estimate summed to ~0 before normalisation */
+#define CBP_DIAG_FALLBACK      16  /* learned form: the plain kernels were kept (smaller judge objective) */
 
 /* Per-frame numerical diagnostics, written in device memory when
  * options->diag is not NULL.  Complex values are (re, im) pairs. */
@@ -147,6 +148,7 @@ typedef struct cbp_diag {
   double  khat[2][CBP_MAX_S][CBP_MAX_S][2];        /* averaged kernel spectra [kernel][i (x freq)][j (y freq)] */
   float   sample_features[2][CBP_MAX_S][32];         /* the learned form's spectrum features of each sample */
   double  sample_weights[2 * CBP_MAX_S + 1];          /* learned form: wX_0.., wY_0.., tau (unused otherwise) */
+  double  judge[2];                                  /* learned form: J of the plain and of the learned kernels */
 } cbp_diag;
 
 /* Human-readable name of a status code (static string, never NULL). */

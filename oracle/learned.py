@@ -204,11 +204,40 @@ def recover_kernels_learned(B1, B2, m: int, n: int, params, S: int = 0, full: bo
     wY, tY = weights_from_outputs(oY)
     tau = float(np.median(np.concatenate([tX, tY])))
     a, b, _ = scale_fix_weighted(f["P"], f["Q"], wX, wY)
-    K1, _ = assemble_weighted(f["P"][0], f["Q"][0], a, b, k1, wX, wY, tau)
-    K2, _ = assemble_weighted(f["P"][1], f["Q"][1], a, b, k2, wX, wY, tau)
+    L1, _ = assemble_weighted(f["P"][0], f["Q"][0], a, b, k1, wX, wY, tau)
+    L2, _ = assemble_weighted(f["P"][1], f["Q"][1], a, b, k2, wX, wY, tau)
+    # the plain method judges: keep its kernels when their objective is smaller
+    Jp = judge_objective(K1p, K2p, f["EX"], f["EY"], S)
+    Jl = judge_objective(L1, L2, f["EX"], f["EY"], S)
+    K1, K2 = (K1p, K2p) if Jp < Jl else (L1, L2)
     if not full:
         return K1, K2
-    return K1, K2, dict(plain=(K1p, K2p), wX=wX, wY=wY, tau=tau, features=(XF, YF), base=f)
+    return K1, K2, dict(plain=(K1p, K2p), learned=(L1, L2), judge=(Jp, Jl), fallback=Jp < Jl, wX=wX, wY=wY,
+                        tau=tau, features=(XF, YF), base=f)
+
+
+def kernel_slices(K1, K2, S: int, pass_: int, j: int) -> np.ndarray:
+    """x = (u: K2 slice, v: K1 slice) of the kernels at sample j of a pass:
+    pass X (0) evaluates along y at w_j, pass Y (1) along x."""
+    w = np.exp(-2j * np.pi * j / S)
+    def sl(K):
+        p = w ** np.arange(K.shape[0])
+        return p @ K if pass_ == 0 else K @ p
+    return np.concatenate([sl(K2), sl(K1)])
+
+
+def judge_objective(K1, K2, EX, EY, S: int) -> float:
+    """The plain method's objective for a kernel pair: the sum over both
+    passes and all samples of the Rayleigh quotient x^H G x / x^H x of the
+    pair's slices in the sample's Gram (the per-sample TLS residual)."""
+    k1, k2 = K1.shape[0], K2.shape[0]
+    J = 0.0
+    for p, (E1, E2) in enumerate((EX, EY)):
+        for j in range(S):
+            G = cbp.sample_gram(E1[j], E2[j], k1, k2)
+            x = kernel_slices(K1, K2, S, p, j)
+            J += float(np.real(np.vdot(x, G @ x)) / np.real(np.vdot(x, x)))
+    return J
 
 
 # --------------------------------------------------------------------------

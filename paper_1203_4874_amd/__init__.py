@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "lib", "library_path", "CbpError", "Precision", "workspace_size", "eval_unit_circle",
     "recover_kernels", "deblur", "deblur_batch", "Deblurrer", "PreparedBatch", "decode_diag", "profile",
-    "Flags", "last_tuning", "sample_grams", "MlpState", "mlp_forward", "mlp_blob_from_params",
+    "Flags", "last_tuning", "sample_grams", "MlpState", "mlp_forward", "mlp_blob_from_params", "load_mlp",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -85,7 +85,8 @@ class CbpDiag(ctypes.Structure):
                 ("scale_vec", ctypes.c_double * 2 * (2 * CBP_MAX_S)),
                 ("khat", ctypes.c_double * 2 * CBP_MAX_S * CBP_MAX_S * 2),
                 ("sample_features", ctypes.c_float * 32 * CBP_MAX_S * 2),
-                ("sample_weights", ctypes.c_double * (2 * CBP_MAX_S + 1))]
+                ("sample_weights", ctypes.c_double * (2 * CBP_MAX_S + 1)),
+                ("judge", ctypes.c_double * 2)]
 
 
 _LIB = None
@@ -220,7 +221,8 @@ def decode_diag(buf: np.ndarray) -> dict:
                 scale_vec=(scv[:2 * S, 0] + 1j * scv[:2 * S, 1]).copy(),
                 khat=(kh[:, :S, :S, 0] + 1j * kh[:, :S, :S, 1]).copy(),
                 sample_features=np.ctypeslib.as_array(d.sample_features).reshape(2, CBP_MAX_S, 32)[:, :S].copy(),
-                sample_weights=np.ctypeslib.as_array(d.sample_weights)[:2 * S + 1].copy())
+                sample_weights=np.ctypeslib.as_array(d.sample_weights)[:2 * S + 1].copy(),
+                judge=list(d.judge))
 
 
 @dataclass
@@ -412,6 +414,19 @@ def mlp_forward(blob, X, stream=None):
     _check(lib().cbp_mlp_forward(blob.data_ptr(), X.data_ptr(), X.shape[0], out.data_ptr(), _stream_ptr(stream)),
            "cbp_mlp_forward")
     return out
+
+
+WEIGHTS = os.path.join(_HERE, "weights", "cbp_mlp.npz")
+
+
+def load_mlp(path: str = WEIGHTS, device="cuda"):
+    """The trained network (packed FP32 parameters in an .npz written by
+    paper_1203_4874_amd.train_mlp) as an inference blob on the device."""
+    with np.load(path, allow_pickle=False) as z:
+        params = np.ascontiguousarray(z["params"], dtype=np.float32)
+    if params.size != MlpState.param_count():
+        raise ValueError(f"{path}: {params.size} parameters, expected {MlpState.param_count()}")
+    return mlp_blob_from_params(params, device)
 
 
 def mlp_blob_from_params(params, device="cuda"):

@@ -42,7 +42,7 @@ int smooth7(int n) {
 // for any frame within (maxH, maxW, maxk, S, nch) fits the size that
 // cbp_workspace_size() reports for those bounds.
 struct region_sizes {
-  size_t fpart, ex, ey, corr, xvec, lam0, pq, cbuf, kern, t, u, feat, wts;
+  size_t fpart, ex, ey, corr, xvec, lam0, pq, cbuf, kern, t, u, feat, wts, kalt;
 };
 
 region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
@@ -63,6 +63,7 @@ region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
   r.u = (size_t)nch * Hmax * hx * 2 * esize;
   r.feat = 2 * (size_t)S * 32 * sizeof(float);
   r.wts = (2 * (size_t)S + 1) * sizeof(double);
+  r.kalt = 2 * (size_t)CBP_MAX_K * CBP_MAX_K * sizeof(double);
   return r;
 }
 
@@ -83,6 +84,7 @@ size_t layout(frame_plan* fp, const region_sizes& r) {
   fp->off_u = take(r.u);
   fp->off_feat = take(r.feat);
   fp->off_wts = take(r.wts);
+  fp->off_kalt = take(r.kalt);
   fp->total = o;
   return o;
 }
@@ -221,6 +223,7 @@ frame_desc make_desc(const frame_plan& fp, const cbp_image* b1, const cbp_image*
   d.diag = (cbp_diag*)diag;
   d.feat = (learned || diag) ? (float*)(ws + fp.off_feat) : nullptr;
   d.wts = learned ? (double*)(ws + fp.off_wts) : nullptr;
+  d.Kalt = (double*)(ws + fp.off_kalt);
   return d;
 }
 
@@ -372,8 +375,16 @@ hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool 
   if (cv.gram_fmt < 0) CBP_TRY(launch_gram(br(Q_GRAM), cv.grid[Q_GRAM], st));
   else CBP_TRY(launch_gram_mfma(br(Q_GRAMM), cv.grid[Q_GRAMM], cv.gram_fmt, cv.maxStride, st));
   CBP_TRY(launch_sample(br(Q_SAMPLE), cv.grid[Q_SAMPLE], cv.maxN, st));
-  if (cv.mlp) CBP_TRY(launch_mlp_frames(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.mlp, st));
-  CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, cv.mlp != nullptr, st));
+  if (cv.mlp) {
+    // the learned form: plain kernels (the fallback), the network's weights,
+    // the learned kernels, and the judge between them
+    CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, 0, 1, st));
+    CBP_TRY(launch_mlp_frames(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.mlp, st));
+    CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, 1, 0, st));
+    CBP_TRY(launch_judge(br(Q_FINALIZE), cv.grid[Q_FINALIZE], st));
+  } else {
+    CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, 0, 0, st));
+  }
   if (latent) {
     CBP_TRY(launch_col<T>(br(Q_COL), cv.grid[Q_COL], cv.maxPy, cv.maxcw, st));
     CBP_TRY(launch_row_inv<T>(br(Q_ROW_INV), cv.grid[Q_ROW_INV], cv.maxPx, st));

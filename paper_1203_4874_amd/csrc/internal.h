@@ -40,7 +40,7 @@ struct frame_plan {
   int cw;                  // columns per workgroup in the column pass
   fft_plan fy, fx;
   size_t off_fpart, off_ex, off_ey, off_corr, off_xvec, off_lam0, off_pq, off_cbuf, off_kern,
-      off_t1, off_t2, off_u, off_feat, off_wts, total;
+      off_t1, off_t2, off_u, off_feat, off_wts, off_kalt, total;
 };
 
 // Everything a kernel needs about one frame (device pointers).
@@ -78,6 +78,7 @@ struct frame_desc {
   // assembly)
   float* feat;
   double* wts;
+  double* Kalt;   // the plain method's kernels (fallback of the learned form), 2 x CBP_MAX_K^2
 };
 
 // Work items of each queue for one frame (the grid of a one-frame launch).
@@ -178,8 +179,11 @@ hipError_t launch_gram(const batch_ref& br, int grid, hipStream_t st);
 // dense Gram matrices (2 S N N complex FP64, [pass][sample][p][q]); items of Q_GRAMM
 hipError_t launch_gram_expand(const batch_ref& br, int grid, double* out, hipStream_t st);
 hipError_t launch_sample(const batch_ref& br, int grid, int maxN, hipStream_t st);
-hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned,
+hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned, int plain_only,
                            hipStream_t st);
+// the learned form's judge: keeps the plain kernels where their per-sample
+// residual objective is smaller (items of Q_FINALIZE)
+hipError_t launch_judge(const batch_ref& br, int grid, hipStream_t st);
 size_t finalize_lds_bytes(int S, int learned);
 size_t sample_lds_bytes(int N);
 

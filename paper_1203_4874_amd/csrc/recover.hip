@@ -493,11 +493,84 @@ __device__ inline void learned_assembly(const c64* tw, int S, int k, const doubl
   __syncthreads();
 }
 
-// Items: one per frame.
-__global__ __launch_bounds__(SMALL_NT) void k_finalize(batch_ref br) {
+// Items: one per frame.  plain_only: the plain method's kernels into the
+// learned form's fallback slots (d.Kalt), ignoring the network's weights.
+__global__ __launch_bounds__(SMALL_NT) void k_finalize(batch_ref br, int plain_only) {
   extern __shared__ __attribute__((aligned(16))) char sm_fin[];
   for_items<Q_FINALIZE>(br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
-    finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, d.cbuf, d.K1, d.K2, d.diag, sm_fin, d.wts);
+    if (plain_only)
+      finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, d.cbuf, d.Kalt, d.Kalt + CBP_MAX_K * CBP_MAX_K, nullptr, sm_fin,
+                     nullptr);
+    else
+      finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, d.cbuf, d.K1, d.K2, d.diag, sm_fin, d.wts);
+  });
+}
+
+// The learned form's judge: the plain method's objective
+//   J(K1, K2) = sum over passes and samples of x^H G x / x^H x,
+// with x = (K2 slice, K1 slice) of the kernels at that sample (the
+// per-sample TLS residual the plain method minimises), for the plain
+// kernels (d.Kalt) and the learned ones (d.K1, d.K2); the plain ones replace
+// the learned ones when their J is smaller.  Items: one per frame.
+__global__ __launch_bounds__(64) void k_judge(batch_ref br) {
+  __shared__ c64 tw[CBP_MAX_S];
+  __shared__ c64 xs[CBP_MAX_N];
+  for_items<Q_FINALIZE>(br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
+    const int S = d.S, k1 = d.k1, k2 = d.k2, N = k1 + k2, NL = 2 * N - 1;
+    const int l = threadIdx.x;
+    unit_twiddles(tw, S);
+    __syncthreads();
+    double J[2];
+    for (int set = 0; set < 2; ++set) {
+      const double* A1 = set ? d.K1 : d.Kalt;
+      const double* A2 = set ? d.K2 : d.Kalt + CBP_MAX_K * CBP_MAX_K;
+      double acc = 0.0;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int j = 0; j < S; ++j) {
+          if (l < N) {
+            const bool u = l < k2;
+            const double* K = u ? A2 : A1;
+            const int k = u ? k2 : k1, c = u ? l : l - k2;
+            c64 sacc = {0.0, 0.0};
+            int t = 0;
+            for (int r = 0; r < k; ++r) {
+              const double kv = pass == 0 ? K[r * k + c] : K[c * k + r];   // along y (pass X) or x (pass Y)
+              sacc = sacc + c64{kv * tw[t].re, kv * tw[t].im};
+              t += j;
+              if (t >= S) t -= S;
+            }
+            xs[l] = sacc;
+          }
+          __syncthreads();
+          const gram_acc G{d.corr + ((size_t)pass * S + j) * NL, k1, k2};
+          double num = 0.0, nx = 0.0;
+          if (l < N) {
+            c64 y = {0.0, 0.0};
+            for (int q = 0; q < N; ++q) {
+              const cdd g = G.get(l, q);
+              y = y + c64{dd_val(g.re), dd_val(g.im)} * xs[q];
+            }
+            const c64 xl = xs[l];
+            num = xl.re * y.re + xl.im * y.im;   // Re(conj(x_l) y_l)
+            nx = norm2(xl);
+          }
+          num = wsum(num);
+          nx = wsum(nx);
+          acc += num / nx;
+          __syncthreads();
+        }
+      J[set] = acc;
+    }
+    const bool fallback = J[0] < J[1];
+    if (fallback) {
+      for (int e = l; e < k1 * k1; e += 64) d.K1[e] = d.Kalt[e];
+      for (int e = l; e < k2 * k2; e += 64) d.K2[e] = d.Kalt[CBP_MAX_K * CBP_MAX_K + e];
+    }
+    if (l == 0 && d.diag) {
+      d.diag->judge[0] = J[0];
+      d.diag->judge[1] = J[1];
+      if (fallback) atomicOr(&d.diag->flags, CBP_DIAG_FALLBACK);
+    }
   });
 }
 
@@ -569,10 +642,15 @@ hipError_t launch_sample(const batch_ref& br, int grid, int maxN, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned,
+hipError_t launch_judge(const batch_ref& br, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_judge, dim3(grid), dim3(64), 0, st, br);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned, int plain_only,
                            hipStream_t st) {
   prof_begin(PH_FINALIZE, st);
-  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(SMALL_NT), finalize_lds_bytes(maxS, learned), st, br);
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(SMALL_NT), finalize_lds_bytes(maxS, learned), st, br, plain_only);
   prof_end(PH_FINALIZE, st);
   return hipGetLastError();
 }

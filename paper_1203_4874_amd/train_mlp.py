@@ -9,9 +9,10 @@ frames.  Every pair goes through the library's batched deblurring call with
 diagnostics on, which returns each sample's spectrum features, null vector
 and the averaged kernel spectra.  Targets come from the true kernels:
 
-  * w*: the inverse squared sine of the angle between the sample's null
-    vector and the true kernel slices at that sample, divided by its
-    geometric mean over the frame's 2S samples, clipped to [1e-3, 1e3];
+  * w*: the inverse sine of the angle between the sample's null vector and
+    the true kernel slices at that sample, divided by its geometric mean over
+    the frame's 2S samples, clipped to [0.1, 10] (a compressed confidence:
+    the network's error in log w then moves a weight by a bounded factor);
   * tau*: S times the noise-to-signal ratio of the frame's averaged spectra
     against the true spectra (after the best complex scale), floored at
     1e-12 -- a ridge strength in the units of the assembly's normal matrix.
@@ -19,7 +20,9 @@ and the averaged kernel spectra.  Targets come from the true kernels:
 The network (32 -> 128 -> 128 -> 2, BF16 on the matrix cores) is trained with
 the library's own forward / backward / Adam kernels on (features, (log w*,
 log tau*)).  The held-out pairs are then deblurred with and without the
-network and both kernel errors against the truth are reported.
+network and both kernel errors against the truth are reported (the learned
+call includes the judge that keeps the plain kernels when the plain method's
+objective prefers them).
 """
 
 from __future__ import annotations
@@ -92,8 +95,8 @@ def targets(diag, K1, K2):
             t = xs[p][j]
             c = abs(np.vdot(t, x)) ** 2 / (np.vdot(x, x).real * np.vdot(t, t).real)
             sin2[p, j] = max(1.0 - c, 1e-10)
-    w = 1.0 / sin2
-    w = np.clip(w / np.exp(np.mean(np.log(w))), 1e-3, 1e3)
+    w = 1.0 / np.sqrt(sin2)
+    w = np.clip(w / np.exp(np.mean(np.log(w))), 0.1, 10.0)
     num = den = 0.0
     for c, K in enumerate((K1, K2)):
         Kt = true_spectra(K, S)
@@ -145,32 +148,33 @@ def main():
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_1203_4874_amd", "weights"))
     args = ap.parse_args()
 
+    # the generator processes are forked before anything touches the GPU
+    import multiprocessing as mp
+    ex = ProcessPoolExecutor(max_workers=args.workers, mp_context=mp.get_context("fork"))
+    list(ex.map(abs, range(4 * args.workers)))
+
     import torch
     import paper_1203_4874_amd as P
     dev = torch.device("cuda:0")
     P.lib()
     total = args.pairs + args.holdout
     t0 = time.time()
-    pairs = []
-    with ProcessPoolExecutor(max_workers=args.workers) as ex:
-        for i, p in enumerate(ex.map(make_pair, range(total), chunksize=64)):
-            pairs.append(p)
-            if (i + 1) % 2000 == 0:
-                print(f"[train] generated {i + 1}/{total} pairs ({time.time() - t0:.0f} s)", flush=True)
-    train, hold = pairs[:args.pairs], pairs[args.pairs:]
-
-    t0 = time.time()
     Xs, Ts = [], []
-    for c0 in range(0, len(train), 2000):
-        res = run_pairs(P, torch, dev, train[c0:c0 + 2000])
-        for p, (dg, _, _) in zip(train[c0:c0 + 2000], res):
-            if dg is None:
-                continue
-            X, T = targets(dg, p["K1"], p["K2"])
-            Xs.append(X)
-            Ts.append(T)
-        print(f"[train] features of {min(c0 + 2000, len(train))}/{len(train)} pairs ({time.time() - t0:.0f} s)",
-              flush=True)
+    chunk = 2000
+    with ex:
+        # training pairs, generated and consumed chunk by chunk (only features and targets are kept)
+        for c0 in range(0, args.pairs, chunk):
+            ids = list(range(c0, min(c0 + chunk, args.pairs)))
+            pairs = list(ex.map(make_pair, ids, chunksize=32))
+            res = run_pairs(P, torch, dev, pairs)
+            for p, (dg, _, _) in zip(pairs, res):
+                if dg is None:
+                    continue
+                X, T = targets(dg, p["K1"], p["K2"])
+                Xs.append(X)
+                Ts.append(T)
+            print(f"[train] features of {ids[-1] + 1}/{args.pairs} pairs ({time.time() - t0:.0f} s)", flush=True)
+        hold = list(ex.map(make_pair, range(args.pairs, total), chunksize=32))
     X = np.concatenate(Xs)
     T = np.concatenate(Ts)
     ok = np.isfinite(X).all(1) & np.isfinite(T).all(1)
@@ -186,6 +190,9 @@ def main():
         o += rows * cols
         init[o:o + rows] = 0.0
         o += rows
+    # output biases at the targets' centre: w = softplus(o1) = 1, o2 = mean log tau*
+    init[-2] = np.log(np.e - 1.0)
+    init[-1] = float(np.mean(T[:, 1]))
     st = P.MlpState(args.batch, dev)
     st.set_params(init)
     Xd = torch.as_tensor(X, device=dev)
@@ -201,7 +208,7 @@ def main():
             ids = perm[b * args.batch:(b + 1) * args.batch]
             xb, tb = Xd[ids].contiguous(), Td[ids].contiguous()
             step += 1
-            lr = args.lr * 0.5 * (1 + np.cos(np.pi * step / (args.epochs * steps_per_epoch)))
+            lr = args.lr * (0.05 + 0.95 * 0.5 * (1 + np.cos(np.pi * step / (args.epochs * steps_per_epoch))))
             loss = st.train_step(xb, tb, lr, step)
             tot += float(loss.item()) if b % 16 == 0 else 0.0
         print(f"[train] epoch {ep + 1}/{args.epochs}: loss ~{tot / max(1, (steps_per_epoch + 15) // 16):.4f} "

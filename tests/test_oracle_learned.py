@@ -144,3 +144,25 @@ def test_bf16_network_emulation_reduces_to_fp64_on_representable_values():
     v = learned.pack(p)
     q = learned.unpack(v)
     assert all(np.array_equal(p[k], q[k]) for k in p) and v.size == 20994
+
+
+def test_judge_objective_is_zero_on_true_kernels_and_prefers_them():
+    """Noiseless: the true kernels' slices are the per-sample null vectors, so
+    their objective is ~0 (relative to the Gram scale) and any perturbation
+    raises it."""
+    r = synth.rng_for(91)
+    L = r.random((36, 40))
+    K1, K2 = synth.draw_coprime_pair(r, 4, 5, "uniform")
+    B1, B2 = synth.full_conv2d(L, K1), synth.full_conv2d(L, K2)
+    S = 5
+    EX = [cbp.unit_circle_eval(B, S)[0] for B in (B1, B2)]
+    EY = [cbp.unit_circle_eval(B, S)[1] for B in (B1, B2)]
+    J0 = learned.judge_objective(K1, K2, EX, EY, S)
+    scale = sum(np.trace(cbp.sample_gram(EX[0][j], EX[1][j], 4, 5)).real for j in range(S))
+    assert J0 <= 1e-20 * scale
+    J1 = learned.judge_objective(K1 + 1e-3 * r.random(K1.shape), K2, EX, EY, S)
+    assert J1 > 1e6 * max(J0, 1e-300)
+    # the slices of a kernel pair at a sample are the ones the oracle's truth pins use
+    x = learned.kernel_slices(K1, K2, S, 0, 2)
+    w = np.exp(-2j * np.pi * 2 / S)
+    assert np.allclose(x[:5], (w ** np.arange(5)) @ K2) and np.allclose(x[5:], (w ** np.arange(4)) @ K1)
