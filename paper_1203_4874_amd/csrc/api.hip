@@ -42,7 +42,7 @@ int smooth7(int n) {
 // for any frame within (maxH, maxW, maxk, S, nch) fits the size that
 // cbp_workspace_size() reports for those bounds.
 struct region_sizes {
-  size_t fpart, ex, ey, corr, xvec, lam0, pq, cbuf, kern, t, u, feat, wts, kalt;
+  size_t fpart, ex, ey, corr, xvec, lam0, pq, cbuf, kern, t, u, feat, wts, kalt, twxd, twx, twy;
 };
 
 region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
@@ -64,6 +64,9 @@ region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
   r.feat = 2 * (size_t)S * 32 * sizeof(float);
   r.wts = (2 * (size_t)S + 1) * sizeof(double);
   r.kalt = 2 * (size_t)CBP_MAX_K * CBP_MAX_K * sizeof(double);
+  r.twxd = (size_t)Px * sizeof(c64);
+  r.twx = (size_t)Px * 2 * esize;
+  r.twy = (size_t)smooth7(Hmax) * 2 * esize;
   return r;
 }
 
@@ -85,6 +88,9 @@ size_t layout(frame_plan* fp, const region_sizes& r) {
   fp->off_feat = take(r.feat);
   fp->off_wts = take(r.wts);
   fp->off_kalt = take(r.kalt);
+  fp->off_twxd = take(r.twxd);
+  fp->off_twx = take(r.twx);
+  fp->off_twy = take(r.twy);
   fp->total = o;
   return o;
 }
@@ -224,6 +230,9 @@ frame_desc make_desc(const frame_plan& fp, const cbp_image* b1, const cbp_image*
   d.feat = (learned || diag) ? (float*)(ws + fp.off_feat) : nullptr;
   d.wts = learned ? (double*)(ws + fp.off_wts) : nullptr;
   d.Kalt = (double*)(ws + fp.off_kalt);
+  d.twxd = (c64*)(ws + fp.off_twxd);
+  d.twx = ws + fp.off_twx;
+  d.twy = ws + fp.off_twy;
   return d;
 }
 
@@ -364,7 +373,10 @@ hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool 
   hipStream_t side = ds.side;
   CBP_TRY(hipEventRecord(ds.ev_fork, st));
   CBP_TRY(hipStreamWaitEvent(side, ds.ev_fork, 0));
-  if (latent) CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, side));
+  if (latent) {
+    CBP_TRY(launch_twiddles<T>(br(Q_TWID), cv.grid[Q_TWID], side));
+    CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, side));
+  }
   else CBP_TRY(launch_eval_rows<T>(br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], side));
   CBP_TRY(hipEventRecord(ds.ev_side, side));
   if (diag) CBP_TRY(launch_diag_init(br(Q_DIAG), cv.grid[Q_DIAG], st));

@@ -8,15 +8,15 @@
 //     negative pivots of the LDL^T factorisation of T - s I is the number of
 //     eigenvalues below s (Sylvester's law of inertia).  64 probes per round,
 //     8 rounds, leave a bracket [lo, hi] of width ~6e-15 ||T||.
-//  3. sigma = lo - 16 n eps ||T|| < lam0, so B = G - sigma I is positive
-//     definite with its smallest eigenvalue well separated from the rest;
-//     M = B^{-1} by Gauss-Jordan elimination (no pivoting is needed for a
-//     positive definite matrix).
-//  4. Inverse iteration x <- M x / ||M x|| (error shrinks by
-//     (lam0 - sigma) / (lam1 - sigma) per step).
-//  5. Newton refinement against G held in double-double:
+//  3. sigma = lo - 16 n eps ||T|| < lam0, so T - sigma I is positive
+//     definite with its smallest eigenvalue well separated from the rest; its
+//     LDL^T factors (d_k > 0) give inverse iteration on T at O(n) per solve,
+//     and the Householder reflectors (kept in the reduced matrix's strictly
+//     lower part) and the diagonal unitary map T's eigenvector y back to G's:
+//     x = Q D y.
+//  4. Newton refinement against G held in double-double:
 //       r = G x - mu x (mu = x^H G x, both double-double),
-//       x <- (x - M r) / ||x - M r||,
+//       x <- (x - M r) / ||x - M r||,  M = Q D (T - sigma I)^{-1} D^H Q^H,
 //     until the correction is below 4e-15; M r approximates the exact Newton
 //     step sum_k v_k (v_k^H r) / (lam_k - mu) with relative error
 //     (mu - sigma) / (lam_k - sigma).
@@ -34,21 +34,23 @@ namespace cbp {
 
 constexpr int SMALL_NT = 64;
 constexpr int SMALL_REFINE_MAX = 4;
-constexpr int SMALL_INVIT = 4;
+constexpr int SMALL_INVIT = 3;
 constexpr int SMALL_BISECT_ROUNDS = 8;
 
 struct small_ws {
-  c64* A;       // n*n: matrix being reduced, then B, then M = B^{-1}
+  c64* A;       // n*n: matrix being reduced; afterwards the reflectors below the diagonal
   c64* e;       // n: complex off-diagonal of the Hermitian tridiagonal
-  c64* w;       // n: scratch (Householder vector / GJ column)
-  c64* u;       // n: scratch (Householder w / GJ row)
+  c64* w;       // n: scratch (Householder vector; then the LDL^T factors {1/d_k, l_k})
+  c64* u;       // n: scratch (Householder w; then the right-hand side of a tridiagonal solve)
   c64* x;       // n: result vector
   double* a;    // n: diagonal of T
   double* b;    // n: off-diagonal of T, b[k] = T[k+1][k]
+  dd* part;     // 4 x 64 x 2: partial double-double row sums of the refinement's product
 };
 
 __host__ __device__ inline size_t small_lds_bytes(int n) {
-  return (size_t)n * n * sizeof(c64) + (size_t)n * (4 * sizeof(c64) + 2 * sizeof(double)) + 64;
+  return (size_t)n * n * sizeof(c64) + (size_t)n * (4 * sizeof(c64) + 2 * sizeof(double)) +
+         (size_t)4 * 64 * 2 * sizeof(dd) + 64;
 }
 
 __device__ inline small_ws small_carve(char* base, int n) {
@@ -60,7 +62,8 @@ __device__ inline small_ws small_carve(char* base, int n) {
   s.u = (c64*)p; p += n * sizeof(c64);
   s.x = (c64*)p; p += n * sizeof(c64);
   s.a = (double*)p; p += n * sizeof(double);
-  s.b = (double*)p;
+  s.b = (double*)p; p += n * sizeof(double);
+  s.part = (dd*)p;
   return s;
 }
 
@@ -168,8 +171,9 @@ __device__ inline void small_tridiag(small_ws& s, int n) {
     const double x0r = readlane_d(xl.re, 0), x0i = readlane_d(xl.im, 0);
     const double ax0sq = x0r * x0r + x0i * x0i;
     const double tail = wsum(l >= 1 ? norm2(xl) : 0.0);
-    if (!(tail > 0.0)) {                        // column already reduced
+    if (!(tail > 0.0)) {                        // column already reduced: reflector k = I
       if (l == 0) s.e[k] = {x0r, x0i};
+      if (l < m) A[(size_t)(o + l) * n + k] = {0.0, 0.0};
       continue;
     }
     const double nx = s2 * rsq_nr(s2);
@@ -182,6 +186,7 @@ __device__ inline void small_tridiag(small_ws& s, int n) {
       const c64 ul = (l == 0) ? c64{xl.re - alpha.re, xl.im - alpha.im} : xl;
       vl = {ul.re * sc, ul.im * sc};
       V[l] = vl;
+      A[(size_t)(o + l) * n + k] = vl;          // reflector k, kept for the back-transformation
     }
     __syncthreads();
     // p = A' v (A' trailing m x m block; A'[l][j] = conj(A'[j][l]) read by column)
@@ -314,7 +319,8 @@ __device__ inline double small_spectrum(const small_ws& s, int n) {
   return exp10(0.5 * (lo + hi));
 }
 
-// ---------------------------------------------------------------- 3. inverse
+// ---------------------------------------------------------------- Gauss-Jordan inverse
+// (used by the learned form's assembly)
 // s.A <- s.A^{-1} for a Hermitian positive definite matrix (Gauss-Jordan, no
 // pivoting; row and column k are staged in s.u / s.w before the update).
 __device__ inline void small_gj_inverse(small_ws& s, int n) {
@@ -361,23 +367,135 @@ __device__ inline void small_gj_inverse(small_ws& s, int n) {
   }
 }
 
-// y = M x for Hermitian M = s.A (lane l reads column l: M[l][j] = conj(M[j][l])).
-__device__ inline c64 small_matvec(const small_ws& s, int n, const c64* __restrict__ x) {
+// ---------------------------------------------------------------- 3. tridiagonal solves
+// The recurrences below are serial in k.  Every lane runs them in step on the
+// same values read from LDS (broadcast reads, eight entries per batch, so the
+// reads overlap the arithmetic of the previous batch); lane 0 stores the
+// results.
+
+// LDL^T factors of T - sigma I into s.w[k] = {1/d_k, l_k = b_k / d_k}
+// (d_0 = a_0 - sigma, d_{k+1} = a_{k+1} - sigma - b_k l_k).  Pivots at or
+// below pivmin (reachable only through rounding, since T - sigma I is
+// positive definite) are raised to it.
+__device__ inline void tri_factor(small_ws& s, int n, double sigma, double pivmin) {
   const int l = threadIdx.x;
-  c64 s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
-  if (l < n) {
-    const c64* colp = s.A + l;
-    int j = 0;
-    for (; j + 4 <= n; j += 4) {
-      const c64 a0 = colp[(size_t)j * n], a1 = colp[(size_t)(j + 1) * n];
-      const c64 a2 = colp[(size_t)(j + 2) * n], a3 = colp[(size_t)(j + 3) * n];
-      const c64 x0 = x[j], x1 = x[j + 1], x2 = x[j + 2], x3 = x[j + 3];
-      s0 = s0 + cmulc(a0, x0) + cmulc(a2, x2);
-      s1 = s1 + cmulc(a1, x1) + cmulc(a3, x3);
+  double d = s.a[0] - sigma;
+  for (int k0 = 0; k0 < n; k0 += 8) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k0 + t;
+      av[t] = k + 1 < n ? s.a[k + 1] : 0.0;
+      bv[t] = k < n ? s.b[k] : 0.0;
     }
-    for (; j < n; ++j) s0 = s0 + cmulc(colp[(size_t)j * n], x[j]);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k0 + t;
+      if (k < n) {
+        if (!(d > pivmin)) d = pivmin;
+        const double id = rcp_nr(d);
+        const double lk = bv[t] * id;
+        if (l == 0) s.w[k] = {id, lk};
+        d = av[t] - sigma - bv[t] * lk;
+      }
+    }
   }
-  return s0 + s1;
+  __syncthreads();
+}
+
+// z = (T - sigma I)^{-1} r from the factors in s.w (lane k holds r_k and
+// receives z_k; lanes >= n hold zeros).  Forward L w = r and the diagonal
+// (w'_k = w_k / d_k, kept in s.u), then backward L^T z = w'.
+__device__ inline c64 tri_solve(small_ws& s, c64 r, int n) {
+  const int l = threadIdx.x;
+  if (l < n) s.u[l] = r;
+  __syncthreads();
+  double wr = 0.0, wi = 0.0, lprev = 0.0;
+  for (int k0 = 0; k0 < n; k0 += 8) {
+    c64 rv[8], fv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k0 + t;
+      rv[t] = k < n ? s.u[k] : c64{0.0, 0.0};
+      fv[t] = k < n ? s.w[k] : c64{0.0, 0.0};
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k0 + t;
+      if (k < n) {
+        wr = rv[t].re - lprev * wr;
+        wi = rv[t].im - lprev * wi;
+        lprev = fv[t].im;
+        if (l == 0) s.u[k] = {wr * fv[t].re, wi * fv[t].re};
+      }
+    }
+  }
+  __syncthreads();
+  c64 z = {0.0, 0.0};
+  double zr = 0.0, zi = 0.0;
+  for (int k1 = n - 1; k1 >= 0; k1 -= 8) {
+    c64 wv[8], fv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k1 - t;
+      wv[t] = k >= 0 ? s.u[k] : c64{0.0, 0.0};
+      fv[t] = k >= 0 ? s.w[k] : c64{0.0, 0.0};
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k1 - t;
+      if (k >= 0) {
+        const double lk = k + 1 < n ? fv[t].im : 0.0;
+        zr = wv[t].re - lk * zr;
+        zi = wv[t].im - lk * zi;
+        if (l == k) z = {zr, zi};
+      }
+    }
+  }
+  __syncthreads();
+  return z;
+}
+
+// Diagonal unitary D with D^H T_c D = T (T_c the complex tridiagonal with
+// subdiagonal e_k, T its real form with b_k = |e_k|): ph_0 = 1,
+// ph_{k+1} = ph_k e_k / |e_k|.  Lane k receives ph_k.
+__device__ inline c64 tri_phases(const small_ws& s, int n) {
+  const int l = threadIdx.x;
+  c64 p = {1.0, 0.0};
+  c64 ph = {l < n ? 1.0 : 0.0, 0.0};
+  for (int k = 0; k + 1 < n; ++k) {
+    const c64 e = s.e[k];
+    const double ae = s.b[k];
+    if (ae > 0.0) {
+      const double ir = 1.0 / ae;
+      p = p * c64{e.re * ir, e.im * ir};
+    }
+    if (l == k + 1) ph = p;
+  }
+  return ph;
+}
+
+// z <- Q z (adjoint: Q^H z) with Q = H_0 H_1 ... H_{n-3}, H_k = I - v_k v_k^H
+// (||v_k||^2 = 2 or v_k = 0), v_k kept in column k below the diagonal of s.A.
+// Lane l holds z_l.  The next reflector's entry is read ahead of the wave
+// reduction that the current one needs.
+__device__ inline c64 apply_reflectors(const small_ws& s, int n, c64 z, bool adjoint) {
+  const int l = threadIdx.x;
+  const int K = n - 2;
+  if (K <= 0) return z;
+  int k = adjoint ? 0 : K - 1;
+  const int dk = adjoint ? 1 : -1;
+  c64 v = (l > k && l < n) ? s.A[(size_t)l * n + k] : c64{0.0, 0.0};
+  for (int t = 0; t < K; ++t) {
+    const int kn = k + dk;
+    c64 vn = {0.0, 0.0};
+    if (t + 1 < K && l > kn && l < n) vn = s.A[(size_t)l * n + kn];
+    const c64 dot = wsum_c(cmulc(v, z));
+    z = z - v * dot;
+    v = vn;
+    k = kn;
+  }
+  return z;
 }
 
 // ---------------------------------------------------------------- the solver
@@ -407,67 +525,80 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_lam
     *lam1 = __builtin_nan("");
   }
   const double sigma = lo0 - 16.0 * n * 2.2e-16 * tn;
-  // B = G - sigma I (rounded G), inverted in place
-  {
-    const float rn = 1.0f / (float)n;
-    for (int e = l; e < n * n; e += SMALL_NT) {
-      int i, jj;
-      split_index(e, n, rn, i, jj);
-      const cdd g = acc.get(i, jj);
-      s.A[e] = {g.re.hi - (i == jj ? sigma : 0.0), g.im.hi};
-    }
+  const double pivmin = 1e-300 + 2.2e-16 * 2.2e-16 * tn;
+  tri_factor(s, n, sigma, pivmin);
+  const c64 ph = tri_phases(s, n);
+  // inverse iteration on T from a fixed, generic start vector
+  c64 y = l < n ? c64{1.0 + 0.6180339887 * (double)((l * 7) % 11), 0.0} : c64{0.0, 0.0};
+  for (int it = 0; it < SMALL_INVIT; ++it) {
+    y = tri_solve(s, y, n);
+    const double nr = sqrt(wsum(norm2(y)));
+    y = {y.re / nr, y.im / nr};
   }
-  __syncthreads();
-  small_gj_inverse(s, n);
-  // inverse iteration from a fixed, generic start vector
-  c64 xl = l < n ? c64{1.0 + 0.6180339887 * (double)l, 0.5 - 0.4142135624 * (double)((l * 7) % 5)}
-                 : c64{0.0, 0.0};
+  c64 xl = apply_reflectors(s, n, ph * y, false);
+  {
+    const double nr = sqrt(wsum(l < n ? norm2(xl) : 0.0));
+    xl = l < n ? c64{xl.re / nr, xl.im / nr} : c64{0.0, 0.0};
+  }
   if (l < n) s.x[l] = xl;
   __syncthreads();
-  for (int it = 0; it < SMALL_INVIT; ++it) {
-    const c64 y = small_matvec(s, n, s.x);
-    const double nr = sqrt(wsum(l < n ? norm2(y) : 0.0));
-    xl = l < n ? c64{y.re / nr, y.im / nr} : c64{0.0, 0.0};
-    __syncthreads();
-    if (l < n) s.x[l] = xl;
-    __syncthreads();
-  }
-  // Newton refinement against the double-double matrix
+  // Newton refinement against the double-double matrix.  The product G x is
+  // split over ng lane groups (lane l: row l mod n, columns of group l / n),
+  // whose partial sums are added in group order.
+  const int ng = n <= 16 ? 4 : (n <= 21 ? 3 : (n <= 32 ? 2 : 1));
+  const int row = l % n, grp = l / n;
+  const int jspan = (n + ng - 1) / ng;
+  const int j0 = grp * jspan, j1 = min(n, j0 + jspan);
   dd mu = {0.0, 0.0};
+  double dprev = 0.0;
   int it = 0;
   bool done = false;
   for (;; ++it) {
-    dd yre = {0.0, 0.0}, yim = {0.0, 0.0};
-    if (l < n) {
+    if (grp < ng) {
       dot2 ar, ai;
       ar.init();
       ai.init();
-      for (int j = 0; j < n; ++j) {
-        const cdd g = acc.get(l, j);
+      for (int j = j0; j < j1; ++j) {
+        const cdd g = acc.get(row, j);
         const c64 xj = s.x[j];
         ar.add_prod(g.re.hi, xj.re); ar.add(g.re.lo * xj.re);
         ar.add_prod(-g.im.hi, xj.im); ar.add(-g.im.lo * xj.im);
         ai.add_prod(g.re.hi, xj.im); ai.add(g.re.lo * xj.im);
         ai.add_prod(g.im.hi, xj.re); ai.add(g.im.lo * xj.re);
       }
-      yre = ar.result();
-      yim = ai.result();
+      s.part[2 * l] = ar.result();
+      s.part[2 * l + 1] = ai.result();
     }
+    __syncthreads();
+    dd yre = {0.0, 0.0}, yim = {0.0, 0.0};
+    if (l < n) {
+      yre = s.part[2 * l];
+      yim = s.part[2 * l + 1];
+      for (int g = 1; g < ng; ++g) {
+        yre = dd_add(yre, s.part[2 * (g * n + l)]);
+        yim = dd_add(yim, s.part[2 * (g * n + l) + 1]);
+      }
+    }
+    __syncthreads();
     dot2 t;
     t.init();
     t.add_prod(xl.re, yre.hi); t.add(xl.re * yre.lo);
     t.add_prod(xl.im, yim.hi); t.add(xl.im * yim.lo);
     mu = wsum_dd(t.result());
     if (done || it == SMALL_REFINE_MAX) break;
+    c64 r = {0.0, 0.0};
     if (l < n) {
       dot2 qr, qi;
       qr.init(); qi.init();
       qr.add_dd(yre); qr.add_prod(-mu.hi, xl.re); qr.add(-mu.lo * xl.re);
       qi.add_dd(yim); qi.add_prod(-mu.hi, xl.im); qi.add(-mu.lo * xl.im);
-      s.u[l] = {dd_val(qr.result()), dd_val(qi.result())};
+      r = {dd_val(qr.result()), dd_val(qi.result())};
     }
-    __syncthreads();
-    const c64 cl = small_matvec(s, n, s.u);
+    // correction c = Q D (T - sigma I)^{-1} D^H Q^H r
+    c64 z = apply_reflectors(s, n, r, true);
+    z = cmulc(ph, z);
+    z = tri_solve(s, z, n);
+    const c64 cl = apply_reflectors(s, n, ph * z, false);
     const c64 xn = l < n ? xl - cl : c64{0.0, 0.0};
     const double nrm = sqrt(wsum(norm2(xn)));
     const double dn = sqrt(wsum(l < n ? norm2(cl) : 0.0));
@@ -475,7 +606,10 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_lam
     __syncthreads();
     if (l < n) s.x[l] = xl;
     __syncthreads();
-    done = !(dn > 4e-15);
+    // converged when the correction, or the next one predicted from the
+    // linear rate dn / dprev of the last two, is below 4e-15
+    done = !(dn > 4e-15) || (dprev > 0.0 && dn * dn <= 4e-15 * dprev);
+    dprev = dn;
   }
   *steps = it;
   return mu;

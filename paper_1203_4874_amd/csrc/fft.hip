@@ -24,13 +24,33 @@ namespace cbp {
 
 namespace {
 
+// Copy a twiddle table (global, filled by k_twiddles) into LDS.
 template <typename T>
-__device__ inline void fft_twiddles(cplx<T>* tw, int N) {
-  for (int t = threadIdx.x; t < N; t += blockDim.x) {
-    double s, c;
-    sincospi(-2.0 * (double)t / (double)N, &s, &c);
-    tw[t] = {T(c), T(s)};
-  }
+__device__ inline void load_twiddles(cplx<T>* tw, const void* g, int N) {
+  const cplx<T>* src = (const cplx<T>*)g;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = src[t];
+}
+
+// ---------------------------------------------------------------- tables
+// Items: 256 consecutive indices of [0, Px + Py): x tables for t < Px, the y
+// table after.  The FP64 value is rounded once to T, so a table entry equals
+// what an in-place evaluation of exp(-2 pi i t / P) would give.
+template <typename T>
+__global__ __launch_bounds__(256) void k_twiddles(batch_ref br) {
+  for_items<Q_TWID>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+    const int t = item * 256 + (int)threadIdx.x;
+    if (t < d.Px) {
+      double s, c;
+      sincospi(-2.0 * (double)t / (double)d.Px, &s, &c);
+      d.twxd[t] = {c, s};
+      ((cplx<T>*)d.twx)[t] = {T(c), T(s)};
+    } else if (t < d.Px + d.Py) {
+      const int u = t - d.Px;
+      double s, c;
+      sincospi(-2.0 * (double)u / (double)d.Py, &s, &c);
+      ((cplx<T>*)d.twy)[u] = {T(c), T(s)};
+    }
+  });
 }
 
 // Run all passes of plan p on nbatch transforms (stride bstride) held in a;
@@ -73,7 +93,7 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
     const T* r1 = (const T*)d.b1 + ch * d.cs1 + (int64_t)y * d.p1;
     const T* r2 = (const T*)d.b2 + ch * d.cs2 + (int64_t)y * d.p2;
     const bool in1 = y < d.H1, in2 = y < d.H2;
-    fft_twiddles(tw, N);
+    load_twiddles(tw, d.twx, N);
     if (with_ey)
       for (int t = threadIdx.x; t < d.S; t += blockDim.x) {
         double sn, cs;
@@ -146,6 +166,7 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
     const int k1 = d.k1, k2 = d.k2, Px = d.Px, H1 = d.H1, H2 = d.H2;
     const double* K1 = d.K1;
     const double* K2 = d.K2;
+    const c64* twd = d.twxd;
     const T lam = (T)d.lambda;
     const int nf = 2 * cw;                      // transforms in flight: (column, frame)
     cplx<T>* a = (cplx<T>*)sm_cf;               // [nf][N]
@@ -157,7 +178,7 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
     const int64_t tpc = (int64_t)d.Hmax * hx;
     const cplx<T>* s1 = (const cplx<T>*)d.t1 + ch * tpc;
     const cplx<T>* s2 = (const cplx<T>*)d.t2 + ch * tpc;
-    fft_twiddles(tw, N);
+    load_twiddles(tw, d.twy, N);
     // load: element (y, f) with f = 2*col + frame; consecutive threads walk f
     // (adjacent columns of one row) for coalescing
     for (int e = threadIdx.x; e < nf * N; e += blockDim.x) {
@@ -180,13 +201,12 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
       const int kx = kx0 + c;
       double sr = 0.0, si = 0.0;
       if (yy < k && kx < hx) {
-        int64_t t = 0;
+        int t = 0;
         for (int x = 0; x < k; ++x) {
-          double sn, cs;
-          sincospi(-2.0 * (double)t / (double)Px, &sn, &cs);
+          const c64 w = twd[t];
           const double kv = K[yy * k + x];
-          sr += kv * cs;
-          si += kv * sn;
+          sr += kv * w.re;
+          si += kv * w.im;
           t += kx;
           if (t >= Px) t -= Px;
         }
@@ -247,7 +267,7 @@ __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
     const cplx<T>* ua = (const cplx<T>*)d.u + (int64_t)ch * m * hx + (int64_t)ya * hx;
     const cplx<T>* ub = ua + hx;
     const bool hb = yb < m;
-    fft_twiddles(tw, N);
+    load_twiddles(tw, d.twx, N);
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
       cplx<T> A, B;
       const bool edge = (k == 0) || (2 * k == N);
@@ -312,6 +332,14 @@ hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_twiddles(const batch_ref& br, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddles<T>, dim3(grid), dim3(256), 0, st, br);
+  return hipGetLastError();
+}
+
+template hipError_t launch_twiddles<float>(const batch_ref&, int, hipStream_t);
+template hipError_t launch_twiddles<double>(const batch_ref&, int, hipStream_t);
 template hipError_t launch_row_fwd<float>(const batch_ref&, int, int, int, hipStream_t);
 template hipError_t launch_row_fwd<double>(const batch_ref&, int, int, int, hipStream_t);
 template hipError_t launch_col<float>(const batch_ref&, int, int, int, hipStream_t);

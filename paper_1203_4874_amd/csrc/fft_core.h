@@ -120,11 +120,12 @@ CBP_HD void dft_small(cplx<T>* v) {
 }
 
 // ---------------------------------------------------------------- one butterfly
+// Butterfly j of a pass with k = j mod Ns given: reads src[j + r N/R],
+// twiddles the inputs by w^(r k N/(Ns R)), writes dst[(j - k) R + k + r Ns].
 template <int R, int DIR, typename T>
 CBP_HD void stockham_bfly(const cplx<T>* src, cplx<T>* dst, int N, int Ns, int twstep,
-                          const cplx<T>* tw, int j) {
+                          const cplx<T>* tw, int j, int k) {
   const int NR = N / R;
-  const int k = j % Ns;
   cplx<T> v[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = src[j + r * NR];
@@ -142,6 +143,11 @@ CBP_HD void stockham_bfly(const cplx<T>* src, cplx<T>* dst, int N, int Ns, int t
 #pragma unroll
   for (int r = 0; r < R; ++r) dst[out + r * Ns] = v[r];
 }
+
+// q = floor(a / b) for 0 <= a < 2^22, 1 <= b <= 2^22, from a float
+// reciprocal: (a + 1/2) / b has fractional part in [1/(2b), 1 - 1/(2b)],
+// further from an integer than the product's rounding error (a / b) 2^-23.
+CBP_HD int fdiv_floor(int a, float rb) { return (int)(((float)a + 0.5f) * rb); }
 
 // ---------------------------------------------------------------- plans
 constexpr int FFT_MAX_PASSES = 16;
@@ -177,28 +183,34 @@ inline bool make_fft_plan(int N, fft_plan* p, int order = 0) {
   return r == 1;
 }
 
-// One pass over `nbatch` transforms stored at src + f*bstride (f < nbatch),
-// butterflies distributed over threads tid, tid+nthr, ...  Returns nothing;
-// the caller synchronises between passes.
-template <int DIR, typename T>
-CBP_HD void fft_pass(const cplx<T>* src, cplx<T>* dst, int N, int R, int Ns, const cplx<T>* tw,
-                     int nbatch, int bstride, int tid, int nthr) {
+// One pass of radix R over `nbatch` transforms stored at src + f*bstride
+// (f < nbatch), butterflies distributed over threads tid, tid+nthr, ...  The
+// caller synchronises between passes.
+template <int R, int DIR, typename T>
+CBP_HD void fft_pass_r(const cplx<T>* src, cplx<T>* dst, int N, int Ns, const cplx<T>* tw, int nbatch, int bstride,
+                       int tid, int nthr) {
   const int nb = N / R;
   const int total = nb * nbatch;
   const int twstep = N / (Ns * R);
+  const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns;
   for (int t = tid; t < total; t += nthr) {
-    const int f = t / nb;
+    const int f = nbatch == 1 ? 0 : fdiv_floor(t, rnb);
     const int j = t - f * nb;
-    const cplx<T>* s = src + (size_t)f * bstride;
-    cplx<T>* d = dst + (size_t)f * bstride;
-    switch (R) {
-      case 2: stockham_bfly<2, DIR>(s, d, N, Ns, twstep, tw, j); break;
-      case 3: stockham_bfly<3, DIR>(s, d, N, Ns, twstep, tw, j); break;
-      case 4: stockham_bfly<4, DIR>(s, d, N, Ns, twstep, tw, j); break;
-      case 5: stockham_bfly<5, DIR>(s, d, N, Ns, twstep, tw, j); break;
-      case 7: stockham_bfly<7, DIR>(s, d, N, Ns, twstep, tw, j); break;
-      default: stockham_bfly<8, DIR>(s, d, N, Ns, twstep, tw, j); break;
-    }
+    const int k = j - fdiv_floor(j, rns) * Ns;
+    stockham_bfly<R, DIR>(src + (size_t)f * bstride, dst + (size_t)f * bstride, N, Ns, twstep, tw, j, k);
+  }
+}
+
+template <int DIR, typename T>
+CBP_HD void fft_pass(const cplx<T>* src, cplx<T>* dst, int N, int R, int Ns, const cplx<T>* tw,
+                     int nbatch, int bstride, int tid, int nthr) {
+  switch (R) {
+    case 2: fft_pass_r<2, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
+    case 3: fft_pass_r<3, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
+    case 4: fft_pass_r<4, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
+    case 5: fft_pass_r<5, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
+    case 7: fft_pass_r<7, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
+    default: fft_pass_r<8, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
   }
 }
 

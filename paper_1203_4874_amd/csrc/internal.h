@@ -23,7 +23,7 @@ namespace cbp {
 // Work queues, one per kernel.
 enum queue_id {
   Q_DIAG = 0, Q_FOLD, Q_EVAL_COLS, Q_EVAL_ROWS, Q_ROW_FWD, Q_GRAM, Q_GRAMM, Q_SAMPLE, Q_FINALIZE, Q_COL,
-  Q_ROW_INV, Q_COUNT
+  Q_ROW_INV, Q_TWID, Q_COUNT
 };
 
 // Frames per batched launch (the item prefix sums of one launch sit in LDS).
@@ -40,7 +40,7 @@ struct frame_plan {
   int cw;                  // columns per workgroup in the column pass
   fft_plan fy, fx;
   size_t off_fpart, off_ex, off_ey, off_corr, off_xvec, off_lam0, off_pq, off_cbuf, off_kern,
-      off_t1, off_t2, off_u, off_feat, off_wts, off_kalt, total;
+      off_t1, off_t2, off_u, off_feat, off_wts, off_kalt, off_twxd, off_twx, off_twy, total;
 };
 
 // Everything a kernel needs about one frame (device pointers).
@@ -79,6 +79,11 @@ struct frame_desc {
   float* feat;
   double* wts;
   double* Kalt;   // the plain method's kernels (fallback of the learned form), 2 x CBP_MAX_K^2
+  // twiddle tables of the FFT grid, exp(-2 pi i t / P): FP64 over x (the
+  // kernels' row DFTs) and in the transform type over x and y
+  c64* twxd;
+  void* twx;
+  void* twy;
 };
 
 // Work items of each queue for one frame (the grid of a one-frame launch).
@@ -96,6 +101,7 @@ inline int queue_items(int q, const frame_plan& p) {
     case Q_FINALIZE: return 1;
     case Q_COL: return ((p.hx + p.cw - 1) / p.cw) * p.nch;
     case Q_ROW_INV: return ((p.m + 1) / 2) * p.nch;
+    case Q_TWID: return (p.Px + p.Py + 255) / 256;
   }
   return 0;
 }
@@ -204,6 +210,9 @@ template <typename T>
 hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st);
 template <typename T>
 hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t st);
+// the twiddle tables of every frame (items of Q_TWID; before the FFT passes)
+template <typename T>
+hipError_t launch_twiddles(const batch_ref& br, int grid, hipStream_t st);
 size_t row_lds_bytes(int N, int esize);
 size_t col_lds_bytes(int N, int cw, int esize);
 void set_recover_attrs();

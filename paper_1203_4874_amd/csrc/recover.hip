@@ -36,21 +36,27 @@ namespace {
 struct gram_acc {
   const cdd* rho;
   int k1, k2;
+  // Row i varies across lanes, column j is uniform: one index and two sign
+  // choices, no divergent branches.
   __device__ cdd get(int i, int j) const {
-    if (i < k2) {
-      if (j < k2) {
-        const int l = i - j;
-        return l >= 0 ? rho[l] : cdd_conj(rho[-l]);
-      }
-      const int q = j - k2;
-      return cdd_neg(rho[k2 + k1 + (i - q) + (k1 - 1)]);
+    const bool ia = i < k2, ja = j < k2;
+    const int lag = i - j;
+    const int cross = k2 + k1 + (k1 - 1);
+    int idx;
+    bool cj, ng;
+    if (ia == ja) {                      // G11 or G22: rho_aa(i - j), conj for negative lags
+      idx = (ia ? 0 : k2) + (lag < 0 ? -lag : lag);
+      cj = lag < 0;
+      ng = false;
+    } else {                             // G12 = -rho12(p - q), G21 = G12^H
+      idx = ia ? cross + i - (j - k2) : cross + j - (i - k2);
+      cj = !ia;
+      ng = true;
     }
-    const int p = i - k2;
-    if (j >= k2) {
-      const int l = p - (j - k2);
-      return l >= 0 ? rho[k2 + l] : cdd_conj(rho[k2 - l]);
-    }
-    return cdd_conj(cdd_neg(rho[k2 + k1 + (j - p) + (k1 - 1)]));
+    cdd v = rho[idx];
+    if (cj) v.im = dd_neg(v.im);
+    if (ng) v = cdd_neg(v);
+    return v;
   }
 };
 

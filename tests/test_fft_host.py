@@ -61,3 +61,27 @@ def test_radix_constants():
             if s is not None:
                 assert abs(mp.mpf(s) - mp.sin(2 * mp.pi * k / R)) < 1e-19
     assert abs(mp.mpf(vals["r2_2"]) - mp.sqrt(0.5)) < 1e-19
+
+
+def test_float_reciprocal_index_split_is_exact():
+    """fft_core.h splits t = f nb + j and j = q Ns + k with
+    floor((a + 1/2) * fl(1/b)) in FP32; exhaustive over every pass of every
+    7-smooth size up to 2048, with up to 16 transforms per launch."""
+    def smooth(n):
+        for p in (2, 3, 5, 7):
+            while n % p == 0:
+                n //= p
+        return n == 1
+    f32 = np.float32
+    for N in (n for n in range(2, 2049) if smooth(n)):
+        for R in (2, 3, 4, 5, 7, 8):
+            if N % R:
+                continue
+            nb = N // R
+            t = np.arange(nb * 16, dtype=np.int64)
+            q = ((t.astype(f32) + f32(0.5)) * (f32(1.0) / f32(nb))).astype(np.int64)
+            assert np.array_equal(q, t // nb), (N, R)
+            for Ns in {d for d in range(1, N + 1) if N % (d * R) == 0}:
+                j = np.arange(nb, dtype=np.int64)
+                q2 = ((j.astype(f32) + f32(0.5)) * (f32(1.0) / f32(Ns))).astype(np.int64)
+                assert np.array_equal(q2, j // Ns), (N, R, Ns)
