@@ -10,13 +10,14 @@
 //     8 rounds, leave a bracket [lo, hi] of width ~6e-15 ||T||.
 //  3. sigma = lo - 16 n eps ||T|| < lam0, so T - sigma I is positive
 //     definite with its smallest eigenvalue well separated from the rest; its
-//     LDL^T factors (d_k > 0) give inverse iteration on T at O(n) per solve,
-//     and the Householder reflectors (kept in the reduced matrix's strictly
-//     lower part) and the diagonal unitary map T's eigenvector y back to G's:
-//     x = Q D y.
+//     LDL^T factors (d_k > 0) give X = (T - sigma I)^{-1} explicitly (one
+//     column per lane), the Householder reflectors (kept in the reduced
+//     matrix's strictly lower part) and the diagonal unitary D give W = Q D
+//     explicitly (one column per lane), and inverse iteration runs on T:
+//     y <- X y, x = W y.
 //  4. Newton refinement against G held in double-double:
 //       r = G x - mu x (mu = x^H G x, both double-double),
-//       x <- (x - M r) / ||x - M r||,  M = Q D (T - sigma I)^{-1} D^H Q^H,
+//       x <- (x - M r) / ||x - M r||,  M = W X W^H = (G~ - sigma I)^{-1},
 //     until the correction is below 4e-15; M r approximates the exact Newton
 //     step sum_k v_k (v_k^H r) / (lam_k - mu) with relative error
 //     (mu - sigma) / (lam_k - sigma).
@@ -46,11 +47,13 @@ struct small_ws {
   double* a;    // n: diagonal of T
   double* b;    // n: off-diagonal of T, b[k] = T[k+1][k]
   dd* part;     // 4 x 64 x 2: partial double-double row sums of the refinement's product
+  c64* W;       // n x (n+1): W = Q D (row stride n + 1)
+  double* X;    // n x n: (T - sigma I)^{-1}, in the storage of A once W is built
 };
 
 __host__ __device__ inline size_t small_lds_bytes(int n) {
   return (size_t)n * n * sizeof(c64) + (size_t)n * (4 * sizeof(c64) + 2 * sizeof(double)) +
-         (size_t)4 * 64 * 2 * sizeof(dd) + 64;
+         (size_t)4 * 64 * 2 * sizeof(dd) + (size_t)n * (n + 1) * sizeof(c64) + 64;
 }
 
 __device__ inline small_ws small_carve(char* base, int n) {
@@ -63,7 +66,9 @@ __device__ inline small_ws small_carve(char* base, int n) {
   s.x = (c64*)p; p += n * sizeof(c64);
   s.a = (double*)p; p += n * sizeof(double);
   s.b = (double*)p; p += n * sizeof(double);
-  s.part = (dd*)p;
+  s.part = (dd*)p; p += (size_t)4 * 64 * 2 * sizeof(dd);
+  s.W = (c64*)p;
+  s.X = (double*)s.A;
   return s;
 }
 
@@ -155,27 +160,62 @@ __device__ inline void split_index(int e, int n, float rn, int& i, int& j) {
   else if (j < 0) { --i; j += n; }
 }
 
+// Lanes of a wave over an m-column (or m-row) operation with a reduction
+// along the other index: lane l serves column c = l mod m and the index
+// range [j0, j1) of group l / m (g groups; lanes of group >= g are idle), so
+// up to four lanes share a column's loop.  Partial results are combined in
+// group order, so the sums do not depend on timing.
+struct lane_split {
+  int c, grp, g, j0, j1;
+};
+
+__device__ inline lane_split split_lanes(int m) {
+  const int l = threadIdx.x;
+  lane_split r;
+  r.g = m <= 16 ? 4 : (m <= 21 ? 3 : (m <= 32 ? 2 : 1));
+  r.grp = (int)((float)l / (float)m);      // exact: l < 64, m <= 64
+  r.c = l - r.grp * m;
+  const int span = (m + r.g - 1) / r.g;
+  r.j0 = r.grp * span;
+  r.j1 = r.grp < r.g ? min(m, r.j0 + span) : r.j0;
+  return r;
+}
+
+// Sum of the g partial values part[grp * m + l] for lane l < m.
+__device__ inline c64 combine_parts(const c64* part, const lane_split& sp, int m) {
+  const int l = threadIdx.x;
+  c64 v = {0.0, 0.0};
+  if (l < m)
+    for (int gr = 0; gr < sp.g; ++gr) v = v + part[gr * m + l];
+  return v;
+}
+
 // ---------------------------------------------------------------- 1. tridiagonal
-// Householder reduction of s.A (destroyed); T in s.a, s.b.
+// Householder reduction of s.A (destroyed); T in s.a, s.b.  The trailing
+// block's product p = A' v and its rank-2 update run on split lanes (up to
+// four lanes per column), with the partial products combined through LDS.
 __device__ inline void small_tridiag(small_ws& s, int n) {
   const int l = threadIdx.x;
   c64* __restrict__ A = s.A;
   c64* __restrict__ V = s.w;
   c64* __restrict__ W = s.u;
+  c64* __restrict__ part = (c64*)s.part;
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
     const int o = k + 1;
+    const lane_split sp = split_lanes(m);
     c64 xl = {0.0, 0.0};
     if (l < m) xl = conj(A[k * n + o + l]);     // A[o+l][k]
-    const double s2 = wsum(norm2(xl));
     const double x0r = readlane_d(xl.re, 0), x0i = readlane_d(xl.im, 0);
     const double ax0sq = x0r * x0r + x0i * x0i;
     const double tail = wsum(l >= 1 ? norm2(xl) : 0.0);
     if (!(tail > 0.0)) {                        // column already reduced: reflector k = I
       if (l == 0) s.e[k] = {x0r, x0i};
       if (l < m) A[(size_t)(o + l) * n + k] = {0.0, 0.0};
+      __syncthreads();
       continue;
     }
+    const double s2 = ax0sq + tail;
     const double nx = s2 * rsq_nr(s2);
     const double ax0 = ax0sq > 0.0 ? ax0sq * rsq_nr(ax0sq) : 0.0;
     const c64 ph = ax0 > 0.0 ? c64{x0r / ax0, x0i / ax0} : c64{1.0, 0.0};
@@ -189,31 +229,33 @@ __device__ inline void small_tridiag(small_ws& s, int n) {
       A[(size_t)(o + l) * n + k] = vl;          // reflector k, kept for the back-transformation
     }
     __syncthreads();
-    // p = A' v (A' trailing m x m block; A'[l][j] = conj(A'[j][l]) read by column)
-    c64 p0 = {0.0, 0.0}, p1 = {0.0, 0.0};
-    if (l < m) {
-      const c64* col = A + (size_t)o * n + o + l;
-      int j = 0;
-      for (; j + 4 <= m; j += 4) {
+    // p = A' v (A' trailing m x m block; A'[c][j] = conj(A'[j][c]) read by column)
+    {
+      c64 p0 = {0.0, 0.0}, p1 = {0.0, 0.0};
+      const c64* col = A + (size_t)o * n + o + sp.c;
+      int j = sp.j0;
+      for (; j + 4 <= sp.j1; j += 4) {
         const c64 a0 = col[(size_t)j * n], a1 = col[(size_t)(j + 1) * n];
         const c64 a2 = col[(size_t)(j + 2) * n], a3 = col[(size_t)(j + 3) * n];
         const c64 v0 = V[j], v1 = V[j + 1], v2 = V[j + 2], v3 = V[j + 3];
         p0 = p0 + cmulc(a0, v0) + cmulc(a2, v2);
         p1 = p1 + cmulc(a1, v1) + cmulc(a3, v3);
       }
-      for (; j < m; ++j) p0 = p0 + cmulc(col[(size_t)j * n], V[j]);
+      for (; j < sp.j1; ++j) p0 = p0 + cmulc(col[(size_t)j * n], V[j]);
+      if (sp.grp < sp.g) part[l] = p0 + p1;
     }
-    const c64 pl = p0 + p1;
+    __syncthreads();
+    const c64 pl = combine_parts(part, sp, m);
     const double K = 0.5 * wsum(l < m ? (vl.re * pl.re + vl.im * pl.im) : 0.0);  // Re(v^H p) / 2
     const c64 wl = {pl.re - K * vl.re, pl.im - K * vl.im};
     if (l < m) W[l] = wl;
     __syncthreads();
-    // A' -= v w^H + w v^H   (lane l rewrites column l, four rows at a time)
-    if (l < m) {
-      const c64 cw = conj(wl), cv = conj(vl);
-      c64* col = A + (size_t)o * n + o + l;
-      int j = 0;
-      for (; j + 4 <= m; j += 4) {
+    // A' -= v w^H + w v^H   (lane (c, group) rewrites its rows of column c)
+    if (sp.grp < sp.g) {
+      const c64 cw = conj(W[sp.c]), cv = conj(V[sp.c]);
+      c64* col = A + (size_t)o * n + o + sp.c;
+      int j = sp.j0;
+      for (; j + 4 <= sp.j1; j += 4) {
         c64 a0 = col[(size_t)j * n], a1 = col[(size_t)(j + 1) * n];
         c64 a2 = col[(size_t)(j + 2) * n], a3 = col[(size_t)(j + 3) * n];
         const c64 v0 = V[j], v1 = V[j + 1], v2 = V[j + 2], v3 = V[j + 3];
@@ -227,7 +269,7 @@ __device__ inline void small_tridiag(small_ws& s, int n) {
         col[(size_t)(j + 2) * n] = a2;
         col[(size_t)(j + 3) * n] = a3;
       }
-      for (; j < m; ++j) {
+      for (; j < sp.j1; ++j) {
         const c64 a0 = col[(size_t)j * n];
         col[(size_t)j * n] = a0 - V[j] * cw - W[j] * cv;
       }
@@ -403,57 +445,50 @@ __device__ inline void tri_factor(small_ws& s, int n, double sigma, double pivmi
   __syncthreads();
 }
 
-// z = (T - sigma I)^{-1} r from the factors in s.w (lane k holds r_k and
-// receives z_k; lanes >= n hold zeros).  Forward L w = r and the diagonal
-// (w'_k = w_k / d_k, kept in s.u), then backward L^T z = w'.
-__device__ inline c64 tri_solve(small_ws& s, c64 r, int n) {
+// X = (T - sigma I)^{-1} (real symmetric) from the factors in s.w: lane j
+// solves for column j (forward L w = e_j, w'_k = w_k / d_k, backward
+// L^T z = w'), the factors being broadcast reads.  Overwrites s.A, so W
+// must be built first.
+__device__ inline void build_x(small_ws& s, int n) {
   const int l = threadIdx.x;
-  if (l < n) s.u[l] = r;
+  double* X = s.X;
   __syncthreads();
-  double wr = 0.0, wi = 0.0, lprev = 0.0;
-  for (int k0 = 0; k0 < n; k0 += 8) {
-    c64 rv[8], fv[8];
+  if (l < n) {
+    double w = 0.0, lprev = 0.0;
+    for (int k0 = 0; k0 < n; k0 += 8) {
+      c64 fv[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int k = k0 + t;
-      rv[t] = k < n ? s.u[k] : c64{0.0, 0.0};
-      fv[t] = k < n ? s.w[k] : c64{0.0, 0.0};
+      for (int t = 0; t < 8; ++t) fv[t] = k0 + t < n ? s.w[k0 + t] : c64{0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = k0 + t;
+        if (k < n) {
+          w = (k == l ? 1.0 : 0.0) - lprev * w;
+          lprev = fv[t].im;
+          X[(size_t)k * n + l] = w * fv[t].re;
+        }
+      }
     }
+    double z = 0.0;
+    for (int k1 = n - 1; k1 >= 0; k1 -= 8) {
+      double wv[8], lv[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int k = k0 + t;
-      if (k < n) {
-        wr = rv[t].re - lprev * wr;
-        wi = rv[t].im - lprev * wi;
-        lprev = fv[t].im;
-        if (l == 0) s.u[k] = {wr * fv[t].re, wi * fv[t].re};
+      for (int t = 0; t < 8; ++t) {
+        const int k = k1 - t;
+        wv[t] = k >= 0 ? X[(size_t)k * n + l] : 0.0;
+        lv[t] = (k >= 0 && k + 1 < n) ? s.w[k].im : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = k1 - t;
+        if (k >= 0) {
+          z = wv[t] - lv[t] * z;
+          X[(size_t)k * n + l] = z;
+        }
       }
     }
   }
   __syncthreads();
-  c64 z = {0.0, 0.0};
-  double zr = 0.0, zi = 0.0;
-  for (int k1 = n - 1; k1 >= 0; k1 -= 8) {
-    c64 wv[8], fv[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int k = k1 - t;
-      wv[t] = k >= 0 ? s.u[k] : c64{0.0, 0.0};
-      fv[t] = k >= 0 ? s.w[k] : c64{0.0, 0.0};
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int k = k1 - t;
-      if (k >= 0) {
-        const double lk = k + 1 < n ? fv[t].im : 0.0;
-        zr = wv[t].re - lk * zr;
-        zi = wv[t].im - lk * zi;
-        if (l == k) z = {zr, zi};
-      }
-    }
-  }
-  __syncthreads();
-  return z;
 }
 
 // Diagonal unitary D with D^H T_c D = T (T_c the complex tridiagonal with
@@ -475,27 +510,115 @@ __device__ inline c64 tri_phases(const small_ws& s, int n) {
   return ph;
 }
 
-// z <- Q z (adjoint: Q^H z) with Q = H_0 H_1 ... H_{n-3}, H_k = I - v_k v_k^H
-// (||v_k||^2 = 2 or v_k = 0), v_k kept in column k below the diagonal of s.A.
-// Lane l holds z_l.  The next reflector's entry is read ahead of the wave
-// reduction that the current one needs.
-__device__ inline c64 apply_reflectors(const small_ws& s, int n, c64 z, bool adjoint) {
+// W = Q D with Q = H_0 H_1 ... H_{n-3}, H_k = I - v_k v_k^H (||v_k||^2 = 2 or
+// v_k = 0; v_k kept in column k below the diagonal of s.A) and D the phases.
+// Built as H_0 (H_1 (... (H_{n-3} I))): H_k changes only rows and columns
+// k+1..n-1, W <- W - v_k (v_k^H W) there; the m = n-k-1 column dot products
+// and updates run on split lanes.
+__device__ inline void build_w(small_ws& s, int n, c64 ph) {
   const int l = threadIdx.x;
-  const int K = n - 2;
-  if (K <= 0) return z;
-  int k = adjoint ? 0 : K - 1;
-  const int dk = adjoint ? 1 : -1;
-  c64 v = (l > k && l < n) ? s.A[(size_t)l * n + k] : c64{0.0, 0.0};
-  for (int t = 0; t < K; ++t) {
-    const int kn = k + dk;
-    c64 vn = {0.0, 0.0};
-    if (t + 1 < K && l > kn && l < n) vn = s.A[(size_t)l * n + kn];
-    const c64 dot = wsum_c(cmulc(v, z));
-    z = z - v * dot;
-    v = vn;
-    k = kn;
+  const int ld = n + 1;
+  c64* __restrict__ Wm = s.W;
+  const c64* __restrict__ A = s.A;
+  c64* __restrict__ part = (c64*)s.part;
+  c64* __restrict__ dcol = s.u;
+  if (l < n)
+    for (int i = 0; i < n; ++i) Wm[(size_t)i * ld + l] = {i == l ? 1.0 : 0.0, 0.0};
+  __syncthreads();
+  for (int k = n - 3; k >= 0; --k) {
+    const int m = n - k - 1, o = k + 1;
+    const lane_split sp = split_lanes(m);
+    const c64* v = A + (size_t)o * n + k;          // v[j * n] = v_k[o + j]
+    c64* w = Wm + (size_t)o * ld + o + sp.c;       // w[j * ld] = W[o + j][o + c]
+    c64 d0 = {0.0, 0.0}, d1 = {0.0, 0.0};
+    int j = sp.j0;
+    for (; j + 4 <= sp.j1; j += 4) {
+      const c64 v0 = v[(size_t)j * n], v1 = v[(size_t)(j + 1) * n];
+      const c64 v2 = v[(size_t)(j + 2) * n], v3 = v[(size_t)(j + 3) * n];
+      const c64 w0 = w[(size_t)j * ld], w1 = w[(size_t)(j + 1) * ld];
+      const c64 w2 = w[(size_t)(j + 2) * ld], w3 = w[(size_t)(j + 3) * ld];
+      d0 = d0 + cmulc(v0, w0) + cmulc(v2, w2);
+      d1 = d1 + cmulc(v1, w1) + cmulc(v3, w3);
+    }
+    for (; j < sp.j1; ++j) d0 = d0 + cmulc(v[(size_t)j * n], w[(size_t)j * ld]);
+    if (sp.grp < sp.g) part[l] = d0 + d1;
+    __syncthreads();
+    const c64 dl = combine_parts(part, sp, m);
+    if (l < m) dcol[l] = dl;
+    __syncthreads();
+    if (sp.grp < sp.g) {
+      const c64 d = dcol[sp.c];
+      j = sp.j0;
+      for (; j + 4 <= sp.j1; j += 4) {
+        const c64 v0 = v[(size_t)j * n], v1 = v[(size_t)(j + 1) * n];
+        const c64 v2 = v[(size_t)(j + 2) * n], v3 = v[(size_t)(j + 3) * n];
+        const c64 w0 = w[(size_t)j * ld], w1 = w[(size_t)(j + 1) * ld];
+        const c64 w2 = w[(size_t)(j + 2) * ld], w3 = w[(size_t)(j + 3) * ld];
+        w[(size_t)j * ld] = w0 - v0 * d;
+        w[(size_t)(j + 1) * ld] = w1 - v1 * d;
+        w[(size_t)(j + 2) * ld] = w2 - v2 * d;
+        w[(size_t)(j + 3) * ld] = w3 - v3 * d;
+      }
+      for (; j < sp.j1; ++j) w[(size_t)j * ld] = w[(size_t)j * ld] - v[(size_t)j * n] * d;
+    }
+    __syncthreads();
   }
-  return z;
+  if (l < n)
+    for (int i = 0; i < n; ++i) Wm[(size_t)i * ld + l] = Wm[(size_t)i * ld + l] * ph;
+  __syncthreads();
+}
+
+// out_c = sum_{j < n} f(c, j) for lane c < n, on split lanes (f reads LDS).
+template <class F>
+__device__ inline c64 split_sum(small_ws& s, int n, F f) {
+  const int l = threadIdx.x;
+  const lane_split sp = split_lanes(n);
+  c64 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+  int j = sp.j0;
+  for (; j + 4 <= sp.j1; j += 4) {
+    const c64 f0 = f(sp.c, j), f1 = f(sp.c, j + 1), f2 = f(sp.c, j + 2), f3 = f(sp.c, j + 3);
+    a0 = a0 + f0 + f2;
+    a1 = a1 + f1 + f3;
+  }
+  for (; j < sp.j1; ++j) a0 = a0 + f(sp.c, j);
+  c64* part = (c64*)s.part;
+  if (sp.grp < sp.g) part[l] = a0 + a1;
+  __syncthreads();
+  const c64 r = combine_parts(part, sp, n);
+  __syncthreads();
+  return r;
+}
+
+// Products with W and X; the input vector is in LDS (b), lane l returns
+// entry l (zero for l >= n).
+__device__ inline c64 w_adj_mul(small_ws& s, int n, const c64* b) {   // W^H b
+  const int ld = n + 1;
+  const c64* Wm = s.W;
+  return split_sum(s, n, [&](int c, int i) __attribute__((always_inline)) {
+    return cmulc(Wm[(size_t)i * ld + c], b[i]);
+  });
+}
+
+__device__ inline c64 w_mul(small_ws& s, int n, const c64* b) {       // W b
+  const int ld = n + 1;
+  const c64* Wm = s.W;
+  return split_sum(s, n, [&](int c, int j) __attribute__((always_inline)) { return Wm[(size_t)c * ld + j] * b[j]; });
+}
+
+__device__ inline c64 x_mul(small_ws& s, int n, const c64* b) {       // X b (X symmetric)
+  const double* X = s.X;
+  return split_sum(s, n, [&](int c, int k) __attribute__((always_inline)) {
+    const double x = X[(size_t)k * n + c];
+    const c64 bk = b[k];
+    return c64{x * bk.re, x * bk.im};
+  });
+}
+
+// Stage lane values into b (LDS) for a product.
+__device__ inline void stage(c64* b, c64 v, int n) {
+  __syncthreads();
+  if ((int)threadIdx.x < n) b[threadIdx.x] = v;
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------- the solver
@@ -528,14 +651,18 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_lam
   const double pivmin = 1e-300 + 2.2e-16 * 2.2e-16 * tn;
   tri_factor(s, n, sigma, pivmin);
   const c64 ph = tri_phases(s, n);
-  // inverse iteration on T from a fixed, generic start vector
+  build_w(s, n, ph);
+  build_x(s, n);
+  // inverse iteration on T from a fixed, generic start vector, then x = W y
   c64 y = l < n ? c64{1.0 + 0.6180339887 * (double)((l * 7) % 11), 0.0} : c64{0.0, 0.0};
   for (int it = 0; it < SMALL_INVIT; ++it) {
-    y = tri_solve(s, y, n);
+    stage(s.u, y, n);
+    y = x_mul(s, n, s.u);
     const double nr = sqrt(wsum(norm2(y)));
     y = {y.re / nr, y.im / nr};
   }
-  c64 xl = apply_reflectors(s, n, ph * y, false);
+  stage(s.u, y, n);
+  c64 xl = w_mul(s, n, s.u);
   {
     const double nr = sqrt(wsum(l < n ? norm2(xl) : 0.0));
     xl = l < n ? c64{xl.re / nr, xl.im / nr} : c64{0.0, 0.0};
@@ -594,11 +721,13 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_lam
       qi.add_dd(yim); qi.add_prod(-mu.hi, xl.im); qi.add(-mu.lo * xl.im);
       r = {dd_val(qr.result()), dd_val(qi.result())};
     }
-    // correction c = Q D (T - sigma I)^{-1} D^H Q^H r
-    c64 z = apply_reflectors(s, n, r, true);
-    z = cmulc(ph, z);
-    z = tri_solve(s, z, n);
-    const c64 cl = apply_reflectors(s, n, ph * z, false);
+    // correction c = W X W^H r
+    stage(s.u, r, n);
+    const c64 t1 = w_adj_mul(s, n, s.u);
+    stage(s.u, t1, n);
+    const c64 t2 = x_mul(s, n, s.u);
+    stage(s.u, t2, n);
+    const c64 cl = w_mul(s, n, s.u);
     const c64 xn = l < n ? xl - cl : c64{0.0, 0.0};
     const double nrm = sqrt(wsum(norm2(xn)));
     const double dn = sqrt(wsum(l < n ? norm2(cl) : 0.0));

@@ -133,6 +133,7 @@ __global__ __launch_bounds__(64) void k_gram(batch_ref br) {
 // one wave each.
 __global__ __launch_bounds__(SMALL_NT) void k_sample(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_sample[];
+  __shared__ c64 twq[CBP_MAX_S];
   for_items<Q_SAMPLE>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const int k1 = d.k1, k2 = d.k2, S = d.S;
     const int N = k1 + k2, NL = 2 * N - 1;
@@ -162,6 +163,30 @@ __global__ __launch_bounds__(SMALL_NT) void k_sample(batch_ref br) {
         diag->sample_vec[pass][j][l][0] = xi.re;
         diag->sample_vec[pass][j][l][1] = xi.im;
       }
+    }
+    // the scale fix's cofactors evaluated on the other axis, this sample's
+    // share: pass X sample j gives P_c[.][j], pass Y sample i gives Q_c[i][.]
+    // (c = 0: the v part, k1 taps; c = 1: the u part, k2 taps)
+    if (l < S) {
+      double sn, cs;
+      sincospi(-2.0 * (double)l / (double)S, &sn, &cs);
+      twq[l] = {cs, sn};
+    }
+    __syncthreads();
+    if (l < 2 * S) {
+      const int c = l < S ? 0 : 1, f = l - c * S;
+      const c64* xs = c == 0 ? w.x + k2 : w.x;
+      const int len = c == 0 ? k1 : k2;
+      c64 acc = {0.0, 0.0};
+      int t = 0;
+      for (int x = 0; x < len; ++x) {
+        acc = acc + xs[x] * twq[t];
+        t += f;
+        if (t >= S) t -= S;
+      }
+      const size_t SS = (size_t)S * S;
+      if (pass == 0) d.pq[c * SS + (size_t)f * S + j] = acc;        // P_c[i = f][j]
+      else d.pq[(2 + c) * SS + (size_t)j * S + f] = acc;             // Q_c[i = j][jj = f]
     }
     const bool bad = wmax(l < N && !finite_c(xi) ? 1.0 : 0.0) > 0.0;
     if (d.feat) {
@@ -220,27 +245,11 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
   c64* kbuf = w.A;
   c64* tbuf = w.A + 2 * SS;
   unit_twiddles(tw, S);
-  __syncthreads();
-  // cofactors evaluated on the other axis: pq = [P1, P2, Q1, Q2], each [i][j]
-  for (int e = tid; e < 4 * SS; e += SMALL_NT) {
-    const int which = e / SS, ij = e - which * SS;
-    const int i = ij / S, jj = ij - i * S;
-    const c64* xs;
-    int len, f;
-    if (which == 0) { xs = xvec + ((size_t)jj) * N + k2; len = k1; f = i; }          // P1: v of pass X sample jj
-    else if (which == 1) { xs = xvec + ((size_t)jj) * N; len = k2; f = i; }          // P2: u of pass X sample jj
-    else if (which == 2) { xs = xvec + ((size_t)S + i) * N + k2; len = k1; f = jj; } // Q1: v of pass Y sample i
-    else { xs = xvec + ((size_t)S + i) * N; len = k2; f = jj; }                      // Q2: u of pass Y sample i
-    c64 acc = {0.0, 0.0};
-    int t = 0;
-    for (int x = 0; x < len; ++x) {
-      acc = acc + xs[x] * tw[t];
-      t += f;
-      if (t >= S) t -= S;
-    }
-    pq[e] = acc;
-  }
-  __threadfence_block();
+  // the cofactors evaluated on the other axis, pq = [P1, P2, Q1, Q2] (each
+  // [i][j], written by the sample solves), staged in the solver's W region
+  // (2S (2S + 1) >= 4 S^2 entries, free until the solve)
+  c64* pql = w.W;
+  for (int e = tid; e < 4 * SS; e += SMALL_NT) pql[e] = pq[e];
   __syncthreads();
   // H blocks in double-double
   for (int e = tid; e < SS; e += SMALL_NT) {
@@ -250,8 +259,8 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
     im.init();
     const double W = wts ? wts[jj] * wts[S + i] : 1.0;
     for (int c = 0; c < 2; ++c) {
-      c64 P = pq[(size_t)c * SS + i * S + jj];
-      const c64 Q = pq[(size_t)(2 + c) * SS + i * S + jj];
+      c64 P = pql[(size_t)c * SS + i * S + jj];
+      const c64 Q = pql[(size_t)(2 + c) * SS + i * S + jj];
       if (wts) P = {W * P.re, W * P.im};
       re.add_prod(-P.re, Q.re); re.add_prod(-P.im, Q.im);
       im.add_prod(-P.re, Q.im); im.add_prod(P.im, Q.re);
@@ -264,7 +273,7 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
     if (t < S) {
       for (int c = 0; c < 2; ++c)
         for (int i = 0; i < S; ++i) {
-          const c64 P = pq[(size_t)c * SS + i * S + t];
+          const c64 P = pql[(size_t)c * SS + i * S + t];
           const double W = wts ? wts[t] * wts[S + i] : 1.0;
           if (wts) { d.add_prod(W * P.re, P.re); d.add_prod(W * P.im, P.im); }
           else { d.add_prod(P.re, P.re); d.add_prod(P.im, P.im); }
@@ -274,7 +283,7 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
       const int i = t - S;
       for (int c = 0; c < 2; ++c)
         for (int jj = 0; jj < S; ++jj) {
-          const c64 Q = pq[(size_t)(2 + c) * SS + i * S + jj];
+          const c64 Q = pql[(size_t)(2 + c) * SS + i * S + jj];
           const double W = wts ? wts[jj] * wts[S + i] : 1.0;
           if (wts) { d.add_prod(W * Q.re, Q.re); d.add_prod(W * Q.im, Q.im); }
           else { d.add_prod(Q.re, Q.re); d.add_prod(Q.im, Q.im); }
@@ -334,7 +343,7 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
   if (wts) {
     if (diag)
       for (int t = tid; t <= n2; t += SMALL_NT) diag->sample_weights[t] = wts[t];
-    c64* xt = (c64*)((char*)sm_fin + fin_base_bytes(S));   // S^2 + 2 CBP_MAX_S extra entries
+    c64* xt = w.W;   // S^2 + 2 CBP_MAX_S entries from the solver's W onwards (free after the solve)
     learned_assembly(tw, S, k1, wts, Kh, tbuf, xt, K1, diag, 0);
     learned_assembly(tw, S, k2, wts, Kh + SS, tbuf, xt, K2, diag, 1);
     return;
@@ -611,8 +620,11 @@ __global__ void k_diag_init(batch_ref br) {
 
 size_t finalize_lds_bytes(int S, int learned) {
   const size_t base = fin_base_bytes(S);
-  // the learned assembly: T1 / Z1 (S^2) and the inversion's two vectors
-  return learned ? base + ((size_t)S * S + 2 * CBP_MAX_S) * sizeof(c64) : base;
+  // the learned assembly: T1 / Z1 (S^2) and the inversion's two vectors, from
+  // the solver's W (2S (2S + 1) entries, the last region of the solver's LDS)
+  const size_t need = ((size_t)S * S + 2 * CBP_MAX_S) * sizeof(c64);
+  const size_t have = (size_t)(2 * S) * (2 * S + 1) * sizeof(c64);
+  return learned && need > have ? base + (need - have) : base;
 }
 
 size_t sample_lds_bytes(int N) {
