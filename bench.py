@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--batch-frames", type=int, default=64,
                     help="frames of the 720p batching workload reported beside the headline (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--colour-frames", type=int, default=8,
+                    help="frames of the 1080p colour workload (one batch; 0 = skip)")
+    ap.add_argument("--colour-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (counter calibration runs)")
     return ap.parse_args()
@@ -162,12 +165,81 @@ def bench_batch(P, torch, dev, orc, args):
                 psnr_vs_truth_db_min=min(pt))
 
 
+def _colour_frame(f):
+    """One frame of the 1080p colour workload as FP32 frames (pool worker)."""
+    import synth
+    h = synth.config5_frame(f)
+    return dict(B1=h["B1"].astype(np.float32), B2=h["B2"].astype(np.float32), K1=h["K1"], K2=h["K2"],
+                L=h["L"].astype(np.float32), m=h["m"], n=h["n"], S=h["S"], lam=h["lam"])
+
+
+def bench_colour(P, torch, dev, orc, args, host, blob):
+    """Colour batching: one batch of 1080x1920 RGB frames (channels share one
+    kernel pair from the channel-summed Grams; per-channel division), one
+    15x15 / 17x17 pair, noise 5e-3, lambda 1e-4, FP32 frames, replayed as one
+    HIP graph; the plain mixed form and the learned form.  Per-batch latency
+    percentiles over repeated calls; accuracy on frame 0 against the truth
+    and the oracle's colour route."""
+    nf = len(host)
+    m, n = host[0]["m"], host[0]["n"]
+    frames = [(torch.as_tensor(h["B1"], device=dev), torch.as_tensor(h["B2"], device=dev), m, n) for h in host]
+    H = max(max(h["B1"].shape[1], h["B2"].shape[1]) for h in host)
+    W = max(max(h["B1"].shape[2], h["B2"].shape[2]) for h in host)
+    d = P.Deblurrer(H, W, H - m + 1, 3, nf, P.Precision.MIXED)
+    h0 = host[0]
+    Lo, R1, R2 = orc.deblur(h0["B1"].astype(np.float64), h0["B2"].astype(np.float64), m, n, 0, h0["lam"])
+    out = {}
+    for form, mlp in (("mixed", None), ("learned", blob)):
+        if form == "learned" and mlp is None:
+            continue
+        pb = d.prepare_batch(frames, lam=h0["lam"], flags=P.Flags.GRAPH, mlp=mlp)
+        for _ in range(2):
+            pb.run(check=False)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.colour_steps):
+            t0 = time.perf_counter()
+            pb.run(check=False)
+            torch.cuda.synchronize()
+            times.append(1e3 * (time.perf_counter() - t0))
+        ms = np.array(times)
+        p50 = float(np.percentile(ms, 50))
+        K1 = pb.K1s[0].cpu().numpy()
+        K2 = pb.K2s[0].cpu().numpy()
+        L = pb.latents[0].double().cpu().numpy()
+        kt = max(float(np.linalg.norm(K1 - h0["K1"]) / np.linalg.norm(h0["K1"])),
+                 float(np.linalg.norm(K2 - h0["K2"]) / np.linalg.norm(h0["K2"])))
+        ko = max(float(np.linalg.norm(K1 - R1) / np.linalg.norm(R1)),
+                 float(np.linalg.norm(K2 - R2) / np.linalg.norm(R2)))
+        out[form] = dict(value=nf * m * n / 1e6 / (p50 / 1e3), channel_value=3 * nf * m * n / 1e6 / (p50 / 1e3),
+                         ms_per_batch_p50=p50, ms_per_batch_p99=float(np.percentile(ms, 99)),
+                         kernel_rel_l2_vs_truth=kt, kernel_rel_l2_vs_plain_oracle=ko,
+                         psnr_vs_truth_db_min=min(psnr(L[c], h0["L"][c]) for c in range(3)),
+                         psnr_vs_plain_oracle_db_min=min(psnr(L[c], Lo[c]) for c in range(3)))
+        print(f"[bench] colour {form}: p50 {p50:.3f} ms per {nf}-frame batch", file=sys.stderr, flush=True)
+    return dict(workload=f"{nf} x 1080x1920 RGB frames (moving blobs, channel gains + texture), one coprime "
+                         "15x15/17x17 pair, noise 5e-3, lambda 1e-4, FP32 frames, batch of "
+                         f"{nf} as one HIP graph", metric="deblurred Mpixel/s (RGB pixel counted once)",
+                unit="Mpixel/s", forms=out, steps=args.colour_steps)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
+
+    colour_host = None
+    if args.colour_frames > 0:
+        # generated in forked workers before anything touches the GPU
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        t0 = time.perf_counter()
+        with ProcessPoolExecutor(max_workers=min(8, args.colour_frames), mp_context=mp.get_context("fork")) as ex:
+            colour_host = list(ex.map(_colour_frame, range(args.colour_frames)))
+        print(f"[bench] colour workload generated ({args.colour_frames} frames, {time.perf_counter() - t0:.1f} s)",
+              file=sys.stderr, flush=True)
 
     import torch
     import synth
@@ -181,9 +253,15 @@ def main():
     H2, W2 = c["B2"].shape
     k1, k2, S = c["K1"].shape[0], c["K2"].shape[0], c["S"]
 
+    blob = P.load_mlp(device=dev) if os.path.exists(P.WEIGHTS) else None
     forms = {}
     for name, npd, tdt, prec in (("mixed", np.float32, torch.float32, P.Precision.MIXED),
-                                 ("fp64", np.float64, torch.float64, P.Precision.FP64)):
+                                 ("fp64", np.float64, torch.float64, P.Precision.FP64),
+                                 ("mfma32", np.float32, torch.float32, P.Precision.MFMA32),
+                                 ("bf16", np.float32, torch.float32, P.Precision.BF16),
+                                 ("learned", np.float32, torch.float32, P.Precision.MIXED)):
+        if name == "learned" and blob is None:
+            continue
         B1 = c["B1"].astype(npd)
         B2 = c["B2"].astype(npd)
         b1 = torch.as_tensor(B1, device=dev)
@@ -192,10 +270,11 @@ def main():
         out = torch.empty((m, n), dtype=tdt, device=dev)
         K1 = torch.empty((k1, k1), dtype=torch.float64, device=dev)
         K2 = torch.empty((k2, k2), dtype=torch.float64, device=dev)
-        forms[name] = dict(B1=B1, B2=B2, b1=b1, b2=b2, d=d, out=out, K1=K1, K2=K2)
+        forms[name] = dict(B1=B1, B2=B2, b1=b1, b2=b2, d=d, out=out, K1=K1, K2=K2,
+                           mlp=blob if name == "learned" else None)
 
     def step(f):
-        f["d"].deblur(f["b1"], f["b2"], m, n, lam=lam, out=f["out"], K1=f["K1"], K2=f["K2"])
+        f["d"].deblur(f["b1"], f["b2"], m, n, lam=lam, out=f["out"], K1=f["K1"], K2=f["K2"], mlp=f["mlp"])
 
     results = {}
     for name, f in forms.items():
@@ -226,8 +305,10 @@ def main():
         L = f["out"].double().cpu().numpy()
         kr = float(np.linalg.norm(f["K1"].cpu().numpy() - R1) / np.linalg.norm(R1))
         kr2 = float(np.linalg.norm(f["K2"].cpu().numpy() - R2) / np.linalg.norm(R2))
+        kt = float(np.linalg.norm(f["K1"].cpu().numpy() - c["K1"]) / np.linalg.norm(c["K1"]))
+        kt2 = float(np.linalg.norm(f["K2"].cpu().numpy() - c["K2"]) / np.linalg.norm(c["K2"]))
         results[name].update(psnr_vs_oracle=psnr(L, Lo), psnr_vs_truth=psnr(L, c["L"]),
-                             kernel_rel_l2_vs_oracle=max(kr, kr2))
+                             kernel_rel_l2_vs_oracle=max(kr, kr2), kernel_rel_l2_vs_truth=max(kt, kt2))
 
     mpix = m * n / 1e6
     main_form = results["mixed"]
@@ -302,9 +383,36 @@ def main():
         cpu = dict(value=reps * mpix / el, unit="Mpixel/s", cores=int(threads), kind="oracle",
                    sample=f"{reps} repetitions of the same 480x640 frame (FP64 NumPy/SciPy oracle, {el:.1f} s)")
 
+    # PCIe-inclusive rate of the headline form: frames from pinned host
+    # memory, the latent back to pinned host memory, in every step
+    f = forms["mixed"]
+    h1 = torch.from_numpy(np.ascontiguousarray(f["B1"])).pin_memory()
+    h2 = torch.from_numpy(np.ascontiguousarray(f["B2"])).pin_memory()
+    hL = torch.empty((m, n), dtype=torch.float32).pin_memory()
+
+    def pstep():
+        f["b1"].copy_(h1, non_blocking=True)
+        f["b2"].copy_(h2, non_blocking=True)
+        step(f)
+        hL.copy_(f["out"], non_blocking=True)
+
+    for _ in range(args.warmup):
+        pstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pstep()
+    torch.cuda.synchronize()
+    pms = 1e3 * (time.perf_counter() - t0) / args.steps
+    pcie = dict(value=mpix / (pms / 1e3), unit="Mpixel/s", ms_per_step=pms,
+                note="frames H2D from pinned host memory and the latent D2H, inside every step")
+
     batched = None
     if args.batch_frames > 0:
         batched = bench_batch(P, torch, dev, orc, args)
+    colour = None
+    if colour_host:
+        colour = bench_colour(P, torch, dev, orc, args, colour_host, blob)
 
     if args.copy_calibration:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
@@ -339,7 +447,21 @@ def main():
                        "psnr_vs_oracle_db": results["fp64"]["psnr_vs_oracle"],
                        "kernel_rel_l2_vs_oracle": results["fp64"]["kernel_rel_l2_vs_oracle"],
                        "phases_us": results["fp64"]["phases_us"]},
+        "precision_forms": {k: {"value": mpix / (results[k]["ms"] / 1e3), "ms_per_step": results[k]["ms"],
+                                "psnr_vs_oracle_db": results[k]["psnr_vs_oracle"],
+                                "kernel_rel_l2_vs_oracle": results[k]["kernel_rel_l2_vs_oracle"],
+                                "phases_us": results[k]["phases_us"]}
+                            for k in ("mfma32", "bf16")},
+        "learned": None if "learned" not in results else {
+            "value": mpix / (results["learned"]["ms"] / 1e3), "ms_per_step": results["learned"]["ms"],
+            "kernel_rel_l2_vs_truth": results["learned"]["kernel_rel_l2_vs_truth"],
+            "plain_kernel_rel_l2_vs_truth": results["mixed"]["kernel_rel_l2_vs_truth"],
+            "psnr_vs_truth_db": results["learned"]["psnr_vs_truth"],
+            "plain_psnr_vs_truth_db": results["mixed"]["psnr_vs_truth"],
+            "phases_us": results["learned"]["phases_us"]},
+        "pcie_inclusive": pcie,
         "batched_720p": batched,
+        "colour_1080p": colour,
     }
     print(json.dumps(line))
 

@@ -163,12 +163,19 @@ def sample_cofactors(E1: np.ndarray, E2: np.ndarray, k1: int, k2: int, fmt=None)
     matrix-core forms round them (round_operands); the null vector is then
     exact for those operands.
     """
-    S = E1.shape[0]
+    E1 = np.asarray(E1)
+    E2 = np.asarray(E2)
+    if E1.ndim == 2:                       # one channel
+        E1, E2 = E1[None], E2[None]
+    S = E1.shape[1]
     U = np.zeros((S, k2), dtype=np.complex128)
     V = np.zeros((S, k1), dtype=np.complex128)
     spec = np.zeros((S, k1 + k2))
     for j in range(S):
-        A = sample_matrix(round_operands(E1[j], fmt), round_operands(E2[j], fmt), k1, k2)
+        # colour frames share one kernel pair: the channels' sample matrices
+        # are stacked, so the Gram is the sum of the channels' Grams
+        A = np.vstack([sample_matrix(round_operands(E1[c, j], fmt), round_operands(E2[c, j], fmt), k1, k2)
+                       for c in range(E1.shape[0])])
         x, sp = null_vector(A)
         U[j], V[j], spec[j] = x[:k2], x[k2:], sp
     return U, V, spec
@@ -264,9 +271,12 @@ def assemble_kernel(Pc, Qc, a, b, k: int):
 
 def deconvolve(B1, B2, K1, K2, m: int, n: int, lam: float = 0.0):
     """L = crop_{m x n} IFFT2( (conj Kh1 Bh1 + conj Kh2 Bh2) / (|Kh1|^2+|Kh2|^2+lam) )
-    on the Py x Px grid, Py = smooth7(max H_c), Px = smooth7(max W_c)."""
+    on the Py x Px grid, Py = smooth7(max H_c), Px = smooth7(max W_c).
+    Colour frames ([channel][y][x]) are divided channel by channel."""
     B1 = np.asarray(B1, dtype=np.float64)
     B2 = np.asarray(B2, dtype=np.float64)
+    if B1.ndim == 3:
+        return np.stack([deconvolve(B1[c], B2[c], K1, K2, m, n, lam) for c in range(B1.shape[0])])
     Py = smooth7(max(B1.shape[0], B2.shape[0]))
     Px = smooth7(max(B1.shape[1], B2.shape[1]))
     s = (Py, Px)
@@ -284,12 +294,22 @@ def recover_kernels(B1, B2, m: int, n: int, S: int = 0, full: bool = False, gram
     """Kernels K1, K2 from the blurred pair (O1-O6).  With ``full`` also
     returns every intermediate in a dict.  gram_fmt ("f32" / "bf16") rounds
     the per-sample operands as the matrix-core precision forms do."""
-    k1, k2 = kernel_sizes(B1.shape, B2.shape, m, n)
+    B1 = np.asarray(B1)
+    B2 = np.asarray(B2)
+    k1, k2 = kernel_sizes(B1.shape[-2:], B2.shape[-2:], m, n)
     S = S or max(k1, k2)
     if S < max(k1, k2):
         raise ValueError("S must be >= max kernel size")
-    EX1, EY1 = unit_circle_eval(B1, S)
-    EX2, EY2 = unit_circle_eval(B2, S)
+    if B1.ndim == 3:
+        # colour frames [channel][y][x]: every channel evaluated; the samples'
+        # null vectors come from the channels' stacked sample matrices
+        ev1 = [unit_circle_eval(B1[c], S) for c in range(B1.shape[0])]
+        ev2 = [unit_circle_eval(B2[c], S) for c in range(B2.shape[0])]
+        EX1, EY1 = np.stack([e[0] for e in ev1]), np.stack([e[1] for e in ev1])
+        EX2, EY2 = np.stack([e[0] for e in ev2]), np.stack([e[1] for e in ev2])
+    else:
+        EX1, EY1 = unit_circle_eval(B1, S)
+        EX2, EY2 = unit_circle_eval(B2, S)
     XU, XV, Xspec = sample_cofactors(EX1, EX2, k1, k2, gram_fmt)
     YU, YV, Yspec = sample_cofactors(EY1, EY2, k1, k2, gram_fmt)
     P, Q = cofactor_grids(XU, XV, YU, YV, S)

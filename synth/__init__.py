@@ -253,3 +253,44 @@ def config3_frames(seed: int = 1003, nframes: int = 64, m: int = 720, n: int = 1
         yield dict(L=L, K1=K1, K2=K2, B1=B1, B2=B2, m=m, n=n,
                    S=int(max(k1, k2)), lam=1e-4, noise=noise)
 
+
+
+def blob_frame(seed: int, f: int, m: int, n: int, blobs: int = 30, max_shift: int = 4):
+    """Frame f of ``blob_sequence`` alone (the random walk is advanced without
+    rendering the frames before it), so frames can be made independently."""
+    r = rng_for(seed, 0)
+    bg = gaussian_scene(r, m, n)
+    cy = r.uniform(0, m, blobs)
+    cx = r.uniform(0, n, blobs)
+    rad = r.uniform(8, 40, blobs)
+    amp = r.uniform(-0.5, 0.5, blobs)
+    for g in range(1, f + 1):
+        rf = rng_for(seed, 1, g)
+        cy = np.clip(cy + rf.integers(-max_shift, max_shift + 1, blobs), 0, m - 1)
+        cx = np.clip(cx + rf.integers(-max_shift, max_shift + 1, blobs), 0, n - 1)
+    yy, xx = np.mgrid[0:m, 0:n].astype(np.float64)
+    img = bg.copy()
+    for b in range(blobs):
+        img += amp[b] * np.exp(-((yy - cy[b]) ** 2 + (xx - cx[b]) ** 2) / (2 * rad[b] ** 2))
+    return np.clip(img, 0.0, 1.0)
+
+
+def config5_frame(f: int, seed: int = 1005, m: int = 1080, n: int = 1920, noise: float = 5e-3,
+                  k1: int = 15, k2: int = 17):
+    """Frame f of the 1080p colour workload, [channel][y][x]: the moving-blob
+    scene scaled by a per-channel gain U(0.6, 1.0) plus 0.05 U[0,1) texture
+    per channel, one coprime 15x15 / 17x17 pair (U(0,1) entries, sum 1) for
+    every frame, additive N(0, noise^2) per channel and stream."""
+    K1, K2 = draw_coprime_pair(rng_for(seed, 5), k1, k2, "uniform")
+    gains = rng_for(seed, 6).uniform(0.6, 1.0, 3)
+    L = blob_frame(seed, f, m, n)
+    Ls = np.stack([g * L + 0.05 * rng_for(seed, 7, f, c).random((m, n)) for c, g in enumerate(gains)])
+    B = [blur_pair(rng_for(seed, 8, f, c), Ls[c], K1, K2, noise) for c in range(3)]
+    return dict(L=Ls, K1=K1, K2=K2, B1=np.stack([b[0] for b in B]), B2=np.stack([b[1] for b in B]),
+                m=m, n=n, S=max(k1, k2), lam=1e-4, noise=noise)
+
+
+def config5_frames(seed: int = 1005, nframes: int = 8, **kw):
+    """Frames 0..nframes-1 of the 1080p colour workload (config5_frame)."""
+    for f in range(nframes):
+        yield config5_frame(f, seed, **kw)
