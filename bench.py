@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--colour-frames", type=int, default=8,
                     help="frames of the 1080p colour workload (one batch; 0 = skip)")
     ap.add_argument("--colour-steps", type=int, default=20)
+    ap.add_argument("--forms", default="mixed,fp64,mfma32,bf16,learned",
+                    help="comma-separated forms of the single-frame workload (mixed is always run)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (counter calibration runs)")
     return ap.parse_args()
@@ -262,6 +264,8 @@ def main():
                                  ("learned", np.float32, torch.float32, P.Precision.MIXED)):
         if name == "learned" and blob is None:
             continue
+        if name != "mixed" and name not in args.forms.split(","):
+            continue
         B1 = c["B1"].astype(npd)
         B2 = c["B2"].astype(npd)
         b1 = torch.as_tensor(B1, device=dev)
@@ -443,15 +447,16 @@ def main():
         "kernel_rel_l2_vs_oracle": main_form["kernel_rel_l2_vs_oracle"],
         "phases_us": main_form["phases_us"],
         "phases_roofline": kern_roof,
-        "plain_fp64": {"value": mpix / (results["fp64"]["ms"] / 1e3), "ms_per_step": results["fp64"]["ms"],
-                       "psnr_vs_oracle_db": results["fp64"]["psnr_vs_oracle"],
-                       "kernel_rel_l2_vs_oracle": results["fp64"]["kernel_rel_l2_vs_oracle"],
-                       "phases_us": results["fp64"]["phases_us"]},
+        "plain_fp64": None if "fp64" not in results else {
+            "value": mpix / (results["fp64"]["ms"] / 1e3), "ms_per_step": results["fp64"]["ms"],
+            "psnr_vs_oracle_db": results["fp64"]["psnr_vs_oracle"],
+            "kernel_rel_l2_vs_oracle": results["fp64"]["kernel_rel_l2_vs_oracle"],
+            "phases_us": results["fp64"]["phases_us"]},
         "precision_forms": {k: {"value": mpix / (results[k]["ms"] / 1e3), "ms_per_step": results[k]["ms"],
                                 "psnr_vs_oracle_db": results[k]["psnr_vs_oracle"],
                                 "kernel_rel_l2_vs_oracle": results[k]["kernel_rel_l2_vs_oracle"],
                                 "phases_us": results[k]["phases_us"]}
-                            for k in ("mfma32", "bf16")},
+                            for k in ("mfma32", "bf16") if k in results},
         "learned": None if "learned" not in results else {
             "value": mpix / (results["learned"]["ms"] / 1e3), "ms_per_step": results["learned"]["ms"],
             "kernel_rel_l2_vs_truth": results["learned"]["kernel_rel_l2_vs_truth"],
