@@ -115,48 +115,47 @@ __global__ __launch_bounds__(256) void k_eval_cols(batch_ref br) {
   });
 }
 
-// Row fold and S-point DFT: one wave per row; lane l folds the chunks
-// x in [q S, q S + S), q = l, l + 64, ...; wave reductions sum the lanes.
+// Row fold and S-point DFT: one wave per row.  With G = floor(64 / S) lane
+// groups, lane l = g S + r (g < G) sums the row entries x = r + S (g + G i),
+// i = 0, 1, ... in order; residue r is then the sum of its G partials in
+// group order.  k_row_fwd folds the rows it holds with the same lanes and
+// the same order, so both give the same bits.
 // Items: (block of 4 rows, cf).
 template <typename T>
 __global__ __launch_bounds__(256) void k_eval_rows(batch_ref br) {
+  __shared__ double part[4][64];
   __shared__ double g[4][CBP_MAX_S];
   __shared__ c64 tw[CBP_MAX_S];
   for_items<Q_EVAL_ROWS>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const int ny = (d.Hmax + 3) / 4;
     const int by = item % ny, cf = item / ny;
-    const int S = d.S;
+    const int S = d.S, G = 64 / S;
     const T* b;
     int64_t pitch;
     int H, W;
     pick(d, cf, b, pitch, H, W);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int y = by * 4 + w;
+    const int gl = l / S, r = l - gl * S;
     unit_twiddles(tw, S);
-    double acc[CBP_MAX_S];
-#pragma unroll
-    for (int r = 0; r < CBP_MAX_S; ++r) acc[r] = 0.0;
-    if (y < H) {
+    double acc = 0.0;
+    if (y < H && gl < G) {
       const T* row = b + (int64_t)y * pitch;
-      for (int x0 = l * S; x0 < W; x0 += 64 * S) {
-#pragma unroll
-        for (int r = 0; r < CBP_MAX_S; ++r)
-          if (r < S && x0 + r < W) acc[r] += (double)row[x0 + r];
-      }
+      for (int x = r + S * gl; x < W; x += S * G) acc += (double)row[x];
     }
-#pragma unroll
-    for (int r = 0; r < CBP_MAX_S; ++r) {
-      if (r < S) {
-        const double s = wsum(acc[r]);
-        if (l == 0) g[w][r] = s;
-      }
+    part[w][l] = acc;
+    __syncthreads();
+    if (l < S) {
+      double sr = part[w][l];
+      for (int q = 1; q < G; ++q) sr += part[w][q * S + l];
+      g[w][l] = sr;
     }
     __syncthreads();
     if (y < H && l < S) {
       c64 e = {0.0, 0.0};
       int t = 0;
-      for (int r = 0; r < S; ++r) {
-        const double f = g[w][r];
+      for (int rr = 0; rr < S; ++rr) {
+        const double f = g[w][rr];
         e.re += f * tw[t].re;
         e.im += f * tw[t].im;
         t += l;

@@ -62,7 +62,7 @@ __device__ __attribute__((always_inline)) inline cplx<T>* fft_lds(cplx<T>* a, cp
   cplx<T>* dst = b;
   int Ns = 1;
   for (int s = 0; s < p.npass; ++s) {
-    const int R = p.radix[s];
+    const int R = plan_radix(p, s);
     fft_pass<DIR>(src, dst, p.N, R, Ns, tw, nbatch, bstride, threadIdx.x, blockDim.x);
     __syncthreads();
     cplx<T>* t = src;
@@ -82,6 +82,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
   extern __shared__ __attribute__((aligned(16))) char sm_rf[];
   __shared__ double gy[2][CBP_MAX_S];
+  __shared__ double fpart_l[2][64];
   __shared__ c64 twS[CBP_MAX_S];
   for_items<Q_ROW_FWD>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const fft_plan& px = d.fx;
@@ -107,33 +108,32 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
     }
     __syncthreads();
     if (with_ey) {
-      const int S = d.S;
+      // the row evaluation of both rows (k_eval_rows's lanes and order):
+      // wave fr folds frame fr's row into partials, lane g S + r summing
+      // x = r + S (g + G i); the residues then add their G partials in order
+      const int S = d.S, G = 64 / S;
       const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-      const int fr = wv & 1, par = wv >> 1;
-      const int W = fr ? d.W2 : d.W1;
-      double acc[CBP_MAX_S];
-#pragma unroll
-      for (int r = 0; r < CBP_MAX_S; ++r) acc[r] = 0.0;
-      if (fr ? in2 : in1) {
-        for (int x0 = l * S; x0 < W; x0 += 64 * S) {
-#pragma unroll
-          for (int r = 0; r < CBP_MAX_S; ++r)
-            if (r < S && (r & 1) == par && x0 + r < W) acc[r] += (double)(fr ? a[x0 + r].im : a[x0 + r].re);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < CBP_MAX_S; ++r) {
-        if (r < S && (r & 1) == par) {
-          const double sr = wsum(acc[r]);
-          if (l == 0) gy[fr][r] = sr;
-        }
+      const int gl = l / S, r = l - gl * S;
+      if (wv < 2) {
+        const int W = wv ? d.W2 : d.W1;
+        double acc = 0.0;
+        if ((wv ? in2 : in1) && gl < G)
+          for (int x = r + S * gl; x < W; x += S * G) acc += (double)(wv ? a[x].im : a[x].re);
+        fpart_l[wv][l] = acc;
       }
       __syncthreads();
-      if (wv < 2 && l < S && (fr ? in2 : in1)) {
+      if (wv < 2 && l < S) {
+        double sr = fpart_l[wv][l];
+        for (int q = 1; q < G; ++q) sr += fpart_l[wv][q * S + l];
+        gy[wv][l] = sr;
+      }
+      __syncthreads();
+      if (wv < 2 && l < S && (wv ? in2 : in1)) {
+        const int fr = wv;
         c64 e = {0.0, 0.0};
         int t = 0;
-        for (int r = 0; r < S; ++r) {
-          const double f = gy[fr][r];
+        for (int rr = 0; rr < S; ++rr) {
+          const double f = gy[fr][rr];
           e.re += f * twS[t].re;
           e.im += f * twS[t].im;
           t += l;

@@ -156,7 +156,10 @@ struct fft_plan {
   int N;
   int npass;
   int radix[FFT_MAX_PASSES];
+  unsigned long long code;  // radix of pass s in bits [4s, 4s + 4) (device code reads this, no array index)
 };
+
+CBP_HD int plan_radix(const fft_plan& p, int s) { return (int)((p.code >> (4 * s)) & 15u); }
 
 // Factor N into the supported radices.  `order` picks the pass order:
 //   0: radix 8 first, then 4, 2, 3, 5, 7 (fewest passes);
@@ -171,11 +174,13 @@ inline bool make_fft_plan(int N, fft_plan* p, int order = 0) {
   if (N < 1 || order < 0 || order >= FFT_ORDERS) return false;
   p->N = N;
   p->npass = 0;
+  p->code = 0;
   int r = N;
   for (int t = 0; t < 6; ++t) {
     const int R = orders[order][t];
     while (r % R == 0) {
       if (p->npass >= FFT_MAX_PASSES) return false;
+      p->code |= (unsigned long long)R << (4 * p->npass);
       p->radix[p->npass++] = R;
       r /= R;
     }

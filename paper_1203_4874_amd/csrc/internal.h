@@ -143,7 +143,10 @@ __device__ inline void for_items(const batch_ref& br, F&& body) {
   for (int t = threadIdx.x; t <= nf; t += blockDim.x) st[t] = s[t];
   __syncthreads();
   int first, end, step;
-  xcd_items(st[nf], first, end, step);
+  xcd_items(__builtin_amdgcn_readfirstlane(st[nf]), first, end, step);
+  // descriptors are read-only while kernels run: reading them through the
+  // constant address space with a wave-uniform index lets the scalar unit
+  // load them into SGPRs
   for (int it = first; it < end; it += step) {
     int lo = 0, hi = nf;  // st[lo] <= it < st[hi]
     while (hi - lo > 1) {
@@ -151,7 +154,15 @@ __device__ inline void for_items(const batch_ref& br, F&& body) {
       if (st[mid] <= it) lo = mid;
       else hi = mid;
     }
-    body(br.descs[lo], it - st[lo]);
+    const int fi = __builtin_amdgcn_readfirstlane(lo);
+    const int base = __builtin_amdgcn_readfirstlane(st[fi]);
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) frame_desc cdesc;
+    const frame_desc d = ((const cdesc*)br.descs)[fi];
+#else
+    const frame_desc d = br.descs[fi];
+#endif
+    body(d, it - base);
     __syncthreads();
   }
 }

@@ -98,10 +98,15 @@ __global__ __launch_bounds__(64) void k_gram(batch_ref br) {
     if (li < k2) { fa = 0; fb = 0; l = li; }
     else if (li < k2 + k1) { fa = 1; fb = 1; l = li - k2; }
     else { fa = 0; fb = 1; l = li - (k1 + k2) - (k1 - 1); }
-    const int la = pass == 0 ? (fa ? d.W2 : d.W1) : (fa ? d.H2 : d.H1);
-    const int lb = pass == 0 ? (fb ? d.W2 : d.W1) : (fb ? d.H2 : d.H1);
-    const int stride = pass == 0 ? d.Wmax : d.Hmax;
-    const c64* base = pass == 0 ? d.ex : d.ey;
+    // fields into locals first: a select between fields would select between
+    // their addresses and keep the descriptor copy out of registers
+    const int W1 = d.W1, W2 = d.W2, H1 = d.H1, H2 = d.H2, Wmax = d.Wmax, Hmax = d.Hmax;
+    const c64* ex = d.ex;
+    const c64* ey = d.ey;
+    const int la = pass == 0 ? (fa ? W2 : W1) : (fa ? H2 : H1);
+    const int lb = pass == 0 ? (fb ? W2 : W1) : (fb ? H2 : H1);
+    const int stride = pass == 0 ? Wmax : Hmax;
+    const c64* base = pass == 0 ? ex : ey;
     const int t0 = max(0, -l), t1 = min(la, lb - l);
     dot2 sre, sim;
     sre.init();

@@ -26,9 +26,9 @@ int main() {
   cplx<double>* dst = b.data();
   int Ns = 1;
   for (int s = 0; s < p.npass; ++s) {
-    if (dir < 0) fft_pass<-1>(src, dst, N, p.radix[s], Ns, tw.data(), 1, N, 0, 1);
-    else fft_pass<+1>(src, dst, N, p.radix[s], Ns, tw.data(), 1, N, 0, 1);
-    Ns *= p.radix[s];
+    if (dir < 0) fft_pass<-1>(src, dst, N, plan_radix(p, s), Ns, tw.data(), 1, N, 0, 1);
+    else fft_pass<+1>(src, dst, N, plan_radix(p, s), Ns, tw.data(), 1, N, 0, 1);
+    Ns *= plan_radix(p, s);
     cplx<double>* t = src; src = dst; dst = t;
   }
   for (int i = 0; i < N; ++i) std::printf("%.17g %.17g\n", src[i].re, src[i].im);
