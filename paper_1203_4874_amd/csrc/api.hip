@@ -117,8 +117,12 @@ struct tuning {
 };
 constexpr tuning kDefaultTuning = {32, 0, 0, 0};
 
+// Columns per column-pass strip: a power of two (the kernel splits indices
+// with shifts), at most 8.
 int choose_cw(int Py, int hx, int esize, int want) {
   int cw = want > 0 ? want : 4;
+  if (cw > 8) cw = 8;
+  while (cw & (cw - 1)) cw &= cw - 1;
   while (cw > 1 && (col_lds_bytes(Py, cw, esize) > kLdsLimit - 4096 || (want <= 0 && (hx + cw - 1) / cw < 128)))
     cw >>= 1;
   return cw;

@@ -181,8 +181,9 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
     load_twiddles(tw, d.twy, N);
     // load: element (y, f) with f = 2*col + frame; consecutive threads walk f
     // (adjacent columns of one row) for coalescing
+    const int lnf = __builtin_ctz(nf);         // cw, hence nf, is a power of two
     for (int e = threadIdx.x; e < nf * N; e += blockDim.x) {
-      const int y = e / nf, f = e - y * nf;
+      const int y = e >> lnf, f = e & (nf - 1);
       const int col = kx0 + (f >> 1);
       const int fr = f & 1;
       cplx<T> val = {T(0), T(0)};
@@ -217,19 +218,19 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
     cplx<T>* f1 = fft_lds<-1>(a, b, py, tw, nf, N);
     cplx<T>* f2 = (f1 == a) ? b : a;
     // filter: combined spectrum written into the frame-1 slot of each column
+    const float rN = 1.0f / (float)N;
+    const int kmax = k1 > k2 ? k1 : k2;
     for (int e = threadIdx.x; e < cw * N; e += blockDim.x) {
-      const int c = e / N, ky = e - c * N;
-      cplx<T> kh1 = {T(0), T(0)}, kh2 = {T(0), T(0)};
-      int t = 0;
+      const int c = fdiv_floor(e, rN), ky = e - c * N;
+      // kernel spectra at (ky, kx): sum_yy kr[yy] z^yy, z = exp(-2 pi i ky / Py),
+      // by Horner's rule (kr is zero beyond each kernel's size)
       const cplx<T>* kr1 = kr + (size_t)c * 2 * CBP_MAX_K;
       const cplx<T>* kr2 = kr1 + CBP_MAX_K;
-      const int kmax = k1 > k2 ? k1 : k2;
-      for (int yy = 0; yy < kmax; ++yy) {
-        const cplx<T> w = tw[t];
-        if (yy < k1) kh1 = kh1 + kr1[yy] * w;
-        if (yy < k2) kh2 = kh2 + kr2[yy] * w;
-        t += ky;
-        if (t >= N) t -= N;
+      const cplx<T> z = tw[ky];
+      cplx<T> kh1 = kr1[kmax - 1], kh2 = kr2[kmax - 1];
+      for (int yy = kmax - 2; yy >= 0; --yy) {
+        kh1 = kh1 * z + kr1[yy];
+        kh2 = kh2 * z + kr2[yy];
       }
       const cplx<T> B1 = f1[(size_t)(2 * c) * N + ky];
       const cplx<T> B2 = f1[(size_t)(2 * c + 1) * N + ky];
@@ -242,8 +243,9 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
     // inverse column FFT of the cw combined spectra (slots 0, 2, 4, ...)
     const cplx<T>* r = fft_lds<+1>(f1, f2, py, tw, cw, 2 * N);
     cplx<T>* uo = (cplx<T>*)d.u + (int64_t)ch * m * hx;
+    const int lcw = __builtin_ctz(cw);
     for (int e = threadIdx.x; e < m * cw; e += blockDim.x) {
-      const int y = e / cw, c = e - y * cw;
+      const int y = e >> lcw, c = e & (cw - 1);
       const int col = kx0 + c;
       if (col < hx) uo[(int64_t)y * hx + col] = r[(size_t)(2 * c) * N + y];
     }
