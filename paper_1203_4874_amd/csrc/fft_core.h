@@ -120,28 +120,38 @@ CBP_HD void dft_small(cplx<T>* v) {
 }
 
 // ---------------------------------------------------------------- one butterfly
+// 24-bit integer product (full-rate on the GPU; every index here is < 2^24).
+CBP_HD int mul24(int a, int b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __mul24(a, b);
+#else
+  return a * b;
+#endif
+}
+
 // Butterfly j of a pass with k = j mod Ns given: reads src[j + r N/R],
-// twiddles the inputs by w^(r k N/(Ns R)), writes dst[(j - k) R + k + r Ns].
-template <int R, int DIR, typename T>
-CBP_HD void stockham_bfly(const cplx<T>* src, cplx<T>* dst, int N, int Ns, int twstep,
-                          const cplx<T>* tw, int j, int k) {
-  const int NR = N / R;
+// twiddles the inputs by w^(r k N/(Ns R)) (TW: Ns > 1), writes
+// dst[(j - k) R + k + r Ns].
+template <int R, int DIR, bool TW, typename T>
+CBP_HD void stockham_bfly(const cplx<T>* src, cplx<T>* dst, int NR, int Ns, int twstep, const cplx<T>* tw, int j,
+                          int k) {
   cplx<T> v[R];
+  const cplx<T>* s = src + j;
 #pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = src[j + r * NR];
-  if (Ns > 1) {
-    const int step = k * twstep;  // twstep = N / (Ns * R); r * step < N
+  for (int r = 0; r < R; ++r) v[r] = s[mul24(r, NR)];
+  if (TW) {
+    const int step = mul24(k, twstep);  // twstep = N / (Ns * R); r * step < N
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      cplx<T> w = tw[r * step];
+      cplx<T> w = tw[mul24(r, step)];
       if (DIR > 0) w.im = -w.im;
       v[r] = v[r] * w;
     }
   }
   dft_small<R, DIR>(v);
-  const int out = (j - k) * R + k;
+  cplx<T>* o = dst + mul24(j - k, R) + k;
 #pragma unroll
-  for (int r = 0; r < R; ++r) dst[out + r * Ns] = v[r];
+  for (int r = 0; r < R; ++r) o[mul24(r, Ns)] = v[r];
 }
 
 // q = floor(a / b) for 0 <= a < 2^22, 1 <= b <= 2^22, from a float
@@ -191,19 +201,31 @@ inline bool make_fft_plan(int N, fft_plan* p, int order = 0) {
 // One pass of radix R over `nbatch` transforms stored at src + f*bstride
 // (f < nbatch), butterflies distributed over threads tid, tid+nthr, ...  The
 // caller synchronises between passes.
-template <int R, int DIR, typename T>
-CBP_HD void fft_pass_r(const cplx<T>* src, cplx<T>* dst, int N, int Ns, const cplx<T>* tw, int nbatch, int bstride,
-                       int tid, int nthr) {
+template <int R, int DIR, bool TW, typename T>
+CBP_HD void fft_pass_rt(const cplx<T>* src, cplx<T>* dst, int N, int Ns, const cplx<T>* tw, int nbatch, int bstride,
+                        int tid, int nthr) {
   const int nb = N / R;
   const int total = nb * nbatch;
   const int twstep = N / (Ns * R);
   const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns;
   for (int t = tid; t < total; t += nthr) {
     const int f = nbatch == 1 ? 0 : fdiv_floor(t, rnb);
-    const int j = t - f * nb;
-    const int k = j - fdiv_floor(j, rns) * Ns;
-    stockham_bfly<R, DIR>(src + (size_t)f * bstride, dst + (size_t)f * bstride, N, Ns, twstep, tw, j, k);
+    const int j = t - mul24(f, nb);
+    const int k = TW ? j - mul24(fdiv_floor(j, rns), Ns) : 0;
+    const int off = mul24(f, bstride);
+    stockham_bfly<R, DIR, TW>(src + off, dst + off, nb, Ns, twstep, tw, j, k);
   }
+}
+
+// One pass of radix R over `nbatch` transforms stored at src + f*bstride
+// (f < nbatch), butterflies distributed over threads tid, tid+nthr, ...  The
+// caller synchronises between passes.  The first pass (Ns = 1) has no
+// twiddles.
+template <int R, int DIR, typename T>
+CBP_HD void fft_pass_r(const cplx<T>* src, cplx<T>* dst, int N, int Ns, const cplx<T>* tw, int nbatch, int bstride,
+                       int tid, int nthr) {
+  if (Ns == 1) fft_pass_rt<R, DIR, false>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr);
+  else fft_pass_rt<R, DIR, true>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr);
 }
 
 template <int DIR, typename T>
