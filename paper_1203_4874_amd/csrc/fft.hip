@@ -24,13 +24,6 @@ namespace cbp {
 
 namespace {
 
-// Copy a twiddle table (global, filled by k_twiddles) into LDS.
-template <typename T>
-__device__ inline void load_twiddles(cplx<T>* tw, const void* g, int N) {
-  const cplx<T>* src = (const cplx<T>*)g;
-  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = src[t];
-}
-
 // ---------------------------------------------------------------- tables
 // Items: 256 consecutive indices of [0, Px + Py): x tables for t < Px, the y
 // table after.  The FP64 value is rounded once to T, so a table entry equals
@@ -89,12 +82,11 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
     const int N = px.N, hx = d.hx;
     cplx<T>* a = (cplx<T>*)sm_rf;
     cplx<T>* b = a + N;
-    cplx<T>* tw = b + N;
+    const cplx<T>* tw = (const cplx<T>*)d.twx;   // global table (L1 / L2 resident)
     const int y = item % d.Hmax, ch = item / d.Hmax;
     const T* r1 = (const T*)d.b1 + ch * d.cs1 + (int64_t)y * d.p1;
     const T* r2 = (const T*)d.b2 + ch * d.cs2 + (int64_t)y * d.p2;
     const bool in1 = y < d.H1, in2 = y < d.H2;
-    load_twiddles(tw, d.twx, N);
     if (with_ey)
       for (int t = threadIdx.x; t < d.S; t += blockDim.x) {
         double sn, cs;
@@ -171,14 +163,13 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
     const int nf = 2 * cw;                      // transforms in flight: (column, frame)
     cplx<T>* a = (cplx<T>*)sm_cf;               // [nf][N]
     cplx<T>* b = a + (size_t)nf * N;            // [nf][N]
-    cplx<T>* tw = b + (size_t)nf * N;           // [N]
-    cplx<T>* kr = tw + N;                       // [cw][2][CBP_MAX_K] row DFTs of the kernels at kx
+    const cplx<T>* tw = (const cplx<T>*)d.twy;  // global table (L1 / L2 resident)
+    cplx<T>* kr = b + (size_t)nf * N;           // [cw][2][CBP_MAX_K] row DFTs of the kernels at kx
     const int nstrip = (hx + cw - 1) / cw;
     const int kx0 = (item % nstrip) * cw, ch = item / nstrip;
     const int64_t tpc = (int64_t)d.Hmax * hx;
     const cplx<T>* s1 = (const cplx<T>*)d.t1 + ch * tpc;
     const cplx<T>* s2 = (const cplx<T>*)d.t2 + ch * tpc;
-    load_twiddles(tw, d.twy, N);
     // load: element (y, f) with f = 2*col + frame; consecutive threads walk f
     // (adjacent columns of one row) for coalescing
     const int lnf = __builtin_ctz(nf);         // cw, hence nf, is a power of two
@@ -263,13 +254,12 @@ __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
     const T scale = (T)(1.0 / ((double)d.Py * (double)d.Px));
     cplx<T>* a = (cplx<T>*)sm_ri;
     cplx<T>* b = a + N;
-    cplx<T>* tw = b + N;
+    const cplx<T>* tw = (const cplx<T>*)d.twx;   // global table (L1 / L2 resident)
     const int npair = (m + 1) / 2;
     const int ya = 2 * (item % npair), yb = ya + 1, ch = item / npair;
     const cplx<T>* ua = (const cplx<T>*)d.u + (int64_t)ch * m * hx + (int64_t)ya * hx;
     const cplx<T>* ub = ua + hx;
     const bool hb = yb < m;
-    load_twiddles(tw, d.twx, N);
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
       cplx<T> A, B;
       const bool edge = (k == 0) || (2 * k == N);
@@ -296,9 +286,9 @@ __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
 
 }  // namespace
 
-size_t row_lds_bytes(int N, int esize) { return (size_t)3 * N * 2 * esize; }
+size_t row_lds_bytes(int N, int esize) { return (size_t)2 * N * 2 * esize; }
 size_t col_lds_bytes(int N, int cw, int esize) {
-  return ((size_t)(4 * cw + 1) * N + (size_t)cw * 2 * CBP_MAX_K) * 2 * esize;
+  return ((size_t)(4 * cw) * N + (size_t)cw * 2 * CBP_MAX_K) * 2 * esize;
 }
 
 void set_fft_attrs() {
