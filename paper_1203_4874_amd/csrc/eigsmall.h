@@ -18,7 +18,8 @@
 //  4. Newton refinement against G held in double-double:
 //       r = G x - mu x (mu = x^H G x, both double-double),
 //       x <- (x - M r) / ||x - M r||,  M = W X W^H = (G~ - sigma I)^{-1},
-//     until the correction is below 4e-15; M r approximates the exact Newton
+//     until the change of direction (the correction's part orthogonal to x)
+//     is below 4e-15; M r approximates the exact Newton
 //     step sum_k v_k (v_k^H r) / (lam_k - mu) with relative error
 //     (mu - sigma) / (lam_k - sigma).
 //
@@ -730,13 +731,18 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_lam
     const c64 cl = w_mul(s, n, s.u);
     const c64 xn = l < n ? xl - cl : c64{0.0, 0.0};
     const double nrm = sqrt(wsum(norm2(xn)));
-    const double dn = sqrt(wsum(l < n ? norm2(cl) : 0.0));
+    // the change of direction: with c = alpha x + c_perp, x - c turns by
+    // |c_perp| / |1 - alpha| (the part along x, which M amplifies from the
+    // rounding of r, only rescales x)
+    const c64 al = wsum_c(l < n ? cmulc(xl, cl) : c64{0.0, 0.0});
+    const c64 cp = l < n ? cl - xl * al : c64{0.0, 0.0};
+    const double dn = sqrt(wsum(norm2(cp))) / sqrt((1.0 - al.re) * (1.0 - al.re) + al.im * al.im);
     xl = {xn.re / nrm, xn.im / nrm};
     __syncthreads();
     if (l < n) s.x[l] = xl;
     __syncthreads();
-    // converged when the correction, or the next one predicted from the
-    // linear rate dn / dprev of the last two, is below 4e-15
+    // converged when the change of direction, or the next one predicted from
+    // the linear rate dn / dprev of the last two, is below 4e-15
     done = !(dn > 4e-15) || (dprev > 0.0 && dn * dn <= 4e-15 * dprev);
     dprev = dn;
   }
