@@ -73,14 +73,15 @@ def source_hash(names):
 # minimum HBM traffic of the kernel's own inputs and outputs.  FLOPs: the FP64
 # arithmetic of the kernel's algorithm, counted as real operations (a complex
 # multiply-add is 8, a double-double complex multiply-add about 40).
-def eig_flops(n, refine_steps, invit=4, bisect_probes=64 * 8):
+def eig_flops(n, refine_steps, invit=3, bisect_probes=64 * 8):
     """One Hermitian smallest-eigenvector solve of order n: Householder
-    tridiagonalisation (16/3 n^3), Sturm multisection (about 4 n per probe),
-    Gauss-Jordan inverse of the shifted matrix (8 n^3), `invit` inverse
-    iterations (8 n^2 each) and `refine_steps` residual corrections (a
-    double-double Gram mat-vec, 40 n^2, plus an FP64 mat-vec, 8 n^2)."""
-    return (16.0 / 3.0 + 8.0) * n ** 3 + invit * 8 * n * n + bisect_probes * 4 * n \
-        + refine_steps * 48 * n * n
+    tridiagonalisation (16/3 n^3), Sturm multisection (about 5 n per probe),
+    W = QD from the reflectors (8/3 n^3), X = (T - sigma I)^{-1} (4 n^2),
+    `invit` inverse iterations with X (4 n^2 each), x = W y (8 n^2) and
+    `refine_steps` Newton corrections (a double-double Gram mat-vec, 40 n^2,
+    and the products with W^H, X and W, 20 n^2)."""
+    return (16.0 / 3.0 + 8.0 / 3.0) * n ** 3 + 4 * n * n + invit * 4 * n * n + 8 * n * n \
+        + bisect_probes * 5 * n + refine_steps * 60 * n * n
 
 
 def kernel_models(H1, W1, H2, W2, m, n, k1, k2, S, Py, Px, esize, refine_sample, refine_scale):
