@@ -241,6 +241,7 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
                                       double* K2, cbp_diag* diag, char* sm_fin, const double* wts) {
   const int N = k1 + k2, n2 = 2 * S, SS = S * S;
   const int tid = threadIdx.x;
+  const float rS = 1.0f / (float)S, rSS = 1.0f / (float)SS, rn2 = 1.0f / (float)n2;
   c64* tw = (c64*)sm_fin;                        // S
   dd* Da = (dd*)(tw + CBP_MAX_S);                // S
   dd* Db = Da + CBP_MAX_S;                       // S
@@ -254,11 +255,24 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
   // [i][j], written by the sample solves), staged in the solver's W region
   // (2S (2S + 1) >= 4 S^2 entries, free until the solve)
   c64* pql = w.W;
-  for (int e = tid; e < 4 * SS; e += SMALL_NT) pql[e] = pq[e];
+  for (int e0 = 0; e0 < 4 * SS; e0 += 8 * SMALL_NT) {   // eight loads in flight per lane
+    c64 v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = e0 + tid + t * SMALL_NT;
+      v[t] = e < 4 * SS ? pq[e] : c64{0.0, 0.0};
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = e0 + tid + t * SMALL_NT;
+      if (e < 4 * SS) pql[e] = v[t];
+    }
+  }
   __syncthreads();
   // H blocks in double-double
   for (int e = tid; e < SS; e += SMALL_NT) {
-    const int jj = e / S, i = e - jj * S;
+    int jj, i;
+    split_index(e, S, rS, jj, i);
     dot2 re, im;
     re.init();
     im.init();
@@ -300,7 +314,8 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
   __syncthreads();
   const scale_acc H{Da, Db, cbuf, S};
   for (int e = tid; e < n2 * n2; e += SMALL_NT) {
-    const int r = e / n2, c = e - r * n2;
+    int r, c;
+    split_index(e, n2, rn2, r, c);
     const cdd h = H.get(r, c);
     w.A[e] = {h.re.hi, h.im.hi};
   }
@@ -326,8 +341,10 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
   c64* Kh = kbuf;
   c64* Tm = tbuf;
   for (int e = tid; e < 2 * SS; e += SMALL_NT) {
-    const int c = e / SS, ij = e - c * SS;
-    const int i = ij / S, jj = ij - i * S;
+    int c, ij;
+    split_index(e, SS, rSS, c, ij);
+    int i, jj;
+    split_index(ij, S, rS, i, jj);
     const c64 P = pq[(size_t)c * SS + ij], Q = pq[(size_t)(2 + c) * SS + ij];
     c64 kv;
     if (wts) {
@@ -355,8 +372,10 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
   }
   // inverse DFT along x: Tm[c][j][x] = sum_i Kh[c][i][j] w_i^{-x}
   for (int e = tid; e < 2 * SS; e += SMALL_NT) {
-    const int c = e / SS, jx = e - c * SS;
-    const int jj = jx / S, x = jx - jj * S;
+    int c, jx;
+    split_index(e, SS, rSS, c, jx);
+    int jj, x;
+    split_index(jx, S, rS, jj, x);
     c64 acc = {0.0, 0.0};
     int t = 0;
     for (int i = 0; i < S; ++i) {
@@ -369,8 +388,10 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
   __syncthreads();
   // inverse DFT along y: Kf[c][y][x] = sum_j w_j^{-y} Tm[c][j][x]   (into Kh)
   for (int e = tid; e < 2 * SS; e += SMALL_NT) {
-    const int c = e / SS, yx = e - c * SS;
-    const int y = yx / S, x = yx - y * S;
+    int c, yx;
+    split_index(e, SS, rSS, c, yx);
+    int y, x;
+    split_index(yx, S, rS, y, x);
     c64 acc = {0.0, 0.0};
     int t = 0;
     for (int jj = 0; jj < S; ++jj) {
@@ -383,9 +404,11 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
   __syncthreads();
   for (int c = 0; c < 2; ++c) {
     const int k = c == 0 ? k1 : k2;
+    const float rk = 1.0f / (float)k;
     double sr = 0.0, si = 0.0, ein = 0.0, eall = 0.0;
     for (int e = tid; e < SS; e += SMALL_NT) {
-      const int y = e / S, x = e - y * S;
+      int y, x;
+      split_index(e, S, rS, y, x);
       const c64 v = Kh[(size_t)c * SS + e];
       const double p = norm2(v);
       eall += p;
@@ -399,7 +422,8 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
     double* K = c == 0 ? K1 : K2;
     double re2 = 0.0, im2 = 0.0;
     for (int e = tid; e < k * k; e += SMALL_NT) {
-      const int y = e / k, x = e - y * k;
+      int y, x;
+      split_index(e, k, rk, y, x);
       const c64 v = Kh[(size_t)c * SS + y * S + x];
       const double kr = (v.re * sr + v.im * si) / s2;
       const double ki = (v.im * sr - v.re * si) / s2;
@@ -421,6 +445,7 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
 __device__ inline void learned_assembly(const c64* tw, int S, int k, const double* wts, c64* Kh, c64* tb, c64* xt,
                                         double* K, cbp_diag* diag, int c) {
   const int tid = threadIdx.x, kk = k * k;
+  const float rS = 1.0f / (float)S, rk = 1.0f / (float)k;
   const double tau = wts[2 * S];
   c64* Ax = tb;             // k x k
   c64* By = tb + kk;        // k x k
@@ -428,7 +453,8 @@ __device__ inline void learned_assembly(const c64* tw, int S, int k, const doubl
   c64* Cm = Kh;             // k x k, over Khat once T1 is formed
   // F[i][x] = w_i^x = tw[(i x) mod S];  u_i = wY_i,  v_j = wX_j
   for (int e = tid; e < kk; e += SMALL_NT) {
-    const int p = e / k, q = e - p * k;
+    int p, q;
+    split_index(e, k, rk, p, q);
     c64 a = {0.0, 0.0}, b = {0.0, 0.0};
     for (int i = 0; i < S; ++i) {
       const c64 fp = tw[(i * p) % S], fq = tw[(i * q) % S];
@@ -443,7 +469,8 @@ __device__ inline void learned_assembly(const c64* tw, int S, int k, const doubl
   }
   // T1[x][j] = sum_i conj(F[i][x]) u_i Khat[i][j]
   for (int e = tid; e < k * S; e += SMALL_NT) {
-    const int x = e / S, jj = e - x * S;
+    int x, jj;
+    split_index(e, S, rS, x, jj);
     c64 acc = {0.0, 0.0};
     for (int i = 0; i < S; ++i) {
       const c64 g = cmulc(tw[(i * x) % S], Kh[i * S + jj]);
@@ -454,7 +481,8 @@ __device__ inline void learned_assembly(const c64* tw, int S, int k, const doubl
   __syncthreads();
   // C[x][y] = sum_j T1[x][j] v_j conj(F[j][y])
   for (int e = tid; e < kk; e += SMALL_NT) {
-    const int x = e / k, y = e - x * k;
+    int x, y;
+    split_index(e, k, rk, x, y);
     c64 acc = {0.0, 0.0};
     for (int jj = 0; jj < S; ++jj) {
       const c64 g = cmulc(tw[(jj * y) % S], T1[x * S + jj]);
@@ -473,14 +501,16 @@ __device__ inline void learned_assembly(const c64* tw, int S, int k, const doubl
   small_gj_inverse(g, k);
   // Z1 = Ax^{-1} C (into T1), Z = Z1 By^{-1} (into Cm)
   for (int e = tid; e < kk; e += SMALL_NT) {
-    const int x = e / k, y = e - x * k;
+    int x, y;
+    split_index(e, k, rk, x, y);
     c64 acc = {0.0, 0.0};
     for (int t = 0; t < k; ++t) acc = acc + Ax[x * k + t] * Cm[t * k + y];
     T1[e] = acc;
   }
   __syncthreads();
   for (int e = tid; e < kk; e += SMALL_NT) {
-    const int x = e / k, y = e - x * k;
+    int x, y;
+    split_index(e, k, rk, x, y);
     c64 acc = {0.0, 0.0};
     for (int t = 0; t < k; ++t) acc = acc + T1[x * k + t] * By[t * k + y];
     Cm[e] = acc;
@@ -494,7 +524,8 @@ __device__ inline void learned_assembly(const c64* tw, int S, int k, const doubl
   const double s2 = sr * sr + si * si;
   double re2 = 0.0, im2 = 0.0;
   for (int e = tid; e < kk; e += SMALL_NT) {
-    const int y = e / k, x = e - y * k;
+    int y, x;
+    split_index(e, k, rk, y, x);
     const c64 v = Cm[x * k + y];
     const double kr = (v.re * sr + v.im * si) / s2;
     const double ki = (v.im * sr - v.re * si) / s2;
@@ -515,14 +546,17 @@ __device__ inline void learned_assembly(const c64* tw, int S, int k, const doubl
 
 // Items: one per frame.  plain_only: the plain method's kernels into the
 // learned form's fallback slots (d.Kalt), ignoring the network's weights.
-__global__ __launch_bounds__(SMALL_NT) void k_finalize(batch_ref br, int plain_only) {
+// c_off: byte offset of the coupling block in LDS for every frame of the
+// launch (sized for the launch's largest S), or 0 to keep it in the workspace.
+__global__ __launch_bounds__(SMALL_NT) void k_finalize(batch_ref br, int plain_only, int c_off) {
   extern __shared__ __attribute__((aligned(16))) char sm_fin[];
   for_items<Q_FINALIZE>(br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
+    cdd* cb = c_off ? (cdd*)(sm_fin + c_off) : d.cbuf;
     if (plain_only)
-      finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, d.cbuf, d.Kalt, d.Kalt + CBP_MAX_K * CBP_MAX_K, nullptr, sm_fin,
+      finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, cb, d.Kalt, d.Kalt + CBP_MAX_K * CBP_MAX_K, nullptr, sm_fin,
                      nullptr);
     else
-      finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, d.cbuf, d.K1, d.K2, d.diag, sm_fin, d.wts);
+      finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, cb, d.K1, d.K2, d.diag, sm_fin, d.wts);
   });
 }
 
@@ -623,13 +657,28 @@ __global__ void k_diag_init(batch_ref br) {
 
 }  // namespace
 
-size_t finalize_lds_bytes(int S, int learned) {
+// LDS of the finalize without the coupling block: the plain part and, for
+// the learned assembly, T1 / Z1 (S^2) and the inversion's two vectors, taken
+// from the solver's W (2S (2S + 1) entries, the last region of the solver's
+// LDS) plus what they need beyond it.
+size_t fin_lds_core(int S, int learned) {
   const size_t base = fin_base_bytes(S);
-  // the learned assembly: T1 / Z1 (S^2) and the inversion's two vectors, from
-  // the solver's W (2S (2S + 1) entries, the last region of the solver's LDS)
   const size_t need = ((size_t)S * S + 2 * CBP_MAX_S) * sizeof(c64);
   const size_t have = (size_t)(2 * S) * (2 * S + 1) * sizeof(c64);
   return learned && need > have ? base + (need - have) : base;
+}
+
+// Byte offset of the scale system's coupling block C (S^2 double-double
+// entries) in LDS, after the core regions, when it fits (else 0: C stays in
+// the workspace); the refinement's products read it on every step.
+size_t fin_c_offset(int S, int learned) {
+  const size_t core = (fin_lds_core(S, learned) + 15) & ~(size_t)15;
+  return core + (size_t)S * S * sizeof(cdd) <= (size_t)158 * 1024 ? core : 0;
+}
+
+size_t finalize_lds_bytes(int S, int learned) {
+  const size_t c = fin_c_offset(S, learned);
+  return c ? c + (size_t)S * S * sizeof(cdd) : fin_lds_core(S, learned);
 }
 
 size_t sample_lds_bytes(int N) {
@@ -673,7 +722,8 @@ hipError_t launch_judge(const batch_ref& br, int grid, hipStream_t st) {
 hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned, int plain_only,
                            hipStream_t st) {
   prof_begin(PH_FINALIZE, st);
-  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(SMALL_NT), finalize_lds_bytes(maxS, learned), st, br, plain_only);
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(SMALL_NT), finalize_lds_bytes(maxS, learned), st, br, plain_only,
+                     (int)fin_c_offset(maxS, learned));
   prof_end(PH_FINALIZE, st);
   return hipGetLastError();
 }
