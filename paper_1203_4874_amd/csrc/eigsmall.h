@@ -10,14 +10,14 @@
 //     8 rounds, leave a bracket [lo, hi] of width ~6e-15 ||T||.
 //  3. sigma = lo - 16 n eps ||T|| < lam0, so T - sigma I is positive
 //     definite with its smallest eigenvalue well separated from the rest; its
-//     LDL^T factors (d_k > 0) give X = (T - sigma I)^{-1} explicitly (one
-//     column per lane), the Householder reflectors (kept in the reduced
-//     matrix's strictly lower part) and the diagonal unitary D give W = Q D
-//     explicitly (one column per lane), and inverse iteration runs on T:
-//     y <- X y, x = W y.
+//     LDL^T factors (d_k > 0) solve (T - sigma I) z = r by one forward and
+//     one backward substitution.  Inverse iteration runs on T (y <- (T -
+//     sigma I)^{-1} y) and x = W y with W = Q D: the Householder reflectors
+//     (kept in the reduced matrix's strictly lower part) applied one by one,
+//     after the diagonal unitary D that makes the tridiagonal real.
 //  4. Newton refinement against G held in double-double:
 //       r = G x - mu x (mu = x^H G x, both double-double),
-//       x <- (x - M r) / ||x - M r||,  M = W X W^H = (G~ - sigma I)^{-1},
+//       x <- (x - M r) / ||x - M r||,  M = W (T - sigma I)^{-1} W^H,
 //     until the change of direction (the correction's part orthogonal to x)
 //     is below 4e-15; M r approximates the exact Newton
 //     step sum_k v_k (v_k^H r) / (lam_k - mu) with relative error
@@ -48,8 +48,7 @@ struct small_ws {
   double* a;    // n: diagonal of T
   double* b;    // n: off-diagonal of T, b[k] = T[k+1][k]
   dd* part;     // 4 x 64 x 2: partial double-double row sums of the refinement's product
-  c64* W;       // n x (n+1): W = Q D (row stride n + 1)
-  double* X;    // n x n: (T - sigma I)^{-1}, in the storage of A once W is built
+  c64* W;       // n x (n+1): not used by the solver (callers stage data there before or after it)
 };
 
 __host__ __device__ inline size_t small_lds_bytes(int n) {
@@ -69,7 +68,6 @@ __device__ inline small_ws small_carve(char* base, int n) {
   s.b = (double*)p; p += n * sizeof(double);
   s.part = (dd*)p; p += (size_t)4 * 64 * 2 * sizeof(dd);
   s.W = (c64*)p;
-  s.X = (double*)s.A;
   return s;
 }
 
@@ -103,14 +101,27 @@ __device__ inline double readlane_d(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes (fixed order; the result is wave-uniform).
+// Lane permutation with zero fill: lanes whose source lies outside the wave
+// read 0 (bound control), so no prior value of the destination is needed.
+template <int CTRL>
+__device__ inline double dpp_z(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes (fixed order; the result is wave-uniform).  Within
+// each row of 16 lanes: quad permutations and row mirrors; then lane 15 of
+// each row is added into the next row and lane 31 into rows 2 and 3, so lane
+// 63 ends with ((r3 + r2) + (r1 + r0)) of the row sums r0..r3 (other lanes
+// may hold partial or doubled sums and are not read).
 __device__ inline double wsum(double v) {
-  v += dpp_d<0xB1>(v, 0.0);        // quad_perm [1,0,3,2]
-  v += dpp_d<0x4E>(v, 0.0);        // quad_perm [2,3,0,1]
-  v += dpp_d<0x141>(v, 0.0);       // row_half_mirror
-  v += dpp_d<0x140>(v, 0.0);       // row_mirror
-  v += dpp_d<0x142, 0xa>(v, 0.0);  // row_bcast:15 into rows 1, 3
-  v += dpp_d<0x143, 0xc>(v, 0.0);  // row_bcast:31 into rows 2, 3
+  v += dpp_z<0xB1>(v);     // quad_perm [1,0,3,2]
+  v += dpp_z<0x4E>(v);     // quad_perm [2,3,0,1]
+  v += dpp_z<0x141>(v);    // row_half_mirror
+  v += dpp_z<0x140>(v);    // row_mirror
+  v += dpp_z<0x142>(v);    // row_bcast:15
+  v += dpp_z<0x143>(v);    // row_bcast:31
   return readlane_d(v, 63);
 }
 
@@ -128,28 +139,40 @@ __device__ inline double wmin(double v) {
 __device__ inline double wmax(double v) { return -wmin(-v); }
 
 __device__ inline c64 wsum_c(c64 v) {
-  v.re += dpp_d<0xB1>(v.re, 0.0);       v.im += dpp_d<0xB1>(v.im, 0.0);
-  v.re += dpp_d<0x4E>(v.re, 0.0);       v.im += dpp_d<0x4E>(v.im, 0.0);
-  v.re += dpp_d<0x141>(v.re, 0.0);      v.im += dpp_d<0x141>(v.im, 0.0);
-  v.re += dpp_d<0x140>(v.re, 0.0);      v.im += dpp_d<0x140>(v.im, 0.0);
-  v.re += dpp_d<0x142, 0xa>(v.re, 0.0); v.im += dpp_d<0x142, 0xa>(v.im, 0.0);
-  v.re += dpp_d<0x143, 0xc>(v.re, 0.0); v.im += dpp_d<0x143, 0xc>(v.im, 0.0);
+  v.re += dpp_z<0xB1>(v.re);  v.im += dpp_z<0xB1>(v.im);
+  v.re += dpp_z<0x4E>(v.re);  v.im += dpp_z<0x4E>(v.im);
+  v.re += dpp_z<0x141>(v.re); v.im += dpp_z<0x141>(v.im);
+  v.re += dpp_z<0x140>(v.re); v.im += dpp_z<0x140>(v.im);
+  v.re += dpp_z<0x142>(v.re); v.im += dpp_z<0x142>(v.im);
+  v.re += dpp_z<0x143>(v.re); v.im += dpp_z<0x143>(v.im);
   return {readlane_d(v.re, 63), readlane_d(v.im, 63)};
 }
 
-template <int CTRL, int ROWMASK = 0xf>
-__device__ inline dd dpp_dd(dd v) {
-  return {dpp_d<CTRL, ROWMASK>(v.hi, 0.0), dpp_d<CTRL, ROWMASK>(v.lo, 0.0)};
+// The same sum when only lanes 0..31 can be nonzero: lane 31 ends with
+// r1 + r0.
+__device__ inline c64 wsum_c32(c64 v) {
+  v.re += dpp_z<0xB1>(v.re);  v.im += dpp_z<0xB1>(v.im);
+  v.re += dpp_z<0x4E>(v.re);  v.im += dpp_z<0x4E>(v.im);
+  v.re += dpp_z<0x141>(v.re); v.im += dpp_z<0x141>(v.im);
+  v.re += dpp_z<0x140>(v.re); v.im += dpp_z<0x140>(v.im);
+  v.re += dpp_z<0x142>(v.re); v.im += dpp_z<0x142>(v.im);
+  return {readlane_d(v.re, 31), readlane_d(v.im, 31)};
 }
 
-// Double-double sum over the 64 lanes (dd_add at each level).
+template <int CTRL>
+__device__ inline dd dpp_dd(dd v) {
+  return {dpp_z<CTRL>(v.hi), dpp_z<CTRL>(v.lo)};
+}
+
+// Double-double sum over the 64 lanes (dd_add at each level, the order of
+// wsum).
 __device__ inline dd wsum_dd(dd v) {
   v = dd_add(v, dpp_dd<0xB1>(v));
   v = dd_add(v, dpp_dd<0x4E>(v));
   v = dd_add(v, dpp_dd<0x141>(v));
   v = dd_add(v, dpp_dd<0x140>(v));
-  v = dd_add(v, dpp_dd<0x142, 0xa>(v));
-  v = dd_add(v, dpp_dd<0x143, 0xc>(v));
+  v = dd_add(v, dpp_dd<0x142>(v));
+  v = dd_add(v, dpp_dd<0x143>(v));
   return {readlane_d(v.hi, 63), readlane_d(v.lo, 63)};
 }
 
@@ -209,6 +232,7 @@ __device__ inline void small_tridiag(small_ws& s, int n) {
     if (l < m) xl = conj(A[k * n + o + l]);     // A[o+l][k]
     const double x0r = readlane_d(xl.re, 0), x0i = readlane_d(xl.im, 0);
     const double ax0sq = x0r * x0r + x0i * x0i;
+    const double r0 = rsq_nr(ax0sq > 0.0 ? ax0sq : 1.0);   // 1 / |x_0|, overlapping the sum below
     const double tail = wsum(l >= 1 ? norm2(xl) : 0.0);
     if (!(tail > 0.0)) {                        // column already reduced: reflector k = I
       if (l == 0) s.e[k] = {x0r, x0i};
@@ -218,8 +242,8 @@ __device__ inline void small_tridiag(small_ws& s, int n) {
     }
     const double s2 = ax0sq + tail;
     const double nx = s2 * rsq_nr(s2);
-    const double ax0 = ax0sq > 0.0 ? ax0sq * rsq_nr(ax0sq) : 0.0;
-    const c64 ph = ax0 > 0.0 ? c64{x0r / ax0, x0i / ax0} : c64{1.0, 0.0};
+    const double ax0 = ax0sq > 0.0 ? ax0sq * r0 : 0.0;
+    const c64 ph = ax0sq > 0.0 ? c64{x0r * r0, x0i * r0} : c64{1.0, 0.0};
     const c64 alpha = {-ph.re * nx, -ph.im * nx};
     const double sc = rsq_nr(nx * (nx + ax0));  // sqrt(2) / ||x - alpha e_0||
     c64 vl = {0.0, 0.0};
@@ -446,180 +470,123 @@ __device__ inline void tri_factor(small_ws& s, int n, double sigma, double pivmi
   __syncthreads();
 }
 
-// X = (T - sigma I)^{-1} (real symmetric) from the factors in s.w: lane j
-// solves for column j (forward L w = e_j, w'_k = w_k / d_k, backward
-// L^T z = w'), the factors being broadcast reads.  Overwrites s.A, so W
-// must be built first.
-__device__ inline void build_x(small_ws& s, int n) {
+// (T - sigma I) z = r from the factors in s.w (L D L^T, L unit lower
+// bidiagonal): forward w_k = r_k - l_{k-1} w_{k-1}, then w_k / d_k, then
+// backward z_k = w_k / d_k - l_k z_{k+1}.  r arrives lane-distributed and is
+// staged in s.u; every lane runs both recurrences on broadcast reads (eight
+// entries per batch; steps past the ends run on clamped entries and are
+// discarded), lane k keeps w_k / d_k, which goes back to s.u for the
+// backward pass, and lane k returns z_k (zero for k >= n).
+__device__ inline __attribute__((always_inline)) c64 tri_solve(small_ws& s, int n, c64 r) {
   const int l = threadIdx.x;
-  double* X = s.X;
+  c64* __restrict__ b = s.u;
+  const c64* __restrict__ f = s.w;
   __syncthreads();
-  if (l < n) {
-    double w = 0.0, lprev = 0.0;
-    for (int k0 = 0; k0 < n; k0 += 8) {
-      c64 fv[8];
+  if (l < n) b[l] = r;
+  __syncthreads();
+  c64 w = {0.0, 0.0}, wl = {0.0, 0.0};
+  double lp = 0.0;
+  for (int k0 = 0; k0 < n; k0 += 8) {
+    c64 fv[8], rv[8];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) fv[t] = k0 + t < n ? s.w[k0 + t] : c64{0.0, 0.0};
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int k = k0 + t;
-        if (k < n) {
-          w = (k == l ? 1.0 : 0.0) - lprev * w;
-          lprev = fv[t].im;
-          X[(size_t)k * n + l] = w * fv[t].re;
-        }
-      }
+    for (int t = 0; t < 8; ++t) {
+      const int k = min(k0 + t, n - 1);
+      fv[t] = f[k];
+      rv[t] = b[k];
     }
-    double z = 0.0;
-    for (int k1 = n - 1; k1 >= 0; k1 -= 8) {
-      double wv[8], lv[8];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int k = k1 - t;
-        wv[t] = k >= 0 ? X[(size_t)k * n + l] : 0.0;
-        lv[t] = (k >= 0 && k + 1 < n) ? s.w[k].im : 0.0;
-      }
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int k = k1 - t;
-        if (k >= 0) {
-          z = wv[t] - lv[t] * z;
-          X[(size_t)k * n + l] = z;
-        }
-      }
+    for (int t = 0; t < 8; ++t) {
+      w = {rv[t].re - lp * w.re, rv[t].im - lp * w.im};
+      lp = fv[t].im;
+      if (l == k0 + t) wl = {w.re * fv[t].re, w.im * fv[t].re};
     }
   }
   __syncthreads();
+  if (l < n) b[l] = wl;
+  __syncthreads();
+  c64 z = {0.0, 0.0}, out = {0.0, 0.0};
+  for (int k1 = n - 1; k1 >= 0; k1 -= 8) {
+    c64 fv[8], wv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = max(k1 - t, 0);
+      fv[t] = f[k];
+      wv[t] = b[k];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const double lk = k1 - t + 1 < n ? fv[t].im : 0.0;
+      z = {wv[t].re - lk * z.re, wv[t].im - lk * z.im};
+      if (l == k1 - t) out = z;
+    }
+  }
+  return out;
 }
 
 // Diagonal unitary D with D^H T_c D = T (T_c the complex tridiagonal with
 // subdiagonal e_k, T its real form with b_k = |e_k|): ph_0 = 1,
-// ph_{k+1} = ph_k e_k / |e_k|.  Lane k receives ph_k.
+// ph_{k+1} = ph_k e_k / |e_k|, i.e. lane k receives the product of the unit
+// factors of e_0 .. e_{k-1} (an inclusive product scan over the lanes by DPP
+// row shifts and row broadcasts; zero for lanes >= n).
+template <int CTRL, int ROWMASK>
+__device__ inline c64 scan_mul_step(c64 x) {
+  const c64 y = {dpp_d<CTRL, ROWMASK>(x.re, 1.0), dpp_d<CTRL, ROWMASK>(x.im, 0.0)};   // absent lanes give 1
+  return x * y;
+}
+
 __device__ inline c64 tri_phases(const small_ws& s, int n) {
   const int l = threadIdx.x;
-  c64 p = {1.0, 0.0};
-  c64 ph = {l < n ? 1.0 : 0.0, 0.0};
-  for (int k = 0; k + 1 < n; ++k) {
-    const c64 e = s.e[k];
-    const double ae = s.b[k];
+  c64 t = {1.0, 0.0};
+  if (l >= 1 && l < n) {
+    const double ae = s.b[l - 1];
     if (ae > 0.0) {
-      const double ir = 1.0 / ae;
-      p = p * c64{e.re * ir, e.im * ir};
+      const c64 e = s.e[l - 1];
+      const double ir = rcp_nr(ae);
+      t = {e.re * ir, e.im * ir};
     }
-    if (l == k + 1) ph = p;
   }
-  return ph;
+  t = scan_mul_step<0x111, 0xf>(t);   // row_shr:1
+  t = scan_mul_step<0x112, 0xf>(t);   // row_shr:2
+  t = scan_mul_step<0x114, 0xf>(t);   // row_shr:4
+  t = scan_mul_step<0x118, 0xf>(t);   // row_shr:8
+  t = scan_mul_step<0x142, 0xa>(t);   // row_bcast:15 into rows 1, 3
+  t = scan_mul_step<0x143, 0xc>(t);   // row_bcast:31 into rows 2, 3
+  return l < n ? t : c64{0.0, 0.0};
 }
 
-// W = Q D with Q = H_0 H_1 ... H_{n-3}, H_k = I - v_k v_k^H (||v_k||^2 = 2 or
-// v_k = 0; v_k kept in column k below the diagonal of s.A) and D the phases.
-// Built as H_0 (H_1 (... (H_{n-3} I))): H_k changes only rows and columns
-// k+1..n-1, W <- W - v_k (v_k^H W) there; the m = n-k-1 column dot products
-// and updates run on split lanes.
-__device__ inline void build_w(small_ws& s, int n, c64 ph) {
+// Q y (adjoint false) or Q^H y (adjoint true) for Q = H_0 H_1 ... H_{n-3},
+// H_k = I - v_k v_k^H, v_k kept in column k below the diagonal of s.A (zero
+// for an identity step).  Lane l holds y_l (zero for l >= n); each reflector
+// costs one wave sum.  Reflector entries are read eight at a time from
+// clamped (always valid) addresses and zeroed where they lie outside v_k.
+template <bool HALF>
+__device__ inline __attribute__((always_inline)) c64 q_apply_w(const small_ws& s, int n, c64 y, bool adjoint) {
   const int l = threadIdx.x;
-  const int ld = n + 1;
-  c64* __restrict__ Wm = s.W;
-  const c64* __restrict__ A = s.A;
-  c64* __restrict__ part = (c64*)s.part;
-  c64* __restrict__ dcol = s.u;
-  if (l < n)
-    for (int i = 0; i < n; ++i) Wm[(size_t)i * ld + l] = {i == l ? 1.0 : 0.0, 0.0};
-  __syncthreads();
-  for (int k = n - 3; k >= 0; --k) {
-    const int m = n - k - 1, o = k + 1;
-    const lane_split sp = split_lanes(m);
-    const c64* v = A + (size_t)o * n + k;          // v[j * n] = v_k[o + j]
-    c64* w = Wm + (size_t)o * ld + o + sp.c;       // w[j * ld] = W[o + j][o + c]
-    c64 d0 = {0.0, 0.0}, d1 = {0.0, 0.0};
-    int j = sp.j0;
-    for (; j + 4 <= sp.j1; j += 4) {
-      const c64 v0 = v[(size_t)j * n], v1 = v[(size_t)(j + 1) * n];
-      const c64 v2 = v[(size_t)(j + 2) * n], v3 = v[(size_t)(j + 3) * n];
-      const c64 w0 = w[(size_t)j * ld], w1 = w[(size_t)(j + 1) * ld];
-      const c64 w2 = w[(size_t)(j + 2) * ld], w3 = w[(size_t)(j + 3) * ld];
-      d0 = d0 + cmulc(v0, w0) + cmulc(v2, w2);
-      d1 = d1 + cmulc(v1, w1) + cmulc(v3, w3);
+  const int nr = n - 2;
+  const int ll = min(l, n - 1);
+  const c64* __restrict__ row = s.A + (size_t)ll * n;
+  for (int t0 = 0; t0 < nr; t0 += 8) {
+    c64 vv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = min(t0 + u, nr - 1);
+      const int k = adjoint ? t : nr - 1 - t;
+      vv[u] = row[k];
+      if (!(l > k && l < n)) vv[u] = {0.0, 0.0};
     }
-    for (; j < sp.j1; ++j) d0 = d0 + cmulc(v[(size_t)j * n], w[(size_t)j * ld]);
-    if (sp.grp < sp.g) part[l] = d0 + d1;
-    __syncthreads();
-    const c64 dl = combine_parts(part, sp, m);
-    if (l < m) dcol[l] = dl;
-    __syncthreads();
-    if (sp.grp < sp.g) {
-      const c64 d = dcol[sp.c];
-      j = sp.j0;
-      for (; j + 4 <= sp.j1; j += 4) {
-        const c64 v0 = v[(size_t)j * n], v1 = v[(size_t)(j + 1) * n];
-        const c64 v2 = v[(size_t)(j + 2) * n], v3 = v[(size_t)(j + 3) * n];
-        const c64 w0 = w[(size_t)j * ld], w1 = w[(size_t)(j + 1) * ld];
-        const c64 w2 = w[(size_t)(j + 2) * ld], w3 = w[(size_t)(j + 3) * ld];
-        w[(size_t)j * ld] = w0 - v0 * d;
-        w[(size_t)(j + 1) * ld] = w1 - v1 * d;
-        w[(size_t)(j + 2) * ld] = w2 - v2 * d;
-        w[(size_t)(j + 3) * ld] = w3 - v3 * d;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (t0 + u < nr) {
+        const c64 d = HALF ? wsum_c32(cmulc(vv[u], y)) : wsum_c(cmulc(vv[u], y));
+        y = y - vv[u] * d;
       }
-      for (; j < sp.j1; ++j) w[(size_t)j * ld] = w[(size_t)j * ld] - v[(size_t)j * n] * d;
     }
-    __syncthreads();
   }
-  if (l < n)
-    for (int i = 0; i < n; ++i) Wm[(size_t)i * ld + l] = Wm[(size_t)i * ld + l] * ph;
-  __syncthreads();
+  return y;
 }
 
-// out_c = sum_{j < n} f(c, j) for lane c < n, on split lanes (f reads LDS).
-template <class F>
-__device__ inline c64 split_sum(small_ws& s, int n, F f) {
-  const int l = threadIdx.x;
-  const lane_split sp = split_lanes(n);
-  c64 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
-  int j = sp.j0;
-  for (; j + 4 <= sp.j1; j += 4) {
-    const c64 f0 = f(sp.c, j), f1 = f(sp.c, j + 1), f2 = f(sp.c, j + 2), f3 = f(sp.c, j + 3);
-    a0 = a0 + f0 + f2;
-    a1 = a1 + f1 + f3;
-  }
-  for (; j < sp.j1; ++j) a0 = a0 + f(sp.c, j);
-  c64* part = (c64*)s.part;
-  if (sp.grp < sp.g) part[l] = a0 + a1;
-  __syncthreads();
-  const c64 r = combine_parts(part, sp, n);
-  __syncthreads();
-  return r;
-}
-
-// Products with W and X; the input vector is in LDS (b), lane l returns
-// entry l (zero for l >= n).
-__device__ inline c64 w_adj_mul(small_ws& s, int n, const c64* b) {   // W^H b
-  const int ld = n + 1;
-  const c64* Wm = s.W;
-  return split_sum(s, n, [&](int c, int i) __attribute__((always_inline)) {
-    return cmulc(Wm[(size_t)i * ld + c], b[i]);
-  });
-}
-
-__device__ inline c64 w_mul(small_ws& s, int n, const c64* b) {       // W b
-  const int ld = n + 1;
-  const c64* Wm = s.W;
-  return split_sum(s, n, [&](int c, int j) __attribute__((always_inline)) { return Wm[(size_t)c * ld + j] * b[j]; });
-}
-
-__device__ inline c64 x_mul(small_ws& s, int n, const c64* b) {       // X b (X symmetric)
-  const double* X = s.X;
-  return split_sum(s, n, [&](int c, int k) __attribute__((always_inline)) {
-    const double x = X[(size_t)k * n + c];
-    const c64 bk = b[k];
-    return c64{x * bk.re, x * bk.im};
-  });
-}
-
-// Stage lane values into b (LDS) for a product.
-__device__ inline void stage(c64* b, c64 v, int n) {
-  __syncthreads();
-  if ((int)threadIdx.x < n) b[threadIdx.x] = v;
-  __syncthreads();
+__device__ inline __attribute__((always_inline)) c64 q_apply(const small_ws& s, int n, c64 y, bool adjoint) {
+  return n <= 32 ? q_apply_w<true>(s, n, y, adjoint) : q_apply_w<false>(s, n, y, adjoint);
 }
 
 // ---------------------------------------------------------------- the solver
@@ -652,18 +619,14 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_lam
   const double pivmin = 1e-300 + 2.2e-16 * 2.2e-16 * tn;
   tri_factor(s, n, sigma, pivmin);
   const c64 ph = tri_phases(s, n);
-  build_w(s, n, ph);
-  build_x(s, n);
   // inverse iteration on T from a fixed, generic start vector, then x = W y
   c64 y = l < n ? c64{1.0 + 0.6180339887 * (double)((l * 7) % 11), 0.0} : c64{0.0, 0.0};
   for (int it = 0; it < SMALL_INVIT; ++it) {
-    stage(s.u, y, n);
-    y = x_mul(s, n, s.u);
+    y = tri_solve(s, n, y);
     const double nr = sqrt(wsum(norm2(y)));
     y = {y.re / nr, y.im / nr};
   }
-  stage(s.u, y, n);
-  c64 xl = w_mul(s, n, s.u);
+  c64 xl = q_apply(s, n, y * ph, false);
   {
     const double nr = sqrt(wsum(l < n ? norm2(xl) : 0.0));
     xl = l < n ? c64{xl.re / nr, xl.im / nr} : c64{0.0, 0.0};
@@ -722,13 +685,10 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_lam
       qi.add_dd(yim); qi.add_prod(-mu.hi, xl.im); qi.add(-mu.lo * xl.im);
       r = {dd_val(qr.result()), dd_val(qi.result())};
     }
-    // correction c = W X W^H r
-    stage(s.u, r, n);
-    const c64 t1 = w_adj_mul(s, n, s.u);
-    stage(s.u, t1, n);
-    const c64 t2 = x_mul(s, n, s.u);
-    stage(s.u, t2, n);
-    const c64 cl = w_mul(s, n, s.u);
+    // correction c = W (T - sigma I)^{-1} W^H r
+    const c64 t1 = cmulc(ph, q_apply(s, n, r, true));
+    const c64 t2 = tri_solve(s, n, t1);
+    const c64 cl = q_apply(s, n, t2 * ph, false);
     const c64 xn = l < n ? xl - cl : c64{0.0, 0.0};
     const double nrm = sqrt(wsum(norm2(xn)));
     // the change of direction: with c = alpha x + c_perp, x - c turns by

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_sample(batch_ref br) {
 //   Ax = Fx^H D_u Fx, By = Fy^T D_v conj(Fy), C = Fx^H D_u Khat D_v conj(Fy),
 // u = wY, v = wX, F[i][x] = w_i^x (the separable weighted fit with per-axis
 // Tikhonov terms), then is divided by its complex sum (real part kept).
-__device__ inline void learned_assembly(const c64* tw, int S, int k, const double* wts, c64* Kh, c64* tb, c64* xt,
+__device__ inline __attribute__((always_inline)) void learned_assembly(const c64* tw, int S, int k, const double* wts, c64* Kh, c64* tb, c64* xt,
                                         double* K, cbp_diag* diag, int c);
 
 // LDS of the plain finalize: twiddles, the two diagonal blocks, the solver.
@@ -237,7 +237,7 @@ __host__ __device__ inline size_t fin_base_bytes(int S) {
   return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) + small_lds_bytes(2 * S);
 }
 
-__device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c64* pq, cdd* cbuf, double* K1,
+__device__ inline __attribute__((always_inline)) void finalize_frame(const c64* xvec, int S, int k1, int k2, c64* pq, cdd* cbuf, double* K1,
                                       double* K2, cbp_diag* diag, char* sm_fin, const double* wts) {
   const int N = k1 + k2, n2 = 2 * S, SS = S * S;
   const int tid = threadIdx.x;
@@ -442,7 +442,7 @@ __device__ inline void finalize_frame(const c64* xvec, int S, int k1, int k2, c6
   }
 }
 
-__device__ inline void learned_assembly(const c64* tw, int S, int k, const double* wts, c64* Kh, c64* tb, c64* xt,
+__device__ inline __attribute__((always_inline)) void learned_assembly(const c64* tw, int S, int k, const double* wts, c64* Kh, c64* tb, c64* xt,
                                         double* K, cbp_diag* diag, int c) {
   const int tid = threadIdx.x, kk = k * k;
   const float rS = 1.0f / (float)S, rk = 1.0f / (float)k;
@@ -552,11 +552,10 @@ __global__ __launch_bounds__(SMALL_NT) void k_finalize(batch_ref br, int plain_o
   extern __shared__ __attribute__((aligned(16))) char sm_fin[];
   for_items<Q_FINALIZE>(br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
     cdd* cb = c_off ? (cdd*)(sm_fin + c_off) : d.cbuf;
-    if (plain_only)
-      finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, cb, d.Kalt, d.Kalt + CBP_MAX_K * CBP_MAX_K, nullptr, sm_fin,
-                     nullptr);
-    else
-      finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, cb, d.K1, d.K2, d.diag, sm_fin, d.wts);
+    double* K1 = plain_only ? d.Kalt : d.K1;
+    double* K2 = plain_only ? d.Kalt + CBP_MAX_K * CBP_MAX_K : d.K2;
+    finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, cb, K1, K2, plain_only ? nullptr : d.diag, sm_fin,
+                   plain_only ? nullptr : d.wts);
   });
 }
 
