@@ -592,23 +592,24 @@ __device__ inline __attribute__((always_inline)) c64 q_apply(const small_ws& s, 
 // ---------------------------------------------------------------- the solver
 // acc.get(i, j) gives G in double-double; G's rounded value must already be
 // in s.A (destroyed).  Leaves the unit eigenvector in s.x (lane l also keeps
-// entry l) and returns mu = x^H G x (dd).  *lam1 receives the second
-// smallest eigenvalue when want_lam1 (else NaN); *steps the number of
-// refinement steps.
+// entry l) and *steps the number of refinement steps.  With want_diag it
+// returns mu = x^H G x (dd) of that vector and *lam1 receives the second
+// smallest eigenvalue; without, both are NaN (the product G x of the final
+// vector serves only mu, so it is skipped).
 template <class Acc>
-__device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_lam1, double* lam1, int* steps) {
+__device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_diag, double* lam1, int* steps) {
   const int l = threadIdx.x;
   if (n == 1) {
     if (l == 0) s.x[0] = {1.0, 0.0};
     __syncthreads();
     *lam1 = __builtin_nan("");
     *steps = 0;
-    return acc.get(0, 0).re;
+    return want_diag ? acc.get(0, 0).re : dd{__builtin_nan(""), 0.0};
   }
   small_tridiag(s, n);
   double lo0, hi0, tn;
   small_bisect(s, n, 1, &lo0, &hi0, &tn);
-  if (want_lam1) {
+  if (want_diag) {
     double lo1, hi1, tn1;
     small_bisect(s, n, 2, &lo1, &hi1, &tn1);
     *lam1 = 0.5 * (lo1 + hi1);
@@ -705,6 +706,11 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_lam
     // the linear rate dn / dprev of the last two, is below 4e-15
     done = !(dn > 4e-15) || (dprev > 0.0 && dn * dn <= 4e-15 * dprev);
     dprev = dn;
+    if (done && !want_diag) {
+      ++it;
+      mu = {__builtin_nan(""), 0.0};
+      break;
+    }
   }
   *steps = it;
   return mu;

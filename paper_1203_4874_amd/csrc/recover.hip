@@ -208,7 +208,6 @@ __global__ __launch_bounds__(SMALL_NT) void k_sample(batch_ref br) {
     }
     if (l == 0) {
       const double l0 = dd_val(mu);
-      d.lam0[pass * S + j] = l0;
       if (diag) {
         diag->sample_lambda0[pass][j] = l0;
         diag->sample_lambda1[pass][j] = lam1;
