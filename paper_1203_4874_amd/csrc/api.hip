@@ -113,7 +113,7 @@ struct tuning {
   int wg_per_cu;   // persistent-grid cap of the streaming queues, workgroups per CU (0: one per item)
   int fft_order;   // radix pass order of the row and column FFTs
 };
-constexpr tuning kDefaultTuning = {32, 0, 0, 0};
+constexpr tuning kDefaultTuning = {128, 0, 0, 0};
 
 // Columns per column-pass strip: a power of two (the kernel splits indices
 // with shifts), at most 8.
@@ -669,7 +669,7 @@ tuning autotune(dev_state& ds, const std::vector<frame_req>& reqs, const cbp_opt
     }
   };
   for (int order = 1; order < FFT_ORDERS; ++order) { tuning t = best; t.fft_order = order; consider(t); }
-  for (int rows : {64, 128, 256}) { tuning t = best; t.fold_rows = rows; consider(t); }
+  for (int rows : {32, 64, 128, 256}) { tuning t = best; t.fold_rows = rows; consider(t); }
   for (int cw : {1, 2, 4, 8}) { tuning t = best; t.cw = cw; consider(t); }
   for (int wpc : {2, 4, 8, 16}) { tuning t = best; t.wg_per_cu = wpc; consider(t); }
   *best_ms = bms;
@@ -810,7 +810,7 @@ cbp_status cbp_eval_unit_circle(const cbp_image* b, int32_t S, double* ex, doubl
   d.ex = (c64*)ex;
   d.ey = (c64*)ey;
   int items[Q_COUNT] = {};
-  items[Q_FOLD] = ((d.Wmax + 63) / 64) * d.RG;
+  items[Q_FOLD] = ((d.Wmax + 63) / 64) * S * d.RG;
   items[Q_EVAL_COLS] = (d.Wmax + 15) / 16;
   items[Q_EVAL_ROWS] = (d.Hmax + 3) / 4;
   std::vector<char> hb(head, 0);

@@ -6,8 +6,9 @@
 //   EY[i][y] = sum_x B[y][x] w_i^x = sum_{r<S} w_i^r G[y][r],  G[y][r] = sum_{x = r mod S} B[y][x]
 // i.e. a fold of the frame modulo S along one axis (one FP64 add per pixel)
 // followed by an S-point DFT.  All accumulation is FP64 whatever the frame
-// type.  The column fold runs over row groups (partials per group, summed in
-// a fixed order by the evaluation kernel), the row fold one row per wave.
+// type.  The column fold runs over row groups and residues (partials per
+// group, summed in a fixed order by the evaluation kernel), the row fold one
+// row per wave.
 //
 // Layouts (cf = 2*channel + frame):
 //   fpart [RG][ncf][S][Wmax] double, EX [ncf][S][Wmax] c64, EY [ncf][S][Hmax] c64.
@@ -37,13 +38,18 @@ __device__ inline void unit_twiddles(c64* tw, int S) {
 }
 
 // Column fold over rows [g*rpg, (g+1)*rpg) of one (channel, frame): one
-// thread per column, S independent accumulators, 64 columns per item.
-// Items: (column block, row group, cf).
+// thread per (column, residue r), summing the rows y = r mod S of the group
+// in increasing order (four loads in flight), 64 columns per item.
+// Items: (column block, residue, row group, cf).
 template <typename T>
 __global__ __launch_bounds__(64) void k_fold_cols(batch_ref br) {
   for_items<Q_FOLD>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+    const int S = d.S;
     const int nx = (d.Wmax + 63) / 64;
-    const int bx = item % nx, rest = item / nx;
+    const int bx = item % nx;
+    int rest = item / nx;
+    const int r = rest % S;
+    rest /= S;
     const int g = rest % d.RG, cf = rest / d.RG;
     const T* b;
     int64_t pitch;
@@ -51,22 +57,20 @@ __global__ __launch_bounds__(64) void k_fold_cols(batch_ref br) {
     pick(d, cf, b, pitch, H, W);
     const int x = bx * 64 + threadIdx.x;
     if (x >= W) return;
-    const int S = d.S;
-    const int y0 = g * d.rpg;
-    const int y1 = min(y0 + d.rpg, H);
-    double acc[CBP_MAX_S];
-#pragma unroll
-    for (int r = 0; r < CBP_MAX_S; ++r) acc[r] = 0.0;
-    for (int yb = y0; yb < y1; yb += S) {
-      const T* col = b + (int64_t)yb * pitch + x;
-#pragma unroll
-      for (int r = 0; r < CBP_MAX_S; ++r)
-        if (r < S && yb + r < y1) acc[r] += (double)col[(int64_t)r * pitch];
+    const int y1 = min(g * d.rpg + d.rpg, H);
+    const T* col = b + x;
+    double acc = 0.0;
+    int y = g * d.rpg + r;
+    for (; y + 3 * S < y1; y += 4 * S) {
+      const T v0 = col[(int64_t)y * pitch], v1 = col[(int64_t)(y + S) * pitch];
+      const T v2 = col[(int64_t)(y + 2 * S) * pitch], v3 = col[(int64_t)(y + 3 * S) * pitch];
+      acc += (double)v0;
+      acc += (double)v1;
+      acc += (double)v2;
+      acc += (double)v3;
     }
-    double* out = d.fpart + ((size_t)g * d.ncf + cf) * S * (size_t)d.Wmax + x;
-#pragma unroll
-    for (int r = 0; r < CBP_MAX_S; ++r)
-      if (r < S) out[(size_t)r * d.Wmax] = acc[r];
+    for (; y < y1; y += S) acc += (double)col[(int64_t)y * pitch];
+    d.fpart[(((size_t)g * d.ncf + cf) * S + r) * (size_t)d.Wmax + x] = acc;
   });
 }
 

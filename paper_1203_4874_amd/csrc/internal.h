@@ -90,7 +90,7 @@ inline int queue_items(int q, const frame_plan& p) {
   const int ncf = 2 * p.nch;
   switch (q) {
     case Q_DIAG: return 1;
-    case Q_FOLD: return ((p.Wmax + 63) / 64) * p.RG * ncf;
+    case Q_FOLD: return ((p.Wmax + 63) / 64) * p.S * p.RG * ncf;
     case Q_EVAL_COLS: return ((p.Wmax + 15) / 16) * ncf;
     case Q_EVAL_ROWS: return ((p.Hmax + 3) / 4) * ncf;
     case Q_ROW_FWD: return p.Hmax * p.nch;
