@@ -30,7 +30,7 @@
  *   - Kernels are FP64, row-major k_c x k_c, in DEVICE memory.
  *   - The caller owns every buffer, including the workspace, whose size comes
  *     from cbp_workspace_size().  The library allocates no device memory for
- *     data; it keeps per device a side stream, events, a small ring of pinned
+ *     data; it keeps per device a capture stream, events, a small ring of pinned
  *     host staging buffers (frame descriptors of batched calls), the HIP
  *     graphs of CBP_FLAG_GRAPH calls and the autotuner's choices, until the
  *     process ends.

@@ -301,15 +301,17 @@ struct graph_entry {
 };
 constexpr size_t kMaxGraphs = 32;
 
-// Side stream, events, staging ring, graph and tuning caches of one device
-// (created once; every stream at the default priority).  The row pass
-// depends only on the input frames, so it runs on the side stream beside the
-// column fold -> Gram -> eigen-solve chain, which occupies few compute units.
+// Capture stream, events, staging ring, graph and tuning caches of one
+// device (created once; every stream at the default priority).  A call's
+// kernels all run in order on the caller's stream: running the row pass on a
+// second stream beside the column fold -> Gram chain measured slower than the
+// plain order, the two cross-stream event waits costing more than the
+// overlap gained.
 struct dev_state {
   std::mutex launch_mu;  // one launch sequence at a time per device (the events are shared)
   bool ready = false;
-  hipStream_t side = nullptr, cap = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_side = nullptr, t0 = nullptr, t1 = nullptr;
+  hipStream_t cap = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
   pinned_slot ring[kRing];
   int next = 0;
   std::map<std::string, graph_entry> graphs;
@@ -327,10 +329,7 @@ dev_state* get_dev() {
   std::lock_guard<std::mutex> g(mu);
   dev_state& f = states[dev];
   if (!f.ready) {
-    if (note("hipStreamCreateWithFlags", hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking)) != hipSuccess ||
-        note("hipStreamCreateWithFlags", hipStreamCreateWithFlags(&f.cap, hipStreamNonBlocking)) != hipSuccess ||
-        note("hipEventCreateWithFlags", hipEventCreateWithFlags(&f.ev_fork, hipEventDisableTiming)) != hipSuccess ||
-        note("hipEventCreateWithFlags", hipEventCreateWithFlags(&f.ev_side, hipEventDisableTiming)) != hipSuccess ||
+    if (note("hipStreamCreateWithFlags", hipStreamCreateWithFlags(&f.cap, hipStreamNonBlocking)) != hipSuccess ||
         note("hipEventCreate", hipEventCreate(&f.t0)) != hipSuccess ||
         note("hipEventCreate", hipEventCreate(&f.t1)) != hipSuccess)
       return nullptr;
@@ -371,20 +370,15 @@ template <typename T>
 hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool diag, hipStream_t st) {
   const batch_ref b = {cv.descs, cv.starts, cv.nf};
   auto br = [&](int) { return b; };
-  hipStream_t side = ds.side;
-  CBP_TRY(hipEventRecord(ds.ev_fork, st));
-  CBP_TRY(hipStreamWaitEvent(side, ds.ev_fork, 0));
   if (latent) {
-    CBP_TRY(launch_twiddles<T>(br(Q_TWID), cv.grid[Q_TWID], side));
-    CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, side));
+    CBP_TRY(launch_twiddles<T>(br(Q_TWID), cv.grid[Q_TWID], st));
+    CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, st));
   }
-  else CBP_TRY(launch_eval_rows<T>(br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], side));
-  CBP_TRY(hipEventRecord(ds.ev_side, side));
+  else CBP_TRY(launch_eval_rows<T>(br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], st));
   if (diag) CBP_TRY(launch_diag_init(br(Q_DIAG), cv.grid[Q_DIAG], st));
   CBP_TRY(launch_fold<T>(br(Q_FOLD), cv.grid[Q_FOLD], st));
   CBP_TRY(launch_eval_cols(br(Q_EVAL_COLS), cv.grid[Q_EVAL_COLS], st));
   // join: the Gram needs the row evaluation (and the column pass the row spectra)
-  CBP_TRY(hipStreamWaitEvent(st, ds.ev_side, 0));
   if (cv.gram_fmt < 0) CBP_TRY(launch_gram(br(Q_GRAM), cv.grid[Q_GRAM], st));
   else CBP_TRY(launch_gram_mfma(br(Q_GRAMM), cv.grid[Q_GRAMM], cv.gram_fmt, cv.maxStride, st));
   CBP_TRY(launch_sample(br(Q_SAMPLE), cv.grid[Q_SAMPLE], cv.maxN, st));
