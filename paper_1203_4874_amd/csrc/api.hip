@@ -370,13 +370,11 @@ template <typename T>
 hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool diag, hipStream_t st) {
   const batch_ref b = {cv.descs, cv.starts, cv.nf};
   auto br = [&](int) { return b; };
-  if (latent) {
-    CBP_TRY(launch_twiddles<T>(br(Q_TWID), cv.grid[Q_TWID], st));
-    CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, st));
-  }
-  else CBP_TRY(launch_eval_rows<T>(br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], st));
   if (diag) CBP_TRY(launch_diag_init(br(Q_DIAG), cv.grid[Q_DIAG], st));
-  CBP_TRY(launch_fold<T>(br(Q_FOLD), cv.grid[Q_FOLD], st));
+  // the column fold and, for the row pass that follows, the twiddle tables
+  CBP_TRY(launch_fold<T>(br(Q_FOLD), cv.grid[Q_FOLD], latent ? cv.grid[Q_TWID] : 0, st));
+  if (latent) CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, st));
+  else CBP_TRY(launch_eval_rows<T>(br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], st));
   CBP_TRY(launch_eval_cols(br(Q_EVAL_COLS), cv.grid[Q_EVAL_COLS], st));
   // join: the Gram needs the row evaluation (and the column pass the row spectra)
   if (cv.gram_fmt < 0) CBP_TRY(launch_gram(br(Q_GRAM), cv.grid[Q_GRAM], st));
@@ -819,8 +817,8 @@ cbp_status cbp_eval_unit_circle(const cbp_image* b, int32_t S, double* ex, doubl
   (void)hipGetLastError();
   auto run = [&]() -> hipError_t {
     CBP_TRY(upload_bytes(*ds, ws, hb, st));
-    if (b->dtype == CBP_F32) CBP_TRY(launch_fold<float>(br, grid_for(items[Q_FOLD], 0), st));
-    else CBP_TRY(launch_fold<double>(br, grid_for(items[Q_FOLD], 0), st));
+    if (b->dtype == CBP_F32) CBP_TRY(launch_fold<float>(br, grid_for(items[Q_FOLD], 0), 0, st));
+    else CBP_TRY(launch_fold<double>(br, grid_for(items[Q_FOLD], 0), 0, st));
     CBP_TRY(launch_eval_cols(br, grid_for(items[Q_EVAL_COLS], 0), st));
     if (b->dtype == CBP_F32) CBP_TRY(launch_eval_rows<float>(br, grid_for(items[Q_EVAL_ROWS], 0), st));
     else CBP_TRY(launch_eval_rows<double>(br, grid_for(items[Q_EVAL_ROWS], 0), st));
@@ -862,10 +860,10 @@ cbp_status cbp_sample_grams(const cbp_image* b1, const cbp_image* b2, int32_t m,
   auto run = [&]() -> hipError_t {
     CBP_TRY(upload_head(*ds, bb, st));
     if (b1->dtype == CBP_F32) {
-      CBP_TRY(launch_fold<float>(br, cv.grid[Q_FOLD], st));
+      CBP_TRY(launch_fold<float>(br, cv.grid[Q_FOLD], 0, st));
       CBP_TRY(launch_eval_rows<float>(br, cv.grid[Q_EVAL_ROWS], st));
     } else {
-      CBP_TRY(launch_fold<double>(br, cv.grid[Q_FOLD], st));
+      CBP_TRY(launch_fold<double>(br, cv.grid[Q_FOLD], 0, st));
       CBP_TRY(launch_eval_rows<double>(br, cv.grid[Q_EVAL_ROWS], st));
     }
     CBP_TRY(launch_eval_cols(br, cv.grid[Q_EVAL_COLS], st));

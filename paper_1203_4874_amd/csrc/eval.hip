@@ -41,9 +41,39 @@ __device__ inline void unit_twiddles(c64* tw, int S) {
 // thread per (column, residue r), summing the rows y = r mod S of the group
 // in increasing order (four loads in flight), 64 columns per item.
 // Items: (column block, residue, row group, cf).
+// Twiddle tables exp(-2 pi i t / P) of the row and column FFTs (the row
+// table also in FP64 for the kernel spectra); an item is 256 consecutive
+// indices of [0, Px + Py), the row table first.  The FP64 value is rounded
+// once to T, so an entry equals what an in-place evaluation would give.
 template <typename T>
-__global__ __launch_bounds__(64) void k_fold_cols(batch_ref br) {
-  for_items<Q_FOLD>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+__device__ inline void twiddle_item(const frame_desc& d, int item) {
+  for (int u = threadIdx.x; u < 256; u += blockDim.x) {
+    const int t = item * 256 + u;
+    if (t < d.Px) {
+      double s, c;
+      sincospi(-2.0 * (double)t / (double)d.Px, &s, &c);
+      d.twxd[t] = {c, s};
+      ((cplx<T>*)d.twx)[t] = {T(c), T(s)};
+    } else if (t < d.Px + d.Py) {
+      const int v = t - d.Px;
+      double s, c;
+      sincospi(-2.0 * (double)v / (double)d.Py, &s, &c);
+      ((cplx<T>*)d.twy)[v] = {T(c), T(s)};
+    }
+  }
+}
+
+// Workgroups [0, gf) fold; the rest fill the twiddle tables.
+template <typename T>
+__global__ __launch_bounds__(64) void k_fold_cols(batch_ref br, int gf) {
+  if ((int)blockIdx.x >= gf) {
+    for_items_part<Q_TWID>(br, (int)blockIdx.x - gf, (int)gridDim.x - gf,
+                           [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+                             twiddle_item<T>(d, item);
+                           });
+    return;
+  }
+  for_items_part<Q_FOLD>(br, (int)blockIdx.x, gf, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const int S = d.S;
     const int nx = (d.Wmax + 63) / 64;
     const int bx = item % nx;
@@ -173,9 +203,9 @@ __global__ __launch_bounds__(256) void k_eval_rows(batch_ref br) {
 }  // namespace
 
 template <typename T>
-hipError_t launch_fold(const batch_ref& br, int grid, hipStream_t st) {
+hipError_t launch_fold(const batch_ref& br, int grid, int twid_grid, hipStream_t st) {
   prof_begin(PH_FOLD, st);
-  hipLaunchKernelGGL(k_fold_cols<T>, dim3(grid), dim3(64), 0, st, br);
+  hipLaunchKernelGGL(k_fold_cols<T>, dim3(grid + twid_grid), dim3(64), 0, st, br, grid);
   prof_end(PH_FOLD, st);
   return hipGetLastError();
 }
@@ -195,8 +225,8 @@ hipError_t launch_eval_rows(const batch_ref& br, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-template hipError_t launch_fold<float>(const batch_ref&, int, hipStream_t);
-template hipError_t launch_fold<double>(const batch_ref&, int, hipStream_t);
+template hipError_t launch_fold<float>(const batch_ref&, int, int, hipStream_t);
+template hipError_t launch_fold<double>(const batch_ref&, int, int, hipStream_t);
 template hipError_t launch_eval_rows<float>(const batch_ref&, int, hipStream_t);
 template hipError_t launch_eval_rows<double>(const batch_ref&, int, hipStream_t);
 

@@ -24,28 +24,6 @@ namespace cbp {
 
 namespace {
 
-// ---------------------------------------------------------------- tables
-// Items: 256 consecutive indices of [0, Px + Py): x tables for t < Px, the y
-// table after.  The FP64 value is rounded once to T, so a table entry equals
-// what an in-place evaluation of exp(-2 pi i t / P) would give.
-template <typename T>
-__global__ __launch_bounds__(256) void k_twiddles(batch_ref br) {
-  for_items<Q_TWID>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
-    const int t = item * 256 + (int)threadIdx.x;
-    if (t < d.Px) {
-      double s, c;
-      sincospi(-2.0 * (double)t / (double)d.Px, &s, &c);
-      d.twxd[t] = {c, s};
-      ((cplx<T>*)d.twx)[t] = {T(c), T(s)};
-    } else if (t < d.Px + d.Py) {
-      const int u = t - d.Px;
-      double s, c;
-      sincospi(-2.0 * (double)u / (double)d.Py, &s, &c);
-      ((cplx<T>*)d.twy)[u] = {T(c), T(s)};
-    }
-  });
-}
-
 // Run all passes of plan p on nbatch transforms (stride bstride) held in a;
 // b is the ping-pong partner.  Returns the buffer holding the result.
 template <int DIR, typename T>
@@ -324,14 +302,7 @@ hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t 
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_twiddles(const batch_ref& br, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_twiddles<T>, dim3(grid), dim3(256), 0, st, br);
-  return hipGetLastError();
-}
 
-template hipError_t launch_twiddles<float>(const batch_ref&, int, hipStream_t);
-template hipError_t launch_twiddles<double>(const batch_ref&, int, hipStream_t);
 template hipError_t launch_row_fwd<float>(const batch_ref&, int, int, int, hipStream_t);
 template hipError_t launch_row_fwd<double>(const batch_ref&, int, int, int, hipStream_t);
 template hipError_t launch_col<float>(const batch_ref&, int, int, int, hipStream_t);

@@ -118,8 +118,7 @@ struct batch_ref {
 // grid that is a multiple of 8, XCD x takes the contiguous item range
 // [x T / 8, (x + 1) T / 8), so neighbouring items (the lags of one sample,
 // adjacent rows and strips of one frame) share their inputs in one XCD's L2.
-__device__ inline void xcd_items(int T, int& first, int& end, int& step) {
-  const int G = gridDim.x, b = blockIdx.x;
+__device__ inline void xcd_items(int T, int b, int G, int& first, int& end, int& step) {
   if (G < 8 || (G & 7) != 0) {
     first = b;
     end = T;
@@ -132,17 +131,19 @@ __device__ inline void xcd_items(int T, int& first, int& end, int& step) {
   step = G >> 3;
 }
 
-// Run body(frame, item) for every item of queue Q owned by this workgroup.
-// The body may use __syncthreads(); a barrier separates consecutive items.
+// Run body(frame, item) for every item of queue Q owned by workgroup b of
+// the G workgroups serving Q (a launch may split its workgroups between
+// queues).  The body may use __syncthreads(); a barrier separates
+// consecutive items.
 template <int Q, typename F>
-__device__ inline void for_items(const batch_ref& br, F&& body) {
+__device__ inline void for_items_part(const batch_ref& br, int b, int G, F&& body) {
   __shared__ int st[BATCH_CHUNK + 1];
   const int nf = br.nframes;
   const int* s = br.starts + (size_t)Q * (nf + 1);
   for (int t = threadIdx.x; t <= nf; t += blockDim.x) st[t] = s[t];
   __syncthreads();
   int first, end, step;
-  xcd_items(__builtin_amdgcn_readfirstlane(st[nf]), first, end, step);
+  xcd_items(__builtin_amdgcn_readfirstlane(st[nf]), b, G, first, end, step);
   // descriptors are read-only while kernels run: reading them through the
   // constant address space with a wave-uniform index lets the scalar unit
   // load them into SGPRs
@@ -165,6 +166,12 @@ __device__ inline void for_items(const batch_ref& br, F&& body) {
     __syncthreads();
   }
 }
+
+// Every item of queue Q owned by this workgroup of the whole launch.
+template <int Q, typename F>
+__device__ inline void for_items(const batch_ref& br, F&& body) {
+  for_items_part<Q>(br, (int)blockIdx.x, (int)gridDim.x, body);
+}
 #endif
 
 // ---------------------------------------------------------------- phase timing
@@ -182,9 +189,11 @@ void prof_end(int phase, hipStream_t st);
 // ---------------------------------------------------------------- launchers
 // Each launches one queue over `grid` workgroups (any grid >= 1 covers every
 // item; a multiple of 8 enables the XCD-aware item ranges).
-// eval.hip
+// eval.hip.  launch_fold runs the column fold on `grid` workgroups and, on
+// twid_grid more, the twiddle tables of every frame (items of Q_TWID; the
+// FFT passes need them, the fold does not, so they share one launch).
 template <typename T>
-hipError_t launch_fold(const batch_ref& br, int grid, hipStream_t st);
+hipError_t launch_fold(const batch_ref& br, int grid, int twid_grid, hipStream_t st);
 hipError_t launch_eval_cols(const batch_ref& br, int grid, hipStream_t st);
 template <typename T>
 hipError_t launch_eval_rows(const batch_ref& br, int grid, hipStream_t st);
@@ -220,9 +229,6 @@ template <typename T>
 hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st);
 template <typename T>
 hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t st);
-// the twiddle tables of every frame (items of Q_TWID; before the FFT passes)
-template <typename T>
-hipError_t launch_twiddles(const batch_ref& br, int grid, hipStream_t st);
 size_t row_lds_bytes(int N, int esize);
 size_t col_lds_bytes(int N, int cw, int esize);
 void set_recover_attrs();
