@@ -76,12 +76,14 @@ def source_hash(names):
 def eig_flops(n, refine_steps, invit=3, bisect_probes=64 * 8):
     """One Hermitian smallest-eigenvector solve of order n: Householder
     tridiagonalisation (16/3 n^3), Sturm multisection (about 5 n per probe),
-    W = QD from the reflectors (8/3 n^3), X = (T - sigma I)^{-1} (4 n^2),
-    `invit` inverse iterations with X (4 n^2 each), x = W y (8 n^2) and
-    `refine_steps` Newton corrections (a double-double Gram mat-vec, 40 n^2,
-    and the products with W^H, X and W, 20 n^2)."""
-    return (16.0 / 3.0 + 8.0 / 3.0) * n ** 3 + 4 * n * n + invit * 4 * n * n + 8 * n * n \
-        + bisect_probes * 5 * n + refine_steps * 60 * n * n
+    the LDL^T factors of T - sigma I (4 n), `invit` inverse iterations on T
+    (forward and backward substitution on a complex vector and its norm,
+    about 16 n each), x = Q D y with the reflectors applied one by one (a dot
+    and an axpy per reflector, 8 n^2) and `refine_steps` Newton corrections
+    (a double-double Gram mat-vec, 40 n^2, two reflector sweeps, 16 n^2, and
+    a tridiagonal solve)."""
+    return 16.0 / 3.0 * n ** 3 + bisect_probes * 5 * n + 4 * n + invit * 16 * n + 8 * n * n \
+        + refine_steps * (56 * n * n + 16 * n)
 
 
 def kernel_models(H1, W1, H2, W2, m, n, k1, k2, S, Py, Px, esize, refine_sample, refine_scale):
