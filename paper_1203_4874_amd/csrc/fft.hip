@@ -62,8 +62,9 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
     cplx<T>* b = a + N;
     const cplx<T>* tw = (const cplx<T>*)d.twx;   // global table (L1 / L2 resident)
     const int y = item % d.Hmax, ch = item / d.Hmax;
-    const T* r1 = (const T*)d.b1 + ch * d.cs1 + (int64_t)y * d.p1;
-    const T* r2 = (const T*)d.b2 + ch * d.cs2 + (int64_t)y * d.p2;
+    // row pointers clamped to each frame's last row (rows past it read as zero)
+    const T* r1 = (const T*)d.b1 + ch * d.cs1 + (int64_t)min(y, d.H1 - 1) * d.p1;
+    const T* r2 = (const T*)d.b2 + ch * d.cs2 + (int64_t)min(y, d.H2 - 1) * d.p2;
     const bool in1 = y < d.H1, in2 = y < d.H2;
     if (with_ey)
       for (int t = threadIdx.x; t < d.S; t += blockDim.x) {
@@ -71,10 +72,24 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
         sincospi(-2.0 * (double)t / (double)d.S, &sn, &cs);
         twS[t] = {cs, sn};
       }
-    for (int x = threadIdx.x; x < N; x += blockDim.x) {
-      const T u = (in1 && x < d.W1) ? r1[x] : T(0);
-      const T w = (in2 && x < d.W2) ? r2[x] : T(0);
-      a[x] = {u, w};
+    // eight loads per frame and thread in flight, from clamped (always valid)
+    // addresses; entries outside the frame are zeroed afterwards
+    {
+      const int W1 = d.W1, W2 = d.W2;
+      for (int x0 = 0; x0 < N; x0 += 8 * (int)blockDim.x) {
+        T uv[8], wv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int x = x0 + t * (int)blockDim.x + (int)threadIdx.x;
+          uv[t] = r1[min(x, W1 - 1)];
+          wv[t] = r2[min(x, W2 - 1)];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int x = x0 + t * (int)blockDim.x + (int)threadIdx.x;
+          if (x < N) a[x] = {(in1 && x < W1) ? uv[t] : T(0), (in2 && x < W2) ? wv[t] : T(0)};
+        }
+      }
     }
     __syncthreads();
     if (with_ey) {
@@ -151,16 +166,29 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
     // load: element (y, f) with f = 2*col + frame; consecutive threads walk f
     // (adjacent columns of one row) for coalescing
     const int lnf = __builtin_ctz(nf);         // cw, hence nf, is a power of two
-    for (int e = threadIdx.x; e < nf * N; e += blockDim.x) {
-      const int y = e >> lnf, f = e & (nf - 1);
-      const int col = kx0 + (f >> 1);
-      const int fr = f & 1;
-      cplx<T> val = {T(0), T(0)};
-      if (col < hx) {
-        if (fr == 0 && y < H1) val = s1[(int64_t)y * hx + col];
-        if (fr == 1 && y < H2) val = s2[(int64_t)y * hx + col];
+    // eight loads per thread in flight from clamped (always valid) addresses;
+    // entries outside the frame or past the last column are zeroed afterwards
+    for (int e0 = 0; e0 < nf * N; e0 += 8 * (int)blockDim.x) {
+      cplx<T> v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int e = e0 + t * (int)blockDim.x + (int)threadIdx.x;
+        const int y = e >> lnf, f = e & (nf - 1);
+        const int col = min(kx0 + (f >> 1), hx - 1);
+        const int fr = f & 1;
+        const cplx<T>* src = fr ? s2 : s1;
+        v[t] = src[(int64_t)min(y, (fr ? H2 : H1) - 1) * hx + col];
       }
-      a[(size_t)f * N + y] = val;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int e = e0 + t * (int)blockDim.x + (int)threadIdx.x;
+        const int y = e >> lnf, f = e & (nf - 1);
+        const int fr = f & 1;
+        if (e < nf * N) {
+          const bool in = kx0 + (f >> 1) < hx && y < (fr ? H2 : H1);
+          a[(size_t)f * N + y] = in ? v[t] : cplx<T>{T(0), T(0)};
+        }
+      }
     }
     // kernel row DFTs at this strip's columns: kr[c][fr][yy] = sum_x K[yy][x] exp(-2 pi i kx x / Px)
     for (int e = threadIdx.x; e < cw * 2 * CBP_MAX_K; e += blockDim.x) {
@@ -171,14 +199,24 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
       const int kx = kx0 + c;
       double sr = 0.0, si = 0.0;
       if (yy < k && kx < hx) {
+        // eight (twiddle, coefficient) pairs loaded per batch, summed in x order
         int t = 0;
-        for (int x = 0; x < k; ++x) {
-          const c64 w = twd[t];
-          const double kv = K[yy * k + x];
-          sr += kv * w.re;
-          si += kv * w.im;
-          t += kx;
-          if (t >= Px) t -= Px;
+        for (int x0 = 0; x0 < k; x0 += 8) {
+          c64 w[8];
+          double kv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            w[u] = twd[t];
+            kv[u] = K[yy * k + min(x0 + u, k - 1)];
+            t += kx;
+            if (t >= Px) t -= Px;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (x0 + u < k) {
+              sr += kv[u] * w[u].re;
+              si += kv[u] * w[u].im;
+            }
         }
       }
       kr[e] = {T(sr), T(si)};
@@ -238,18 +276,29 @@ __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
     const cplx<T>* ua = (const cplx<T>*)d.u + (int64_t)ch * m * hx + (int64_t)ya * hx;
     const cplx<T>* ub = ua + hx;
     const bool hb = yb < m;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-      cplx<T> A, B;
-      const bool edge = (k == 0) || (2 * k == N);
-      if (k < hx) {
-        A = ua[k];
-        B = hb ? ub[k] : cplx<T>{T(0), T(0)};
-      } else {
-        A = conj(ua[N - k]);
-        B = hb ? conj(ub[N - k]) : cplx<T>{T(0), T(0)};
+    // eight index pairs per thread in flight: entry k < hx read directly,
+    // k >= hx as the conjugate of entry N - k (< hx); indices past N clamp
+    // to 0 and are discarded
+    const cplx<T>* ubv = hb ? ub : ua;
+    for (int k0 = 0; k0 < N; k0 += 8 * (int)blockDim.x) {
+      cplx<T> Av[8], Bv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = k0 + t * (int)blockDim.x + (int)threadIdx.x;
+        const int kk = k < hx ? k : max(N - k, 0);
+        Av[t] = ua[kk];
+        Bv[t] = ubv[kk];
       }
-      if (edge) { A.im = T(0); B.im = T(0); }
-      a[k] = {A.re - B.im, A.im + B.re};   // A + i B
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = k0 + t * (int)blockDim.x + (int)threadIdx.x;
+        if (k < N) {
+          cplx<T> A = Av[t], B = hb ? Bv[t] : cplx<T>{T(0), T(0)};
+          if (k >= hx) { A = conj(A); B = conj(B); }
+          if ((k == 0) || (2 * k == N)) { A.im = T(0); B.im = T(0); }
+          a[k] = {A.re - B.im, A.im + B.re};   // A + i B
+        }
+      }
     }
     __syncthreads();
     const cplx<T>* z = fft_lds<+1>(a, b, px, tw, 1, N);
