@@ -42,7 +42,7 @@ int smooth7(int n) {
 // for any frame within (maxH, maxW, maxk, S, nch) fits the size that
 // cbp_workspace_size() reports for those bounds.
 struct region_sizes {
-  size_t fpart, ex, ey, corr, xvec, pq, cbuf, kern, t, u, feat, wts, kalt, twxd, twx, twy;
+  size_t fpart, ex, ey, corr, xvec, pq, kern, t, u, feat, wts, kalt, twxd, twx, twy;
 };
 
 region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
@@ -56,7 +56,6 @@ region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
   r.corr = 2 * (size_t)S * (4 * (size_t)kmax - 1) * sizeof(cdd);
   r.xvec = 2 * (size_t)S * 2 * kmax * sizeof(c64);
   r.pq = 4 * (size_t)S * S * sizeof(c64);
-  r.cbuf = (size_t)S * S * sizeof(cdd);
   r.kern = 2 * (size_t)CBP_MAX_K * CBP_MAX_K * sizeof(double);
   r.t = (size_t)nch * Hmax * hx * 2 * esize;
   r.u = (size_t)nch * Hmax * hx * 2 * esize;
@@ -78,7 +77,6 @@ size_t layout(frame_plan* fp, const region_sizes& r) {
   fp->off_corr = take(r.corr);
   fp->off_xvec = take(r.xvec);
   fp->off_pq = take(r.pq);
-  fp->off_cbuf = take(r.cbuf);
   fp->off_kern = take(r.kern);
   fp->off_t1 = take(r.t);
   fp->off_t2 = take(r.t);
@@ -215,7 +213,6 @@ frame_desc make_desc(const frame_plan& fp, const cbp_image* b1, const cbp_image*
   d.corr = (cdd*)(ws + fp.off_corr);
   d.xvec = (c64*)(ws + fp.off_xvec);
   d.pq = (c64*)(ws + fp.off_pq);
-  d.cbuf = (cdd*)(ws + fp.off_cbuf);
   d.t1 = ws + fp.off_t1;
   d.t2 = ws + fp.off_t2;
   d.u = ws + fp.off_u;

@@ -39,7 +39,7 @@ struct frame_plan {
   int Py, Px, hx;          // FFT grid and half-spectrum width
   int cw;                  // columns per workgroup in the column pass
   fft_plan fy, fx;
-  size_t off_fpart, off_ex, off_ey, off_corr, off_xvec, off_pq, off_cbuf, off_kern,
+  size_t off_fpart, off_ex, off_ey, off_corr, off_xvec, off_pq, off_kern,
       off_t1, off_t2, off_u, off_feat, off_wts, off_kalt, off_twxd, off_twx, off_twy, total;
 };
 
@@ -61,7 +61,6 @@ struct frame_desc {
   cdd* corr;
   c64* xvec;
   c64* pq;
-  cdd* cbuf;
   void* t1;
   void* t2;
   void* u;

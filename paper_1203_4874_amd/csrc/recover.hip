@@ -236,7 +236,7 @@ __host__ __device__ inline size_t fin_base_bytes(int S) {
   return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) + small_lds_bytes(2 * S);
 }
 
-__device__ inline __attribute__((always_inline)) void finalize_frame(const c64* xvec, int S, int k1, int k2, c64* pq, cdd* cbuf, double* K1,
+__device__ inline __attribute__((always_inline)) void finalize_frame(const c64* xvec, int S, int k1, int k2, c64* pq, double* K1,
                                       double* K2, cbp_diag* diag, char* sm_fin, const double* wts) {
   const int N = k1 + k2, n2 = 2 * S, SS = S * S;
   const int tid = threadIdx.x;
@@ -251,9 +251,12 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
   c64* tbuf = w.A + 2 * SS;
   unit_twiddles(tw, S);
   // the cofactors evaluated on the other axis, pq = [P1, P2, Q1, Q2] (each
-  // [i][j], written by the sample solves), staged in the solver's W region
-  // (2S (2S + 1) >= 4 S^2 entries, free until the solve)
-  c64* pql = w.W;
+  // [i][j], written by the sample solves), staged in the solver's matrix
+  // region (4 S^2 entries, filled with H's rounding once they are read); the
+  // coupling block C (S^2 double-double entries) goes to the W region, which
+  // the solver leaves free, so every read of H is an LDS read
+  c64* pql = w.A;
+  cdd* cmat = (cdd*)w.W;
   for (int e0 = 0; e0 < 4 * SS; e0 += 8 * SMALL_NT) {   // eight loads in flight per lane
     c64 v[8];
 #pragma unroll
@@ -283,7 +286,7 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
       re.add_prod(-P.re, Q.re); re.add_prod(-P.im, Q.im);
       im.add_prod(-P.re, Q.im); im.add_prod(P.im, Q.re);
     }
-    cbuf[e] = cdd{re.result(), im.result()};
+    cmat[e] = cdd{re.result(), im.result()};
   }
   for (int t = tid; t < n2; t += SMALL_NT) {
     dot2 d;
@@ -311,7 +314,7 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
   }
   __threadfence_block();
   __syncthreads();
-  const scale_acc H{Da, Db, cbuf, S};
+  const scale_acc H{Da, Db, cmat, S};
   for (int e = tid; e < n2 * n2; e += SMALL_NT) {
     int r, c;
     split_index(e, n2, rn2, r, c);
@@ -545,15 +548,12 @@ __device__ inline __attribute__((always_inline)) void learned_assembly(const c64
 
 // Items: one per frame.  plain_only: the plain method's kernels into the
 // learned form's fallback slots (d.Kalt), ignoring the network's weights.
-// c_off: byte offset of the coupling block in LDS for every frame of the
-// launch (sized for the launch's largest S), or 0 to keep it in the workspace.
-__global__ __launch_bounds__(SMALL_NT) void k_finalize(batch_ref br, int plain_only, int c_off) {
+__global__ __launch_bounds__(SMALL_NT) void k_finalize(batch_ref br, int plain_only) {
   extern __shared__ __attribute__((aligned(16))) char sm_fin[];
   for_items<Q_FINALIZE>(br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
-    cdd* cb = c_off ? (cdd*)(sm_fin + c_off) : d.cbuf;
     double* K1 = plain_only ? d.Kalt : d.K1;
     double* K2 = plain_only ? d.Kalt + CBP_MAX_K * CBP_MAX_K : d.K2;
-    finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, cb, K1, K2, plain_only ? nullptr : d.diag, sm_fin,
+    finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, K1, K2, plain_only ? nullptr : d.diag, sm_fin,
                    plain_only ? nullptr : d.wts);
   });
 }
@@ -655,28 +655,16 @@ __global__ void k_diag_init(batch_ref br) {
 
 }  // namespace
 
-// LDS of the finalize without the coupling block: the plain part and, for
-// the learned assembly, T1 / Z1 (S^2) and the inversion's two vectors, taken
-// from the solver's W (2S (2S + 1) entries, the last region of the solver's
-// LDS) plus what they need beyond it.
-size_t fin_lds_core(int S, int learned) {
+// LDS of the finalize: the plain part (the coupling block lives in the
+// solver's W region) and, for the learned assembly, T1 / Z1 (S^2) and the
+// inversion's two vectors, taken from the same W region (2S (2S + 1)
+// entries, the last region of the solver's LDS) plus what they need beyond
+// it.
+size_t finalize_lds_bytes(int S, int learned) {
   const size_t base = fin_base_bytes(S);
   const size_t need = ((size_t)S * S + 2 * CBP_MAX_S) * sizeof(c64);
   const size_t have = (size_t)(2 * S) * (2 * S + 1) * sizeof(c64);
   return learned && need > have ? base + (need - have) : base;
-}
-
-// Byte offset of the scale system's coupling block C (S^2 double-double
-// entries) in LDS, after the core regions, when it fits (else 0: C stays in
-// the workspace); the refinement's products read it on every step.
-size_t fin_c_offset(int S, int learned) {
-  const size_t core = (fin_lds_core(S, learned) + 15) & ~(size_t)15;
-  return core + (size_t)S * S * sizeof(cdd) <= (size_t)158 * 1024 ? core : 0;
-}
-
-size_t finalize_lds_bytes(int S, int learned) {
-  const size_t c = fin_c_offset(S, learned);
-  return c ? c + (size_t)S * S * sizeof(cdd) : fin_lds_core(S, learned);
 }
 
 size_t sample_lds_bytes(int N) {
@@ -720,8 +708,7 @@ hipError_t launch_judge(const batch_ref& br, int grid, hipStream_t st) {
 hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned, int plain_only,
                            hipStream_t st) {
   prof_begin(PH_FINALIZE, st);
-  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(SMALL_NT), finalize_lds_bytes(maxS, learned), st, br, plain_only,
-                     (int)fin_c_offset(maxS, learned));
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(SMALL_NT), finalize_lds_bytes(maxS, learned), st, br, plain_only);
   prof_end(PH_FINALIZE, st);
   return hipGetLastError();
 }
