@@ -288,29 +288,40 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
     }
     cmat[e] = cdd{re.result(), im.result()};
   }
+  // diagonal blocks: Da[t] = sum over (c, i) of w |P_c[i][t]|^2, Db[t] =
+  // sum over (c, j) of w |Q_c[t][j]|^2, in that order, with the entries
+  // read eight at a time (clamped indices; the extra reads are not summed)
   for (int t = tid; t < n2; t += SMALL_NT) {
+    const bool isa = t < S;
+    const int tt = isa ? t : t - S;
     dot2 d;
     d.init();
-    if (t < S) {
-      for (int c = 0; c < 2; ++c)
-        for (int i = 0; i < S; ++i) {
-          const c64 P = pql[(size_t)c * SS + i * S + t];
-          const double W = wts ? wts[t] * wts[S + i] : 1.0;
-          if (wts) { d.add_prod(W * P.re, P.re); d.add_prod(W * P.im, P.im); }
-          else { d.add_prod(P.re, P.re); d.add_prod(P.im, P.im); }
+    for (int q0 = 0; q0 < 2 * S; q0 += 8) {
+      c64 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = min(q0 + u, 2 * S - 1);
+        const int c = q >= S, r = q - c * S;
+        v[u] = pql[isa ? (size_t)c * SS + r * S + tt : (size_t)(2 + c) * SS + tt * S + r];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u;
+        if (q < 2 * S) {
+          const int r = q >= S ? q - S : q;
+          if (wts) {
+            const double W = isa ? wts[tt] * wts[S + r] : wts[r] * wts[S + tt];
+            d.add_prod(W * v[u].re, v[u].re);
+            d.add_prod(W * v[u].im, v[u].im);
+          } else {
+            d.add_prod(v[u].re, v[u].re);
+            d.add_prod(v[u].im, v[u].im);
+          }
         }
-      Da[t] = d.result();
-    } else {
-      const int i = t - S;
-      for (int c = 0; c < 2; ++c)
-        for (int jj = 0; jj < S; ++jj) {
-          const c64 Q = pql[(size_t)(2 + c) * SS + i * S + jj];
-          const double W = wts ? wts[jj] * wts[S + i] : 1.0;
-          if (wts) { d.add_prod(W * Q.re, Q.re); d.add_prod(W * Q.im, Q.im); }
-          else { d.add_prod(Q.re, Q.re); d.add_prod(Q.im, Q.im); }
-        }
-      Db[i] = d.result();
+      }
     }
+    if (isa) Da[tt] = d.result();
+    else Db[tt] = d.result();
   }
   __threadfence_block();
   __syncthreads();
@@ -342,25 +353,39 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
   // averaged spectra Kh[c][i][j]
   c64* Kh = kbuf;
   c64* Tm = tbuf;
-  for (int e = tid; e < 2 * SS; e += SMALL_NT) {
-    int c, ij;
-    split_index(e, SS, rSS, c, ij);
-    int i, jj;
-    split_index(ij, S, rS, i, jj);
-    const c64 P = pq[(size_t)c * SS + ij], Q = pq[(size_t)(2 + c) * SS + ij];
-    c64 kv;
-    if (wts) {
-      const double wx = wts[jj], wy = wts[S + i], r = 1.0 / (wx + wy);
-      const c64 a = w.x[jj] * P, b = w.x[S + i] * Q;
-      kv = {(wx * a.re + wy * b.re) * r, (wx * a.im + wy * b.im) * r};
-    } else {
-      const c64 v = w.x[jj] * P + w.x[S + i] * Q;
-      kv = {0.5 * v.re, 0.5 * v.im};
+  for (int e0 = 0; e0 < 2 * SS; e0 += 4 * SMALL_NT) {
+    c64 Pv[4], Qv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {   // eight loads in flight per lane (indices clamped in range)
+      const int e = min(e0 + tid + u * SMALL_NT, 2 * SS - 1);
+      int c, ij;
+      split_index(e, SS, rSS, c, ij);
+      Pv[u] = pq[(size_t)c * SS + ij];
+      Qv[u] = pq[(size_t)(2 + c) * SS + ij];
     }
-    Kh[e] = kv;
-    if (diag) {
-      diag->khat[c][i][jj][0] = kv.re;
-      diag->khat[c][i][jj][1] = kv.im;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + tid + u * SMALL_NT;
+      if (e >= 2 * SS) break;
+      int c, ij;
+      split_index(e, SS, rSS, c, ij);
+      int i, jj;
+      split_index(ij, S, rS, i, jj);
+      const c64 P = Pv[u], Q = Qv[u];
+      c64 kv;
+      if (wts) {
+        const double wx = wts[jj], wy = wts[S + i], r = 1.0 / (wx + wy);
+        const c64 a = w.x[jj] * P, b = w.x[S + i] * Q;
+        kv = {(wx * a.re + wy * b.re) * r, (wx * a.im + wy * b.im) * r};
+      } else {
+        const c64 v = w.x[jj] * P + w.x[S + i] * Q;
+        kv = {0.5 * v.re, 0.5 * v.im};
+      }
+      Kh[e] = kv;
+      if (diag) {
+        diag->khat[c][i][jj][0] = kv.re;
+        diag->khat[c][i][jj][1] = kv.im;
+      }
     }
   }
   __syncthreads();
