@@ -48,7 +48,7 @@ struct small_ws {
   double* a;    // n: diagonal of T
   double* b;    // n: off-diagonal of T, b[k] = T[k+1][k]
   dd* part;     // 4 x 64 x 2: partial double-double row sums of the refinement's product
-  c64* W;       // n x (n+1): not used by the solver (callers stage data there before or after it)
+  c64* W;       // n x (n+1): never touched by the solver; callers may keep data there across a solve
 };
 
 __host__ __device__ inline size_t small_lds_bytes(int n) {
