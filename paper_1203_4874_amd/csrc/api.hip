@@ -370,9 +370,14 @@ hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool 
   if (diag) CBP_TRY(launch_diag_init(br(Q_DIAG), cv.grid[Q_DIAG], st));
   // the column fold and, for the row pass that follows, the twiddle tables
   CBP_TRY(launch_fold<T>(br(Q_FOLD), cv.grid[Q_FOLD], latent ? cv.grid[Q_TWID] : 0, st));
-  if (latent) CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, st));
-  else CBP_TRY(launch_eval_rows<T>(br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], st));
-  CBP_TRY(launch_eval_cols(br(Q_EVAL_COLS), cv.grid[Q_EVAL_COLS], st));
+  // the row pass (with the row evaluation) and, on extra workgroups, the
+  // column evaluation of the fold
+  if (latent) {
+    CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, cv.grid[Q_EVAL_COLS], st));
+  } else {
+    CBP_TRY(launch_eval_rows<T>(br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], st));
+    CBP_TRY(launch_eval_cols(br(Q_EVAL_COLS), cv.grid[Q_EVAL_COLS], st));
+  }
   // join: the Gram needs the row evaluation (and the column pass the row spectra)
   if (cv.gram_fmt < 0) CBP_TRY(launch_gram(br(Q_GRAM), cv.grid[Q_GRAM], st));
   else CBP_TRY(launch_gram_mfma(br(Q_GRAMM), cv.grid[Q_GRAMM], cv.gram_fmt, cv.maxStride, st));

@@ -29,14 +29,6 @@ __device__ inline void pick(const frame_desc& d, int cf, const T*& b, int64_t& p
   else { b = (const T*)d.b2 + ch * d.cs2; pitch = d.p2; H = d.H2; W = d.W2; }
 }
 
-__device__ inline void unit_twiddles(c64* tw, int S) {
-  for (int t = threadIdx.x; t < S; t += blockDim.x) {
-    double s, c;
-    sincospi(-2.0 * (double)t / (double)S, &s, &c);
-    tw[t] = {c, s};
-  }
-}
-
 // Column fold over rows [g*rpg, (g+1)*rpg) of one (channel, frame): one
 // thread per (column, residue r), summing the rows y = r mod S of the group
 // in increasing order (four loads in flight), 64 columns per item.
@@ -104,48 +96,13 @@ __global__ __launch_bounds__(64) void k_fold_cols(batch_ref br, int gf) {
   });
 }
 
-// Sum the row-group partials of the column fold and apply the S-point DFT;
-// 16 columns per item, 16 residues / frequencies in flight per column.
-// Items: (column block, cf).
+// The column evaluation on its own (kernel-only calls; a deblurring call runs
+// it on extra workgroups of the row-pass launch).  Items: (column block, cf).
 __global__ __launch_bounds__(256) void k_eval_cols(batch_ref br) {
   __shared__ double F[CBP_MAX_S][16];
   __shared__ c64 tw[CBP_MAX_S];
   for_items<Q_EVAL_COLS>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
-    const int nx = (d.Wmax + 15) / 16;
-    const int bx = item % nx, cf = item / nx;
-    const int S = d.S, Wmax = d.Wmax, RG = d.RG;
-    const int W = (cf & 1) ? d.W2 : d.W1;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int x = bx * 16 + tx;
-    unit_twiddles(tw, S);
-    for (int r = ty; r < S; r += 16) {
-      double s0 = 0.0, s1 = 0.0;
-      if (x < W) {
-        const double* p = d.fpart + ((size_t)cf * S + r) * Wmax + x;
-        const size_t gs = (size_t)d.ncf * S * Wmax;
-        int g = 0;
-        for (; g + 2 <= RG; g += 2) {
-          s0 += p[(size_t)g * gs];
-          s1 += p[(size_t)(g + 1) * gs];
-        }
-        if (g < RG) s0 += p[(size_t)g * gs];
-      }
-      F[r][tx] = s0 + s1;
-    }
-    __syncthreads();
-    if (x >= W) return;
-    for (int j = ty; j < S; j += 16) {
-      c64 acc = {0.0, 0.0};
-      int t = 0;
-      for (int r = 0; r < S; ++r) {
-        const double f = F[r][tx];
-        acc.re += f * tw[t].re;
-        acc.im += f * tw[t].im;
-        t += j;
-        if (t >= S) t -= S;
-      }
-      d.ex[((size_t)cf * S + j) * Wmax + x] = acc;
-    }
+    eval_cols_item(d, item, F, tw);
   });
 }
 

@@ -50,12 +50,23 @@ __device__ __attribute__((always_inline)) inline cplx<T>* fft_lds(cplx<T>* a, cp
 // same order, hence the same bits) is taken from the row in LDS; waves 0-3
 // fold (frame, residue parity) = (w & 1, w >> 1).
 template <typename T>
-__global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
+// Workgroups [0, gr) run the row pass; the rest run the column evaluation
+// (its scratch carved from the dynamic LDS).
+__global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int gr) {
   extern __shared__ __attribute__((aligned(16))) char sm_rf[];
   __shared__ double gy[2][CBP_MAX_S];
   __shared__ double fpart_l[2][64];
   __shared__ c64 twS[CBP_MAX_S];
-  for_items<Q_ROW_FWD>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+  if ((int)blockIdx.x >= gr) {
+    double(*F)[16] = (double(*)[16])sm_rf;
+    c64* twe = (c64*)(sm_rf + (size_t)CBP_MAX_S * 16 * sizeof(double));
+    for_items_part<Q_EVAL_COLS>(br, (int)blockIdx.x - gr, (int)gridDim.x - gr,
+                                [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+                                  eval_cols_item(d, item, F, twe);
+                                });
+    return;
+  }
+  for_items_part<Q_ROW_FWD>(br, (int)blockIdx.x, gr, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const fft_plan& px = d.fx;
     const int N = px.N, hx = d.hx;
     cplx<T>* a = (cplx<T>*)sm_rf;
@@ -326,11 +337,12 @@ void set_fft_attrs() {
 }
 
 template <typename T>
-hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey,
+hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey, int eval_grid,
                           hipStream_t st) {
   prof_begin(PH_ROW_FWD, st);
-  hipLaunchKernelGGL(k_row_fwd<T>, dim3(grid), dim3(256), row_lds_bytes(maxPx, (int)sizeof(T)), st, br,
-                     with_ey);
+  size_t lds = row_lds_bytes(maxPx, (int)sizeof(T));
+  if (eval_grid > 0 && lds < kEvalColsLds) lds = kEvalColsLds;
+  hipLaunchKernelGGL(k_row_fwd<T>, dim3(grid + eval_grid), dim3(256), lds, st, br, with_ey, grid);
   prof_end(PH_ROW_FWD, st);
   return hipGetLastError();
 }
@@ -352,8 +364,8 @@ hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t 
 }
 
 
-template hipError_t launch_row_fwd<float>(const batch_ref&, int, int, int, hipStream_t);
-template hipError_t launch_row_fwd<double>(const batch_ref&, int, int, int, hipStream_t);
+template hipError_t launch_row_fwd<float>(const batch_ref&, int, int, int, int, hipStream_t);
+template hipError_t launch_row_fwd<double>(const batch_ref&, int, int, int, int, hipStream_t);
 template hipError_t launch_col<float>(const batch_ref&, int, int, int, hipStream_t);
 template hipError_t launch_col<double>(const batch_ref&, int, int, int, hipStream_t);
 template hipError_t launch_row_inv<float>(const batch_ref&, int, int, hipStream_t);

@@ -171,6 +171,60 @@ template <int Q, typename F>
 __device__ inline void for_items(const batch_ref& br, F&& body) {
   for_items_part<Q>(br, (int)blockIdx.x, (int)gridDim.x, body);
 }
+
+// w_t = exp(-2 pi i t / S), t < S, into tw (the workgroup's threads).
+__device__ inline void unit_twiddles(c64* tw, int S) {
+  for (int t = threadIdx.x; t < S; t += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * (double)t / (double)S, &s, &c);
+    tw[t] = {c, s};
+  }
+}
+
+// One item of the column evaluation (Sec. 4 eq. 3: the S-point DFT of the
+// column fold): the row-group partials of 16 columns of one (channel, frame)
+// summed in group order into F[r][column], then EX[cf][j][x] = sum_r
+// w_j^r F[r][x].  256 threads: 16 columns x 16 residues / frequencies in
+// flight.  F (CBP_MAX_S x 16 doubles) and tw (CBP_MAX_S) are LDS scratch.
+// Items: (column block, cf).
+__device__ inline void eval_cols_item(const frame_desc& d, int item, double (*F)[16], c64* tw) {
+  const int nx = (d.Wmax + 15) / 16;
+  const int bx = item % nx, cf = item / nx;
+  const int S = d.S, Wmax = d.Wmax, RG = d.RG;
+  const int W = (cf & 1) ? d.W2 : d.W1;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int x = bx * 16 + tx;
+  unit_twiddles(tw, S);
+  for (int r = ty; r < S; r += 16) {
+    double s0 = 0.0, s1 = 0.0;
+    if (x < W) {
+      const double* p = d.fpart + ((size_t)cf * S + r) * Wmax + x;
+      const size_t gs = (size_t)d.ncf * S * Wmax;
+      int g = 0;
+      for (; g + 2 <= RG; g += 2) {
+        s0 += p[(size_t)g * gs];
+        s1 += p[(size_t)(g + 1) * gs];
+      }
+      if (g < RG) s0 += p[(size_t)g * gs];
+    }
+    F[r][tx] = s0 + s1;
+  }
+  __syncthreads();
+  if (x >= W) return;
+  for (int j = ty; j < S; j += 16) {
+    c64 acc = {0.0, 0.0};
+    int t = 0;
+    for (int r = 0; r < S; ++r) {
+      const double f = F[r][tx];
+      acc.re += f * tw[t].re;
+      acc.im += f * tw[t].im;
+      t += j;
+      if (t >= S) t -= S;
+    }
+    d.ex[((size_t)cf * S + j) * Wmax + x] = acc;
+  }
+}
+constexpr size_t kEvalColsLds = (size_t)CBP_MAX_S * 16 * sizeof(double) + (size_t)CBP_MAX_S * sizeof(c64);
 #endif
 
 // ---------------------------------------------------------------- phase timing
@@ -221,8 +275,10 @@ void set_gram_mfma_attrs();
 
 // fft.hip.  with_ey: the row pass also writes the row evaluation EY (the
 // k_eval_rows result, bit for bit) from the rows it already holds.
+// launch_row_fwd runs the column evaluation too, on eval_grid more workgroups
+// (items of Q_EVAL_COLS; it needs the column fold, the row pass does not).
 template <typename T>
-hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey,
+hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey, int eval_grid,
                           hipStream_t st);
 template <typename T>
 hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st);

@@ -75,14 +75,6 @@ struct scale_acc {
   }
 };
 
-__device__ inline void unit_twiddles(c64* tw, int S) {
-  for (int t = threadIdx.x; t < S; t += blockDim.x) {
-    double s, c;
-    sincospi(-2.0 * (double)t / (double)S, &s, &c);
-    tw[t] = {c, s};
-  }
-}
-
 __device__ inline bool finite_c(c64 v) { return isfinite(v.re) && isfinite(v.im); }
 
 // Correlations rho for every (pass, sample, lag), summed over channels.
