@@ -10,14 +10,14 @@
 //     8 rounds, leave a bracket [lo, hi] of width ~6e-15 ||T||.
 //  3. sigma = lo - 16 n eps ||T|| < lam0, so T - sigma I is positive
 //     definite with its smallest eigenvalue well separated from the rest; its
-//     LDL^T factors (d_k > 0) solve (T - sigma I) z = r by one forward and
-//     one backward substitution.  Inverse iteration runs on T (y <- (T -
-//     sigma I)^{-1} y) and x = W y with W = Q D: the Householder reflectors
-//     (kept in the reduced matrix's strictly lower part) applied one by one,
-//     after the diagonal unitary D that makes the tridiagonal real.
+//     LDL^T factors (d_k > 0) give X = (T - sigma I)^{-1} explicitly (one
+//     column per lane).  Inverse iteration runs on T (y <- X y) and
+//     x = W y with W = Q D: the Householder reflectors (kept in the reduced
+//     matrix's strictly lower part) applied one by one, after the diagonal
+//     unitary D that makes the tridiagonal real.
 //  4. Newton refinement against G held in double-double:
 //       r = G x - mu x (mu = x^H G x, both double-double),
-//       x <- (x - M r) / ||x - M r||,  M = W (T - sigma I)^{-1} W^H,
+//       x <- (x - M r) / ||x - M r||,  M = W X W^H,
 //     until the change of direction (the correction's part orthogonal to x)
 //     is below 4e-15; M r approximates the exact Newton
 //     step sum_k v_k (v_k^H r) / (lam_k - mu) with relative error
@@ -48,7 +48,9 @@ struct small_ws {
   double* a;    // n: diagonal of T
   double* b;    // n: off-diagonal of T, b[k] = T[k+1][k]
   dd* part;     // 4 x 64 x 2: partial double-double row sums of the refinement's product
-  c64* W;       // n x (n+1): never touched by the solver; callers may keep data there across a solve
+  c64* W;       // n x (n+1) entries: the solver keeps X in the second half; callers may keep up to
+                //   n^2 doubles in the first half across a solve
+  double* X;    // n x n: (T - sigma I)^{-1}, from double offset n^2 of W
 };
 
 __host__ __device__ inline size_t small_lds_bytes(int n) {
@@ -68,6 +70,7 @@ __device__ inline small_ws small_carve(char* base, int n) {
   s.b = (double*)p; p += n * sizeof(double);
   s.part = (dd*)p; p += (size_t)4 * 64 * 2 * sizeof(dd);
   s.W = (c64*)p;
+  s.X = (double*)p + (size_t)n * n;
   return s;
 }
 
@@ -470,57 +473,86 @@ __device__ inline void tri_factor(small_ws& s, int n, double sigma, double pivmi
   __syncthreads();
 }
 
-// (T - sigma I) z = r from the factors in s.w (L D L^T, L unit lower
-// bidiagonal): forward w_k = r_k - l_{k-1} w_{k-1}, then w_k / d_k, then
-// backward z_k = w_k / d_k - l_k z_{k+1}.  r arrives lane-distributed and is
-// staged in s.u; every lane runs both recurrences on broadcast reads (eight
-// entries per batch; steps past the ends run on clamped entries and are
-// discarded), lane k keeps w_k / d_k, which goes back to s.u for the
-// backward pass, and lane k returns z_k (zero for k >= n).
-__device__ inline __attribute__((always_inline)) c64 tri_solve(small_ws& s, int n, c64 r) {
+// X = (T - sigma I)^{-1} (real symmetric) from the factors in s.w: lane j
+// solves for column j (forward L w = e_j, w'_k = w_k / d_k, backward
+// L^T z = w'), the factors being broadcast reads.
+__device__ inline void build_x(small_ws& s, int n) {
   const int l = threadIdx.x;
-  c64* __restrict__ b = s.u;
-  const c64* __restrict__ f = s.w;
+  double* X = s.X;
+  __syncthreads();
+  if (l < n) {
+    double w = 0.0, lprev = 0.0;
+    for (int k0 = 0; k0 < n; k0 += 8) {
+      c64 fv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) fv[t] = k0 + t < n ? s.w[k0 + t] : c64{0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = k0 + t;
+        if (k < n) {
+          w = (k == l ? 1.0 : 0.0) - lprev * w;
+          lprev = fv[t].im;
+          X[(size_t)k * n + l] = w * fv[t].re;
+        }
+      }
+    }
+    double z = 0.0;
+    for (int k1 = n - 1; k1 >= 0; k1 -= 8) {
+      double wv[8], lv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = k1 - t;
+        wv[t] = k >= 0 ? X[(size_t)k * n + l] : 0.0;
+        lv[t] = (k >= 0 && k + 1 < n) ? s.w[k].im : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = k1 - t;
+        if (k >= 0) {
+          z = wv[t] - lv[t] * z;
+          X[(size_t)k * n + l] = z;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// out_c = sum_{j < n} f(c, j) for lane c < n, on split lanes (f reads LDS).
+template <class F>
+__device__ inline c64 split_sum(small_ws& s, int n, F f) {
+  const int l = threadIdx.x;
+  const lane_split sp = split_lanes(n);
+  c64 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+  int j = sp.j0;
+  for (; j + 4 <= sp.j1; j += 4) {
+    const c64 f0 = f(sp.c, j), f1 = f(sp.c, j + 1), f2 = f(sp.c, j + 2), f3 = f(sp.c, j + 3);
+    a0 = a0 + f0 + f2;
+    a1 = a1 + f1 + f3;
+  }
+  for (; j < sp.j1; ++j) a0 = a0 + f(sp.c, j);
+  c64* part = (c64*)s.part;
+  if (sp.grp < sp.g) part[l] = a0 + a1;
+  __syncthreads();
+  const c64 r = combine_parts(part, sp, n);
+  __syncthreads();
+  return r;
+}
+
+// X r for lane-distributed r (staged in s.u); lane c returns entry c (zero
+// for c >= n).  X is symmetric, so entry c is read along column c.
+__device__ inline c64 x_mul(small_ws& s, int n, c64 r) {
+  const int l = threadIdx.x;
+  c64* b = s.u;
   __syncthreads();
   if (l < n) b[l] = r;
   __syncthreads();
-  c64 w = {0.0, 0.0}, wl = {0.0, 0.0};
-  double lp = 0.0;
-  for (int k0 = 0; k0 < n; k0 += 8) {
-    c64 fv[8], rv[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int k = min(k0 + t, n - 1);
-      fv[t] = f[k];
-      rv[t] = b[k];
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      w = {rv[t].re - lp * w.re, rv[t].im - lp * w.im};
-      lp = fv[t].im;
-      if (l == k0 + t) wl = {w.re * fv[t].re, w.im * fv[t].re};
-    }
-  }
-  __syncthreads();
-  if (l < n) b[l] = wl;
-  __syncthreads();
-  c64 z = {0.0, 0.0}, out = {0.0, 0.0};
-  for (int k1 = n - 1; k1 >= 0; k1 -= 8) {
-    c64 fv[8], wv[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int k = max(k1 - t, 0);
-      fv[t] = f[k];
-      wv[t] = b[k];
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const double lk = k1 - t + 1 < n ? fv[t].im : 0.0;
-      z = {wv[t].re - lk * z.re, wv[t].im - lk * z.im};
-      if (l == k1 - t) out = z;
-    }
-  }
-  return out;
+  const double* X = s.X;
+  return split_sum(s, n, [&](int c, int k) __attribute__((always_inline)) {
+    const double x = X[(size_t)k * n + c];
+    const c64 bk = b[k];
+    return c64{x * bk.re, x * bk.im};
+  });
 }
 
 // Diagonal unitary D with D^H T_c D = T (T_c the complex tridiagonal with
@@ -620,10 +652,11 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_dia
   const double pivmin = 1e-300 + 2.2e-16 * 2.2e-16 * tn;
   tri_factor(s, n, sigma, pivmin);
   const c64 ph = tri_phases(s, n);
+  build_x(s, n);
   // inverse iteration on T from a fixed, generic start vector, then x = W y
   c64 y = l < n ? c64{1.0 + 0.6180339887 * (double)((l * 7) % 11), 0.0} : c64{0.0, 0.0};
   for (int it = 0; it < SMALL_INVIT; ++it) {
-    y = tri_solve(s, n, y);
+    y = x_mul(s, n, y);
     const double nr = sqrt(wsum(norm2(y)));
     y = {y.re / nr, y.im / nr};
   }
@@ -688,7 +721,7 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_dia
     }
     // correction c = W (T - sigma I)^{-1} W^H r
     const c64 t1 = cmulc(ph, q_apply(s, n, r, true));
-    const c64 t2 = tri_solve(s, n, t1);
+    const c64 t2 = x_mul(s, n, t1);
     const c64 cl = q_apply(s, n, t2 * ph, false);
     const c64 xn = l < n ? xl - cl : c64{0.0, 0.0};
     const double nrm = sqrt(wsum(norm2(xn)));
