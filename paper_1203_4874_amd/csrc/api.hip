@@ -364,12 +364,14 @@ int grid_for(int items, int cap) {
 }
 
 template <typename T>
-hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool diag, hipStream_t st) {
+hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool diag, hipStream_t st,
+                         const inline_head* ih) {
   const batch_ref b = {cv.descs, cv.starts, cv.nf};
   auto br = [&](int) { return b; };
-  if (diag) CBP_TRY(launch_diag_init(br(Q_DIAG), cv.grid[Q_DIAG], st));
   // the column fold and, for the row pass that follows, the twiddle tables
-  CBP_TRY(launch_fold<T>(br(Q_FOLD), cv.grid[Q_FOLD], latent ? cv.grid[Q_TWID] : 0, st));
+  // (the first launch: with an inline head it also stores the call's head)
+  CBP_TRY(launch_fold<T>(br(Q_FOLD), cv.grid[Q_FOLD], latent ? cv.grid[Q_TWID] : 0, ih, st));
+  if (diag) CBP_TRY(launch_diag_init(br(Q_DIAG), cv.grid[Q_DIAG], st));
   // the row pass (with the row evaluation) and, on extra workgroups, the
   // column evaluation of the fold
   if (latent) {
@@ -399,9 +401,10 @@ hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool 
   return hipSuccess;
 }
 
-hipError_t enqueue(dev_state& ds, int dtype, const chunk_view& cv, bool latent, bool diag, hipStream_t st) {
-  return dtype == CBP_F32 ? enqueue_chunk<float>(ds, cv, latent, diag, st)
-                          : enqueue_chunk<double>(ds, cv, latent, diag, st);
+hipError_t enqueue(dev_state& ds, int dtype, const chunk_view& cv, bool latent, bool diag, hipStream_t st,
+                   const inline_head* ih) {
+  return dtype == CBP_F32 ? enqueue_chunk<float>(ds, cv, latent, diag, st, ih)
+                          : enqueue_chunk<double>(ds, cv, latent, diag, st, ih);
 }
 
 // ---------------------------------------------------------------- batches
@@ -566,12 +569,26 @@ hipError_t upload_head(dev_state& ds, const batch_build& bb, hipStream_t st) {
   return upload_bytes(ds, bb.head_dev, bb.head, st);
 }
 
-hipError_t enqueue_batch(dev_state& ds, const batch_build& bb, hipStream_t st) {
+hipError_t enqueue_batch(dev_state& ds, const batch_build& bb, hipStream_t st, const inline_head* ih = nullptr) {
   for (const chunk_view& cv : bb.chunks) {
-    const hipError_t e = enqueue(ds, bb.dtype, cv, bb.latent, bb.diag, st);
+    const hipError_t e = enqueue(ds, bb.dtype, cv, bb.latent, bb.diag, st, ih);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// The head of a one-chunk call of at most three frames as an inline head (the
+// descriptors, then the chunk's prefix sums); false when it does not fit.
+bool make_inline_head(const batch_build& bb, inline_head* ih) {
+  if (bb.chunks.size() != 1) return false;
+  const int nf = bb.chunks[0].nf;
+  const size_t nd = (size_t)nf * sizeof(frame_desc), ns = (size_t)Q_COUNT * (nf + 1) * sizeof(int);
+  if (nd % 16 != 0 || ns % 16 != 0 || nd + ns > (size_t)kInlineHeadMax) return false;
+  ih->ndesc_bytes = (int)nd;
+  ih->nstart_bytes = (int)ns;
+  std::memcpy(ih->bytes, bb.head.data(), nd);
+  std::memcpy(ih->bytes + nd, bb.head.data() + head_desc_bytes(nf), ns);
+  return true;
 }
 
 // Key of a captured graph: everything its nodes bake in.
@@ -710,8 +727,13 @@ cbp_status batch_call(const std::vector<frame_req>& reqs, cbp_status* per_frame,
   if (o->flags & CBP_FLAG_GRAPH) {
     e = run_graph(*ds, bb, st);
   } else {
-    e = upload_head(*ds, bb, st);
-    if (e == hipSuccess) e = enqueue_batch(*ds, bb, st);
+    inline_head ih;
+    if (make_inline_head(bb, &ih)) {
+      e = enqueue_batch(*ds, bb, st, &ih);
+    } else {
+      e = upload_head(*ds, bb, st);
+      if (e == hipSuccess) e = enqueue_batch(*ds, bb, st);
+    }
   }
   if (e != hipSuccess) return CBP_E_DEVICE;
   return first;
@@ -819,8 +841,8 @@ cbp_status cbp_eval_unit_circle(const cbp_image* b, int32_t S, double* ex, doubl
   (void)hipGetLastError();
   auto run = [&]() -> hipError_t {
     CBP_TRY(upload_bytes(*ds, ws, hb, st));
-    if (b->dtype == CBP_F32) CBP_TRY(launch_fold<float>(br, grid_for(items[Q_FOLD], 0), 0, st));
-    else CBP_TRY(launch_fold<double>(br, grid_for(items[Q_FOLD], 0), 0, st));
+    if (b->dtype == CBP_F32) CBP_TRY(launch_fold<float>(br, grid_for(items[Q_FOLD], 0), 0, nullptr, st));
+    else CBP_TRY(launch_fold<double>(br, grid_for(items[Q_FOLD], 0), 0, nullptr, st));
     CBP_TRY(launch_eval_cols(br, grid_for(items[Q_EVAL_COLS], 0), st));
     if (b->dtype == CBP_F32) CBP_TRY(launch_eval_rows<float>(br, grid_for(items[Q_EVAL_ROWS], 0), st));
     else CBP_TRY(launch_eval_rows<double>(br, grid_for(items[Q_EVAL_ROWS], 0), st));
@@ -862,10 +884,10 @@ cbp_status cbp_sample_grams(const cbp_image* b1, const cbp_image* b2, int32_t m,
   auto run = [&]() -> hipError_t {
     CBP_TRY(upload_head(*ds, bb, st));
     if (b1->dtype == CBP_F32) {
-      CBP_TRY(launch_fold<float>(br, cv.grid[Q_FOLD], 0, st));
+      CBP_TRY(launch_fold<float>(br, cv.grid[Q_FOLD], 0, nullptr, st));
       CBP_TRY(launch_eval_rows<float>(br, cv.grid[Q_EVAL_ROWS], st));
     } else {
-      CBP_TRY(launch_fold<double>(br, cv.grid[Q_FOLD], 0, st));
+      CBP_TRY(launch_fold<double>(br, cv.grid[Q_FOLD], 0, nullptr, st));
       CBP_TRY(launch_eval_rows<double>(br, cv.grid[Q_EVAL_ROWS], st));
     }
     CBP_TRY(launch_eval_cols(br, cv.grid[Q_EVAL_COLS], st));

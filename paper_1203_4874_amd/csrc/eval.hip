@@ -55,9 +55,25 @@ __device__ inline void twiddle_item(const frame_desc& d, int item) {
   }
 }
 
-// Workgroups [0, gf) fold; the rest fill the twiddle tables.
+// Workgroups [0, gf) fold; the rest fill the twiddle tables.  With an inline
+// head (ih.ndesc_bytes > 0) every workgroup reads the descriptors and prefix
+// sums from the launch's arguments and workgroup 0 stores them at br's place
+// in the workspace head for the later launches.
 template <typename T>
-__global__ __launch_bounds__(64) void k_fold_cols(batch_ref br, int gf) {
+__global__ __launch_bounds__(64) void k_fold_cols(batch_ref br_ws, int gf, inline_head ih) {
+  batch_ref br = br_ws;
+  if (ih.ndesc_bytes > 0) {
+    br.descs = (const frame_desc*)ih.bytes;
+    br.starts = (const int*)(ih.bytes + ih.ndesc_bytes);
+    if (blockIdx.x == 0) {
+      const uint4* src = (const uint4*)ih.bytes;
+      uint4* dd = (uint4*)br_ws.descs;
+      uint4* ds = (uint4*)br_ws.starts;
+      const int nd = ih.ndesc_bytes / 16, ns = ih.nstart_bytes / 16;
+      for (int i = threadIdx.x; i < nd; i += blockDim.x) dd[i] = src[i];
+      for (int i = threadIdx.x; i < ns; i += blockDim.x) ds[i] = src[nd + i];
+    }
+  }
   if ((int)blockIdx.x >= gf) {
     for_items_part<Q_TWID>(br, (int)blockIdx.x - gf, (int)gridDim.x - gf,
                            [&](const frame_desc& d, int item) __attribute__((always_inline)) {
@@ -160,9 +176,12 @@ __global__ __launch_bounds__(256) void k_eval_rows(batch_ref br) {
 }  // namespace
 
 template <typename T>
-hipError_t launch_fold(const batch_ref& br, int grid, int twid_grid, hipStream_t st) {
+hipError_t launch_fold(const batch_ref& br, int grid, int twid_grid, const inline_head* ih, hipStream_t st) {
   prof_begin(PH_FOLD, st);
-  hipLaunchKernelGGL(k_fold_cols<T>, dim3(grid + twid_grid), dim3(64), 0, st, br, grid);
+  inline_head h;
+  if (ih) h = *ih;
+  else h.ndesc_bytes = h.nstart_bytes = 0;
+  hipLaunchKernelGGL(k_fold_cols<T>, dim3(grid + twid_grid), dim3(64), 0, st, br, grid, h);
   prof_end(PH_FOLD, st);
   return hipGetLastError();
 }
@@ -182,8 +201,8 @@ hipError_t launch_eval_rows(const batch_ref& br, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-template hipError_t launch_fold<float>(const batch_ref&, int, int, hipStream_t);
-template hipError_t launch_fold<double>(const batch_ref&, int, int, hipStream_t);
+template hipError_t launch_fold<float>(const batch_ref&, int, int, const inline_head*, hipStream_t);
+template hipError_t launch_fold<double>(const batch_ref&, int, int, const inline_head*, hipStream_t);
 template hipError_t launch_eval_rows<float>(const batch_ref&, int, hipStream_t);
 template hipError_t launch_eval_rows<double>(const batch_ref&, int, hipStream_t);
 

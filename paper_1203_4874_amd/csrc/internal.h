@@ -242,11 +242,25 @@ void prof_end(int phase, hipStream_t st);
 // ---------------------------------------------------------------- launchers
 // Each launches one queue over `grid` workgroups (any grid >= 1 covers every
 // item; a multiple of 8 enables the XCD-aware item ranges).
+// The head of a small one-chunk call (frame descriptors, then the per-queue
+// item prefix sums of the chunk) passed by value to the first launch, which
+// reads its descriptors from it and stores it into the workspace head for the
+// launches that follow: no host-to-device copy precedes the call's kernels.
+constexpr int kInlineHeadMax = 1600;   // three frames
+struct inline_head {
+  int ndesc_bytes;    // nframes * sizeof(frame_desc); 0: no inline head
+  int nstart_bytes;   // Q_COUNT * (nframes + 1) * sizeof(int)
+  int pad[2];
+  alignas(16) char bytes[kInlineHeadMax];
+};
+
 // eval.hip.  launch_fold runs the column fold on `grid` workgroups and, on
 // twid_grid more, the twiddle tables of every frame (items of Q_TWID; the
-// FFT passes need them, the fold does not, so they share one launch).
+// FFT passes need them, the fold does not, so they share one launch).  With
+// ih, the launch carries the call's head (br then points at its place in the
+// workspace).
 template <typename T>
-hipError_t launch_fold(const batch_ref& br, int grid, int twid_grid, hipStream_t st);
+hipError_t launch_fold(const batch_ref& br, int grid, int twid_grid, const inline_head* ih, hipStream_t st);
 hipError_t launch_eval_cols(const batch_ref& br, int grid, hipStream_t st);
 template <typename T>
 hipError_t launch_eval_rows(const batch_ref& br, int grid, hipStream_t st);
