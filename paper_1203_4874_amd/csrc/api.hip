@@ -107,7 +107,7 @@ int max_fft(int esize) { return esize == 4 ? CBP_MAX_FFT_F32 : CBP_MAX_FFT_F64; 
 // Launch-shape knobs of one batch class, chosen by the autotuner.
 struct tuning {
   int fold_rows;   // target rows per column-fold group (rounded up to a multiple of S; >= 32)
-  int cw;          // columns per column-pass strip (0: widest that fits and keeps >= 128 strips)
+  int cw;          // columns per column-pass strip (0: widest that fits and keeps >= 256 strips, one per CU)
   int wg_per_cu;   // persistent-grid cap of the streaming queues, workgroups per CU (0: one per item)
   int fft_order;   // radix pass order of the row and column FFTs
 };
@@ -119,7 +119,7 @@ int choose_cw(int Py, int hx, int esize, int want) {
   int cw = want > 0 ? want : 4;
   if (cw > 8) cw = 8;
   while (cw & (cw - 1)) cw &= cw - 1;
-  while (cw > 1 && (col_lds_bytes(Py, cw, esize) > kLdsLimit - 4096 || (want <= 0 && (hx + cw - 1) / cw < 128)))
+  while (cw > 1 && (col_lds_bytes(Py, cw, esize) > kLdsLimit - 4096 || (want <= 0 && (hx + cw - 1) / cw < 256)))
     cw >>= 1;
   return cw;
 }
