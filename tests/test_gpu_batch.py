@@ -90,6 +90,39 @@ def test_uneven_batch_equals_single_and_oracle(P, npd, prec, ktol):
         assert p >= 60
 
 
+@pytest.mark.parametrize("nb", [1, 2, 3, 4])
+def test_small_batches_equal_single(P, nb):
+    """Calls of up to three frames carry their work-list head in the first
+    launch's arguments, larger ones upload it: both give each frame the bits
+    of the same frame deblurred alone, and a graph of a small call replays
+    them."""
+    frames, _ = uneven_frames(905, SHAPES[:nb], np.float32, noise=1e-3)
+    d = _deblurrer(P, frames, 1, len(frames))
+    Ls, K1s, K2s, st = d.deblur_batch(frames, lam=1e-4)
+    torch.cuda.synchronize()
+    assert st == [0] * nb
+    one = _deblurrer(P, frames, 1, 1)
+    for (b1, b2, m, n), L, K1, K2 in zip(frames, Ls, K1s, K2s):
+        L1, J1, J2 = one.deblur(b1, b2, m, n, lam=1e-4)
+        torch.cuda.synchronize()
+        assert torch.equal(L1, L) and torch.equal(J1, K1) and torch.equal(J2, K2), (nb, m, n)
+    if nb == 2:
+        eager = d.prepare_batch(frames, lam=1e-4)
+        g = d.prepare_batch(frames, lam=1e-4, flags=P.Flags.GRAPH)
+        eager.run()
+        torch.cuda.synchronize()
+        ref = [(L.clone(), K1.clone()) for L, K1 in zip(eager.latents, eager.K1s)]
+        for rep in range(3):
+            for L in g.latents:
+                L.zero_()
+            g.run()
+            torch.cuda.synchronize()
+            for (L, K1), (Lr, K1r) in zip(zip(g.latents, g.K1s), ref):
+                assert torch.equal(L, Lr) and torch.equal(K1, K1r), rep
+            eager.run()
+            torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("npd", [np.float32, np.float64])
 def test_kernel_only_call_equals_deblur_kernels(P, npd):
     """cbp_recover_kernels evaluates rows in k_eval_rows; cbp_deblur takes the
