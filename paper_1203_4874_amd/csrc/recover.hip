@@ -397,6 +397,7 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
     split_index(jx, S, rS, jj, x);
     c64 acc = {0.0, 0.0};
     int t = 0;
+#pragma unroll 4
     for (int i = 0; i < S; ++i) {
       acc = acc + Kh[(size_t)c * SS + i * S + jj] * conj(tw[t]);
       t += x;
@@ -413,6 +414,7 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
     split_index(yx, S, rS, y, x);
     c64 acc = {0.0, 0.0};
     int t = 0;
+#pragma unroll 4
     for (int jj = 0; jj < S; ++jj) {
       acc = acc + Tm[(size_t)c * SS + jj * S + x] * conj(tw[t]);
       t += y;
@@ -433,10 +435,13 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
       eall += p;
       if (y < k && x < k) { sr += v.re; si += v.im; ein += p; }
     }
-    sr = wsum(sr);
-    si = wsum(si);
-    ein = wsum(ein);
-    eall = wsum(eall);
+    {   // pairs of sums share a reduction (each component in wsum's order)
+      const c64 a = wsum_c(c64{sr, si}), b = wsum_c(c64{ein, eall});
+      sr = a.re;
+      si = a.im;
+      ein = b.re;
+      eall = b.im;
+    }
     const double s2 = sr * sr + si * si;
     double* K = c == 0 ? K1 : K2;
     double re2 = 0.0, im2 = 0.0;
@@ -450,8 +455,11 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
       re2 += kr * kr;
       im2 += ki * ki;
     }
-    re2 = wsum(re2);
-    im2 = wsum(im2);
+    {
+      const c64 q = wsum_c(c64{re2, im2});
+      re2 = q.re;
+      im2 = q.im;
+    }
     if (tid == 0 && diag) {
       diag->kernel_imag[c] = sqrt(im2) / fmax(sqrt(re2), 1e-300);
       diag->kernel_outside[c] = (eall - ein) / fmax(eall, 1e-300);
