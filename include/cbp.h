@@ -10,7 +10,7 @@
  *
  * Method (Sec. 4 and Sec. 5), every step on the GPU inside one call:
  *   1. evaluate both frames as polynomials at S roots of unity along one axis
- *      at a time (eq. 3; Sec. 5: "exactly a DFT"), for both axis orders;
+ *      at a time (eq. 3; Sec. 5: the evaluation is an S-point DFT), for both axis orders;
  *   2. at every sample, the 1-D cofactors are the null vector of the stacked
  *      convolution matrix [C(b1) | -C(b2)], taken as the smallest eigenvector
  *      of its Hermitian Gram matrix (Sec. 5: one small factorisation per
@@ -127,7 +127,8 @@ typedef struct cbp_options {
 #define CBP_DIAG_SAMPLE_WEAK    2  /* some per-sample Gram had no clear null direction */
 #define CBP_DIAG_SCALE_WEAK     4  /* the scale system had no clear null direction */
 #define CBP_DIAG_KERNEL_ZERO    8  /* a kernel estimate summed to ~0 before normalisation */
-#define CBP_DIAG_FALLBACK      16  /* learned form: the plain kernels were kept (smaller judge objective) */
+#define CBP_DIAG_FALLBACK      16  /* learned form: the plain kernels were kept (the learned objective was larger or not a number) */
+#define CBP_DIAG_BAD_NETWORK   32  /* learned form: the network blob's header is not this library's (unit weights used) */
 
 /* Per-frame numerical diagnostics, written in device memory when
  * options->diag is not NULL.  Complex values are (re, im) pairs. */

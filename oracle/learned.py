@@ -209,10 +209,13 @@ def recover_kernels_learned(B1, B2, m: int, n: int, params, S: int = 0, full: bo
     # the plain method judges: keep its kernels when their objective is smaller
     Jp = judge_objective(K1p, K2p, f["EX"], f["EY"], S)
     Jl = judge_objective(L1, L2, f["EX"], f["EY"], S)
-    K1, K2 = (K1p, K2p) if Jp < Jl else (L1, L2)
+    # the learned kernels are kept only when their objective is a number no
+    # larger than the plain one's
+    fallback = not (Jl <= Jp)
+    K1, K2 = (K1p, K2p) if fallback else (L1, L2)
     if not full:
         return K1, K2
-    return K1, K2, dict(plain=(K1p, K2p), learned=(L1, L2), judge=(Jp, Jl), fallback=Jp < Jl, wX=wX, wY=wY,
+    return K1, K2, dict(plain=(K1p, K2p), learned=(L1, L2), judge=(Jp, Jl), fallback=fallback, wX=wX, wY=wY,
                         tau=tau, features=(XF, YF), base=f)
 
 

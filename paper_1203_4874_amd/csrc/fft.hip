@@ -253,9 +253,12 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
       const cplx<T> B1 = f1[(size_t)(2 * c) * N + ky];
       const cplx<T> B2 = f1[(size_t)(2 * c + 1) * N + ky];
       const cplx<T> num = cmulc(kh1, B1) + cmulc(kh2, B2);
-      const T den = norm2(kh1) + norm2(kh2) + lam;
+      const T kk = norm2(kh1) + norm2(kh2);
+      const T den = kk + lam;
       const T inv = den > T(0) ? T(1) / den : T(0);
-      f1[(size_t)(2 * c) * N + ky] = {num.re * inv, num.im * inv};
+      // where both kernel spectra vanish (a zeroed kernel pair) the
+      // quotient is zero, whatever the frames hold
+      f1[(size_t)(2 * c) * N + ky] = kk > T(0) ? cplx<T>{num.re * inv, num.im * inv} : cplx<T>{T(0), T(0)};
     }
     __syncthreads();
     // inverse column FFT of the cw combined spectra (slots 0, 2, 4, ...)

@@ -167,8 +167,19 @@ __global__ __launch_bounds__(256) void k_mlp_frames(batch_ref br, const mlp_blob
   __shared__ double mid[2];
   for_items<Q_FINALIZE>(br, [&](const frame_desc& d, int) __attribute__((always_inline)) {
     const int n = 2 * d.S;
-    mlp_block(L, d.feat, n, blob->W1, blob->W2, blob->W3, blob->b1, blob->b2, blob->b3, nullptr, nullptr);
     const int t = threadIdx.x;
+    // a blob whose header is not this network's: unit weights and tau = 0
+    // (the learned assembly then reduces to the plain one) and a flag
+    if (blob->magic != MLP_MAGIC || blob->version != MLP_VERSION || blob->feat != MLP_FEAT ||
+        blob->hidden != MLP_HIDDEN) {
+      if (t < n) d.wts[t] = 1.0;
+      if (t == 0) {
+        d.wts[n] = 0.0;
+        if (d.diag) atomicOr(&d.diag->flags, CBP_DIAG_BAD_NETWORK);
+      }
+      return;
+    }
+    mlp_block(L, d.feat, n, blob->W1, blob->W2, blob->W3, blob->b1, blob->b2, blob->b3, nullptr, nullptr);
     if (t < n) {
       const double o1 = L.out[t][0], o2 = L.out[t][1];
       const double sp = o1 > 30.0 ? o1 : log1p(exp(o1));

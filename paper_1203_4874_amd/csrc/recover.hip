@@ -77,6 +77,15 @@ struct scale_acc {
 
 __device__ inline bool finite_c(c64 v) { return isfinite(v.re) && isfinite(v.im); }
 
+// Both kernels to zero (each lane clears the entries it wrote): a pair whose
+// estimate is non-finite or sums to zero is returned as zeros, so that the
+// Fourier division that follows writes a zero latent instead of spreading
+// the non-finite values.
+__device__ inline void zero_kernels(double* K1, int k1, double* K2, int k2) {
+  for (int e = threadIdx.x; e < k1 * k1; e += SMALL_NT) K1[e] = 0.0;
+  for (int e = threadIdx.x; e < k2 * k2; e += SMALL_NT) K2[e] = 0.0;
+}
+
 // Correlations rho for every (pass, sample, lag), summed over channels.
 // Items: (lag, sample, pass), one wave each; Dot2 accumulation per lane,
 // then a fixed-order double-double wave reduction.
@@ -220,7 +229,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_sample(batch_ref br) {
 //   Ax = Fx^H D_u Fx, By = Fy^T D_v conj(Fy), C = Fx^H D_u Khat D_v conj(Fy),
 // u = wY, v = wX, F[i][x] = w_i^x (the separable weighted fit with per-axis
 // Tikhonov terms), then is divided by its complex sum (real part kept).
-__device__ inline __attribute__((always_inline)) void learned_assembly(const c64* tw, int S, int k, const double* wts, c64* Kh, c64* tb, c64* xt,
+__device__ inline __attribute__((always_inline)) bool learned_assembly(const c64* tw, int S, int k, const double* wts, c64* Kh, c64* tb, c64* xt,
                                         double* K, cbp_diag* diag, int c);
 
 // LDS of the plain finalize: twiddles, the two diagonal blocks, the solver.
@@ -385,8 +394,9 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
     if (diag)
       for (int t = tid; t <= n2; t += SMALL_NT) diag->sample_weights[t] = wts[t];
     c64* xt = w.W;   // S^2 + 2 CBP_MAX_S entries from the solver's W onwards (free after the solve)
-    learned_assembly(tw, S, k1, wts, Kh, tbuf, xt, K1, diag, 0);
-    learned_assembly(tw, S, k2, wts, Kh + SS, tbuf, xt, K2, diag, 1);
+    const bool bad1 = learned_assembly(tw, S, k1, wts, Kh, tbuf, xt, K1, diag, 0);
+    const bool bad2 = learned_assembly(tw, S, k2, wts, Kh + SS, tbuf, xt, K2, diag, 1);
+    if (bad1 || bad2) zero_kernels(K1, k1, K2, k2);
     return;
   }
   // inverse DFT along x: Tm[c][j][x] = sum_i Kh[c][i][j] w_i^{-x}
@@ -423,6 +433,7 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
     Kh[e] = acc;
   }
   __syncthreads();
+  bool bad = false;   // a kernel estimate is non-finite or sums to zero
   for (int c = 0; c < 2; ++c) {
     const int k = c == 0 ? k1 : k2;
     const float rk = 1.0f / (float)k;
@@ -466,10 +477,13 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
       if (!(s2 > 0.0) || !isfinite(s2)) atomicOr(&diag->flags, CBP_DIAG_KERNEL_ZERO);
       if (!isfinite(re2)) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
     }
+    bad = bad || !(s2 > 0.0) || !isfinite(s2) || !isfinite(re2);   // wave-uniform
   }
+  if (bad) zero_kernels(K1, k1, K2, k2);
 }
 
-__device__ inline __attribute__((always_inline)) void learned_assembly(const c64* tw, int S, int k, const double* wts, c64* Kh, c64* tb, c64* xt,
+// Returns true when the kernel is non-finite or sums to zero (wave-uniform).
+__device__ inline __attribute__((always_inline)) bool learned_assembly(const c64* tw, int S, int k, const double* wts, c64* Kh, c64* tb, c64* xt,
                                         double* K, cbp_diag* diag, int c) {
   const int tid = threadIdx.x, kk = k * k;
   const float rS = 1.0f / (float)S, rk = 1.0f / (float)k;
@@ -569,6 +583,7 @@ __device__ inline __attribute__((always_inline)) void learned_assembly(const c64
     if (!isfinite(re2)) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
   }
   __syncthreads();
+  return !(s2 > 0.0) || !isfinite(s2) || !isfinite(re2);
 }
 
 // Items: one per frame.  plain_only: the plain method's kernels into the
@@ -638,7 +653,9 @@ __global__ __launch_bounds__(64) void k_judge(batch_ref br) {
         }
       J[set] = acc;
     }
-    const bool fallback = J[0] < J[1];
+    // NaN-safe: the learned kernels are kept only when their objective is a
+    // number no larger than the plain one's
+    const bool fallback = !(J[1] <= J[0]);
     if (fallback) {
       for (int e = l; e < k1 * k1; e += 64) d.K1[e] = d.Kalt[e];
       for (int e = l; e < k2 * k2; e += 64) d.K2[e] = d.Kalt[CBP_MAX_K * CBP_MAX_K + e];

@@ -91,3 +91,32 @@ def test_colour_batch_equals_single_calls(P):
         assert torch.equal(L, Ls[i]) and torch.equal(K1, K1s[i]) and torch.equal(K2, K2s[i])
         Lo, R1, R2 = orc.deblur(frames[i][0], frames[i][1], m, n, 0, 1e-4)
         assert max(rel(K1.cpu().numpy(), R1), rel(K2.cpu().numpy(), R2)) <= 1e-6
+
+
+def test_colour_1080p_frame_matches_oracle(P):
+    """One frame of the 1080p colour stream at its full size: 1080x1920 RGB,
+    one coprime 15x15 / 17x17 pair, noise 5e-3, lambda 1e-4, FP32 frames
+    (mixed form), in the launch configuration the benchmark times (a batch
+    call replayed as a HIP graph), against the oracle's colour route on the
+    same FP32 values."""
+    h = synth.config5_frame(0)
+    B1 = h["B1"].astype(np.float32)
+    B2 = h["B2"].astype(np.float32)
+    m, n = h["m"], h["n"]
+    dev = _dev()
+    b1 = torch.as_tensor(B1, device=dev)
+    b2 = torch.as_tensor(B2, device=dev)
+    H, W = max(B1.shape[1], B2.shape[1]), max(B1.shape[2], B2.shape[2])
+    d = P.Deblurrer(H, W, H - m + 1, 3, 1, P.Precision.MIXED)
+    print("[case] 1080x1920 RGB frame, k=(15,17), mixed, graph replay", flush=True)
+    pb = d.prepare_batch([(b1, b2, m, n)], lam=h["lam"], flags=P.Flags.GRAPH)
+    pb.run()
+    pb.run()
+    torch.cuda.synchronize()
+    L = pb.latents[0].double().cpu().numpy()
+    Lo, R1, R2 = orc.deblur(B1.astype(np.float64), B2.astype(np.float64), m, n, 0, h["lam"])
+    e = max(rel(pb.K1s[0].cpu().numpy(), R1), rel(pb.K2s[0].cpu().numpy(), R2))
+    ps = [psnr(L[c], Lo[c]) for c in range(3)]
+    print(f"1080p RGB: kernel rel-L2 vs oracle {e:.2e}, PSNR per channel {', '.join(f'{p:.1f}' for p in ps)} dB")
+    assert L.shape == (3, m, n)
+    assert e <= 1e-3 and min(ps) >= 60.0

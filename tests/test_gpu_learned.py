@@ -6,9 +6,12 @@ route with the same (seeded, synthetic) parameters.
 Bars: network outputs within 2e-3 of the output scale and gradients within
 1e-2 (norm-wise, per parameter block) of the bf16-emulated oracle -- the
 residue is FP32 accumulation, which can move a bfloat16 rounding of a hidden
-activation by one unit (2^-8 relative); learned kernels within 1e-3 of the
-oracle's learned kernels (FP32 frames); constant network outputs (unit
-weights, tau ~ 0) give the plain kernels to 1e-9.
+activation by one unit (2^-8 relative); every gradient block also within
+GRAD_BOUND of the exact FP64 gradient (pinned by central differences);
+learned kernels within 1e-3 of the oracle's learned kernels (FP32 frames);
+constant network outputs (unit weights, tau ~ 0) give the plain kernels to
+1e-9; one Adam step equal to NumPy's Adam on the GPU's own gradient to FP32
+rounding.
 """
 
 import numpy as np
@@ -74,6 +77,17 @@ def test_network_forward_matches_bf16_oracle(P):
         assert err <= 2e-3
 
 
+# Norm-wise bound of each GPU gradient block against the exact FP64 gradient.
+# Along the path of a block's gradient at most seven operands are rounded to
+# bfloat16 (inputs, W1, h1, W2, h2, dZ2, dZ1), each by at most u = 2^-9
+# relative (round to nearest even on the 16 dropped bits).  To first order
+# the block's relative error is bounded by the sum of these, 7u = 1.4e-2,
+# times the amplification of the products' cancellations; ReLU masks that
+# flip where a pre-activation lies within a rounding of zero add a few
+# entries of the same size.  Four times 7u covers both.
+GRAD_BOUND = 4 * 7 * 2.0 ** -9
+
+
 def test_network_gradients_match_bf16_oracle(P):
     p = _params(5, scale=3.0)
     q = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
@@ -94,9 +108,47 @@ def test_network_gradients_match_bf16_oracle(P):
         e = rel(gg[k], go[k])
         print(f"grad {k}: rel-L2 {e:.2e}")
         assert e <= 1e-2, k
-    # and the bf16-emulated oracle gradient is close to the exact FP64 one
-    _, gx = orl.loss_and_grad(q, X, T[:, 0], T[:, 1])
-    assert rel(go["W2"], gx["W2"]) <= 5e-2
+    # every block of the GPU gradient against the exact FP64 gradient, whose
+    # correctness central differences pin (test_oracle_learned)
+    lx, gx = orl.loss_and_grad(q, X, T[:, 0], T[:, 1])
+    assert abs(float(loss.item()) - lx) <= GRAD_BOUND * abs(lx)
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        e = rel(gg[k], gx[k])
+        print(f"grad {k} vs FP64: rel-L2 {e:.2e} (bound {GRAD_BOUND:.2e})")
+        assert e <= GRAD_BOUND, k
+
+
+def test_adam_step_matches_numpy_adam(P):
+    """Two Adam steps on the GPU equal NumPy's Adam (beta 0.9 / 0.999, eps
+    1e-8, bias-corrected, steps counted from 1) applied to the gradients the
+    GPU computes at each step, to FP32 rounding of the parameters."""
+    p = _params(6, scale=2.0)
+    q = orl.pack({k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}).astype(np.float32)
+    n = 300
+    X = torch.as_tensor(_features(31, n), dtype=torch.float32, device=_dev())
+    r = np.random.default_rng(32)
+    T = torch.as_tensor(np.stack([r.standard_normal(n), -5.0 + r.standard_normal(n)], 1), dtype=torch.float32,
+                        device=_dev())
+    st = P.MlpState(512, _dev())
+    st.set_params(q)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    w = q.astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    for step in (1, 2):
+        _, g = st.gradients(X, T)          # the gradient the step will use (deterministic kernels)
+        g = g.cpu().numpy().astype(np.float64)
+        st.train_step(X, T, lr, step)
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        mh = m / (1 - b1 ** step)
+        vh = v / (1 - b2 ** step)
+        w = w - lr * mh / (np.sqrt(vh) + eps)
+        got = st.get_params().cpu().numpy().astype(np.float64)
+        err = np.abs(got - w).max()
+        print(f"adam step {step}: max |param - numpy| {err:.2e}")
+        assert err <= 4 * 2.0 ** -24 * np.abs(w).max() + 1e-3 * lr
+        w = got                             # continue from the GPU's FP32 parameters
 
 
 def test_adam_training_lowers_the_loss(P):

@@ -166,3 +166,82 @@ def test_judge_objective_is_zero_on_true_kernels_and_prefers_them():
     x = learned.kernel_slices(K1, K2, S, 0, 2)
     w = np.exp(-2j * np.pi * 2 / S)
     assert np.allclose(x[:5], (w ** np.arange(5)) @ K2) and np.allclose(x[5:], (w ** np.arange(4)) @ K1)
+
+
+def _exact_case(n=8, seed=23):
+    """Parameters, inputs and every activation and back-propagated signal
+    exactly representable in bfloat16: sparse {0, +-1} layer weights,
+    half-integer inputs and biases, a head in quarters, and targets chosen so
+    that dL/do1 = 0 and dL/do2 = 1/4 exactly.  Every sum is then exact in FP64
+    whatever its order, so any rounding point of the emulation is the
+    identity."""
+    rng = np.random.default_rng(seed)
+
+    def sparse(o, i, nnz):
+        W = np.zeros((o, i))
+        for r in range(o):
+            c = rng.choice(i, nnz, replace=False)
+            W[r, c] = rng.choice([-1.0, 1.0], nnz)
+        return W
+
+    p = dict(W1=sparse(128, 32, 4), b1=0.5 * rng.integers(-2, 3, 128),
+             W2=sparse(128, 128, 4), b2=0.5 * rng.integers(-2, 3, 128),
+             W3=0.25 * rng.integers(-4, 5, (2, 128)) * (rng.random((2, 128)) < 0.1), b3=np.array([0.5, -1.0]))
+    X = 0.5 * rng.integers(-2, 3, (n, 32))
+    o, _ = learned.mlp_forward(p, X)
+    t1 = np.log(learned.softplus(o[:, 0]))
+    t2 = o[:, 1] - n / 8.0
+    return p, X, t1, t2
+
+
+def test_bf16_network_equals_fp64_network_where_bf16_is_exact():
+    """Pin of the bf16 emulation against the FP64 network (itself pinned by
+    central differences): on a case where bfloat16 holds every operand,
+    activation and back-propagated signal exactly, the emulated forward and
+    the emulated loss and gradients of every block equal the FP64 ones bit
+    for bit -- so the emulation multiplies, transposes and masks the same
+    quantities as the exact network and differs from it only by its
+    roundings."""
+    p, X, t1, t2 = _exact_case()
+    for v in (*p.values(), X):
+        assert np.array_equal(learned.round_bf16(v), v)
+    o0, c0 = learned.mlp_forward(p, X)
+    o1, c1 = learned.mlp_forward_bf16(p, X)
+    assert np.array_equal(o0, o1)
+    assert np.array_equal(learned.round_bf16(c0["h1"]), c0["h1"]) and np.array_equal(c0["h1"], c1["h1"])
+    assert np.array_equal(learned.round_bf16(c0["h2"]), c0["h2"]) and np.array_equal(c0["h2"], c1["h2"])
+    l0, g0 = learned.loss_and_grad(p, X, t1, t2)
+    l1, g1 = learned.loss_and_grad_bf16(p, X, t1, t2)
+    assert l0 == l1
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        assert np.array_equal(g0[k], g1[k]), k
+        assert np.any(g0[k] != 0.0), k          # the case exercises every block
+    # the signals into the hidden layers are exact here too
+    dO = np.zeros_like(o0)
+    dO[:, 1] = 0.25
+    dZ2 = (dO @ p["W3"]) * (c0["z2"] > 0)
+    assert np.array_equal(learned.round_bf16(dZ2), dZ2)
+    dZ1 = (dZ2 @ p["W2"]) * (c0["z1"] > 0)
+    assert np.array_equal(learned.round_bf16(dZ1), dZ1)
+
+
+def test_bf16_emulation_rounds_at_the_stated_points():
+    """Each rounding point of the emulation is live: perturbing one operand
+    of the exact case by less than half a bfloat16 unit leaves the emulated
+    result unchanged where that operand is rounded (inputs, W1, W2), and
+    moves the exact network's result."""
+    p, X, t1, t2 = _exact_case()
+    l1, g1 = learned.loss_and_grad_bf16(p, X, t1, t2)
+    for name in ("W1", "W2"):
+        q = {k: v.copy() for k, v in p.items()}
+        nz = np.argwhere(q[name] != 0)[0]
+        q[name][tuple(nz)] *= 1.0 + 2.0 ** -10          # below half an ulp of a bf16 +-1
+        _, gq = learned.loss_and_grad_bf16(q, X, t1, t2)
+        _, gx = learned.loss_and_grad(q, X, t1, t2)
+        _, g0 = learned.loss_and_grad(p, X, t1, t2)
+        assert all(np.array_equal(gq[k], g1[k]) for k in g1), name
+        assert any(not np.array_equal(gx[k], g0[k]) for k in g0), name
+    Xq = X + (X != 0) * X * 2.0 ** -10
+    oq, _ = learned.mlp_forward_bf16(p, Xq)
+    o1, _ = learned.mlp_forward_bf16(p, X)
+    assert np.array_equal(oq, o1)
