@@ -16,6 +16,8 @@ Modules
   learned -- the learned form: spectrum features, the MLP (forward, backward,
             loss), the weighted scale fix and the weighted, regularised
             assembly; it reduces to cbp's steps at unit weights.
+  sizes  -- blind kernel-size estimation: the per-sample nullity test over
+            trial sizes (the kernel degree stage of Sec. 4 and Sec. 5).
 """
 
-from . import cbp, tls2d, exact, learned  # noqa: F401
+from . import cbp, tls2d, exact, learned, sizes  # noqa: F401
