@@ -18,6 +18,8 @@ Modules
             assembly; it reduces to cbp's steps at unit weights.
   sizes  -- blind kernel-size estimation: the per-sample nullity test over
             trial sizes (the kernel degree stage of Sec. 4 and Sec. 5).
+  variants -- the paper's narrower steps: single-channel division B1 / K1,
+            the k1-only scale least squares, the one-axis scale fix.
 """
 
-from . import cbp, tls2d, exact, learned, sizes  # noqa: F401
+from . import cbp, tls2d, exact, learned, sizes, variants  # noqa: F401
