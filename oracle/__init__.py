@@ -20,6 +20,9 @@ Modules
             trial sizes (the kernel degree stage of Sec. 4 and Sec. 5).
   variants -- the paper's narrower steps: single-channel division B1 / K1,
             the k1-only scale least squares, the one-axis scale fix.
+  encoder -- the CBP encoder (Philox4x64-10 kernel draws, the coprimality
+            redraw rule, the full-convolution blur) and the multi-level
+            8-bit streams with dropped least significant bits (Sec. 3).
 """
 
-from . import cbp, tls2d, exact, learned, sizes, variants  # noqa: F401
+from . import cbp, tls2d, exact, learned, sizes, variants, encoder  # noqa: F401
