@@ -225,6 +225,30 @@ cbp_status cbp_deblur_batch(int32_t nframes, const cbp_image* b1s, const cbp_ima
                             cbp_image* latents, double* const* K1s, double* const* K2s,
                             cbp_status* per_frame, const cbp_options* opts);
 
+/* cbp_deblur for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * call uses no caller workspace: options->workspace and workspace_bytes are
+ * ignored, and the workspace is a scratch array of
+ * cbp_noalloc_scratch_bytes() bytes (48 MiB) that the library holds in every
+ * device's memory until the process ends (a grayscale 1080p frame in the
+ * MIXED form, or a 720p frame in FP64, fits).  The caller still passes the
+ * frames, the latent, the kernels (nullable) and options->diag.  The call
+ * makes no hipMalloc, hipFree or pinned-host allocation; the library's
+ * per-device set-up (stream, events, the scratch address) happens on the
+ * first call of any entry point on that device.
+ * Errors: CBP_E_NOMEM when the frame needs more than the scratch holds
+ * (cbp_last_error() names both sizes); CBP_E_UNSUPPORTED when
+ * options->flags holds CBP_FLAG_GRAPH or CBP_FLAG_AUTOTUNE (graphs and the
+ * autotuner allocate); otherwise as cbp_deblur.  Every call on one device shares that device's scratch, which
+ * keeps the last call's contents (nothing in it needs to start at zero):
+ * calls that overlap on one device -- on two streams, or from two threads --
+ * race on it and must be serialised by the caller. */
+cbp_status cbp_deblur_noalloc(const cbp_image* b1, const cbp_image* b2, cbp_image* latent,
+                              double* K1, double* K2, const cbp_options* opts);
+
+/* Size in bytes of the scratch array that cbp_deblur_noalloc uses. */
+size_t cbp_noalloc_scratch_bytes(void);
+
 /* Launch shapes chosen by the last CBP_FLAG_AUTOTUNE search on the current
  * device, with the time of one batch call under them. */
 typedef struct cbp_tuning {

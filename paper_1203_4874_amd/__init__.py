@@ -21,7 +21,8 @@ import numpy as np
 __all__ = [
     "lib", "library_path", "CbpError", "Precision", "workspace_size", "eval_unit_circle",
     "recover_kernels", "deblur", "deblur_batch", "Deblurrer", "PreparedBatch", "decode_diag", "profile",
-    "Flags", "last_tuning", "sample_grams", "MlpState", "mlp_forward", "mlp_blob_from_params", "load_mlp",
+    "Flags", "last_tuning", "sample_grams", "deblur_noalloc", "noalloc_scratch_bytes", "MlpState", "mlp_forward",
+    "mlp_blob_from_params", "load_mlp",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -107,6 +108,9 @@ _SIGS = {
     "cbp_deblur_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage),
                                         ctypes.POINTER(CbpImage), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(CbpOptions)]),
+    "cbp_deblur_noalloc": (ctypes.c_int, [ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage),
+                                          ctypes.POINTER(CbpImage), _P, _P, ctypes.POINTER(CbpOptions)]),
+    "cbp_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "cbp_last_tuning": (ctypes.c_int, [ctypes.c_void_p]),
     "cbp_sample_grams": (ctypes.c_int, [ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage), ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(CbpOptions)]),
@@ -499,6 +503,30 @@ def deblur(b1, b2, m: int, n: int, samples: int = 0, lam: float = 0.0, diag: boo
     d = _one_shot(b1, b2, m, n, samples, diag)
     L, K1, K2 = d.deblur(b1, b2, m, n, lam)
     return (L, K1, K2, d.read_diag()) if diag else (L, K1, K2)
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().cbp_noalloc_scratch_bytes())
+
+
+def deblur_noalloc(b1, b2, out, K1, K2, samples: int = 0, lam: float = 0.0, precision=None, diag=None,
+                   stream=None):
+    """cbp_deblur_noalloc: the library's per-device scratch replaces the
+    workspace.  out (the latent, whose shape gives m x n), K1 and K2 are
+    caller-allocated device tensors; diag is an optional device byte tensor
+    of diag_size() bytes."""
+    i1, i2, io = _image(b1), _image(b2), _image(out)
+    o = CbpOptions()
+    o.precision = _precision_of(b1) if precision is None else precision
+    o.samples = samples
+    o.lambda_ = lam
+    o.stream = _stream_ptr(stream)
+    o.diag = diag.data_ptr() if diag is not None else None
+    _check(lib().cbp_deblur_noalloc(ctypes.byref(i1), ctypes.byref(i2), ctypes.byref(io),
+                                    K1.data_ptr() if K1 is not None else None,
+                                    K2.data_ptr() if K2 is not None else None, ctypes.byref(o)),
+           "cbp_deblur_noalloc")
+    return out, K1, K2
 
 
 def deblur_batch(pairs, samples: int = 0, lam: float = 0.0, flags: int = 0):

@@ -22,6 +22,14 @@ namespace cbp {
 namespace {
 
 constexpr size_t kAlign = 256;
+
+// Scratch of the allocation-free entry point (cbp_deblur_noalloc): the
+// workspace of one call, one copy per device, held until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory: host
+// code uses only the address hipGetSymbolAddress returns on each device
+// (dev_state::scratch).
+constexpr size_t kScratchBytes = size_t(48) << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
 constexpr size_t kLdsLimit = 160 * 1024;
 constexpr int kComputeUnits = 256;
 constexpr int32_t kKnownFlags = CBP_FLAG_GRAPH | CBP_FLAG_AUTOTUNE;
@@ -90,6 +98,10 @@ size_t layout(frame_plan* fp, const region_sizes& r) {
   fp->total = o;
   return o;
 }
+
+// a one-frame head always fits the first launch's arguments
+static_assert(sizeof(frame_desc) % 16 == 0 && sizeof(frame_desc) + Q_COUNT * 2 * sizeof(int) <= kInlineHeadMax,
+              "one frame's head must travel inline");
 
 int nchunks(int nframes) { return (nframes + BATCH_CHUNK - 1) / BATCH_CHUNK; }
 
@@ -316,6 +328,7 @@ struct dev_state {
   std::map<std::string, tuning> tuned;
   bool have_last = false;
   cbp_tuning last = {};
+  void* scratch = nullptr;   // this device's copy of `scratch` (device address)
 };
 
 dev_state* get_dev() {
@@ -333,6 +346,9 @@ dev_state* get_dev() {
     for (pinned_slot& s : f.ring)
       if (note("hipEventCreateWithFlags", hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess)
         return nullptr;
+    if (note("hipGetSymbolAddress", hipGetSymbolAddress(&f.scratch, HIP_SYMBOL(scratch))) != hipSuccess ||
+        f.scratch == nullptr)
+      return nullptr;
     set_recover_attrs();
     set_fft_attrs();
     set_gram_mfma_attrs();
@@ -695,7 +711,10 @@ tuning autotune(dev_state& ds, const std::vector<frame_req>& reqs, const cbp_opt
   return best;
 }
 
-cbp_status batch_call(const std::vector<frame_req>& reqs, cbp_status* per_frame, const cbp_options* o) {
+// no_alloc: the call must not allocate (the allocation-free entry point):
+// its head has to travel inline, never through a pinned staging copy.
+cbp_status batch_call(const std::vector<frame_req>& reqs, cbp_status* per_frame, const cbp_options* o,
+                      bool no_alloc = false) {
   if (reqs.empty() || !o) return CBP_E_INVALID;
   for (const frame_req& r : reqs)
     if (!r.b1 || !r.b2) return CBP_E_INVALID;
@@ -738,6 +757,8 @@ cbp_status batch_call(const std::vector<frame_req>& reqs, cbp_status* per_frame,
     inline_head ih;
     if (make_inline_head(bb, &ih)) {
       e = enqueue_batch(*ds, bb, st, &ih);
+    } else if (no_alloc) {
+      return CBP_E_UNSUPPORTED;
     } else {
       e = upload_head(*ds, bb, st);
       if (e == hipSuccess) e = enqueue_batch(*ds, bb, st);
@@ -917,6 +938,35 @@ cbp_status cbp_deblur_batch(int32_t nframes, const cbp_image* b1s, const cbp_ima
                         opts->diag ? (void*)((cbp_diag*)opts->diag + f) : nullptr};
   return batch_call(reqs, per_frame, opts);
 }
+
+cbp_status cbp_deblur_noalloc(const cbp_image* b1, const cbp_image* b2, cbp_image* latent, double* K1, double* K2,
+                              const cbp_options* opts) {
+  if (!opts || !latent || !b1 || !b2) return CBP_E_INVALID;
+  // graphs pin a host copy of their head and the autotuner stages uploads:
+  // both allocate, so neither is offered here
+  if (opts->flags & (CBP_FLAG_GRAPH | CBP_FLAG_AUTOTUNE)) return CBP_E_UNSUPPORTED;
+  // host validation and the scratch bound first (no HIP call before them)
+  frame_plan fp;
+  const cbp_status s = make_plan(b1, b2, latent->height, latent->width, opts, kDefaultTuning, &fp);
+  if (s != CBP_OK) return s;
+  const size_t need = head_bytes(1) + fp.total;
+  if (need > kScratchBytes) {
+    std::snprintf(t_error, sizeof t_error, "cbp_deblur_noalloc: the frame needs %zu bytes of scratch, the limit is %zu",
+                  need, kScratchBytes);
+    return CBP_E_NOMEM;
+  }
+  dev_state* ds = get_dev();
+  if (!ds) return CBP_E_DEVICE;
+  // the one-frame head always travels in the first launch's arguments, so
+  // the call makes no staging copy; the workspace is this device's scratch
+  cbp_options o = *opts;
+  o.workspace = ds->scratch;
+  o.workspace_bytes = kScratchBytes;
+  const std::vector<frame_req> reqs = {frame_req{b1, b2, latent, latent->height, latent->width, K1, K2, o.diag}};
+  return batch_call(reqs, nullptr, &o, true);
+}
+
+size_t cbp_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 const char* cbp_last_error(void) { return t_error; }
 

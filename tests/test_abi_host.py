@@ -120,3 +120,32 @@ def test_batch_host_validation(P):
     assert L.cbp_deblur_batch(0, I1, I2, IO, None, None, st, ctypes.byref(o)) == 1
     t = P.CbpTuning()
     assert L.cbp_last_tuning(None) == 1
+
+
+def test_noalloc_host_validation(P):
+    """cbp_deblur_noalloc rejects, before any HIP call, the flags that would
+    allocate (graphs, the autotuner) and frames whose workspace exceeds the
+    library's scratch; the scratch bound is the stated 48 MiB and the mixed
+    1080p grayscale frame it is sized for fits it."""
+    global P_
+    P_ = P
+    L = P.lib()
+    limit = P.noalloc_scratch_bytes()
+    assert limit == 48 << 20
+    assert P.workspace_size(1096, 1936, 17, 1, 1, P.Precision.MIXED) <= limit
+    o = P.CbpOptions()
+    o.precision = P.Precision.MIXED
+    call = lambda a, b, c, opts: L.cbp_deblur_noalloc(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), None,
+                                                      None, ctypes.byref(opts))
+    i1, i2 = _img(0x1000, 0, 488, 648), _img(0x2000, 0, 490, 650)
+    lat = _img(0x3000, 0, 480, 640)
+    for f in (P.Flags.GRAPH, P.Flags.AUTOTUNE):
+        o.flags = f
+        assert call(i1, i2, lat, o) == 6
+    o.flags = 0
+    assert call(i1, i2, _img(0x3000, 0, 481, 640), o) == 2   # the usual shape checks come first
+    # a 1080p RGB frame needs ~132 MiB of workspace: too large for the scratch
+    big1, big2 = _img(0x1000, 0, 1094, 1934, 3), _img(0x2000, 0, 1096, 1936, 3)
+    assert call(big1, big2, _img(0x3000, 0, 1080, 1920, 3), o) == 5
+    assert b"scratch" in L.cbp_last_error()
+    assert L.cbp_deblur_noalloc(None, ctypes.byref(i2), ctypes.byref(lat), None, None, ctypes.byref(o)) == 1
