@@ -55,7 +55,7 @@ extern "C" {
 #define CBP_MAX_S 32   /* largest number of samples per axis */
 #define CBP_MAX_N 64   /* largest per-sample unknown count k1 + k2 */
 #define CBP_MAX_FFT_F32 2048  /* largest FFT grid side, FP32 division */
-#define CBP_MAX_FFT_F64 1792  /* largest FFT grid side, FP64 division */
+#define CBP_MAX_FFT_F64 2048  /* largest FFT grid side, FP64 division */
 
 typedef enum {
   CBP_OK = 0,
@@ -67,7 +67,7 @@ typedef enum {
   CBP_E_UNSUPPORTED = 6   /* option combination not built */
 } cbp_status;
 
-typedef enum { CBP_F32 = 0, CBP_F64 = 1 } cbp_dtype;
+typedef enum { CBP_F32 = 0, CBP_F64 = 1, CBP_U8 = 2 /* 8-bit streams: cbp_quantize / cbp_dequantize only */ } cbp_dtype;
 
 /* Precision form.
  *   FP64   : FP64 frames; evaluation, Gram (double-double accumulated), the
@@ -97,7 +97,7 @@ typedef struct cbp_options {
   double      lambda;           /* Tikhonov term of the Fourier division, >= 0 */
   double      tau;              /* reserved, must be 0 (the learned form predicts its own) */
   int32_t     learned;          /* 1 = learned form: weights from the network in mlp_blob (k1 + k2 <= 32) */
-  int32_t     flags;            /* CBP_FLAG_* bits; 0 = eager launches with default launch shapes */
+  int32_t     flags;            /* CBP_FLAG_* bits; 0 = the default method, eager launches, default launch shapes */
   const void* mlp_blob;         /* device network blob (cbp_mlp_export) when learned = 1, else NULL */
   void*       stream;           /* hipStream_t */
   void*       workspace;        /* device scratch owned by the caller */
@@ -109,7 +109,7 @@ typedef struct cbp_options {
  *   CBP_FLAG_GRAPH    : the call's launches are captured once into a HIP graph
  *                       (keyed by every pointer, size and option the launches
  *                       bake in) and replayed with one hipGraphLaunch on later
- *                       calls with the same key.  Up to 32 graphs are cached
+ *                       calls with the same key.  Up to 64 graphs are cached
  *                       per device; evicting one synchronises the device.
  *   CBP_FLAG_AUTOTUNE : on the first call of a batch class (dtype, frame count,
  *                       largest frame, kernel and channel count, S, precision)
@@ -121,6 +121,28 @@ typedef struct cbp_options {
  *                       the choice, with or without the flag. */
 #define CBP_FLAG_GRAPH     1
 #define CBP_FLAG_AUTOTUNE  2
+/* The paper's narrower steps, in place of this library's readings:
+ *   CBP_FLAG_DIVIDE_B1 : single-channel division (Sec. 4: B1 divided by K1 in
+ *                        the Fourier domain; Sec. 5: one frame of the pair is
+ *                        deblurred): Lhat = conj(K1hat) B1hat / (|K1hat|^2 + lambda)
+ *                        on the same grid (where K1hat vanishes the quotient is 0);
+ *   CBP_FLAG_SCALE_K1  : the scale least squares over kernel 1's equations only
+ *                        (Sec. 5: 2t unknowns over the t x t entries of k1's two
+ *                        estimates); both kernels use the scales it finds;
+ *   CBP_FLAG_ONE_AXIS  : the per-sample scales of pass X alone, fixed by the
+ *                        kernels' finite support: with a_j the scale of sample j,
+ *                        sum_j a_j X_j[x] w_j^{-y} must vanish for k_c <= y < S
+ *                        (smallest eigenvector of those equations' Gram, FP64
+ *                        with double-double entries); needs
+ *                        k1 (S - k1) + k2 (S - k2) >= S - 1 (so S >= k + 1 when
+ *                        k1 = k2 = k; CBP_E_INVALID otherwise).  The kernels are
+ *                        the real part of (1/S) sum_j a_j X_j[x] w_j^{-y} on their
+ *                        support, divided by its complex sum.
+ * SCALE_K1 and ONE_AXIS exclude each other (CBP_E_INVALID) and the learned
+ * form (CBP_E_UNSUPPORTED). */
+#define CBP_FLAG_DIVIDE_B1 4
+#define CBP_FLAG_SCALE_K1  8
+#define CBP_FLAG_ONE_AXIS  16
 
 /* Diagnostic flags (cbp_diag.flags). */
 #define CBP_DIAG_NONFINITE      1  /* a non-finite value reached the kernels */
@@ -248,6 +270,109 @@ cbp_status cbp_deblur_noalloc(const cbp_image* b1, const cbp_image* b2, cbp_imag
 
 /* Size in bytes of the scratch array that cbp_deblur_noalloc uses. */
 size_t cbp_noalloc_scratch_bytes(void);
+
+/* ------------------------------------------------------------------------
+ * Blind kernel-size estimation (Sec. 4: the kernel degree is found first,
+ * from the singularity of nested submatrices, after Barnett; Sec. 5 and
+ * Table 1: the kernel degree estimation stage, an odd-size search 9..25).
+ *
+ * With the latent size unknown, only d = H1 - H2 = W1 - W2 = k1 - k2 is
+ * known.  For each candidate k (trial sizes k1' = k, k2' = k - d) and each of
+ * S unit-circle samples of both passes, the per-sample system
+ * [C_{k-d}(e1) | -C_k(e2)] has nullity max(0, k - k1 + 1) (zero below the
+ * true size).  The test value is s = lambda_min / lambda_max of its Gram (the
+ * Grams of every candidate are principal submatrices of one Gram, built from
+ * one set of double-double correlations).  The score of a candidate is the
+ * median over the 2S samples of log10(max(s, 1e-13)); the estimate is the
+ * candidate whose score drops most below the previous candidate's (0 before
+ * the first; the smaller candidate on ties).  A largest drop below 2
+ * decades means no candidate made the systems singular: the estimate is then
+ * the largest candidate and CBP_SIZE_NONE_SINGULAR is set; a winning first
+ * candidate sets CBP_SIZE_FIRST_SINGULAR (the true size may lie below the
+ * range).  Noise raises every s toward the noise level; the test separates
+ * the sizes when the frames' noise is well below the kernels' conditioning. */
+#define CBP_SIZE_NONE_SINGULAR   1
+#define CBP_SIZE_FIRST_SINGULAR  2
+
+typedef struct cbp_size_search {
+  int32_t kmin, kmax, step;  /* candidates k1' = kmin, kmin + step, ... <= kmax, kept when
+                                1 <= k1' - d, both trial sizes <= 32 and k1' <= min(H1, W1) */
+  int32_t samples;           /* S per pass (1..32); 0 = the largest trial size of either frame */
+} cbp_size_search;
+
+typedef struct cbp_size_result {   /* written in DEVICE memory */
+  int32_t k1, k2;                  /* the estimate */
+  int32_t flags;                   /* CBP_SIZE_* */
+  int32_t ncand;                   /* candidates tested */
+  int32_t samples;                 /* S used */
+  int32_t reserved;
+  int32_t cand[CBP_MAX_K];         /* the candidates k1' (ascending) */
+  double  score[CBP_MAX_K];        /* median over samples of log10(max(s, 1e-13)) */
+  double  drop[CBP_MAX_K];         /* score[c-1] - score[c] (score[-1] = 0) */
+} cbp_size_result;
+
+/* Workspace bytes of cbp_estimate_kernel_sizes for frames of at most
+ * maxH x maxW, `channels` channels and the given search (0 when the search
+ * has no candidate or S is out of range).  opts may be NULL (FP64). */
+size_t cbp_size_workspace_size(int32_t maxH, int32_t maxW, int32_t channels, int32_t d,
+                               const cbp_size_search* search, const cbp_options* opts);
+
+/* Estimate (k1, k2) of a blurred pair without the latent size.  b1, b2: the
+ * pair (same dtype and channel count; colour frames stack their channels'
+ * systems as the recovery does); result: one cbp_size_result in device
+ * memory; ratios (device, nullable) receives s for every
+ * [candidate][pass][sample] (ncand * 2 * S doubles).  opts: precision FP64
+ * (FP64 frames) or MIXED (FP32 frames), the stream and the workspace
+ * (cbp_size_workspace_size); the other fields are ignored.  Asynchronous;
+ * the caller reads `result` after synchronising the stream.
+ * Errors (host side): CBP_E_SHAPE when H1 - H2 != W1 - W2 or no candidate
+ * fits; CBP_E_INVALID for a bad search (kmin < 1, kmax < kmin, step < 1, S
+ * outside 0..32), NULL pointers or a matrix-core precision; CBP_E_NOMEM when
+ * the workspace is too small. */
+cbp_status cbp_estimate_kernel_sizes(const cbp_image* b1, const cbp_image* b2, const cbp_size_search* search,
+                                     cbp_size_result* result, double* ratios, const cbp_options* opts);
+
+/* ------------------------------------------------------------------------
+ * The CBP encoder (Sec. 3, blur kernel selection: large random kernels, a
+ * new coprime pair for every frame; Sec. 4 eq. 1 without sensor noise) and
+ * the multi-level 8-bit streams (Sec. 3, multi-level security: a level sees
+ * the streams without some least significant bits).
+ *
+ * cbp_draw_kernel_pairs: the kernel pairs of frames frame0 .. frame0 +
+ * nframes - 1.  Entry e (row-major) of kernel s in {1, 2} at draw attempt a is
+ * u_e = ((w >> 11) + 1/2) 2^-53 with w word e mod 4 of Philox4x64-10
+ * (Salmon et al., SC 2011) at counter (e / 4, s, a, 0) and key (seed, frame);
+ * the kernel is u / sum(u) (sum in entry order).  A pair is redrawn (a + 1)
+ * while, at some sample w_j (j < S; S = samples, 0 = max(k1, k2)) of either
+ * evaluation order, the Sylvester system [C_{k2-1}(p) | -C_{k1-1}(q)] of the
+ * kernel slices p = k1(w_j, .), q = k2(w_j, .) (or k1(., w_j), k2(., w_j))
+ * has lambda_min / lambda_max of its Gram at or below 1e-12 (the slices
+ * nearly share a root); at most 64 attempts.  K1s (nframes * k1 * k1 doubles)
+ * and K2s receive the pairs, attempts[f] (device int32) the attempt used or
+ * -1 when none passed (the last draw is kept), min_ratio[f] (device, nullable)
+ * the smallest ratio of the kept pair.  One wave per frame; asynchronous on
+ * `stream`.  Errors: CBP_E_INVALID (NULL buffers, nframes < 1, frame0 < 0,
+ * S outside 1..32), CBP_E_SHAPE (k outside 1..32). */
+cbp_status cbp_draw_kernel_pairs(uint64_t seed, int64_t frame0, int32_t nframes, int32_t k1, int32_t k2,
+                                 int32_t samples, double* K1s, double* K2s, int32_t* attempts, double* min_ratio,
+                                 void* stream);
+
+/* B1 = L (x) K1 and B2 = L (x) K2 (full linear convolution, every channel):
+ * latent m x n, b1 (m + k1 - 1) x (n + k1 - 1), b2 likewise with k2, one
+ * dtype and channel count; K1, K2 device FP64 row-major.  FP32 frames
+ * accumulate in FP32 (the kernel rounded to FP32), FP64 frames in FP64.
+ * Asynchronous on `stream`.  Errors: CBP_E_INVALID, CBP_E_SHAPE. */
+cbp_status cbp_encode(const cbp_image* latent, const double* K1, int32_t k1, const double* K2, int32_t k2,
+                      cbp_image* b1, cbp_image* b2, void* stream);
+
+/* The 8-bit stream of a level without the drop_bits (0..8) least significant
+ * bits: dst = clamp(rint(255 src), 0, 255) & (255 << drop_bits), rint rounding
+ * half to even in src's precision.  src: FP32 / FP64 image; dst: a CBP_U8
+ * image of the same shape (pitch and channel stride in bytes). */
+cbp_status cbp_quantize(const cbp_image* src, cbp_image* dst, int32_t drop_bits, void* stream);
+
+/* The receiver's frame: dst = src / 255 in dst's precision (src CBP_U8). */
+cbp_status cbp_dequantize(const cbp_image* src, cbp_image* dst, void* stream);
 
 /* Launch shapes chosen by the last CBP_FLAG_AUTOTUNE search on the current
  * device, with the time of one batch call under them. */

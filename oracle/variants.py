@@ -22,8 +22,9 @@ thin; the paper itself describes, or implies, these narrower steps:
     sample w_j, each scaled by an unknown c_j) and a_j = 1 / c_j,
         K_c[y, x] = (1/S) sum_j a_j X^c_j[x] w_j^{-y},   y < S,
     must vanish for k_c <= y < S.  These k_c (S - k_c) equations per kernel
-    fix a up to one factor when S >= max(k1, k2) + 1 (at S = k1 = k2 there
-    are none); a is the smallest right singular vector of the stacked
+    can fix a up to one factor only when there are at least S - 1 of them
+    (at S = k1 = k2 there are none; the fix then refuses); a is the smallest
+    right singular vector of the stacked
     equations and K_c is the real part of the expression above on its
     support, divided by its complex sum.
 """
@@ -66,8 +67,9 @@ def one_axis_system(XU, XV, k1: int, k2: int, S: int) -> np.ndarray:
         for x in range(k):
             for y in range(k, S):
                 rows.append(X[:, x] * np.exp(2j * np.pi * ((np.arange(S) * y) % S) / S))
-    if not rows:
-        raise ValueError("the one-axis scale fix needs S >= max(k1, k2) + 1")
+    if len(rows) < S - 1:
+        raise ValueError("the one-axis scale fix needs at least S - 1 support equations "
+                         "(S >= max(k1, k2) + 1 when k1 = k2)")
     return np.array(rows)
 
 

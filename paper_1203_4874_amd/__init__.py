@@ -22,7 +22,8 @@ __all__ = [
     "lib", "library_path", "CbpError", "Precision", "workspace_size", "eval_unit_circle",
     "recover_kernels", "deblur", "deblur_batch", "Deblurrer", "PreparedBatch", "decode_diag", "profile",
     "Flags", "last_tuning", "sample_grams", "deblur_noalloc", "noalloc_scratch_bytes", "MlpState", "mlp_forward",
-    "mlp_blob_from_params", "load_mlp",
+    "mlp_blob_from_params", "load_mlp", "estimate_kernel_sizes", "draw_kernel_pairs", "encode", "quantize",
+    "dequantize",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -46,6 +47,9 @@ class Precision:
 class Flags:
     GRAPH = 1      # capture the call's launches in a HIP graph, replay on later identical calls
     AUTOTUNE = 2   # search the launch shapes of this batch class on its first call
+    DIVIDE_B1 = 4  # single-channel division B1 / K1
+    SCALE_K1 = 8   # scale least squares over kernel 1's equations only
+    ONE_AXIS = 16  # per-sample scales of one evaluation order, fixed by the kernels' support
 
 
 class CbpError(RuntimeError):
@@ -90,6 +94,21 @@ class CbpDiag(ctypes.Structure):
                 ("judge", ctypes.c_double * 2)]
 
 
+class CbpSizeSearch(ctypes.Structure):
+    _fields_ = [("kmin", ctypes.c_int32), ("kmax", ctypes.c_int32), ("step", ctypes.c_int32),
+                ("samples", ctypes.c_int32)]
+
+
+class CbpSizeResult(ctypes.Structure):
+    _fields_ = [("k1", ctypes.c_int32), ("k2", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("ncand", ctypes.c_int32), ("samples", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("cand", ctypes.c_int32 * CBP_MAX_K), ("score", ctypes.c_double * CBP_MAX_K),
+                ("drop", ctypes.c_double * CBP_MAX_K)]
+
+
+SIZE_NONE_SINGULAR = 1
+SIZE_FIRST_SINGULAR = 2
+
 _LIB = None
 
 # every entry point declared in include/cbp.h with (restype, argtypes)
@@ -111,6 +130,17 @@ _SIGS = {
     "cbp_deblur_noalloc": (ctypes.c_int, [ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage),
                                           ctypes.POINTER(CbpImage), _P, _P, ctypes.POINTER(CbpOptions)]),
     "cbp_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "cbp_size_workspace_size": (ctypes.c_size_t, [ctypes.c_int32] * 4 + [ctypes.POINTER(CbpSizeSearch),
+                                                                      ctypes.POINTER(CbpOptions)]),
+    "cbp_estimate_kernel_sizes": (ctypes.c_int, [ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage),
+                                                 ctypes.POINTER(CbpSizeSearch), _P, _P,
+                                                 ctypes.POINTER(CbpOptions)]),
+    "cbp_draw_kernel_pairs": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]),
+    "cbp_encode": (ctypes.c_int, [ctypes.POINTER(CbpImage), _P, ctypes.c_int32, _P, ctypes.c_int32,
+                                  ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage), _P]),
+    "cbp_quantize": (ctypes.c_int, [ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage), ctypes.c_int32, _P]),
+    "cbp_dequantize": (ctypes.c_int, [ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage), _P]),
     "cbp_last_tuning": (ctypes.c_int, [ctypes.c_void_p]),
     "cbp_sample_grams": (ctypes.c_int, [ctypes.POINTER(CbpImage), ctypes.POINTER(CbpImage), ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(CbpOptions)]),
@@ -175,6 +205,23 @@ def _image(t) -> CbpImage:
     if sx != 1:
         raise ValueError("frames must have unit stride along x")
     return CbpImage(t.data_ptr(), 0 if t.dtype == torch.float32 else 1, H, W, C, sy, sc)
+
+
+def _image_u8(t) -> CbpImage:
+    torch = _torch()
+    if not t.is_cuda or t.dtype != torch.uint8:
+        raise ValueError("8-bit streams must be uint8 device tensors")
+    if t.dim() == 2:
+        C, (H, W) = 1, t.shape
+        sc, sy, sx = t.shape[0] * t.stride(0), t.stride(0), t.stride(1)
+    elif t.dim() == 3:
+        C, H, W = t.shape
+        sc, sy, sx = t.stride(0), t.stride(1), t.stride(2)
+    else:
+        raise ValueError("streams must be (H, W) or (C, H, W)")
+    if sx != 1:
+        raise ValueError("streams must have unit stride along x")
+    return CbpImage(t.data_ptr(), 2, H, W, C, sy, sc)
 
 
 def _precision_of(t) -> int:
@@ -503,6 +550,92 @@ def deblur(b1, b2, m: int, n: int, samples: int = 0, lam: float = 0.0, diag: boo
     d = _one_shot(b1, b2, m, n, samples, diag)
     L, K1, K2 = d.deblur(b1, b2, m, n, lam)
     return (L, K1, K2, d.read_diag()) if diag else (L, K1, K2)
+
+
+def estimate_kernel_sizes(b1, b2, kmin: int = 1, kmax: int = CBP_MAX_K, step: int = 1, samples: int = 0,
+                          ratios: bool = False, stream=None) -> dict:
+    """cbp_estimate_kernel_sizes: blind (k1, k2) of a blurred pair (no latent
+    size).  Synchronises and returns the estimate, its flags, the candidates
+    with their scores and drops and (ratios=True) the per-sample ratios
+    [candidate][pass][sample]."""
+    torch = _torch()
+    i1, i2 = _image(b1), _image(b2)
+    se = CbpSizeSearch(kmin, kmax, step, samples)
+    o = CbpOptions()
+    o.precision = _precision_of(b1)
+    d = i1.height - i2.height
+    nbytes = int(lib().cbp_size_workspace_size(max(i1.height, i2.height), max(i1.width, i2.width), i1.channels,
+                                               d, ctypes.byref(se), ctypes.byref(o)))
+    if nbytes == 0:
+        raise CbpError(2, "cbp_size_workspace_size")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=b1.device)
+    res = torch.zeros(ctypes.sizeof(CbpSizeResult), dtype=torch.uint8, device=b1.device)
+    rat = torch.zeros(CBP_MAX_K * 2 * CBP_MAX_S, dtype=torch.float64, device=b1.device) if ratios else None
+    o.stream = _stream_ptr(stream)
+    o.workspace = ws.data_ptr()
+    o.workspace_bytes = ws.numel()
+    _check(lib().cbp_estimate_kernel_sizes(ctypes.byref(i1), ctypes.byref(i2), ctypes.byref(se), res.data_ptr(),
+                                           rat.data_ptr() if rat is not None else None, ctypes.byref(o)),
+           "cbp_estimate_kernel_sizes")
+    torch.cuda.synchronize()
+    r = CbpSizeResult.from_buffer_copy(bytes(res.cpu().numpy()))
+    nc = r.ncand
+    out = dict(k1=r.k1, k2=r.k2, flags=r.flags, S=r.samples, candidates=list(r.cand[:nc]),
+               scores=np.array(r.score[:nc]), drops=np.array(r.drop[:nc]))
+    if rat is not None:
+        out["ratios"] = rat[:nc * 2 * r.samples].cpu().numpy().reshape(nc, 2, r.samples)
+    return out
+
+
+def draw_kernel_pairs(seed: int, frame0: int, nframes: int, k1: int, k2: int, samples: int = 0, device="cuda",
+                      stream=None):
+    """cbp_draw_kernel_pairs: the encoder's coprime kernel pairs of frames
+    frame0 .. frame0 + nframes - 1.  Returns (K1s [n, k1, k1], K2s, attempts,
+    min_ratio) -- the last two synchronised to host numpy arrays."""
+    torch = _torch()
+    K1s = torch.empty((nframes, k1, k1), dtype=torch.float64, device=device)
+    K2s = torch.empty((nframes, k2, k2), dtype=torch.float64, device=device)
+    att = torch.empty(nframes, dtype=torch.int32, device=device)
+    mr = torch.empty(nframes, dtype=torch.float64, device=device)
+    _check(lib().cbp_draw_kernel_pairs(seed, frame0, nframes, k1, k2, samples, K1s.data_ptr(), K2s.data_ptr(),
+                                       att.data_ptr(), mr.data_ptr(), _stream_ptr(stream)), "cbp_draw_kernel_pairs")
+    return K1s, K2s, att.cpu().numpy(), mr.cpu().numpy()
+
+
+def encode(L, K1, K2, b1=None, b2=None, stream=None):
+    """cbp_encode: the blurred pair (B1, B2) of a latent frame."""
+    torch = _torch()
+    k1, k2 = K1.shape[-1], K2.shape[-1]
+    m, n = L.shape[-2], L.shape[-1]
+    lead = tuple(L.shape[:-2])
+    if b1 is None:
+        b1 = torch.empty(lead + (m + k1 - 1, n + k1 - 1), dtype=L.dtype, device=L.device)
+    if b2 is None:
+        b2 = torch.empty(lead + (m + k2 - 1, n + k2 - 1), dtype=L.dtype, device=L.device)
+    il, i1, i2 = _image(L), _image(b1), _image(b2)
+    _check(lib().cbp_encode(ctypes.byref(il), K1.data_ptr(), k1, K2.data_ptr(), k2, ctypes.byref(i1),
+                            ctypes.byref(i2), _stream_ptr(stream)), "cbp_encode")
+    return b1, b2
+
+
+def quantize(B, drop_bits: int = 0, out=None, stream=None):
+    """cbp_quantize: the 8-bit stream of a level without drop_bits low bits."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(B.shape, dtype=torch.uint8, device=B.device)
+    _check(lib().cbp_quantize(ctypes.byref(_image(B)), ctypes.byref(_image_u8(out)), drop_bits, _stream_ptr(stream)),
+           "cbp_quantize")
+    return out
+
+
+def dequantize(q, dtype=None, out=None, stream=None):
+    """cbp_dequantize: q / 255 as float32 (or dtype)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(q.shape, dtype=dtype or torch.float32, device=q.device)
+    _check(lib().cbp_dequantize(ctypes.byref(_image_u8(q)), ctypes.byref(_image(out)), _stream_ptr(stream)),
+           "cbp_dequantize")
+    return out
 
 
 def noalloc_scratch_bytes() -> int:

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libcbp.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["eval.hip", "recover.hip", "gram_mfma.hip", "mlp.hip", "fft.hip", "api.hip"]
+SOURCES = ["eval.hip", "recover.hip", "gram_mfma.hip", "mlp.hip", "fft.hip", "sizes.hip", "encoder.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

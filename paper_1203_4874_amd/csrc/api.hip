@@ -32,7 +32,14 @@ constexpr size_t kScratchBytes = size_t(48) << 20;
 __device__ __align__(256) char scratch[kScratchBytes];
 constexpr size_t kLdsLimit = 160 * 1024;
 constexpr int kComputeUnits = 256;
-constexpr int32_t kKnownFlags = CBP_FLAG_GRAPH | CBP_FLAG_AUTOTUNE;
+constexpr int32_t kKnownFlags =
+    CBP_FLAG_GRAPH | CBP_FLAG_AUTOTUNE | CBP_FLAG_DIVIDE_B1 | CBP_FLAG_SCALE_K1 | CBP_FLAG_ONE_AXIS;
+
+// The VAR_* bits of a call's variant flags.
+int variant_bits(int32_t flags) {
+  return ((flags & CBP_FLAG_DIVIDE_B1) ? VAR_DIVIDE_B1 : 0) | ((flags & CBP_FLAG_SCALE_K1) ? VAR_SCALE_K1 : 0) |
+         ((flags & CBP_FLAG_ONE_AXIS) ? VAR_ONE_AXIS : 0);
+}
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
@@ -100,7 +107,8 @@ size_t layout(frame_plan* fp, const region_sizes& r) {
 }
 
 // a one-frame head always fits the first launch's arguments
-static_assert(sizeof(frame_desc) % 16 == 0 && sizeof(frame_desc) + Q_COUNT * 2 * sizeof(int) <= kInlineHeadMax,
+static_assert(sizeof(frame_desc) % 16 == 0 &&
+                  sizeof(frame_desc) + ((Q_COUNT * 2 * sizeof(int) + 15) & ~(size_t)15) <= kInlineHeadMax,
               "one frame's head must travel inline");
 
 int nchunks(int nframes) { return (nframes + BATCH_CHUNK - 1) / BATCH_CHUNK; }
@@ -145,10 +153,21 @@ bool valid_image(const cbp_image* im) {
   return true;
 }
 
+// An 8-bit stream (the quantisation entry points only).
+bool valid_u8_image(const cbp_image* im) {
+  if (!im || !im->data || im->dtype != CBP_U8) return false;
+  if (im->height < 1 || im->width < 1 || im->channels < 1 || im->pitch < im->width) return false;
+  if (im->channels > 1 && im->channel_stride < (int64_t)im->height * im->pitch) return false;
+  return true;
+}
+
 cbp_status check_options(const cbp_options* o, int dtype) {
   if (!o) return CBP_E_INVALID;
   if ((o->learned != 0) != (o->mlp_blob != nullptr)) return CBP_E_INVALID;   // the learned form needs its network
   if (!(o->lambda >= 0.0) || o->tau != 0.0 || (o->flags & ~kKnownFlags) != 0) return CBP_E_INVALID;
+  // one scale fix at a time; the learned form has its own weighted one
+  if ((o->flags & CBP_FLAG_SCALE_K1) && (o->flags & CBP_FLAG_ONE_AXIS)) return CBP_E_INVALID;
+  if (o->learned && (o->flags & (CBP_FLAG_SCALE_K1 | CBP_FLAG_ONE_AXIS))) return CBP_E_UNSUPPORTED;
   if (o->precision == CBP_PREC_FP64) return dtype == CBP_F64 ? CBP_OK : CBP_E_INVALID;
   if (o->precision == CBP_PREC_MIXED || o->precision == CBP_PREC_MFMA32 || o->precision == CBP_PREC_BF16)
     return dtype == CBP_F32 ? CBP_OK : CBP_E_INVALID;
@@ -162,8 +181,10 @@ int gram_format(int precision) {
 }
 
 // Shapes -> plan.  All checks are host-side.
+// sizes_only: the plan of the size-estimation entry point, which runs only
+// the evaluation and the Gram (any S >= 1; no FFT or solver limits).
 cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, const cbp_options* o,
-                     const tuning& tn, frame_plan* fp) {
+                     const tuning& tn, frame_plan* fp, bool sizes_only = false) {
   if (!valid_image(b1) || !valid_image(b2)) return CBP_E_INVALID;
   if (b1->dtype != b2->dtype || b1->channels != b2->channels) return CBP_E_INVALID;
   const cbp_status so = check_options(o, b1->dtype);
@@ -174,7 +195,9 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
   if (k1 < 1 || k2 < 1 || k1 > CBP_MAX_K || k2 > CBP_MAX_K) return CBP_E_SHAPE;
   const int kmax = k1 > k2 ? k1 : k2;
   const int S = o->samples ? o->samples : kmax;
-  if (S < kmax || S > CBP_MAX_S) return CBP_E_INVALID;
+  if (S < (sizes_only ? 1 : kmax) || S > CBP_MAX_S) return CBP_E_INVALID;
+  // the one-axis scale fix needs at least S - 1 support equations
+  if (!sizes_only && (o->flags & CBP_FLAG_ONE_AXIS) && k1 * (S - k1) + k2 * (S - k2) < S - 1) return CBP_E_INVALID;
   const int esize = b1->dtype == CBP_F32 ? 4 : 8;
   fp->H1 = b1->height; fp->W1 = b1->width; fp->H2 = b2->height; fp->W2 = b2->width;
   fp->Hmax = fp->H1 > fp->H2 ? fp->H1 : fp->H2;
@@ -186,6 +209,12 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
   fp->RG = (fp->Hmax + fp->rpg - 1) / fp->rpg;
   fp->Py = smooth7(fp->Hmax);
   fp->Px = smooth7(fp->Wmax);
+  if (sizes_only) {
+    fp->hx = fp->Px / 2 + 1;
+    fp->cw = 1;
+    layout(fp, regions(fp->Hmax, fp->Wmax, kmax, S, fp->nch, esize));
+    return CBP_OK;
+  }
   if (fp->Py > max_fft(esize) || fp->Px > max_fft(esize)) return CBP_E_SHAPE;
   if (!make_fft_plan(fp->Py, &fp->fy, tn.fft_order) || !make_fft_plan(fp->Px, &fp->fx, tn.fft_order))
     return CBP_E_SHAPE;
@@ -203,7 +232,7 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
 }
 
 frame_desc make_desc(const frame_plan& fp, const cbp_image* b1, const cbp_image* b2, char* ws, double* K1,
-                     double* K2, const cbp_image* latent, double lambda, void* diag, bool learned) {
+                     double* K2, const cbp_image* latent, double lambda, void* diag, bool learned, int variant) {
   frame_desc d;
   std::memset(&d, 0, sizeof d);
   d.b1 = b1->data;
@@ -243,6 +272,7 @@ frame_desc make_desc(const frame_plan& fp, const cbp_image* b1, const cbp_image*
   d.twxd = (c64*)(ws + fp.off_twxd);
   d.twx = ws + fp.off_twx;
   d.twy = ws + fp.off_twy;
+  d.variant = variant;
   return d;
 }
 
@@ -308,7 +338,7 @@ struct graph_entry {
   void* host = nullptr;  // pinned copy of the workspace head the graph uploads on every replay
   uint64_t last_use = 0;
 };
-constexpr size_t kMaxGraphs = 32;
+constexpr size_t kMaxGraphs = 64;
 
 // Capture stream, events, staging ring, graph and tuning caches of one
 // device (created once; every stream at the default priority).  A call's
@@ -352,6 +382,8 @@ dev_state* get_dev() {
     set_recover_attrs();
     set_fft_attrs();
     set_gram_mfma_attrs();
+    set_size_attrs();
+    set_encoder_attrs();
     f.ready = true;
   }
   return &f;
@@ -464,7 +496,7 @@ std::string class_key(const std::vector<frame_req>& reqs, const cbp_options* o) 
 // Validate and plan every frame; statuses go to `status` (one per request).
 // Returns CBP_E_NOMEM when the valid frames do not fit the workspace.
 cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o, const tuning& tn,
-                       std::vector<cbp_status>& status, batch_build* bb) {
+                       std::vector<cbp_status>& status, batch_build* bb, bool sizes_only = false) {
   const int nreq = (int)reqs.size();
   status.assign(nreq, CBP_OK);
   bb->idx.clear();
@@ -475,7 +507,7 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
   for (int f = 0; f < nreq; ++f) {
     const frame_req& r = reqs[f];
     frame_plan fp;
-    cbp_status s = make_plan(r.b1, r.b2, r.m, r.n, o, tn, &fp);
+    cbp_status s = make_plan(r.b1, r.b2, r.m, r.n, o, tn, &fp, sizes_only);
     if (s == CBP_OK && r.b1->dtype != dtype) s = CBP_E_INVALID;
     if (s == CBP_OK && (r.latent != nullptr) != latent) s = CBP_E_INVALID;
     if (s == CBP_OK && latent &&
@@ -509,7 +541,7 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
   for (int i = 0; i < nf; ++i) {
     const frame_req& r = reqs[bb->idx[i]];
     descs[i] = make_desc(bb->plans[i], r.b1, r.b2, ws + off, r.K1, r.K2, r.latent, o->lambda, r.diag,
-                         o->learned != 0);
+                         o->learned != 0, variant_bits(o->flags));
     off += bb->plans[i].total;
   }
   const int cap = tn.wg_per_cu > 0 ? tn.wg_per_cu * kComputeUnits : 0;
@@ -598,12 +630,16 @@ hipError_t enqueue_batch(dev_state& ds, const batch_build& bb, hipStream_t st, c
 bool make_inline_head(const batch_build& bb, inline_head* ih) {
   if (bb.chunks.size() != 1) return false;
   const int nf = bb.chunks[0].nf;
+  // the prefix sums travel in whole 16-byte units (the kernel copies them so);
+  // the padding lands in the workspace head's prefix-sum region, which is larger
   const size_t nd = (size_t)nf * sizeof(frame_desc), ns = (size_t)Q_COUNT * (nf + 1) * sizeof(int);
-  if (nd % 16 != 0 || ns % 16 != 0 || nd + ns > (size_t)kInlineHeadMax) return false;
+  const size_t nsp = (ns + 15) & ~(size_t)15;
+  if (nd % 16 != 0 || nd + nsp > (size_t)kInlineHeadMax) return false;
   ih->ndesc_bytes = (int)nd;
-  ih->nstart_bytes = (int)ns;
+  ih->nstart_bytes = (int)nsp;
   std::memcpy(ih->bytes, bb.head.data(), nd);
   std::memcpy(ih->bytes + nd, bb.head.data() + head_desc_bytes(nf), ns);
+  std::memset(ih->bytes + nd + ns, 0, nsp - ns);
   return true;
 }
 
@@ -710,6 +746,20 @@ tuning autotune(dev_state& ds, const std::vector<frame_req>& reqs, const cbp_opt
   *best_ms = bms;
   return best;
 }
+
+// Candidates of a size search (as the oracle forms them): k1' = kmin, kmin +
+// step, ... <= kmax with 1 <= k1' - d, both trial sizes <= CBP_MAX_K and
+// k1' <= min(H1, W1).  False for a malformed search.
+bool size_candidates(int d, const cbp_size_search* s, int H1, int W1, size_cands* c) {
+  if (s->kmin < 1 || s->kmax < s->kmin || s->step < 1) return false;
+  c->n = 0;
+  c->d = d;
+  for (int k = s->kmin; k <= s->kmax && c->n < CBP_MAX_K; k += s->step)
+    if (k - d >= 1 && k <= CBP_MAX_K && k - d <= CBP_MAX_K && k <= H1 && k <= W1) c->k1[c->n++] = k;
+  return true;
+}
+
+size_t size_ratio_bytes(int ncand, int S) { return align_up((size_t)ncand * 2 * S * sizeof(double)); }
 
 // no_alloc: the call must not allocate (the allocation-free entry point):
 // its head has to travel inline, never through a pinned staging copy.
@@ -967,6 +1017,170 @@ cbp_status cbp_deblur_noalloc(const cbp_image* b1, const cbp_image* b2, cbp_imag
 }
 
 size_t cbp_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+size_t cbp_size_workspace_size(int32_t maxH, int32_t maxW, int32_t channels, int32_t d,
+                               const cbp_size_search* search, const cbp_options* opts) {
+  if (!search || maxH < 1 || maxW < 1 || channels < 1) return 0;
+  size_cands c;
+  if (!size_candidates(d, search, maxH, maxW, &c) || c.n == 0) return 0;
+  const int K1 = c.k1[c.n - 1], kmax = std::max(K1, K1 - d);
+  const int S = search->samples ? search->samples : K1;
+  if (S < 1 || S > CBP_MAX_S) return 0;
+  const int esize = (opts && opts->precision != CBP_PREC_FP64) ? 4 : 8;
+  frame_plan fp;
+  return head_bytes(1) + layout(&fp, regions(maxH, maxW, kmax, S, channels, esize)) + size_ratio_bytes(c.n, S);
+}
+
+cbp_status cbp_estimate_kernel_sizes(const cbp_image* b1, const cbp_image* b2, const cbp_size_search* search,
+                                     cbp_size_result* result, double* ratios, const cbp_options* opts) {
+  if (!b1 || !b2 || !search || !result || !opts) return CBP_E_INVALID;
+  if (!valid_image(b1) || !valid_image(b2) || b1->dtype != b2->dtype || b1->channels != b2->channels)
+    return CBP_E_INVALID;
+  if (opts->precision != CBP_PREC_FP64 && opts->precision != CBP_PREC_MIXED) return CBP_E_INVALID;
+  const int d = b1->height - b2->height;
+  if (b1->width - b2->width != d) return CBP_E_SHAPE;
+  size_cands c;
+  if (!size_candidates(d, search, b1->height, b1->width, &c)) return CBP_E_INVALID;
+  if (c.n == 0) return CBP_E_SHAPE;
+  const int K1 = c.k1[c.n - 1];
+  const int S = search->samples ? search->samples : K1;
+  if (S < 1 || S > CBP_MAX_S) return CBP_E_INVALID;
+  // the frame's plan at the largest trial sizes: its evaluation and Gram
+  // correlations serve every candidate
+  cbp_options o = *opts;
+  o.samples = S;
+  o.lambda = 0.0;
+  o.tau = 0.0;
+  o.learned = 0;
+  o.mlp_blob = nullptr;
+  o.flags = 0;
+  o.diag = nullptr;
+  const size_t rbytes = size_ratio_bytes(c.n, S);
+  if (!o.workspace || o.workspace_bytes < rbytes) return CBP_E_NOMEM;
+  o.workspace_bytes -= rbytes;
+  double* rat = ratios ? ratios : (double*)((char*)o.workspace + o.workspace_bytes);
+  const std::vector<frame_req> reqs = {
+      frame_req{b1, b2, nullptr, b1->height - K1 + 1, b1->width - K1 + 1, nullptr, nullptr, nullptr}};
+  std::vector<cbp_status> status;
+  batch_build bb;
+  const cbp_status s = build_batch(reqs, &o, kDefaultTuning, status, &bb, true);
+  if (s != CBP_OK) return s;
+  if (status[0] != CBP_OK) return status[0];
+  // the probe's items: (candidate, pass, sample)
+  const int items = c.n * 2 * S;
+  int* starts = (int*)(bb.head.data() + head_desc_bytes(1));
+  starts[Q_SIZE_PROBE * 2] = 0;
+  starts[Q_SIZE_PROBE * 2 + 1] = items;
+  chunk_view& cv = bb.chunks[0];
+  cv.items[Q_SIZE_PROBE] = items;
+  cv.grid[Q_SIZE_PROBE] = grid_for(items, 0);
+  int nmax = 1;
+  for (int i = 0; i < c.n; ++i) nmax = std::max(nmax, 2 * c.k1[i] - d);
+  const int NL = 2 * (K1 + (K1 - d)) - 1;
+  dev_state* ds = get_dev();
+  if (!ds) return CBP_E_DEVICE;
+  const batch_ref br = {cv.descs, cv.starts, cv.nf};
+  hipStream_t st = (hipStream_t)opts->stream;
+  std::lock_guard<std::mutex> lk(ds->launch_mu);
+  (void)hipGetLastError();
+  auto run = [&]() -> hipError_t {
+    inline_head ih;
+    const bool inl = make_inline_head(bb, &ih);
+    if (!inl) CBP_TRY(upload_head(*ds, bb, st));
+    if (b1->dtype == CBP_F32) {
+      CBP_TRY(launch_fold<float>(br, cv.grid[Q_FOLD], 0, inl ? &ih : nullptr, st));
+      CBP_TRY(launch_eval_rows<float>(br, cv.grid[Q_EVAL_ROWS], st));
+    } else {
+      CBP_TRY(launch_fold<double>(br, cv.grid[Q_FOLD], 0, inl ? &ih : nullptr, st));
+      CBP_TRY(launch_eval_rows<double>(br, cv.grid[Q_EVAL_ROWS], st));
+    }
+    CBP_TRY(launch_eval_cols(br, cv.grid[Q_EVAL_COLS], st));
+    CBP_TRY(launch_gram(br, cv.grid[Q_GRAM], st));
+    CBP_TRY(launch_size_probe(br, cv.grid[Q_SIZE_PROBE], c, nmax, NL, rat, st));
+    CBP_TRY(launch_size_decide(c, S, rat, result, st));
+    return hipSuccess;
+  };
+  return run() == hipSuccess ? CBP_OK : CBP_E_DEVICE;
+}
+
+// ------------------------------------------------------------------ the encoder and the 8-bit streams
+cbp_status cbp_draw_kernel_pairs(uint64_t seed, int64_t frame0, int32_t nframes, int32_t k1, int32_t k2,
+                                 int32_t samples, double* K1s, double* K2s, int32_t* attempts, double* min_ratio,
+                                 void* stream) {
+  if (!K1s || !K2s || !attempts || nframes < 1 || frame0 < 0) return CBP_E_INVALID;
+  if (k1 < 1 || k2 < 1 || k1 > CBP_MAX_K || k2 > CBP_MAX_K) return CBP_E_SHAPE;
+  const int S = samples ? samples : std::max(k1, k2);
+  if (S < 1 || S > CBP_MAX_S) return CBP_E_INVALID;
+  dev_state* ds = get_dev();
+  if (!ds) return CBP_E_DEVICE;
+  (void)hipGetLastError();
+  return note("launch_draw_pairs", launch_draw_pairs(seed, frame0, nframes, k1, k2, S, K1s, K2s, (int*)attempts,
+                                                    min_ratio, (hipStream_t)stream)) == hipSuccess
+             ? CBP_OK : CBP_E_DEVICE;
+}
+
+cbp_status cbp_encode(const cbp_image* latent, const double* K1, int32_t k1, const double* K2, int32_t k2,
+                      cbp_image* b1, cbp_image* b2, void* stream) {
+  if (!latent || !K1 || !K2 || !b1 || !b2) return CBP_E_INVALID;
+  if (!valid_image(latent) || !valid_image(b1) || !valid_image(b2)) return CBP_E_INVALID;
+  if (b1->dtype != latent->dtype || b2->dtype != latent->dtype || b1->channels != latent->channels ||
+      b2->channels != latent->channels)
+    return CBP_E_INVALID;
+  if (k1 < 1 || k2 < 1 || k1 > CBP_MAX_K || k2 > CBP_MAX_K) return CBP_E_SHAPE;
+  const int m = latent->height, n = latent->width;
+  if (b1->height != m + k1 - 1 || b1->width != n + k1 - 1 || b2->height != m + k2 - 1 || b2->width != n + k2 - 1)
+    return CBP_E_SHAPE;
+  dev_state* ds = get_dev();
+  if (!ds) return CBP_E_DEVICE;
+  (void)hipGetLastError();
+  const int nch = latent->channels;
+  const int64_t lcs = nch > 1 ? latent->channel_stride : 0, c1 = nch > 1 ? b1->channel_stride : 0,
+                c2 = nch > 1 ? b2->channel_stride : 0;
+  hipError_t e;
+  if (latent->dtype == CBP_F32)
+    e = launch_blur<float>((const float*)latent->data, latent->pitch, lcs, m, n, nch, K1, k1, K2, k2,
+                           (float*)b1->data, b1->pitch, c1, (float*)b2->data, b2->pitch, c2, (hipStream_t)stream);
+  else
+    e = launch_blur<double>((const double*)latent->data, latent->pitch, lcs, m, n, nch, K1, k1, K2, k2,
+                            (double*)b1->data, b1->pitch, c1, (double*)b2->data, b2->pitch, c2, (hipStream_t)stream);
+  return note("launch_blur", e) == hipSuccess ? CBP_OK : CBP_E_DEVICE;
+}
+
+cbp_status cbp_quantize(const cbp_image* src, cbp_image* dst, int32_t drop_bits, void* stream) {
+  if (!valid_image(src) || !valid_u8_image(dst) || drop_bits < 0 || drop_bits > 8) return CBP_E_INVALID;
+  if (src->height != dst->height || src->width != dst->width || src->channels != dst->channels) return CBP_E_SHAPE;
+  dev_state* ds = get_dev();
+  if (!ds) return CBP_E_DEVICE;
+  (void)hipGetLastError();
+  const int nch = src->channels;
+  const int64_t scs = nch > 1 ? src->channel_stride : 0, dcs = nch > 1 ? dst->channel_stride : 0;
+  hipError_t e;
+  if (src->dtype == CBP_F32)
+    e = launch_quantize<float>((const float*)src->data, src->pitch, scs, (unsigned char*)dst->data, dst->pitch, dcs,
+                               src->height, src->width, nch, drop_bits, (hipStream_t)stream);
+  else
+    e = launch_quantize<double>((const double*)src->data, src->pitch, scs, (unsigned char*)dst->data, dst->pitch,
+                                dcs, src->height, src->width, nch, drop_bits, (hipStream_t)stream);
+  return note("launch_quantize", e) == hipSuccess ? CBP_OK : CBP_E_DEVICE;
+}
+
+cbp_status cbp_dequantize(const cbp_image* src, cbp_image* dst, void* stream) {
+  if (!valid_u8_image(src) || !valid_image(dst)) return CBP_E_INVALID;
+  if (src->height != dst->height || src->width != dst->width || src->channels != dst->channels) return CBP_E_SHAPE;
+  dev_state* ds = get_dev();
+  if (!ds) return CBP_E_DEVICE;
+  (void)hipGetLastError();
+  const int nch = src->channels;
+  const int64_t scs = nch > 1 ? src->channel_stride : 0, dcs = nch > 1 ? dst->channel_stride : 0;
+  hipError_t e;
+  if (dst->dtype == CBP_F32)
+    e = launch_dequantize<float>((const unsigned char*)src->data, src->pitch, scs, (float*)dst->data, dst->pitch, dcs,
+                                 src->height, src->width, nch, (hipStream_t)stream);
+  else
+    e = launch_dequantize<double>((const unsigned char*)src->data, src->pitch, scs, (double*)dst->data, dst->pitch,
+                                  dcs, src->height, src->width, nch, (hipStream_t)stream);
+  return note("launch_dequantize", e) == hipSuccess ? CBP_OK : CBP_E_DEVICE;
+}
 
 const char* cbp_last_error(void) { return t_error; }
 

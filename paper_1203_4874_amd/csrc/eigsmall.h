@@ -359,6 +359,40 @@ __device__ inline void small_bisect(const small_ws& s, int n, int target, double
   *tn_out = tn;
 }
 
+// ---------------------------------------------------------------- extreme-eigenvalue ratio
+// Workspace of a reduction without eigenvectors (the matrix, three complex
+// vectors, the real tridiagonal and the split-lane partial sums).
+__host__ __device__ inline size_t small_probe_lds_bytes(int n) {
+  return (size_t)n * n * sizeof(c64) + 3 * (size_t)n * sizeof(c64) + 2 * (size_t)n * sizeof(double) +
+         (size_t)64 * sizeof(c64);
+}
+
+__device__ inline small_ws small_probe_carve(char* base, int n) {
+  small_ws s = {};
+  char* p = base;
+  s.A = (c64*)p; p += (size_t)n * n * sizeof(c64);
+  s.e = (c64*)p; p += n * sizeof(c64);
+  s.w = (c64*)p; p += n * sizeof(c64);
+  s.u = (c64*)p; p += n * sizeof(c64);
+  s.a = (double*)p; p += n * sizeof(double);
+  s.b = (double*)p; p += n * sizeof(double);
+  s.part = (dd*)p;   // 64 complex partial sums (the reduction's split lanes)
+  return s;
+}
+
+// lambda_min / lambda_max of the Hermitian positive semidefinite matrix in
+// s.A (n x n, destroyed): Householder tridiagonalisation, then Sturm
+// multisection brackets of the smallest and the largest eigenvalue (their
+// midpoints; the smallest clamped at 0).  Wave-uniform; 0 for a zero matrix.
+__device__ inline double small_extreme_ratio(small_ws& s, int n) {
+  small_tridiag(s, n);
+  double lo0, hi0, lo1, hi1, tn;
+  small_bisect(s, n, 1, &lo0, &hi0, &tn);
+  small_bisect(s, n, n, &lo1, &hi1, &tn);
+  const double lmin = fmax(0.5 * (lo0 + hi0), 0.0), lmax = 0.5 * (lo1 + hi1);
+  return lmax > 0.0 ? lmin / lmax : 0.0;
+}
+
 // Every eigenvalue of T on a log scale: lane l < n returns its (l+1)-th
 // smallest eigenvalue, bisected in log10 over [1e-15 ||T||, ||T||] to
 // SPECTRUM_ITERS steps (values below the range return its bottom).  Used for

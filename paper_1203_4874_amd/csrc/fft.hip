@@ -3,7 +3,8 @@
 // Sec. 5: an inverse FFT of the divided spectrum).  Over a Py x Px grid that
 // covers both frames (no wrap-around of the full convolutions):
 //   Lhat = (conj(K1hat) B1hat + conj(K2hat) B2hat) / (|K1hat|^2 + |K2hat|^2 + lambda),
-//   L    = IFFT2(Lhat) cropped to m x n.
+//   L    = IFFT2(Lhat) cropped to m x n
+// (with the single-channel variant, the paper's B1 / K1: the K2 terms drop).
 //
 // Three passes, each a hand-written Stockham FFT in LDS (fft_core.h):
 //   1. row pass: row y of B1 and row y of B2 packed as one complex row
@@ -164,6 +165,7 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
     const double* K2 = d.K2;
     const c64* twd = d.twxd;
     const T lam = (T)d.lambda;
+    const bool two = !(d.variant & VAR_DIVIDE_B1);   // two-channel division, or B1 / K1 alone
     const int nf = 2 * cw;                      // transforms in flight: (column, frame)
     cplx<T>* a = (cplx<T>*)sm_cf;               // [nf][N]
     cplx<T>* b = a + (size_t)nf * N;            // [nf][N]
@@ -252,8 +254,8 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
       }
       const cplx<T> B1 = f1[(size_t)(2 * c) * N + ky];
       const cplx<T> B2 = f1[(size_t)(2 * c + 1) * N + ky];
-      const cplx<T> num = cmulc(kh1, B1) + cmulc(kh2, B2);
-      const T kk = norm2(kh1) + norm2(kh2);
+      const cplx<T> num = two ? cmulc(kh1, B1) + cmulc(kh2, B2) : cmulc(kh1, B1);
+      const T kk = two ? norm2(kh1) + norm2(kh2) : norm2(kh1);
       const T den = kk + lam;
       const T inv = den > T(0) ? T(1) / den : T(0);
       // where both kernel spectra vanish (a zeroed kernel pair) the

@@ -23,7 +23,7 @@ namespace cbp {
 // Work queues, one per kernel.
 enum queue_id {
   Q_DIAG = 0, Q_FOLD, Q_EVAL_COLS, Q_EVAL_ROWS, Q_ROW_FWD, Q_GRAM, Q_GRAMM, Q_SAMPLE, Q_FINALIZE, Q_COL,
-  Q_ROW_INV, Q_TWID, Q_COUNT
+  Q_ROW_INV, Q_TWID, Q_SIZE_PROBE, Q_COUNT
 };
 
 // Frames per batched launch (the item prefix sums of one launch sit in LDS).
@@ -82,7 +82,12 @@ struct frame_desc {
   c64* twxd;
   void* twx;
   void* twy;
+  // paper-faithful variants (CBP_FLAG_DIVIDE_B1 / SCALE_K1 / ONE_AXIS as
+  // VAR_* bits); 0 = the default method
+  int variant;
+  int pad_[3];
 };
+constexpr int VAR_DIVIDE_B1 = 1, VAR_SCALE_K1 = 2, VAR_ONE_AXIS = 4;
 
 // Work items of each queue for one frame (the grid of a one-frame launch).
 inline int queue_items(int q, const frame_plan& p) {
@@ -100,6 +105,7 @@ inline int queue_items(int q, const frame_plan& p) {
     case Q_COL: return ((p.hx + p.cw - 1) / p.cw) * p.nch;
     case Q_ROW_INV: return ((p.m + 1) / 2) * p.nch;
     case Q_TWID: return (p.Px + p.Py + 255) / 256;
+    case Q_SIZE_PROBE: return 0;   // set by the size-estimation entry point (candidates x 2S)
   }
   return 0;
 }
@@ -246,7 +252,7 @@ void prof_end(int phase, hipStream_t st);
 // item prefix sums of the chunk) passed by value to the first launch, which
 // reads its descriptors from it and stores it into the workspace head for the
 // launches that follow: no host-to-device copy precedes the call's kernels.
-constexpr int kInlineHeadMax = 1600;   // three frames
+constexpr int kInlineHeadMax = 1664;   // three frames
 struct inline_head {
   int ndesc_bytes;    // nframes * sizeof(frame_desc); 0: no inline head
   int nstart_bytes;   // Q_COUNT * (nframes + 1) * sizeof(int)
@@ -302,6 +308,38 @@ size_t row_lds_bytes(int N, int esize);
 size_t col_lds_bytes(int N, int cw, int esize);
 void set_recover_attrs();
 void set_fft_attrs();
+
+// sizes.hip: blind kernel-size estimation.  Candidates k1' (ascending) with
+// k2' = k1' - d; the probe's items are (candidate, pass, sample) of the one
+// frame of br, whose plan holds the largest trial sizes; ratios is
+// [n][2][S] device scratch.
+struct size_cands {
+  int n;                 // candidate count (<= CBP_MAX_K)
+  int d;                 // k1 - k2 = H1 - H2
+  int k1[CBP_MAX_K];
+};
+hipError_t launch_size_probe(const batch_ref& br, int grid, const size_cands& c, int nmax, int NLmax, double* ratios,
+                             hipStream_t st);
+hipError_t launch_size_decide(const size_cands& c, int S, const double* ratios, cbp_size_result* out,
+                              hipStream_t st);
+size_t size_probe_lds_bytes(int nmax, int NLmax);
+void set_size_attrs();
+
+// encoder.hip: the encoder's kernel draws, the blur and the 8-bit streams.
+hipError_t launch_draw_pairs(unsigned long long seed, long long frame0, int nframes, int k1, int k2, int S,
+                             double* K1s, double* K2s, int* attempts, double* min_ratio, hipStream_t st);
+size_t draw_pairs_lds_bytes(int k1, int k2);
+void set_encoder_attrs();
+template <typename T>
+hipError_t launch_blur(const T* L, int64_t lp, int64_t lcs, int m, int n, int nch, const double* K1, int k1,
+                       const double* K2, int k2, T* B1, int64_t p1, int64_t cs1, T* B2, int64_t p2, int64_t cs2,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_quantize(const T* src, int64_t sp, int64_t scs, unsigned char* dst, int64_t dp, int64_t dcs, int H,
+                           int W, int nch, int drop, hipStream_t st);
+template <typename T>
+hipError_t launch_dequantize(const unsigned char* src, int64_t sp, int64_t scs, T* dst, int64_t dp, int64_t dcs,
+                             int H, int W, int nch, hipStream_t st);
 
 // mlp.hip: the learned form's network on every frame of the launch
 // (features -> weights and tau); blob is a device mlp_blob.

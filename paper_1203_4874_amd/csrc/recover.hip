@@ -237,8 +237,178 @@ __host__ __device__ inline size_t fin_base_bytes(int S) {
   return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) + small_lds_bytes(2 * S);
 }
 
+// Kernels from the per-sample scales: both kernels' normalisation (divide by
+// the complex sum over the support, keep the real part) and diagnostics;
+// F1 / F2 hold each kernel's S x S (row stride S) inverse transform.  Returns
+// true when a kernel is non-finite or sums to zero (wave-uniform).
+__device__ inline __attribute__((always_inline)) bool normalise_kernels(const c64* F1, const c64* F2, int S, int k1,
+                                                                         int k2, double* K1, double* K2,
+                                                                         cbp_diag* diag) {
+  const int tid = threadIdx.x, SS = S * S;
+  const float rS = 1.0f / (float)S;
+  bool bad = false;
+  for (int c = 0; c < 2; ++c) {
+    const int k = c == 0 ? k1 : k2;
+    const c64* F = c == 0 ? F1 : F2;
+    const float rk = 1.0f / (float)k;
+    double sr = 0.0, si = 0.0, ein = 0.0, eall = 0.0;
+    for (int e = tid; e < SS; e += SMALL_NT) {
+      int y, x;
+      split_index(e, S, rS, y, x);
+      const c64 v = F[e];
+      const double p = norm2(v);
+      eall += p;
+      if (y < k && x < k) { sr += v.re; si += v.im; ein += p; }
+    }
+    {   // pairs of sums share a reduction (each component in wsum's order)
+      const c64 a = wsum_c(c64{sr, si}), b = wsum_c(c64{ein, eall});
+      sr = a.re;
+      si = a.im;
+      ein = b.re;
+      eall = b.im;
+    }
+    const double s2 = sr * sr + si * si;
+    double* K = c == 0 ? K1 : K2;
+    double re2 = 0.0, im2 = 0.0;
+    for (int e = tid; e < k * k; e += SMALL_NT) {
+      int y, x;
+      split_index(e, k, rk, y, x);
+      const c64 v = F[y * S + x];
+      const double kr = (v.re * sr + v.im * si) / s2;
+      const double ki = (v.im * sr - v.re * si) / s2;
+      K[e] = kr;
+      re2 += kr * kr;
+      im2 += ki * ki;
+    }
+    {
+      const c64 q = wsum_c(c64{re2, im2});
+      re2 = q.re;
+      im2 = q.im;
+    }
+    if (tid == 0 && diag) {
+      diag->kernel_imag[c] = sqrt(im2) / fmax(sqrt(re2), 1e-300);
+      diag->kernel_outside[c] = (eall - ein) / fmax(eall, 1e-300);
+      if (!(s2 > 0.0) || !isfinite(s2)) atomicOr(&diag->flags, CBP_DIAG_KERNEL_ZERO);
+      if (!isfinite(re2)) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
+    }
+    bad = bad || !(s2 > 0.0) || !isfinite(s2) || !isfinite(re2);   // wave-uniform
+  }
+  return bad;
+}
+
+// Scale system of the one-axis fix (S x S, double-double entries in LDS).
+struct cdd_mat_acc {
+  const cdd* H;
+  int n;
+  __device__ cdd get(int r, int c) const { return H[r * n + c]; }
+};
+
+// The one-axis scale fix (the paper's scales from one evaluation order,
+// fixed by the kernels' finite support).  With the pass-X null vectors X_j
+// (u: kernel 2's slice, k2 taps; v: kernel 1's slice, k1 taps) and a_j the
+// scale of sample j, the inverse DFT over j of a_j X^c_j[x] must vanish at
+// rows k_c <= y < S.  The Gram of those equations is
+//   H[j][j'] = sum_c (sum_{x < k_c} conj(X^c_j[x]) X^c_j'[x]) g_c(j - j'),
+//   g_c(t) = sum_{y = k_c}^{S-1} w^{t y},  w = exp(-2 pi i / S),
+// and a is its smallest eigenvector; K_c[y][x] = (1/S) sum_j a_j X^c_j[x] w_j^{-y}.
+__device__ inline __attribute__((always_inline)) void one_axis_frame(const c64* xvec, int S, int k1, int k2,
+                                                                      double* K1, double* K2, cbp_diag* diag,
+                                                                      char* sm_fin) {
+  const int N = k1 + k2, SS = S * S, tid = threadIdx.x;
+  const float rS = 1.0f / (float)S;
+  c64* tw = (c64*)sm_fin;                                   // S
+  c64* X = tw + CBP_MAX_S;                                  // [S][N]
+  char* after = (char*)(X + (((size_t)S * N + 1) & ~(size_t)1));
+  small_ws w = small_carve(after, S);
+  cdd* Hm = (cdd*)(after + small_lds_bytes(S));             // [S][S]
+  unit_twiddles(tw, S);
+  for (int e = tid; e < S * N; e += SMALL_NT) X[e] = xvec[e];   // pass X: [j][l]
+  __syncthreads();
+  for (int e = tid; e < SS; e += SMALL_NT) {
+    int j, jp;
+    split_index(e, S, rS, j, jp);
+    int t = j - jp;
+    if (t < 0) t += S;
+    dot2 re, im;
+    re.init();
+    im.init();
+    for (int c = 0; c < 2; ++c) {
+      const int k = c == 0 ? k1 : k2, o = c == 0 ? k2 : 0;
+      dot2 sre, sim;
+      sre.init();
+      sim.init();
+      for (int x = 0; x < k; ++x) {
+        const c64 a = X[j * N + o + x], b = X[jp * N + o + x];
+        sre.add_prod(a.re, b.re); sre.add_prod(a.im, b.im);
+        sim.add_prod(a.re, b.im); sim.add_prod(-a.im, b.re);
+      }
+      c64 g = {0.0, 0.0};
+      int ty = (t * k) % S;
+      for (int y = k; y < S; ++y) {
+        g = g + tw[ty];
+        ty += t;
+        if (ty >= S) ty -= S;
+      }
+      const dd sr = sre.result(), si = sim.result();
+      re.add_prod(sr.hi, g.re); re.add_prod(sr.lo, g.re); re.add_prod(-si.hi, g.im); re.add_prod(-si.lo, g.im);
+      im.add_prod(sr.hi, g.im); im.add_prod(sr.lo, g.im); im.add_prod(si.hi, g.re); im.add_prod(si.lo, g.re);
+    }
+    Hm[e] = cdd{re.result(), im.result()};
+  }
+  __syncthreads();
+  for (int e = tid; e < SS; e += SMALL_NT) w.A[e] = {Hm[e].re.hi, Hm[e].im.hi};
+  const cdd_mat_acc H{Hm, S};
+  const double hmax = wmax(tid < S ? dd_val(Hm[tid * S + tid].re) : 0.0);
+  __syncthreads();
+  double lam1;
+  int steps;
+  const dd mu = small_eig(w, H, S, diag != nullptr, &lam1, &steps);
+  if (tid == 0 && diag) {
+    diag->k1 = k1; diag->k2 = k2; diag->S = S; diag->n = N;
+    diag->scale_lambda0 = dd_val(mu);
+    diag->scale_lambda1 = lam1;
+    diag->scale_scale = hmax;
+    diag->refine_scale = steps;
+    if (!(lam1 - dd_val(mu) > 1e-13 * hmax)) atomicOr(&diag->flags, CBP_DIAG_SCALE_WEAK);
+  }
+  if (diag)
+    for (int t = tid; t < S; t += SMALL_NT) {
+      diag->scale_vec[t][0] = w.x[t].re;
+      diag->scale_vec[t][1] = w.x[t].im;
+    }
+  __syncthreads();
+  // F[c][y][x] = (1/S) sum_j a_j X^c_j[x] w_j^{-y}  (into the solver's matrix region, 2 S^2 entries)
+  c64* F = w.A;    // kernel 1: the solver's matrix region (S^2 entries, free after the solve)
+  c64* F2 = w.W;   // kernel 2: its W region (S (S + 1) entries)
+  const double rs = 1.0 / (double)S;
+  for (int e = tid; e < 2 * SS; e += SMALL_NT) {
+    const int c = e >= SS, yx = e - c * SS;
+    int y, x;
+    split_index(yx, S, rS, y, x);
+    const int k = c == 0 ? k1 : k2, o = c == 0 ? k2 : 0;
+    c64 acc = {0.0, 0.0};
+    if (x < k) {
+      int t = 0;
+      for (int j = 0; j < S; ++j) {
+        acc = acc + (w.x[j] * X[j * N + o + x]) * conj(tw[t]);
+        t += y;
+        if (t >= S) t -= S;
+      }
+    }
+    (c == 0 ? F : F2)[yx] = {acc.re * rs, acc.im * rs};
+  }
+  __syncthreads();
+  if (normalise_kernels(F, F2, S, k1, k2, K1, K2, diag)) zero_kernels(K1, k1, K2, k2);
+}
+
 __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* xvec, int S, int k1, int k2, c64* pq, double* K1,
-                                      double* K2, cbp_diag* diag, char* sm_fin, const double* wts) {
+                                      double* K2, cbp_diag* diag, char* sm_fin, const double* wts, int variant) {
+  if (variant & VAR_ONE_AXIS) {
+    one_axis_frame(xvec, S, k1, k2, K1, K2, diag, sm_fin);
+    return;
+  }
+  // kernel 1's equations only (the k1-only scale least squares) or both kernels'
+  const int nc = (variant & VAR_SCALE_K1) ? 1 : 2;
   const int N = k1 + k2, n2 = 2 * S, SS = S * S;
   const int tid = threadIdx.x;
   const float rS = 1.0f / (float)S, rSS = 1.0f / (float)SS, rn2 = 1.0f / (float)n2;
@@ -280,7 +450,7 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
     re.init();
     im.init();
     const double W = wts ? wts[jj] * wts[S + i] : 1.0;
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < nc; ++c) {
       c64 P = pql[(size_t)c * SS + i * S + jj];
       const c64 Q = pql[(size_t)(2 + c) * SS + i * S + jj];
       if (wts) P = {W * P.re, W * P.im};
@@ -297,18 +467,19 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
     const int tt = isa ? t : t - S;
     dot2 d;
     d.init();
-    for (int q0 = 0; q0 < 2 * S; q0 += 8) {
+    const int nq = nc * S;
+    for (int q0 = 0; q0 < nq; q0 += 8) {
       c64 v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int q = min(q0 + u, 2 * S - 1);
+        const int q = min(q0 + u, nq - 1);
         const int c = q >= S, r = q - c * S;
         v[u] = pql[isa ? (size_t)c * SS + r * S + tt : (size_t)(2 + c) * SS + tt * S + r];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int q = q0 + u;
-        if (q < 2 * S) {
+        if (q < nq) {
           const int r = q >= S ? q - S : q;
           if (wts) {
             const double W = isa ? wts[tt] * wts[S + r] : wts[r] * wts[S + tt];
@@ -433,53 +604,7 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
     Kh[e] = acc;
   }
   __syncthreads();
-  bool bad = false;   // a kernel estimate is non-finite or sums to zero
-  for (int c = 0; c < 2; ++c) {
-    const int k = c == 0 ? k1 : k2;
-    const float rk = 1.0f / (float)k;
-    double sr = 0.0, si = 0.0, ein = 0.0, eall = 0.0;
-    for (int e = tid; e < SS; e += SMALL_NT) {
-      int y, x;
-      split_index(e, S, rS, y, x);
-      const c64 v = Kh[(size_t)c * SS + e];
-      const double p = norm2(v);
-      eall += p;
-      if (y < k && x < k) { sr += v.re; si += v.im; ein += p; }
-    }
-    {   // pairs of sums share a reduction (each component in wsum's order)
-      const c64 a = wsum_c(c64{sr, si}), b = wsum_c(c64{ein, eall});
-      sr = a.re;
-      si = a.im;
-      ein = b.re;
-      eall = b.im;
-    }
-    const double s2 = sr * sr + si * si;
-    double* K = c == 0 ? K1 : K2;
-    double re2 = 0.0, im2 = 0.0;
-    for (int e = tid; e < k * k; e += SMALL_NT) {
-      int y, x;
-      split_index(e, k, rk, y, x);
-      const c64 v = Kh[(size_t)c * SS + y * S + x];
-      const double kr = (v.re * sr + v.im * si) / s2;
-      const double ki = (v.im * sr - v.re * si) / s2;
-      K[e] = kr;
-      re2 += kr * kr;
-      im2 += ki * ki;
-    }
-    {
-      const c64 q = wsum_c(c64{re2, im2});
-      re2 = q.re;
-      im2 = q.im;
-    }
-    if (tid == 0 && diag) {
-      diag->kernel_imag[c] = sqrt(im2) / fmax(sqrt(re2), 1e-300);
-      diag->kernel_outside[c] = (eall - ein) / fmax(eall, 1e-300);
-      if (!(s2 > 0.0) || !isfinite(s2)) atomicOr(&diag->flags, CBP_DIAG_KERNEL_ZERO);
-      if (!isfinite(re2)) atomicOr(&diag->flags, CBP_DIAG_NONFINITE);
-    }
-    bad = bad || !(s2 > 0.0) || !isfinite(s2) || !isfinite(re2);   // wave-uniform
-  }
-  if (bad) zero_kernels(K1, k1, K2, k2);
+  if (normalise_kernels(Kh, Kh + SS, S, k1, k2, K1, K2, diag)) zero_kernels(K1, k1, K2, k2);
 }
 
 // Returns true when the kernel is non-finite or sums to zero (wave-uniform).
@@ -594,7 +719,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_finalize(batch_ref br, int plain_o
     double* K1 = plain_only ? d.Kalt : d.K1;
     double* K2 = plain_only ? d.Kalt + CBP_MAX_K * CBP_MAX_K : d.K2;
     finalize_frame(d.xvec, d.S, d.k1, d.k2, d.pq, K1, K2, plain_only ? nullptr : d.diag, sm_fin,
-                   plain_only ? nullptr : d.wts);
+                   plain_only ? nullptr : d.wts, d.variant);
   });
 }
 

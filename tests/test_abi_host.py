@@ -149,3 +149,61 @@ def test_noalloc_host_validation(P):
     assert call(big1, big2, _img(0x3000, 0, 1080, 1920, 3), o) == 5
     assert b"scratch" in L.cbp_last_error()
     assert L.cbp_deblur_noalloc(None, ctypes.byref(i2), ctypes.byref(lat), None, None, ctypes.byref(o)) == 1
+
+
+def test_size_estimation_host_validation(P):
+    """cbp_estimate_kernel_sizes: host-side errors before any HIP call."""
+    global P_
+    P_ = P
+    L = P.lib()
+    o = P.CbpOptions()
+    o.precision = P.Precision.FP64
+    se = P.CbpSizeSearch(1, 16, 1, 0)
+    i1, i2 = _img(0x1000, 1, 50, 60), _img(0x2000, 1, 48, 58)
+    call = lambda a, b, s, opts, res=0x4000: L.cbp_estimate_kernel_sizes(
+        ctypes.byref(a), ctypes.byref(b), ctypes.byref(s), res, None, ctypes.byref(opts))
+    assert call(i1, i2, se, o) == 5                                    # no workspace
+    assert call(i1, _img(0x2000, 1, 48, 59), se, o) == 2               # H1 - H2 != W1 - W2
+    assert call(i1, i2, P.CbpSizeSearch(0, 16, 1, 0), o) == 1          # kmin < 1
+    assert call(i1, i2, P.CbpSizeSearch(5, 4, 1, 0), o) == 1           # kmax < kmin
+    assert call(i1, i2, P.CbpSizeSearch(1, 16, 0, 0), o) == 1          # step < 1
+    assert call(i1, i2, P.CbpSizeSearch(1, 16, 1, 33), o) == 1         # S > 32
+    assert call(i1, i2, P.CbpSizeSearch(40, 50, 1, 0), o) == 2         # no candidate fits
+    assert call(i1, i2, se, o, res=None) == 1                          # no result buffer
+    assert call(_img(0x1000, 0, 50, 60), i2, se, o) == 1               # dtypes differ
+    o.precision = P.Precision.MFMA32
+    assert call(_img(0x1000, 0, 50, 60), _img(0x2000, 0, 48, 58), se, o) == 1   # dd Gram forms only
+    o.precision = P.Precision.FP64
+    ws = lambda *a: L.cbp_size_workspace_size(*a[:4], ctypes.byref(a[4]), ctypes.byref(o))
+    assert ws(50, 60, 1, 2, se) > 0
+    assert ws(50, 60, 1, 2, P.CbpSizeSearch(1, 16, 0, 0)) == 0
+    assert ws(50, 60, 3, 2, se) > ws(50, 60, 1, 2, se)
+
+
+def test_encoder_host_validation(P):
+    """Encoder and 8-bit stream entry points: host-side errors before any HIP call."""
+    global P_
+    P_ = P
+    L = P.lib()
+    assert L.cbp_draw_kernel_pairs(1, 0, 0, 5, 5, 0, 0x1000, 0x2000, 0x3000, None, None) == 1    # no frame
+    assert L.cbp_draw_kernel_pairs(1, 0, 4, 0, 5, 0, 0x1000, 0x2000, 0x3000, None, None) == 2    # k < 1
+    assert L.cbp_draw_kernel_pairs(1, 0, 4, 5, 33, 0, 0x1000, 0x2000, 0x3000, None, None) == 2   # k > 32
+    assert L.cbp_draw_kernel_pairs(1, 0, 4, 5, 5, 33, 0x1000, 0x2000, 0x3000, None, None) == 1   # S > 32
+    assert L.cbp_draw_kernel_pairs(1, -1, 4, 5, 5, 0, 0x1000, 0x2000, 0x3000, None, None) == 1   # frame0 < 0
+    assert L.cbp_draw_kernel_pairs(1, 0, 4, 5, 5, 0, None, 0x2000, 0x3000, None, None) == 1
+    lat = _img(0x1000, 0, 40, 50)
+    enc = lambda l, k1, k2, b1, b2: L.cbp_encode(ctypes.byref(l), 0x5000, k1, 0x6000, k2, ctypes.byref(b1),
+                                                 ctypes.byref(b2), None)
+    assert enc(lat, 5, 3, _img(0x2000, 0, 45, 54), _img(0x3000, 0, 42, 52)) == 2     # B1 height != m + k1 - 1
+    assert enc(lat, 5, 3, _img(0x2000, 1, 44, 54), _img(0x3000, 0, 42, 52)) == 1     # dtype differs
+    assert enc(lat, 40, 3, _img(0x2000, 0, 79, 89), _img(0x3000, 0, 42, 52)) == 2    # k > 32
+    q8 = P.CbpImage(0x7000, 2, 40, 50, 1, 50, 2000)
+    assert L.cbp_quantize(ctypes.byref(lat), ctypes.byref(q8), 9, None) == 1         # drop_bits > 8
+    assert L.cbp_quantize(ctypes.byref(lat), ctypes.byref(lat), 0, None) == 1        # dst must be 8-bit
+    assert L.cbp_quantize(ctypes.byref(lat), ctypes.byref(P.CbpImage(0x7000, 2, 41, 50, 1, 50, 2050)), 0,
+                          None) == 2
+    assert L.cbp_dequantize(ctypes.byref(lat), ctypes.byref(lat), None) == 1        # src must be 8-bit
+    # an 8-bit image is not a frame of the deblurring entry points
+    o = P.CbpOptions()
+    o.precision = P.Precision.MIXED
+    assert L.cbp_deblur(ctypes.byref(q8), ctypes.byref(q8), ctypes.byref(lat), None, None, ctypes.byref(o)) == 1
