@@ -1,18 +1,31 @@
 """Benchmark: deblurred Mpixel/s of the CBP hot path (kernel recovery + two-channel
 Fourier division) on one MI355X.
 
-Workload: one 480x640 grayscale frame per step (smooth scene of 40 anisotropic
-Gaussians + 0.1 texture), coprime 9x9 / 11x11 kernels (Gaussian sigma 2 + 0.2
-uniform, sum 1), additive noise sigma 1e-3, lambda 1e-4, S = 11.  Inputs are
-generated on the host, copied to the device once and resident in HBM before
-the timed region.  The headline `value` is the mixed form (FP32 frames and FFT,
-FP64 kernel recovery); the plain FP64 form is timed the same way and reported
-beside it, each with its PSNR against the FP64 oracle's latent.
+Headline workload: a stream of 300 RGB frames of 1080x1920 (a moving-blob
+surveillance scene, per-channel gains and texture), one coprime 15x15 / 17x17
+kernel pair for every frame, additive noise sigma 5e-3, lambda 1e-4, S = 17.
+The stream cycles through U (default 24) generated frames; every one of the
+300 frames has its own device buffers, resident in HBM before the timed
+region.  Frames are deblurred in batches of 8 (one cbp_deblur_batch call per
+batch, each replayed as a HIP graph); channels share one kernel pair and the
+latent is divided channel by channel.  The headline `value` is the mixed form
+(FP32 frames, FFT and division; FP64 evaluation, double-double Gram, FP64
+eigen-solves and scale fix); the plain FP64 form is timed the same way and
+reported beside it, each with its kernel error and PSNR against the FP64
+oracle on sampled frames.
 
-A step is one cbp_deblur call (every kernel of the path).  W untimed warm-up
-steps, then exactly K timed steps between two device synchronisations.  A
-second pass of K steps records HIP events around every kernel (on the stream
-the kernels run on) for the per-kernel averages and the roofline line.
+A step is one batch (one call over 8 frames: every kernel of the path).  All
+batches of the stream are captured once before timing; then W untimed warm-up
+steps and exactly K timed steps (step i runs batch i mod 38) between two
+device synchronisations.  A profiled pass (HIP events around every kernel on
+the call's stream, eager launches) gives the per-kernel averages for the
+roofline line.  A real-time pass replays the stream at 30 frames per second
+arrival (a batch starts when its last frame has arrived) for per-frame
+arrival-to-output latency percentiles.
+
+Also reported: the form the workload names (learned weights + BF16 Gram),
+the 480x640 single-frame workload (every precision form), the 64-frame 720p
+batching workload, and the CPU oracle on sampled frames of the stream.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -39,26 +52,38 @@ FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=38, help="timed batch steps (38 = the 300-frame stream once)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=300, help="frames of the 1080p RGB stream")
+    ap.add_argument("--unique-frames", type=int, default=24, help="generated frames the stream cycles through")
+    ap.add_argument("--batch", type=int, default=8, help="frames per call (one HIP graph per batch)")
+    ap.add_argument("--fps", type=float, default=30.0, help="arrival rate of the real-time pass (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-frames", type=int, default=4, help="stream frames the oracle runs on")
+    ap.add_argument("--forms", default="fp64,learned_bf16",
+                    help="comma-separated extra forms on the stream (fp64, learned_bf16, learned)")
+    ap.add_argument("--single-steps", type=int, default=100,
+                    help="steps of the 480x640 single-frame workload (0 = skip)")
     ap.add_argument("--batch-frames", type=int, default=64,
-                    help="frames of the 720p batching workload reported beside the headline (0 = skip)")
+                    help="frames of the 720p batching workload (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=10)
-    ap.add_argument("--colour-frames", type=int, default=8,
-                    help="frames of the 1080p colour workload (one batch; 0 = skip)")
-    ap.add_argument("--colour-steps", type=int, default=20)
-    ap.add_argument("--forms", default="mixed,fp64,mfma32,bf16,learned",
-                    help="comma-separated forms of the single-frame workload (mixed is always run)")
+    ap.add_argument("--workers", type=int, default=16, help="host processes generating the stream's frames")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (counter calibration runs)")
     return ap.parse_args()
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def psnr(a, b, peak=1.0):
     mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
     return float("inf") if mse == 0 else 10.0 * np.log10(peak * peak / mse)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 def source_hash(names):
@@ -69,19 +94,50 @@ def source_hash(names):
     return h.hexdigest()[:16]
 
 
-# Algorithmic cost of each kernel for one frame of this workload.  Bytes: the
-# minimum HBM traffic of the kernel's own inputs and outputs.  FLOPs: the FP64
-# arithmetic of the kernel's algorithm, counted as real operations (a complex
-# multiply-add is 8, a double-double complex multiply-add about 40).
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def traffic_for(phase, workload):
+    """Calibrated HBM bytes per launch of a kernel on a workload, from the
+    committed counter summary, while the kernel's sources are unchanged."""
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tf):
+        return None
+    with open(tf) as fh:
+        tr = json.load(fh)
+    ent = tr.get(f"{phase}@{workload}")
+    if ent and ent.get("source_hash") == source_hash(ent.get("sources", [])):
+        return ent.get("bytes_per_launch")
+    return None
+
+
+# Algorithmic cost of each kernel for one frame of the single-frame workload.
+# Bytes: the minimum HBM traffic of the kernel's own inputs and outputs.
+# FLOPs: the FP64 arithmetic of the kernel's algorithm, counted as real
+# operations (a complex multiply-add is 8, a double-double one about 40).
 def eig_flops(n, refine_steps, invit=3, bisect_probes=64 * 8):
     """One Hermitian smallest-eigenvector solve of order n: Householder
     tridiagonalisation (16/3 n^3), Sturm multisection (about 5 n per probe),
-    the LDL^T factors of T - sigma I (4 n), `invit` inverse iterations on T
-    (forward and backward substitution on a complex vector and its norm,
-    about 16 n each), x = Q D y with the reflectors applied one by one (a dot
-    and an axpy per reflector, 8 n^2) and `refine_steps` Newton corrections
-    (a double-double Gram mat-vec, 40 n^2, two reflector sweeps, 16 n^2, and
-    a tridiagonal solve)."""
+    the LDL^T factors of T - sigma I (4 n), `invit` inverse iterations,
+    x = Q D y with the reflectors applied one by one (8 n^2) and
+    `refine_steps` Newton corrections (a double-double Gram mat-vec, 40 n^2,
+    two reflector sweeps, 16 n^2, and a solve)."""
     return 16.0 / 3.0 * n ** 3 + bisect_probes * 5 * n + 4 * n + invit * 16 * n + 8 * n * n \
         + refine_steps * (56 * n * n + 16 * n)
 
@@ -91,12 +147,9 @@ def kernel_models(H1, W1, H2, W2, m, n, k1, k2, S, Py, Px, esize, refine_sample,
     N = k1 + k2
     cplx = 2 * esize
     pix_in = (H1 * W1 + H2 * W2)
-    # cofactor grids P, Q for both kernels (S*S*k complex MACs each), the
-    # scale system (|P|^2, |Q|^2 sums and the cross sums), the 2S solve, the
-    # averaged spectra and the two-stage S x S inverse DFT cropped to k x k
     fin = sum(2 * S * S * k * 8 + (S * S * k + S * k * k) * 8 * 2 for k in (k1, k2)) \
         + 2 * 2 * S * S * 3 + 2 * S * S * 8 + eig_flops(2 * S, refine_scale) + 2 * S * S * 14
-    models = {
+    return {
         "fold_cols": dict(bound="hbm", bytes=pix_in * esize + 8 * S * (W1 + W2)),
         "eval_rows": dict(bound="hbm", bytes=pix_in * esize + 16 * S * (H1 + H2)),
         "row_fft_fwd": dict(bound="hbm", bytes=pix_in * esize + cplx * hx * (H1 + H2)),
@@ -105,7 +158,185 @@ def kernel_models(H1, W1, H2, W2, m, n, k1, k2, S, Py, Px, esize, refine_sample,
         "sample_eig": dict(bound="alu", flops=2 * S * eig_flops(N, refine_sample), peak=FP64_PEAK_TFLOPS),
         "scale_assemble": dict(bound="alu", flops=fin, peak=FP64_PEAK_TFLOPS),
     }
-    return models
+
+
+# ---------------------------------------------------------------- the 1080p RGB stream
+
+def _colour_frame(f):
+    """Frame f of the 1080p colour workload as FP32 frames (pool worker)."""
+    import synth
+    h = synth.config5_frame(f)
+    return dict(B1=h["B1"].astype(np.float32), B2=h["B2"].astype(np.float32), K1=h["K1"], K2=h["K2"],
+                L=h["L"].astype(np.float32), m=h["m"], n=h["n"], S=h["S"], lam=h["lam"], noise=h["noise"])
+
+
+class Stream:
+    """The stream's frames in HBM (one buffer pair and one latent per frame)
+    and its batches, prepared once (argument marshalling, graph capture)."""
+
+    def __init__(self, P, torch, dev, host, nframes, batch, dtype, precision, flags, mlp=None):
+        self.P, self.torch = P, torch
+        self.nframes, self.batch = nframes, batch
+        U = len(host)
+        m, n = host[0]["m"], host[0]["n"]
+        self.m, self.n = m, n
+        src1 = [torch.as_tensor(h["B1"], device=dev).to(dtype) for h in host]
+        src2 = [torch.as_tensor(h["B2"], device=dev).to(dtype) for h in host]
+        self.b1 = [src1[f % U].clone() for f in range(nframes)]
+        self.b2 = [src2[f % U].clone() for f in range(nframes)]
+        del src1, src2
+        self.out = [torch.empty((3, m, n), dtype=dtype, device=dev) for _ in range(nframes)]
+        H = max(max(h["B1"].shape[1], h["B2"].shape[1]) for h in host)
+        W = max(max(h["B1"].shape[2], h["B2"].shape[2]) for h in host)
+        self.d = P.Deblurrer(H, W, H - m + 1, 3, batch, precision, device=dev)
+        self.starts = list(range(0, nframes, batch))
+        self.batches = []
+        for s in self.starts:
+            fr = range(s, min(s + batch, nframes))
+            pairs = [(self.b1[f], self.b2[f], m, n) for f in fr]
+            self.batches.append(self.d.prepare_batch(pairs, lam=host[0]["lam"], outs=[self.out[f] for f in fr],
+                                                     flags=flags, mlp=mlp))
+        torch.cuda.synchronize()
+
+    def frames_in(self, i):
+        b = i % len(self.batches)
+        return min(self.starts[b] + self.batch, self.nframes) - self.starts[b]
+
+    def run(self, i):
+        self.batches[i % len(self.batches)].run(check=False)
+
+    def kernels(self, f):
+        pb = self.batches[f // self.batch]
+        j = f - self.starts[f // self.batch]
+        return pb.K1s[j].cpu().numpy(), pb.K2s[j].cpu().numpy()
+
+
+def time_stream(torch, s, warmup, steps):
+    for i in range(len(s.batches)):          # capture every batch's graph (untimed)
+        s.run(i)
+    torch.cuda.synchronize()
+    for i in range(warmup):
+        s.run(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        s.run(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    frames = sum(s.frames_in(i) for i in range(steps))
+    return dict(seconds=dt, frames=frames, ms_per_step=1e3 * dt / steps,
+                value=frames * s.m * s.n / 1e6 / dt)
+
+
+def profile_stream(P, torch, s, nb):
+    """Per-kernel averages (us per launch) over nb full batches run eagerly."""
+    P_flags = [pb.flags for pb in s.batches]
+    for pb in s.batches:
+        pb.flags = 0
+    with P.profile() as prof:
+        for i in range(nb):
+            s.run(i)
+        torch.cuda.synchronize()
+    for pb, fl in zip(s.batches, P_flags):
+        pb.flags = fl
+    return {k: (v[0] / v[1] * 1e3 if v[1] else None) for k, v in prof.result.items()}
+
+
+def arrival_pass(torch, s, fps):
+    """Replay the stream with frame f arriving at f / fps seconds: batch b is
+    launched once its last frame has arrived (and after the batches before
+    it, on one stream).  Returns per-frame arrival-to-output latencies (ms)
+    and per-batch launch-to-output times (ms)."""
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    ends = [torch.cuda.Event(enable_timing=True) for _ in s.batches]
+    launch = []
+    e0.record()
+    t0 = time.perf_counter()
+    for b, st in enumerate(s.starts):
+        last = min(st + s.batch, s.nframes) - 1
+        due = t0 + last / fps
+        while True:
+            now = time.perf_counter()
+            if now >= due:
+                break
+            time.sleep(min(0.002, due - now))
+        launch.append(time.perf_counter() - t0)
+        s.run(b)
+        ends[b].record()
+    torch.cuda.synchronize()
+    done = [e0.elapsed_time(e) / 1e3 for e in ends]       # seconds after t0 (device clock)
+    lat = []
+    for b, st in enumerate(s.starts):
+        for f in range(st, min(st + s.batch, s.nframes)):
+            lat.append(1e3 * (done[b] - f / fps))
+    proc = [1e3 * (done[b] - launch[b]) for b in range(len(s.starts))]
+    return np.array(lat), np.array(proc)
+
+
+# ---------------------------------------------------------------- secondary workloads
+
+def bench_single(P, torch, dev, orc, args, blob):
+    """One 480x640 grayscale frame per call, every precision form."""
+    import synth
+    c = synth.config2()
+    m, n, lam = c["m"], c["n"], c["lam"]
+    H1, W1 = c["B1"].shape
+    H2, W2 = c["B2"].shape
+    k1, k2, S = c["K1"].shape[0], c["K2"].shape[0], c["S"]
+    Lo, R1, R2 = orc.deblur(c["B1"], c["B2"], m, n, S, lam)
+    res = {}
+    for name, npd, tdt, prec in (("mixed", np.float32, torch.float32, P.Precision.MIXED),
+                                 ("fp64", np.float64, torch.float64, P.Precision.FP64),
+                                 ("mfma32", np.float32, torch.float32, P.Precision.MFMA32),
+                                 ("bf16", np.float32, torch.float32, P.Precision.BF16),
+                                 ("learned", np.float32, torch.float32, P.Precision.MIXED)):
+        if name == "learned" and blob is None:
+            continue
+        mlp = blob if name == "learned" else None
+        b1 = torch.as_tensor(c["B1"].astype(npd), device=dev)
+        b2 = torch.as_tensor(c["B2"].astype(npd), device=dev)
+        d = P.Deblurrer(max(H1, H2), max(W1, W2), max(k1, k2), precision=prec, device=dev)
+        out = torch.empty((m, n), dtype=tdt, device=dev)
+        K1 = torch.empty((k1, k1), dtype=torch.float64, device=dev)
+        K2 = torch.empty((k2, k2), dtype=torch.float64, device=dev)
+
+        def step():
+            d.deblur(b1, b2, m, n, lam=lam, out=out, K1=K1, K2=K2, mlp=mlp)
+
+        for _ in range(10):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.single_steps):
+            step()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.single_steps
+        with P.profile() as prof:
+            for _ in range(args.single_steps):
+                step()
+            torch.cuda.synchronize()
+        phases = {k: (v[0] / v[1] * 1e3 if v[1] else None) for k, v in prof.result.items()}
+        L = out.double().cpu().numpy()
+        Kg1, Kg2 = K1.cpu().numpy(), K2.cpu().numpy()
+        res[name] = dict(value=m * n / 1e6 / (ms / 1e3), ms_per_step=ms,
+                         kernel_rel_l2_vs_oracle=max(rel(Kg1, R1), rel(Kg2, R2)),
+                         kernel_rel_l2_vs_truth=max(rel(Kg1, c["K1"]), rel(Kg2, c["K2"])),
+                         psnr_vs_oracle_db=psnr(L, Lo), psnr_vs_truth_db=psnr(L, c["L"]), phases_us=phases)
+        log(f"single {name}: {ms:.4f} ms/frame")
+    # per-kernel fractions of the mixed form
+    Py, Px = orc.smooth7(max(H1, H2)), orc.smooth7(max(W1, W2))
+    models = kernel_models(H1, W1, H2, W2, m, n, k1, k2, S, Py, Px, 4, 2, 2)
+    kr = {}
+    for k, v in res["mixed"]["phases_us"].items():
+        if v and k in models:
+            mdl = models[k]
+            if mdl["bound"] == "hbm":
+                kr[k] = dict(bound="hbm", frac=mdl["bytes"] / (v * 1e-6) / 1e9 / HBM_PEAK_GBS)
+            else:
+                kr[k] = dict(bound="alu", frac=mdl["flops"] / (v * 1e-6) / 1e12 / mdl["peak"])
+    return dict(workload="480x640 grayscale frame, coprime 9x9/11x11 kernels, noise 1e-3, lambda 1e-4, S=11, "
+                         "one cbp_deblur call per frame", forms=res, phases_roofline_mixed=kr)
 
 
 def bench_batch(P, torch, dev, orc, args):
@@ -117,8 +348,7 @@ def bench_batch(P, torch, dev, orc, args):
     nf = args.batch_frames
     t0 = time.perf_counter()
     fr = list(synth.config3_frames(nframes=nf))
-    print(f"[bench] batch workload generated ({nf} frames, {time.perf_counter() - t0:.1f} s)", file=sys.stderr,
-          flush=True)
+    log(f"720p batch workload generated ({nf} frames, {time.perf_counter() - t0:.1f} s)")
     frames = [(torch.as_tensor(f["B1"].astype(np.float32), device=dev),
                torch.as_tensor(f["B2"].astype(np.float32), device=dev), f["m"], f["n"]) for f in fr]
     d = P.Deblurrer(734, 1294, 15, 1, nf, P.Precision.MIXED)
@@ -126,107 +356,96 @@ def bench_batch(P, torch, dev, orc, args):
     tune.run()
     torch.cuda.synchronize()
     tuned = P.last_tuning()
-    out = {}
-    for name, flags in (("graph", P.Flags.GRAPH), ("eager", 0)):
-        pb = d.prepare_batch(frames, lam=1e-4, flags=flags)
-        for _ in range(2):
-            pb.run(check=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.batch_steps):
-            pb.run(check=False)
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / args.batch_steps
-        out[name] = dict(ms_per_batch=ms, value=nf * 720 * 1280 / 1e6 / (ms / 1e3))
-        print(f"[bench] batch {name}: {ms:.3f} ms per {nf}-frame batch", file=sys.stderr, flush=True)
-        if name == "graph":
-            keep = pb
+    pb = d.prepare_batch(frames, lam=1e-4, flags=P.Flags.GRAPH)
+    for _ in range(2):
+        pb.run(check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        pb.run(check=False)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.batch_steps
+    log(f"720p batch graph: {ms:.3f} ms per {nf}-frame batch")
     with P.profile() as prof:
         pe = d.prepare_batch(frames, lam=1e-4)
         for _ in range(3):
             pe.run(check=False)
         torch.cuda.synchronize()
     phases = {k: (v[0] / v[1] * 1e3 if v[1] else None) for k, v in prof.result.items()}
-    # accuracy on sampled frames (oracle, outside the timed region)
     errs, ps, pt = [], [], []
     for f in (0, nf // 2, nf - 1):
         h = fr[f]
         B1 = h["B1"].astype(np.float32).astype(np.float64)
         B2 = h["B2"].astype(np.float32).astype(np.float64)
         Lo, R1, R2 = orc.deblur(B1, B2, h["m"], h["n"], 0, 1e-4)
-        K1 = keep.K1s[f].cpu().numpy()
-        K2 = keep.K2s[f].cpu().numpy()
-        L = keep.latents[f].double().cpu().numpy()
-        errs.append(max(float(np.linalg.norm(K1 - R1) / np.linalg.norm(R1)),
-                        float(np.linalg.norm(K2 - R2) / np.linalg.norm(R2))))
+        L = pb.latents[f].double().cpu().numpy()
+        errs.append(max(rel(pb.K1s[f].cpu().numpy(), R1), rel(pb.K2s[f].cpu().numpy(), R2)))
         ps.append(psnr(L, Lo))
         pt.append(psnr(L, h["L"]))
+    byts = sum(4 * (f["B1"].size + f["B2"].size + f["m"] * f["n"]) for f in fr)
     return dict(workload=f"{nf} x 720x1280 moving-blob frames, per-frame coprime kernels 7..15 (uneven), "
-                         "noise 1e-3, lambda 1e-4, FP32 frames (mixed form)",
-                metric="deblurred Mpixel/s", value=out["graph"]["value"], unit="Mpixel/s",
-                ms_per_batch=out["graph"]["ms_per_batch"], eager=out["eager"], tuning=tuned,
-                phases_us_per_batch=phases, sampled_frames=[0, nf // 2, nf - 1],
-                kernel_rel_l2_vs_oracle_max=max(errs), psnr_vs_oracle_db_min=min(ps),
-                psnr_vs_truth_db_min=min(pt))
+                         "noise 1e-3, lambda 1e-4, FP32 frames (mixed form), one call, autotuned, HIP graph",
+                metric="deblurred Mpixel/s", value=nf * 720 * 1280 / 1e6 / (ms / 1e3), unit="Mpixel/s",
+                ms_per_batch=ms, tuning=tuned, phases_us_per_batch=phases,
+                hbm_frac_end_to_end=byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                sampled_frames=[0, nf // 2, nf - 1], kernel_rel_l2_vs_oracle_max=max(errs),
+                psnr_vs_oracle_db_min=min(ps), psnr_vs_truth_db_min=min(pt))
 
 
-def _colour_frame(f):
-    """One frame of the 1080p colour workload as FP32 frames (pool worker)."""
-    import synth
-    h = synth.config5_frame(f)
-    return dict(B1=h["B1"].astype(np.float32), B2=h["B2"].astype(np.float32), K1=h["K1"], K2=h["K2"],
-                L=h["L"].astype(np.float32), m=h["m"], n=h["n"], S=h["S"], lam=h["lam"])
-
-
-def bench_colour(P, torch, dev, orc, args, host, blob):
-    """Colour batching: one batch of 1080x1920 RGB frames (channels share one
-    kernel pair from the channel-summed Grams; per-channel division), one
-    15x15 / 17x17 pair, noise 5e-3, lambda 1e-4, FP32 frames, replayed as one
-    HIP graph; the plain mixed form and the learned form.  Per-batch latency
-    percentiles over repeated calls; accuracy on frame 0 against the truth
-    and the oracle's colour route."""
-    nf = len(host)
-    m, n = host[0]["m"], host[0]["n"]
-    frames = [(torch.as_tensor(h["B1"], device=dev), torch.as_tensor(h["B2"], device=dev), m, n) for h in host]
-    H = max(max(h["B1"].shape[1], h["B2"].shape[1]) for h in host)
-    W = max(max(h["B1"].shape[2], h["B2"].shape[2]) for h in host)
-    d = P.Deblurrer(H, W, H - m + 1, 3, nf, P.Precision.MIXED)
-    h0 = host[0]
-    Lo, R1, R2 = orc.deblur(h0["B1"].astype(np.float64), h0["B2"].astype(np.float64), m, n, 0, h0["lam"])
-    out = {}
-    for form, mlp in (("mixed", None), ("learned", blob)):
-        if form == "learned" and mlp is None:
-            continue
-        pb = d.prepare_batch(frames, lam=h0["lam"], flags=P.Flags.GRAPH, mlp=mlp)
-        for _ in range(2):
-            pb.run(check=False)
+def bench_encoder_multilevel(P, torch, dev, host, args):
+    """The encoder on the GPU (kernel pairs drawn per frame, both streams
+    blurred) and the multi-level workload (Sec. 3): the first stream frame's
+    private stream without b least significant bits, decoded by the path."""
+    h = host[0]
+    m, n = h["m"], h["n"]
+    k1, k2 = h["K1"].shape[0], h["K2"].shape[0]
+    L = torch.as_tensor(h["L"], device=dev)                        # (3, m, n) FP32
+    nf = 8
+    K1s, K2s, att, _ = P.draw_kernel_pairs(1005, 0, nf, k1, k2, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    K1s, K2s, att, _ = P.draw_kernel_pairs(1005, 0, nf, k1, k2, device=dev)
+    torch.cuda.synchronize()
+    draw_ms = 1e3 * (time.perf_counter() - t0)
+    b1 = torch.empty((3, m + k1 - 1, n + k1 - 1), dtype=torch.float32, device=dev)
+    b2 = torch.empty((3, m + k2 - 1, n + k2 - 1), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        P.encode(L, K1s[0], K2s[0], b1, b2)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for f in range(reps):
+        P.encode(L, K1s[f % nf], K2s[f % nf], b1, b2)
+    torch.cuda.synchronize()
+    enc_ms = 1e3 * (time.perf_counter() - t0) / reps
+    log(f"encoder: {draw_ms:.2f} ms for {nf} kernel pairs, {enc_ms:.3f} ms per 1080p RGB frame pair")
+    # multi-level: the stream's blurred pair as 8-bit streams, b low bits of the private one dropped
+    B1 = torch.as_tensor(h["B1"], device=dev)
+    B2 = torch.as_tensor(h["B2"], device=dev)
+    d = P.Deblurrer(B2.shape[1], B2.shape[2], max(k1, k2), 3, 1, P.Precision.MIXED, device=dev)
+    q1 = P.quantize(B1, 0)
+    d1 = P.dequantize(q1)
+    levels = []
+    for b in range(0, 5):
+        q2 = P.quantize(B2, b)
+        d2 = P.dequantize(q2)
+        Lr, R1, R2 = d.deblur(d1, d2, m, n, lam=h["lam"])
         torch.cuda.synchronize()
-        times = []
-        for _ in range(args.colour_steps):
-            t0 = time.perf_counter()
-            pb.run(check=False)
-            torch.cuda.synchronize()
-            times.append(1e3 * (time.perf_counter() - t0))
-        ms = np.array(times)
-        p50 = float(np.percentile(ms, 50))
-        K1 = pb.K1s[0].cpu().numpy()
-        K2 = pb.K2s[0].cpu().numpy()
-        L = pb.latents[0].double().cpu().numpy()
-        kt = max(float(np.linalg.norm(K1 - h0["K1"]) / np.linalg.norm(h0["K1"])),
-                 float(np.linalg.norm(K2 - h0["K2"]) / np.linalg.norm(h0["K2"])))
-        ko = max(float(np.linalg.norm(K1 - R1) / np.linalg.norm(R1)),
-                 float(np.linalg.norm(K2 - R2) / np.linalg.norm(R2)))
-        out[form] = dict(value=nf * m * n / 1e6 / (p50 / 1e3), channel_value=3 * nf * m * n / 1e6 / (p50 / 1e3),
-                         ms_per_batch_p50=p50, ms_per_batch_p99=float(np.percentile(ms, 99)),
-                         kernel_rel_l2_vs_truth=kt, kernel_rel_l2_vs_plain_oracle=ko,
-                         psnr_vs_truth_db_min=min(psnr(L[c], h0["L"][c]) for c in range(3)),
-                         psnr_vs_plain_oracle_db_min=min(psnr(L[c], Lo[c]) for c in range(3)))
-        print(f"[bench] colour {form}: p50 {p50:.3f} ms per {nf}-frame batch", file=sys.stderr, flush=True)
-    return dict(workload=f"{nf} x 1080x1920 RGB frames (moving blobs, channel gains + texture), one coprime "
-                         "15x15/17x17 pair, noise 5e-3, lambda 1e-4, FP32 frames, batch of "
-                         f"{nf} as one HIP graph", metric="deblurred Mpixel/s (RGB pixel counted once)",
-                unit="Mpixel/s", forms=out, steps=args.colour_steps)
+        Lh = Lr.double().cpu().numpy()
+        levels.append(dict(dropped_bits=b,
+                           psnr_vs_truth_db=min(psnr(Lh[c], h["L"][c]) for c in range(3)),
+                           kernel_rel_l2_vs_truth=max(rel(R1.cpu().numpy(), h["K1"]), rel(R2.cpu().numpy(), h["K2"]))))
+        log(f"multi-level: {b} bits dropped -> PSNR {levels[-1]['psnr_vs_truth_db']:.2f} dB")
+    return dict(encoder=dict(workload=f"{nf} kernel pairs {k1}x{k1}/{k2}x{k2} drawn and checked per frame; "
+                                      "1080x1920 RGB latent blurred into both streams (FP32)",
+                             draw_ms_per_batch=draw_ms, attempts=[int(a) for a in att],
+                             blur_ms_per_frame=enc_ms, blur_mpixel_per_s=m * n / 1e3 / enc_ms),
+                multilevel=dict(workload="frame 0 of the stream: public stream at 8 bits, private stream "
+                                         "without b least significant bits, decoded by the mixed form",
+                                levels=levels))
 
+
+# ---------------------------------------------------------------- main
 
 def main():
     args = parse()
@@ -234,205 +453,127 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
+    U = max(1, min(args.unique_frames, args.frames))
 
-    colour_host = None
-    if args.colour_frames > 0:
-        # generated in forked workers before anything touches the GPU
-        import multiprocessing as mp
-        from concurrent.futures import ProcessPoolExecutor
-        t0 = time.perf_counter()
-        with ProcessPoolExecutor(max_workers=min(8, args.colour_frames), mp_context=mp.get_context("fork")) as ex:
-            colour_host = list(ex.map(_colour_frame, range(args.colour_frames)))
-        print(f"[bench] colour workload generated ({args.colour_frames} frames, {time.perf_counter() - t0:.1f} s)",
-              file=sys.stderr, flush=True)
+    # the stream's frames are generated in forked workers before anything touches the GPU
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=max(1, min(args.workers, U)), mp_context=mp.get_context("fork")) as ex:
+        host = list(ex.map(_colour_frame, range(U)))
+    log(f"stream: {U} distinct 1080p RGB frames generated in {time.perf_counter() - t0:.1f} s")
 
     import torch
-    import synth
     import paper_1203_4874_amd as P
+    from oracle import cbp as orc
 
     dev = torch.device("cuda:0")
     P.lib()
-    c = synth.config2()
-    m, n, lam = c["m"], c["n"], c["lam"]
-    H1, W1 = c["B1"].shape
-    H2, W2 = c["B2"].shape
-    k1, k2, S = c["K1"].shape[0], c["K2"].shape[0], c["S"]
-
     blob = P.load_mlp(device=dev) if os.path.exists(P.WEIGHTS) else None
-    forms = {}
-    for name, npd, tdt, prec in (("mixed", np.float32, torch.float32, P.Precision.MIXED),
-                                 ("fp64", np.float64, torch.float64, P.Precision.FP64),
-                                 ("mfma32", np.float32, torch.float32, P.Precision.MFMA32),
-                                 ("bf16", np.float32, torch.float32, P.Precision.BF16),
-                                 ("learned", np.float32, torch.float32, P.Precision.MIXED)):
-        if name == "learned" and blob is None:
-            continue
-        if name != "mixed" and name not in args.forms.split(","):
-            continue
-        B1 = c["B1"].astype(npd)
-        B2 = c["B2"].astype(npd)
-        b1 = torch.as_tensor(B1, device=dev)
-        b2 = torch.as_tensor(B2, device=dev)
-        d = P.Deblurrer(max(H1, H2), max(W1, W2), max(k1, k2), precision=prec, device=dev)
-        out = torch.empty((m, n), dtype=tdt, device=dev)
-        K1 = torch.empty((k1, k1), dtype=torch.float64, device=dev)
-        K2 = torch.empty((k2, k2), dtype=torch.float64, device=dev)
-        forms[name] = dict(B1=B1, B2=B2, b1=b1, b2=b2, d=d, out=out, K1=K1, K2=K2,
-                           mlp=blob if name == "learned" else None)
+    m, n = host[0]["m"], host[0]["n"]
+    H1, W1 = host[0]["B1"].shape[1:]
+    H2, W2 = host[0]["B2"].shape[1:]
+    k1, k2 = host[0]["K1"].shape[0], host[0]["K2"].shape[0]
+    S = host[0]["S"]
+    bytes_frame = 4 * 3 * (H1 * W1 + H2 * W2 + m * n)          # read B1, B2 and write L, FP32, all channels
+    nb = (args.frames + args.batch - 1) // args.batch
 
-    def step(f):
-        f["d"].deblur(f["b1"], f["b2"], m, n, lam=lam, out=f["out"], K1=f["K1"], K2=f["K2"], mlp=f["mlp"])
-
-    results = {}
-    for name, f in forms.items():
-        for _ in range(args.warmup):
-            step(f)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step(f)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        ms = 1e3 * dt / args.steps
-        print(f"[bench] {name}: {args.steps} steps in {dt:.3f} s ({ms:.4f} ms/step)", file=sys.stderr, flush=True)
-        # per-kernel timing pass (HIP events on the call's stream)
-        with P.profile() as prof:
-            for _ in range(args.steps):
-                step(f)
-            torch.cuda.synchronize()
-        phases = {k: (v[0] / v[1] * 1e3 if v[1] else None) for k, v in prof.result.items()}
-        results[name] = dict(ms=ms, phases_us=phases)
-
-    # the headline form replayed as one HIP graph per call (the library captures
-    # the call's launch sequence once and replays it)
-    f = forms["mixed"]
-    for _ in range(args.warmup):
-        f["d"].deblur(f["b1"], f["b2"], m, n, lam=lam, out=f["out"], K1=f["K1"], K2=f["K2"], flags=P.Flags.GRAPH)
-    torch.cuda.synchronize()
+    # ---- headline: the mixed form on the stream
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        f["d"].deblur(f["b1"], f["b2"], m, n, lam=lam, out=f["out"], K1=f["K1"], K2=f["K2"], flags=P.Flags.GRAPH)
-    torch.cuda.synchronize()
-    gms = 1e3 * (time.perf_counter() - t0) / args.steps
-    print(f"[bench] mixed, graph replay: {gms:.4f} ms/step", file=sys.stderr, flush=True)
+    main_s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32, P.Precision.MIXED, P.Flags.GRAPH)
+    log(f"stream in HBM ({args.frames} frames, {time.perf_counter() - t0:.1f} s)")
+    tm = time_stream(torch, main_s, args.warmup, args.steps)
+    log(f"mixed: {args.steps} steps in {tm['seconds']:.4f} s ({tm['ms_per_step']:.3f} ms per {args.batch}-frame step)")
+    phases = profile_stream(P, torch, main_s, min(nb, 8))
+    lat = proc = None
+    if args.fps > 0:
+        lat, proc = arrival_pass(torch, main_s, args.fps)
+        log(f"arrival pass: p50 {np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms")
 
-    # accuracy of each form against the FP64 oracle (outside the timed regions)
-    from oracle import cbp as orc
-    Lo, R1, R2 = orc.deblur(c["B1"], c["B2"], m, n, S, lam)
-    for name, f in forms.items():
-        step(f)
-        torch.cuda.synchronize()
-        L = f["out"].double().cpu().numpy()
-        kr = float(np.linalg.norm(f["K1"].cpu().numpy() - R1) / np.linalg.norm(R1))
-        kr2 = float(np.linalg.norm(f["K2"].cpu().numpy() - R2) / np.linalg.norm(R2))
-        kt = float(np.linalg.norm(f["K1"].cpu().numpy() - c["K1"]) / np.linalg.norm(c["K1"]))
-        kt2 = float(np.linalg.norm(f["K2"].cpu().numpy() - c["K2"]) / np.linalg.norm(c["K2"]))
-        results[name].update(psnr_vs_oracle=psnr(L, Lo), psnr_vs_truth=psnr(L, c["L"]),
-                             kernel_rel_l2_vs_oracle=max(kr, kr2), kernel_rel_l2_vs_truth=max(kt, kt2))
+    # sampled frames of the stream against the oracle (outside the timed regions)
+    samples = sorted(set(int(round(x)) for x in np.linspace(0, args.frames - 1, max(1, args.cpu_frames))))
+    orc_res = {}
+    t0 = time.perf_counter()
+    for f in samples:
+        h = host[f % U]
+        orc_res[f] = orc.deblur(h["B1"].astype(np.float64), h["B2"].astype(np.float64), m, n, 0, h["lam"])
+    cpu_el = time.perf_counter() - t0
+    threads = blas_threads()
+    single = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+        h = host[samples[0] % U]
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            orc.deblur(h["B1"].astype(np.float64), h["B2"].astype(np.float64), m, n, 0, h["lam"])
+            single = time.perf_counter() - t0
+    log(f"oracle: {len(samples)} frames in {cpu_el:.1f} s")
 
-    mpix = m * n / 1e6
-    main_form = results["mixed"]
-    value = mpix / (main_form["ms"] / 1e3)
+    def accuracy(s):
+        ek, ps, pt, kt = [], [], [], []
+        for f in samples:
+            Lo, R1, R2 = orc_res[f]
+            h = host[f % U]
+            K1, K2 = s.kernels(f)
+            L = s.out[f].double().cpu().numpy()
+            ek.append(max(rel(K1, R1), rel(K2, R2)))
+            kt.append(max(rel(K1, h["K1"]), rel(K2, h["K2"])))
+            ps.append(min(psnr(L[c], Lo[c]) for c in range(3)))
+            pt.append(min(psnr(L[c], h["L"][c]) for c in range(3)))
+        return dict(sampled_frames=samples, kernel_rel_l2_vs_oracle_max=max(ek), psnr_vs_oracle_db_min=min(ps),
+                    kernel_rel_l2_vs_truth_max=max(kt), psnr_vs_truth_db_min=min(pt))
 
-    # roofline of the dominant kernel of the headline form
-    ph = {k: v for k, v in main_form["phases_us"].items() if v}
+    acc_main = accuracy(main_s)
+
+    # roofline: algorithmic bytes of one launch (the frames of one batch) over
+    # the dominant kernel's average launch time, and over the whole step
+    ph = {k: v for k, v in phases.items() if v}
     dom = max(ph, key=ph.get)
-    Py, Px = orc.smooth7(max(H1, H2)), orc.smooth7(max(W1, W2))
-    # refinement step counts of the solves (diag run, outside the timed regions)
-    f = forms["mixed"]
-    dd = P.Deblurrer(max(H1, H2), max(W1, W2), max(k1, k2), precision=P.Precision.MIXED, device=dev, diag=True)
-    dd.deblur(f["b1"], f["b2"], m, n, lam=lam, out=f["out"], K1=f["K1"], K2=f["K2"])
-    dg = dd.read_diag()
-    models = kernel_models(H1, W1, H2, W2, m, n, k1, k2, S, Py, Px, 4,
-                           dg["refine_sample"], dg["refine_scale"])
-    roof = None
-    if dom in models:
-        mdl = models[dom]
-        t = ph[dom] * 1e-6
-        if mdl["bound"] == "hbm":
-            ach = mdl["bytes"] / t / 1e9
-            roof = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=ach / HBM_PEAK_GBS, algorithmic_bytes=mdl["bytes"])
-        else:
-            ach = mdl["flops"] / t / 1e12
-            roof = dict(kernel=dom, bound="alu", achieved=ach, peak=mdl["peak"], unit="TFLOP/s",
-                        frac=ach / mdl["peak"], algorithmic_flops=mdl["flops"])
-        roof["avg_us"] = ph[dom]
-        if dom == "scale_assemble":
-            roof["launch"] = "one 64-lane workgroup per frame (a single solve of order 2S)"
-        elif dom == "sample_eig":
-            roof["launch"] = f"{2 * S} workgroups of 64 lanes (one solve of order k1+k2 each)"
-        roof["traffic"] = None
-        tf = os.path.join(ROOT, "profiles", "traffic.json")
-        if os.path.exists(tf):
-            with open(tf) as fh:
-                tr = json.load(fh)
-            ent = tr.get(dom)
-            if ent and ent.get("source_hash") == source_hash(ent.get("sources", [])):
-                roof["traffic"] = ent.get("bytes_per_launch")
-    else:
-        roof = dict(kernel=dom, bound="alu", achieved=None, peak=None, unit=None, frac=None, traffic=None,
-                    avg_us=ph[dom])
+    per_launch = bytes_frame * args.batch
+    ach = per_launch / (ph[dom] * 1e-6) / 1e9
+    roof = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                traffic=traffic_for(dom, "stream_1080p_rgb_batch8"), avg_us=ph[dom],
+                algorithmic_bytes_per_launch=per_launch,
+                launch=f"one launch per phase over the {args.batch} frames of a batch (3 channels each)",
+                end_to_end=dict(achieved=per_launch / (tm["ms_per_step"] * 1e-3) / 1e9,
+                                frac=per_launch / (tm["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                note="the same bytes over the whole step (every kernel of the path)"))
 
-    # every kernel's fraction of its own bound, for the stage split
-    kern_roof = {}
-    for k, v in ph.items():
-        if k in models:
-            mdl = models[k]
-            if mdl["bound"] == "hbm":
-                kern_roof[k] = dict(bound="hbm", GBs=mdl["bytes"] / (v * 1e-6) / 1e9,
-                                    frac=mdl["bytes"] / (v * 1e-6) / 1e9 / HBM_PEAK_GBS)
-            else:
-                kern_roof[k] = dict(bound="alu", TFLOPs=mdl["flops"] / (v * 1e-6) / 1e12,
-                                    frac=mdl["flops"] / (v * 1e-6) / 1e12 / mdl["peak"])
+    # ---- the other forms on the stream
+    extra = {}
+    forms = [f for f in args.forms.split(",") if f]
+    del main_s
+    torch.cuda.empty_cache()
+    for name in forms:
+        if name.startswith("learned") and blob is None:
+            continue
+        if name == "fp64":
+            s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float64, P.Precision.FP64, P.Flags.GRAPH)
+        elif name == "learned_bf16":
+            s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32, P.Precision.BF16, P.Flags.GRAPH,
+                       mlp=blob)
+        elif name == "learned":
+            s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32, P.Precision.MIXED, P.Flags.GRAPH,
+                       mlp=blob)
+        else:
+            continue
+        t = time_stream(torch, s, args.warmup, args.steps)
+        log(f"{name}: {t['ms_per_step']:.3f} ms per step")
+        extra[name] = dict(value=t["value"], ms_per_step=t["ms_per_step"], **accuracy(s))
+        del s
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-        except Exception:
-            threads = os.cpu_count() or 1
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            orc.deblur(c["B1"], c["B2"], m, n, S, lam)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el >= args.cpu_seconds:
-                break
-        cpu = dict(value=reps * mpix / el, unit="Mpixel/s", cores=int(threads), kind="oracle",
-                   sample=f"{reps} repetitions of the same 480x640 frame (FP64 NumPy/SciPy oracle, {el:.1f} s)")
+        cpu = dict(value=len(samples) * m * n / 1e6 / cpu_el, unit="Mpixel/s", cores=int(threads), kind="oracle",
+                   sample=f"frames {samples} of the stream (1080x1920 RGB), FP64 NumPy/SciPy oracle, "
+                          f"{cpu_el:.1f} s",
+                   single_thread=dict(value=m * n / 1e6 / single, seconds_per_frame=single),
+                   host_cpu=cpu_model(), host_logical_cpus=os.cpu_count())
 
-    # PCIe-inclusive rate of the headline form: frames from pinned host
-    # memory, the latent back to pinned host memory, in every step
-    f = forms["mixed"]
-    h1 = torch.from_numpy(np.ascontiguousarray(f["B1"])).pin_memory()
-    h2 = torch.from_numpy(np.ascontiguousarray(f["B2"])).pin_memory()
-    hL = torch.empty((m, n), dtype=torch.float32).pin_memory()
-
-    def pstep():
-        f["b1"].copy_(h1, non_blocking=True)
-        f["b2"].copy_(h2, non_blocking=True)
-        step(f)
-        hL.copy_(f["out"], non_blocking=True)
-
-    for _ in range(args.warmup):
-        pstep()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pstep()
-    torch.cuda.synchronize()
-    pms = 1e3 * (time.perf_counter() - t0) / args.steps
-    pcie = dict(value=mpix / (pms / 1e3), unit="Mpixel/s", ms_per_step=pms,
-                note="frames H2D from pinned host memory and the latent D2H, inside every step")
-
-    batched = None
-    if args.batch_frames > 0:
-        batched = bench_batch(P, torch, dev, orc, args)
-    colour = None
-    if colour_host:
-        colour = bench_colour(P, torch, dev, orc, args, colour_host, blob)
+    enc_ml = bench_encoder_multilevel(P, torch, dev, host, args)
+    single_res = bench_single(P, torch, dev, orc, args, blob) if args.single_steps > 0 else None
+    batched = bench_batch(P, torch, dev, orc, args) if args.batch_frames > 0 else None
 
     if args.copy_calibration:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
@@ -443,48 +584,43 @@ def main():
 
     line = {
         "metric": "deblurred Mpixel/s (kernel recovery + deconv), mixed form, PSNR vs FP64 oracle reported",
-        "value": value,
+        "value": tm["value"],
         "unit": "Mpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": main_form["ms"],
+        "ms_per_step": tm["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (frames, FFT, division) + f64 (evaluation, Gram, eigen-solves, scale fix)",
         "data": "synthetic",
-        "config": {"workload": "480x640 grayscale frame, coprime 9x9/11x11 kernels, noise 1e-3, lambda 1e-4, S=11",
-                   "frames_per_step": 1, "blurred": [[H1, W1], [H2, W2]], "fft_grid": [Py, Px]},
+        "config": {"workload": f"stream of {args.frames} x 1080x1920 RGB frames (moving blobs, channel gains + "
+                               f"texture) cycled from {U} generated frames, one coprime 15x15/17x17 pair, "
+                               "noise 5e-3, lambda 1e-4, S=17, HIP-graph batches of "
+                               f"{args.batch} frames, inputs resident in HBM",
+                   "frames": args.frames, "unique_frames": U, "frames_per_step": args.batch,
+                   "pixels_per_frame": m * n, "channels": 3, "blurred": [[H1, W1], [H2, W2]],
+                   "kernels": [k1, k2], "samples": S,
+                   "fft_grid": [orc.smooth7(max(H1, H2)), orc.smooth7(max(W1, W2))]},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "psnr_vs_oracle_db": main_form["psnr_vs_oracle"],
-        "psnr_vs_truth_db": main_form["psnr_vs_truth"],
-        "kernel_rel_l2_vs_oracle": main_form["kernel_rel_l2_vs_oracle"],
-        "phases_us": main_form["phases_us"],
-        "phases_roofline": kern_roof,
-        "plain_fp64": None if "fp64" not in results else {
-            "value": mpix / (results["fp64"]["ms"] / 1e3), "ms_per_step": results["fp64"]["ms"],
-            "psnr_vs_oracle_db": results["fp64"]["psnr_vs_oracle"],
-            "kernel_rel_l2_vs_oracle": results["fp64"]["kernel_rel_l2_vs_oracle"],
-            "phases_us": results["fp64"]["phases_us"]},
-        "precision_forms": {k: {"value": mpix / (results[k]["ms"] / 1e3), "ms_per_step": results[k]["ms"],
-                                "psnr_vs_oracle_db": results[k]["psnr_vs_oracle"],
-                                "kernel_rel_l2_vs_oracle": results[k]["kernel_rel_l2_vs_oracle"],
-                                "phases_us": results[k]["phases_us"]}
-                            for k in ("mfma32", "bf16") if k in results},
-        "learned": None if "learned" not in results else {
-            "value": mpix / (results["learned"]["ms"] / 1e3), "ms_per_step": results["learned"]["ms"],
-            "kernel_rel_l2_vs_truth": results["learned"]["kernel_rel_l2_vs_truth"],
-            "plain_kernel_rel_l2_vs_truth": results["mixed"]["kernel_rel_l2_vs_truth"],
-            "psnr_vs_truth_db": results["learned"]["psnr_vs_truth"],
-            "plain_psnr_vs_truth_db": results["mixed"]["psnr_vs_truth"],
-            "phases_us": results["learned"]["phases_us"]},
-        "graph_replay": {"value": mpix / (gms / 1e3), "ms_per_step": gms,
-                         "note": "the headline form with the call captured once and replayed as a HIP graph"},
-        "pcie_inclusive": pcie,
+        "channel_mpixel_per_s": 3 * tm["value"],
+        "accuracy": acc_main,
+        "latency_ms": None if lat is None else {
+            "arrival_fps": args.fps,
+            "frame_p50": float(np.percentile(lat, 50)), "frame_p99": float(np.percentile(lat, 99)),
+            "batch_p50": float(np.percentile(proc, 50)), "batch_p99": float(np.percentile(proc, 99)),
+            "note": "frame: arrival to output, including the wait for its batch to fill; "
+                    "batch: launch to output"},
+        "phases_us_per_launch": phases,
+        "plain_fp64": extra.get("fp64"),
+        "learned_bf16": extra.get("learned_bf16"),
+        "learned": extra.get("learned"),
+        "encoder": enc_ml["encoder"],
+        "multilevel": enc_ml["multilevel"],
+        "single_frame_480x640": single_res,
         "batched_720p": batched,
-        "colour_1080p": colour,
     }
     print(json.dumps(line))
 
