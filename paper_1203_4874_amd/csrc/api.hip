@@ -57,7 +57,7 @@ int smooth7(int n) {
 // for any frame within (maxH, maxW, maxk, S, nch) fits the size that
 // cbp_workspace_size() reports for those bounds.
 struct region_sizes {
-  size_t fpart, ex, ey, corr, xvec, pq, kern, t, u, feat, wts, kalt, twxd, twx, twy;
+  size_t fpart, ex, ey, corr, xvec, pq, kern, t, u, feat, wts, kalt, twxd;
 };
 
 region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
@@ -78,8 +78,6 @@ region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
   r.wts = (2 * (size_t)S + 1) * sizeof(double);
   r.kalt = 2 * (size_t)CBP_MAX_K * CBP_MAX_K * sizeof(double);
   r.twxd = (size_t)Px * sizeof(c64);
-  r.twx = (size_t)Px * 2 * esize;
-  r.twy = (size_t)smooth7(Hmax) * 2 * esize;
   return r;
 }
 
@@ -100,8 +98,6 @@ size_t layout(frame_plan* fp, const region_sizes& r) {
   fp->off_wts = take(r.wts);
   fp->off_kalt = take(r.kalt);
   fp->off_twxd = take(r.twxd);
-  fp->off_twx = take(r.twx);
-  fp->off_twy = take(r.twy);
   fp->total = o;
   return o;
 }
@@ -270,8 +266,6 @@ frame_desc make_desc(const frame_plan& fp, const cbp_image* b1, const cbp_image*
   d.wts = learned ? (double*)(ws + fp.off_wts) : nullptr;
   d.Kalt = (double*)(ws + fp.off_kalt);
   d.twxd = (c64*)(ws + fp.off_twxd);
-  d.twx = ws + fp.off_twx;
-  d.twy = ws + fp.off_twy;
   d.variant = variant;
   return d;
 }

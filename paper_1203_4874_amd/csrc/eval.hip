@@ -45,12 +45,6 @@ __device__ inline void twiddle_item(const frame_desc& d, int item) {
       double s, c;
       sincospi(-2.0 * (double)t / (double)d.Px, &s, &c);
       d.twxd[t] = {c, s};
-      ((cplx<T>*)d.twx)[t] = {T(c), T(s)};
-    } else if (t < d.Px + d.Py) {
-      const int v = t - d.Px;
-      double s, c;
-      sincospi(-2.0 * (double)v / (double)d.Py, &s, &c);
-      ((cplx<T>*)d.twy)[v] = {T(c), T(s)};
     }
   }
 }

@@ -25,10 +25,26 @@ namespace cbp {
 
 namespace {
 
+// The split twiddle tables of an N-point transform (fft_core.h tw_split) into
+// LDS: lo[i] = w_N^i, i < 64, and hi[j] = w_N^{64 j}, j < ceil(N / 64), each an
+// FP64 sincospi rounded once to T.  The passes read them from LDS instead of
+// a table in global memory.
+template <typename T>
+__device__ inline tw_split<T> split_twiddles(cplx<T>* lo, cplx<T>* hi, int N) {
+  const int nhi = (N + 63) >> 6;
+  for (int t = threadIdx.x; t < 64 + nhi; t += blockDim.x) {
+    const int e = t < 64 ? t : 64 * (t - 64);
+    double sn, cs;
+    sincospi(-2.0 * (double)e / (double)N, &sn, &cs);
+    (t < 64 ? lo[t] : hi[t - 64]) = {T(cs), T(sn)};
+  }
+  return tw_split<T>{lo, hi};
+}
+
 // Run all passes of plan p on nbatch transforms (stride bstride) held in a;
 // b is the ping-pong partner.  Returns the buffer holding the result.
-template <int DIR, typename T>
-__device__ __attribute__((always_inline)) inline cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, const fft_plan& p, const cplx<T>* tw, int nbatch,
+template <int DIR, typename T, typename Tab>
+__device__ __attribute__((always_inline)) inline cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, const fft_plan& p, const Tab& tw, int nbatch,
                                    int bstride) {
   cplx<T>* src = a;
   cplx<T>* dst = b;
@@ -55,6 +71,7 @@ template <typename T>
 // (its scratch carved from the dynamic LDS).
 __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int gr) {
   extern __shared__ __attribute__((aligned(16))) char sm_rf[];
+  __shared__ cplx<T> twl[64], twh[CBP_MAX_FFT_F32 / 64];
   __shared__ double gy[2][CBP_MAX_S];
   __shared__ double fpart_l[2][64];
   __shared__ c64 twS[CBP_MAX_S];
@@ -72,7 +89,7 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int 
     const int N = px.N, hx = d.hx;
     cplx<T>* a = (cplx<T>*)sm_rf;
     cplx<T>* b = a + N;
-    const cplx<T>* tw = (const cplx<T>*)d.twx;   // global table (L1 / L2 resident)
+    const tw_split<T> tw = split_twiddles(twl, twh, N);
     const int y = item % d.Hmax, ch = item / d.Hmax;
     // row pointers clamped to each frame's last row (rows past it read as zero)
     const T* r1 = (const T*)d.b1 + ch * d.cs1 + (int64_t)min(y, d.H1 - 1) * d.p1;
@@ -157,6 +174,7 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int 
 template <typename T>
 __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_cf[];
+  __shared__ cplx<T> twl[64], twh[CBP_MAX_FFT_F32 / 64];
   for_items<Q_COL>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const fft_plan& py = d.fy;
     const int N = py.N, cw = d.cw, hx = d.hx, m = d.m;
@@ -169,7 +187,7 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
     const int nf = 2 * cw;                      // transforms in flight: (column, frame)
     cplx<T>* a = (cplx<T>*)sm_cf;               // [nf][N]
     cplx<T>* b = a + (size_t)nf * N;            // [nf][N]
-    const cplx<T>* tw = (const cplx<T>*)d.twy;  // global table (L1 / L2 resident)
+    const tw_split<T> tw = split_twiddles(twl, twh, N);
     cplx<T>* kr = b + (size_t)nf * N;           // [cw][2][CBP_MAX_K] row DFTs of the kernels at kx
     const int nstrip = (hx + cw - 1) / cw;
     const int kx0 = (item % nstrip) * cw, ch = item / nstrip;
@@ -280,13 +298,14 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_ri[];
+  __shared__ cplx<T> twl[64], twh[CBP_MAX_FFT_F32 / 64];
   for_items<Q_ROW_INV>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const fft_plan& px = d.fx;
     const int N = px.N, hx = d.hx, m = d.m, n = d.n;
     const T scale = (T)(1.0 / ((double)d.Py * (double)d.Px));
     cplx<T>* a = (cplx<T>*)sm_ri;
     cplx<T>* b = a + N;
-    const cplx<T>* tw = (const cplx<T>*)d.twx;   // global table (L1 / L2 resident)
+    const tw_split<T> tw = split_twiddles(twl, twh, N);
     const int npair = (m + 1) / 2;
     const int ya = 2 * (item % npair), yb = ya + 1, ch = item / npair;
     const cplx<T>* ua = (const cplx<T>*)d.u + (int64_t)ch * m * hx + (int64_t)ya * hx;

@@ -10,8 +10,9 @@
 // Frameworks for the Fast Fourier Transform", SIAM 1992).
 //
 // DIR = -1 computes X[m] = sum_t x[t] exp(-2 pi i m t / N) (forward),
-// DIR = +1 the same with +i (unnormalised inverse).  Twiddles come from a
-// table tw[t] = exp(-2 pi i t / N), t in [0, N).
+// DIR = +1 the same with +i (unnormalised inverse).  Twiddles tw[t] =
+// exp(-2 pi i t / N), t in [0, N), come from any table type with
+// operator[]: a full table, or tw_split's two short tables.
 //
 // Everything here is host+device so the same butterfly code can be checked
 // on the CPU.
@@ -129,11 +130,22 @@ CBP_HD int mul24(int a, int b) {
 #endif
 }
 
+// w_N^t = lo[t mod 64] hi[t div 64] with lo[i] = w_N^i (i < 64) and
+// hi[j] = w_N^{64 j} (j < ceil(N / 64)): two short tables (96 entries for
+// N <= 2048) instead of N entries, one complex product per twiddle (within a
+// few units in the last place of the directly rounded value).
+template <typename T>
+struct tw_split {
+  const cplx<T>* lo;
+  const cplx<T>* hi;
+  CBP_HD cplx<T> operator[](int t) const { return lo[t & 63] * hi[t >> 6]; }
+};
+
 // Butterfly j of a pass with k = j mod Ns given: reads src[j + r N/R],
 // twiddles the inputs by w^(r k N/(Ns R)) (TW: Ns > 1), writes
 // dst[(j - k) R + k + r Ns].
-template <int R, int DIR, bool TW, typename T>
-CBP_HD void stockham_bfly(const cplx<T>* src, cplx<T>* dst, int NR, int Ns, int twstep, const cplx<T>* tw, int j,
+template <int R, int DIR, bool TW, typename T, typename Tab>
+CBP_HD void stockham_bfly(const cplx<T>* src, cplx<T>* dst, int NR, int Ns, int twstep, const Tab& tw, int j,
                           int k) {
   cplx<T> v[R];
   const cplx<T>* s = src + j;
@@ -201,8 +213,8 @@ inline bool make_fft_plan(int N, fft_plan* p, int order = 0) {
 // One pass of radix R over `nbatch` transforms stored at src + f*bstride
 // (f < nbatch), butterflies distributed over threads tid, tid+nthr, ...  The
 // caller synchronises between passes.
-template <int R, int DIR, bool TW, typename T>
-CBP_HD void fft_pass_rt(const cplx<T>* src, cplx<T>* dst, int N, int Ns, const cplx<T>* tw, int nbatch, int bstride,
+template <int R, int DIR, bool TW, typename T, typename Tab>
+CBP_HD void fft_pass_rt(const cplx<T>* src, cplx<T>* dst, int N, int Ns, const Tab& tw, int nbatch, int bstride,
                         int tid, int nthr) {
   const int nb = N / R;
   const int total = nb * nbatch;
@@ -221,15 +233,15 @@ CBP_HD void fft_pass_rt(const cplx<T>* src, cplx<T>* dst, int N, int Ns, const c
 // (f < nbatch), butterflies distributed over threads tid, tid+nthr, ...  The
 // caller synchronises between passes.  The first pass (Ns = 1) has no
 // twiddles.
-template <int R, int DIR, typename T>
-CBP_HD void fft_pass_r(const cplx<T>* src, cplx<T>* dst, int N, int Ns, const cplx<T>* tw, int nbatch, int bstride,
+template <int R, int DIR, typename T, typename Tab>
+CBP_HD void fft_pass_r(const cplx<T>* src, cplx<T>* dst, int N, int Ns, const Tab& tw, int nbatch, int bstride,
                        int tid, int nthr) {
   if (Ns == 1) fft_pass_rt<R, DIR, false>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr);
   else fft_pass_rt<R, DIR, true>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr);
 }
 
-template <int DIR, typename T>
-CBP_HD void fft_pass(const cplx<T>* src, cplx<T>* dst, int N, int R, int Ns, const cplx<T>* tw,
+template <int DIR, typename T, typename Tab>
+CBP_HD void fft_pass(const cplx<T>* src, cplx<T>* dst, int N, int R, int Ns, const Tab& tw,
                      int nbatch, int bstride, int tid, int nthr) {
   switch (R) {
     case 2: fft_pass_r<2, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;

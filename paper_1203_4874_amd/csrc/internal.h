@@ -40,7 +40,7 @@ struct frame_plan {
   int cw;                  // columns per workgroup in the column pass
   fft_plan fy, fx;
   size_t off_fpart, off_ex, off_ey, off_corr, off_xvec, off_pq, off_kern,
-      off_t1, off_t2, off_u, off_feat, off_wts, off_kalt, off_twxd, off_twx, off_twy, total;
+      off_t1, off_t2, off_u, off_feat, off_wts, off_kalt, off_twxd, total;
 };
 
 // Everything a kernel needs about one frame (device pointers).
@@ -77,11 +77,9 @@ struct frame_desc {
   float* feat;
   double* wts;
   double* Kalt;   // the plain method's kernels (fallback of the learned form), 2 x CBP_MAX_K^2
-  // twiddle tables of the FFT grid, exp(-2 pi i t / P): FP64 over x (the
-  // kernels' row DFTs) and in the transform type over x and y
+  // twiddle table exp(-2 pi i t / Px), FP64 (the kernels' row DFTs in the
+  // column pass; the FFT passes build short tables of their own in LDS)
   c64* twxd;
-  void* twx;
-  void* twy;
   // paper-faithful variants (CBP_FLAG_DIVIDE_B1 / SCALE_K1 / ONE_AXIS as
   // VAR_* bits); 0 = the default method
   int variant;
@@ -104,7 +102,7 @@ inline int queue_items(int q, const frame_plan& p) {
     case Q_FINALIZE: return 1;
     case Q_COL: return ((p.hx + p.cw - 1) / p.cw) * p.nch;
     case Q_ROW_INV: return ((p.m + 1) / 2) * p.nch;
-    case Q_TWID: return (p.Px + p.Py + 255) / 256;
+    case Q_TWID: return (p.Px + 255) / 256;
     case Q_SIZE_PROBE: return 0;   // set by the size-estimation entry point (candidates x 2S)
   }
   return 0;
