@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--workers", type=int, default=16, help="host processes generating the stream's frames")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes for the stream")
+    ap.add_argument("--lanes", type=int, default=1,
+                    help="streams the stream's batches alternate on (each with its own workspace)")
     ap.add_argument("--only-timing", action="store_true",
                     help="stop after the timed steps (kernel-trace runs: the last W + K dispatches of each kernel "
                          "are the timed graph replays)")
@@ -178,7 +180,8 @@ class Stream:
     """The stream's frames in HBM (one buffer pair and one latent per frame)
     and its batches, prepared once (argument marshalling, graph capture)."""
 
-    def __init__(self, P, torch, dev, host, nframes, batch, dtype, precision, flags, mlp=None, autotune=True):
+    def __init__(self, P, torch, dev, host, nframes, batch, dtype, precision, flags, mlp=None, autotune=True,
+                 lanes=1):
         self.P, self.torch = P, torch
         self.nframes, self.batch = nframes, batch
         U = len(host)
@@ -192,14 +195,20 @@ class Stream:
         self.out = [torch.empty((3, m, n), dtype=dtype, device=dev) for _ in range(nframes)]
         H = max(max(h["B1"].shape[1], h["B2"].shape[1]) for h in host)
         W = max(max(h["B1"].shape[2], h["B2"].shape[2]) for h in host)
-        self.d = P.Deblurrer(H, W, H - m + 1, 3, batch, precision, device=dev)
+        # `lanes` streams, each with its own workspace: batch i runs on lane
+        # i mod lanes, so one batch's kernel recovery (a few one-wave solves)
+        # can share the chip with the previous batch's streaming passes
+        self.lanes = [torch.cuda.current_stream()] + [torch.cuda.Stream(device=dev) for _ in range(lanes - 1)]
+        self.ds = [P.Deblurrer(H, W, H - m + 1, 3, batch, precision, device=dev) for _ in range(lanes)]
+        self.d = self.ds[0]
         self.starts = list(range(0, nframes, batch))
         self.batches = []
-        for s in self.starts:
+        for i, s in enumerate(self.starts):
             fr = range(s, min(s + batch, nframes))
             pairs = [(self.b1[f], self.b2[f], m, n) for f in fr]
-            self.batches.append(self.d.prepare_batch(pairs, lam=host[0]["lam"], outs=[self.out[f] for f in fr],
-                                                     flags=flags, mlp=mlp))
+            self.batches.append(self.ds[i % lanes].prepare_batch(pairs, lam=host[0]["lam"],
+                                                                 outs=[self.out[f] for f in fr], flags=flags,
+                                                                 mlp=mlp))
         if autotune:
             # the launch shapes of each batch class (full batches, the shorter
             # last one) searched once; later calls of the class use them
@@ -216,7 +225,13 @@ class Stream:
         return min(self.starts[b] + self.batch, self.nframes) - self.starts[b]
 
     def run(self, i):
-        self.batches[i % len(self.batches)].run(check=False)
+        # the inputs are resident before any batch runs; a lane's batches reuse its
+        # workspace in stream order
+        b = i % len(self.batches)
+        self.batches[b].run(stream=self.lane_of(b), check=False)
+
+    def lane_of(self, b):
+        return self.lanes[b % len(self.lanes)]
 
     def kernels(self, f):
         pb = self.batches[f // self.batch]
@@ -276,7 +291,7 @@ def arrival_pass(torch, s, fps):
             time.sleep(min(0.002, due - now))
         launch.append(time.perf_counter() - t0)
         s.run(b)
-        ends[b].record()
+        ends[b].record(s.lane_of(b))
     torch.cuda.synchronize()
     done = [e0.elapsed_time(e) / 1e3 for e in ends]       # seconds after t0 (device clock)
     lat = []
@@ -497,7 +512,7 @@ def main():
     # ---- headline: the mixed form on the stream
     t0 = time.perf_counter()
     main_s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32, P.Precision.MIXED, P.Flags.GRAPH,
-                    autotune=not args.no_autotune)
+                    autotune=not args.no_autotune, lanes=args.lanes)
     log(f"stream in HBM ({args.frames} frames, {time.perf_counter() - t0:.1f} s)")
     tm = time_stream(torch, main_s, args.warmup, args.steps)
     log(f"mixed: {args.steps} steps in {tm['seconds']:.4f} s ({tm['ms_per_step']:.3f} ms per {args.batch}-frame step)")
