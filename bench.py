@@ -60,8 +60,11 @@ def parse():
     ap.add_argument("--fps", type=float, default=30.0, help="arrival rate of the real-time pass (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=4, help="stream frames the oracle runs on")
-    ap.add_argument("--forms", default="fp64,learned_bf16",
-                    help="comma-separated extra forms on the stream (fp64, learned_bf16, learned)")
+    ap.add_argument("--precision", default="mfma64", choices=["mixed", "mfma64"],
+                    help="Gram form of the headline: double-double on the vector units or FP64 matrix cores")
+    ap.add_argument("--forms", default="fp64,mixed,learned_mfma64",
+                    help="comma-separated extra forms on the stream (fp64, mixed, mfma64, learned, learned_mfma64, "
+                         "learned_bf16)")
     ap.add_argument("--single-steps", type=int, default=100,
                     help="steps of the 480x640 single-frame workload (0 = skip)")
     ap.add_argument("--batch-frames", type=int, default=64,
@@ -316,6 +319,7 @@ def bench_single(P, torch, dev, orc, args, blob):
     res = {}
     for name, npd, tdt, prec in (("mixed", np.float32, torch.float32, P.Precision.MIXED),
                                  ("fp64", np.float64, torch.float64, P.Precision.FP64),
+                                 ("mfma64", np.float32, torch.float32, P.Precision.MFMA64),
                                  ("mfma32", np.float32, torch.float32, P.Precision.MFMA32),
                                  ("bf16", np.float32, torch.float32, P.Precision.BF16),
                                  ("learned", np.float32, torch.float32, P.Precision.MIXED)):
@@ -369,7 +373,7 @@ def bench_single(P, torch, dev, orc, args, blob):
 
 def bench_batch(P, torch, dev, orc, args):
     """The batching form: N moving-blob 720x1280 frames with per-frame uneven
-    kernels 7..15, noise 1e-3, lambda 1e-4, FP32 frames (mixed form), all
+    kernels 7..15, noise 1e-3, lambda 1e-4, FP32 frames (the headline's form), all
     frames in one work-list launch per phase, launch shapes from the
     autotuner, replayed as one HIP graph per call."""
     import synth
@@ -379,7 +383,8 @@ def bench_batch(P, torch, dev, orc, args):
     log(f"720p batch workload generated ({nf} frames, {time.perf_counter() - t0:.1f} s)")
     frames = [(torch.as_tensor(f["B1"].astype(np.float32), device=dev),
                torch.as_tensor(f["B2"].astype(np.float32), device=dev), f["m"], f["n"]) for f in fr]
-    d = P.Deblurrer(734, 1294, 15, 1, nf, P.Precision.MIXED)
+    prec = P.Precision.MFMA64 if args.precision == "mfma64" else P.Precision.MIXED
+    d = P.Deblurrer(734, 1294, 15, 1, nf, prec)
     tune = d.prepare_batch(frames, lam=1e-4, flags=P.Flags.AUTOTUNE)
     tune.run()
     torch.cuda.synchronize()
@@ -412,7 +417,8 @@ def bench_batch(P, torch, dev, orc, args):
         pt.append(psnr(L, h["L"]))
     byts = sum(4 * (f["B1"].size + f["B2"].size + f["m"] * f["n"]) for f in fr)
     return dict(workload=f"{nf} x 720x1280 moving-blob frames, per-frame coprime kernels 7..15 (uneven), "
-                         "noise 1e-3, lambda 1e-4, FP32 frames (mixed form), one call, autotuned, HIP graph",
+                         f"noise 1e-3, lambda 1e-4, FP32 frames ({args.precision} form), one call, autotuned, "
+                         "HIP graph",
                 metric="deblurred Mpixel/s", value=nf * 720 * 1280 / 1e6 / (ms / 1e3), unit="Mpixel/s",
                 ms_per_batch=ms, tuning=tuned, phases_us_per_batch=phases,
                 hbm_frac_end_to_end=byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -511,11 +517,13 @@ def main():
 
     # ---- headline: the mixed form on the stream
     t0 = time.perf_counter()
-    main_s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32, P.Precision.MIXED, P.Flags.GRAPH,
+    head_prec = P.Precision.MFMA64 if args.precision == "mfma64" else P.Precision.MIXED
+    main_s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32, head_prec, P.Flags.GRAPH,
                     autotune=not args.no_autotune, lanes=args.lanes)
     log(f"stream in HBM ({args.frames} frames, {time.perf_counter() - t0:.1f} s)")
     tm = time_stream(torch, main_s, args.warmup, args.steps)
-    log(f"mixed: {args.steps} steps in {tm['seconds']:.4f} s ({tm['ms_per_step']:.3f} ms per {args.batch}-frame step)")
+    log(f"{args.precision}: {args.steps} steps in {tm['seconds']:.4f} s ({tm['ms_per_step']:.3f} ms per "
+        f"{args.batch}-frame step)")
     if args.only_timing:
         print(json.dumps({"metric": "deblurred Mpixel/s", "value": tm["value"], "unit": "Mpixel/s", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup, "ms_per_step": tm["ms_per_step"],
@@ -585,8 +593,17 @@ def main():
     for name in forms:
         if name.startswith("learned") and blob is None:
             continue
+        if name == args.precision:
+            continue
         if name == "fp64":
             s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float64, P.Precision.FP64, P.Flags.GRAPH)
+        elif name in ("mixed", "mfma64"):
+            s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32,
+                       P.Precision.MFMA64 if name == "mfma64" else P.Precision.MIXED, P.Flags.GRAPH,
+                       autotune=not args.no_autotune)
+        elif name == "learned_mfma64":
+            s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32, P.Precision.MFMA64, P.Flags.GRAPH,
+                       mlp=blob)
         elif name == "learned_bf16":
             s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32, P.Precision.BF16, P.Flags.GRAPH,
                        mlp=blob)
@@ -621,7 +638,8 @@ def main():
         torch.cuda.synchronize()
 
     line = {
-        "metric": "deblurred Mpixel/s (kernel recovery + deconv), mixed form, PSNR vs FP64 oracle reported",
+        "metric": f"deblurred Mpixel/s (kernel recovery + deconv), {args.precision} form, PSNR vs FP64 oracle "
+                  "reported",
         "value": tm["value"],
         "unit": "Mpixel/s",
         "n_gpus": 1,
@@ -631,7 +649,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (frames, FFT, division) + f64 (evaluation, Gram, eigen-solves, scale fix)",
+        "dtype": "f32 (frames, FFT, division) + f64 (evaluation, Gram, eigen-solves, scale fix)"
+                 + (", Gram on FP64 matrix cores" if args.precision == "mfma64" else ""),
         "data": "synthetic",
         "config": {"workload": f"stream of {args.frames} x 1080x1920 RGB frames (moving blobs, channel gains + "
                                f"texture) cycled from {U} generated frames, one coprime 15x15/17x17 pair, "
@@ -654,8 +673,7 @@ def main():
                     "batch: launch to output"},
         "phases_us_per_launch": phases,
         "plain_fp64": extra.get("fp64"),
-        "learned_bf16": extra.get("learned_bf16"),
-        "learned": extra.get("learned"),
+        "other_forms": {k: v for k, v in extra.items() if k != "fp64"},
         "encoder": enc_ml["encoder"],
         "multilevel": enc_ml["multilevel"],
         "single_frame_480x640": single_res,

@@ -77,10 +77,15 @@ typedef enum { CBP_F32 = 0, CBP_F64 = 1, CBP_U8 = 2 /* 8-bit streams: cbp_quanti
  *   MFMA32 : as MIXED, but the per-sample Gram is A^H A on the matrix cores
  *            from FP32-rounded operands, FP32 accumulation (k1 + k2 <= 32).
  *   BF16   : as MFMA32 with bfloat16 operands (FP32 accumulation).
- * The two matrix-core forms square the conditioning of the per-sample
- * problems in FP32: their kernel error against the FP64 method is reported,
- * not bounded (see cbp_sample_grams). */
-typedef enum { CBP_PREC_FP64 = 0, CBP_PREC_MIXED = 1, CBP_PREC_MFMA32 = 2, CBP_PREC_BF16 = 3 } cbp_precision;
+ *   MFMA64 : as MIXED, but the Gram's correlations come from the FP64 matrix
+ *            cores (v_mfma_f64_16x16x4f64) on the FP64 evaluations, FP64
+ *            accumulation (k1 + k2 <= 32): an FP64-accurate Gram instead of
+ *            a double-double one.
+ * MFMA32 and BF16 square the conditioning of the per-sample problems in
+ * FP32: their kernel error against the FP64 method is reported, not bounded
+ * (see cbp_sample_grams). */
+typedef enum { CBP_PREC_FP64 = 0, CBP_PREC_MIXED = 1, CBP_PREC_MFMA32 = 2, CBP_PREC_BF16 = 3,
+               CBP_PREC_MFMA64 = 4 } cbp_precision;
 
 typedef struct cbp_image {
   void*     data;            /* device pointer */

@@ -42,6 +42,7 @@ class Precision:
     MIXED = 1
     MFMA32 = 2
     BF16 = 3
+    MFMA64 = 4
 
 
 class Flags:

@@ -165,15 +165,17 @@ cbp_status check_options(const cbp_options* o, int dtype) {
   if ((o->flags & CBP_FLAG_SCALE_K1) && (o->flags & CBP_FLAG_ONE_AXIS)) return CBP_E_INVALID;
   if (o->learned && (o->flags & (CBP_FLAG_SCALE_K1 | CBP_FLAG_ONE_AXIS))) return CBP_E_UNSUPPORTED;
   if (o->precision == CBP_PREC_FP64) return dtype == CBP_F64 ? CBP_OK : CBP_E_INVALID;
-  if (o->precision == CBP_PREC_MIXED || o->precision == CBP_PREC_MFMA32 || o->precision == CBP_PREC_BF16)
+  if (o->precision == CBP_PREC_MIXED || o->precision == CBP_PREC_MFMA32 || o->precision == CBP_PREC_BF16 ||
+      o->precision == CBP_PREC_MFMA64)
     return dtype == CBP_F32 ? CBP_OK : CBP_E_INVALID;
   return CBP_E_INVALID;
 }
 
 // Gram route of a precision form: -1 = double-double correlations (FP64,
-// MIXED), 0 = matrix cores on FP32 operands (MFMA32), 1 = on bfloat16 (BF16).
+// MIXED), 0 = matrix cores on FP32 operands (MFMA32), 1 = on bfloat16 (BF16),
+// 2 = FP64 matrix cores on the FP64 evaluations (MFMA64).
 int gram_format(int precision) {
-  return precision == CBP_PREC_MFMA32 ? 0 : precision == CBP_PREC_BF16 ? 1 : -1;
+  return precision == CBP_PREC_MFMA32 ? 0 : precision == CBP_PREC_BF16 ? 1 : precision == CBP_PREC_MFMA64 ? 2 : -1;
 }
 
 // Shapes -> plan.  All checks are host-side.

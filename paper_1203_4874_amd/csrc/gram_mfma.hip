@@ -1,5 +1,5 @@
-// Per-sample Gram matrices on the matrix cores (precision forms MFMA32 and
-// BF16).  G = A^H A for A = [C_k2(e1) | -C_k1(e2)] (the stacked convolution
+// Per-sample Gram matrices on the matrix cores (precision forms MFMA32,
+// BF16 and MFMA64; the last at the end of this file).  G = A^H A for A = [C_k2(e1) | -C_k1(e2)] (the stacked convolution
 // matrix of one sample) is a dense contraction over the L = len(e1) + k2 - 1
 // rows of A.  In real form, with M = [Re A | Im A] (L x 2N, N = k1 + k2 <= 32,
 // padded with zero columns to 64),
@@ -164,16 +164,117 @@ __global__ __launch_bounds__(256) void k_gram_mfma(batch_ref br) {
   });
 }
 
+// ---------------------------------------------------------------- FP64 matrix cores
+// Precision form MFMA64: the Gram's correlations on v_mfma_f64_16x16x4f64
+// from the FP64 evaluations themselves (no operand rounding), FP64
+// accumulation.  Only the columns 0 and k2 of G are needed (every correlation
+// is in them: rho11(l) = G[l][0], rho22(l) = G[k2+l][k2], rho12(l) = -G[l][k2]
+// for l >= 0 and -conj(G[k2-l][0]) for l < 0), so only the four columns
+// {0, k2, N, N + k2} of R = M^T M are formed: four 16 x 16 tiles (rows p of
+// R in blocks of 16) whose first four columns are those (B's other columns
+// are zero).  v_mfma_f64_16x16x4f64 takes A[i][k] from lane 16 k + i, B[k][j]
+// from lane 16 k + j and leaves D[4 (lane / 16) + v][lane % 16] in
+// accumulator v of each lane.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int GM64_RS = 5;      // row stride of the R column buffer (doubles)
+constexpr int GM64_WAVES = 16;  // waves per workgroup: the rows of one item are split over them
+
+__global__ __launch_bounds__(64 * GM64_WAVES) void k_gram_mfma64(batch_ref br) {
+  extern __shared__ __attribute__((aligned(16))) char sm_gm[];
+  for_items<Q_GRAMM>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+    const int S = d.S, k1 = d.k1, k2 = d.k2, N = k1 + k2, NL = 2 * N - 1;
+    const int j = item % S, pass = item / S;
+    const int len1 = pass ? d.H1 : d.W1, len2 = pass ? d.H2 : d.W2;
+    const int L = len1 + k2 - 1;
+    const int stride = pass ? d.Hmax : d.Wmax;
+    const int P = stride + GM_PAD;
+    const c64* base = pass ? d.ey : d.ex;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double* Rc = (double*)sm_gm;                       // [64][GM64_RS]: R[p][{0, k2, N, N + k2}]
+    double* sd = Rc + 64 * GM64_RS + 3;                // [4][P] staged re / im of e1 and -e2 (odd offset: 16-B aligned below)
+    sd = (double*)(((size_t)sd + 15) & ~(size_t)15);
+    // this lane's operands: A rows p = 16 pb + lane % 16 (four blocks pb),
+    // B column jj = lane % 16 (columns 0..3 map to R's q in {0, k2, N, N + k2})
+    const int i16 = lane & 15, kk = lane >> 4;
+    mcol ca[4];
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) ca[pb] = column_of(16 * pb + i16, k2, N);
+    const int qs[4] = {0, k2, N, N + k2};
+    const mcol cb = i16 < 4 ? column_of(qs[i16], k2, N) : mcol{-1, 0};
+    v4d acc[4] = {};
+    for (int ch = 0; ch < d.nch; ++ch) {
+      const c64* e1 = base + ((size_t)(ch * 2 + 0) * S + j) * stride;
+      const c64* e2 = base + ((size_t)(ch * 2 + 1) * S + j) * stride;
+      for (int t = tid; t < P; t += 64 * GM64_WAVES) {
+        const int i1 = t - GM_PAD_L;
+        const c64 a = (i1 >= 0 && i1 < len1) ? e1[i1] : c64{0.0, 0.0};
+        const c64 b = (i1 >= 0 && i1 < len2) ? e2[i1] : c64{0.0, 0.0};
+        sd[0 * P + t] = a.re; sd[1 * P + t] = -b.re;
+        sd[2 * P + t] = a.im; sd[3 * P + t] = -b.im;
+      }
+      __syncthreads();
+      const double* pa[4];
+#pragma unroll
+      for (int pb = 0; pb < 4; ++pb) pa[pb] = ca[pb].arr >= 0 ? sd + ca[pb].arr * P + GM_PAD_L - ca[pb].shift : nullptr;
+      const double* pbp = cb.arr >= 0 ? sd + cb.arr * P + GM_PAD_L - cb.shift : nullptr;
+      // K = 4 rows per step: lane supplies row r0 + lane / 16; wave w takes
+      // steps w, w + GM64_WAVES, ...
+      for (int r0 = 4 * w; r0 < L; r0 += 4 * GM64_WAVES) {
+        const int r = r0 + kk;
+        const double bv = pbp ? pbp[r] : 0.0;
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+          const double av = pa[pb] ? pa[pb][r] : 0.0;
+          acc[pb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[pb], 0, 0, 0);
+        }
+      }
+      __syncthreads();  // staging buffers are rewritten for the next channel
+    }
+    // the waves' partial columns summed into Rc in wave order
+    for (int ww = 0; ww < GM64_WAVES; ++ww) {
+      if (w == ww && i16 < 4) {
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int p = 16 * pb + 4 * v + kk;   // D row 4 v + lane / 16, column lane % 16
+            if (ww == 0) Rc[p * GM64_RS + i16] = acc[pb][v];
+            else Rc[p * GM64_RS + i16] += acc[pb][v];
+          }
+      }
+      __syncthreads();
+    }
+    // G[p][c] for c in {0 (column 0), 1 (column k2)}
+    auto G = [&](int p, int c) -> c64 {
+      return c64{Rc[p * GM64_RS + c] + Rc[(N + p) * GM64_RS + 2 + c], Rc[p * GM64_RS + 2 + c] - Rc[(N + p) * GM64_RS + c]};
+    };
+    for (int li = tid; li < NL; li += 64 * GM64_WAVES) {
+      c64 g;
+      if (li < k2) g = G(li, 0);                                     // rho11(l) = G[l][0]
+      else if (li < k2 + k1) g = G(k2 + (li - k2), 1);              // rho22(l) = G[k2+l][k2]
+      else {
+        const int l = li - (k1 + k2) - (k1 - 1);
+        g = l >= 0 ? G(l, 1) : conj(G(k2 - l, 0));                   // G[l][k2] or G[0][k2-l]
+        g = c64{-g.re, -g.im};                                       // rho12 = -G12
+      }
+      d.corr[((size_t)pass * S + j) * NL + li] = cdd{{g.re, 0.0}, {g.im, 0.0}};
+    }
+  });
+}
+
 }  // namespace
 
 size_t gram_mfma_lds_bytes(int maxStride, int fmt) {
   const size_t P = (size_t)maxStride + GM_PAD;
+  if (fmt == 2) return 64 * GM64_RS * sizeof(double) + 32 + 4 * P * sizeof(double);
   return 64 * GM_RS * sizeof(float) + 4 * P * (fmt == 0 ? sizeof(float) : sizeof(unsigned short));
 }
 
 void set_gram_mfma_attrs() {
   hipFuncSetAttribute((const void*)k_gram_mfma<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   hipFuncSetAttribute((const void*)k_gram_mfma<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_gram_mfma64, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 hipError_t launch_gram_mfma(const batch_ref& br, int grid, int fmt, int maxStride,
@@ -181,8 +282,10 @@ hipError_t launch_gram_mfma(const batch_ref& br, int grid, int fmt, int maxStrid
   prof_begin(PH_GRAM, st);
   if (fmt == 0)
     hipLaunchKernelGGL(k_gram_mfma<0>, dim3(grid), dim3(256), gram_mfma_lds_bytes(maxStride, 0), st, br);
-  else
+  else if (fmt == 1)
     hipLaunchKernelGGL(k_gram_mfma<1>, dim3(grid), dim3(256), gram_mfma_lds_bytes(maxStride, 1), st, br);
+  else
+    hipLaunchKernelGGL(k_gram_mfma64, dim3(grid), dim3(64 * GM64_WAVES), gram_mfma_lds_bytes(maxStride, 2), st, br);
   prof_end(PH_GRAM, st);
   return hipGetLastError();
 }

@@ -158,3 +158,70 @@ def test_precision_forms_error_report(P, case):
         assert np.isfinite(K1).all() and np.isfinite(L).all()
         if fmt is None:
             assert e <= 1e-3 and p >= 60
+
+
+def test_mfma64_grams_within_fp64_bound(P):
+    """MFMA64: the correlations from the FP64 matrix cores on the FP64
+    evaluations.  Against the double-double Gram of the same device
+    evaluations (MIXED reads the same FP32 frames through the same evaluation
+    kernels), the only difference is the FP64 accumulation of L products plus
+    the final sum of two entries, so entrywise
+        |G_mfma64 - G_dd| <= (L + 3) 2^-53 (|M|^T |M|);
+    a layout or index mistake breaks this by orders of magnitude.  Against
+    the oracle the Gram keeps the double-double form's 1e-12 of max |G|."""
+    for (m, n, k1, k2) in [(64, 64, 5, 5), (96, 140, 9, 11), (40, 33, 3, 7), (30, 250, 15, 17),
+                           (20, 30, 16, 16), (44, 36, 1, 6)]:
+        B1, B2, _, _, _ = _pair(37, m, n, k1, k2, np.float32)
+        b1, b2 = to_dev(B1, torch.float32), to_dev(B2, torch.float32)
+        G = P.sample_grams(b1, b2, m, n, precision=P.Precision.MFMA64).cpu().numpy()
+        Gd = P.sample_grams(b1, b2, m, n, precision=P.Precision.MIXED).cpu().numpy()
+        Go, Mabs, L = _oracle_grams(B1, B2, m, n, None)
+        N = k1 + k2
+        c = (L + 3) * 2.0 ** -53
+        bound_re = c * (Mabs[:, :, :N, :N] + Mabs[:, :, N:, N:])
+        bound_im = c * (Mabs[:, :, :N, N:] + Mabs[:, :, N:, :N])
+        worst = max((np.abs(G.real - Gd.real) / np.maximum(bound_re, 1e-300)).max(),
+                    (np.abs(G.imag - Gd.imag) / np.maximum(bound_im, 1e-300)).max())
+        err = np.abs(G - Go).max() / np.abs(Go).max()
+        print(f"MFMA64 Gram {m}x{n} k=({k1},{k2}): worst |G - G_dd| / bound = {worst:.3f}, "
+              f"max err vs oracle / max |G| {err:.2e}", flush=True)
+        assert worst <= 1.0
+        assert err <= 1e-12
+
+
+def test_mfma64_channels_sum(P):
+    B = [_pair(39 + c, 48, 52, 4, 6, np.float32) for c in range(3)]
+    B1 = np.stack([b[0] for b in B])
+    B2 = np.stack([b[1] for b in B])
+    G = P.sample_grams(to_dev(B1, torch.float32), to_dev(B2, torch.float32), 48, 52,
+                       precision=P.Precision.MFMA64).cpu().numpy()
+    Go = sum(_oracle_grams(B1[c], B2[c], 48, 52, None)[0] for c in range(3))
+    assert np.abs(G - Go).max() / np.abs(Go).max() <= 1e-13
+
+
+@pytest.mark.parametrize("case", ["config2_noiseless", "config2", "config3_frame", "config5_frame"])
+def test_mfma64_kernels_meet_the_mixed_target(P, case):
+    """The FP64 matrix-core Gram keeps the mixed form's bar: kernels within
+    1e-3 (rel-L2) of the FP64 oracle, latent >= 60 dB against its latent."""
+    if case.startswith("config2"):
+        c = synth.config2(noise=0.0 if case == "config2_noiseless" else 1e-3)
+    elif case == "config3_frame":
+        c = next(synth.config3_frames(nframes=1))
+    else:
+        c = synth.config5_frame(0)
+    m, n, lam = c["m"], c["n"], c["lam"]
+    B1 = c["B1"].astype(np.float32).astype(np.float64)
+    B2 = c["B2"].astype(np.float32).astype(np.float64)
+    print(f"MFMA64 {case}: frames {B1.shape} / {B2.shape}", flush=True)
+    Lo, R1, R2 = orc.deblur(B1, B2, m, n, 0, lam)
+    H, W = max(B1.shape[-2], B2.shape[-2]), max(B1.shape[-1], B2.shape[-1])
+    k = max(c["K1"].shape[0], c["K2"].shape[0])
+    nch = B1.shape[0] if B1.ndim == 3 else 1
+    d = P.Deblurrer(H, W, k, nch, precision=P.Precision.MFMA64)
+    L, K1, K2 = d.deblur(to_dev(B1, torch.float32), to_dev(B2, torch.float32), m, n, lam=lam)
+    torch.cuda.synchronize()
+    K1, K2, L = K1.cpu().numpy(), K2.cpu().numpy(), L.cpu().numpy()
+    e = max(rel(K1, R1), rel(K2, R2))
+    p = min(psnr(L[c_], Lo[c_]) for c_ in range(nch)) if nch > 1 else psnr(L, Lo)
+    print(f"  kernel rel-L2 vs FP64 oracle {e:.2e}, latent PSNR vs oracle {p:.1f} dB", flush=True)
+    assert e <= 1e-3 and p >= 60.0
