@@ -60,10 +60,16 @@ struct region_sizes {
   size_t fpart, ex, ey, corr, xvec, pq, kern, t, u, feat, wts, kalt, twxd;
 };
 
+// Row pitch of T and U: hx entries of 2 esize bytes rounded up to 128 bytes.
+int pitch_of(int hx, int esize) {
+  const int per = 128 / (2 * esize);
+  return (hx + per - 1) / per * per;
+}
+
 region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
   region_sizes r;
   const int Px = smooth7(Wmax);
-  const size_t hx = (size_t)Px / 2 + 1;
+  const size_t hx = pitch_of((int)((size_t)Px / 2 + 1), esize);
   const size_t ncf = 2 * (size_t)nch;
   r.fpart = ((size_t)(Hmax + 31) / 32 + 1) * ncf * S * (size_t)Wmax * sizeof(double);
   r.ex = ncf * S * (size_t)Wmax * sizeof(c64);
@@ -131,11 +137,19 @@ constexpr tuning kDefaultTuning = {128, 0, 0, 0};
 
 // Columns per column-pass strip: a power of two (the kernel splits indices
 // with shifts), at most 8.
-int choose_cw(int Py, int hx, int esize, int want) {
-  int cw = want > 0 ? want : 4;
-  if (cw > 8) cw = 8;
+// Does a strip of cw columns of length Py fit the column pass?
+bool col_fits(int Py, int cw, int esize) {
+  return col_lds_bytes(Py, cw, esize) <= kLdsLimit - 4096 && (int64_t)cw * Py <= col_max_strip_elems(esize);
+}
+
+// Columns per column-pass strip: `want` (a power of two up to 16) if given,
+// else the widest strip that still leaves at least 256 strips over the
+// frame's channels; either way narrowed until the strip fits.
+int choose_cw(int Py, int hx, int nch, int esize, int want) {
+  int cw = want > 0 ? want : 16;
+  if (cw > 16) cw = 16;
   while (cw & (cw - 1)) cw &= cw - 1;
-  while (cw > 1 && (col_lds_bytes(Py, cw, esize) > kLdsLimit - 4096 || (want <= 0 && (hx + cw - 1) / cw < 256)))
+  while (cw > 1 && (!col_fits(Py, cw, esize) || (want <= 0 && (int64_t)((hx + cw - 1) / cw) * nch < 256)))
     cw >>= 1;
   return cw;
 }
@@ -209,6 +223,7 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
   fp->Px = smooth7(fp->Wmax);
   if (sizes_only) {
     fp->hx = fp->Px / 2 + 1;
+    fp->hxp = pitch_of(fp->hx, esize);
     fp->cw = 1;
     layout(fp, regions(fp->Hmax, fp->Wmax, kmax, S, fp->nch, esize));
     return CBP_OK;
@@ -217,13 +232,14 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
   if (!make_fft_plan(fp->Py, &fp->fy, tn.fft_order) || !make_fft_plan(fp->Px, &fp->fx, tn.fft_order))
     return CBP_E_SHAPE;
   fp->hx = fp->Px / 2 + 1;
-  fp->cw = choose_cw(fp->Py, fp->hx, esize, tn.cw);
+  fp->hxp = pitch_of(fp->hx, esize);
+  fp->cw = choose_cw(fp->Py, fp->hx, fp->nch, esize, tn.cw);
   const int gfmt = gram_format(o->precision);
   if (gfmt >= 0 && (fp->N > 32 || gram_mfma_lds_bytes(std::max(fp->Hmax, fp->Wmax), gfmt) > kLdsLimit - 2048))
     return CBP_E_UNSUPPORTED;
   if (o->learned && fp->N > 32) return CBP_E_UNSUPPORTED;   // 32 spectrum features per sample
   if (sample_lds_bytes(fp->N) > kLdsLimit - 2048 || finalize_lds_bytes(S, o->learned != 0) > kLdsLimit - 2048 ||
-      row_lds_bytes(fp->Px, esize) > kLdsLimit - 2048 || col_lds_bytes(fp->Py, fp->cw, esize) > kLdsLimit - 2048)
+      row_lds_bytes(fp->Px, esize) > kLdsLimit - 2048 || !col_fits(fp->Py, fp->cw, esize))
     return CBP_E_SHAPE;
   layout(fp, regions(fp->Hmax, fp->Wmax, kmax, S, fp->nch, esize));
   return CBP_OK;
@@ -244,6 +260,7 @@ frame_desc make_desc(const frame_plan& fp, const cbp_image* b1, const cbp_image*
   d.ncf = 2 * fp.nch;
   d.m = fp.m; d.n = fp.n; d.k1 = fp.k1; d.k2 = fp.k2; d.S = fp.S; d.N = fp.N;
   d.rpg = fp.rpg; d.RG = fp.RG; d.Py = fp.Py; d.Px = fp.Px; d.hx = fp.hx; d.cw = fp.cw;
+  d.hxp = fp.hxp;
   d.fy = fp.fy;
   d.fx = fp.fx;
   d.fpart = (double*)(ws + fp.off_fpart);
@@ -571,7 +588,7 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
     }
     const int esize = dtype == CBP_F32 ? 4 : 8;
     // the widest strip and the tallest column share one allocation; keep it in LDS
-    while (cv.maxcw > 1 && col_lds_bytes(cv.maxPy, cv.maxcw, esize) > kLdsLimit - 2048) {
+    while (cv.maxcw > 1 && !col_fits(cv.maxPy, cv.maxcw, esize)) {
       cv.maxcw >>= 1;
       for (int i = 0; i < cnt; ++i) {
         frame_plan& p = bb->plans[f0 + i];
@@ -737,7 +754,7 @@ tuning autotune(dev_state& ds, const std::vector<frame_req>& reqs, const cbp_opt
   };
   for (int order = 1; order < FFT_ORDERS; ++order) { tuning t = best; t.fft_order = order; consider(t); }
   for (int rows : {32, 64, 128, 256}) { tuning t = best; t.fold_rows = rows; consider(t); }
-  for (int cw : {1, 2, 4, 8}) { tuning t = best; t.cw = cw; consider(t); }
+  for (int cw : {1, 2, 4, 8, 16}) { tuning t = best; t.cw = cw; consider(t); }
   for (int wpc : {2, 4, 8, 16}) { tuning t = best; t.wg_per_cu = wpc; consider(t); }
   *best_ms = bms;
   return best;

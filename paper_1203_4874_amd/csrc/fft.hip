@@ -14,6 +14,8 @@
 //      T_1 and T_2 columns (zero rows beyond H_c), the filter above with the
 //      kernel spectra evaluated in place from the k x k kernels, inverse FFT,
 //      keep the first m rows -> U[y][kx];
+// T and U rows have a pitch of hxp >= hx entries, a multiple of 128 bytes, so
+// the column pass reads and writes whole row segments.
 //   3. inverse row pass: two rows of U packed as one complex spectrum (each
 //      completed by Hermitian symmetry), one inverse FFT, real / imaginary
 //      parts are the two output rows, scaled by 1/(Py Px), cropped to n.
@@ -157,8 +159,8 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int 
       }
     }
     const cplx<T>* z = fft_lds<-1>(a, b, px, tw, 1, N);
-    cplx<T>* o1 = (cplx<T>*)d.t1 + (int64_t)ch * d.Hmax * hx + (int64_t)y * hx;
-    cplx<T>* o2 = (cplx<T>*)d.t2 + (int64_t)ch * d.Hmax * hx + (int64_t)y * hx;
+    cplx<T>* o1 = (cplx<T>*)d.t1 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
+    cplx<T>* o2 = (cplx<T>*)d.t2 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
     for (int k = threadIdx.x; k < hx; k += blockDim.x) {
       const cplx<T> zk = z[k];
       const cplx<T> zn = conj(z[k == 0 ? 0 : N - k]);
@@ -170,59 +172,174 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int 
 }
 
 // ---------------------------------------------------------------- pass 2
+// The column pass keeps one strip of cw columns (cw up to 16: up to 128-byte
+// row segments of T) in LDS, column-major with an odd leading dimension, and
+// transforms it in place: every pass reads its butterflies' inputs into
+// registers, synchronises, and writes the outputs over them.  One buffer per
+// strip instead of two frames' ping-pong pairs is what makes wide strips fit;
+// frame 2's spectrum waits in registers while frame 1 is transformed.  The
+// workgroup has NT = 512 or 1024 threads; the twiddles w_N^t are a full
+// N-entry table in LDS (one read per twiddle).
+
+// threadIdx.x behind an empty asm statement: values derived from it are
+// recomputed where they are used instead of being hoisted out of the item
+// loop, where they would stay live (one register each) across the kernel.
+__device__ __attribute__((always_inline)) inline int local_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// Largest cw * N of a strip: 9.5 FP32 (4.75 FP64) complex entries per
+// thread, so each thread's share of a pass and of the stashed spectrum stays
+// in registers.
+template <typename T, int NT>
+constexpr int col_max_elems() { return NT * 76 / (int)sizeof(cplx<T>); }
+
+// Butterflies per thread of a radix-R pass over the largest strip.
+template <typename T, int NT, int R>
+constexpr int col_mb() { return (col_max_elems<T, NT>() / R + NT - 1) / NT; }
+
+// One radix-R pass (stride Ns) over ncol columns of length N at buf + c ld,
+// in place: butterfly j of column c reads buf[c ld + j + r N/R] and writes
+// buf[c ld + (j - k) R + k + r Ns], k = j mod Ns (the Stockham indexing of
+// fft_core.h, read and write phases separated by a barrier).
+template <int R, int DIR, int NT, typename T>
+__device__ __attribute__((always_inline)) inline void col_pass(cplx<T>* buf, int ld, int N, int Ns,
+                                                               const cplx<T>* tw, int ncol) {
+  constexpr int MB = col_mb<T, NT, R>();
+  const int NR = N / R;
+  const int total = NR * ncol;
+  const int twstep = N / (Ns * R);
+  const float rnr = 1.0f / (float)NR, rns = 1.0f / (float)Ns;
+  cplx<T> v[MB][R];
+  int pos[MB];
+  const int tid = local_tid();
+#pragma unroll
+  for (int q = 0; q < MB; ++q) {
+    const int b = tid + q * NT;
+    pos[q] = -1;
+    if (b < total) {
+      const int c = fdiv_floor(b, rnr);
+      const int j = b - mul24(c, NR);
+      const int k = j - mul24(fdiv_floor(j, rns), Ns);
+      const cplx<T>* src = buf + mul24(c, ld) + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[mul24(r, NR)];
+      if (Ns > 1) {
+        const int step = mul24(k, twstep);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cplx<T> w = tw[mul24(r, step)];
+          if (DIR > 0) w.im = -w.im;
+          v[q][r] = v[q][r] * w;
+        }
+      }
+      dft_small<R, DIR>(v[q]);
+      pos[q] = mul24(c, ld) + mul24(j - k, R) + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MB; ++q)
+    if (pos[q] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pos[q] + mul24(r, Ns)] = v[q][r];
+    }
+  __syncthreads();
+}
+
+template <int DIR, int NT, typename T>
+__device__ __attribute__((always_inline)) inline void col_fft(cplx<T>* buf, int ld, const fft_plan& p,
+                                                              const cplx<T>* tw, int ncol) {
+  int Ns = 1;
+  for (int s = 0; s < p.npass; ++s) {
+    const int R = plan_radix(p, s);
+    switch (R) {
+      case 2: col_pass<2, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
+      case 3: col_pass<3, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
+      case 4: col_pass<4, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
+      case 5: col_pass<5, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
+      case 7: col_pass<7, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
+      default: col_pass<8, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
+    }
+    Ns *= R;
+  }
+}
+
+// Strip rows [0, Hf) of src (row pitch tp) into buf[c ld + y], rows [Hf, N)
+// and columns past hx as zeros.  Element e = y cw + c: cw consecutive
+// threads read one row segment; eight loads per thread in flight from
+// clamped (always valid) addresses.
+template <int NT, typename T>
+__device__ __attribute__((always_inline)) inline void col_load(cplx<T>* buf, int ld, const cplx<T>* src, int tp,
+                                                               int Hf, int N, int kx0, int hx, int lcw) {
+  const int cw = 1 << lcw;
+  const int tot = N << lcw;
+  const int tid = local_tid();
+  for (int e0 = 0; e0 < tot; e0 += 8 * NT) {
+    cplx<T> v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = e0 + t * NT + tid;
+      const int y = e >> lcw, c = e & (cw - 1);
+      v[t] = src[(int64_t)min(y, Hf - 1) * tp + min(kx0 + c, hx - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = e0 + t * NT + tid;
+      const int y = e >> lcw, c = e & (cw - 1);
+      if (e < tot) buf[mul24(c, ld) + y] = (y < Hf && kx0 + c < hx) ? v[t] : cplx<T>{T(0), T(0)};
+    }
+  }
+}
+
+// The strip's entries as each thread holds them for the stash and the
+// filter: column c = tid / (NT / cw) (wave-uniform: NT / cw >= 64) and, for
+// even N, row pairs (y, y + N/2), y = tid mod (NT / cw) + i NT / cw, whose
+// twiddles differ only in sign; for odd N, single rows.  f(slot, y) is
+// called for each held entry with slot < col_slots.
+template <typename T, int NT>
+constexpr int col_pairs() { return (col_max_elems<T, NT>() / 2 + NT - 1) / NT; }
+template <typename T, int NT>
+constexpr int col_singles() { return (col_max_elems<T, NT>() + NT - 1) / NT; }
+template <typename T, int NT>
+constexpr int col_slots() {
+  return 2 * col_pairs<T, NT>() > col_singles<T, NT>() ? 2 * col_pairs<T, NT>() : col_singles<T, NT>();
+}
+
 // Items: (strip of cw columns, channel).
-template <typename T>
-__global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_col_filter(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_cf[];
-  __shared__ cplx<T> twl[64], twh[CBP_MAX_FFT_F32 / 64];
+  constexpr int SP = col_pairs<T, NT>(), SE = col_singles<T, NT>(), SM = col_slots<T, NT>();
+  constexpr int LNT = NT == 1024 ? 10 : 9;
   for_items<Q_COL>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const fft_plan& py = d.fy;
-    const int N = py.N, cw = d.cw, hx = d.hx, m = d.m;
+    const int N = py.N, cw = d.cw, hx = d.hx, tp = d.hxp, m = d.m;
+    const int ld = N | 1;
     const int k1 = d.k1, k2 = d.k2, Px = d.Px, H1 = d.H1, H2 = d.H2;
     const double* K1 = d.K1;
     const double* K2 = d.K2;
     const c64* twd = d.twxd;
     const T lam = (T)d.lambda;
     const bool two = !(d.variant & VAR_DIVIDE_B1);   // two-channel division, or B1 / K1 alone
-    const int nf = 2 * cw;                      // transforms in flight: (column, frame)
-    cplx<T>* a = (cplx<T>*)sm_cf;               // [nf][N]
-    cplx<T>* b = a + (size_t)nf * N;            // [nf][N]
-    const tw_split<T> tw = split_twiddles(twl, twh, N);
-    cplx<T>* kr = b + (size_t)nf * N;           // [cw][2][CBP_MAX_K] row DFTs of the kernels at kx
+    cplx<T>* buf = (cplx<T>*)sm_cf;                   // [cw][ld]
+    cplx<T>* kr = buf + (size_t)cw * ld;              // [cw][2][CBP_MAX_K] row DFTs of the kernels at kx
+    cplx<T>* tw = kr + (size_t)cw * 2 * CBP_MAX_K;    // [N] w_N^t
     const int nstrip = (hx + cw - 1) / cw;
     const int kx0 = (item % nstrip) * cw, ch = item / nstrip;
-    const int64_t tpc = (int64_t)d.Hmax * hx;
+    const int lcw = __builtin_ctz(cw);                // cw is a power of two
+    const int64_t tpc = (int64_t)d.Hmax * tp;
     const cplx<T>* s1 = (const cplx<T>*)d.t1 + ch * tpc;
     const cplx<T>* s2 = (const cplx<T>*)d.t2 + ch * tpc;
-    // load: element (y, f) with f = 2*col + frame; consecutive threads walk f
-    // (adjacent columns of one row) for coalescing
-    const int lnf = __builtin_ctz(nf);         // cw, hence nf, is a power of two
-    // eight loads per thread in flight from clamped (always valid) addresses;
-    // entries outside the frame or past the last column are zeroed afterwards
-    for (int e0 = 0; e0 < nf * N; e0 += 8 * (int)blockDim.x) {
-      cplx<T> v[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int e = e0 + t * (int)blockDim.x + (int)threadIdx.x;
-        const int y = e >> lnf, f = e & (nf - 1);
-        const int col = min(kx0 + (f >> 1), hx - 1);
-        const int fr = f & 1;
-        const cplx<T>* src = fr ? s2 : s1;
-        v[t] = src[(int64_t)min(y, (fr ? H2 : H1) - 1) * hx + col];
-      }
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int e = e0 + t * (int)blockDim.x + (int)threadIdx.x;
-        const int y = e >> lnf, f = e & (nf - 1);
-        const int fr = f & 1;
-        if (e < nf * N) {
-          const bool in = kx0 + (f >> 1) < hx && y < (fr ? H2 : H1);
-          a[(size_t)f * N + y] = in ? v[t] : cplx<T>{T(0), T(0)};
-        }
-      }
+    for (int t = threadIdx.x; t < N; t += NT) {
+      double sn, cs;
+      sincospi(-2.0 * (double)t / (double)N, &sn, &cs);
+      tw[t] = {T(cs), T(sn)};
     }
     // kernel row DFTs at this strip's columns: kr[c][fr][yy] = sum_x K[yy][x] exp(-2 pi i kx x / Px)
-    for (int e = threadIdx.x; e < cw * 2 * CBP_MAX_K; e += blockDim.x) {
+    for (int e = threadIdx.x; e < cw * 2 * CBP_MAX_K; e += NT) {
       const int c = e / (2 * CBP_MAX_K), rem = e - c * 2 * CBP_MAX_K;
       const int fr = rem / CBP_MAX_K, yy = rem - fr * CBP_MAX_K;
       const int k = fr ? k2 : k1;
@@ -252,44 +369,96 @@ __global__ __launch_bounds__(256) void k_col_filter(batch_ref br) {
       }
       kr[e] = {T(sr), T(si)};
     }
-    __syncthreads();
-    cplx<T>* f1 = fft_lds<-1>(a, b, py, tw, nf, N);
-    cplx<T>* f2 = (f1 == a) ? b : a;
-    // filter: combined spectrum written into the frame-1 slot of each column
-    const float rN = 1.0f / (float)N;
-    const int kmax = k1 > k2 ? k1 : k2;
-    for (int e = threadIdx.x; e < cw * N; e += blockDim.x) {
-      const int c = fdiv_floor(e, rN), ky = e - c * N;
-      // kernel spectra at (ky, kx): sum_yy kr[yy] z^yy, z = exp(-2 pi i ky / Py),
-      // by Horner's rule (kr is zero beyond each kernel's size)
-      const cplx<T>* kr1 = kr + (size_t)c * 2 * CBP_MAX_K;
-      const cplx<T>* kr2 = kr1 + CBP_MAX_K;
-      const cplx<T> z = tw[ky];
-      cplx<T> kh1 = kr1[kmax - 1], kh2 = kr2[kmax - 1];
-      for (int yy = kmax - 2; yy >= 0; --yy) {
-        kh1 = kh1 * z + kr1[yy];
-        kh2 = kh2 * z + kr2[yy];
+    // the entries this thread holds (see col_slots)
+    const bool even = (N & 1) == 0;
+    const int h = even ? N >> 1 : N;
+    auto for_held = [&](auto&& f) __attribute__((always_inline)) {
+      const int tid = local_tid();
+      const int ltpc = LNT - lcw;
+      const int c = tid >> ltpc, r = tid & ((1 << ltpc) - 1);
+      if (even) {
+#pragma unroll
+        for (int i = 0; i < SP; ++i) {
+          const int y = r + (i << ltpc);
+          if (y < h) f(2 * i, 2 * i + 1, c, y, true);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < SE; ++i) {
+          const int y = r + (i << ltpc);
+          if (y < N) f(i, i, c, y, false);
+        }
       }
-      const cplx<T> B1 = f1[(size_t)(2 * c) * N + ky];
-      const cplx<T> B2 = f1[(size_t)(2 * c + 1) * N + ky];
-      const cplx<T> num = two ? cmulc(kh1, B1) + cmulc(kh2, B2) : cmulc(kh1, B1);
+    };
+    cplx<T> st2[SM];
+    if (two) {
+      col_load<NT>(buf, ld, s2, tp, H2, N, kx0, hx, lcw);
+      __syncthreads();
+      col_fft<-1, NT>(buf, ld, py, tw, cw);
+      for_held([&](int a, int b, int c, int y, bool pair) __attribute__((always_inline)) {
+        st2[a] = buf[mul24(c, ld) + y];
+        if (pair) st2[b] = buf[mul24(c, ld) + y + h];
+      });
+      __syncthreads();   // buf is refilled with frame 1
+    }
+    col_load<NT>(buf, ld, s1, tp, H1, N, kx0, hx, lcw);
+    __syncthreads();
+    col_fft<-1, NT>(buf, ld, py, tw, cw);
+    // filter: the combined spectrum in place of frame 1's
+    const int kmax = k1 > k2 ? k1 : k2;
+    auto filt = [&](cplx<T>* at, const cplx<T>& kh1, const cplx<T>& kh2, const cplx<T>& b2)
+        __attribute__((always_inline)) {
+      const cplx<T> B1 = *at;
+      const cplx<T> num = two ? cmulc(kh1, B1) + cmulc(kh2, b2) : cmulc(kh1, B1);
       const T kk = two ? norm2(kh1) + norm2(kh2) : norm2(kh1);
       const T den = kk + lam;
       const T inv = den > T(0) ? T(1) / den : T(0);
       // where both kernel spectra vanish (a zeroed kernel pair) the
       // quotient is zero, whatever the frames hold
-      f1[(size_t)(2 * c) * N + ky] = kk > T(0) ? cplx<T>{num.re * inv, num.im * inv} : cplx<T>{T(0), T(0)};
-    }
+      *at = kk > T(0) ? cplx<T>{num.re * inv, num.im * inv} : cplx<T>{T(0), T(0)};
+    };
+    for_held([&](int a, int b, int c, int y, bool pair) __attribute__((always_inline)) {
+      // kernel spectra at (ky, kx) = sum_yy kr[yy] z^yy, z = w_N^y: for a row
+      // pair as E(z^2) + z O(z^2) and E(z^2) - z O(z^2) (even / odd
+      // coefficients by Horner's rule in u = z^2), else by Horner's rule in z;
+      // kr is zero beyond each kernel's size and the column is wave-uniform
+      const cplx<T>* kr1 = kr + (size_t)c * 2 * CBP_MAX_K;
+      const cplx<T>* kr2 = kr1 + CBP_MAX_K;
+      const cplx<T> z = tw[y];
+      if (pair) {
+        const cplx<T> u = tw[2 * y];
+        const int ke = (kmax + 1) >> 1;          // even coefficients 0, 2, .., 2 (ke - 1)
+        cplx<T> e1 = kr1[2 * (ke - 1)], e2 = kr2[2 * (ke - 1)];
+        cplx<T> o1 = {T(0), T(0)}, o2 = {T(0), T(0)};
+        if (2 * ke - 1 < CBP_MAX_K) { o1 = kr1[2 * ke - 1]; o2 = kr2[2 * ke - 1]; }
+        for (int t = ke - 2; t >= 0; --t) {
+          e1 = e1 * u + kr1[2 * t];
+          e2 = e2 * u + kr2[2 * t];
+          o1 = o1 * u + kr1[2 * t + 1];
+          o2 = o2 * u + kr2[2 * t + 1];
+        }
+        const cplx<T> zo1 = z * o1, zo2 = z * o2;
+        filt(buf + mul24(c, ld) + y, e1 + zo1, e2 + zo2, st2[a]);
+        filt(buf + mul24(c, ld) + y + h, e1 - zo1, e2 - zo2, st2[b]);
+      } else {
+        cplx<T> kh1 = kr1[kmax - 1], kh2 = kr2[kmax - 1];
+        for (int yy = kmax - 2; yy >= 0; --yy) {
+          kh1 = kh1 * z + kr1[yy];
+          kh2 = kh2 * z + kr2[yy];
+        }
+        filt(buf + mul24(c, ld) + y, kh1, kh2, st2[a]);
+      }
+    });
     __syncthreads();
-    // inverse column FFT of the cw combined spectra (slots 0, 2, 4, ...)
-    const cplx<T>* r = fft_lds<+1>(f1, f2, py, tw, cw, 2 * N);
-    cplx<T>* uo = (cplx<T>*)d.u + (int64_t)ch * m * hx;
-    const int lcw = __builtin_ctz(cw);
-    for (int e = threadIdx.x; e < m * cw; e += blockDim.x) {
+    col_fft<+1, NT>(buf, ld, py, tw, cw);
+    // the first m rows, row segments of cw columns
+    cplx<T>* uo = (cplx<T>*)d.u + (int64_t)ch * m * tp;
+    for (int e = threadIdx.x; e < (m << lcw); e += NT) {
       const int y = e >> lcw, c = e & (cw - 1);
       const int col = kx0 + c;
-      if (col < hx) uo[(int64_t)y * hx + col] = r[(size_t)(2 * c) * N + y];
+      if (col < hx) uo[(int64_t)y * tp + col] = buf[mul24(c, ld) + y];
     }
+    __syncthreads();   // the next item refills buf, kr and tw
   });
 }
 
@@ -308,8 +477,8 @@ __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
     const tw_split<T> tw = split_twiddles(twl, twh, N);
     const int npair = (m + 1) / 2;
     const int ya = 2 * (item % npair), yb = ya + 1, ch = item / npair;
-    const cplx<T>* ua = (const cplx<T>*)d.u + (int64_t)ch * m * hx + (int64_t)ya * hx;
-    const cplx<T>* ub = ua + hx;
+    const cplx<T>* ua = (const cplx<T>*)d.u + (int64_t)ch * m * d.hxp + (int64_t)ya * d.hxp;
+    const cplx<T>* ub = ua + d.hxp;
     const bool hb = yb < m;
     // eight index pairs per thread in flight: entry k < hx read directly,
     // k >= hx as the conjugate of entry N - k (< hx); indices past N clamp
@@ -350,13 +519,24 @@ __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
 
 size_t row_lds_bytes(int N, int esize) { return (size_t)2 * N * 2 * esize; }
 size_t col_lds_bytes(int N, int cw, int esize) {
-  return ((size_t)(4 * cw) * N + (size_t)cw * 2 * CBP_MAX_K) * 2 * esize;
+  return ((size_t)cw * (N | 1) + (size_t)cw * 2 * CBP_MAX_K + (size_t)N) * 2 * esize;
 }
 
+// Threads of the column-pass workgroup for a strip of cw * N entries: 512
+// while the strip fits their registers and cw <= 8 (one wave or more per
+// column), else 1024.
+int col_threads(int N, int cw, int esize) {
+  const int lim = esize == 4 ? col_max_elems<float, 512>() : col_max_elems<double, 512>();
+  return (cw <= 8 && (int64_t)cw * N <= lim) ? 512 : 1024;
+}
+
+int col_max_strip_elems(int esize) { return esize == 4 ? col_max_elems<float, 1024>() : col_max_elems<double, 1024>(); }
+
 void set_fft_attrs() {
-  const void* fns[6] = {(const void*)k_row_fwd<float>, (const void*)k_col_filter<float>, (const void*)k_row_inv<float>,
-                        (const void*)k_row_fwd<double>, (const void*)k_col_filter<double>,
-                        (const void*)k_row_inv<double>};
+  const void* fns[8] = {(const void*)k_row_fwd<float>, (const void*)k_col_filter<float, 512>,
+                        (const void*)k_col_filter<float, 1024>, (const void*)k_row_inv<float>,
+                        (const void*)k_row_fwd<double>, (const void*)k_col_filter<double, 512>,
+                        (const void*)k_col_filter<double, 1024>, (const void*)k_row_inv<double>};
   for (const void* f : fns) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
@@ -374,7 +554,11 @@ hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey,
 template <typename T>
 hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st) {
   prof_begin(PH_COL_FILTER, st);
-  hipLaunchKernelGGL(k_col_filter<T>, dim3(grid), dim3(256), col_lds_bytes(maxPy, maxcw, (int)sizeof(T)), st, br);
+  const size_t lds = col_lds_bytes(maxPy, maxcw, (int)sizeof(T));
+  if (col_threads(maxPy, maxcw, (int)sizeof(T)) == 512)
+    hipLaunchKernelGGL((k_col_filter<T, 512>), dim3(grid), dim3(512), lds, st, br);
+  else
+    hipLaunchKernelGGL((k_col_filter<T, 1024>), dim3(grid), dim3(1024), lds, st, br);
   prof_end(PH_COL_FILTER, st);
   return hipGetLastError();
 }

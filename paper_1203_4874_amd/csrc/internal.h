@@ -37,6 +37,7 @@ struct frame_plan {
   int nch;
   int rpg, RG;             // fold row-group size (multiple of S) and count
   int Py, Px, hx;          // FFT grid and half-spectrum width
+  int hxp;                 // row pitch of T and U (entries): hx rounded up to 128 bytes
   int cw;                  // columns per workgroup in the column pass
   fft_plan fy, fx;
   size_t off_fpart, off_ex, off_ey, off_corr, off_xvec, off_pq, off_kern,
@@ -83,7 +84,8 @@ struct frame_desc {
   // paper-faithful variants (CBP_FLAG_DIVIDE_B1 / SCALE_K1 / ONE_AXIS as
   // VAR_* bits); 0 = the default method
   int variant;
-  int pad_[3];
+  int hxp;           // row pitch of T and U (entries), a multiple of 128 bytes
+  int pad_[2];
 };
 constexpr int VAR_DIVIDE_B1 = 1, VAR_SCALE_K1 = 2, VAR_ONE_AXIS = 4;
 
@@ -304,6 +306,7 @@ template <typename T>
 hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t st);
 size_t row_lds_bytes(int N, int esize);
 size_t col_lds_bytes(int N, int cw, int esize);
+int col_max_strip_elems(int esize);   // largest cw * Py the column pass holds
 void set_recover_attrs();
 void set_fft_attrs();
 
