@@ -72,8 +72,9 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--workers", type=int, default=16, help="host processes generating the stream's frames")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes for the stream")
-    ap.add_argument("--lanes", type=int, default=1,
-                    help="streams the stream's batches alternate on (each with its own workspace)")
+    ap.add_argument("--lanes", type=int, default=3,
+                    help="streams the stream's batches alternate on (each with its own workspace): one "
+                         "batch's kernel recovery overlaps the previous batches' FFT passes")
     ap.add_argument("--only-timing", action="store_true",
                     help="stop after the timed steps (kernel-trace runs: the last W + K dispatches of each kernel "
                          "are the timed graph replays)")
@@ -275,8 +276,8 @@ def profile_stream(P, torch, s, nb):
 
 def arrival_pass(torch, s, fps):
     """Replay the stream with frame f arriving at f / fps seconds: batch b is
-    launched once its last frame has arrived (and after the batches before
-    it, on one stream).  Returns per-frame arrival-to-output latencies (ms)
+    launched once its last frame has arrived, on its lane's stream (after the
+    lane's earlier batches).  Returns per-frame arrival-to-output latencies (ms)
     and per-batch launch-to-output times (ms)."""
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -608,20 +609,21 @@ def main():
         if name == args.precision:
             continue
         if name == "fp64":
-            s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float64, P.Precision.FP64, P.Flags.GRAPH)
+            s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float64, P.Precision.FP64, P.Flags.GRAPH,
+                       lanes=args.lanes)
         elif name in ("mixed", "mfma64"):
             s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32,
                        P.Precision.MFMA64 if name == "mfma64" else P.Precision.MIXED, P.Flags.GRAPH,
-                       autotune=not args.no_autotune)
+                       autotune=not args.no_autotune, lanes=args.lanes)
         elif name == "learned_mfma64":
             s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32, P.Precision.MFMA64, P.Flags.GRAPH,
-                       mlp=blob)
+                       mlp=blob, lanes=args.lanes)
         elif name == "learned_bf16":
             s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32, P.Precision.BF16, P.Flags.GRAPH,
-                       mlp=blob)
+                       mlp=blob, lanes=args.lanes)
         elif name == "learned":
             s = Stream(P, torch, dev, host, args.frames, args.batch, torch.float32, P.Precision.MIXED, P.Flags.GRAPH,
-                       mlp=blob)
+                       mlp=blob, lanes=args.lanes)
         else:
             continue
         t = time_stream(torch, s, args.warmup, args.steps)
@@ -665,6 +667,7 @@ def main():
                                "noise 5e-3, lambda 1e-4, S=17, HIP-graph batches of "
                                f"{args.batch} frames, inputs resident in HBM",
                    "frames": args.frames, "unique_frames": U, "frames_per_step": args.batch,
+                   "lanes": args.lanes,
                    "pixels_per_frame": m * n, "channels": 3, "blurred": [[H1, W1], [H2, W2]],
                    "kernels": [k1, k2], "samples": S,
                    "launch_shapes": None if args.no_autotune else main_s_tuning,

@@ -143,13 +143,16 @@ bool col_fits(int Py, int cw, int esize) {
 }
 
 // Columns per column-pass strip: `want` (a power of two up to 16) if given,
-// else the widest strip that still leaves at least 256 strips over the
-// frame's channels; either way narrowed until the strip fits.
+// else the widest strip of a 512-thread workgroup (two per CU) that still
+// leaves at least 256 strips over the frame's channels; either way narrowed
+// until the strip fits.
 int choose_cw(int Py, int hx, int nch, int esize, int want) {
-  int cw = want > 0 ? want : 16;
+  int cw = want > 0 ? want : 8;
   if (cw > 16) cw = 16;
   while (cw & (cw - 1)) cw &= cw - 1;
-  while (cw > 1 && (!col_fits(Py, cw, esize) || (want <= 0 && (int64_t)((hx + cw - 1) / cw) * nch < 256)))
+  while (cw > 1 && (!col_fits(Py, cw, esize) ||
+                    (want <= 0 && (col_threads(Py, cw, esize) != 512 ||
+                                   (int64_t)((hx + cw - 1) / cw) * nch < 256))))
     cw >>= 1;
   return cw;
 }

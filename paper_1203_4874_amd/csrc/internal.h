@@ -307,6 +307,7 @@ hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t 
 size_t row_lds_bytes(int N, int esize);
 size_t col_lds_bytes(int N, int cw, int esize);
 int col_max_strip_elems(int esize);   // largest cw * Py the column pass holds
+int col_threads(int N, int cw, int esize);   // column-pass workgroup size for a strip
 void set_recover_attrs();
 void set_fft_attrs();
 
