@@ -134,9 +134,8 @@ struct tuning {
   int fft_order;   // radix pass order of the row and column FFTs
 };
 constexpr tuning kDefaultTuning = {128, 0, 0, 0};
+constexpr int kRowWgPerCu = 4;   // resident row-pass workgroups per CU (LDS: a row and a twiddle table of 2048 entries)
 
-// Columns per column-pass strip: a power of two (the kernel splits indices
-// with shifts), at most 8.
 // Does a strip of cw columns of length Py fit the column pass?
 bool col_fits(int Py, int cw, int esize) {
   return col_lds_bytes(Py, cw, esize) <= kLdsLimit - 4096 && (int64_t)cw * Py <= col_max_strip_elems(esize);
@@ -575,7 +574,10 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
       for (int i = 0; i < cnt; ++i) sq[i + 1] = sq[i] + queue_items(q, bb->plans[f0 + i]);
       cv.items[q] = sq[cnt];
       const bool streaming = q != Q_SAMPLE && q != Q_FINALIZE && q != Q_DIAG && q != Q_GRAMM;
-      cv.grid[q] = grid_for(cv.items[q], streaming ? cap : 0);
+      // the row passes always run a persistent grid (their workgroups load
+      // the next rows while transforming the current ones)
+      const bool row = q == Q_ROW_FWD || q == Q_ROW_INV;
+      cv.grid[q] = grid_for(cv.items[q], row ? (cap > 0 ? cap : kRowWgPerCu * kComputeUnits) : streaming ? cap : 0);
     }
     cv.maxN = cv.maxS = cv.maxPx = cv.maxPy = cv.maxcw = cv.maxStride = 1;
     cv.gram_fmt = gram_format(o->precision);

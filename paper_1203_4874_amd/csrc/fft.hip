@@ -27,159 +27,12 @@ namespace cbp {
 
 namespace {
 
-// The split twiddle tables of an N-point transform (fft_core.h tw_split) into
-// LDS: lo[i] = w_N^i, i < 64, and hi[j] = w_N^{64 j}, j < ceil(N / 64), each an
-// FP64 sincospi rounded once to T.  The passes read them from LDS instead of
-// a table in global memory.
-template <typename T>
-__device__ inline tw_split<T> split_twiddles(cplx<T>* lo, cplx<T>* hi, int N) {
-  const int nhi = (N + 63) >> 6;
-  for (int t = threadIdx.x; t < 64 + nhi; t += blockDim.x) {
-    const int e = t < 64 ? t : 64 * (t - 64);
-    double sn, cs;
-    sincospi(-2.0 * (double)e / (double)N, &sn, &cs);
-    (t < 64 ? lo[t] : hi[t - 64]) = {T(cs), T(sn)};
-  }
-  return tw_split<T>{lo, hi};
-}
-
-// Run all passes of plan p on nbatch transforms (stride bstride) held in a;
-// b is the ping-pong partner.  Returns the buffer holding the result.
-template <int DIR, typename T, typename Tab>
-__device__ __attribute__((always_inline)) inline cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, const fft_plan& p, const Tab& tw, int nbatch,
-                                   int bstride) {
-  cplx<T>* src = a;
-  cplx<T>* dst = b;
-  int Ns = 1;
-  for (int s = 0; s < p.npass; ++s) {
-    const int R = plan_radix(p, s);
-    fft_pass<DIR>(src, dst, p.N, R, Ns, tw, nbatch, bstride, threadIdx.x, blockDim.x);
-    __syncthreads();
-    cplx<T>* t = src;
-    src = dst;
-    dst = t;
-    Ns *= R;
-  }
-  return src;
-}
-
-// ---------------------------------------------------------------- pass 1
-// Items: (row y, channel).  With with_ey, the unit-circle evaluation of both
-// rows (fold modulo S and S-point DFT, as k_eval_rows: the same lanes, the
-// same order, hence the same bits) is taken from the row in LDS; waves 0-3
-// fold (frame, residue parity) = (w & 1, w >> 1).
-template <typename T>
-// Workgroups [0, gr) run the row pass; the rest run the column evaluation
-// (its scratch carved from the dynamic LDS).
-__global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int gr) {
-  extern __shared__ __attribute__((aligned(16))) char sm_rf[];
-  __shared__ cplx<T> twl[64], twh[CBP_MAX_FFT_F32 / 64];
-  __shared__ double gy[2][CBP_MAX_S];
-  __shared__ double fpart_l[2][64];
-  __shared__ c64 twS[CBP_MAX_S];
-  if ((int)blockIdx.x >= gr) {
-    double(*F)[16] = (double(*)[16])sm_rf;
-    c64* twe = (c64*)(sm_rf + (size_t)CBP_MAX_S * 16 * sizeof(double));
-    for_items_part<Q_EVAL_COLS>(br, (int)blockIdx.x - gr, (int)gridDim.x - gr,
-                                [&](const frame_desc& d, int item) __attribute__((always_inline)) {
-                                  eval_cols_item(d, item, F, twe);
-                                });
-    return;
-  }
-  for_items_part<Q_ROW_FWD>(br, (int)blockIdx.x, gr, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
-    const fft_plan& px = d.fx;
-    const int N = px.N, hx = d.hx;
-    cplx<T>* a = (cplx<T>*)sm_rf;
-    cplx<T>* b = a + N;
-    const tw_split<T> tw = split_twiddles(twl, twh, N);
-    const int y = item % d.Hmax, ch = item / d.Hmax;
-    // row pointers clamped to each frame's last row (rows past it read as zero)
-    const T* r1 = (const T*)d.b1 + ch * d.cs1 + (int64_t)min(y, d.H1 - 1) * d.p1;
-    const T* r2 = (const T*)d.b2 + ch * d.cs2 + (int64_t)min(y, d.H2 - 1) * d.p2;
-    const bool in1 = y < d.H1, in2 = y < d.H2;
-    if (with_ey)
-      for (int t = threadIdx.x; t < d.S; t += blockDim.x) {
-        double sn, cs;
-        sincospi(-2.0 * (double)t / (double)d.S, &sn, &cs);
-        twS[t] = {cs, sn};
-      }
-    // eight loads per frame and thread in flight, from clamped (always valid)
-    // addresses; entries outside the frame are zeroed afterwards
-    {
-      const int W1 = d.W1, W2 = d.W2;
-      for (int x0 = 0; x0 < N; x0 += 8 * (int)blockDim.x) {
-        T uv[8], wv[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int x = x0 + t * (int)blockDim.x + (int)threadIdx.x;
-          uv[t] = r1[min(x, W1 - 1)];
-          wv[t] = r2[min(x, W2 - 1)];
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int x = x0 + t * (int)blockDim.x + (int)threadIdx.x;
-          if (x < N) a[x] = {(in1 && x < W1) ? uv[t] : T(0), (in2 && x < W2) ? wv[t] : T(0)};
-        }
-      }
-    }
-    __syncthreads();
-    if (with_ey) {
-      // the row evaluation of both rows (k_eval_rows's lanes and order):
-      // wave fr folds frame fr's row into partials, lane g S + r summing
-      // x = r + S (g + G i); the residues then add their G partials in order
-      const int S = d.S, G = 64 / S;
-      const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-      const int gl = l / S, r = l - gl * S;
-      if (wv < 2) {
-        const int W = wv ? d.W2 : d.W1;
-        double acc = 0.0;
-        if ((wv ? in2 : in1) && gl < G)
-          for (int x = r + S * gl; x < W; x += S * G) acc += (double)(wv ? a[x].im : a[x].re);
-        fpart_l[wv][l] = acc;
-      }
-      __syncthreads();
-      if (wv < 2 && l < S) {
-        double sr = fpart_l[wv][l];
-        for (int q = 1; q < G; ++q) sr += fpart_l[wv][q * S + l];
-        gy[wv][l] = sr;
-      }
-      __syncthreads();
-      if (wv < 2 && l < S && (wv ? in2 : in1)) {
-        const int fr = wv;
-        c64 e = {0.0, 0.0};
-        int t = 0;
-        for (int rr = 0; rr < S; ++rr) {
-          const double f = gy[fr][rr];
-          e.re += f * twS[t].re;
-          e.im += f * twS[t].im;
-          t += l;
-          if (t >= S) t -= S;
-        }
-        d.ey[((size_t)(2 * ch + fr) * S + l) * d.Hmax + y] = e;
-      }
-    }
-    const cplx<T>* z = fft_lds<-1>(a, b, px, tw, 1, N);
-    cplx<T>* o1 = (cplx<T>*)d.t1 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
-    cplx<T>* o2 = (cplx<T>*)d.t2 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
-    for (int k = threadIdx.x; k < hx; k += blockDim.x) {
-      const cplx<T> zk = z[k];
-      const cplx<T> zn = conj(z[k == 0 ? 0 : N - k]);
-      const cplx<T> s = zk + zn, df = zk - zn;
-      if (in1) o1[k] = {T(0.5) * s.re, T(0.5) * s.im};       // (Z_k + conj Z_{N-k}) / 2
-      if (in2) o2[k] = {T(0.5) * df.im, T(-0.5) * df.re};    // (Z_k - conj Z_{N-k}) / (2i)
-    }
-  });
-}
-
-// ---------------------------------------------------------------- pass 2
-// The column pass keeps one strip of cw columns (cw up to 16: up to 128-byte
-// row segments of T) in LDS, column-major with an odd leading dimension, and
-// transforms it in place: every pass reads its butterflies' inputs into
-// registers, synchronises, and writes the outputs over them.  One buffer per
-// strip instead of two frames' ping-pong pairs is what makes wide strips fit;
-// frame 2's spectrum waits in registers while frame 1 is transformed.  The
-// workgroup has NT = 512 or 1024 threads; the twiddles w_N^t are a full
-// N-entry table in LDS (one read per twiddle).
+// ---------------------------------------------------------------- in-place passes
+// The transforms run in place in LDS: every pass reads its butterflies'
+// inputs into registers, synchronises, and writes the outputs over them (one
+// buffer instead of a ping-pong pair).  Twiddles w_N^t come from a full
+// N-entry table in LDS, FP64 sincospi rounded once to T (one read per
+// twiddle).
 
 // threadIdx.x behind an empty asm statement: values derived from it are
 // recomputed where they are used instead of being hoisted out of the item
@@ -190,24 +43,32 @@ __device__ __attribute__((always_inline)) inline int local_tid() {
   return t;
 }
 
-// Largest cw * N of a strip: 9.5 FP32 (4.75 FP64) complex entries per
-// thread, so each thread's share of a pass and of the stashed spectrum stays
-// in registers.
-template <typename T, int NT>
-constexpr int col_max_elems() { return NT * 76 / (int)sizeof(cplx<T>); }
+// Butterflies per thread of a radix-R pass over at most MAXE entries.
+template <int NT, int R, int MAXE>
+constexpr int ip_mb() { return (MAXE / R + NT - 1) / NT; }
 
-// Butterflies per thread of a radix-R pass over the largest strip.
-template <typename T, int NT, int R>
-constexpr int col_mb() { return (col_max_elems<T, NT>() / R + NT - 1) / NT; }
+// w_N^t, t < N, into tw when the table holds another length (tabN: the
+// length it holds, wave-uniform); the caller synchronises before use.
+template <typename T>
+__device__ __attribute__((always_inline)) inline void full_twiddles(cplx<T>* tw, int N, int& tabN) {
+  if (tabN == N) return;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    double sn, cs;
+    sincospi(-2.0 * (double)t / (double)N, &sn, &cs);
+    tw[t] = {T(cs), T(sn)};
+  }
+  tabN = N;
+}
 
-// One radix-R pass (stride Ns) over ncol columns of length N at buf + c ld,
-// in place: butterfly j of column c reads buf[c ld + j + r N/R] and writes
-// buf[c ld + (j - k) R + k + r Ns], k = j mod Ns (the Stockham indexing of
-// fft_core.h, read and write phases separated by a barrier).
-template <int R, int DIR, int NT, typename T>
-__device__ __attribute__((always_inline)) inline void col_pass(cplx<T>* buf, int ld, int N, int Ns,
-                                                               const cplx<T>* tw, int ncol) {
-  constexpr int MB = col_mb<T, NT, R>();
+// One radix-R pass (stride Ns) over ncol transforms of length N at
+// buf + c ld, in place: butterfly j of transform c reads
+// buf[c ld + j + r N/R] and writes buf[c ld + (j - k) R + k + r Ns],
+// k = j mod Ns (the Stockham indexing of fft_core.h, read and write phases
+// separated by a barrier).  ncol N <= MAXE.
+template <int R, int DIR, int NT, int MAXE, typename T>
+__device__ __attribute__((always_inline)) inline void ip_pass(cplx<T>* buf, int ld, int N, int Ns,
+                                                              const cplx<T>* tw, int ncol) {
+  constexpr int MB = ip_mb<NT, R, MAXE>();
   const int NR = N / R;
   const int total = NR * ncol;
   const int twstep = N / (Ns * R);
@@ -220,23 +81,13 @@ __device__ __attribute__((always_inline)) inline void col_pass(cplx<T>* buf, int
     const int b = tid + q * NT;
     pos[q] = -1;
     if (b < total) {
-      const int c = fdiv_floor(b, rnr);
+      const int c = ncol == 1 ? 0 : fdiv_floor(b, rnr);
       const int j = b - mul24(c, NR);
       const int k = j - mul24(fdiv_floor(j, rns), Ns);
-      const cplx<T>* src = buf + mul24(c, ld) + j;
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = src[mul24(r, NR)];
-      if (Ns > 1) {
-        const int step = mul24(k, twstep);
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          cplx<T> w = tw[mul24(r, step)];
-          if (DIR > 0) w.im = -w.im;
-          v[q][r] = v[q][r] * w;
-        }
-      }
-      dft_small<R, DIR>(v[q]);
-      pos[q] = mul24(c, ld) + mul24(j - k, R) + k;
+      const cplx<T>* src = buf + mul24(c, ld);
+      const int base = Ns > 1 ? stockham_read<R, DIR, true>(src, NR, twstep, tw, j, k, v[q])
+                              : stockham_read<R, DIR, false>(src, NR, twstep, tw, j, k, v[q]);
+      pos[q] = mul24(c, ld) + base;
     }
   }
   __syncthreads();
@@ -249,23 +100,195 @@ __device__ __attribute__((always_inline)) inline void col_pass(cplx<T>* buf, int
   __syncthreads();
 }
 
-template <int DIR, int NT, typename T>
-__device__ __attribute__((always_inline)) inline void col_fft(cplx<T>* buf, int ld, const fft_plan& p,
-                                                              const cplx<T>* tw, int ncol) {
+// All passes of plan p over ncol transforms (ncol p.N <= MAXE), in place.
+template <int DIR, int NT, int MAXE, typename T>
+__device__ __attribute__((always_inline)) inline void ip_fft(cplx<T>* buf, int ld, const fft_plan& p,
+                                                             const cplx<T>* tw, int ncol) {
   int Ns = 1;
   for (int s = 0; s < p.npass; ++s) {
     const int R = plan_radix(p, s);
     switch (R) {
-      case 2: col_pass<2, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
-      case 3: col_pass<3, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
-      case 4: col_pass<4, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
-      case 5: col_pass<5, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
-      case 7: col_pass<7, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
-      default: col_pass<8, DIR, NT>(buf, ld, p.N, Ns, tw, ncol); break;
+      case 2: ip_pass<2, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
+      case 3: ip_pass<3, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
+      case 4: ip_pass<4, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
+      case 5: ip_pass<5, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
+      case 7: ip_pass<7, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
+      default: ip_pass<8, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
     }
     Ns *= R;
   }
 }
+
+// Largest row length (entries) of the row passes.
+constexpr int ROW_MAXE = CBP_MAX_FFT_F32 > CBP_MAX_FFT_F64 ? CBP_MAX_FFT_F32 : CBP_MAX_FFT_F64;
+
+// ---------------------------------------------------------------- pass 1
+// Items: (row y, channel).  With with_ey, the unit-circle evaluation of both
+// rows (fold modulo S and S-point DFT, as k_eval_rows: the same lanes, the
+// same order, hence the same bits) is taken from the row in LDS; waves 0-3
+// fold (frame, residue parity) = (w & 1, w >> 1).
+// Workgroups [0, gr) run the row pass; the rest run the column evaluation
+// (its scratch carved from the dynamic LDS).  A row-pass workgroup that owns
+// several items loads the next item's rows into registers while it
+// transforms the current one.
+static_assert(CBP_MAX_FFT_F32 <= 8 * 256 && CBP_MAX_FFT_F64 <= 8 * 256, "one row is eight loads per thread");
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int gr) {
+  extern __shared__ __attribute__((aligned(16))) char sm_rf[];
+  __shared__ double gy[2][CBP_MAX_S];
+  __shared__ double fpart_l[2][64];
+  __shared__ c64 twS[CBP_MAX_S];
+  __shared__ int st[BATCH_CHUNK + 1];
+  if ((int)blockIdx.x >= gr) {
+    double(*F)[16] = (double(*)[16])sm_rf;
+    c64* twe = (c64*)(sm_rf + (size_t)CBP_MAX_S * 16 * sizeof(double));
+    for_items_part<Q_EVAL_COLS>(br, (int)blockIdx.x - gr, (int)gridDim.x - gr,
+                                [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+                                  eval_cols_item(d, item, F, twe);
+                                });
+    return;
+  }
+  const int nf = br.nframes;
+  const int* sq = br.starts + (size_t)Q_ROW_FWD * (nf + 1);
+  for (int t = threadIdx.x; t <= nf; t += blockDim.x) st[t] = sq[t];
+  __syncthreads();
+  int first, end, step;
+  xcd_items(__builtin_amdgcn_readfirstlane(st[nf]), (int)blockIdx.x, gr, first, end, step);
+  // frame of item it (st[fi] <= it < st[fi + 1]), wave-uniform
+  auto frame_of = [&](int it) __attribute__((always_inline)) {
+    int lo = 0, hi = nf;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (st[mid] <= it) lo = mid;
+      else hi = mid;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+  };
+  // descriptors are read-only while kernels run: reading them through the
+  // constant address space with a wave-uniform index lets the scalar unit
+  // load them into SGPRs
+  auto desc = [&](int fi) __attribute__((always_inline)) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) frame_desc cdesc;
+    return ((const cdesc*)br.descs)[fi];
+#else
+    return br.descs[fi];
+#endif
+  };
+  // the two rows of item it into registers: eight loads per frame and
+  // thread, from clamped (always valid) addresses; entries outside the frame
+  // are zeroed when they are stored to LDS
+  T uv[8], wv[8];
+  auto fetch = [&](int it) __attribute__((always_inline)) {
+    const int fi = frame_of(it);
+    const frame_desc d = desc(fi);
+    const int item = it - __builtin_amdgcn_readfirstlane(st[fi]);
+    const int y = item % d.Hmax, ch = item / d.Hmax;
+    // row pointers clamped to each frame's last row (rows past it read as zero)
+    const T* r1 = (const T*)d.b1 + ch * d.cs1 + (int64_t)min(y, d.H1 - 1) * d.p1;
+    const T* r2 = (const T*)d.b2 + ch * d.cs2 + (int64_t)min(y, d.H2 - 1) * d.p2;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int x = t * 256 + (int)threadIdx.x;
+      uv[t] = r1[min(x, d.W1 - 1)];
+      wv[t] = r2[min(x, d.W2 - 1)];
+    }
+  };
+  if (first < end) fetch(first);
+  int tabN = 0;   // length of the twiddle table in LDS
+  for (int it = first; it < end; it += step) {
+    const int fi = frame_of(it);
+    const frame_desc d = desc(fi);
+    const int item = it - __builtin_amdgcn_readfirstlane(st[fi]);
+    const fft_plan& px = d.fx;
+    const int N = px.N, hx = d.hx;
+    cplx<T>* a = (cplx<T>*)sm_rf;
+    cplx<T>* twf = a + N;
+    full_twiddles(twf, N, tabN);
+    const int y = item % d.Hmax, ch = item / d.Hmax;
+    const bool in1 = y < d.H1, in2 = y < d.H2;
+    if (with_ey)
+      for (int t = threadIdx.x; t < d.S; t += blockDim.x) {
+        double sn, cs;
+        sincospi(-2.0 * (double)t / (double)d.S, &sn, &cs);
+        twS[t] = {cs, sn};
+      }
+    {
+      const int W1 = d.W1, W2 = d.W2;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int x = t * 256 + (int)threadIdx.x;
+        if (x < N) a[x] = {(in1 && x < W1) ? uv[t] : T(0), (in2 && x < W2) ? wv[t] : T(0)};
+      }
+    }
+    __syncthreads();
+    // the next item's rows are in flight while this one is transformed
+    if (it + step < end) fetch(it + step);
+    if (with_ey) {
+      // the row evaluation of both rows (k_eval_rows's lanes and order):
+      // wave fr folds frame fr's row into partials, lane g S + r summing
+      // x = r + S (g + G i); the residues then add their G partials in order
+      const int S = d.S, G = 64 / S;
+      const int wvi = threadIdx.x >> 6, l = threadIdx.x & 63;
+      const int gl = l / S, r = l - gl * S;
+      if (wvi < 2) {
+        const int W = wvi ? d.W2 : d.W1;
+        double acc = 0.0;
+        if ((wvi ? in2 : in1) && gl < G)
+          for (int x = r + S * gl; x < W; x += S * G) acc += (double)(wvi ? a[x].im : a[x].re);
+        fpart_l[wvi][l] = acc;
+      }
+      __syncthreads();
+      if (wvi < 2 && l < S) {
+        double sr = fpart_l[wvi][l];
+        for (int q = 1; q < G; ++q) sr += fpart_l[wvi][q * S + l];
+        gy[wvi][l] = sr;
+      }
+      __syncthreads();
+      if (wvi < 2 && l < S && (wvi ? in2 : in1)) {
+        const int fr = wvi;
+        c64 e = {0.0, 0.0};
+        int t = 0;
+        for (int rr = 0; rr < S; ++rr) {
+          const double f = gy[fr][rr];
+          e.re += f * twS[t].re;
+          e.im += f * twS[t].im;
+          t += l;
+          if (t >= S) t -= S;
+        }
+        d.ey[((size_t)(2 * ch + fr) * S + l) * d.Hmax + y] = e;
+      }
+    }
+    ip_fft<-1, 256, ROW_MAXE>(a, N, px, twf, 1);
+    const cplx<T>* z = a;
+    cplx<T>* o1 = (cplx<T>*)d.t1 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
+    cplx<T>* o2 = (cplx<T>*)d.t2 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
+    for (int k = threadIdx.x; k < hx; k += blockDim.x) {
+      const cplx<T> zk = z[k];
+      const cplx<T> zn = conj(z[k == 0 ? 0 : N - k]);
+      const cplx<T> s = zk + zn, df = zk - zn;
+      if (in1) o1[k] = {T(0.5) * s.re, T(0.5) * s.im};       // (Z_k + conj Z_{N-k}) / 2
+      if (in2) o2[k] = {T(0.5) * df.im, T(-0.5) * df.re};    // (Z_k - conj Z_{N-k}) / (2i)
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- pass 2
+// The column pass keeps one strip of cw columns (cw up to 16: up to 128-byte
+// row segments of T) in LDS, column-major with an odd leading dimension, and
+// transforms it in place.  One buffer per strip instead of two frames'
+// ping-pong pairs is what makes wide strips fit; frame 2's spectrum waits in
+// registers while frame 1 is transformed.  The workgroup has NT = 512 or 1024
+// threads.
+
+// Largest cw * N of a strip: 9.5 FP32 (4.75 FP64) complex entries per
+// thread, so each thread's share of a pass and of the stashed spectrum stays
+// in registers.
+template <typename T, int NT>
+constexpr int col_max_elems() { return NT * 76 / (int)sizeof(cplx<T>); }
+
 
 // Strip rows [0, Hf) of src (row pitch tp) into buf[c ld + y], rows [Hf, N)
 // and columns past hx as zeros.  Element e = y cw + c: cw consecutive
@@ -394,7 +417,7 @@ __global__ __launch_bounds__(NT) void k_col_filter(batch_ref br) {
     if (two) {
       col_load<NT>(buf, ld, s2, tp, H2, N, kx0, hx, lcw);
       __syncthreads();
-      col_fft<-1, NT>(buf, ld, py, tw, cw);
+      ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, tw, cw);
       for_held([&](int a, int b, int c, int y, bool pair) __attribute__((always_inline)) {
         st2[a] = buf[mul24(c, ld) + y];
         if (pair) st2[b] = buf[mul24(c, ld) + y + h];
@@ -403,7 +426,7 @@ __global__ __launch_bounds__(NT) void k_col_filter(batch_ref br) {
     }
     col_load<NT>(buf, ld, s1, tp, H1, N, kx0, hx, lcw);
     __syncthreads();
-    col_fft<-1, NT>(buf, ld, py, tw, cw);
+    ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, tw, cw);
     // filter: the combined spectrum in place of frame 1's
     const int kmax = k1 > k2 ? k1 : k2;
     auto filt = [&](cplx<T>* at, const cplx<T>& kh1, const cplx<T>& kh2, const cplx<T>& b2)
@@ -450,7 +473,7 @@ __global__ __launch_bounds__(NT) void k_col_filter(batch_ref br) {
       }
     });
     __syncthreads();
-    col_fft<+1, NT>(buf, ld, py, tw, cw);
+    ip_fft<+1, NT, col_max_elems<T, NT>()>(buf, ld, py, tw, cw);
     // the first m rows, row segments of cw columns
     cplx<T>* uo = (cplx<T>*)d.u + (int64_t)ch * m * tp;
     for (int e = threadIdx.x; e < (m << lcw); e += NT) {
@@ -463,56 +486,95 @@ __global__ __launch_bounds__(NT) void k_col_filter(batch_ref br) {
 }
 
 // ---------------------------------------------------------------- pass 3
-// Items: (pair of output rows, channel).
+// Items: (pair of output rows, channel).  A workgroup that owns several items
+// loads the next item's spectra into registers while it transforms the
+// current one.
 template <typename T>
 __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_ri[];
-  __shared__ cplx<T> twl[64], twh[CBP_MAX_FFT_F32 / 64];
-  for_items<Q_ROW_INV>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+  __shared__ int st[BATCH_CHUNK + 1];
+  const int nf = br.nframes;
+  const int* sq = br.starts + (size_t)Q_ROW_INV * (nf + 1);
+  for (int t = threadIdx.x; t <= nf; t += blockDim.x) st[t] = sq[t];
+  __syncthreads();
+  int first, end, step;
+  xcd_items(__builtin_amdgcn_readfirstlane(st[nf]), (int)blockIdx.x, (int)gridDim.x, first, end, step);
+  auto frame_of = [&](int it) __attribute__((always_inline)) {
+    int lo = 0, hi = nf;   // st[lo] <= it < st[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (st[mid] <= it) lo = mid;
+      else hi = mid;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+  };
+  auto desc = [&](int fi) __attribute__((always_inline)) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) frame_desc cdesc;
+    return ((const cdesc*)br.descs)[fi];
+#else
+    return br.descs[fi];
+#endif
+  };
+  // the spectra of item it's two rows into registers: entry k < hx read
+  // directly, k >= hx as the conjugate of entry N - k (< hx); indices past N
+  // clamp to 0 and are discarded
+  cplx<T> Av[8], Bv[8];
+  auto fetch = [&](int it) __attribute__((always_inline)) {
+    const int fi = frame_of(it);
+    const frame_desc d = desc(fi);
+    const int item = it - __builtin_amdgcn_readfirstlane(st[fi]);
+    const int N = d.fx.N, hx = d.hx, m = d.m;
+    const int npair = (m + 1) / 2;
+    const int ya = 2 * (item % npair), ch = item / npair;
+    const cplx<T>* ua = (const cplx<T>*)d.u + (int64_t)ch * m * d.hxp + (int64_t)ya * d.hxp;
+    const cplx<T>* ubv = ya + 1 < m ? ua + d.hxp : ua;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = t * 256 + (int)threadIdx.x;
+      const int kk = k < hx ? k : max(N - k, 0);
+      Av[t] = ua[kk];
+      Bv[t] = ubv[kk];
+    }
+  };
+  if (first < end) fetch(first);
+  int tabN = 0;   // length of the twiddle table in LDS
+  for (int it = first; it < end; it += step) {
+    const int fi = frame_of(it);
+    const frame_desc d = desc(fi);
+    const int item = it - __builtin_amdgcn_readfirstlane(st[fi]);
     const fft_plan& px = d.fx;
     const int N = px.N, hx = d.hx, m = d.m, n = d.n;
     const T scale = (T)(1.0 / ((double)d.Py * (double)d.Px));
     cplx<T>* a = (cplx<T>*)sm_ri;
-    cplx<T>* b = a + N;
-    const tw_split<T> tw = split_twiddles(twl, twh, N);
+    cplx<T>* twf = a + N;
+    full_twiddles(twf, N, tabN);
     const int npair = (m + 1) / 2;
     const int ya = 2 * (item % npair), yb = ya + 1, ch = item / npair;
-    const cplx<T>* ua = (const cplx<T>*)d.u + (int64_t)ch * m * d.hxp + (int64_t)ya * d.hxp;
-    const cplx<T>* ub = ua + d.hxp;
     const bool hb = yb < m;
-    // eight index pairs per thread in flight: entry k < hx read directly,
-    // k >= hx as the conjugate of entry N - k (< hx); indices past N clamp
-    // to 0 and are discarded
-    const cplx<T>* ubv = hb ? ub : ua;
-    for (int k0 = 0; k0 < N; k0 += 8 * (int)blockDim.x) {
-      cplx<T> Av[8], Bv[8];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int k = k0 + t * (int)blockDim.x + (int)threadIdx.x;
-        const int kk = k < hx ? k : max(N - k, 0);
-        Av[t] = ua[kk];
-        Bv[t] = ubv[kk];
-      }
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int k = k0 + t * (int)blockDim.x + (int)threadIdx.x;
-        if (k < N) {
-          cplx<T> A = Av[t], B = hb ? Bv[t] : cplx<T>{T(0), T(0)};
-          if (k >= hx) { A = conj(A); B = conj(B); }
-          if ((k == 0) || (2 * k == N)) { A.im = T(0); B.im = T(0); }
-          a[k] = {A.re - B.im, A.im + B.re};   // A + i B
-        }
+    for (int t = 0; t < 8; ++t) {
+      const int k = t * 256 + (int)threadIdx.x;
+      if (k < N) {
+        cplx<T> A = Av[t], B = hb ? Bv[t] : cplx<T>{T(0), T(0)};
+        if (k >= hx) { A = conj(A); B = conj(B); }
+        if ((k == 0) || (2 * k == N)) { A.im = T(0); B.im = T(0); }
+        a[k] = {A.re - B.im, A.im + B.re};   // A + i B
       }
     }
     __syncthreads();
-    const cplx<T>* z = fft_lds<+1>(a, b, px, tw, 1, N);
+    // the next item's spectra are in flight while this one is transformed
+    if (it + step < end) fetch(it + step);
+    ip_fft<+1, 256, ROW_MAXE>(a, N, px, twf, 1);
+    const cplx<T>* z = a;
     T* oa = (T*)d.out + ch * d.ocs + (int64_t)ya * d.opitch;
     T* ob = oa + d.opitch;
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
       oa[x] = z[x].re * scale;
       if (hb) ob[x] = z[x].im * scale;
     }
-  });
+    __syncthreads();
+  }
 }
 
 }  // namespace

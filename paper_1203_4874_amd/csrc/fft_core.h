@@ -11,8 +11,8 @@
 //
 // DIR = -1 computes X[m] = sum_t x[t] exp(-2 pi i m t / N) (forward),
 // DIR = +1 the same with +i (unnormalised inverse).  Twiddles tw[t] =
-// exp(-2 pi i t / N), t in [0, N), come from any table type with
-// operator[]: a full table, or tw_split's two short tables.
+// exp(-2 pi i t / N), t in [0, N), come from a table (any type with
+// operator[]).
 //
 // Everything here is host+device so the same butterfly code can be checked
 // on the CPU.
@@ -130,29 +130,19 @@ CBP_HD int mul24(int a, int b) {
 #endif
 }
 
-// w_N^t = lo[t mod 64] hi[t div 64] with lo[i] = w_N^i (i < 64) and
-// hi[j] = w_N^{64 j} (j < ceil(N / 64)): two short tables (96 entries for
-// N <= 2048) instead of N entries, one complex product per twiddle (within a
-// few units in the last place of the directly rounded value).
-template <typename T>
-struct tw_split {
-  const cplx<T>* lo;
-  const cplx<T>* hi;
-  CBP_HD cplx<T> operator[](int t) const { return lo[t & 63] * hi[t >> 6]; }
-};
-
-// Butterfly j of a pass with k = j mod Ns given: reads src[j + r N/R],
-// twiddles the inputs by w^(r k N/(Ns R)) (TW: Ns > 1), writes
-// dst[(j - k) R + k + r Ns].
+// Butterfly j of a radix-R pass with stride Ns (the product of the radices
+// already applied) of an N-point transform at src, k = j mod Ns given: reads
+// src[j + r N/R] into v, twiddles input r by w^(r k twstep) (TW: Ns > 1;
+// twstep = N / (Ns R)), applies the R-point DFT and returns the base
+// (j - k) R + k of its outputs, which belong at base + r Ns.  The kernels run
+// a pass in place: every butterfly is read before any output is written.
 template <int R, int DIR, bool TW, typename T, typename Tab>
-CBP_HD void stockham_bfly(const cplx<T>* src, cplx<T>* dst, int NR, int Ns, int twstep, const Tab& tw, int j,
-                          int k) {
-  cplx<T> v[R];
+CBP_HD int stockham_read(const cplx<T>* src, int NR, int twstep, const Tab& tw, int j, int k, cplx<T>* v) {
   const cplx<T>* s = src + j;
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = s[mul24(r, NR)];
   if (TW) {
-    const int step = mul24(k, twstep);  // twstep = N / (Ns * R); r * step < N
+    const int step = mul24(k, twstep);  // r * step < N
 #pragma unroll
     for (int r = 1; r < R; ++r) {
       cplx<T> w = tw[mul24(r, step)];
@@ -161,9 +151,7 @@ CBP_HD void stockham_bfly(const cplx<T>* src, cplx<T>* dst, int NR, int Ns, int 
     }
   }
   dft_small<R, DIR>(v);
-  cplx<T>* o = dst + mul24(j - k, R) + k;
-#pragma unroll
-  for (int r = 0; r < R; ++r) o[mul24(r, Ns)] = v[r];
+  return mul24(j - k, R) + k;
 }
 
 // q = floor(a / b) for 0 <= a < 2^22, 1 <= b <= 2^22, from a float
@@ -208,49 +196,6 @@ inline bool make_fft_plan(int N, fft_plan* p, int order = 0) {
     }
   }
   return r == 1;
-}
-
-// One pass of radix R over `nbatch` transforms stored at src + f*bstride
-// (f < nbatch), butterflies distributed over threads tid, tid+nthr, ...  The
-// caller synchronises between passes.
-template <int R, int DIR, bool TW, typename T, typename Tab>
-CBP_HD void fft_pass_rt(const cplx<T>* src, cplx<T>* dst, int N, int Ns, const Tab& tw, int nbatch, int bstride,
-                        int tid, int nthr) {
-  const int nb = N / R;
-  const int total = nb * nbatch;
-  const int twstep = N / (Ns * R);
-  const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns;
-  for (int t = tid; t < total; t += nthr) {
-    const int f = nbatch == 1 ? 0 : fdiv_floor(t, rnb);
-    const int j = t - mul24(f, nb);
-    const int k = TW ? j - mul24(fdiv_floor(j, rns), Ns) : 0;
-    const int off = mul24(f, bstride);
-    stockham_bfly<R, DIR, TW>(src + off, dst + off, nb, Ns, twstep, tw, j, k);
-  }
-}
-
-// One pass of radix R over `nbatch` transforms stored at src + f*bstride
-// (f < nbatch), butterflies distributed over threads tid, tid+nthr, ...  The
-// caller synchronises between passes.  The first pass (Ns = 1) has no
-// twiddles.
-template <int R, int DIR, typename T, typename Tab>
-CBP_HD void fft_pass_r(const cplx<T>* src, cplx<T>* dst, int N, int Ns, const Tab& tw, int nbatch, int bstride,
-                       int tid, int nthr) {
-  if (Ns == 1) fft_pass_rt<R, DIR, false>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr);
-  else fft_pass_rt<R, DIR, true>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr);
-}
-
-template <int DIR, typename T, typename Tab>
-CBP_HD void fft_pass(const cplx<T>* src, cplx<T>* dst, int N, int R, int Ns, const Tab& tw,
-                     int nbatch, int bstride, int tid, int nthr) {
-  switch (R) {
-    case 2: fft_pass_r<2, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
-    case 3: fft_pass_r<3, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
-    case 4: fft_pass_r<4, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
-    case 5: fft_pass_r<5, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
-    case 7: fft_pass_r<7, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
-    default: fft_pass_r<8, DIR>(src, dst, N, Ns, tw, nbatch, bstride, tid, nthr); break;
-  }
 }
 
 }  // namespace cbp

@@ -1,9 +1,9 @@
-// Host driver for the library's Stockham FFT passes (csrc/fft_core.h):
-// reads "N dir order split" then N complex values (re im) from stdin, runs
-// every pass of the plan sequentially on the CPU (twiddles from the full table,
-// or with split = 1 from tw_split's two short tables) and prints the
-// transform.  Used by tests/test_fft_host.py to check the butterflies against
-// numpy.fft.
+// Host driver for the library's Stockham butterflies (csrc/fft_core.h):
+// reads "N dir order" then N complex values (re im) from stdin and runs every
+// pass of the plan on the CPU the way the kernels do, in place: each pass
+// reads all of its butterflies (stockham_read, with k = j mod Ns split by the
+// kernels' FP32 reciprocal) before writing their outputs over the input.
+// Prints the transform; tests/test_fft_host.py checks it against numpy.fft.
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -12,44 +12,53 @@
 
 using namespace cbp;
 
+template <int R, int DIR>
+void pass(std::vector<cplx<double>>& buf, int N, int Ns, const cplx<double>* tw) {
+  const int NR = N / R, twstep = N / (Ns * R);
+  const float rns = 1.0f / (float)Ns;
+  std::vector<cplx<double>> out(N);
+  std::vector<int> base(NR);
+  std::vector<cplx<double>> v((size_t)NR * R);
+  for (int j = 0; j < NR; ++j) {
+    const int k = j - fdiv_floor(j, rns) * Ns;
+    base[j] = Ns > 1 ? stockham_read<R, DIR, true>(buf.data(), NR, twstep, tw, j, k, &v[(size_t)j * R])
+                     : stockham_read<R, DIR, false>(buf.data(), NR, twstep, tw, j, k, &v[(size_t)j * R]);
+  }
+  for (int j = 0; j < NR; ++j)
+    for (int r = 0; r < R; ++r) buf[base[j] + r * Ns] = v[(size_t)j * R + r];
+}
+
+template <int DIR>
+void run_pass(int R, std::vector<cplx<double>>& buf, int N, int Ns, const cplx<double>* tw) {
+  switch (R) {
+    case 2: pass<2, DIR>(buf, N, Ns, tw); break;
+    case 3: pass<3, DIR>(buf, N, Ns, tw); break;
+    case 4: pass<4, DIR>(buf, N, Ns, tw); break;
+    case 5: pass<5, DIR>(buf, N, Ns, tw); break;
+    case 7: pass<7, DIR>(buf, N, Ns, tw); break;
+    default: pass<8, DIR>(buf, N, Ns, tw); break;
+  }
+}
+
 int main() {
-  int N, dir, order, split;
-  if (std::scanf("%d %d %d %d", &N, &dir, &order, &split) != 4) return 2;
+  int N, dir, order;
+  if (std::scanf("%d %d %d", &N, &dir, &order) != 3) return 2;
   fft_plan p;
   if (!make_fft_plan(N, &p, order)) { std::printf("BADPLAN\n"); return 3; }
-  std::vector<cplx<double>> a(N), b(N), tw(N);
+  std::vector<cplx<double>> a(N), tw(N);
   for (int i = 0; i < N; ++i)
     if (std::scanf("%lf %lf", &a[i].re, &a[i].im) != 2) return 2;
   for (int t = 0; t < N; ++t) {
     const double ang = -2.0 * M_PI * (double)t / (double)N;
     tw[t] = {std::cos(ang), std::sin(ang)};
   }
-  std::vector<cplx<double>> lo(64), hi((N + 63) / 64);
-  for (int i = 0; i < 64; ++i) {
-    const double ang = -2.0 * M_PI * (double)i / (double)N;
-    lo[i] = {std::cos(ang), std::sin(ang)};
-  }
-  for (int j = 0; j < (int)hi.size(); ++j) {
-    const double ang = -2.0 * M_PI * (double)(64 * j) / (double)N;
-    hi[j] = {std::cos(ang), std::sin(ang)};
-  }
-  const tw_split<double> ts{lo.data(), hi.data()};
-  const cplx<double>* full = tw.data();
-  cplx<double>* src = a.data();
-  cplx<double>* dst = b.data();
   int Ns = 1;
   for (int s = 0; s < p.npass; ++s) {
     const int R = plan_radix(p, s);
-    if (split) {
-      if (dir < 0) fft_pass<-1>(src, dst, N, R, Ns, ts, 1, N, 0, 1);
-      else fft_pass<+1>(src, dst, N, R, Ns, ts, 1, N, 0, 1);
-    } else {
-      if (dir < 0) fft_pass<-1>(src, dst, N, R, Ns, full, 1, N, 0, 1);
-      else fft_pass<+1>(src, dst, N, R, Ns, full, 1, N, 0, 1);
-    }
+    if (dir < 0) run_pass<-1>(R, a, N, Ns, tw.data());
+    else run_pass<+1>(R, a, N, Ns, tw.data());
     Ns *= R;
-    cplx<double>* t = src; src = dst; dst = t;
   }
-  for (int i = 0; i < N; ++i) std::printf("%.17g %.17g\n", src[i].re, src[i].im);
+  for (int i = 0; i < N; ++i) std::printf("%.17g %.17g\n", a[i].re, a[i].im);
   return 0;
 }
