@@ -605,8 +605,12 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
       int* sq = st + (size_t)Q_COL * (cnt + 1);
       for (int i = 0; i < cnt; ++i) sq[i + 1] = sq[i] + queue_items(Q_COL, bb->plans[f0 + i]);
       cv.items[Q_COL] = sq[cnt];
-      cv.grid[Q_COL] = grid_for(cv.items[Q_COL], cap);
     }
+    // the column pass runs a persistent grid: its workgroups load the next
+    // strip while finishing the current one (two 512-thread or one
+    // 1024-thread workgroup per CU)
+    cv.grid[Q_COL] = grid_for(cv.items[Q_COL], cap > 0 ? cap : (col_threads(cv.maxPy, cv.maxcw, esize) == 512 ? 2 : 1) *
+                                                                    kComputeUnits);
     bb->chunks.push_back(cv);
   }
   return CBP_OK;

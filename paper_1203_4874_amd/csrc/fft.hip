@@ -290,33 +290,6 @@ template <typename T, int NT>
 constexpr int col_max_elems() { return NT * 76 / (int)sizeof(cplx<T>); }
 
 
-// Strip rows [0, Hf) of src (row pitch tp) into buf[c ld + y], rows [Hf, N)
-// and columns past hx as zeros.  Element e = y cw + c: cw consecutive
-// threads read one row segment; eight loads per thread in flight from
-// clamped (always valid) addresses.
-template <int NT, typename T>
-__device__ __attribute__((always_inline)) inline void col_load(cplx<T>* buf, int ld, const cplx<T>* src, int tp,
-                                                               int Hf, int N, int kx0, int hx, int lcw) {
-  const int cw = 1 << lcw;
-  const int tot = N << lcw;
-  const int tid = local_tid();
-  for (int e0 = 0; e0 < tot; e0 += 8 * NT) {
-    cplx<T> v[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = e0 + t * NT + tid;
-      const int y = e >> lcw, c = e & (cw - 1);
-      v[t] = src[(int64_t)min(y, Hf - 1) * tp + min(kx0 + c, hx - 1)];
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = e0 + t * NT + tid;
-      const int y = e >> lcw, c = e & (cw - 1);
-      if (e < tot) buf[mul24(c, ld) + y] = (y < Hf && kx0 + c < hx) ? v[t] : cplx<T>{T(0), T(0)};
-    }
-  }
-}
-
 // The strip's entries as each thread holds them for the stash and the
 // filter: column c = tid / (NT / cw) (wave-uniform: NT / cw >= 64) and, for
 // even N, row pairs (y, y + N/2), y = tid mod (NT / cw) + i NT / cw, whose
@@ -331,13 +304,70 @@ constexpr int col_slots() {
   return 2 * col_pairs<T, NT>() > col_singles<T, NT>() ? 2 * col_pairs<T, NT>() : col_singles<T, NT>();
 }
 
-// Items: (strip of cw columns, channel).
+// Items: (strip of cw columns, channel).  A workgroup that owns several
+// items loads the next strip (and frame 1's strip of the current item) into
+// registers while it transforms.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_col_filter(batch_ref br) {
+__global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_cf[];
+  __shared__ int st[BATCH_CHUNK + 1];
   constexpr int SP = col_pairs<T, NT>(), SE = col_singles<T, NT>(), SM = col_slots<T, NT>();
+  constexpr int PF = (col_max_elems<T, NT>() + NT - 1) / NT;   // strip entries per thread
   constexpr int LNT = NT == 1024 ? 10 : 9;
-  for_items<Q_COL>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+  const int nf = br.nframes;
+  const int* sq = br.starts + (size_t)Q_COL * (nf + 1);
+  for (int t = threadIdx.x; t <= nf; t += NT) st[t] = sq[t];
+  __syncthreads();
+  int first, end, step;
+  xcd_items(__builtin_amdgcn_readfirstlane(st[nf]), (int)blockIdx.x, (int)gridDim.x, first, end, step);
+  auto frame_of = [&](int it) __attribute__((always_inline)) {
+    int lo = 0, hi = nf;   // st[lo] <= it < st[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (st[mid] <= it) lo = mid;
+      else hi = mid;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+  };
+  auto desc = [&](int fi) __attribute__((always_inline)) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) frame_desc cdesc;
+    return ((const cdesc*)br.descs)[fi];
+#else
+    return br.descs[fi];
+#endif
+  };
+  // strip entries e = y cw + c (cw consecutive threads read one row
+  // segment) of frame fr of item it into registers, from clamped (always
+  // valid) addresses; rows past the frame and columns past hx are zeroed when
+  // they are stored to LDS
+  cplx<T> pre[PF];
+  auto fetch = [&](int it, int fr) __attribute__((always_inline)) {
+    const int fi = frame_of(it);
+    const frame_desc d = desc(fi);
+    const int item = it - __builtin_amdgcn_readfirstlane(st[fi]);
+    const int cw = d.cw, hx = d.hx, tp = d.hxp, lcw = __builtin_ctz(cw);
+    const int nstrip = (hx + cw - 1) / cw;
+    const int kx0 = (item % nstrip) * cw, ch = item / nstrip;
+    const int Hf = fr ? d.H2 : d.H1;
+    const cplx<T>* src = (const cplx<T>*)(fr ? d.t2 : d.t1) + ch * (int64_t)d.Hmax * tp;
+    const int tid = local_tid();
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = tid + i * NT;
+      const int y = e >> lcw, c = e & (cw - 1);
+      pre[i] = src[(int64_t)min(y, Hf - 1) * tp + min(kx0 + c, hx - 1)];
+    }
+  };
+  auto first_frame = [&](int it) __attribute__((always_inline)) {
+    return (desc(frame_of(it)).variant & VAR_DIVIDE_B1) ? 0 : 1;   // frame 2 first when both are divided
+  };
+  if (first < end) fetch(first, first_frame(first));
+  int tabN = 0;   // length of the twiddle table in LDS
+  for (int it = first; it < end; it += step) {
+    const int fi = frame_of(it);
+    const frame_desc d = desc(fi);
+    const int item = it - __builtin_amdgcn_readfirstlane(st[fi]);
     const fft_plan& py = d.fy;
     const int N = py.N, cw = d.cw, hx = d.hx, tp = d.hxp, m = d.m;
     const int ld = N | 1;
@@ -353,14 +383,18 @@ __global__ __launch_bounds__(NT) void k_col_filter(batch_ref br) {
     const int nstrip = (hx + cw - 1) / cw;
     const int kx0 = (item % nstrip) * cw, ch = item / nstrip;
     const int lcw = __builtin_ctz(cw);                // cw is a power of two
-    const int64_t tpc = (int64_t)d.Hmax * tp;
-    const cplx<T>* s1 = (const cplx<T>*)d.t1 + ch * tpc;
-    const cplx<T>* s2 = (const cplx<T>*)d.t2 + ch * tpc;
-    for (int t = threadIdx.x; t < N; t += NT) {
-      double sn, cs;
-      sincospi(-2.0 * (double)t / (double)N, &sn, &cs);
-      tw[t] = {T(cs), T(sn)};
-    }
+    const int tot = N << lcw;
+    // the registers' strip into buf[c ld + y]
+    auto spill = [&](int Hf) __attribute__((always_inline)) {
+      const int tid = local_tid();
+#pragma unroll
+      for (int i = 0; i < PF; ++i) {
+        const int e = tid + i * NT;
+        const int y = e >> lcw, c = e & (cw - 1);
+        if (e < tot) buf[mul24(c, ld) + y] = (y < Hf && kx0 + c < hx) ? pre[i] : cplx<T>{T(0), T(0)};
+      }
+    };
+    full_twiddles(tw, N, tabN);
     // kernel row DFTs at this strip's columns: kr[c][fr][yy] = sum_x K[yy][x] exp(-2 pi i kx x / Px)
     for (int e = threadIdx.x; e < cw * 2 * CBP_MAX_K; e += NT) {
       const int c = e / (2 * CBP_MAX_K), rem = e - c * 2 * CBP_MAX_K;
@@ -415,8 +449,9 @@ __global__ __launch_bounds__(NT) void k_col_filter(batch_ref br) {
     };
     cplx<T> st2[SM];
     if (two) {
-      col_load<NT>(buf, ld, s2, tp, H2, N, kx0, hx, lcw);
+      spill(H2);
       __syncthreads();
+      fetch(it, 0);   // frame 1's strip in flight while frame 2's is transformed
       ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, tw, cw);
       for_held([&](int a, int b, int c, int y, bool pair) __attribute__((always_inline)) {
         st2[a] = buf[mul24(c, ld) + y];
@@ -424,8 +459,10 @@ __global__ __launch_bounds__(NT) void k_col_filter(batch_ref br) {
       });
       __syncthreads();   // buf is refilled with frame 1
     }
-    col_load<NT>(buf, ld, s1, tp, H1, N, kx0, hx, lcw);
+    spill(H1);
     __syncthreads();
+    // the next item's first strip in flight while this one is finished
+    if (it + step < end) fetch(it + step, first_frame(it + step));
     ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, tw, cw);
     // filter: the combined spectrum in place of frame 1's
     const int kmax = k1 > k2 ? k1 : k2;
@@ -482,7 +519,7 @@ __global__ __launch_bounds__(NT) void k_col_filter(batch_ref br) {
       if (col < hx) uo[(int64_t)y * tp + col] = buf[mul24(c, ld) + y];
     }
     __syncthreads();   // the next item refills buf, kr and tw
-  });
+  }
 }
 
 // ---------------------------------------------------------------- pass 3
