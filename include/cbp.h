@@ -154,7 +154,7 @@ typedef struct cbp_options {
 #define CBP_DIAG_SAMPLE_WEAK    2  /* some per-sample Gram had no clear null direction */
 #define CBP_DIAG_SCALE_WEAK     4  /* the scale system had no clear null direction */
 #define CBP_DIAG_KERNEL_ZERO    8  /* a kernel estimate summed to ~0 before normalisation */
-#define CBP_DIAG_FALLBACK      16  /* learned form: the plain kernels were kept (the learned objective was larger or not a number) */
+#define CBP_DIAG_FALLBACK      16  /* learned form: the plain kernels were kept (a noisy frame, or the learned objective was larger or not a number) */
 #define CBP_DIAG_BAD_NETWORK   32  /* learned form: the network blob's header is not this library's (unit weights used) */
 
 /* Per-frame numerical diagnostics, written in device memory when
@@ -401,6 +401,10 @@ cbp_status cbp_last_tuning(cbp_tuning* out);
  * assembly (spectra averaged with weights wX_j, wY_i; the kernel is the
  * separable weighted fit to them with per-axis Tikhonov strength tau =
  * median of tau_j).  Unit weights and tau = 0 reduce it to the plain method.
+ * The plain kernels are returned instead (CBP_DIAG_FALLBACK) on a noisy frame
+ * -- more than half of the 2S samples with f_0 > -1, i.e. lambda_0 above
+ * 1e-10 lambda_max, where the network does not gain -- and when the plain
+ * method's per-sample objective sum_j x^H G_j x / x^H x is smaller for them.
  * Layers 1 and 2 run on the matrix cores in bfloat16 with FP32 accumulation;
  * the 2-output head, the biases, the master weights and Adam are FP32.
  *

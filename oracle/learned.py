@@ -209,14 +209,28 @@ def recover_kernels_learned(B1, B2, m: int, n: int, params, S: int = 0, full: bo
     # the plain method judges: keep its kernels when their objective is smaller
     Jp = judge_objective(K1p, K2p, f["EX"], f["EY"], S)
     Jl = judge_objective(L1, L2, f["EX"], f["EY"], S)
-    # the learned kernels are kept only when their objective is a number no
-    # larger than the plain one's
-    fallback = not (Jl <= Jp)
+    noisy = frame_is_noisy(XF, YF)
+    # the learned kernels are kept only on a frame without a noise floor and
+    # when their objective is a number no larger than the plain one's
+    fallback = noisy or not (Jl <= Jp)
     K1, K2 = (K1p, K2p) if fallback else (L1, L2)
     if not full:
         return K1, K2
-    return K1, K2, dict(plain=(K1p, K2p), learned=(L1, L2), judge=(Jp, Jl), fallback=fallback, wX=wX, wY=wY,
+    return K1, K2, dict(plain=(K1p, K2p), learned=(L1, L2), judge=(Jp, Jl), fallback=fallback, noisy=noisy,
+                        wX=wX, wY=wY,
                         tau=tau, features=(XF, YF), base=f)
+
+
+# The noise gate of the learned form (no counterpart in the paper): a frame
+# is noisy when more than half of its 2S samples have a smallest-eigenvalue
+# feature f_0 above NOISY_F0 (lambda_0 / lambda_max > 1e-10); there the
+# network does not gain on held-out pairs and the plain kernels are kept.
+NOISY_F0 = -1.0
+
+
+def frame_is_noisy(XF: np.ndarray, YF: np.ndarray) -> bool:
+    f0 = np.concatenate([np.asarray(XF)[:, 0], np.asarray(YF)[:, 0]])
+    return int(np.sum(f0 > NOISY_F0)) > f0.size // 2
 
 
 def kernel_slices(K1, K2, S: int, pass_: int, j: int) -> np.ndarray:

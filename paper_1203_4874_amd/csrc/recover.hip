@@ -728,7 +728,9 @@ __global__ __launch_bounds__(SMALL_NT) void k_finalize(batch_ref br, int plain_o
 // with x = (K2 slice, K1 slice) of the kernels at that sample (the
 // per-sample TLS residual the plain method minimises), for the plain
 // kernels (d.Kalt) and the learned ones (d.K1, d.K2); the plain ones replace
-// the learned ones when their J is smaller.  Items: one per frame.
+// the learned ones when their J is smaller, or when the frame is noisy (the
+// regime where the network does not gain).  Items: one per frame.
+constexpr float LEARNED_NOISY_F0 = -1.0f;
 __global__ __launch_bounds__(64) void k_judge(batch_ref br) {
   __shared__ c64 tw[CBP_MAX_S];
   __shared__ c64 xs[CBP_MAX_N];
@@ -778,9 +780,14 @@ __global__ __launch_bounds__(64) void k_judge(batch_ref br) {
         }
       J[set] = acc;
     }
+    // the network's weights are used only on frames without a noise floor:
+    // when more than half of the 2S samples have lambda_0 / lambda_max above
+    // 1e-10 (spectrum feature f_0 > -1) the plain kernels are kept
+    const float f0 = l < 2 * S ? d.feat[(size_t)l * 32] : -2.0f;   // sample rows (pass, j) in order
+    const bool noisy = wsum(f0 > LEARNED_NOISY_F0 ? 1.0 : 0.0) > (double)S;
     // NaN-safe: the learned kernels are kept only when their objective is a
     // number no larger than the plain one's
-    const bool fallback = !(J[1] <= J[0]);
+    const bool fallback = noisy || !(J[1] <= J[0]);
     if (fallback) {
       for (int e = l; e < k1 * k1; e += 64) d.K1[e] = d.Kalt[e];
       for (int e = l; e < k2 * k2; e += 64) d.K2[e] = d.Kalt[CBP_MAX_K * CBP_MAX_K + e];

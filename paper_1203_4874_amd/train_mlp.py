@@ -1,6 +1,6 @@
 """Train the learned form's network on pairs the method itself generates.
 
-    python -m paper_1203_4874_amd.train_mlp [--pairs 20000] [--holdout 2000] [--out DIR]
+    python -m paper_1203_4874_amd.train_mlp [--pairs 20000] [--holdout 2000] [--out DIR] [--eval-only]
 
 Data (seeded, synthetic): 256 x 256 Gaussian-sum scenes, kernel sizes k1, k2
 drawn independently from {5, 7, ..., 15} (uniform entries, sum 1, coprime),
@@ -21,8 +21,9 @@ The network (32 -> 128 -> 128 -> 2, BF16 on the matrix cores) is trained with
 the library's own forward / backward / Adam kernels on (features, (log w*,
 log tau*)).  The held-out pairs are then deblurred with and without the
 network and both kernel errors against the truth are reported (the learned
-call includes the judge that keeps the plain kernels when the plain method's
-objective prefers them).
+call includes the noise gate, which keeps the plain kernels on frames with a
+noise floor, and the judge that keeps them when the plain method's objective
+prefers them).  --eval-only redoes that comparison for the committed network.
 """
 
 from __future__ import annotations
@@ -146,6 +147,8 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_1203_4874_amd", "weights"))
+    ap.add_argument("--eval-only", action="store_true",
+                    help="skip training: compare the committed network with the plain method on the held-out pairs")
     args = ap.parse_args()
 
     # the generator processes are forked before anything touches the GPU
@@ -158,6 +161,12 @@ def main():
     dev = torch.device("cuda:0")
     P.lib()
     total = args.pairs + args.holdout
+    if args.eval_only:
+        with ex:
+            hold = list(ex.map(make_pair, range(args.pairs, total), chunksize=32))
+        blob = P.load_mlp(os.path.join(args.out, "cbp_mlp.npz"), device=dev)
+        holdout_report(P, torch, dev, hold, blob, args.out, None)
+        return
     t0 = time.time()
     Xs, Ts = [], []
     chunk = 2000
@@ -219,7 +228,13 @@ def main():
     np.savez(os.path.join(args.out, "cbp_mlp.npz"), params=params,
              note=np.array("learned-form network; packed W1, b1, W2, b2, W3, b3 (FP32)"))
 
-    # held-out comparison: plain vs learned, kernel rel-L2 against the truth
+    holdout_report(P, torch, dev, hold, blob, args.out, int(nrow))
+
+
+def holdout_report(P, torch, dev, hold, blob, out, rows_trained):
+    """Held-out comparison, plain vs learned route (noise gate and judge
+    included), kernel rel-L2 against the truth per noise level; written to
+    holdout.json."""
     plain = run_pairs(P, torch, dev, hold)
     learn = run_pairs(P, torch, dev, hold, mlp=blob)
     rows = []
@@ -229,7 +244,7 @@ def main():
         def err(K1, K2):
             return max(np.linalg.norm(K1 - p["K1"]) / np.linalg.norm(p["K1"]),
                        np.linalg.norm(K2 - p["K2"]) / np.linalg.norm(p["K2"]))
-        rows.append((p["noise"], err(a[1], a[2]), err(b[1], b[2])))
+        rows.append((p["noise"], err(a[1], a[2]), err(b[1], b[2]), 1.0 if b[0]["flags"] & 16 else 0.0))
     rows = np.array(rows)
     summary = {}
     for nz in NOISES:
@@ -237,12 +252,15 @@ def main():
         summary[str(nz)] = dict(pairs=int(sel.shape[0]), plain_median=float(np.median(sel[:, 1])),
                                 learned_median=float(np.median(sel[:, 2])),
                                 plain_mean=float(np.mean(sel[:, 1])), learned_mean=float(np.mean(sel[:, 2])),
-                                learned_better_fraction=float(np.mean(sel[:, 2] < sel[:, 1])))
-    summary["rows"] = int(nrow)
+                                learned_better_fraction=float(np.mean(sel[:, 2] < sel[:, 1])),
+                                plain_kept_fraction=float(np.mean(sel[:, 3])))
+    if rows_trained is not None:
+        summary["rows"] = rows_trained
+    summary["note"] = ("learned route = network weights, noise gate (plain kernels on frames with a noise floor) "
+                       "and judge; plain_kept_fraction = frames where the plain kernels were returned")
     print(json.dumps(summary), flush=True)
-    with open(os.path.join(args.out, "holdout.json"), "w") as fh:
+    with open(os.path.join(out, "holdout.json"), "w") as fh:
         json.dump(summary, fh, indent=1)
-
 
 if __name__ == "__main__":
     main()

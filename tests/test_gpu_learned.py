@@ -204,6 +204,8 @@ def test_learned_kernels_match_oracle(P, k1, k2, noise):
     assert abs(dg["judge"][0] - Jp) <= 1e-6 * Jp + floor and abs(dg["judge"][1] - Jl) <= 1e-3 * Jl + floor
     if abs(Jp - Jl) > 1e-3 * max(Jp, Jl) + floor:
         assert fb == info["fallback"]
+    if info["noisy"]:
+        assert fb                                  # the noise gate keeps the plain kernels
     R1, R2 = info["plain"] if fb else info["learned"]
     e = max(rel(G1.cpu().numpy(), R1), rel(G2.cpu().numpy(), R2))
     P1, P2 = info["plain"]
@@ -237,8 +239,10 @@ def test_trained_network_against_plain_on_fresh_pairs(P):
     against the truth on fresh seeded pairs of the training distribution
     (256 x 256, k in 5..15, noise 0 / 1e-3 / 1e-2), deblurred with and without
     it.  The learned call carries the plain method as judge, so its objective
-    never exceeds the plain one; the errors are reported per noise level and
-    the noiseless median must not be worse than the plain one's."""
+    never exceeds the plain one, and a noise gate that keeps the plain kernels
+    on noisy frames (where the network does not gain); the errors are
+    reported per noise level, the noiseless median must not be worse than the
+    plain one's and the noisy ones equal it."""
     import os
     from paper_1203_4874_amd import train_mlp as tm
     if not os.path.exists(P.WEIGHTS):
@@ -253,9 +257,14 @@ def test_trained_network_against_plain_on_fresh_pairs(P):
         eb = max(rel(b[1], p["K1"]), rel(b[2], p["K2"]))
         res.setdefault(p["noise"], []).append((ea, eb))
         assert b[0]["judge"][1] <= b[0]["judge"][0] or b[0]["flags"] & 16
+        if p["noise"] > 0:
+            assert b[0]["flags"] & 16                     # noisy frame: the plain kernels
     for nz, v in sorted(res.items()):
         v = np.array(v)
         print(f"noise {nz}: plain median {np.median(v[:, 0]):.3e} mean {v[:, 0].mean():.3e}; learned median "
               f"{np.median(v[:, 1]):.3e} mean {v[:, 1].mean():.3e}; learned better in {np.mean(v[:, 1] < v[:, 0]):.0%}")
     v0 = np.array(res[0.0])
     assert np.median(v0[:, 1]) <= 1.05 * np.median(v0[:, 0])
+    for nz in (1e-3, 1e-2):
+        v = np.array(res[nz])
+        assert np.median(v[:, 1]) <= np.median(v[:, 0]) * (1 + 1e-12)

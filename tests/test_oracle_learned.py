@@ -168,6 +168,28 @@ def test_judge_objective_is_zero_on_true_kernels_and_prefers_them():
     assert np.allclose(x[:5], (w ** np.arange(5)) @ K2) and np.allclose(x[5:], (w ** np.arange(4)) @ K1)
 
 
+def test_noise_gate_separates_noiseless_from_noisy_frames():
+    """The learned form's noise gate: a noiseless pair has its per-sample
+    lambda_0 at the rounding level (feature f_0 at the 1e-14 floor, -1.4), a
+    pair with noise 1e-3 a noise floor far above 1e-10 (f_0 > -1); exactly
+    half of the samples above the threshold is not yet noisy."""
+    r = synth.rng_for(93)
+    L = synth.gaussian_scene(r, 96, 128)
+    K1, K2 = synth.draw_coprime_pair(r, 5, 7, "uniform")
+    for noise, want in ((0.0, False), (1e-3, True)):
+        B1, B2 = synth.blur_pair(synth.rng_for(94), L, K1, K2, noise)
+        _, _, f = cbp.recover_kernels(B1, B2, 96, 128, 0, full=True)
+        XF, YF = learned.spectrum_features(f["Xspec"]), learned.spectrum_features(f["Yspec"])
+        print(noise, np.median(XF[:, 0]), np.median(YF[:, 0]))
+        assert learned.frame_is_noisy(XF, YF) == want
+    XF = np.full((4, 32), -1.4)
+    YF = np.full((4, 32), -1.4)
+    XF[:, 0] = -0.5                                   # 4 of 8 samples above: not more than half
+    assert not learned.frame_is_noisy(XF, YF)
+    YF[0, 0] = -0.99                                  # 5 of 8
+    assert learned.frame_is_noisy(XF, YF)
+
+
 def _exact_case(n=8, seed=23):
     """Parameters, inputs and every activation and back-propagated signal
     exactly representable in bfloat16: sparse {0, +-1} layer weights,
