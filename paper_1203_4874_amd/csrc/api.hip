@@ -57,7 +57,7 @@ int smooth7(int n) {
 // for any frame within (maxH, maxW, maxk, S, nch) fits the size that
 // cbp_workspace_size() reports for those bounds.
 struct region_sizes {
-  size_t fpart, ex, ey, corr, xvec, pq, kern, t, u, feat, wts, kalt, twxd;
+  size_t fpart, ex, ey, corr, xvec, pq, kern, t, u, feat, wts, kalt, twxd, kr;
 };
 
 // Row pitch of T and U: hx entries of 2 esize bytes rounded up to 128 bytes.
@@ -84,6 +84,7 @@ region_sizes regions(int Hmax, int Wmax, int kmax, int S, int nch, int esize) {
   r.wts = (2 * (size_t)S + 1) * sizeof(double);
   r.kalt = 2 * (size_t)CBP_MAX_K * CBP_MAX_K * sizeof(double);
   r.twxd = (size_t)Px * sizeof(c64);
+  r.kr = ((size_t)Px / 2 + 1) * 2 * CBP_MAX_K * 2 * esize;
   return r;
 }
 
@@ -104,6 +105,7 @@ size_t layout(frame_plan* fp, const region_sizes& r) {
   fp->off_wts = take(r.wts);
   fp->off_kalt = take(r.kalt);
   fp->off_twxd = take(r.twxd);
+  fp->off_kr = take(r.kr);
   fp->total = o;
   return o;
 }
@@ -287,6 +289,7 @@ frame_desc make_desc(const frame_plan& fp, const cbp_image* b1, const cbp_image*
   d.wts = learned ? (double*)(ws + fp.off_wts) : nullptr;
   d.Kalt = (double*)(ws + fp.off_kalt);
   d.twxd = (c64*)(ws + fp.off_twxd);
+  d.kr = ws + fp.off_kr;
   d.variant = variant;
   return d;
 }
@@ -335,7 +338,8 @@ hipError_t note(const char* what, hipError_t e) {
   } while (0)
 
 const char* kPhaseNames[PH_COUNT] = {"fold_cols", "eval_cols", "eval_rows", "gram", "sample_eig",
-                                     "scale_assemble", "row_fft_fwd", "col_fft_filter", "row_fft_inv"};
+                                     "scale_assemble", "row_fft_fwd", "col_fft_filter", "row_fft_inv",
+                                     "kernel_row_dft"};
 
 // ---------------------------------------------------------------- per-device state
 // Pinned host staging for the descriptor upload of an eager batched call;
@@ -458,6 +462,7 @@ hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool 
     CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, 0, 0, st));
   }
   if (latent) {
+    CBP_TRY(launch_kernel_dft<T>(br(Q_KRDFT), cv.grid[Q_KRDFT], st));
     CBP_TRY(launch_col<T>(br(Q_COL), cv.grid[Q_COL], cv.maxPy, cv.maxcw, st));
     CBP_TRY(launch_row_inv<T>(br(Q_ROW_INV), cv.grid[Q_ROW_INV], cv.maxPx, st));
   }

@@ -371,10 +371,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
     const fft_plan& py = d.fy;
     const int N = py.N, cw = d.cw, hx = d.hx, tp = d.hxp, m = d.m;
     const int ld = N | 1;
-    const int k1 = d.k1, k2 = d.k2, Px = d.Px, H1 = d.H1, H2 = d.H2;
-    const double* K1 = d.K1;
-    const double* K2 = d.K2;
-    const c64* twd = d.twxd;
+    const int k1 = d.k1, k2 = d.k2, H1 = d.H1, H2 = d.H2;
     const T lam = (T)d.lambda;
     const bool two = !(d.variant & VAR_DIVIDE_B1);   // two-channel division, or B1 / K1 alone
     cplx<T>* buf = (cplx<T>*)sm_cf;                   // [cw][ld]
@@ -395,36 +392,13 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
       }
     };
     full_twiddles(tw, N, tabN);
-    // kernel row DFTs at this strip's columns: kr[c][fr][yy] = sum_x K[yy][x] exp(-2 pi i kx x / Px)
-    for (int e = threadIdx.x; e < cw * 2 * CBP_MAX_K; e += NT) {
-      const int c = e / (2 * CBP_MAX_K), rem = e - c * 2 * CBP_MAX_K;
-      const int fr = rem / CBP_MAX_K, yy = rem - fr * CBP_MAX_K;
-      const int k = fr ? k2 : k1;
-      const double* K = fr ? K2 : K1;
-      const int kx = kx0 + c;
-      double sr = 0.0, si = 0.0;
-      if (yy < k && kx < hx) {
-        // eight (twiddle, coefficient) pairs loaded per batch, summed in x order
-        int t = 0;
-        for (int x0 = 0; x0 < k; x0 += 8) {
-          c64 w[8];
-          double kv[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            w[u] = twd[t];
-            kv[u] = K[yy * k + min(x0 + u, k - 1)];
-            t += kx;
-            if (t >= Px) t -= Px;
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (x0 + u < k) {
-              sr += kv[u] * w[u].re;
-              si += kv[u] * w[u].im;
-            }
-        }
+    // the kernels' row DFTs at this strip's columns (k_kernel_dft), zero past hx
+    {
+      const cplx<T>* krg = (const cplx<T>*)d.kr;
+      for (int e = threadIdx.x; e < cw * 2 * CBP_MAX_K; e += NT) {
+        const int c = e / (2 * CBP_MAX_K);
+        kr[e] = kx0 + c < hx ? krg[(size_t)kx0 * 2 * CBP_MAX_K + e] : cplx<T>{T(0), T(0)};
       }
-      kr[e] = {T(sr), T(si)};
     }
     // the entries this thread holds (see col_slots)
     const bool even = (N & 1) == 0;
@@ -520,6 +494,49 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
     }
     __syncthreads();   // the next item refills buf, kr and tw
   }
+}
+
+// ---------------------------------------------------------------- kernel row DFTs
+// kr[kx][fr][yy] = sum_x K_fr[yy][x] exp(-2 pi i kx x / Px) for every
+// half-spectrum column kx < hx (zero for yy >= k_fr), in FP64 from the FP64
+// twiddle table, rounded once to T: the column pass evaluates each kernel's
+// spectrum at (ky, kx) from these along y.  Once per frame, shared by its
+// channels.  Items: 256 consecutive entries of [0, hx * 2 * CBP_MAX_K).
+template <typename T>
+__global__ __launch_bounds__(256) void k_kernel_dft(batch_ref br) {
+  for_items<Q_KRDFT>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+    const int e = item * 256 + (int)threadIdx.x;
+    const int hx = d.hx, Px = d.Px;
+    if (e >= hx * 2 * CBP_MAX_K) return;
+    const int kx = e / (2 * CBP_MAX_K), rem = e - kx * 2 * CBP_MAX_K;
+    const int fr = rem / CBP_MAX_K, yy = rem - fr * CBP_MAX_K;
+    const int k = fr ? d.k2 : d.k1;
+    const double* K = fr ? d.K2 : d.K1;
+    const c64* twd = d.twxd;
+    double sr = 0.0, si = 0.0;
+    if (yy < k) {
+      // eight (twiddle, coefficient) pairs loaded per batch, summed in x order
+      int t = 0;
+      for (int x0 = 0; x0 < k; x0 += 8) {
+        c64 w[8];
+        double kv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          w[u] = twd[t];
+          kv[u] = K[yy * k + min(x0 + u, k - 1)];
+          t += kx;
+          if (t >= Px) t -= Px;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (x0 + u < k) {
+            sr += kv[u] * w[u].re;
+            si += kv[u] * w[u].im;
+          }
+      }
+    }
+    ((cplx<T>*)d.kr)[e] = {T(sr), T(si)};
+  });
 }
 
 // ---------------------------------------------------------------- pass 3
@@ -663,6 +680,14 @@ hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipSt
 }
 
 template <typename T>
+hipError_t launch_kernel_dft(const batch_ref& br, int grid, hipStream_t st) {
+  prof_begin(PH_KR_DFT, st);
+  hipLaunchKernelGGL(k_kernel_dft<T>, dim3(grid), dim3(256), 0, st, br);
+  prof_end(PH_KR_DFT, st);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t st) {
   prof_begin(PH_ROW_INV, st);
   hipLaunchKernelGGL(k_row_inv<T>, dim3(grid), dim3(256), row_lds_bytes(maxPx, (int)sizeof(T)), st, br);
@@ -675,6 +700,8 @@ template hipError_t launch_row_fwd<float>(const batch_ref&, int, int, int, int, 
 template hipError_t launch_row_fwd<double>(const batch_ref&, int, int, int, int, hipStream_t);
 template hipError_t launch_col<float>(const batch_ref&, int, int, int, hipStream_t);
 template hipError_t launch_col<double>(const batch_ref&, int, int, int, hipStream_t);
+template hipError_t launch_kernel_dft<float>(const batch_ref&, int, hipStream_t);
+template hipError_t launch_kernel_dft<double>(const batch_ref&, int, hipStream_t);
 template hipError_t launch_row_inv<float>(const batch_ref&, int, int, hipStream_t);
 template hipError_t launch_row_inv<double>(const batch_ref&, int, int, hipStream_t);
 

@@ -23,7 +23,7 @@ namespace cbp {
 // Work queues, one per kernel.
 enum queue_id {
   Q_DIAG = 0, Q_FOLD, Q_EVAL_COLS, Q_EVAL_ROWS, Q_ROW_FWD, Q_GRAM, Q_GRAMM, Q_SAMPLE, Q_FINALIZE, Q_COL,
-  Q_ROW_INV, Q_TWID, Q_SIZE_PROBE, Q_COUNT
+  Q_ROW_INV, Q_TWID, Q_SIZE_PROBE, Q_KRDFT, Q_COUNT
 };
 
 // Frames per batched launch (the item prefix sums of one launch sit in LDS).
@@ -41,7 +41,7 @@ struct frame_plan {
   int cw;                  // columns per workgroup in the column pass
   fft_plan fy, fx;
   size_t off_fpart, off_ex, off_ey, off_corr, off_xvec, off_pq, off_kern,
-      off_t1, off_t2, off_u, off_feat, off_wts, off_kalt, off_twxd, total;
+      off_t1, off_t2, off_u, off_feat, off_wts, off_kalt, off_twxd, off_kr, total;
 };
 
 // Everything a kernel needs about one frame (device pointers).
@@ -85,7 +85,9 @@ struct frame_desc {
   // VAR_* bits); 0 = the default method
   int variant;
   int hxp;           // row pitch of T and U (entries), a multiple of 128 bytes
-  int pad_[2];
+  // the kernels' row DFTs at every half-spectrum column, [hx][2][CBP_MAX_K]
+  // (transform type), for the column pass
+  void* kr;
 };
 constexpr int VAR_DIVIDE_B1 = 1, VAR_SCALE_K1 = 2, VAR_ONE_AXIS = 4;
 
@@ -106,6 +108,7 @@ inline int queue_items(int q, const frame_plan& p) {
     case Q_ROW_INV: return ((p.m + 1) / 2) * p.nch;
     case Q_TWID: return (p.Px + 255) / 256;
     case Q_SIZE_PROBE: return 0;   // set by the size-estimation entry point (candidates x 2S)
+    case Q_KRDFT: return (p.hx * 2 * CBP_MAX_K + 255) / 256;
   }
   return 0;
 }
@@ -238,7 +241,7 @@ constexpr size_t kEvalColsLds = (size_t)CBP_MAX_S * 16 * sizeof(double) + (size_
 // returns).
 enum phase_id {
   PH_FOLD = 0, PH_EVAL_COLS, PH_EVAL_ROWS, PH_GRAM, PH_SAMPLE, PH_FINALIZE,
-  PH_ROW_FWD, PH_COL_FILTER, PH_ROW_INV, PH_COUNT
+  PH_ROW_FWD, PH_COL_FILTER, PH_ROW_INV, PH_KR_DFT, PH_COUNT
 };
 // Record the start / end of a phase on a stream when timing is enabled
 // (no-ops otherwise).  Implemented in api.hip.
@@ -302,6 +305,8 @@ hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey,
                           hipStream_t st);
 template <typename T>
 hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st);
+template <typename T>
+hipError_t launch_kernel_dft(const batch_ref& br, int grid, hipStream_t st);
 template <typename T>
 hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t st);
 size_t row_lds_bytes(int N, int esize);
