@@ -233,7 +233,7 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
     return CBP_OK;
   }
   if (fp->Py > max_fft(esize) || fp->Px > max_fft(esize)) return CBP_E_SHAPE;
-  if (!make_fft_plan(fp->Py, &fp->fy, tn.fft_order) || !make_fft_plan(fp->Px, &fp->fx, tn.fft_order))
+  if (!make_fft_plan(fp->Py, &fp->fy, tn.fft_order) || !make_fft_plan(fp->Px, &fp->fx, tn.fft_order, true))
     return CBP_E_SHAPE;
   fp->hx = fp->Px / 2 + 1;
   fp->hxp = pitch_of(fp->hx, esize);

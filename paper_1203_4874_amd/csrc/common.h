@@ -140,6 +140,12 @@ struct radix_consts {
   static constexpr double s7_2 = 0.97492791218182360702;
   static constexpr double c7_3 = -0.90096886790241912624;
   static constexpr double s7_3 = 0.43388373911755812048;
+  static constexpr double c9_1 = 0.76604444311897803520;   // cos / sin (2 pi k / 9), k = 1, 2, 4
+  static constexpr double s9_1 = 0.64278760968653932632;
+  static constexpr double c9_2 = 0.17364817766693034885;
+  static constexpr double s9_2 = 0.98480775301220805937;
+  static constexpr double c9_4 = -0.93969262078590838405;
+  static constexpr double s9_4 = 0.34202014332566873304;
   static constexpr double r2_2 = 0.70710678118654752440;   // sqrt(2)/2
 };
 

@@ -31,7 +31,7 @@ __device__ inline void pick(const frame_desc& d, int cf, const T*& b, int64_t& p
 
 // Column fold over rows [g*rpg, (g+1)*rpg) of one (channel, frame): one
 // thread per (column, residue r), summing the rows y = r mod S of the group
-// in increasing order (four loads in flight), 64 columns per item.
+// in increasing order (up to sixteen loads in flight), 64 columns per item.
 // Items: (column block, residue, row group, cf).
 // Twiddle tables exp(-2 pi i t / P) of the row and column FFTs (the row
 // table also in FP64 for the kernel spectra); an item is 256 consecutive
@@ -93,6 +93,14 @@ __global__ __launch_bounds__(64) void k_fold_cols(batch_ref br_ws, int gf, inlin
     const T* col = b + x;
     double acc = 0.0;
     int y = g * d.rpg + r;
+    // sixteen loads in flight, then added in increasing y
+    for (; y + 15 * S < y1; y += 16 * S) {
+      T v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = col[(int64_t)(y + u * S) * pitch];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += (double)v[u];
+    }
     for (; y + 3 * S < y1; y += 4 * S) {
       const T v0 = col[(int64_t)y * pitch], v1 = col[(int64_t)(y + S) * pitch];
       const T v2 = col[(int64_t)(y + 2 * S) * pitch], v3 = col[(int64_t)(y + 3 * S) * pitch];

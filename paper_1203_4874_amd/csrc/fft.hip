@@ -101,12 +101,21 @@ __device__ __attribute__((always_inline)) inline void ip_pass(cplx<T>* buf, int 
 }
 
 // All passes of plan p over ncol transforms (ncol p.N <= MAXE), in place.
-template <int DIR, int NT, int MAXE, typename T>
+// R9: the plan may hold radix-9 passes (the row plans; the column plans do
+// not, which keeps the column pass's registers at the radix-8 pass).
+template <int DIR, int NT, int MAXE, bool R9 = false, typename T>
 __device__ __attribute__((always_inline)) inline void ip_fft(cplx<T>* buf, int ld, const fft_plan& p,
                                                              const cplx<T>* tw, int ncol) {
   int Ns = 1;
   for (int s = 0; s < p.npass; ++s) {
     const int R = plan_radix(p, s);
+    if constexpr (R9) {
+      if (R == 9) {
+        ip_pass<9, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol);
+        Ns *= 9;
+        continue;
+      }
+    }
     switch (R) {
       case 2: ip_pass<2, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
       case 3: ip_pass<3, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
@@ -260,7 +269,7 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int 
         d.ey[((size_t)(2 * ch + fr) * S + l) * d.Hmax + y] = e;
       }
     }
-    ip_fft<-1, 256, ROW_MAXE>(a, N, px, twf, 1);
+    ip_fft<-1, 256, ROW_MAXE, true>(a, N, px, twf, 1);
     const cplx<T>* z = a;
     cplx<T>* o1 = (cplx<T>*)d.t1 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
     cplx<T>* o2 = (cplx<T>*)d.t2 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
@@ -619,7 +628,7 @@ __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
     __syncthreads();
     // the next item's spectra are in flight while this one is transformed
     if (it + step < end) fetch(it + step);
-    ip_fft<+1, 256, ROW_MAXE>(a, N, px, twf, 1);
+    ip_fft<+1, 256, ROW_MAXE, true>(a, N, px, twf, 1);
     const cplx<T>* z = a;
     T* oa = (T*)d.out + ch * d.ocs + (int64_t)ya * d.opitch;
     T* ob = oa + d.opitch;

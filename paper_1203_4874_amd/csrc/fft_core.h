@@ -110,6 +110,32 @@ CBP_HD void dft7(cplx<T>* v) {
   v[3] = A3 + B3; v[4] = A3 - B3;
 }
 
+// 9 = 3 x 3: with n = 3a + b and m = c + 3d, w9^(nm) = w3^(ac) w9^(bc) w3^(bd):
+// 3-point DFTs over a of x[3a + b], twiddles w9^(bc), 3-point DFTs over b.
+template <int DIR, typename T>
+CBP_HD void dft9(cplx<T>* v) {
+  cplx<T> y[9];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    cplx<T> t[3] = {v[b], v[b + 3], v[b + 6]};
+    dft3<DIR>(t);
+    y[3 * b] = t[0]; y[3 * b + 1] = t[1]; y[3 * b + 2] = t[2];
+  }
+  const cplx<T> w1 = {T(radix_consts::c9_1), T(DIR) * T(radix_consts::s9_1)};
+  const cplx<T> w2 = {T(radix_consts::c9_2), T(DIR) * T(radix_consts::s9_2)};
+  const cplx<T> w4 = {T(radix_consts::c9_4), T(DIR) * T(radix_consts::s9_4)};
+  y[4] = y[4] * w1;   // b = 1, c = 1
+  y[5] = y[5] * w2;   // b = 1, c = 2
+  y[7] = y[7] * w2;   // b = 2, c = 1
+  y[8] = y[8] * w4;   // b = 2, c = 2
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cplx<T> t[3] = {y[c], y[3 + c], y[6 + c]};
+    dft3<DIR>(t);
+    v[c] = t[0]; v[c + 3] = t[1]; v[c + 6] = t[2];
+  }
+}
+
 template <int R, int DIR, typename T>
 CBP_HD void dft_small(cplx<T>* v) {
   if constexpr (R == 2) dft2<DIR>(v);
@@ -118,6 +144,7 @@ CBP_HD void dft_small(cplx<T>* v) {
   else if constexpr (R == 5) dft5<DIR>(v);
   else if constexpr (R == 7) dft7<DIR>(v);
   else if constexpr (R == 8) dft8<DIR>(v);
+  else if constexpr (R == 9) dft9<DIR>(v);
 }
 
 // ---------------------------------------------------------------- one butterfly
@@ -172,22 +199,25 @@ struct fft_plan {
 CBP_HD int plan_radix(const fft_plan& p, int s) { return (int)((p.code >> (4 * s)) & 15u); }
 
 // Factor N into the supported radices.  `order` picks the pass order:
-//   0: radix 8 first, then 4, 2, 3, 5, 7 (fewest passes);
-//   1: radix 4 first, then 8, 2, 3, 5, 7;
-//   2: odd radices first: 7, 5, 3, then 8, 4, 2.
+//   0: radix 8 first, then 4, 2, (9,) 3, 5, 7 (fewest passes);
+//   1: radix 4 first, then 8, 2, (9,) 3, 5, 7;
+//   2: odd radices first: 7, 5, (9,) 3, then 8, 4, 2.
+// with9 takes factors 9 as one radix-9 pass before the remaining 3.
 // Returns false when N has another prime factor, too many passes, or an
 // unknown order.
 constexpr int FFT_ORDERS = 3;
 
-inline bool make_fft_plan(int N, fft_plan* p, int order = 0) {
-  static const int orders[FFT_ORDERS][6] = {{8, 4, 2, 3, 5, 7}, {4, 8, 2, 3, 5, 7}, {7, 5, 3, 8, 4, 2}};
+inline bool make_fft_plan(int N, fft_plan* p, int order = 0, bool with9 = false) {
+  static const int orders[FFT_ORDERS][7] = {
+      {8, 4, 2, 9, 3, 5, 7}, {4, 8, 2, 9, 3, 5, 7}, {7, 5, 9, 3, 8, 4, 2}};
   if (N < 1 || order < 0 || order >= FFT_ORDERS) return false;
   p->N = N;
   p->npass = 0;
   p->code = 0;
   int r = N;
-  for (int t = 0; t < 6; ++t) {
+  for (int t = 0; t < 7; ++t) {
     const int R = orders[order][t];
+    if (R == 9 && !with9) continue;
     while (r % R == 0) {
       if (p->npass >= FFT_MAX_PASSES) return false;
       p->code |= (unsigned long long)R << (4 * p->npass);

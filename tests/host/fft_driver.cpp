@@ -1,5 +1,5 @@
 // Host driver for the library's Stockham butterflies (csrc/fft_core.h):
-// reads "N dir order" then N complex values (re im) from stdin and runs every
+// reads "N dir order with9" then N complex values (re im) from stdin and runs every
 // pass of the plan on the CPU the way the kernels do, in place: each pass
 // reads all of its butterflies (stockham_read, with k = j mod Ns split by the
 // kernels' FP32 reciprocal) before writing their outputs over the input.
@@ -36,15 +36,16 @@ void run_pass(int R, std::vector<cplx<double>>& buf, int N, int Ns, const cplx<d
     case 4: pass<4, DIR>(buf, N, Ns, tw); break;
     case 5: pass<5, DIR>(buf, N, Ns, tw); break;
     case 7: pass<7, DIR>(buf, N, Ns, tw); break;
+    case 9: pass<9, DIR>(buf, N, Ns, tw); break;
     default: pass<8, DIR>(buf, N, Ns, tw); break;
   }
 }
 
 int main() {
-  int N, dir, order;
-  if (std::scanf("%d %d %d", &N, &dir, &order) != 3) return 2;
+  int N, dir, order, with9;
+  if (std::scanf("%d %d %d %d", &N, &dir, &order, &with9) != 4) return 2;
   fft_plan p;
-  if (!make_fft_plan(N, &p, order)) { std::printf("BADPLAN\n"); return 3; }
+  if (!make_fft_plan(N, &p, order, with9 != 0)) { std::printf("BADPLAN\n"); return 3; }
   std::vector<cplx<double>> a(N), tw(N);
   for (int i = 0; i < N; ++i)
     if (std::scanf("%lf %lf", &a[i].re, &a[i].im) != 2) return 2;

@@ -23,26 +23,29 @@ def driver(tmp_path_factory):
     return exe
 
 
-def run(exe, x, direction, order=0):
-    inp = f"{len(x)} {direction} {order}\n" + "\n".join(f"{float(v.real)!r} {float(v.imag)!r}" for v in x)
+def run(exe, x, direction, order=0, with9=0):
+    inp = f"{len(x)} {direction} {order} {with9}\n" + "\n".join(f"{float(v.real)!r} {float(v.imag)!r}" for v in x)
     out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
     return np.array([complex(*map(float, line.split())) for line in out.strip().split("\n")])
 
 
+@pytest.mark.parametrize("with9", [0, 1])
 @pytest.mark.parametrize("order", [0, 1, 2])
-@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 7, 8, 12, 35, 49, 64, 490, 672, 735, 1120, 1296, 1792, 1944, 2048])
-def test_stockham_matches_numpy(driver, N, order):
-    """Every radix pass order the autotuner may pick computes the same DFT."""
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 7, 8, 9, 12, 18, 27, 35, 49, 64, 81, 490, 672, 735, 1120, 1296,
+                               1792, 1944, 2048])
+def test_stockham_matches_numpy(driver, N, order, with9):
+    """Every radix pass order the autotuner may pick, with and without the
+    radix-9 passes of the row plans, computes the same DFT."""
     r = np.random.default_rng(N)
     x = r.standard_normal(N) + 1j * r.standard_normal(N)
-    y = run(driver, x, -1, order)
+    y = run(driver, x, -1, order, with9)
     assert np.abs(y - np.fft.fft(x)).max() <= 1e-14 * max(1.0, np.abs(np.fft.fft(x)).max())
-    z = run(driver, x, +1, order)
+    z = run(driver, x, +1, order, with9)
     assert np.abs(z - N * np.fft.ifft(x)).max() <= 1e-14 * max(1.0, np.abs(N * np.fft.ifft(x)).max())
 
 
 def test_non_smooth_size_has_no_plan(driver):
-    out = subprocess.run([driver], input="11 -1 0\n" + "0 0\n" * 11, capture_output=True, text=True)
+    out = subprocess.run([driver], input="11 -1 0 0\n" + "0 0\n" * 11, capture_output=True, text=True)
     assert "BADPLAN" in out.stdout
 
 
@@ -53,7 +56,7 @@ def test_radix_constants():
     mp.mp.dps = 30
     src = open(os.path.join(ROOT, "paper_1203_4874_amd", "csrc", "common.h")).read()
     vals = dict(re.findall(r"static constexpr double (\w+) = (-?[0-9.]+);", src))
-    for R in (3, 5, 7):
+    for R in (3, 5, 7, 9):
         for k in range(1, (R - 1) // 2 + 1):
             c = vals.get(f"c{R}_{k}")
             s = vals.get(f"s{R}_{k}")
@@ -75,7 +78,7 @@ def test_float_reciprocal_index_split_is_exact():
         return n == 1
     f32 = np.float32
     for N in (n for n in range(2, 2049) if smooth(n)):
-        for R in (2, 3, 4, 5, 7, 8):
+        for R in (2, 3, 4, 5, 7, 8, 9):
             if N % R:
                 continue
             nb = N // R
