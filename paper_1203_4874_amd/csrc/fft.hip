@@ -292,25 +292,24 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int 
 // registers while frame 1 is transformed.  The workgroup has NT = 512 or 1024
 // threads.
 
-// Largest cw * N of a strip: 9.5 FP32 (4.75 FP64) complex entries per
-// thread, so each thread's share of a pass and of the stashed spectrum stays
-// in registers.
+// Largest cw * N of a strip: 9 FP32 (4.5 FP64) complex entries per thread,
+// so each thread's share of a pass and of the stashed spectrum stays in
+// registers.
 template <typename T, int NT>
-constexpr int col_max_elems() { return NT * 76 / (int)sizeof(cplx<T>); }
+constexpr int col_max_elems() { return NT * 72 / (int)sizeof(cplx<T>); }
 
 
 // The strip's entries as each thread holds them for the stash and the
-// filter: column c = tid / (NT / cw) (wave-uniform: NT / cw >= 64) and, for
-// even N, row pairs (y, y + N/2), y = tid mod (NT / cw) + i NT / cw, whose
-// twiddles differ only in sign; for odd N, single rows.  f(slot, y) is
-// called for each held entry with slot < col_slots.
-template <typename T, int NT>
-constexpr int col_pairs() { return (col_max_elems<T, NT>() / 2 + NT - 1) / NT; }
-template <typename T, int NT>
-constexpr int col_singles() { return (col_max_elems<T, NT>() + NT - 1) / NT; }
+// filter: column c = tid / (NT / cw) (wave-uniform: NT / cw >= 64) and rows in
+// groups of g = 4 (N divisible by 4), 2 (N even) or 1: rows y + j N/g, j < g,
+// y = tid mod (NT / cw) + i NT / cw < N/g, whose twiddles w_N^(y + j N/g)
+// differ by the g-th roots of unity.  Group i holds slots g i .. g i + g - 1.
+template <typename T, int NT, int G>
+constexpr int col_groups() { return (col_max_elems<T, NT>() / G + NT - 1) / NT; }
 template <typename T, int NT>
 constexpr int col_slots() {
-  return 2 * col_pairs<T, NT>() > col_singles<T, NT>() ? 2 * col_pairs<T, NT>() : col_singles<T, NT>();
+  constexpr int a = 4 * col_groups<T, NT, 4>(), b = 2 * col_groups<T, NT, 2>(), c = col_groups<T, NT, 1>();
+  return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
 
 // Items: (strip of cw columns, channel).  A workgroup that owns several
@@ -320,7 +319,7 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_cf[];
   __shared__ int st[BATCH_CHUNK + 1];
-  constexpr int SP = col_pairs<T, NT>(), SE = col_singles<T, NT>(), SM = col_slots<T, NT>();
+  constexpr int SM = col_slots<T, NT>();
   constexpr int PF = (col_max_elems<T, NT>() + NT - 1) / NT;   // strip entries per thread
   constexpr int LNT = NT == 1024 ? 10 : 9;
   const int nf = br.nframes;
@@ -409,24 +408,32 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
         kr[e] = kx0 + c < hx ? krg[(size_t)kx0 * 2 * CBP_MAX_K + e] : cplx<T>{T(0), T(0)};
       }
     }
-    // the entries this thread holds (see col_slots)
-    const bool even = (N & 1) == 0;
-    const int h = even ? N >> 1 : N;
+    // the entries this thread holds (see col_groups): f(group size, slot of
+    // the group's first row, column, y, N / group size)
+    const int g4 = (N & 3) == 0 ? 4 : (N & 1) == 0 ? 2 : 1;
     auto for_held = [&](auto&& f) __attribute__((always_inline)) {
       const int tid = local_tid();
       const int ltpc = LNT - lcw;
       const int c = tid >> ltpc, r = tid & ((1 << ltpc) - 1);
-      if (even) {
+      if (g4 == 4) {
+        const int q = N >> 2;
 #pragma unroll
-        for (int i = 0; i < SP; ++i) {
+        for (int i = 0; i < col_groups<T, NT, 4>(); ++i) {
           const int y = r + (i << ltpc);
-          if (y < h) f(2 * i, 2 * i + 1, c, y, true);
+          if (y < q) f(std::integral_constant<int, 4>(), 4 * i, c, y, q);
+        }
+      } else if (g4 == 2) {
+        const int q = N >> 1;
+#pragma unroll
+        for (int i = 0; i < col_groups<T, NT, 2>(); ++i) {
+          const int y = r + (i << ltpc);
+          if (y < q) f(std::integral_constant<int, 2>(), 2 * i, c, y, q);
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < SE; ++i) {
+        for (int i = 0; i < col_groups<T, NT, 1>(); ++i) {
           const int y = r + (i << ltpc);
-          if (y < N) f(i, i, c, y, false);
+          if (y < N) f(std::integral_constant<int, 1>(), i, c, y, N);
         }
       }
     };
@@ -436,9 +443,9 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
       __syncthreads();
       fetch(it, 0);   // frame 1's strip in flight while frame 2's is transformed
       ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, tw, cw);
-      for_held([&](int a, int b, int c, int y, bool pair) __attribute__((always_inline)) {
-        st2[a] = buf[mul24(c, ld) + y];
-        if (pair) st2[b] = buf[mul24(c, ld) + y + h];
+      for_held([&](auto G, int a, int c, int y, int q) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < G(); ++j) st2[a + j] = buf[mul24(c, ld) + y + j * q];
       });
       __syncthreads();   // buf is refilled with frame 1
     }
@@ -460,36 +467,51 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
       // quotient is zero, whatever the frames hold
       *at = kk > T(0) ? cplx<T>{num.re * inv, num.im * inv} : cplx<T>{T(0), T(0)};
     };
-    for_held([&](int a, int b, int c, int y, bool pair) __attribute__((always_inline)) {
-      // kernel spectra at (ky, kx) = sum_yy kr[yy] z^yy, z = w_N^y: for a row
-      // pair as E(z^2) + z O(z^2) and E(z^2) - z O(z^2) (even / odd
-      // coefficients by Horner's rule in u = z^2), else by Horner's rule in z;
-      // kr is zero beyond each kernel's size and the column is wave-uniform
+    for_held([&](auto G, int a, int c, int y, int q) __attribute__((always_inline)) {
+      // kernel spectra at (ky, kx) = sum_yy kr[yy] z^yy, z = w_N^ky.  For the
+      // group's rows ky = y + j N/g (z = w_N^y times the g-th roots of unity
+      // (-i)^(4j/g)): K = sum_p z^p E_p(z^g), E_p(u) = sum_t kr[g t + p] u^t
+      // by Horner's rule in u = w_N^(g y), then the g-point DFT of the
+      // z^p E_p.  kr is zero beyond each kernel's size; the column is
+      // wave-uniform.
+      constexpr int g = G();
       const cplx<T>* kr1 = kr + (size_t)c * 2 * CBP_MAX_K;
       const cplx<T>* kr2 = kr1 + CBP_MAX_K;
-      const cplx<T> z = tw[y];
-      if (pair) {
-        const cplx<T> u = tw[2 * y];
-        const int ke = (kmax + 1) >> 1;          // even coefficients 0, 2, .., 2 (ke - 1)
-        cplx<T> e1 = kr1[2 * (ke - 1)], e2 = kr2[2 * (ke - 1)];
-        cplx<T> o1 = {T(0), T(0)}, o2 = {T(0), T(0)};
-        if (2 * ke - 1 < CBP_MAX_K) { o1 = kr1[2 * ke - 1]; o2 = kr2[2 * ke - 1]; }
-        for (int t = ke - 2; t >= 0; --t) {
-          e1 = e1 * u + kr1[2 * t];
-          e2 = e2 * u + kr2[2 * t];
-          o1 = o1 * u + kr1[2 * t + 1];
-          o2 = o2 * u + kr2[2 * t + 1];
+      const int nt = (kmax + g - 1) / g;          // coefficients per E_p
+      const cplx<T> u = tw[g * y];
+      cplx<T> P1[g], P2[g];
+#pragma unroll
+      for (int p = 0; p < g; ++p) {
+        const int top = g * (nt - 1) + p;
+        cplx<T> e1 = top < CBP_MAX_K ? kr1[top] : cplx<T>{T(0), T(0)};
+        cplx<T> e2 = top < CBP_MAX_K ? kr2[top] : cplx<T>{T(0), T(0)};
+        for (int t = nt - 2; t >= 0; --t) {
+          e1 = e1 * u + kr1[g * t + p];
+          e2 = e2 * u + kr2[g * t + p];
         }
-        const cplx<T> zo1 = z * o1, zo2 = z * o2;
-        filt(buf + mul24(c, ld) + y, e1 + zo1, e2 + zo2, st2[a]);
-        filt(buf + mul24(c, ld) + y + h, e1 - zo1, e2 - zo2, st2[b]);
+        if (p > 0) {
+          const cplx<T> zp = tw[p * y];
+          e1 = zp * e1;
+          e2 = zp * e2;
+        }
+        P1[p] = e1;
+        P2[p] = e2;
+      }
+      cplx<T>* col = buf + mul24(c, ld) + y;
+      if constexpr (g == 1) {
+        filt(col, P1[0], P2[0], st2[a]);
+      } else if constexpr (g == 2) {
+        filt(col, P1[0] + P1[1], P2[0] + P2[1], st2[a]);
+        filt(col + q, P1[0] - P1[1], P2[0] - P2[1], st2[a + 1]);
       } else {
-        cplx<T> kh1 = kr1[kmax - 1], kh2 = kr2[kmax - 1];
-        for (int yy = kmax - 2; yy >= 0; --yy) {
-          kh1 = kh1 * z + kr1[yy];
-          kh2 = kh2 * z + kr2[yy];
-        }
-        filt(buf + mul24(c, ld) + y, kh1, kh2, st2[a]);
+        // rows y, y + N/4, y + N/2, y + 3N/4: roots 1, -i, -1, i
+        const cplx<T> s02_1 = P1[0] + P1[2], d02_1 = P1[0] - P1[2], s13_1 = P1[1] + P1[3], d13_1 = P1[1] - P1[3];
+        const cplx<T> s02_2 = P2[0] + P2[2], d02_2 = P2[0] - P2[2], s13_2 = P2[1] + P2[3], d13_2 = P2[1] - P2[3];
+        const cplx<T> md13_1 = mul_i(d13_1, -1), md13_2 = mul_i(d13_2, -1);   // -i (P1 - P3)
+        filt(col, s02_1 + s13_1, s02_2 + s13_2, st2[a]);
+        filt(col + q, d02_1 + md13_1, d02_2 + md13_2, st2[a + 1]);
+        filt(col + 2 * q, s02_1 - s13_1, s02_2 - s13_2, st2[a + 2]);
+        filt(col + 3 * q, d02_1 - md13_1, d02_2 - md13_2, st2[a + 3]);
       }
     });
     __syncthreads();
