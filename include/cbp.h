@@ -422,6 +422,15 @@ size_t     cbp_mlp_state_size(int32_t max_rows);
 /* Load parameters into a state and reset its Adam moments. */
 cbp_status cbp_mlp_set_params(void* state, int32_t max_rows, const float* params, void* stream);
 cbp_status cbp_mlp_get_params(const void* state, int32_t max_rows, float* params, void* stream);
+/* Checkpoint of a training state (resume): the master weights and both Adam
+ * moments, cbp_mlp_checkpoint_size() bytes = 3 x cbp_mlp_param_count() FP32
+ * in device memory, caller-owned.  Loading restores them (and the bf16
+ * copies) into a state of any max_rows; the caller keeps the step count
+ * passed to cbp_mlp_train_step.  CBP_E_INVALID on NULL pointers or
+ * max_rows < 1. */
+size_t     cbp_mlp_checkpoint_size(void);
+cbp_status cbp_mlp_save_state(const void* state, int32_t max_rows, float* out, void* stream);
+cbp_status cbp_mlp_load_state(void* state, int32_t max_rows, const float* in, void* stream);
 /* Loss and gradient (packed like the parameters; grads may be NULL) of n <= max_rows rows. */
 cbp_status cbp_mlp_gradients(void* state, int32_t max_rows, const float* X, const float* T, int32_t n,
                              float* loss, float* grads, void* stream);

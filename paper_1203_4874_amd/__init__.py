@@ -151,6 +151,9 @@ _SIGS = {
     "cbp_mlp_state_size": (ctypes.c_size_t, [ctypes.c_int32]),
     "cbp_mlp_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "cbp_mlp_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "cbp_mlp_checkpoint_size": (ctypes.c_size_t, []),
+    "cbp_mlp_save_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "cbp_mlp_load_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "cbp_mlp_gradients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cbp_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
@@ -434,6 +437,25 @@ class MlpState:
         _check(lib().cbp_mlp_get_params(self.buf.data_ptr(), self.rows, p.data_ptr(), _stream_ptr(stream)),
                "cbp_mlp_get_params")
         return p
+
+    def save_state(self, stream=None):
+        """Checkpoint (FP32 device tensor [3][param_count]): master weights and
+        both Adam moments, for resuming training."""
+        torch = _torch()
+        c = torch.empty(3 * self.param_count(), dtype=torch.float32, device=self.device)
+        _check(lib().cbp_mlp_save_state(self.buf.data_ptr(), self.rows, c.data_ptr(), _stream_ptr(stream)),
+               "cbp_mlp_save_state")
+        return c
+
+    def load_state(self, ckpt, stream=None):
+        """Restore a checkpoint written by save_state (any max_rows)."""
+        torch = _torch()
+        c = torch.as_tensor(ckpt, dtype=torch.float32, device=self.device).contiguous()
+        if c.numel() != 3 * self.param_count():
+            raise ValueError(f"checkpoint holds {c.numel()} floats, expected {3 * self.param_count()}")
+        _check(lib().cbp_mlp_load_state(self.buf.data_ptr(), self.rows, c.data_ptr(), _stream_ptr(stream)),
+               "cbp_mlp_load_state")
+        self._keep = c
 
     def gradients(self, X, T, stream=None):
         """(loss, grads) of the mean loss on rows X [n][32], targets T [n][2]."""

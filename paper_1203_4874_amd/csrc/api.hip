@@ -1229,6 +1229,22 @@ cbp_status cbp_mlp_get_params(const void* state, int32_t max_rows, float* params
              ? CBP_OK : CBP_E_DEVICE;
 }
 
+size_t cbp_mlp_checkpoint_size(void) { return (size_t)3 * MLP_NPARAM * sizeof(float); }
+
+cbp_status cbp_mlp_save_state(const void* state, int32_t max_rows, float* out, void* stream) {
+  if (!state || !out || max_rows < 1) return CBP_E_INVALID;
+  (void)hipGetLastError();
+  return note("mlp_save_state", mlp_save_state(state, max_rows, out, (hipStream_t)stream)) == hipSuccess
+             ? CBP_OK : CBP_E_DEVICE;
+}
+
+cbp_status cbp_mlp_load_state(void* state, int32_t max_rows, const float* in, void* stream) {
+  if (!state || !in || max_rows < 1) return CBP_E_INVALID;
+  (void)hipGetLastError();
+  return note("mlp_load_state", mlp_load_state(state, max_rows, in, (hipStream_t)stream)) == hipSuccess
+             ? CBP_OK : CBP_E_DEVICE;
+}
+
 cbp_status cbp_mlp_gradients(void* state, int32_t max_rows, const float* X, const float* T, int32_t n,
                              float* loss, float* grads, void* stream) {
   if (!state || !X || !T || !loss || n < 1 || n > max_rows) return CBP_E_INVALID;

@@ -37,6 +37,8 @@ struct mlp_blob {
 size_t mlp_state_bytes(int rows);
 hipError_t mlp_set_params(void* state, int rows, const float* params, hipStream_t st);
 hipError_t mlp_get_params(const void* state, int rows, float* params, hipStream_t st);
+hipError_t mlp_save_state(const void* state, int rows, float* out, hipStream_t st);
+hipError_t mlp_load_state(void* state, int rows, const float* in, hipStream_t st);
 hipError_t mlp_gradients(void* state, int rows, const float* X, const float* T, int n, float* loss,
                          float* grads, hipStream_t st);
 hipError_t mlp_adam_step(void* state, int rows, float lr, int step, hipStream_t st);

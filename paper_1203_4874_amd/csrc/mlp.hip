@@ -465,6 +465,32 @@ hipError_t mlp_get_params(const void* state, int rows, float* params, hipStream_
   return hipMemcpyAsync(params, s.p, MLP_NPARAM * 4, hipMemcpyDeviceToDevice, st);
 }
 
+// Checkpoint of the training state: master weights and both Adam moments,
+// [3][MLP_NPARAM] FP32.  Loading restores them and the bf16 copies.
+hipError_t mlp_save_state(const void* state, int rows, float* out, hipStream_t st) {
+  const state_view s = carve(const_cast<void*>(state), rows);
+  const float* src[3] = {s.p, s.m, s.v};
+  for (int i = 0; i < 3; ++i) {
+    const hipError_t e = hipMemcpyAsync(out + (size_t)i * MLP_NPARAM, src[i], MLP_NPARAM * 4,
+                                        hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t mlp_load_state(void* state, int rows, const float* in, hipStream_t st) {
+  const state_view s = carve(state, rows);
+  float* dst[3] = {s.p, s.m, s.v};
+  for (int i = 0; i < 3; ++i) {
+    const hipError_t e = hipMemcpyAsync(dst[i], in + (size_t)i * MLP_NPARAM, MLP_NPARAM * 4,
+                                        hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_mlp_quantise, dim3((MLP_HIDDEN * MLP_HIDDEN + 255) / 256), dim3(256), 0, st, s.p, s.W1, s.W2,
+                     s.W2t);
+  return hipGetLastError();
+}
+
 // Forward, loss and backward over n <= rows rows: the gradient of the mean
 // loss into the state (and into grads when not NULL), the loss into *loss.
 hipError_t mlp_gradients(void* state, int rows, const float* X, const float* T, int n, float* loss, float* grads,

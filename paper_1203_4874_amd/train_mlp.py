@@ -1,6 +1,7 @@
 """Train the learned form's network on pairs the method itself generates.
 
     python -m paper_1203_4874_amd.train_mlp [--pairs 20000] [--holdout 2000] [--out DIR] [--eval-only]
+                                            [--checkpoint FILE [--resume]]
 
 Data (seeded, synthetic): 256 x 256 Gaussian-sum scenes, kernel sizes k1, k2
 drawn independently from {5, 7, ..., 15} (uniform entries, sum 1, coprime),
@@ -149,6 +150,9 @@ def main():
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_1203_4874_amd", "weights"))
     ap.add_argument("--eval-only", action="store_true",
                     help="skip training: compare the committed network with the plain method on the held-out pairs")
+    ap.add_argument("--checkpoint", default="",
+                    help="file (.npz) for the training state after every epoch (weights, Adam moments, step)")
+    ap.add_argument("--resume", action="store_true", help="continue from --checkpoint")
     args = ap.parse_args()
 
     # the generator processes are forked before anything touches the GPU
@@ -209,8 +213,14 @@ def main():
     nrow = X.shape[0]
     steps_per_epoch = max(1, nrow // args.batch)
     step = 0
+    first_epoch = 0
+    if args.resume and args.checkpoint and os.path.exists(args.checkpoint):
+        with np.load(args.checkpoint, allow_pickle=False) as z:
+            st.load_state(z["state"])
+            step, first_epoch = int(z["step"]), int(z["epoch"]) + 1
+        print(f"[train] resumed after epoch {first_epoch} (step {step})", flush=True)
     t0 = time.time()
-    for ep in range(args.epochs):
+    for ep in range(first_epoch, args.epochs):
         perm = torch.randperm(nrow, device=dev, generator=torch.Generator(device=dev).manual_seed(ep))
         tot = 0.0
         for b in range(steps_per_epoch):
@@ -222,6 +232,10 @@ def main():
             tot += float(loss.item()) if b % 16 == 0 else 0.0
         print(f"[train] epoch {ep + 1}/{args.epochs}: loss ~{tot / max(1, (steps_per_epoch + 15) // 16):.4f} "
               f"({time.time() - t0:.0f} s)", flush=True)
+        if args.checkpoint:
+            tmp = args.checkpoint + ".tmp.npz"
+            np.savez(tmp, state=st.save_state().cpu().numpy(), step=step, epoch=ep)
+            os.replace(tmp, args.checkpoint)
     params = st.get_params().cpu().numpy()
     blob = st.export()
     os.makedirs(args.out, exist_ok=True)

@@ -44,6 +44,36 @@ def test_stockham_matches_numpy(driver, N, order, with9):
     assert np.abs(z - N * np.fft.ifft(x)).max() <= 1e-14 * max(1.0, np.abs(N * np.fft.ifft(x)).max())
 
 
+@pytest.fixture(scope="module")
+def sanitized_driver(tmp_path_factory):
+    """The same driver built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code: the butterflies, the plans and the index splits)."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("fft_san") / "fft_driver_san")
+    r = subprocess.run([gxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "paper_1203_4874_amd", "csrc"),
+                        os.path.join(ROOT, "tests", "host", "fft_driver.cpp"), "-o", exe],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
+    return exe
+
+
+@pytest.mark.parametrize("N", [1, 2, 9, 49, 81, 490, 1120, 1944, 2048])
+def test_sanitized_butterflies(sanitized_driver, N):
+    """Every pass order with and without radix 9 under ASan / UBSan: no
+    out-of-bounds access, overflow or other undefined behaviour, and the
+    same transform."""
+    r = np.random.default_rng(N + 3)
+    x = r.standard_normal(N) + 1j * r.standard_normal(N)
+    for order in (0, 1, 2):
+        for with9 in (0, 1):
+            y = run(sanitized_driver, x, -1, order, with9)
+            assert np.abs(y - np.fft.fft(x)).max() <= 1e-14 * max(1.0, np.abs(np.fft.fft(x)).max())
+
+
 def test_non_smooth_size_has_no_plan(driver):
     out = subprocess.run([driver], input="11 -1 0 0\n" + "0 0\n" * 11, capture_output=True, text=True)
     assert "BADPLAN" in out.stdout

@@ -170,6 +170,37 @@ def test_adam_training_lowers_the_loss(P):
     assert l1 < l0 / 5
 
 
+def test_training_resumes_from_a_checkpoint(P):
+    """Adam steps continued from a checkpoint (weights and both moments) in a
+    fresh state of another size give the same parameters, bit for bit, as the
+    uninterrupted run."""
+    n = 1024
+    X = _features(23, n)
+    T = np.stack([np.tanh(2 * X[:, 0]), -3.0 + X[:, 1]], 1)
+    Xd = torch.as_tensor(X, dtype=torch.float32, device=_dev())
+    Td = torch.as_tensor(T, dtype=torch.float32, device=_dev())
+    a = P.MlpState(n, _dev())
+    a.set_params(orl.pack(_params(5)).astype(np.float32))
+    for step in range(1, 11):
+        a.train_step(Xd, Td, 2e-3, step)
+    ckpt = a.save_state().cpu().numpy()
+    for step in range(11, 21):
+        a.train_step(Xd, Td, 2e-3, step)
+    b = P.MlpState(2 * n, _dev())
+    b.load_state(ckpt)
+    for step in range(11, 21):
+        b.train_step(Xd, Td, 2e-3, step)
+    torch.cuda.synchronize()
+    pa, pb = a.get_params().cpu().numpy(), b.get_params().cpu().numpy()
+    assert np.array_equal(pa, pb)
+    c = P.MlpState(n, _dev())
+    c.set_params(ckpt[:P.MlpState.param_count()])          # weights alone: Adam restarts, a different path
+    for step in range(11, 21):
+        c.train_step(Xd, Td, 2e-3, step)
+    torch.cuda.synchronize()
+    assert not np.array_equal(pa, c.get_params().cpu().numpy())
+
+
 def _noisy_pair(seed, m, n, k1, k2, noise):
     r = synth.rng_for(seed, m, n)
     L = synth.gaussian_scene(r, m, n)
