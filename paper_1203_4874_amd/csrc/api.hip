@@ -144,7 +144,7 @@ bool col_fits(int Py, int cw, int esize) {
 }
 
 // Columns per column-pass strip: `want` (a power of two up to 16) if given,
-// else the widest strip of a 512-thread workgroup (two per CU) that still
+// else the widest strip of a workgroup of at most 512 threads (two or more per CU) that still
 // leaves at least 256 strips over the frame's channels; either way narrowed
 // until the strip fits.
 int choose_cw(int Py, int hx, int nch, int esize, int want) {
@@ -152,7 +152,7 @@ int choose_cw(int Py, int hx, int nch, int esize, int want) {
   if (cw > 16) cw = 16;
   while (cw & (cw - 1)) cw &= cw - 1;
   while (cw > 1 && (!col_fits(Py, cw, esize) ||
-                    (want <= 0 && (col_threads(Py, cw, esize) != 512 ||
+                    (want <= 0 && (col_threads(Py, cw, esize) > 512 ||
                                    (int64_t)((hx + cw - 1) / cw) * nch < 256))))
     cw >>= 1;
   return cw;
@@ -612,10 +612,10 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
       cv.items[Q_COL] = sq[cnt];
     }
     // the column pass runs a persistent grid: its workgroups load the next
-    // strip while finishing the current one (two 512-thread or one
-    // 1024-thread workgroup per CU)
-    cv.grid[Q_COL] = grid_for(cv.items[Q_COL], cap > 0 ? cap : (col_threads(cv.maxPy, cv.maxcw, esize) == 512 ? 2 : 1) *
-                                                                    kComputeUnits);
+    // strip while finishing the current one (four 256-thread, two
+    // 512-thread or one 1024-thread workgroup per CU)
+    cv.grid[Q_COL] = grid_for(cv.items[Q_COL],
+                              cap > 0 ? cap : 1024 / col_threads(cv.maxPy, cv.maxcw, esize) * kComputeUnits);
     bb->chunks.push_back(cv);
   }
   return CBP_OK;

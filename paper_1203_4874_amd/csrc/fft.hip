@@ -321,7 +321,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
   __shared__ int st[BATCH_CHUNK + 1];
   constexpr int SM = col_slots<T, NT>();
   constexpr int PF = (col_max_elems<T, NT>() + NT - 1) / NT;   // strip entries per thread
-  constexpr int LNT = NT == 1024 ? 10 : 9;
+  constexpr int LNT = NT == 1024 ? 10 : NT == 512 ? 9 : 8;
   const int nf = br.nframes;
   const int* sq = br.starts + (size_t)Q_COL * (nf + 1);
   for (int t = threadIdx.x; t <= nf; t += NT) st[t] = sq[t];
@@ -533,13 +533,17 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
 // twiddle table, rounded once to T: the column pass evaluates each kernel's
 // spectrum at (ky, kx) from these along y.  Once per frame, shared by its
 // channels.  Items: 256 consecutive entries of [0, hx * 2 * CBP_MAX_K).
+static_assert(2 * CBP_MAX_K == 64, "one column's entries fill one wave");
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_kernel_dft(batch_ref br) {
   for_items<Q_KRDFT>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
     const int e = item * 256 + (int)threadIdx.x;
     const int hx = d.hx, Px = d.Px;
     if (e >= hx * 2 * CBP_MAX_K) return;
-    const int kx = e / (2 * CBP_MAX_K), rem = e - kx * 2 * CBP_MAX_K;
+    // a wave's 64 entries share one column kx (2 CBP_MAX_K = 64): its
+    // twiddles are wave-uniform (scalar loads)
+    const int kx = __builtin_amdgcn_readfirstlane(e / (2 * CBP_MAX_K)), rem = e - kx * 2 * CBP_MAX_K;
     const int fr = rem / CBP_MAX_K, yy = rem - fr * CBP_MAX_K;
     const int k = fr ? d.k2 : d.k1;
     const double* K = fr ? d.K2 : d.K1;
@@ -669,21 +673,25 @@ size_t col_lds_bytes(int N, int cw, int esize) {
   return ((size_t)cw * (N | 1) + (size_t)cw * 2 * CBP_MAX_K + (size_t)N) * 2 * esize;
 }
 
-// Threads of the column-pass workgroup for a strip of cw * N entries: 512
-// while the strip fits their registers and cw <= 8 (one wave or more per
-// column), else 1024.
+// Threads of the column-pass workgroup for a strip of cw * N entries: the
+// fewest of 256 / 512 / 1024 whose registers hold the strip with at least
+// one wave per column (cw <= NT / 64).
 int col_threads(int N, int cw, int esize) {
-  const int lim = esize == 4 ? col_max_elems<float, 512>() : col_max_elems<double, 512>();
-  return (cw <= 8 && (int64_t)cw * N <= lim) ? 512 : 1024;
+  const int64_t e = (int64_t)cw * N;
+  const int l256 = esize == 4 ? col_max_elems<float, 256>() : col_max_elems<double, 256>();
+  const int l512 = esize == 4 ? col_max_elems<float, 512>() : col_max_elems<double, 512>();
+  if (cw <= 4 && e <= l256) return 256;
+  return (cw <= 8 && e <= l512) ? 512 : 1024;
 }
 
 int col_max_strip_elems(int esize) { return esize == 4 ? col_max_elems<float, 1024>() : col_max_elems<double, 1024>(); }
 
 void set_fft_attrs() {
-  const void* fns[8] = {(const void*)k_row_fwd<float>, (const void*)k_col_filter<float, 512>,
-                        (const void*)k_col_filter<float, 1024>, (const void*)k_row_inv<float>,
-                        (const void*)k_row_fwd<double>, (const void*)k_col_filter<double, 512>,
-                        (const void*)k_col_filter<double, 1024>, (const void*)k_row_inv<double>};
+  const void* fns[10] = {(const void*)k_row_fwd<float>, (const void*)k_col_filter<float, 256>,
+                         (const void*)k_col_filter<float, 512>, (const void*)k_col_filter<float, 1024>,
+                         (const void*)k_row_inv<float>, (const void*)k_row_fwd<double>,
+                         (const void*)k_col_filter<double, 256>, (const void*)k_col_filter<double, 512>,
+                         (const void*)k_col_filter<double, 1024>, (const void*)k_row_inv<double>};
   for (const void* f : fns) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
@@ -702,7 +710,10 @@ template <typename T>
 hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st) {
   prof_begin(PH_COL_FILTER, st);
   const size_t lds = col_lds_bytes(maxPy, maxcw, (int)sizeof(T));
-  if (col_threads(maxPy, maxcw, (int)sizeof(T)) == 512)
+  const int nt = col_threads(maxPy, maxcw, (int)sizeof(T));
+  if (nt == 256)
+    hipLaunchKernelGGL((k_col_filter<T, 256>), dim3(grid), dim3(256), lds, st, br);
+  else if (nt == 512)
     hipLaunchKernelGGL((k_col_filter<T, 512>), dim3(grid), dim3(512), lds, st, br);
   else
     hipLaunchKernelGGL((k_col_filter<T, 1024>), dim3(grid), dim3(1024), lds, st, br);
