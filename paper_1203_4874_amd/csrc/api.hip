@@ -136,7 +136,7 @@ struct tuning {
   int fft_order;   // radix pass order of the row and column FFTs
 };
 constexpr tuning kDefaultTuning = {128, 0, 0, 0};
-constexpr int kRowWgPerCu = 4;   // resident row-pass workgroups per CU (LDS: a row and a twiddle table of 2048 entries)
+constexpr int kRowWgPerCu = 4;   // resident inverse-row workgroups per CU (LDS: a row and a twiddle table of 2048 entries)
 
 // Does a strip of cw columns of length Py fit the column pass?
 bool col_fits(int Py, int cw, int esize) {
@@ -435,18 +435,16 @@ hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool 
                          const inline_head* ih) {
   const batch_ref b = {cv.descs, cv.starts, cv.nf};
   auto br = [&](int) { return b; };
-  // the column fold and, for the row pass that follows, the twiddle tables
-  // (the first launch: with an inline head it also stores the call's head)
-  CBP_TRY(launch_fold<T>(br(Q_FOLD), cv.grid[Q_FOLD], latent ? cv.grid[Q_TWID] : 0, ih, st));
+  // the first launch (with an inline head it also stores the call's head):
+  // a deblurring call's twiddle table of the kernels' row DFTs only, since
+  // its row pass folds the columns; a kernel-only call's column fold
+  CBP_TRY(launch_fold<T>(br(Q_FOLD), latent ? 0 : cv.grid[Q_FOLD], latent ? cv.grid[Q_TWID] : 0, ih, st));
   if (diag) CBP_TRY(launch_diag_init(br(Q_DIAG), cv.grid[Q_DIAG], st));
-  // the row pass (with the row evaluation) and, on extra workgroups, the
-  // column evaluation of the fold
-  if (latent) {
-    CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, cv.grid[Q_EVAL_COLS], st));
-  } else {
-    CBP_TRY(launch_eval_rows<T>(br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], st));
-    CBP_TRY(launch_eval_cols(br(Q_EVAL_COLS), cv.grid[Q_EVAL_COLS], st));
-  }
+  // the row pass (with the column fold and the row evaluation) or the row
+  // evaluation alone, then the column evaluation of the fold
+  if (latent) CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, st));
+  else CBP_TRY(launch_eval_rows<T>(br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], st));
+  CBP_TRY(launch_eval_cols(br(Q_EVAL_COLS), cv.grid[Q_EVAL_COLS], st));
   // join: the Gram needs the row evaluation (and the column pass the row spectra)
   if (cv.gram_fmt < 0) CBP_TRY(launch_gram(br(Q_GRAM), cv.grid[Q_GRAM], st));
   else CBP_TRY(launch_gram_mfma(br(Q_GRAMM), cv.grid[Q_GRAMM], cv.gram_fmt, cv.maxStride, st));
@@ -597,6 +595,8 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
       cv.maxcw = std::max(cv.maxcw, p.cw);
     }
     const int esize = dtype == CBP_F32 ? 4 : 8;
+    // as many persistent row-pass workgroups as stay resident
+    if (cap == 0) cv.grid[Q_ROW_FWD] = grid_for(cv.items[Q_ROW_FWD], row_fwd_per_cu(cv.maxPx, esize) * kComputeUnits);
     // the widest strip and the tallest column share one allocation; keep it in LDS
     while (cv.maxcw > 1 && !col_fits(cv.maxPy, cv.maxcw, esize)) {
       cv.maxcw >>= 1;

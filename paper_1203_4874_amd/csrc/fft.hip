@@ -20,6 +20,8 @@
 //      completed by Hermitian symmetry), one inverse FFT, real / imaginary
 //      parts are the two output rows, scaled by 1/(Py Px), cropped to n.
 // T is float (mixed form) or double (FP64 form).
+#include <algorithm>
+#include <atomic>
 #include "eigsmall.h"
 #include "internal.h"
 
@@ -132,38 +134,32 @@ __device__ __attribute__((always_inline)) inline void ip_fft(cplx<T>* buf, int l
 constexpr int ROW_MAXE = CBP_MAX_FFT_F32 > CBP_MAX_FFT_F64 ? CBP_MAX_FFT_F32 : CBP_MAX_FFT_F64;
 
 // ---------------------------------------------------------------- pass 1
-// Items: (row y, channel).  With with_ey, the unit-circle evaluation of both
-// rows (fold modulo S and S-point DFT, as k_eval_rows: the same lanes, the
-// same order, hence the same bits) is taken from the row in LDS; waves 0-3
-// fold (frame, residue parity) = (w & 1, w >> 1).
-// Workgroups [0, gr) run the row pass; the rest run the column evaluation
-// (its scratch carved from the dynamic LDS).  A row-pass workgroup that owns
-// several items loads the next item's rows into registers while it
+// Items: (channel, row group g, residue r): the rows y = g rpg + r + S i,
+// i < rpg / S, y < Hmax, in increasing y.  Each row of both frames is packed
+// as B1 + i B2 and transformed; while the rows pass, the workgroup folds them
+// (the column fold of k_fold_cols: the same rows of the same residue and
+// group, summed in increasing y in FP64, hence the same bits) and writes
+// the group's partial sums, so the frames are read once.  With with_ey, the
+// unit-circle evaluation of both rows (fold modulo S and S-point DFT, as
+// k_eval_rows: the same lanes, the same order, hence the same bits) is taken
+// from the row in LDS; waves 0-1 fold frame (w & 1).  The grid is
+// persistent: a workgroup loads its next row into registers while it
 // transforms the current one.
 static_assert(CBP_MAX_FFT_F32 <= 8 * 256 && CBP_MAX_FFT_F64 <= 8 * 256, "one row is eight loads per thread");
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int gr) {
+__global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
   extern __shared__ __attribute__((aligned(16))) char sm_rf[];
   __shared__ double gy[2][CBP_MAX_S];
   __shared__ double fpart_l[2][64];
   __shared__ c64 twS[CBP_MAX_S];
   __shared__ int st[BATCH_CHUNK + 1];
-  if ((int)blockIdx.x >= gr) {
-    double(*F)[16] = (double(*)[16])sm_rf;
-    c64* twe = (c64*)(sm_rf + (size_t)CBP_MAX_S * 16 * sizeof(double));
-    for_items_part<Q_EVAL_COLS>(br, (int)blockIdx.x - gr, (int)gridDim.x - gr,
-                                [&](const frame_desc& d, int item) __attribute__((always_inline)) {
-                                  eval_cols_item(d, item, F, twe);
-                                });
-    return;
-  }
   const int nf = br.nframes;
   const int* sq = br.starts + (size_t)Q_ROW_FWD * (nf + 1);
   for (int t = threadIdx.x; t <= nf; t += blockDim.x) st[t] = sq[t];
   __syncthreads();
   int first, end, step;
-  xcd_items(__builtin_amdgcn_readfirstlane(st[nf]), (int)blockIdx.x, gr, first, end, step);
+  xcd_items(__builtin_amdgcn_readfirstlane(st[nf]), (int)blockIdx.x, (int)gridDim.x, first, end, step);
   // frame of item it (st[fi] <= it < st[fi + 1]), wave-uniform
   auto frame_of = [&](int it) __attribute__((always_inline)) {
     int lo = 0, hi = nf;
@@ -185,102 +181,141 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey, int 
     return br.descs[fi];
 #endif
   };
-  // the two rows of item it into registers: eight loads per frame and
+  // item it -> (channel, first row y0, rows of the item below Hmax)
+  struct rows_of_item { int ch, g, r, y0, nv; };
+  auto item_rows = [&](const frame_desc& d, int item) __attribute__((always_inline)) {
+    const int S = d.S, RG = d.RG, gi = d.rpg / S;
+    rows_of_item q;
+    q.r = item % S;
+    const int rest = item / S;
+    q.g = rest % RG;
+    q.ch = rest / RG;
+    q.y0 = q.g * d.rpg + q.r;
+    q.nv = q.y0 >= d.Hmax ? 0 : min(gi, (d.Hmax - 1 - q.y0) / S + 1);
+    return q;
+  };
+  // the two rows y of channel ch into registers: eight loads per frame and
   // thread, from clamped (always valid) addresses; entries outside the frame
-  // are zeroed when they are stored to LDS
+  // are zeroed when they are used
   T uv[8], wv[8];
-  auto fetch = [&](int it) __attribute__((always_inline)) {
-    const int fi = frame_of(it);
-    const frame_desc d = desc(fi);
-    const int item = it - __builtin_amdgcn_readfirstlane(st[fi]);
-    const int y = item % d.Hmax, ch = item / d.Hmax;
+  auto fetch = [&](const frame_desc& d, int ch, int y) __attribute__((always_inline)) {
     // row pointers clamped to each frame's last row (rows past it read as zero)
     const T* r1 = (const T*)d.b1 + ch * d.cs1 + (int64_t)min(y, d.H1 - 1) * d.p1;
     const T* r2 = (const T*)d.b2 + ch * d.cs2 + (int64_t)min(y, d.H2 - 1) * d.p2;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const int x = t * 256 + (int)threadIdx.x;
+      const int x = t * 256 + local_tid();
       uv[t] = r1[min(x, d.W1 - 1)];
       wv[t] = r2[min(x, d.W2 - 1)];
     }
   };
-  if (first < end) fetch(first);
+  // the first row of the first item at or after it that has rows (it >= end: none)
+  auto fetch_from = [&](int it) __attribute__((always_inline)) {
+    for (; it < end; it += step) {
+      const int fi = frame_of(it);
+      const frame_desc d = desc(fi);
+      const rows_of_item q = item_rows(d, it - __builtin_amdgcn_readfirstlane(st[fi]));
+      if (q.nv > 0) {
+        fetch(d, q.ch, q.y0);
+        return;
+      }
+    }
+  };
+  fetch_from(first);
   int tabN = 0;   // length of the twiddle table in LDS
   for (int it = first; it < end; it += step) {
     const int fi = frame_of(it);
     const frame_desc d = desc(fi);
-    const int item = it - __builtin_amdgcn_readfirstlane(st[fi]);
+    const rows_of_item q = item_rows(d, it - __builtin_amdgcn_readfirstlane(st[fi]));
     const fft_plan& px = d.fx;
-    const int N = px.N, hx = d.hx;
+    const int N = px.N, hx = d.hx, S = d.S;
     cplx<T>* a = (cplx<T>*)sm_rf;
     cplx<T>* twf = a + N;
-    full_twiddles(twf, N, tabN);
-    const int y = item % d.Hmax, ch = item / d.Hmax;
-    const bool in1 = y < d.H1, in2 = y < d.H2;
-    if (with_ey)
-      for (int t = threadIdx.x; t < d.S; t += blockDim.x) {
-        double sn, cs;
-        sincospi(-2.0 * (double)t / (double)d.S, &sn, &cs);
-        twS[t] = {cs, sn};
-      }
-    {
-      const int W1 = d.W1, W2 = d.W2;
+    const int ch = q.ch;
+    const int W1 = d.W1, W2 = d.W2;
+    // the column fold of this item's rows, both frames (FP64, increasing y)
+    double f1[8], f2[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) f1[t] = f2[t] = 0.0;
+    for (int i = 0; i < q.nv; ++i) {
+      const int y = q.y0 + S * i;
+      const bool in1 = y < d.H1, in2 = y < d.H2;
+      full_twiddles(twf, N, tabN);
+      if (with_ey)
+        for (int t = threadIdx.x; t < S; t += blockDim.x) {
+          double sn, cs;
+          sincospi(-2.0 * (double)t / (double)S, &sn, &cs);
+          twS[t] = {cs, sn};
+        }
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
-        const int x = t * 256 + (int)threadIdx.x;
-        if (x < N) a[x] = {(in1 && x < W1) ? uv[t] : T(0), (in2 && x < W2) ? wv[t] : T(0)};
-      }
-    }
-    __syncthreads();
-    // the next item's rows are in flight while this one is transformed
-    if (it + step < end) fetch(it + step);
-    if (with_ey) {
-      // the row evaluation of both rows (k_eval_rows's lanes and order):
-      // wave fr folds frame fr's row into partials, lane g S + r summing
-      // x = r + S (g + G i); the residues then add their G partials in order
-      const int S = d.S, G = 64 / S;
-      const int wvi = threadIdx.x >> 6, l = threadIdx.x & 63;
-      const int gl = l / S, r = l - gl * S;
-      if (wvi < 2) {
-        const int W = wvi ? d.W2 : d.W1;
-        double acc = 0.0;
-        if ((wvi ? in2 : in1) && gl < G)
-          for (int x = r + S * gl; x < W; x += S * G) acc += (double)(wvi ? a[x].im : a[x].re);
-        fpart_l[wvi][l] = acc;
+        const int x = t * 256 + local_tid();
+        const T u1 = (in1 && x < W1) ? uv[t] : T(0), u2 = (in2 && x < W2) ? wv[t] : T(0);
+        f1[t] += (double)u1;
+        f2[t] += (double)u2;
+        if (x < N) a[x] = {u1, u2};
       }
       __syncthreads();
-      if (wvi < 2 && l < S) {
-        double sr = fpart_l[wvi][l];
-        for (int q = 1; q < G; ++q) sr += fpart_l[wvi][q * S + l];
-        gy[wvi][l] = sr;
-      }
-      __syncthreads();
-      if (wvi < 2 && l < S && (wvi ? in2 : in1)) {
-        const int fr = wvi;
-        c64 e = {0.0, 0.0};
-        int t = 0;
-        for (int rr = 0; rr < S; ++rr) {
-          const double f = gy[fr][rr];
-          e.re += f * twS[t].re;
-          e.im += f * twS[t].im;
-          t += l;
-          if (t >= S) t -= S;
+      // the next row is in flight while this one is transformed
+      if (i + 1 < q.nv) fetch(d, ch, y + S);
+      else fetch_from(it + step);
+      if (with_ey) {
+        // the row evaluation of both rows (k_eval_rows's lanes and order):
+        // wave fr folds frame fr's row into partials, lane g S + r summing
+        // x = r + S (g + G i); the residues then add their G partials in order
+        const int G = 64 / S;
+        const int wvi = threadIdx.x >> 6, l = threadIdx.x & 63;
+        const int gl = l / S, rr0 = l - gl * S;
+        if (wvi < 2) {
+          const int W = wvi ? W2 : W1;
+          double acc = 0.0;
+          if ((wvi ? in2 : in1) && gl < G)
+            for (int x = rr0 + S * gl; x < W; x += S * G) acc += (double)(wvi ? a[x].im : a[x].re);
+          fpart_l[wvi][l] = acc;
         }
-        d.ey[((size_t)(2 * ch + fr) * S + l) * d.Hmax + y] = e;
+        __syncthreads();
+        if (wvi < 2 && l < S) {
+          double sr = fpart_l[wvi][l];
+          for (int gq = 1; gq < G; ++gq) sr += fpart_l[wvi][gq * S + l];
+          gy[wvi][l] = sr;
+        }
+        __syncthreads();
+        if (wvi < 2 && l < S && (wvi ? in2 : in1)) {
+          const int fr = wvi;
+          c64 e = {0.0, 0.0};
+          int t = 0;
+          for (int rr = 0; rr < S; ++rr) {
+            const double f = gy[fr][rr];
+            e.re += f * twS[t].re;
+            e.im += f * twS[t].im;
+            t += l;
+            if (t >= S) t -= S;
+          }
+          d.ey[((size_t)(2 * ch + fr) * S + l) * d.Hmax + y] = e;
+        }
       }
+      ip_fft<-1, 256, ROW_MAXE, true>(a, N, px, twf, 1);
+      const cplx<T>* z = a;
+      cplx<T>* o1 = (cplx<T>*)d.t1 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
+      cplx<T>* o2 = (cplx<T>*)d.t2 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
+      for (int k = threadIdx.x; k < hx; k += blockDim.x) {
+        const cplx<T> zk = z[k];
+        const cplx<T> zn = conj(z[k == 0 ? 0 : N - k]);
+        const cplx<T> s = zk + zn, df = zk - zn;
+        if (in1) o1[k] = {T(0.5) * s.re, T(0.5) * s.im};       // (Z_k + conj Z_{N-k}) / 2
+        if (in2) o2[k] = {T(0.5) * df.im, T(-0.5) * df.re};    // (Z_k - conj Z_{N-k}) / (2i)
+      }
+      __syncthreads();
     }
-    ip_fft<-1, 256, ROW_MAXE, true>(a, N, px, twf, 1);
-    const cplx<T>* z = a;
-    cplx<T>* o1 = (cplx<T>*)d.t1 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
-    cplx<T>* o2 = (cplx<T>*)d.t2 + (int64_t)ch * d.Hmax * d.hxp + (int64_t)y * d.hxp;
-    for (int k = threadIdx.x; k < hx; k += blockDim.x) {
-      const cplx<T> zk = z[k];
-      const cplx<T> zn = conj(z[k == 0 ? 0 : N - k]);
-      const cplx<T> s = zk + zn, df = zk - zn;
-      if (in1) o1[k] = {T(0.5) * s.re, T(0.5) * s.im};       // (Z_k + conj Z_{N-k}) / 2
-      if (in2) o2[k] = {T(0.5) * df.im, T(-0.5) * df.re};    // (Z_k - conj Z_{N-k}) / (2i)
+    // the group's column-fold partials (k_fold_cols's layout), for x < W
+    double* fp1 = d.fpart + (((size_t)q.g * d.ncf + 2 * ch) * S + q.r) * (size_t)d.Wmax;
+    double* fp2 = d.fpart + (((size_t)q.g * d.ncf + 2 * ch + 1) * S + q.r) * (size_t)d.Wmax;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int x = t * 256 + local_tid();
+      if (x < W1) fp1[x] = f1[t];
+      if (x < W2) fp2[x] = f2[t];
     }
-    __syncthreads();
   }
 }
 
@@ -686,6 +721,25 @@ int col_threads(int N, int cw, int esize) {
 
 int col_max_strip_elems(int esize) { return esize == 4 ? col_max_elems<float, 1024>() : col_max_elems<double, 1024>(); }
 
+// Resident row-pass workgroups per CU (registers and LDS of a row of maxPx),
+// for the persistent grid: a workgroup beyond that would start only when
+// another ends and leave a tail.
+// Kept per (element size, row length rounded up to 256).
+int row_fwd_per_cu(int maxPx, int esize) {
+  static std::atomic<int> cache[2][9];
+  const int b = std::min(std::max((maxPx + 255) / 256, 1), 8);
+  std::atomic<int>& c = cache[esize == 8][b];
+  int n = c.load(std::memory_order_relaxed);
+  if (n > 0) return n;
+  const void* f = esize == 8 ? (const void*)k_row_fwd<double> : (const void*)k_row_fwd<float>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, row_lds_bytes(256 * b, esize)) != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  c.store(n, std::memory_order_relaxed);
+  return n;
+}
+
 void set_fft_attrs() {
   const void* fns[10] = {(const void*)k_row_fwd<float>, (const void*)k_col_filter<float, 256>,
                          (const void*)k_col_filter<float, 512>, (const void*)k_col_filter<float, 1024>,
@@ -696,12 +750,9 @@ void set_fft_attrs() {
 }
 
 template <typename T>
-hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey, int eval_grid,
-                          hipStream_t st) {
+hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey, hipStream_t st) {
   prof_begin(PH_ROW_FWD, st);
-  size_t lds = row_lds_bytes(maxPx, (int)sizeof(T));
-  if (eval_grid > 0 && lds < kEvalColsLds) lds = kEvalColsLds;
-  hipLaunchKernelGGL(k_row_fwd<T>, dim3(grid + eval_grid), dim3(256), lds, st, br, with_ey, grid);
+  hipLaunchKernelGGL(k_row_fwd<T>, dim3(grid), dim3(256), row_lds_bytes(maxPx, (int)sizeof(T)), st, br, with_ey);
   prof_end(PH_ROW_FWD, st);
   return hipGetLastError();
 }
@@ -738,8 +789,8 @@ hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t 
 }
 
 
-template hipError_t launch_row_fwd<float>(const batch_ref&, int, int, int, int, hipStream_t);
-template hipError_t launch_row_fwd<double>(const batch_ref&, int, int, int, int, hipStream_t);
+template hipError_t launch_row_fwd<float>(const batch_ref&, int, int, int, hipStream_t);
+template hipError_t launch_row_fwd<double>(const batch_ref&, int, int, int, hipStream_t);
 template hipError_t launch_col<float>(const batch_ref&, int, int, int, hipStream_t);
 template hipError_t launch_col<double>(const batch_ref&, int, int, int, hipStream_t);
 template hipError_t launch_kernel_dft<float>(const batch_ref&, int, hipStream_t);

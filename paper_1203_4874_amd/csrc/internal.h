@@ -99,7 +99,7 @@ inline int queue_items(int q, const frame_plan& p) {
     case Q_FOLD: return ((p.Wmax + 63) / 64) * p.S * p.RG * ncf;
     case Q_EVAL_COLS: return ((p.Wmax + 15) / 16) * ncf;
     case Q_EVAL_ROWS: return ((p.Hmax + 3) / 4) * ncf;
-    case Q_ROW_FWD: return p.Hmax * p.nch;
+    case Q_ROW_FWD: return p.nch * p.RG * p.S;   // (channel, row group, residue); rows y < Hmax of each
     case Q_GRAM: return (2 * p.N - 1) * p.S * 2;
     case Q_GRAMM: return p.S * 2;
     case Q_SAMPLE: return p.S * 2;
@@ -233,7 +233,6 @@ __device__ inline void eval_cols_item(const frame_desc& d, int item, double (*F)
     d.ex[((size_t)cf * S + j) * Wmax + x] = acc;
   }
 }
-constexpr size_t kEvalColsLds = (size_t)CBP_MAX_S * 16 * sizeof(double) + (size_t)CBP_MAX_S * sizeof(c64);
 #endif
 
 // ---------------------------------------------------------------- phase timing
@@ -296,13 +295,11 @@ hipError_t launch_gram_mfma(const batch_ref& br, int grid, int fmt, int maxStrid
 size_t gram_mfma_lds_bytes(int maxStride, int fmt);
 void set_gram_mfma_attrs();
 
-// fft.hip.  with_ey: the row pass also writes the row evaluation EY (the
-// k_eval_rows result, bit for bit) from the rows it already holds.
-// launch_row_fwd runs the column evaluation too, on eval_grid more workgroups
-// (items of Q_EVAL_COLS; it needs the column fold, the row pass does not).
+// fft.hip.  The row pass also writes the column fold's partials (the
+// k_fold_cols result, bit for bit) and, with with_ey, the row evaluation EY
+// (the k_eval_rows result, bit for bit) from the rows it already holds.
 template <typename T>
-hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey, int eval_grid,
-                          hipStream_t st);
+hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey, hipStream_t st);
 template <typename T>
 hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st);
 template <typename T>
@@ -310,6 +307,7 @@ hipError_t launch_kernel_dft(const batch_ref& br, int grid, hipStream_t st);
 template <typename T>
 hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t st);
 size_t row_lds_bytes(int N, int esize);
+int row_fwd_per_cu(int maxPx, int esize);
 size_t col_lds_bytes(int N, int cw, int esize);
 int col_max_strip_elems(int esize);   // largest cw * Py the column pass holds
 int col_threads(int N, int cw, int esize);   // column-pass workgroup size for a strip
