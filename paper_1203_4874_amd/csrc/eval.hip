@@ -148,10 +148,7 @@ __global__ __launch_bounds__(256) void k_eval_rows(batch_ref br) {
     const int gl = l / S, r = l - gl * S;
     unit_twiddles(tw, S);
     double acc = 0.0;
-    if (y < H && gl < G) {
-      const T* row = b + (int64_t)y * pitch;
-      for (int x = r + S * gl; x < W; x += S * G) acc += (double)row[x];
-    }
+    if (y < H && gl < G) acc = fold_strided(b + (int64_t)y * pitch, 1, r + S * gl, S * G, W);
     part[w][l] = acc;
     __syncthreads();
     if (l < S) {
@@ -160,18 +157,7 @@ __global__ __launch_bounds__(256) void k_eval_rows(batch_ref br) {
       g[w][l] = sr;
     }
     __syncthreads();
-    if (y < H && l < S) {
-      c64 e = {0.0, 0.0};
-      int t = 0;
-      for (int rr = 0; rr < S; ++rr) {
-        const double f = g[w][rr];
-        e.re += f * tw[t].re;
-        e.im += f * tw[t].im;
-        t += l;
-        if (t >= S) t -= S;
-      }
-      d.ey[((size_t)cf * S + l) * d.Hmax + y] = e;
-    }
+    if (y < H && l < S) d.ey[((size_t)cf * S + l) * d.Hmax + y] = dft_at(g[w], tw, S, l);
   });
 }
 

@@ -223,6 +223,7 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
   };
   fetch_from(first);
   int tabN = 0;   // length of the twiddle table in LDS
+  int tabS = 0;   // S of the unit twiddles in twS
   for (int it = first; it < end; it += step) {
     const int fi = frame_of(it);
     const frame_desc d = desc(fi);
@@ -241,12 +242,12 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
       const int y = q.y0 + S * i;
       const bool in1 = y < d.H1, in2 = y < d.H2;
       full_twiddles(twf, N, tabN);
-      if (with_ey)
-        for (int t = threadIdx.x; t < S; t += blockDim.x) {
-          double sn, cs;
-          sincospi(-2.0 * (double)t / (double)S, &sn, &cs);
-          twS[t] = {cs, sn};
-        }
+      if (with_ey && S != tabS) {
+        // w_t for the row evaluation (made again only when S changes; the
+        // barrier after the row's store orders it before its use)
+        unit_twiddles(twS, S);
+        tabS = S;
+      }
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int x = t * 256 + local_tid();
@@ -269,8 +270,7 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
         if (wvi < 2) {
           const int W = wvi ? W2 : W1;
           double acc = 0.0;
-          if ((wvi ? in2 : in1) && gl < G)
-            for (int x = rr0 + S * gl; x < W; x += S * G) acc += (double)(wvi ? a[x].im : a[x].re);
+          if ((wvi ? in2 : in1) && gl < G) acc = fold_strided((const T*)a + wvi, 2, rr0 + S * gl, S * G, W);
           fpart_l[wvi][l] = acc;
         }
         __syncthreads();
@@ -280,19 +280,8 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
           gy[wvi][l] = sr;
         }
         __syncthreads();
-        if (wvi < 2 && l < S && (wvi ? in2 : in1)) {
-          const int fr = wvi;
-          c64 e = {0.0, 0.0};
-          int t = 0;
-          for (int rr = 0; rr < S; ++rr) {
-            const double f = gy[fr][rr];
-            e.re += f * twS[t].re;
-            e.im += f * twS[t].im;
-            t += l;
-            if (t >= S) t -= S;
-          }
-          d.ey[((size_t)(2 * ch + fr) * S + l) * d.Hmax + y] = e;
-        }
+        if (wvi < 2 && l < S && (wvi ? in2 : in1))
+          d.ey[((size_t)(2 * ch + wvi) * S + l) * d.Hmax + y] = dft_at(gy[wvi], twS, S, l);
       }
       ip_fft<-1, 256, ROW_MAXE, true>(a, N, px, twf, 1);
       const cplx<T>* z = a;

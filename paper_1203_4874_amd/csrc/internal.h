@@ -190,6 +190,53 @@ __device__ inline void unit_twiddles(c64* tw, int S) {
   }
 }
 
+// sum_i p[(x0 + i step) stride] over x0 + i step < W, in increasing i, in
+// FP64: eight loads are issued before their (ordered) additions.
+template <typename T>
+__device__ __attribute__((always_inline)) inline double fold_strided(const T* p, int stride, int x0, int step, int W) {
+  double acc = 0.0;
+  int x = x0;
+  for (; x + 7 * step < W; x += 8 * step) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(x + u * step) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (double)v[u];
+  }
+  for (; x < W; x += step) acc += (double)p[(size_t)x * stride];
+  return acc;
+}
+
+// sum_r f[r] w_(j r mod S), r < S, in increasing r (w from unit_twiddles):
+// four terms' operands are loaded before their (ordered) accumulation.
+__device__ __attribute__((always_inline)) inline c64 dft_at(const double* f, const c64* tw, int S, int j) {
+  c64 e = {0.0, 0.0};
+  int t = 0, r = 0;
+  for (; r + 4 <= S; r += 4) {
+    double fv[4];
+    c64 wv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      fv[u] = f[r + u];
+      wv[u] = tw[t];
+      t += j;
+      if (t >= S) t -= S;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      e.re += fv[u] * wv[u].re;
+      e.im += fv[u] * wv[u].im;
+    }
+  }
+  for (; r < S; ++r) {
+    e.re += f[r] * tw[t].re;
+    e.im += f[r] * tw[t].im;
+    t += j;
+    if (t >= S) t -= S;
+  }
+  return e;
+}
+
 // One item of the column evaluation (Sec. 4 eq. 3: the S-point DFT of the
 // column fold): the row-group partials of 16 columns of one (channel, frame)
 // summed in group order into F[r][column], then EX[cf][j][x] = sum_r
@@ -210,6 +257,17 @@ __device__ inline void eval_cols_item(const frame_desc& d, int item, double (*F)
       const double* p = d.fpart + ((size_t)cf * S + r) * Wmax + x;
       const size_t gs = (size_t)d.ncf * S * Wmax;
       int g = 0;
+      // eight groups' loads in flight; even groups into s0, odd into s1
+      for (; g + 8 <= RG; g += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(g + u) * gs];
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          s0 += v[u];
+          s1 += v[u + 1];
+        }
+      }
       for (; g + 2 <= RG; g += 2) {
         s0 += p[(size_t)g * gs];
         s1 += p[(size_t)(g + 1) * gs];
