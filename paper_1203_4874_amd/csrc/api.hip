@@ -136,22 +136,22 @@ struct tuning {
   int fft_order;   // radix pass order of the row and column FFTs
 };
 constexpr tuning kDefaultTuning = {128, 0, 0, 0};
-constexpr int kRowWgPerCu = 4;   // resident inverse-row workgroups per CU (LDS: a row and a twiddle table of 2048 entries)
+constexpr int kRowWgPerCu = 4;   // resident inverse-row workgroups per CU (LDS: a row and its pass twiddle tables)
 
 // Does a strip of cw columns of length Py fit the column pass?
-bool col_fits(int Py, int cw, int esize) {
-  return col_lds_bytes(Py, cw, esize) <= kLdsLimit - 4096 && (int64_t)cw * Py <= col_max_strip_elems(esize);
+bool col_fits(int Py, int cw, int twn, int esize) {
+  return col_lds_bytes(Py, cw, twn, esize) <= kLdsLimit - 4096 && (int64_t)cw * Py <= col_max_strip_elems(esize);
 }
 
 // Columns per column-pass strip: `want` (a power of two up to 16) if given,
 // else the widest strip of a workgroup of at most 512 threads (two or more per CU) that still
 // leaves at least 256 strips over the frame's channels; either way narrowed
 // until the strip fits.
-int choose_cw(int Py, int hx, int nch, int esize, int want) {
+int choose_cw(int Py, int hx, int nch, int twn, int esize, int want) {
   int cw = want > 0 ? want : 8;
   if (cw > 16) cw = 16;
   while (cw & (cw - 1)) cw &= cw - 1;
-  while (cw > 1 && (!col_fits(Py, cw, esize) ||
+  while (cw > 1 && (!col_fits(Py, cw, twn, esize) ||
                     (want <= 0 && (col_threads(Py, cw, esize) > 512 ||
                                    (int64_t)((hx + cw - 1) / cw) * nch < 256))))
     cw >>= 1;
@@ -237,13 +237,15 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
     return CBP_E_SHAPE;
   fp->hx = fp->Px / 2 + 1;
   fp->hxp = pitch_of(fp->hx, esize);
-  fp->cw = choose_cw(fp->Py, fp->hx, fp->nch, esize, tn.cw);
+  fp->twy = pass_table_entries(fp->fy);
+  fp->twx = pass_table_entries(fp->fx);
+  fp->cw = choose_cw(fp->Py, fp->hx, fp->nch, fp->twy, esize, tn.cw);
   const int gfmt = gram_format(o->precision);
   if (gfmt >= 0 && (fp->N > 32 || gram_mfma_lds_bytes(std::max(fp->Hmax, fp->Wmax), gfmt) > kLdsLimit - 2048))
     return CBP_E_UNSUPPORTED;
   if (o->learned && fp->N > 32) return CBP_E_UNSUPPORTED;   // 32 spectrum features per sample
   if (sample_lds_bytes(fp->N) > kLdsLimit - 2048 || finalize_lds_bytes(S, o->learned != 0) > kLdsLimit - 2048 ||
-      row_lds_bytes(fp->Px, esize) > kLdsLimit - 2048 || !col_fits(fp->Py, fp->cw, esize))
+      row_lds_bytes(fp->Px, fp->twx, esize) > kLdsLimit - 2048 || !col_fits(fp->Py, fp->cw, fp->twy, esize))
     return CBP_E_SHAPE;
   layout(fp, regions(fp->Hmax, fp->Wmax, kmax, S, fp->nch, esize));
   return CBP_OK;
@@ -418,6 +420,7 @@ struct chunk_view {
   int items[Q_COUNT];
   int grid[Q_COUNT];
   int maxN, maxS, maxPx, maxPy, maxcw;
+  int maxTwx, maxTwy;   // largest row / column pass twiddle tables (entries)
   int gram_fmt;   // gram_format() of the call's precision
   int maxStride;  // largest Hmax / Wmax (matrix-core Gram staging)
   const void* mlp;  // the learned form's network (device mlp blob) or NULL
@@ -442,7 +445,7 @@ hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool 
   if (diag) CBP_TRY(launch_diag_init(br(Q_DIAG), cv.grid[Q_DIAG], st));
   // the row pass (with the column fold and the row evaluation) or the row
   // evaluation alone, then the column evaluation of the fold
-  if (latent) CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, 1, st));
+  if (latent) CBP_TRY(launch_row_fwd<T>(br(Q_ROW_FWD), cv.grid[Q_ROW_FWD], cv.maxPx, cv.maxTwx, 1, st));
   else CBP_TRY(launch_eval_rows<T>(br(Q_EVAL_ROWS), cv.grid[Q_EVAL_ROWS], st));
   CBP_TRY(launch_eval_cols(br(Q_EVAL_COLS), cv.grid[Q_EVAL_COLS], st));
   // join: the Gram needs the row evaluation (and the column pass the row spectra)
@@ -461,8 +464,8 @@ hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool 
   }
   if (latent) {
     CBP_TRY(launch_kernel_dft<T>(br(Q_KRDFT), cv.grid[Q_KRDFT], st));
-    CBP_TRY(launch_col<T>(br(Q_COL), cv.grid[Q_COL], cv.maxPy, cv.maxcw, st));
-    CBP_TRY(launch_row_inv<T>(br(Q_ROW_INV), cv.grid[Q_ROW_INV], cv.maxPx, st));
+    CBP_TRY(launch_col<T>(br(Q_COL), cv.grid[Q_COL], cv.maxPy, cv.maxcw, cv.maxTwy, st));
+    CBP_TRY(launch_row_inv<T>(br(Q_ROW_INV), cv.grid[Q_ROW_INV], cv.maxPx, cv.maxTwx, st));
   }
   return hipSuccess;
 }
@@ -593,12 +596,14 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
       cv.maxPx = std::max(cv.maxPx, p.Px);
       cv.maxPy = std::max(cv.maxPy, p.Py);
       cv.maxcw = std::max(cv.maxcw, p.cw);
+      cv.maxTwx = std::max(cv.maxTwx, p.twx);
+      cv.maxTwy = std::max(cv.maxTwy, p.twy);
     }
     const int esize = dtype == CBP_F32 ? 4 : 8;
     // as many persistent row-pass workgroups as stay resident
-    if (cap == 0) cv.grid[Q_ROW_FWD] = grid_for(cv.items[Q_ROW_FWD], row_fwd_per_cu(cv.maxPx, esize) * kComputeUnits);
+    if (cap == 0) cv.grid[Q_ROW_FWD] = grid_for(cv.items[Q_ROW_FWD], row_fwd_per_cu(row_lds_bytes(cv.maxPx, cv.maxTwx, esize), esize) * kComputeUnits);
     // the widest strip and the tallest column share one allocation; keep it in LDS
-    while (cv.maxcw > 1 && !col_fits(cv.maxPy, cv.maxcw, esize)) {
+    while (cv.maxcw > 1 && !col_fits(cv.maxPy, cv.maxcw, cv.maxTwy, esize)) {
       cv.maxcw >>= 1;
       for (int i = 0; i < cnt; ++i) {
         frame_plan& p = bb->plans[f0 + i];

@@ -32,9 +32,9 @@ namespace {
 // ---------------------------------------------------------------- in-place passes
 // The transforms run in place in LDS: every pass reads its butterflies'
 // inputs into registers, synchronises, and writes the outputs over them (one
-// buffer instead of a ping-pong pair).  Twiddles w_N^t come from a full
-// N-entry table in LDS, FP64 sincospi rounded once to T (one read per
-// twiddle).
+// buffer instead of a ping-pong pair).  Twiddles come from the plan's pass
+// tables in LDS (fft_core.h tw_pitch), FP64 sincospi rounded once to T (one
+// read per twiddle).
 
 // threadIdx.x behind an empty asm statement: values derived from it are
 // recomputed where they are used instead of being hoisted out of the item
@@ -62,18 +62,45 @@ __device__ __attribute__((always_inline)) inline void full_twiddles(cplx<T>* tw,
   tabN = N;
 }
 
+// The pass twiddle tables of plan p into tws when they hold another plan's
+// (tabN, tabCode: the length and pass order they hold, wave-uniform); the
+// caller synchronises before use.  Entry k P + r - 1 of the pass with stride
+// Ns is w_(Ns R)^(r k): the angle r k / (Ns R) equals r k (N / (Ns R)) / N
+// exactly in FP64, so the values are those of the full table w_N^t.
+template <typename T>
+__device__ __attribute__((always_inline)) inline void pass_twiddles(cplx<T>* tws, const fft_plan& p, int& tabN,
+                                                                    unsigned long long& tabCode) {
+  if (tabN == p.N && tabCode == p.code) return;
+  int Ns = 1, off = 0;
+  for (int s = 0; s < p.npass; ++s) {
+    const int R = plan_radix(p, s);
+    if (Ns > 1) {
+      const int P = tw_pitch(R), n = Ns * P;
+      for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int k = e / P, r = e - k * P + 1;
+        double sn = 0.0, cs = 1.0;
+        if (r < R) sincospi(-2.0 * (double)(r * k) / (double)(Ns * R), &sn, &cs);
+        tws[off + e] = {T(cs), T(sn)};
+      }
+      off += n;
+    }
+    Ns *= R;
+  }
+  tabN = p.N;
+  tabCode = p.code;
+}
+
 // One radix-R pass (stride Ns) over ncol transforms of length N at
 // buf + c ld, in place: butterfly j of transform c reads
 // buf[c ld + j + r N/R] and writes buf[c ld + (j - k) R + k + r Ns],
 // k = j mod Ns (the Stockham indexing of fft_core.h, read and write phases
-// separated by a barrier).  ncol N <= MAXE.
+// separated by a barrier); tws: the pass's twiddle table.  ncol N <= MAXE.
 template <int R, int DIR, int NT, int MAXE, typename T>
 __device__ __attribute__((always_inline)) inline void ip_pass(cplx<T>* buf, int ld, int N, int Ns,
-                                                              const cplx<T>* tw, int ncol) {
+                                                              const cplx<T>* tws, int ncol) {
   constexpr int MB = ip_mb<NT, R, MAXE>();
   const int NR = N / R;
   const int total = NR * ncol;
-  const int twstep = N / (Ns * R);
   const float rnr = 1.0f / (float)NR, rns = 1.0f / (float)Ns;
   cplx<T> v[MB][R];
   int pos[MB];
@@ -87,8 +114,8 @@ __device__ __attribute__((always_inline)) inline void ip_pass(cplx<T>* buf, int 
       const int j = b - mul24(c, NR);
       const int k = j - mul24(fdiv_floor(j, rns), Ns);
       const cplx<T>* src = buf + mul24(c, ld);
-      const int base = Ns > 1 ? stockham_read<R, DIR, true>(src, NR, twstep, tw, j, k, v[q])
-                              : stockham_read<R, DIR, false>(src, NR, twstep, tw, j, k, v[q]);
+      const int base = Ns > 1 ? stockham_read<R, DIR, true>(src, NR, tws, j, k, v[q])
+                              : stockham_read<R, DIR, false>(src, NR, tws, j, k, v[q]);
       pos[q] = mul24(c, ld) + base;
     }
   }
@@ -102,30 +129,34 @@ __device__ __attribute__((always_inline)) inline void ip_pass(cplx<T>* buf, int 
   __syncthreads();
 }
 
-// All passes of plan p over ncol transforms (ncol p.N <= MAXE), in place.
-// R9: the plan may hold radix-9 passes (the row plans; the column plans do
-// not, which keeps the column pass's registers at the radix-8 pass).
+// All passes of plan p over ncol transforms (ncol p.N <= MAXE), in place;
+// tws: the plan's pass tables (pass_twiddles).  R9: the plan may hold
+// radix-9 passes (the row plans; the column plans do not, which keeps the
+// column pass's registers at the radix-8 pass).
 template <int DIR, int NT, int MAXE, bool R9 = false, typename T>
 __device__ __attribute__((always_inline)) inline void ip_fft(cplx<T>* buf, int ld, const fft_plan& p,
-                                                             const cplx<T>* tw, int ncol) {
+                                                             const cplx<T>* tws, int ncol) {
   int Ns = 1;
+  const cplx<T>* t = tws;   // this pass's table (the first pass, Ns = 1, has none)
   for (int s = 0; s < p.npass; ++s) {
     const int R = plan_radix(p, s);
     if constexpr (R9) {
       if (R == 9) {
-        ip_pass<9, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol);
+        ip_pass<9, DIR, NT, MAXE>(buf, ld, p.N, Ns, t, ncol);
+        if (Ns > 1) t += Ns * tw_pitch(9);
         Ns *= 9;
         continue;
       }
     }
     switch (R) {
-      case 2: ip_pass<2, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
-      case 3: ip_pass<3, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
-      case 4: ip_pass<4, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
-      case 5: ip_pass<5, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
-      case 7: ip_pass<7, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
-      default: ip_pass<8, DIR, NT, MAXE>(buf, ld, p.N, Ns, tw, ncol); break;
+      case 2: ip_pass<2, DIR, NT, MAXE>(buf, ld, p.N, Ns, t, ncol); break;
+      case 3: ip_pass<3, DIR, NT, MAXE>(buf, ld, p.N, Ns, t, ncol); break;
+      case 4: ip_pass<4, DIR, NT, MAXE>(buf, ld, p.N, Ns, t, ncol); break;
+      case 5: ip_pass<5, DIR, NT, MAXE>(buf, ld, p.N, Ns, t, ncol); break;
+      case 7: ip_pass<7, DIR, NT, MAXE>(buf, ld, p.N, Ns, t, ncol); break;
+      default: ip_pass<8, DIR, NT, MAXE>(buf, ld, p.N, Ns, t, ncol); break;
     }
+    if (Ns > 1) t += Ns * tw_pitch(R);
     Ns *= R;
   }
 }
@@ -222,8 +253,9 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
     }
   };
   fetch_from(first);
-  int tabN = 0;   // length of the twiddle table in LDS
-  int tabS = 0;   // S of the unit twiddles in twS
+  int tabN = 0;                  // plan of the pass tables in LDS (length,
+  unsigned long long tabCode = 0;  // pass order)
+  int tabS = 0;                  // S of the unit twiddles in twS
   for (int it = first; it < end; it += step) {
     const int fi = frame_of(it);
     const frame_desc d = desc(fi);
@@ -241,7 +273,7 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
     for (int i = 0; i < q.nv; ++i) {
       const int y = q.y0 + S * i;
       const bool in1 = y < d.H1, in2 = y < d.H2;
-      full_twiddles(twf, N, tabN);
+      pass_twiddles(twf, px, tabN, tabCode);
       if (with_ey && S != tabS) {
         // w_t for the row evaluation (made again only when S changes; the
         // barrier after the row's store orders it before its use)
@@ -395,7 +427,9 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
     return (desc(frame_of(it)).variant & VAR_DIVIDE_B1) ? 0 : 1;   // frame 2 first when both are divided
   };
   if (first < end) fetch(first, first_frame(first));
-  int tabN = 0;   // length of the twiddle table in LDS
+  int tabN = 0;                   // length of the full twiddle table in LDS
+  int tabNp = 0;                  // plan of the pass tables in LDS (length,
+  unsigned long long tabCode = 0;   // pass order)
   for (int it = first; it < end; it += step) {
     const int fi = frame_of(it);
     const frame_desc d = desc(fi);
@@ -408,7 +442,8 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
     const bool two = !(d.variant & VAR_DIVIDE_B1);   // two-channel division, or B1 / K1 alone
     cplx<T>* buf = (cplx<T>*)sm_cf;                   // [cw][ld]
     cplx<T>* kr = buf + (size_t)cw * ld;              // [cw][2][CBP_MAX_K] row DFTs of the kernels at kx
-    cplx<T>* tw = kr + (size_t)cw * 2 * CBP_MAX_K;    // [N] w_N^t
+    cplx<T>* tw = kr + (size_t)cw * 2 * CBP_MAX_K;    // [N] w_N^t (the filter's kernel spectra)
+    cplx<T>* twp = tw + N;                            // the plan's pass tables
     const int nstrip = (hx + cw - 1) / cw;
     const int kx0 = (item % nstrip) * cw, ch = item / nstrip;
     const int lcw = __builtin_ctz(cw);                // cw is a power of two
@@ -424,6 +459,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
       }
     };
     full_twiddles(tw, N, tabN);
+    pass_twiddles(twp, py, tabNp, tabCode);
     // the kernels' row DFTs at this strip's columns (k_kernel_dft), zero past hx
     {
       const cplx<T>* krg = (const cplx<T>*)d.kr;
@@ -466,7 +502,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
       spill(H2);
       __syncthreads();
       fetch(it, 0);   // frame 1's strip in flight while frame 2's is transformed
-      ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, tw, cw);
+      ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, twp, cw);
       for_held([&](auto G, int a, int c, int y, int q) __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < G(); ++j) st2[a + j] = buf[mul24(c, ld) + y + j * q];
@@ -477,7 +513,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
     __syncthreads();
     // the next item's first strip in flight while this one is finished
     if (it + step < end) fetch(it + step, first_frame(it + step));
-    ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, tw, cw);
+    ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, twp, cw);
     // filter: the combined spectrum in place of frame 1's
     const int kmax = k1 > k2 ? k1 : k2;
     auto filt = [&](cplx<T>* at, const cplx<T>& kh1, const cplx<T>& kh2, const cplx<T>& b2)
@@ -539,7 +575,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
       }
     });
     __syncthreads();
-    ip_fft<+1, NT, col_max_elems<T, NT>()>(buf, ld, py, tw, cw);
+    ip_fft<+1, NT, col_max_elems<T, NT>()>(buf, ld, py, twp, cw);
     // the first m rows, row segments of cw columns
     cplx<T>* uo = (cplx<T>*)d.u + (int64_t)ch * m * tp;
     for (int e = threadIdx.x; e < (m << lcw); e += NT) {
@@ -651,7 +687,8 @@ __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
     }
   };
   if (first < end) fetch(first);
-  int tabN = 0;   // length of the twiddle table in LDS
+  int tabN = 0;                  // plan of the pass tables in LDS (length,
+  unsigned long long tabCode = 0;  // pass order)
   for (int it = first; it < end; it += step) {
     const int fi = frame_of(it);
     const frame_desc d = desc(fi);
@@ -661,7 +698,7 @@ __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
     const T scale = (T)(1.0 / ((double)d.Py * (double)d.Px));
     cplx<T>* a = (cplx<T>*)sm_ri;
     cplx<T>* twf = a + N;
-    full_twiddles(twf, N, tabN);
+    pass_twiddles(twf, px, tabN, tabCode);
     const int npair = (m + 1) / 2;
     const int ya = 2 * (item % npair), yb = ya + 1, ch = item / npair;
     const bool hb = yb < m;
@@ -692,9 +729,12 @@ __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
 
 }  // namespace
 
-size_t row_lds_bytes(int N, int esize) { return (size_t)2 * N * 2 * esize; }
-size_t col_lds_bytes(int N, int cw, int esize) {
-  return ((size_t)cw * (N | 1) + (size_t)cw * 2 * CBP_MAX_K + (size_t)N) * 2 * esize;
+// a row and the plan's pass twiddle tables (twn entries)
+size_t row_lds_bytes(int N, int twn, int esize) { return ((size_t)N + (size_t)twn) * 2 * esize; }
+// the strip, the kernels' row DFTs, the full twiddle table and the plan's
+// pass twiddle tables (twn entries)
+size_t col_lds_bytes(int N, int cw, int twn, int esize) {
+  return ((size_t)cw * (N | 1) + (size_t)cw * 2 * CBP_MAX_K + (size_t)N + (size_t)twn) * 2 * esize;
 }
 
 // Threads of the column-pass workgroup for a strip of cw * N entries: the
@@ -710,18 +750,17 @@ int col_threads(int N, int cw, int esize) {
 
 int col_max_strip_elems(int esize) { return esize == 4 ? col_max_elems<float, 1024>() : col_max_elems<double, 1024>(); }
 
-// Resident row-pass workgroups per CU (registers and LDS of a row of maxPx),
+// Resident row-pass workgroups per CU (its registers and lds bytes of LDS),
 // for the persistent grid: a workgroup beyond that would start only when
-// another ends and leave a tail.
-// Kept per (element size, row length rounded up to 256).
-int row_fwd_per_cu(int maxPx, int esize) {
-  static std::atomic<int> cache[2][9];
-  const int b = std::min(std::max((maxPx + 255) / 256, 1), 8);
+// another ends and leave a tail.  Kept per (element size, LDS in 4 KiB steps).
+int row_fwd_per_cu(size_t lds, int esize) {
+  static std::atomic<int> cache[2][41];
+  const int b = std::min((int)((lds + 4095) / 4096), 40);
   std::atomic<int>& c = cache[esize == 8][b];
   int n = c.load(std::memory_order_relaxed);
   if (n > 0) return n;
   const void* f = esize == 8 ? (const void*)k_row_fwd<double> : (const void*)k_row_fwd<float>;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, row_lds_bytes(256 * b, esize)) != hipSuccess || n < 1) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, (size_t)b * 4096) != hipSuccess || n < 1) {
     (void)hipGetLastError();
     return 1;
   }
@@ -739,17 +778,18 @@ void set_fft_attrs() {
 }
 
 template <typename T>
-hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey, hipStream_t st) {
+hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int maxTw, int with_ey, hipStream_t st) {
   prof_begin(PH_ROW_FWD, st);
-  hipLaunchKernelGGL(k_row_fwd<T>, dim3(grid), dim3(256), row_lds_bytes(maxPx, (int)sizeof(T)), st, br, with_ey);
+  hipLaunchKernelGGL(k_row_fwd<T>, dim3(grid), dim3(256), row_lds_bytes(maxPx, maxTw, (int)sizeof(T)), st, br,
+                     with_ey);
   prof_end(PH_ROW_FWD, st);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st) {
+hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, int maxTw, hipStream_t st) {
   prof_begin(PH_COL_FILTER, st);
-  const size_t lds = col_lds_bytes(maxPy, maxcw, (int)sizeof(T));
+  const size_t lds = col_lds_bytes(maxPy, maxcw, maxTw, (int)sizeof(T));
   const int nt = col_threads(maxPy, maxcw, (int)sizeof(T));
   if (nt == 256)
     hipLaunchKernelGGL((k_col_filter<T, 256>), dim3(grid), dim3(256), lds, st, br);
@@ -770,21 +810,21 @@ hipError_t launch_kernel_dft(const batch_ref& br, int grid, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t st) {
+hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, int maxTw, hipStream_t st) {
   prof_begin(PH_ROW_INV, st);
-  hipLaunchKernelGGL(k_row_inv<T>, dim3(grid), dim3(256), row_lds_bytes(maxPx, (int)sizeof(T)), st, br);
+  hipLaunchKernelGGL(k_row_inv<T>, dim3(grid), dim3(256), row_lds_bytes(maxPx, maxTw, (int)sizeof(T)), st, br);
   prof_end(PH_ROW_INV, st);
   return hipGetLastError();
 }
 
 
-template hipError_t launch_row_fwd<float>(const batch_ref&, int, int, int, hipStream_t);
-template hipError_t launch_row_fwd<double>(const batch_ref&, int, int, int, hipStream_t);
-template hipError_t launch_col<float>(const batch_ref&, int, int, int, hipStream_t);
-template hipError_t launch_col<double>(const batch_ref&, int, int, int, hipStream_t);
+template hipError_t launch_row_fwd<float>(const batch_ref&, int, int, int, int, hipStream_t);
+template hipError_t launch_row_fwd<double>(const batch_ref&, int, int, int, int, hipStream_t);
+template hipError_t launch_col<float>(const batch_ref&, int, int, int, int, hipStream_t);
+template hipError_t launch_col<double>(const batch_ref&, int, int, int, int, hipStream_t);
 template hipError_t launch_kernel_dft<float>(const batch_ref&, int, hipStream_t);
 template hipError_t launch_kernel_dft<double>(const batch_ref&, int, hipStream_t);
-template hipError_t launch_row_inv<float>(const batch_ref&, int, int, hipStream_t);
-template hipError_t launch_row_inv<double>(const batch_ref&, int, int, hipStream_t);
+template hipError_t launch_row_inv<float>(const batch_ref&, int, int, int, hipStream_t);
+template hipError_t launch_row_inv<double>(const batch_ref&, int, int, int, hipStream_t);
 
 }  // namespace cbp

@@ -157,22 +157,30 @@ CBP_HD int mul24(int a, int b) {
 #endif
 }
 
+// Twiddles of a pass with radix R and stride Ns > 1 sit in a table of their
+// own, entry k P + r - 1 (k < Ns, 0 < r < R) holding
+// w_(Ns R)^(r k) = exp(-2 pi i r k / (Ns R)), with the odd pitch
+// P = (R - 1) | 1: a butterfly reads its R - 1 twiddles at fixed offsets from
+// one address, and lanes of consecutive k read from distinct LDS banks.
+// The tables of a plan's passes with Ns > 1 follow each other in pass order.
+CBP_HD constexpr int tw_pitch(int R) { return (R - 1) | 1; }
+
 // Butterfly j of a radix-R pass with stride Ns (the product of the radices
 // already applied) of an N-point transform at src, k = j mod Ns given: reads
-// src[j + r N/R] into v, twiddles input r by w^(r k twstep) (TW: Ns > 1;
-// twstep = N / (Ns R)), applies the R-point DFT and returns the base
+// src[j + r N/R] into v, twiddles input r by w_(Ns R)^(r k) from the pass's
+// table tws (TW: Ns > 1), applies the R-point DFT and returns the base
 // (j - k) R + k of its outputs, which belong at base + r Ns.  The kernels run
 // a pass in place: every butterfly is read before any output is written.
-template <int R, int DIR, bool TW, typename T, typename Tab>
-CBP_HD int stockham_read(const cplx<T>* src, int NR, int twstep, const Tab& tw, int j, int k, cplx<T>* v) {
+template <int R, int DIR, bool TW, typename T>
+CBP_HD int stockham_read(const cplx<T>* src, int NR, const cplx<T>* tws, int j, int k, cplx<T>* v) {
   const cplx<T>* s = src + j;
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = s[mul24(r, NR)];
   if (TW) {
-    const int step = mul24(k, twstep);  // r * step < N
+    const cplx<T>* tk = tws + mul24(k, tw_pitch(R));
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      cplx<T> w = tw[mul24(r, step)];
+      cplx<T> w = tk[r - 1];
       if (DIR > 0) w.im = -w.im;
       v[r] = v[r] * w;
     }
@@ -226,6 +234,17 @@ inline bool make_fft_plan(int N, fft_plan* p, int order = 0, bool with9 = false)
     }
   }
   return r == 1;
+}
+
+// Entries of plan p's pass twiddle tables (the passes with Ns > 1).
+inline int pass_table_entries(const fft_plan& p) {
+  int Ns = 1, n = 0;
+  for (int s = 0; s < p.npass; ++s) {
+    const int R = plan_radix(p, s);
+    if (Ns > 1) n += Ns * tw_pitch(R);
+    Ns *= R;
+  }
+  return n;
 }
 
 }  // namespace cbp

@@ -40,6 +40,7 @@ struct frame_plan {
   int hxp;                 // row pitch of T and U (entries): hx rounded up to 128 bytes
   int cw;                  // columns per workgroup in the column pass
   fft_plan fy, fx;
+  int twy, twx;            // entries of the column / row plans' pass twiddle tables
   size_t off_fpart, off_ex, off_ey, off_corr, off_xvec, off_pq, off_kern,
       off_t1, off_t2, off_u, off_feat, off_wts, off_kalt, off_twxd, off_kr, total;
 };
@@ -357,16 +358,16 @@ void set_gram_mfma_attrs();
 // k_fold_cols result, bit for bit) and, with with_ey, the row evaluation EY
 // (the k_eval_rows result, bit for bit) from the rows it already holds.
 template <typename T>
-hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int with_ey, hipStream_t st);
+hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int maxTw, int with_ey, hipStream_t st);
 template <typename T>
-hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, hipStream_t st);
+hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, int maxTw, hipStream_t st);
 template <typename T>
 hipError_t launch_kernel_dft(const batch_ref& br, int grid, hipStream_t st);
 template <typename T>
-hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, hipStream_t st);
-size_t row_lds_bytes(int N, int esize);
-int row_fwd_per_cu(int maxPx, int esize);
-size_t col_lds_bytes(int N, int cw, int esize);
+hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, int maxTw, hipStream_t st);
+size_t row_lds_bytes(int N, int twn, int esize);   // twn: pass twiddle-table entries
+int row_fwd_per_cu(size_t lds, int esize);
+size_t col_lds_bytes(int N, int cw, int twn, int esize);
 int col_max_strip_elems(int esize);   // largest cw * Py the column pass holds
 int col_threads(int N, int cw, int esize);   // column-pass workgroup size for a strip
 void set_recover_attrs();
