@@ -130,12 +130,17 @@ int max_fft(int esize) { return esize == 4 ? CBP_MAX_FFT_F32 : CBP_MAX_FFT_F64; 
 // ---------------------------------------------------------------- tuning
 // Launch-shape knobs of one batch class, chosen by the autotuner.
 struct tuning {
-  int fold_rows;   // target rows per column-fold group (rounded up to a multiple of S; >= 32)
+  int fold_rows;   // target rows per column-fold group (rounded up to a multiple of S; >= 32); 0: from the batch
   int cw;          // columns per column-pass strip (0: widest that fits and keeps >= 256 strips, one per CU)
   int wg_per_cu;   // persistent-grid cap of the streaming queues, workgroups per CU (0: one per item)
   int fft_order;   // radix pass order of the row and column FFTs
 };
-constexpr tuning kDefaultTuning = {128, 0, 0, 0};
+constexpr tuning kDefaultTuning = {0, 0, 0, 0};
+// Row-pass items (one per (channel, fold group, residue)) a batch aims at
+// when fold_rows is 0: a few per resident workgroup, so that a small batch
+// still spreads over the chip and a large one keeps the fold's partial sums
+// (one row per item) small.
+constexpr int kRowItemsTarget = 4096;
 constexpr int kRowWgPerCu = 4;   // resident inverse-row workgroups per CU (LDS: a row and its pass twiddle tables)
 
 // Does a strip of cw columns of length Py fit the column pass?
@@ -199,8 +204,10 @@ int gram_format(int precision) {
 // Shapes -> plan.  All checks are host-side.
 // sizes_only: the plan of the size-estimation entry point, which runs only
 // the evaluation and the Gram (any S >= 1; no FFT or solver limits).
+// batch_rows: channel rows of the whole batch (sum of nch Hmax), which sets
+// the fold group when tn.fold_rows is 0.
 cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, const cbp_options* o,
-                     const tuning& tn, frame_plan* fp, bool sizes_only = false) {
+                     const tuning& tn, frame_plan* fp, bool sizes_only = false, int64_t batch_rows = 0) {
   if (!valid_image(b1) || !valid_image(b2)) return CBP_E_INVALID;
   if (b1->dtype != b2->dtype || b1->channels != b2->channels) return CBP_E_INVALID;
   const cbp_status so = check_options(o, b1->dtype);
@@ -220,8 +227,12 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
   fp->Wmax = fp->W1 > fp->W2 ? fp->W1 : fp->W2;
   fp->m = m; fp->n = n; fp->k1 = k1; fp->k2 = k2; fp->S = S; fp->N = k1 + k2;
   fp->nch = b1->channels;
-  const int rows = tn.fold_rows > 32 ? tn.fold_rows : 32;
-  fp->rpg = S * ((rows + S - 1) / S);
+  // rows of one residue per fold group (each a row-pass item): at least
+  // 32 / S (the workspace's bound on the groups)
+  int gi = (32 + S - 1) / S;
+  if (tn.fold_rows > 0) gi = std::max(gi, (tn.fold_rows + S - 1) / S);
+  else gi = std::max<int64_t>(gi, batch_rows / kRowItemsTarget);
+  fp->rpg = S * gi;
   fp->RG = (fp->Hmax + fp->rpg - 1) / fp->rpg;
   fp->Py = smooth7(fp->Hmax);
   fp->Px = smooth7(fp->Wmax);
@@ -237,7 +248,7 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
     return CBP_E_SHAPE;
   fp->hx = fp->Px / 2 + 1;
   fp->hxp = pitch_of(fp->hx, esize);
-  fp->twy = pass_table_entries(fp->fy);
+  fp->twy = col_table_entries(fp->fy);
   fp->twx = pass_table_entries(fp->fx);
   fp->cw = choose_cw(fp->Py, fp->hx, fp->nch, fp->twy, esize, tn.cw);
   const int gfmt = gram_format(o->precision);
@@ -525,10 +536,13 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
   bb->chunks.clear();
   const int dtype = reqs[0].b1 ? reqs[0].b1->dtype : -1;
   const bool latent = reqs[0].latent != nullptr;
+  int64_t batch_rows = 0;
+  for (const frame_req& r : reqs)
+    if (r.b1 && r.b2) batch_rows += (int64_t)r.b1->channels * std::max(r.b1->height, r.b2->height);
   for (int f = 0; f < nreq; ++f) {
     const frame_req& r = reqs[f];
     frame_plan fp;
-    cbp_status s = make_plan(r.b1, r.b2, r.m, r.n, o, tn, &fp, sizes_only);
+    cbp_status s = make_plan(r.b1, r.b2, r.m, r.n, o, tn, &fp, sizes_only, batch_rows);
     if (s == CBP_OK && r.b1->dtype != dtype) s = CBP_E_INVALID;
     if (s == CBP_OK && (r.latent != nullptr) != latent) s = CBP_E_INVALID;
     if (s == CBP_OK && latent &&
@@ -617,10 +631,9 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
       cv.items[Q_COL] = sq[cnt];
     }
     // the column pass runs a persistent grid: its workgroups load the next
-    // strip while finishing the current one (four 256-thread, two
-    // 512-thread or one 1024-thread workgroup per CU)
+    // strip while finishing the current one (as many as stay resident)
     cv.grid[Q_COL] = grid_for(cv.items[Q_COL],
-                              cap > 0 ? cap : 1024 / col_threads(cv.maxPy, cv.maxcw, esize) * kComputeUnits);
+                              cap > 0 ? cap : col_per_cu(cv.maxPy, cv.maxcw, cv.maxTwy, esize) * kComputeUnits);
     bb->chunks.push_back(cv);
   }
   return CBP_OK;

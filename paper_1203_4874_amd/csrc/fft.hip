@@ -348,6 +348,18 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
 // registers while frame 1 is transformed.  The workgroup has NT = 512 or 1024
 // threads.
 
+// Column stride of a strip in LDS: the smallest ld >= N whose residue modulo
+// the entries of one 128-byte bank row (16 FP32 / 8 FP64 complex) is that
+// count over cw (1 when cw is larger).  The row segments the strip is loaded
+// from and stored to (cw columns of consecutive rows on consecutive lanes)
+// then fall in distinct banks.
+template <typename T>
+__host__ __device__ inline int col_ld(int N, int cw) {
+  constexpr int B = 128 / (int)sizeof(cplx<T>);
+  const int t = cw < B ? B / cw : 1;
+  return N + (((t - N) % B) + B) % B;
+}
+
 // Largest cw * N of a strip: 9 FP32 (4.5 FP64) complex entries per thread,
 // so each thread's share of a pass and of the stashed spectrum stays in
 // registers.
@@ -372,7 +384,7 @@ constexpr int col_slots() {
 // items loads the next strip (and frame 1's strip of the current item) into
 // registers while it transforms.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
+__global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_cf[];
   __shared__ int st[BATCH_CHUNK + 1];
   constexpr int SM = col_slots<T, NT>();
@@ -436,14 +448,17 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
     const int item = it - __builtin_amdgcn_readfirstlane(st[fi]);
     const fft_plan& py = d.fy;
     const int N = py.N, cw = d.cw, hx = d.hx, tp = d.hxp, m = d.m;
-    const int ld = N | 1;
+    const int ld = col_ld<T>(N, cw);
     const int k1 = d.k1, k2 = d.k2, H1 = d.H1, H2 = d.H2;
     const T lam = (T)d.lambda;
     const bool two = !(d.variant & VAR_DIVIDE_B1);   // two-channel division, or B1 / K1 alone
     cplx<T>* buf = (cplx<T>*)sm_cf;                   // [cw][ld]
     cplx<T>* kr = buf + (size_t)cw * ld;              // [cw][2][CBP_MAX_K] row DFTs of the kernels at kx
     cplx<T>* tw = kr + (size_t)cw * 2 * CBP_MAX_K;    // [N] w_N^t (the filter's kernel spectra)
-    cplx<T>* twp = tw + N;                            // the plan's pass tables
+    // the filter's row groups (see col_groups) and its w_N^(g4 y), y < N / g4
+    const int g4 = col_group_size(N);
+    cplx<T>* twg = tw + N;
+    cplx<T>* twp = g4 > 1 ? twg + N / g4 : twg;       // the plan's pass tables
     const int nstrip = (hx + cw - 1) / cw;
     const int kx0 = (item % nstrip) * cw, ch = item / nstrip;
     const int lcw = __builtin_ctz(cw);                // cw is a power of two
@@ -458,6 +473,12 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
         if (e < tot) buf[mul24(c, ld) + y] = (y < Hf && kx0 + c < hx) ? pre[i] : cplx<T>{T(0), T(0)};
       }
     };
+    if (tabN != N && g4 > 1)
+      for (int y = threadIdx.x; y < N / g4; y += NT) {
+        double sn, cs;
+        sincospi(-2.0 * (double)(g4 * y) / (double)N, &sn, &cs);   // = w_N^t, t = g4 y, as full_twiddles
+        twg[y] = {T(cs), T(sn)};
+      }
     full_twiddles(tw, N, tabN);
     pass_twiddles(twp, py, tabNp, tabCode);
     // the kernels' row DFTs at this strip's columns (k_kernel_dft), zero past hx
@@ -470,7 +491,6 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
     }
     // the entries this thread holds (see col_groups): f(group size, slot of
     // the group's first row, column, y, N / group size)
-    const int g4 = (N & 3) == 0 ? 4 : (N & 1) == 0 ? 2 : 1;
     auto for_held = [&](auto&& f) __attribute__((always_inline)) {
       const int tid = local_tid();
       const int ltpc = LNT - lcw;
@@ -538,7 +558,7 @@ __global__ __launch_bounds__(NT, 4) void k_col_filter(batch_ref br) {
       const cplx<T>* kr1 = kr + (size_t)c * 2 * CBP_MAX_K;
       const cplx<T>* kr2 = kr1 + CBP_MAX_K;
       const int nt = (kmax + g - 1) / g;          // coefficients per E_p
-      const cplx<T> u = tw[g * y];
+      const cplx<T> u = g == 1 ? tw[y] : twg[y];
       cplx<T> P1[g], P2[g];
 #pragma unroll
       for (int p = 0; p < g; ++p) {
@@ -731,10 +751,11 @@ __global__ __launch_bounds__(256) void k_row_inv(batch_ref br) {
 
 // a row and the plan's pass twiddle tables (twn entries)
 size_t row_lds_bytes(int N, int twn, int esize) { return ((size_t)N + (size_t)twn) * 2 * esize; }
-// the strip, the kernels' row DFTs, the full twiddle table and the plan's
-// pass twiddle tables (twn entries)
+// the strip (column stride col_ld <= N + 15), the kernels' row DFTs, the
+// full twiddle table and twn more entries (col_table_entries: the filter's
+// w_N^(g y) and the plan's pass twiddle tables)
 size_t col_lds_bytes(int N, int cw, int twn, int esize) {
-  return ((size_t)cw * (N | 1) + (size_t)cw * 2 * CBP_MAX_K + (size_t)N + (size_t)twn) * 2 * esize;
+  return ((size_t)cw * (N + 15) + (size_t)cw * 2 * CBP_MAX_K + (size_t)N + (size_t)twn) * 2 * esize;
 }
 
 // Threads of the column-pass workgroup for a strip of cw * N entries: the
@@ -761,6 +782,30 @@ int row_fwd_per_cu(size_t lds, int esize) {
   if (n > 0) return n;
   const void* f = esize == 8 ? (const void*)k_row_fwd<double> : (const void*)k_row_fwd<float>;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, (size_t)b * 4096) != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  c.store(n, std::memory_order_relaxed);
+  return n;
+}
+
+// Resident column-pass workgroups per CU for strips of cw columns of length
+// N (its variant's registers and LDS), for the persistent grid.  Kept per
+// (element size, variant, LDS in 4 KiB steps).
+int col_per_cu(int N, int cw, int twn, int esize) {
+  static std::atomic<int> cache[2][3][41];
+  const int nt = col_threads(N, cw, esize);
+  const int v = nt == 256 ? 0 : nt == 512 ? 1 : 2;
+  const int b = std::min((int)((col_lds_bytes(N, cw, twn, esize) + 4095) / 4096), 40);
+  std::atomic<int>& c = cache[esize == 8][v][b];
+  int n = c.load(std::memory_order_relaxed);
+  if (n > 0) return n;
+  const void* fs[2][3] = {{(const void*)k_col_filter<float, 256>, (const void*)k_col_filter<float, 512>,
+                           (const void*)k_col_filter<float, 1024>},
+                          {(const void*)k_col_filter<double, 256>, (const void*)k_col_filter<double, 512>,
+                           (const void*)k_col_filter<double, 1024>}};
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs[esize == 8][v], nt, (size_t)b * 4096) != hipSuccess ||
+      n < 1) {
     (void)hipGetLastError();
     return 1;
   }

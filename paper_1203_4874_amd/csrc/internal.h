@@ -40,7 +40,7 @@ struct frame_plan {
   int hxp;                 // row pitch of T and U (entries): hx rounded up to 128 bytes
   int cw;                  // columns per workgroup in the column pass
   fft_plan fy, fx;
-  int twy, twx;            // entries of the column / row plans' pass twiddle tables
+  int twy, twx;            // column pass: col_table_entries; row passes: the row plan's pass tables
   size_t off_fpart, off_ex, off_ey, off_corr, off_xvec, off_pq, off_kern,
       off_t1, off_t2, off_u, off_feat, off_wts, off_kalt, off_twxd, off_kr, total;
 };
@@ -120,6 +120,18 @@ struct batch_ref {
   const int* starts;        // [Q_COUNT][nframes + 1] item prefix sums
   int nframes;
 };
+
+// Rows per group of the column filter's kernel-spectrum evaluation (rows
+// y + j N/g, j < g, share one Horner chain in w_N^(g y)): 4, 2 or 1 as N
+// allows.
+__host__ __device__ inline int col_group_size(int N) { return (N & 3) == 0 ? 4 : (N & 1) == 0 ? 2 : 1; }
+
+// Column-pass twiddle entries beyond the full table: the filter's
+// w_N^(g y), y < N / g (g > 1), and the pass tables of plan p.
+inline int col_table_entries(const fft_plan& p) {
+  const int g = col_group_size(p.N);
+  return (g > 1 ? p.N / g : 0) + pass_table_entries(p);
+}
 
 #if defined(__HIPCC__)
 // Items [first, end) step `step` of this workgroup.  Workgroups are
@@ -369,7 +381,8 @@ size_t row_lds_bytes(int N, int twn, int esize);   // twn: pass twiddle-table en
 int row_fwd_per_cu(size_t lds, int esize);
 size_t col_lds_bytes(int N, int cw, int twn, int esize);
 int col_max_strip_elems(int esize);   // largest cw * Py the column pass holds
-int col_threads(int N, int cw, int esize);   // column-pass workgroup size for a strip
+int col_threads(int N, int cw, int esize);
+int col_per_cu(int N, int cw, int twn, int esize);   // resident column-pass workgroups per CU   // column-pass workgroup size for a strip
 void set_recover_attrs();
 void set_fft_attrs();
 
