@@ -382,7 +382,7 @@ cbp_status cbp_dequantize(const cbp_image* src, cbp_image* dst, void* stream);
 /* Launch shapes chosen by the last CBP_FLAG_AUTOTUNE search on the current
  * device, with the time of one batch call under them. */
 typedef struct cbp_tuning {
-  int32_t fold_rows;          /* rows per column-fold group (before rounding up to a multiple of S; 0 = from the batch size) */
+  int32_t fold_rows;          /* rows per column-fold group (before rounding up to a multiple of S; 0 = from the frame size) */
   int32_t strip_columns;      /* columns per column-pass strip (0 = automatic) */
   int32_t workgroups_per_cu;  /* persistent-grid cap of the streaming launches (0 = one workgroup per item) */
   int32_t fft_order;          /* radix pass order: 0 = 8,4,2,3,5,7; 1 = 4,8,2,3,5,7; 2 = 7,5,3,8,4,2 */

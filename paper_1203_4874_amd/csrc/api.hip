@@ -130,17 +130,17 @@ int max_fft(int esize) { return esize == 4 ? CBP_MAX_FFT_F32 : CBP_MAX_FFT_F64; 
 // ---------------------------------------------------------------- tuning
 // Launch-shape knobs of one batch class, chosen by the autotuner.
 struct tuning {
-  int fold_rows;   // target rows per column-fold group (rounded up to a multiple of S; >= 32); 0: from the batch
+  int fold_rows;   // target rows per column-fold group (rounded up to a multiple of S; >= 32); 0: from the frame
   int cw;          // columns per column-pass strip (0: widest that fits and keeps >= 256 strips, one per CU)
   int wg_per_cu;   // persistent-grid cap of the streaming queues, workgroups per CU (0: one per item)
   int fft_order;   // radix pass order of the row and column FFTs
 };
 constexpr tuning kDefaultTuning = {0, 0, 0, 0};
-// Row-pass items (one per (channel, fold group, residue)) a batch aims at
-// when fold_rows is 0: a few per resident workgroup, so that a small batch
-// still spreads over the chip and a large one keeps the fold's partial sums
-// (one row per item) small.
-constexpr int kRowItemsTarget = 4096;
+// Row-pass items (one per (channel, fold group, residue)) a frame aims at
+// when fold_rows is 0: one frame alone still spreads over the chip, a large
+// frame keeps the fold's partial sums (one row per item) small.  The group
+// depends on the frame alone, so a frame gets the same bits in any batch.
+constexpr int kRowItemsPerFrame = 1024;
 constexpr int kRowWgPerCu = 4;   // resident inverse-row workgroups per CU (LDS: a row and its pass twiddle tables)
 
 // Does a strip of cw columns of length Py fit the column pass?
@@ -204,10 +204,8 @@ int gram_format(int precision) {
 // Shapes -> plan.  All checks are host-side.
 // sizes_only: the plan of the size-estimation entry point, which runs only
 // the evaluation and the Gram (any S >= 1; no FFT or solver limits).
-// batch_rows: channel rows of the whole batch (sum of nch Hmax), which sets
-// the fold group when tn.fold_rows is 0.
 cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, const cbp_options* o,
-                     const tuning& tn, frame_plan* fp, bool sizes_only = false, int64_t batch_rows = 0) {
+                     const tuning& tn, frame_plan* fp, bool sizes_only = false) {
   if (!valid_image(b1) || !valid_image(b2)) return CBP_E_INVALID;
   if (b1->dtype != b2->dtype || b1->channels != b2->channels) return CBP_E_INVALID;
   const cbp_status so = check_options(o, b1->dtype);
@@ -231,7 +229,7 @@ cbp_status make_plan(const cbp_image* b1, const cbp_image* b2, int m, int n, con
   // 32 / S (the workspace's bound on the groups)
   int gi = (32 + S - 1) / S;
   if (tn.fold_rows > 0) gi = std::max(gi, (tn.fold_rows + S - 1) / S);
-  else gi = std::max<int64_t>(gi, batch_rows / kRowItemsTarget);
+  else gi = std::max(gi, fp->nch * fp->Hmax / kRowItemsPerFrame);
   fp->rpg = S * gi;
   fp->RG = (fp->Hmax + fp->rpg - 1) / fp->rpg;
   fp->Py = smooth7(fp->Hmax);
@@ -536,13 +534,10 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
   bb->chunks.clear();
   const int dtype = reqs[0].b1 ? reqs[0].b1->dtype : -1;
   const bool latent = reqs[0].latent != nullptr;
-  int64_t batch_rows = 0;
-  for (const frame_req& r : reqs)
-    if (r.b1 && r.b2) batch_rows += (int64_t)r.b1->channels * std::max(r.b1->height, r.b2->height);
   for (int f = 0; f < nreq; ++f) {
     const frame_req& r = reqs[f];
     frame_plan fp;
-    cbp_status s = make_plan(r.b1, r.b2, r.m, r.n, o, tn, &fp, sizes_only, batch_rows);
+    cbp_status s = make_plan(r.b1, r.b2, r.m, r.n, o, tn, &fp, sizes_only);
     if (s == CBP_OK && r.b1->dtype != dtype) s = CBP_E_INVALID;
     if (s == CBP_OK && (r.latent != nullptr) != latent) s = CBP_E_INVALID;
     if (s == CBP_OK && latent &&
