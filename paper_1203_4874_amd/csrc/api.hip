@@ -140,7 +140,7 @@ constexpr tuning kDefaultTuning = {0, 0, 0, 0};
 // when fold_rows is 0: one frame alone still spreads over the chip, a large
 // frame keeps the fold's partial sums (one row per item) small.  The group
 // depends on the frame alone, so a frame gets the same bits in any batch.
-constexpr int kRowItemsPerFrame = 1024;
+constexpr int kRowItemsPerFrame = 512;
 constexpr int kRowWgPerCu = 4;   // resident inverse-row workgroups per CU (LDS: a row and its pass twiddle tables)
 
 // Does a strip of cw columns of length Py fit the column pass?

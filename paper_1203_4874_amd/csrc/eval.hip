@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_eval_rows(batch_ref br) {
       g[w][l] = sr;
     }
     __syncthreads();
-    if (y < H && l < S) d.ey[((size_t)cf * S + l) * d.Hmax + y] = dft_at(g[w], tw, S, l);
+    if (y < H && l < S) d.ey[((size_t)cf * S + l) * d.Hmax + y] = dft_at(g[w], 1, tw, S, l);
   });
 }
 

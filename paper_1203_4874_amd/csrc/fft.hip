@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
         }
         __syncthreads();
         if (wvi < 2 && l < S && (wvi ? in2 : in1))
-          d.ey[((size_t)(2 * ch + wvi) * S + l) * d.Hmax + y] = dft_at(gy[wvi], twS, S, l);
+          d.ey[((size_t)(2 * ch + wvi) * S + l) * d.Hmax + y] = dft_at(gy[wvi], 1, twS, S, l);
       }
       ip_fft<-1, 256, ROW_MAXE, true>(a, N, px, twf, 1);
       const cplx<T>* z = a;

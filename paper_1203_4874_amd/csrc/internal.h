@@ -220,9 +220,10 @@ __device__ __attribute__((always_inline)) inline double fold_strided(const T* p,
   return acc;
 }
 
-// sum_r f[r] w_(j r mod S), r < S, in increasing r (w from unit_twiddles):
-// four terms' operands are loaded before their (ordered) accumulation.
-__device__ __attribute__((always_inline)) inline c64 dft_at(const double* f, const c64* tw, int S, int j) {
+// sum_r f[r fs] w_(j r mod S), r < S, in increasing r (w from
+// unit_twiddles): four terms' operands are loaded before their (ordered)
+// accumulation.
+__device__ __attribute__((always_inline)) inline c64 dft_at(const double* f, int fs, const c64* tw, int S, int j) {
   c64 e = {0.0, 0.0};
   int t = 0, r = 0;
   for (; r + 4 <= S; r += 4) {
@@ -230,7 +231,7 @@ __device__ __attribute__((always_inline)) inline c64 dft_at(const double* f, con
     c64 wv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      fv[u] = f[r + u];
+      fv[u] = f[(r + u) * fs];
       wv[u] = tw[t];
       t += j;
       if (t >= S) t -= S;
@@ -242,8 +243,8 @@ __device__ __attribute__((always_inline)) inline c64 dft_at(const double* f, con
     }
   }
   for (; r < S; ++r) {
-    e.re += f[r] * tw[t].re;
-    e.im += f[r] * tw[t].im;
+    e.re += f[r * fs] * tw[t].re;
+    e.im += f[r * fs] * tw[t].im;
     t += j;
     if (t >= S) t -= S;
   }
@@ -254,8 +255,9 @@ __device__ __attribute__((always_inline)) inline c64 dft_at(const double* f, con
 // column fold): the row-group partials of 16 columns of one (channel, frame)
 // summed in group order into F[r][column], then EX[cf][j][x] = sum_r
 // w_j^r F[r][x].  256 threads: 16 columns x 16 residues / frequencies in
-// flight.  F (CBP_MAX_S x 16 doubles) and tw (CBP_MAX_S) are LDS scratch.
+// flight, each thread two residues when S > 16.  F (CBP_MAX_S x 16 doubles) and tw (CBP_MAX_S) are LDS scratch.
 // Items: (column block, cf).
+static_assert(CBP_MAX_S <= 32, "the column evaluation holds residues ty and ty + 16 per thread");
 __device__ inline void eval_cols_item(const frame_desc& d, int item, double (*F)[16], c64* tw) {
   const int nx = (d.Wmax + 15) / 16;
   const int bx = item % nx, cf = item / nx;
@@ -264,45 +266,50 @@ __device__ inline void eval_cols_item(const frame_desc& d, int item, double (*F)
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int x = bx * 16 + tx;
   unit_twiddles(tw, S);
-  for (int r = ty; r < S; r += 16) {
-    double s0 = 0.0, s1 = 0.0;
-    if (x < W) {
-      const double* p = d.fpart + ((size_t)cf * S + r) * Wmax + x;
-      const size_t gs = (size_t)d.ncf * S * Wmax;
-      int g = 0;
-      // eight groups' loads in flight; even groups into s0, odd into s1
-      for (; g + 8 <= RG; g += 8) {
-        double v[8];
+  // residues ty and ty + 16 (S <= 32) at once: eight groups' loads of each in
+  // flight; even groups into s0, odd into s1, in group order
+  {
+    const bool h0 = ty < S && x < W, h1 = ty + 16 < S && x < W;
+    const size_t gs = (size_t)d.ncf * S * Wmax;
+    const double* p0 = d.fpart + ((size_t)cf * S + ty) * Wmax + x;
+    const double* p1 = p0 + (size_t)16 * Wmax;
+    double s0 = 0.0, s1 = 0.0, t0 = 0.0, t1 = 0.0;
+    int g = 0;
+    for (; g + 8 <= RG; g += 8) {
+      double v[8], w[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(g + u) * gs];
+      for (int u = 0; u < 8; ++u) {
+        v[u] = h0 ? p0[(size_t)(g + u) * gs] : 0.0;
+        w[u] = h1 ? p1[(size_t)(g + u) * gs] : 0.0;
+      }
 #pragma unroll
-        for (int u = 0; u < 8; u += 2) {
-          s0 += v[u];
-          s1 += v[u + 1];
-        }
+      for (int u = 0; u < 8; u += 2) {
+        s0 += v[u];
+        s1 += v[u + 1];
+        t0 += w[u];
+        t1 += w[u + 1];
       }
-      for (; g + 2 <= RG; g += 2) {
-        s0 += p[(size_t)g * gs];
-        s1 += p[(size_t)(g + 1) * gs];
-      }
-      if (g < RG) s0 += p[(size_t)g * gs];
     }
-    F[r][tx] = s0 + s1;
+    for (; g + 2 <= RG; g += 2) {
+      if (h0) {
+        s0 += p0[(size_t)g * gs];
+        s1 += p0[(size_t)(g + 1) * gs];
+      }
+      if (h1) {
+        t0 += p1[(size_t)g * gs];
+        t1 += p1[(size_t)(g + 1) * gs];
+      }
+    }
+    if (g < RG) {
+      if (h0) s0 += p0[(size_t)g * gs];
+      if (h1) t0 += p1[(size_t)g * gs];
+    }
+    if (ty < S) F[ty][tx] = s0 + s1;
+    if (ty + 16 < S) F[ty + 16][tx] = t0 + t1;
   }
   __syncthreads();
   if (x >= W) return;
-  for (int j = ty; j < S; j += 16) {
-    c64 acc = {0.0, 0.0};
-    int t = 0;
-    for (int r = 0; r < S; ++r) {
-      const double f = F[r][tx];
-      acc.re += f * tw[t].re;
-      acc.im += f * tw[t].im;
-      t += j;
-      if (t >= S) t -= S;
-    }
-    d.ex[((size_t)cf * S + j) * Wmax + x] = acc;
-  }
+  for (int j = ty; j < S; j += 16) d.ex[((size_t)cf * S + j) * Wmax + x] = dft_at(&F[0][tx], 16, tw, S, j);
 }
 #endif
 
