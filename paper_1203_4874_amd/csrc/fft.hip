@@ -94,14 +94,18 @@ __device__ __attribute__((always_inline)) inline void pass_twiddles(cplx<T>* tws
 // buf + c ld, in place: butterfly j of transform c reads
 // buf[c ld + j + r N/R] and writes buf[c ld + (j - k) R + k + r Ns],
 // k = j mod Ns (the Stockham indexing of fft_core.h, read and write phases
-// separated by a barrier); tws: the pass's twiddle table.  ncol N <= MAXE.
+// separated by a barrier); tws: the pass's twiddle table.  ncol (a power of
+// two) N <= MAXE.  Butterfly b of the pass is (c, j) = (b mod ncol,
+// b / ncol): consecutive lanes take the same j of consecutive transforms,
+// whose entries the strip's column stride puts in distinct banks.
 template <int R, int DIR, int NT, int MAXE, typename T>
 __device__ __attribute__((always_inline)) inline void ip_pass(cplx<T>* buf, int ld, int N, int Ns,
                                                               const cplx<T>* tws, int ncol) {
   constexpr int MB = ip_mb<NT, R, MAXE>();
   const int NR = N / R;
   const int total = NR * ncol;
-  const float rnr = 1.0f / (float)NR, rns = 1.0f / (float)Ns;
+  const int lnc = __builtin_ctz(ncol);
+  const float rns = 1.0f / (float)Ns;
   cplx<T> v[MB][R];
   int pos[MB];
   const int tid = local_tid();
@@ -110,9 +114,8 @@ __device__ __attribute__((always_inline)) inline void ip_pass(cplx<T>* buf, int 
     const int b = tid + q * NT;
     pos[q] = -1;
     if (b < total) {
-      const int c = ncol == 1 ? 0 : fdiv_floor(b, rnr);
-      const int j = b - mul24(c, NR);
-      const int k = j - mul24(fdiv_floor(j, rns), Ns);
+      const int c = b & (ncol - 1), j = b >> lnc;
+      const int k = Ns > 1 ? j - mul24(fdiv_floor(j, rns), Ns) : 0;
       const cplx<T>* src = buf + mul24(c, ld);
       const int base = Ns > 1 ? stockham_read<R, DIR, true>(src, NR, tws, j, k, v[q])
                               : stockham_read<R, DIR, false>(src, NR, tws, j, k, v[q]);
