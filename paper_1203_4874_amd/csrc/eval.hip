@@ -124,27 +124,27 @@ __global__ __launch_bounds__(256) void k_eval_cols(batch_ref br) {
   });
 }
 
-// Row fold and S-point DFT: one wave per row.  With G = floor(64 / S) lane
-// groups, lane l = g S + r (g < G) sums the row entries x = r + S (g + G i),
-// i = 0, 1, ... in order; residue r is then the sum of its G partials in
-// group order.  k_row_fwd folds the rows it holds with the same lanes and
-// the same order, so both give the same bits.
-// Items: (block of 4 rows, cf).
+// Row fold and S-point DFT: two waves per row.  With G = floor(128 / S)
+// lane groups, lane l = g S + r (g < G) of the pair sums the row entries
+// x = r + S (g + G i), i = 0, 1, ... in order; residue r is then the sum of
+// its G partials in group order.  k_row_fwd folds the rows it holds with the
+// same lanes and the same order, so both give the same bits.
+// Items: (pair of rows, cf).
 template <typename T>
 __global__ __launch_bounds__(256) void k_eval_rows(batch_ref br) {
-  __shared__ double part[4][64];
-  __shared__ double g[4][CBP_MAX_S];
+  __shared__ double part[2][128];
+  __shared__ double g[2][CBP_MAX_S];
   __shared__ c64 tw[CBP_MAX_S];
   for_items<Q_EVAL_ROWS>(br, [&](const frame_desc& d, int item) __attribute__((always_inline)) {
-    const int ny = (d.Hmax + 3) / 4;
+    const int ny = (d.Hmax + 1) / 2;
     const int by = item % ny, cf = item / ny;
-    const int S = d.S, G = 64 / S;
+    const int S = d.S, G = 128 / S;
     const T* b;
     int64_t pitch;
     int H, W;
     pick(d, cf, b, pitch, H, W);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int y = by * 4 + w;
+    const int w = threadIdx.x >> 7, l = threadIdx.x & 127;
+    const int y = by * 2 + w;
     const int gl = l / S, r = l - gl * S;
     unit_twiddles(tw, S);
     double acc = 0.0;

@@ -185,7 +185,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
   extern __shared__ __attribute__((aligned(16))) char sm_rf[];
   __shared__ double gy[2][CBP_MAX_S];
-  __shared__ double fpart_l[2][64];
+  __shared__ double fpart_l[2][128];
   __shared__ c64 twS[CBP_MAX_S];
   __shared__ int st[BATCH_CHUNK + 1];
   const int nf = br.nframes;
@@ -297,26 +297,26 @@ __global__ __launch_bounds__(256) void k_row_fwd(batch_ref br, int with_ey) {
       else fetch_from(it + step);
       if (with_ey) {
         // the row evaluation of both rows (k_eval_rows's lanes and order):
-        // wave fr folds frame fr's row into partials, lane g S + r summing
-        // x = r + S (g + G i); the residues then add their G partials in order
-        const int G = 64 / S;
-        const int wvi = threadIdx.x >> 6, l = threadIdx.x & 63;
+        // waves 2 fr, 2 fr + 1 fold frame fr's row into partials, lane
+        // g S + r of the pair summing x = r + S (g + G i); the residues then
+        // add their G partials in order
+        const int G = 128 / S;
+        const int fr = threadIdx.x >> 7, l = threadIdx.x & 127;
         const int gl = l / S, rr0 = l - gl * S;
-        if (wvi < 2) {
-          const int W = wvi ? W2 : W1;
+        const bool inr = fr ? in2 : in1;
+        {
           double acc = 0.0;
-          if ((wvi ? in2 : in1) && gl < G) acc = fold_strided((const T*)a + wvi, 2, rr0 + S * gl, S * G, W);
-          fpart_l[wvi][l] = acc;
+          if (inr && gl < G) acc = fold_strided((const T*)a + fr, 2, rr0 + S * gl, S * G, fr ? W2 : W1);
+          fpart_l[fr][l] = acc;
         }
         __syncthreads();
-        if (wvi < 2 && l < S) {
-          double sr = fpart_l[wvi][l];
-          for (int gq = 1; gq < G; ++gq) sr += fpart_l[wvi][gq * S + l];
-          gy[wvi][l] = sr;
+        if (l < S) {
+          double sr = fpart_l[fr][l];
+          for (int gq = 1; gq < G; ++gq) sr += fpart_l[fr][gq * S + l];
+          gy[fr][l] = sr;
         }
         __syncthreads();
-        if (wvi < 2 && l < S && (wvi ? in2 : in1))
-          d.ey[((size_t)(2 * ch + wvi) * S + l) * d.Hmax + y] = dft_at(gy[wvi], 1, twS, S, l);
+        if (l < S && inr) d.ey[((size_t)(2 * ch + fr) * S + l) * d.Hmax + y] = dft_at(gy[fr], 1, twS, S, l);
       }
       ip_fft<-1, 256, ROW_MAXE, true>(a, N, px, twf, 1);
       const cplx<T>* z = a;

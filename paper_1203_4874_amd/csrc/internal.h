@@ -99,7 +99,7 @@ inline int queue_items(int q, const frame_plan& p) {
     case Q_DIAG: return 1;
     case Q_FOLD: return ((p.Wmax + 63) / 64) * p.S * p.RG * ncf;
     case Q_EVAL_COLS: return ((p.Wmax + 15) / 16) * ncf;
-    case Q_EVAL_ROWS: return ((p.Hmax + 3) / 4) * ncf;
+    case Q_EVAL_ROWS: return ((p.Hmax + 1) / 2) * ncf;
     case Q_ROW_FWD: return p.nch * p.RG * p.S;   // (channel, row group, residue); rows y < Hmax of each
     case Q_GRAM: return (2 * p.N - 1) * p.S * 2;
     case Q_GRAMM: return p.S * 2;
