@@ -159,10 +159,15 @@ def kernel_models(H1, W1, H2, W2, m, n, k1, k2, S, Py, Px, esize, refine_sample,
     pix_in = (H1 * W1 + H2 * W2)
     fin = sum(2 * S * S * k * 8 + (S * S * k + S * k * k) * 8 * 2 for k in (k1, k2)) \
         + 2 * 2 * S * S * 3 + 2 * S * S * 8 + eig_flops(2 * S, refine_scale) + 2 * S * S * 14
+    # a deblurring call's row pass reads the frames once: it also folds the
+    # columns (the fold's output, S rows per frame) and writes the row
+    # evaluation; its first launch only writes the FP64 twiddle table of the
+    # kernels' row DFTs (Px entries)
     return {
-        "fold_cols": dict(bound="hbm", bytes=pix_in * esize + 8 * S * (W1 + W2)),
-        "eval_rows": dict(bound="hbm", bytes=pix_in * esize + 16 * S * (H1 + H2)),
-        "row_fft_fwd": dict(bound="hbm", bytes=pix_in * esize + cplx * hx * (H1 + H2)),
+        "fold_cols": dict(bound="hbm", bytes=16 * Px),
+        "eval_cols": dict(bound="hbm", bytes=8 * S * (W1 + W2) + 16 * S * (W1 + W2)),
+        "row_fft_fwd": dict(bound="hbm", bytes=pix_in * esize + cplx * hx * (H1 + H2) + 8 * S * (W1 + W2)
+                            + 16 * S * (H1 + H2)),
         "col_fft_filter": dict(bound="hbm", bytes=cplx * hx * (H1 + H2) + cplx * hx * m),
         "row_fft_inv": dict(bound="hbm", bytes=cplx * hx * m + esize * m * n),
         "sample_eig": dict(bound="alu", flops=2 * S * eig_flops(N, refine_sample), peak=FP64_PEAK_TFLOPS),
