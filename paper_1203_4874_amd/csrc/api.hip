@@ -430,6 +430,7 @@ struct chunk_view {
   int grid[Q_COUNT];
   int maxN, maxS, maxPx, maxPy, maxcw;
   int maxTwx, maxTwy;   // largest row / column pass twiddle tables (entries)
+  int colGroups;        // the column filter's row groups of the frames (bit g set for group g)
   int gram_fmt;   // gram_format() of the call's precision
   int maxStride;  // largest Hmax / Wmax (matrix-core Gram staging)
   const void* mlp;  // the learned form's network (device mlp blob) or NULL
@@ -473,7 +474,7 @@ hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool 
   }
   if (latent) {
     CBP_TRY(launch_kernel_dft<T>(br(Q_KRDFT), cv.grid[Q_KRDFT], st));
-    CBP_TRY(launch_col<T>(br(Q_COL), cv.grid[Q_COL], cv.maxPy, cv.maxcw, cv.maxTwy, st));
+    CBP_TRY(launch_col<T>(br(Q_COL), cv.grid[Q_COL], cv.maxPy, cv.maxcw, cv.maxTwy, cv.colGroups, st));
     CBP_TRY(launch_row_inv<T>(br(Q_ROW_INV), cv.grid[Q_ROW_INV], cv.maxPx, cv.maxTwx, st));
   }
   return hipSuccess;
@@ -595,6 +596,7 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
       cv.grid[q] = grid_for(cv.items[q], row ? (cap > 0 ? cap : kRowWgPerCu * kComputeUnits) : streaming ? cap : 0);
     }
     cv.maxN = cv.maxS = cv.maxPx = cv.maxPy = cv.maxcw = cv.maxStride = 1;
+    cv.colGroups = 0;
     cv.gram_fmt = gram_format(o->precision);
     cv.mlp = o->learned ? o->mlp_blob : nullptr;
     for (int i = 0; i < cnt; ++i) {
@@ -607,6 +609,7 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
       cv.maxcw = std::max(cv.maxcw, p.cw);
       cv.maxTwx = std::max(cv.maxTwx, p.twx);
       cv.maxTwy = std::max(cv.maxTwy, p.twy);
+      cv.colGroups |= 1 << col_group_size(p.Py);
     }
     const int esize = dtype == CBP_F32 ? 4 : 8;
     // as many persistent row-pass workgroups as stay resident
@@ -628,7 +631,7 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
     // the column pass runs a persistent grid: its workgroups load the next
     // strip while finishing the current one (as many as stay resident)
     cv.grid[Q_COL] = grid_for(cv.items[Q_COL],
-                              cap > 0 ? cap : col_per_cu(cv.maxPy, cv.maxcw, cv.maxTwy, esize) * kComputeUnits);
+                              cap > 0 ? cap : col_per_cu(cv.maxPy, cv.maxcw, cv.maxTwy, col_group_size(cv.maxPy), esize) * kComputeUnits);
     bb->chunks.push_back(cv);
   }
   return CBP_OK;

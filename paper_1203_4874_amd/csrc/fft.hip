@@ -372,25 +372,26 @@ constexpr int col_max_elems() { return NT * 72 / (int)sizeof(cplx<T>); }
 
 // The strip's entries as each thread holds them for the stash and the
 // filter: column c = tid / (NT / cw) (wave-uniform: NT / cw >= 64) and rows in
-// groups of g = 4 (N divisible by 4), 2 (N even) or 1: rows y + j N/g, j < g,
+// groups of g = 4, 2 or 1 (g divides N): rows y + j N/g, j < g,
 // y = tid mod (NT / cw) + i NT / cw < N/g, whose twiddles w_N^(y + j N/g)
 // differ by the g-th roots of unity.  Group i holds slots g i .. g i + g - 1.
 template <typename T, int NT, int G>
 constexpr int col_groups() { return (col_max_elems<T, NT>() / G + NT - 1) / NT; }
-template <typename T, int NT>
-constexpr int col_slots() {
-  constexpr int a = 4 * col_groups<T, NT, 4>(), b = 2 * col_groups<T, NT, 2>(), c = col_groups<T, NT, 1>();
-  return a > b ? (a > c ? a : c) : (b > c ? b : c);
-}
 
 // Items: (strip of cw columns, channel).  A workgroup that owns several
 // items loads the next strip (and frame 1's strip of the current item) into
 // registers while it transforms.
-template <typename T, int NT>
+// G: rows per group of the filter's kernel-spectrum evaluation.  A launch
+// takes the items of the frames whose group (col_group_size of their N) is
+// G and passes over the others, which a launch with their G takes: each
+// frame is filtered with its own group whatever the batch, and a
+// compile-time group keeps the stashed spectrum's slots compile-time
+// indices, in registers.
+template <typename T, int NT, int G>
 __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_cf[];
   __shared__ int st[BATCH_CHUNK + 1];
-  constexpr int SM = col_slots<T, NT>();
+  constexpr int SM = G * col_groups<T, NT, G>();
   constexpr int PF = (col_max_elems<T, NT>() + NT - 1) / NT;   // strip entries per thread
   constexpr int LNT = NT == 1024 ? 10 : NT == 512 ? 9 : 8;
   const int nf = br.nframes;
@@ -441,11 +442,18 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
   auto first_frame = [&](int it) __attribute__((always_inline)) {
     return (desc(frame_of(it)).variant & VAR_DIVIDE_B1) ? 0 : 1;   // frame 2 first when both are divided
   };
-  if (first < end) fetch(first, first_frame(first));
+  // the first item at or after it of a frame with group G (end: none)
+  auto next_item = [&](int it) __attribute__((always_inline)) {
+    for (; it < end; it += step)
+      if (col_group_size(desc(frame_of(it)).fy.N) == G) break;
+    return it < end ? it : end;
+  };
+  const int it0 = next_item(first);
+  if (it0 < end) fetch(it0, first_frame(it0));
   int tabN = 0;                   // length of the full twiddle table in LDS
   int tabNp = 0;                  // plan of the pass tables in LDS (length,
   unsigned long long tabCode = 0;   // pass order)
-  for (int it = first; it < end; it += step) {
+  for (int it = it0, nit; it < end; it = nit) {
     const int fi = frame_of(it);
     const frame_desc d = desc(fi);
     const int item = it - __builtin_amdgcn_readfirstlane(st[fi]);
@@ -458,10 +466,9 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
     cplx<T>* buf = (cplx<T>*)sm_cf;                   // [cw][ld]
     cplx<T>* kr = buf + (size_t)cw * ld;              // [cw][2][CBP_MAX_K] row DFTs of the kernels at kx
     cplx<T>* tw = kr + (size_t)cw * 2 * CBP_MAX_K;    // [N] w_N^t (the filter's kernel spectra)
-    // the filter's row groups (see col_groups) and its w_N^(g4 y), y < N / g4
-    const int g4 = col_group_size(N);
+    // the filter's row groups (see col_groups) and its w_N^(G y), y < N / G
     cplx<T>* twg = tw + N;
-    cplx<T>* twp = g4 > 1 ? twg + N / g4 : twg;       // the plan's pass tables
+    cplx<T>* twp = G > 1 ? twg + N / G : twg;         // the plan's pass tables
     const int nstrip = (hx + cw - 1) / cw;
     const int kx0 = (item % nstrip) * cw, ch = item / nstrip;
     const int lcw = __builtin_ctz(cw);                // cw is a power of two
@@ -476,10 +483,10 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
         if (e < tot) buf[mul24(c, ld) + y] = (y < Hf && kx0 + c < hx) ? pre[i] : cplx<T>{T(0), T(0)};
       }
     };
-    if (tabN != N && g4 > 1)
-      for (int y = threadIdx.x; y < N / g4; y += NT) {
+    if (G > 1 && tabN != N)
+      for (int y = threadIdx.x; y < N / G; y += NT) {
         double sn, cs;
-        sincospi(-2.0 * (double)(g4 * y) / (double)N, &sn, &cs);   // = w_N^t, t = g4 y, as full_twiddles
+        sincospi(-2.0 * (double)(G * y) / (double)N, &sn, &cs);   // = w_N^t, t = G y, as full_twiddles
         twg[y] = {T(cs), T(sn)};
       }
     full_twiddles(tw, N, tabN);
@@ -498,26 +505,11 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
       const int tid = local_tid();
       const int ltpc = LNT - lcw;
       const int c = tid >> ltpc, r = tid & ((1 << ltpc) - 1);
-      if (g4 == 4) {
-        const int q = N >> 2;
+      const int q = N / G;
 #pragma unroll
-        for (int i = 0; i < col_groups<T, NT, 4>(); ++i) {
-          const int y = r + (i << ltpc);
-          if (y < q) f(std::integral_constant<int, 4>(), 4 * i, c, y, q);
-        }
-      } else if (g4 == 2) {
-        const int q = N >> 1;
-#pragma unroll
-        for (int i = 0; i < col_groups<T, NT, 2>(); ++i) {
-          const int y = r + (i << ltpc);
-          if (y < q) f(std::integral_constant<int, 2>(), 2 * i, c, y, q);
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < col_groups<T, NT, 1>(); ++i) {
-          const int y = r + (i << ltpc);
-          if (y < N) f(std::integral_constant<int, 1>(), i, c, y, N);
-        }
+      for (int i = 0; i < col_groups<T, NT, G>(); ++i) {
+        const int y = r + (i << ltpc);
+        if (y < q) f(std::integral_constant<int, G>(), G * i, c, y, q);
       }
     };
     cplx<T> st2[SM];
@@ -526,16 +518,17 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
       __syncthreads();
       fetch(it, 0);   // frame 1's strip in flight while frame 2's is transformed
       ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, twp, cw);
-      for_held([&](auto G, int a, int c, int y, int q) __attribute__((always_inline)) {
+      for_held([&](auto GC, int a, int c, int y, int q) __attribute__((always_inline)) {
 #pragma unroll
-        for (int j = 0; j < G(); ++j) st2[a + j] = buf[mul24(c, ld) + y + j * q];
+        for (int j = 0; j < GC(); ++j) st2[a + j] = buf[mul24(c, ld) + y + j * q];
       });
       __syncthreads();   // buf is refilled with frame 1
     }
     spill(H1);
     __syncthreads();
     // the next item's first strip in flight while this one is finished
-    if (it + step < end) fetch(it + step, first_frame(it + step));
+    nit = next_item(it + step);
+    if (nit < end) fetch(nit, first_frame(nit));
     ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, twp, cw);
     // filter: the combined spectrum in place of frame 1's
     const int kmax = k1 > k2 ? k1 : k2;
@@ -550,14 +543,14 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
       // quotient is zero, whatever the frames hold
       *at = kk > T(0) ? cplx<T>{num.re * inv, num.im * inv} : cplx<T>{T(0), T(0)};
     };
-    for_held([&](auto G, int a, int c, int y, int q) __attribute__((always_inline)) {
+    for_held([&](auto GC, int a, int c, int y, int q) __attribute__((always_inline)) {
       // kernel spectra at (ky, kx) = sum_yy kr[yy] z^yy, z = w_N^ky.  For the
       // group's rows ky = y + j N/g (z = w_N^y times the g-th roots of unity
       // (-i)^(4j/g)): K = sum_p z^p E_p(z^g), E_p(u) = sum_t kr[g t + p] u^t
       // by Horner's rule in u = w_N^(g y), then the g-point DFT of the
       // z^p E_p.  kr is zero beyond each kernel's size; the column is
       // wave-uniform.
-      constexpr int g = G();
+      constexpr int g = GC();
       const cplx<T>* kr1 = kr + (size_t)c * 2 * CBP_MAX_K;
       const cplx<T>* kr2 = kr1 + CBP_MAX_K;
       const int nt = (kmax + g - 1) / g;          // coefficients per E_p
@@ -795,19 +788,31 @@ int row_fwd_per_cu(size_t lds, int esize) {
 // Resident column-pass workgroups per CU for strips of cw columns of length
 // N (its variant's registers and LDS), for the persistent grid.  Kept per
 // (element size, variant, LDS in 4 KiB steps).
-int col_per_cu(int N, int cw, int twn, int esize) {
-  static std::atomic<int> cache[2][3][41];
+// The column-pass instance of element type T, workgroup size nt and filter
+// group g.
+template <typename T>
+const void* col_kernel(int nt, int g) {
+  if (nt == 256)
+    return g == 4 ? (const void*)k_col_filter<T, 256, 4> : g == 2 ? (const void*)k_col_filter<T, 256, 2>
+                                                                   : (const void*)k_col_filter<T, 256, 1>;
+  if (nt == 512)
+    return g == 4 ? (const void*)k_col_filter<T, 512, 4> : g == 2 ? (const void*)k_col_filter<T, 512, 2>
+                                                                   : (const void*)k_col_filter<T, 512, 1>;
+  return g == 4 ? (const void*)k_col_filter<T, 1024, 4> : g == 2 ? (const void*)k_col_filter<T, 1024, 2>
+                                                                  : (const void*)k_col_filter<T, 1024, 1>;
+}
+
+int col_per_cu(int N, int cw, int twn, int g, int esize) {
+  static std::atomic<int> cache[2][3][3][41];
   const int nt = col_threads(N, cw, esize);
   const int v = nt == 256 ? 0 : nt == 512 ? 1 : 2;
+  const int gi = g == 4 ? 0 : g == 2 ? 1 : 2;
   const int b = std::min((int)((col_lds_bytes(N, cw, twn, esize) + 4095) / 4096), 40);
-  std::atomic<int>& c = cache[esize == 8][v][b];
+  std::atomic<int>& c = cache[esize == 8][v][gi][b];
   int n = c.load(std::memory_order_relaxed);
   if (n > 0) return n;
-  const void* fs[2][3] = {{(const void*)k_col_filter<float, 256>, (const void*)k_col_filter<float, 512>,
-                           (const void*)k_col_filter<float, 1024>},
-                          {(const void*)k_col_filter<double, 256>, (const void*)k_col_filter<double, 512>,
-                           (const void*)k_col_filter<double, 1024>}};
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs[esize == 8][v], nt, (size_t)b * 4096) != hipSuccess ||
+  const void* f = esize == 8 ? col_kernel<double>(nt, g) : col_kernel<float>(nt, g);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, nt, (size_t)b * 4096) != hipSuccess ||
       n < 1) {
     (void)hipGetLastError();
     return 1;
@@ -817,12 +822,14 @@ int col_per_cu(int N, int cw, int twn, int esize) {
 }
 
 void set_fft_attrs() {
-  const void* fns[10] = {(const void*)k_row_fwd<float>, (const void*)k_col_filter<float, 256>,
-                         (const void*)k_col_filter<float, 512>, (const void*)k_col_filter<float, 1024>,
-                         (const void*)k_row_inv<float>, (const void*)k_row_fwd<double>,
-                         (const void*)k_col_filter<double, 256>, (const void*)k_col_filter<double, 512>,
-                         (const void*)k_col_filter<double, 1024>, (const void*)k_row_inv<double>};
+  const void* fns[4] = {(const void*)k_row_fwd<float>, (const void*)k_row_inv<float>, (const void*)k_row_fwd<double>,
+                        (const void*)k_row_inv<double>};
   for (const void* f : fns) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  for (int nt : {256, 512, 1024})
+    for (int g : {4, 2, 1}) {
+      hipFuncSetAttribute(col_kernel<float>(nt, g), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      hipFuncSetAttribute(col_kernel<double>(nt, g), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    }
 }
 
 template <typename T>
@@ -835,18 +842,16 @@ hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int maxTw, i
 }
 
 template <typename T>
-hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, int maxTw, hipStream_t st) {
+hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, int maxTw, int gmask, hipStream_t st) {
   prof_begin(PH_COL_FILTER, st);
   const size_t lds = col_lds_bytes(maxPy, maxcw, maxTw, (int)sizeof(T));
   const int nt = col_threads(maxPy, maxcw, (int)sizeof(T));
-  if (nt == 256)
-    hipLaunchKernelGGL((k_col_filter<T, 256>), dim3(grid), dim3(256), lds, st, br);
-  else if (nt == 512)
-    hipLaunchKernelGGL((k_col_filter<T, 512>), dim3(grid), dim3(512), lds, st, br);
-  else
-    hipLaunchKernelGGL((k_col_filter<T, 1024>), dim3(grid), dim3(1024), lds, st, br);
+  void* args[] = {(void*)&br};
+  hipError_t e = hipSuccess;
+  for (int g : {4, 2, 1})
+    if ((gmask >> g & 1) && e == hipSuccess) e = hipLaunchKernel(col_kernel<T>(nt, g), dim3(grid), dim3(nt), args, lds, st);
   prof_end(PH_COL_FILTER, st);
-  return hipGetLastError();
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 template <typename T>
@@ -868,8 +873,8 @@ hipError_t launch_row_inv(const batch_ref& br, int grid, int maxPx, int maxTw, h
 
 template hipError_t launch_row_fwd<float>(const batch_ref&, int, int, int, int, hipStream_t);
 template hipError_t launch_row_fwd<double>(const batch_ref&, int, int, int, int, hipStream_t);
-template hipError_t launch_col<float>(const batch_ref&, int, int, int, int, hipStream_t);
-template hipError_t launch_col<double>(const batch_ref&, int, int, int, int, hipStream_t);
+template hipError_t launch_col<float>(const batch_ref&, int, int, int, int, int, hipStream_t);
+template hipError_t launch_col<double>(const batch_ref&, int, int, int, int, int, hipStream_t);
 template hipError_t launch_kernel_dft<float>(const batch_ref&, int, hipStream_t);
 template hipError_t launch_kernel_dft<double>(const batch_ref&, int, hipStream_t);
 template hipError_t launch_row_inv<float>(const batch_ref&, int, int, int, hipStream_t);

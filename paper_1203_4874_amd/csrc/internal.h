@@ -127,7 +127,8 @@ struct batch_ref {
 __host__ __device__ inline int col_group_size(int N) { return (N & 3) == 0 ? 4 : (N & 1) == 0 ? 2 : 1; }
 
 // Column-pass twiddle entries beyond the full table: the filter's
-// w_N^(g y), y < N / g (g > 1), and the pass tables of plan p.
+// w_N^(g y), y < N / g (g = col_group_size(N) > 1), and the pass tables of
+// plan p.
 inline int col_table_entries(const fft_plan& p) {
   const int g = col_group_size(p.N);
   return (g > 1 ? p.N / g : 0) + pass_table_entries(p);
@@ -379,7 +380,9 @@ void set_gram_mfma_attrs();
 template <typename T>
 hipError_t launch_row_fwd(const batch_ref& br, int grid, int maxPx, int maxTw, int with_ey, hipStream_t st);
 template <typename T>
-hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, int maxTw, hipStream_t st);
+// gmask: the filter groups g (bit g) of the batch's frames; one launch per
+// group, each taking the items of its frames
+hipError_t launch_col(const batch_ref& br, int grid, int maxPy, int maxcw, int maxTw, int gmask, hipStream_t st);
 template <typename T>
 hipError_t launch_kernel_dft(const batch_ref& br, int grid, hipStream_t st);
 template <typename T>
@@ -389,7 +392,7 @@ int row_fwd_per_cu(size_t lds, int esize);
 size_t col_lds_bytes(int N, int cw, int twn, int esize);
 int col_max_strip_elems(int esize);   // largest cw * Py the column pass holds
 int col_threads(int N, int cw, int esize);
-int col_per_cu(int N, int cw, int twn, int esize);   // resident column-pass workgroups per CU   // column-pass workgroup size for a strip
+int col_per_cu(int N, int cw, int twn, int g, int esize);   // resident column-pass workgroups per CU   // column-pass workgroup size for a strip
 void set_recover_attrs();
 void set_fft_attrs();
 
