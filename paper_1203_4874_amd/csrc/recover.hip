@@ -66,7 +66,7 @@ struct scale_acc {
   const dd* Db;
   const cdd* C;
   int S;
-  __device__ cdd get(int r, int c) const {
+  __device__ __attribute__((always_inline)) cdd get(int r, int c) const {
     const dd z = {0.0, 0.0};
     if (r < S && c < S) return r == c ? cdd{Da[r], z} : cdd{z, z};
     if (r >= S && c >= S) return r == c ? cdd{Db[r - S], z} : cdd{z, z};
