@@ -117,12 +117,16 @@ static_assert(sizeof(frame_desc) % 16 == 0 &&
 
 int nchunks(int nframes) { return (nframes + BATCH_CHUNK - 1) / BATCH_CHUNK; }
 
-// Workspace head: the frame descriptors and per-queue item prefix sums of a
-// batched call (frames follow it).
+// Workspace head: the frame descriptors, the per-queue item prefix sums and
+// the item counters of the dynamic launches of a batched call (frames follow
+// it).
 size_t head_desc_bytes(int nframes) { return align_up((size_t)nframes * sizeof(frame_desc)); }
+size_t head_starts_bytes(int nframes) {
+  return align_up((size_t)nchunks(nframes) * Q_COUNT * (BATCH_CHUNK + 1) * sizeof(int));
+}
 size_t head_bytes(int nframes) {
-  return head_desc_bytes(nframes) +
-         align_up((size_t)nchunks(nframes) * Q_COUNT * (BATCH_CHUNK + 1) * sizeof(int));
+  return head_desc_bytes(nframes) + head_starts_bytes(nframes) +
+         align_up((size_t)nchunks(nframes) * CTR_COUNT * sizeof(int));
 }
 
 int max_fft(int esize) { return esize == 4 ? CBP_MAX_FFT_F32 : CBP_MAX_FFT_F64; }
@@ -425,6 +429,7 @@ dev_state* get_dev() {
 struct chunk_view {
   const frame_desc* descs;  // device
   const int* starts;        // device
+  int* ctr;                 // device: the chunk's item counters
   int nf;
   int items[Q_COUNT];
   int grid[Q_COUNT];
@@ -446,7 +451,7 @@ int grid_for(int items, int cap) {
 template <typename T>
 hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool diag, hipStream_t st,
                          const inline_head* ih) {
-  const batch_ref b = {cv.descs, cv.starts, cv.nf};
+  const batch_ref b = {cv.descs, cv.starts, cv.nf, cv.ctr};
   auto br = [&](int) { return b; };
   // the first launch (with an inline head it also stores the call's head):
   // a deblurring call's twiddle table of the kernels' row DFTs only, since
@@ -582,6 +587,7 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
     chunk_view cv = {};
     cv.descs = (const frame_desc*)bb->head_dev + f0;
     cv.starts = (const int*)(bb->head_dev + head_desc_bytes(nf)) + (size_t)c * Q_COUNT * (BATCH_CHUNK + 1);
+    cv.ctr = (int*)(bb->head_dev + head_desc_bytes(nf) + head_starts_bytes(nf)) + (size_t)c * CTR_COUNT;
     cv.nf = cnt;
     for (int q = 0; q < Q_COUNT; ++q) {
       // layout of one chunk's prefix sums: [Q][cnt + 1]
@@ -961,7 +967,7 @@ cbp_status cbp_eval_unit_circle(const cbp_image* b, int32_t S, double* ex, doubl
   dev_state* ds = get_dev();
   if (!ds) return CBP_E_DEVICE;
   hipStream_t st = (hipStream_t)opts->stream;
-  const batch_ref br = {(const frame_desc*)ws, (const int*)(ws + head_desc_bytes(1)), 1};
+  const batch_ref br = {(const frame_desc*)ws, (const int*)(ws + head_desc_bytes(1)), 1, nullptr};
   std::lock_guard<std::mutex> lk(ds->launch_mu);
   (void)hipGetLastError();
   auto run = [&]() -> hipError_t {
@@ -1002,7 +1008,7 @@ cbp_status cbp_sample_grams(const cbp_image* b1, const cbp_image* b2, int32_t m,
   dev_state* ds = get_dev();
   if (!ds) return CBP_E_DEVICE;
   const chunk_view& cv = bb.chunks[0];
-  const batch_ref br = {cv.descs, cv.starts, cv.nf};
+  const batch_ref br = {cv.descs, cv.starts, cv.nf, cv.ctr};
   hipStream_t st = (hipStream_t)opts->stream;
   std::lock_guard<std::mutex> lk(ds->launch_mu);
   (void)hipGetLastError();
@@ -1125,7 +1131,7 @@ cbp_status cbp_estimate_kernel_sizes(const cbp_image* b1, const cbp_image* b2, c
   const int NL = 2 * (K1 + (K1 - d)) - 1;
   dev_state* ds = get_dev();
   if (!ds) return CBP_E_DEVICE;
-  const batch_ref br = {cv.descs, cv.starts, cv.nf};
+  const batch_ref br = {cv.descs, cv.starts, cv.nf, cv.ctr};
   hipStream_t st = (hipStream_t)opts->stream;
   std::lock_guard<std::mutex> lk(ds->launch_mu);
   (void)hipGetLastError();

@@ -56,6 +56,10 @@ __device__ inline void twiddle_item(const frame_desc& d, int item) {
 template <typename T>
 __global__ __launch_bounds__(64) void k_fold_cols(batch_ref br_ws, int gf, inline_head ih) {
   batch_ref br = br_ws;
+  // the call's item counters start at zero (the later launches of the
+  // chunk hand out their items from them)
+  if (blockIdx.x == 0 && br_ws.ctr != nullptr)
+    for (int i = threadIdx.x; i < CTR_COUNT; i += blockDim.x) br_ws.ctr[i] = 0;
   if (ih.ndesc_bytes > 0) {
     br.descs = (const frame_desc*)ih.bytes;
     br.starts = (const int*)(ih.bytes + ih.ndesc_bytes);

@@ -394,12 +394,15 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
   constexpr int SM = G * col_groups<T, NT, G>();
   constexpr int PF = (col_max_elems<T, NT>() + NT - 1) / NT;   // strip entries per thread
   constexpr int LNT = NT == 1024 ? 10 : NT == 512 ? 9 : 8;
+  __shared__ int s_next[2];   // the workgroup's next items (thread 0 takes them), alternate slots
   const int nf = br.nframes;
   const int* sq = br.starts + (size_t)Q_COL * (nf + 1);
   for (int t = threadIdx.x; t <= nf; t += NT) st[t] = sq[t];
   __syncthreads();
-  int first, end, step;
-  xcd_items(__builtin_amdgcn_readfirstlane(st[nf]), (int)blockIdx.x, (int)gridDim.x, first, end, step);
+  // items handed out dynamically from this group's counters (dyn_items)
+  const dyn_items q = make_dyn_items(br.ctr + CTR_COL + 8 * (G == 4 ? 0 : G == 2 ? 1 : 2),
+                                     __builtin_amdgcn_readfirstlane(st[nf]), (int)blockIdx.x, (int)gridDim.x);
+  const int end = q.hi;
   auto frame_of = [&](int it) __attribute__((always_inline)) {
     int lo = 0, hi = nf;   // st[lo] <= it < st[hi]
     while (hi - lo > 1) {
@@ -442,18 +445,35 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
   auto first_frame = [&](int it) __attribute__((always_inline)) {
     return (desc(frame_of(it)).variant & VAR_DIVIDE_B1) ? 0 : 1;   // frame 2 first when both are divided
   };
-  // the first item at or after it of a frame with group G (end: none)
-  auto next_item = [&](int it) __attribute__((always_inline)) {
-    for (; it < end; it += step)
-      if (col_group_size(desc(frame_of(it)).fy.N) == G) break;
-    return it < end ? it : end;
+  // Thread 0: from the item raw taken (its counter value, whose atomic may
+  // still be in flight), the first item of a frame with group G (end: none;
+  // the items of other groups are passed over, their launch has its own
+  // counters).
+  auto settle = [&](int raw) __attribute__((always_inline)) {
+    int i = raw;
+    while (i < end && col_group_size(desc(frame_of(i)).fy.N) != G) i = q.take();
+    return i;
   };
-  const int it0 = next_item(first);
+  // one item ahead: the counter value taken while an item is processed is
+  // read only when the next one starts, so the atomic's latency is hidden
+  int ahead = 0;
+  if (threadIdx.x == 0) {
+    s_next[0] = settle(q.take());
+    ahead = q.lo + atomicAdd(q.ctr, 1);
+  }
+  __syncthreads();
+  const int it0 = __builtin_amdgcn_readfirstlane(s_next[0]);
   if (it0 < end) fetch(it0, first_frame(it0));
   int tabN = 0;                   // length of the full twiddle table in LDS
   int tabNp = 0;                  // plan of the pass tables in LDS (length,
   unsigned long long tabCode = 0;   // pass order)
-  for (int it = it0, nit; it < end; it = nit) {
+  for (int it = it0, nit, par = 1; it < end; it = nit, par ^= 1) {
+    // the item after this one, read by every thread after the next barrier
+    // (slot par: its last reads were two items ago)
+    if (threadIdx.x == 0) {
+      s_next[par] = settle(ahead < end ? ahead : end);
+      ahead = q.lo + atomicAdd(q.ctr, 1);
+    }
     const int fi = frame_of(it);
     const frame_desc d = desc(fi);
     const int item = it - __builtin_amdgcn_readfirstlane(st[fi]);
@@ -527,7 +547,7 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
     spill(H1);
     __syncthreads();
     // the next item's first strip in flight while this one is finished
-    nit = next_item(it + step);
+    nit = __builtin_amdgcn_readfirstlane(s_next[par]);
     if (nit < end) fetch(nit, first_frame(nit));
     ip_fft<-1, NT, col_max_elems<T, NT>()>(buf, ld, py, twp, cw);
     // filter: the combined spectrum in place of frame 1's

@@ -119,7 +119,14 @@ struct batch_ref {
   const frame_desc* descs;  // nframes descriptors
   const int* starts;        // [Q_COUNT][nframes + 1] item prefix sums
   int nframes;
+  int* ctr;                 // [CTR_COUNT] item counters of the dynamic launches (zeroed by the first launch)
 };
+
+// Item counters of a chunk's dynamically scheduled launches, eight each (one
+// per XCD): the row pass, the inverse rows, and the column pass per filter
+// group (4, 2, 1).
+constexpr int CTR_ROW_FWD = 0, CTR_ROW_INV = 8, CTR_COL = 16, CTR_COUNT = 64;
+static_assert(CTR_COL + 3 * 8 <= CTR_COUNT, "counter block");
 
 // Rows per group of the column filter's kernel-spectrum evaluation (rows
 // y + j N/g, j < g, share one Horner chain in w_N^(g y)): 4, 2 or 1 as N
@@ -151,6 +158,27 @@ __device__ inline void xcd_items(int T, int b, int G, int& first, int& end, int&
   first = (int)(((int64_t)x * T) >> 3) + (b >> 3);
   end = (int)(((int64_t)(x + 1) * T) >> 3);
   step = G >> 3;
+}
+
+// Items [0, T) of a persistent grid handed out dynamically: workgroup b of G
+// takes the items of its XCD's range [x T / 8, (x + 1) T / 8) (x = b mod 8,
+// the XCD it runs on when G is a multiple of 8; otherwise one range) one at
+// a time from that range's counter, so a workgroup that starts late (its CU
+// still busy with another launch) takes fewer items instead of delaying the
+// launch, and adjacent items still share an XCD's L2.
+struct dyn_items {
+  int* ctr;
+  int lo, hi;
+  // one thread: the next item, hi when the range is exhausted
+  __device__ int take() const {
+    const int i = lo + atomicAdd(ctr, 1);
+    return i < hi ? i : hi;
+  }
+};
+__device__ inline dyn_items make_dyn_items(int* ctr8, int T, int b, int G) {
+  if (G < 8 || (G & 7) != 0) return dyn_items{ctr8, 0, T};
+  const int x = b & 7;
+  return dyn_items{ctr8 + x, (int)(((int64_t)x * T) >> 3), (int)(((int64_t)(x + 1) * T) >> 3)};
 }
 
 // Run body(frame, item) for every item of queue Q owned by workgroup b of
