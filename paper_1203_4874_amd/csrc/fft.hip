@@ -399,9 +399,14 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
   const int* sq = br.starts + (size_t)Q_COL * (nf + 1);
   for (int t = threadIdx.x; t <= nf; t += NT) st[t] = sq[t];
   __syncthreads();
-  // items handed out dynamically from this group's counters (dyn_items)
-  const dyn_items q = make_dyn_items(br.ctr + CTR_COL + 8 * (G == 4 ? 0 : G == 2 ? 1 : 2),
-                                     __builtin_amdgcn_readfirstlane(st[nf]), (int)blockIdx.x, (int)gridDim.x);
+  // items handed out dynamically from this group's counters (dyn_items);
+  // with no more items than workgroups, one item per workgroup as
+  // xcd_items assigns them (a workgroup that took two, one ahead, would
+  // leave another idle)
+  const int ntot = __builtin_amdgcn_readfirstlane(st[nf]);
+  const bool dyn = ntot > (int)gridDim.x;
+  const dyn_items q = make_dyn_items(br.ctr + CTR_COL + 8 * (G == 4 ? 0 : G == 2 ? 1 : 2), ntot, (int)blockIdx.x,
+                                     (int)gridDim.x);
   const int end = q.hi;
   auto frame_of = [&](int it) __attribute__((always_inline)) {
     int lo = 0, hi = nf;   // st[lo] <= it < st[hi]
@@ -451,15 +456,21 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
   // counters).
   auto settle = [&](int raw) __attribute__((always_inline)) {
     int i = raw;
-    while (i < end && col_group_size(desc(frame_of(i)).fy.N) != G) i = q.take();
+    while (i < end && col_group_size(desc(frame_of(i)).fy.N) != G) i = dyn ? q.take() : end;
     return i;
   };
   // one item ahead: the counter value taken while an item is processed is
   // read only when the next one starts, so the atomic's latency is hidden
-  int ahead = 0;
+  int ahead = end;
   if (threadIdx.x == 0) {
-    s_next[0] = settle(q.take());
-    ahead = q.lo + atomicAdd(q.ctr, 1);
+    if (dyn) {
+      s_next[0] = settle(q.take());
+      ahead = q.lo + atomicAdd(q.ctr, 1);
+    } else {
+      int first, last, step;
+      xcd_items(ntot, (int)blockIdx.x, (int)gridDim.x, first, last, step);
+      s_next[0] = settle(first < last ? first : end);
+    }
   }
   __syncthreads();
   const int it0 = __builtin_amdgcn_readfirstlane(s_next[0]);
@@ -472,7 +483,7 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_col_filter(batch
     // (slot par: its last reads were two items ago)
     if (threadIdx.x == 0) {
       s_next[par] = settle(ahead < end ? ahead : end);
-      ahead = q.lo + atomicAdd(q.ctr, 1);
+      ahead = dyn ? q.lo + atomicAdd(q.ctr, 1) : end;
     }
     const int fi = frame_of(it);
     const frame_desc d = desc(fi);
