@@ -47,18 +47,23 @@ struct small_ws {
   c64* x;       // n: result vector
   double* a;    // n: diagonal of T
   double* b;    // n: off-diagonal of T, b[k] = T[k+1][k]
-  dd* part;     // 4 x 64 x 2: partial double-double row sums of the refinement's product
-  c64* W;       // n x (n+1) entries: the solver keeps X in the second half; callers may keep up to
-                //   n^2 doubles in the first half across a solve
-  double* X;    // n x n: (T - sigma I)^{-1}, from double offset n^2 of W
+  dd* part;     // 64 x 2: partial double-double row sums of the refinement's product (ng n <= 64 lanes)
+  c64* W;       // with a caller half: n x (n+1) entries, the solver keeping X in the second half and
+                //   callers up to n^2 doubles in the first half across a solve; else X alone
+  double* X;    // n x n: (T - sigma I)^{-1}
 };
 
-__host__ __device__ inline size_t small_lds_bytes(int n) {
+// LDS of a solve of order n; caller_half: the W region also holds the
+// caller's n^2 doubles (the scale solve's coupling block), else only X (a
+// smaller footprint, so that the sample solves fit on a CU beside the FFT
+// passes' workgroups).
+__host__ __device__ inline size_t small_lds_bytes(int n, bool caller_half = true) {
   return (size_t)n * n * sizeof(c64) + (size_t)n * (4 * sizeof(c64) + 2 * sizeof(double)) +
-         (size_t)4 * 64 * 2 * sizeof(dd) + (size_t)n * (n + 1) * sizeof(c64) + 64;
+         (size_t)SMALL_NT * 2 * sizeof(dd) +
+         (caller_half ? (size_t)n * (n + 1) * sizeof(c64) : (size_t)n * n * sizeof(double)) + 64;
 }
 
-__device__ inline small_ws small_carve(char* base, int n) {
+__device__ inline small_ws small_carve(char* base, int n, bool caller_half = true) {
   small_ws s;
   char* p = base;
   s.A = (c64*)p; p += (size_t)n * n * sizeof(c64);
@@ -68,9 +73,9 @@ __device__ inline small_ws small_carve(char* base, int n) {
   s.x = (c64*)p; p += n * sizeof(c64);
   s.a = (double*)p; p += n * sizeof(double);
   s.b = (double*)p; p += n * sizeof(double);
-  s.part = (dd*)p; p += (size_t)4 * 64 * 2 * sizeof(dd);
+  s.part = (dd*)p; p += (size_t)SMALL_NT * 2 * sizeof(dd);
   s.W = (c64*)p;
-  s.X = (double*)p + (size_t)n * n;
+  s.X = caller_half ? (double*)p + (size_t)n * n : (double*)p;
   return s;
 }
 

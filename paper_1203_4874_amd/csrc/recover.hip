@@ -147,7 +147,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_sample(batch_ref br) {
     const int l = threadIdx.x;
     cbp_diag* diag = d.diag;
     cdd* rho = (cdd*)sm_sample;
-    small_ws w = small_carve(sm_sample + (((size_t)NL * sizeof(cdd) + 15) & ~(size_t)15), N);
+    small_ws w = small_carve(sm_sample + (((size_t)NL * sizeof(cdd) + 15) & ~(size_t)15), N, false);
     for (int t = l; t < NL; t += SMALL_NT) rho[t] = d.corr[((size_t)pass * S + j) * NL + t];
     __syncthreads();
     const gram_acc G{rho, k1, k2};
@@ -842,7 +842,7 @@ size_t finalize_lds_bytes(int S, int learned) {
 }
 
 size_t sample_lds_bytes(int N) {
-  return ((((size_t)(2 * N - 1) * sizeof(cdd)) + 15) & ~(size_t)15) + small_lds_bytes(N);
+  return ((((size_t)(2 * N - 1) * sizeof(cdd)) + 15) & ~(size_t)15) + small_lds_bytes(N, false);
 }
 
 void set_recover_attrs() {
