@@ -168,6 +168,40 @@ def test_graph_replays_equal_eager(P):
     assert rel(g.K1s[1].cpu().numpy(), R1) <= 1e-3
 
 
+def test_graph_replays_with_dynamic_column_items(P):
+    """A batch whose column pass has more strips than workgroups hands them
+    out from counters in the workspace head, which every call (and every
+    replay of its graph) starts from zero: replays equal the eager call bit
+    for bit, and a frame of the batch equals the same frame alone (one strip
+    per workgroup, no counters)."""
+    shapes = [(720, 1280, 7, 9)] * 6
+    frames, host = uneven_frames(907, shapes, np.float32, noise=1e-3)
+    d = _deblurrer(P, frames, 1, len(frames))
+    eager = d.prepare_batch(frames, lam=1e-4)
+    eager.run()
+    torch.cuda.synchronize()
+    ref = [(L.clone(), K1.clone()) for L, K1 in zip(eager.latents, eager.K1s)]
+    g = d.prepare_batch(frames, lam=1e-4, flags=P.Flags.GRAPH)
+    for rep in range(3):
+        for L in g.latents:
+            L.zero_()
+        g.run()
+        torch.cuda.synchronize()
+        for (L, K1), (Lr, K1r) in zip(zip(g.latents, g.K1s), ref):
+            assert torch.equal(L, Lr) and torch.equal(K1, K1r), rep
+        eager.run()
+        torch.cuda.synchronize()
+    one = _deblurrer(P, frames[:1], 1, 1)
+    b1, b2, m, n = frames[2]
+    L1, J1, _ = one.deblur(b1, b2, m, n, lam=1e-4)
+    torch.cuda.synchronize()
+    assert torch.equal(L1, ref[2][0]) and torch.equal(J1, ref[2][1])
+    h = host[2]
+    Lo, R1, _ = orc.deblur(h["B1"], h["B2"], m, n, 0, 1e-4)
+    assert rel(J1.cpu().numpy(), R1) <= 1e-3
+    assert psnr(L1.cpu().numpy(), Lo) >= 60
+
+
 def test_graph_single_frame_call(P):
     c = synth.config2()
     b1 = to_dev(c["B1"].astype(np.float32), torch.float32)
