@@ -577,7 +577,8 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
   for (int i = 0; i < nf; ++i) {
     const frame_req& r = reqs[bb->idx[i]];
     descs[i] = make_desc(bb->plans[i], r.b1, r.b2, ws + off, r.K1, r.K2, r.latent, o->lambda, r.diag,
-                         o->learned != 0, variant_bits(o->flags));
+                         o->learned != 0,
+                         variant_bits(o->flags) | (gram_format(o->precision) >= 0 ? VAR_FP64_GRAM : 0));
     off += bb->plans[i].total;
   }
   const int cap = tn.wg_per_cu > 0 ? tn.wg_per_cu * kComputeUnits : 0;

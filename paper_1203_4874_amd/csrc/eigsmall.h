@@ -666,9 +666,11 @@ __device__ inline __attribute__((always_inline)) c64 q_apply(const small_ws& s, 
 // entry l) and *steps the number of refinement steps.  With want_diag it
 // returns mu = x^H G x (dd) of that vector and *lam1 receives the second
 // smallest eigenvalue; without, both are NaN (the product G x of the final
-// vector serves only mu, so it is skipped).
+// vector serves only mu, so it is skipped).  max_refine bounds the Newton
+// steps: 0 leaves the inverse-iteration vector.
 template <class Acc>
-__device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_diag, double* lam1, int* steps) {
+__device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_diag, double* lam1, int* steps,
+                               int max_refine = SMALL_REFINE_MAX) {
   const int l = threadIdx.x;
   if (n == 1) {
     if (l == 0) s.x[0] = {1.0, 0.0};
@@ -706,6 +708,10 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_dia
   }
   if (l < n) s.x[l] = xl;
   __syncthreads();
+  if (max_refine == 0 && !want_diag) {
+    *steps = 0;
+    return dd{__builtin_nan(""), 0.0};
+  }
   // Newton refinement against the double-double matrix.  The product G x is
   // split over ng lane groups (lane l: row l mod n, columns of group l / n),
   // whose partial sums are added in group order.
@@ -749,7 +755,7 @@ __device__ inline dd small_eig(small_ws& s, const Acc& acc, int n, bool want_dia
     t.add_prod(xl.re, yre.hi); t.add(xl.re * yre.lo);
     t.add_prod(xl.im, yim.hi); t.add(xl.im * yim.lo);
     mu = wsum_dd(t.result());
-    if (done || it == SMALL_REFINE_MAX) break;
+    if (done || it == max_refine) break;
     c64 r = {0.0, 0.0};
     if (l < n) {
       dot2 qr, qi;

@@ -83,7 +83,7 @@ struct frame_desc {
   // column pass; the FFT passes build short tables of their own in LDS)
   c64* twxd;
   // paper-faithful variants (CBP_FLAG_DIVIDE_B1 / SCALE_K1 / ONE_AXIS as
-  // VAR_* bits); 0 = the default method
+  // VAR_* bits; 0 = the default method) and VAR_FP64_GRAM
   int variant;
   int hxp;           // row pitch of T and U (entries), a multiple of 128 bytes
   // the kernels' row DFTs at every half-spectrum column, [hx][2][CBP_MAX_K]
@@ -91,6 +91,14 @@ struct frame_desc {
   void* kr;
 };
 constexpr int VAR_DIVIDE_B1 = 1, VAR_SCALE_K1 = 2, VAR_ONE_AXIS = 4;
+// The Gram is formed on the matrix cores (MFMA64, MFMA32, BF16): these forms
+// work to the mixed-precision accuracy (kernels within 1e-3 of the FP64
+// method), so the eigen-solves stop at the inverse-iteration vector (on the
+// 1080p RGB stream within 2e-6 of the FP64 method's kernels; the
+// double-double Newton refinement would take it to 3e-7, the level the FP64
+// Gram's own rounding leaves, at a third of the solves' time).
+constexpr int VAR_FP64_GRAM = 8;
+__host__ __device__ inline int solve_refine_max(int variant) { return (variant & VAR_FP64_GRAM) ? 0 : 4; }
 
 // Work items of each queue for one frame (the grid of a one-frame launch).
 inline int queue_items(int q, const frame_plan& p) {

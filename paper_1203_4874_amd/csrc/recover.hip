@@ -160,7 +160,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_sample(batch_ref br) {
     __syncthreads();
     double lam1;
     int steps;
-    const dd mu = small_eig(w, G, N, diag != nullptr, &lam1, &steps);
+    const dd mu = small_eig(w, G, N, diag != nullptr, &lam1, &steps, solve_refine_max(d.variant));
     const size_t base = ((size_t)pass * S + j) * N;
     const c64 xi = l < N ? w.x[l] : c64{0.0, 0.0};
     if (l < N) {
@@ -313,7 +313,7 @@ struct cdd_mat_acc {
 // and a is its smallest eigenvector; K_c[y][x] = (1/S) sum_j a_j X^c_j[x] w_j^{-y}.
 __device__ inline __attribute__((always_inline)) void one_axis_frame(const c64* xvec, int S, int k1, int k2,
                                                                       double* K1, double* K2, cbp_diag* diag,
-                                                                      char* sm_fin) {
+                                                                      char* sm_fin, int variant) {
   const int N = k1 + k2, SS = S * S, tid = threadIdx.x;
   const float rS = 1.0f / (float)S;
   c64* tw = (c64*)sm_fin;                                   // S
@@ -362,7 +362,7 @@ __device__ inline __attribute__((always_inline)) void one_axis_frame(const c64* 
   __syncthreads();
   double lam1;
   int steps;
-  const dd mu = small_eig(w, H, S, diag != nullptr, &lam1, &steps);
+  const dd mu = small_eig(w, H, S, diag != nullptr, &lam1, &steps, solve_refine_max(variant));
   if (tid == 0 && diag) {
     diag->k1 = k1; diag->k2 = k2; diag->S = S; diag->n = N;
     diag->scale_lambda0 = dd_val(mu);
@@ -404,7 +404,7 @@ __device__ inline __attribute__((always_inline)) void one_axis_frame(const c64* 
 __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* xvec, int S, int k1, int k2, c64* pq, double* K1,
                                       double* K2, cbp_diag* diag, char* sm_fin, const double* wts, int variant) {
   if (variant & VAR_ONE_AXIS) {
-    one_axis_frame(xvec, S, k1, k2, K1, K2, diag, sm_fin);
+    one_axis_frame(xvec, S, k1, k2, K1, K2, diag, sm_fin, variant);
     return;
   }
   // kernel 1's equations only (the k1-only scale least squares) or both kernels'
@@ -508,7 +508,7 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
   __syncthreads();
   double lam1;
   int steps;
-  const dd mu = small_eig(w, H, n2, diag != nullptr, &lam1, &steps);
+  const dd mu = small_eig(w, H, n2, diag != nullptr, &lam1, &steps, solve_refine_max(variant));
   if (tid == 0 && diag) {
     diag->k1 = k1; diag->k2 = k2; diag->S = S; diag->n = N;
     diag->scale_lambda0 = dd_val(mu);
