@@ -570,38 +570,52 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
     if (bad1 || bad2) zero_kernels(K1, k1, K2, k2);
     return;
   }
-  // inverse DFT along x: Tm[c][j][x] = sum_i Kh[c][i][j] w_i^{-x}
-  for (int e = tid; e < 2 * SS; e += SMALL_NT) {
-    int c, jx;
+  // inverse DFT along x: Tm[c][j][x] = sum_i Kh[c][i][j] w_i^{-x}, two
+  // outputs per lane at a time (independent chains, each summed in i order)
+  for (int e = tid; e < 2 * SS; e += 2 * SMALL_NT) {
+    const int f = min(e + SMALL_NT, 2 * SS - 1);
+    int c, jx, jj, x, c2, jx2, jj2, x2;
     split_index(e, SS, rSS, c, jx);
-    int jj, x;
     split_index(jx, S, rS, jj, x);
-    c64 acc = {0.0, 0.0};
-    int t = 0;
+    split_index(f, SS, rSS, c2, jx2);
+    split_index(jx2, S, rS, jj2, x2);
+    c64 acc = {0.0, 0.0}, acc2 = {0.0, 0.0};
+    int t = 0, t2 = 0;
 #pragma unroll 4
     for (int i = 0; i < S; ++i) {
       acc = acc + Kh[(size_t)c * SS + i * S + jj] * conj(tw[t]);
+      acc2 = acc2 + Kh[(size_t)c2 * SS + i * S + jj2] * conj(tw[t2]);
       t += x;
       if (t >= S) t -= S;
+      t2 += x2;
+      if (t2 >= S) t2 -= S;
     }
     Tm[e] = acc;
+    if (e + SMALL_NT < 2 * SS) Tm[f] = acc2;
   }
   __syncthreads();
-  // inverse DFT along y: Kf[c][y][x] = sum_j w_j^{-y} Tm[c][j][x]   (into Kh)
-  for (int e = tid; e < 2 * SS; e += SMALL_NT) {
-    int c, yx;
+  // inverse DFT along y: Kf[c][y][x] = sum_j w_j^{-y} Tm[c][j][x]   (into Kh),
+  // two outputs per lane at a time as above
+  for (int e = tid; e < 2 * SS; e += 2 * SMALL_NT) {
+    const int f = min(e + SMALL_NT, 2 * SS - 1);
+    int c, yx, y, x, c2, yx2, y2, x2;
     split_index(e, SS, rSS, c, yx);
-    int y, x;
     split_index(yx, S, rS, y, x);
-    c64 acc = {0.0, 0.0};
-    int t = 0;
+    split_index(f, SS, rSS, c2, yx2);
+    split_index(yx2, S, rS, y2, x2);
+    c64 acc = {0.0, 0.0}, acc2 = {0.0, 0.0};
+    int t = 0, t2 = 0;
 #pragma unroll 4
     for (int jj = 0; jj < S; ++jj) {
       acc = acc + Tm[(size_t)c * SS + jj * S + x] * conj(tw[t]);
+      acc2 = acc2 + Tm[(size_t)c2 * SS + jj * S + x2] * conj(tw[t2]);
       t += y;
       if (t >= S) t -= S;
+      t2 += y2;
+      if (t2 >= S) t2 -= S;
     }
     Kh[e] = acc;
+    if (e + SMALL_NT < 2 * SS) Kh[f] = acc2;
   }
   __syncthreads();
   if (normalise_kernels(Kh, Kh + SS, S, k1, k2, K1, K2, diag)) zero_kernels(K1, k1, K2, k2);
