@@ -19,6 +19,8 @@
 // fixed order, so results do not depend on scheduling).
 #include "internal.h"
 
+#include <type_traits>
+
 namespace cbp {
 
 namespace {
@@ -167,18 +169,76 @@ __global__ __launch_bounds__(256) void k_gram_mfma(batch_ref br) {
 // ---------------------------------------------------------------- FP64 matrix cores
 // Precision form MFMA64: the Gram's correlations on v_mfma_f64_16x16x4f64
 // from the FP64 evaluations themselves (no operand rounding), FP64
-// accumulation.  Only the columns 0 and k2 of G are needed (every correlation
-// is in them: rho11(l) = G[l][0], rho22(l) = G[k2+l][k2], rho12(l) = -G[l][k2]
-// for l >= 0 and -conj(G[k2-l][0]) for l < 0), so only the four columns
-// {0, k2, N, N + k2} of R = M^T M are formed: four 16 x 16 tiles (rows p of
-// R in blocks of 16) whose first four columns are those (B's other columns
-// are zero).  v_mfma_f64_16x16x4f64 takes A[i][k] from lane 16 k + i, B[k][j]
-// from lane 16 k + j and leaves D[4 (lane / 16) + v][lane % 16] in
-// accumulator v of each lane.
+// accumulation.  Every correlation is in the columns 0 and k2 of G, so only
+// the four columns {0, k2, N, N + k2} of R = M^T M are needed, and each of
+// those columns has shift 0: with the staged arrays x_0 = Re e1, x_1 =
+// -Re e2, x_2 = Im e1, x_3 = -Im e2 (x_a has k_a shifts: k2 for e1, k1 for
+// e2),
+//   R[(a, s)][(b, 0)] = c_ab(s) = sum_r x_a[r] x_b[r + s],  0 <= s < k_a,
+// a lag correlation of two staged arrays.  With the rows split into blocks
+// of 16, D_ab[i][j] = sum_m x_a[16 m + i] x_b[16 m + j] gives every lag at
+// once: c_ab(l) = sum_{i<16} D_ab[i][i + l].  D_ab is formed in 16 x 16 tiles
+// (columns j in [16 t, 16 t + 16)) by the matrix cores, K = 4 blocks (64
+// rows) per instruction: A[i][k] = x_a[16 (m0 + k) + i] and B[k][jj] =
+// x_b[16 (m0 + k) + 16 t + jj] are both the contiguous run x[64 step + lane]
+// (shifted by 16 t for B).  For a < b one tile range serves c_ab and c_ba
+// (c_ba(s) = c_ab(-s)); lags l in [-(k_b - 1), k_a - 1] need t from
+// -ceil((k_b - 1) / 16) to floor((k_a + 14) / 16), for a = b t from 0.  That
+// is 26 tiles for 2 <= k1, k2 <= 17 and at most 34 for k1 + k2 <= 32; each
+// tile belongs to one wave for all rows, so no partial sums are combined and
+// the result does not depend on scheduling.
+// v_mfma_f64_16x16x4f64 takes A[i][k] from lane 16 k + i, B[k][j] from lane
+// 16 k + j and leaves D[4 v + lane / 16][lane % 16] in accumulator v.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int GM64_RS = 5;      // row stride of the R column buffer (doubles)
-constexpr int GM64_WAVES = 16;  // waves per workgroup: the rows of one item are split over them
+constexpr int GM64_WAVES = 16;  // waves per workgroup; tile u of wave w is w + 16 u
+constexpr int GM64_TPW = 3;     // tiles per wave at most
+
+// Shifts of staged array a (e1 arrays: k2, e2 arrays: k1).
+__host__ __device__ constexpr int gm64_k(int a, int k1, int k2) { return (a & 1) ? k1 : k2; }
+__host__ __device__ constexpr int gm64_tlo(int a, int b, int k1, int k2) {
+  return a == b ? 0 : -((gm64_k(b, k1, k2) + 14) >> 4);
+}
+__host__ __device__ constexpr int gm64_thi(int a, int k1, int k2) { return (gm64_k(a, k1, k2) + 14) >> 4; }
+// Tiles of the (k1, k2) item: pairs a <= b in order (0,0), (0,1), .. (3,3).
+__host__ __device__ constexpr int gm64_tiles(int k1, int k2) {
+  int n = 0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = a; b < 4; ++b) n += gm64_thi(a, k1, k2) - gm64_tlo(a, b, k1, k2) + 1;
+  return n;
+}
+constexpr int gm64_max_tiles() {
+  int m = 0;
+  for (int k1 = 1; k1 < 32; ++k1)
+    for (int k2 = 1; k1 + k2 <= 32; ++k2) m = gm64_tiles(k1, k2) > m ? gm64_tiles(k1, k2) : m;
+  return m;
+}
+constexpr int GM64_MAX_TILES = gm64_max_tiles();
+static_assert(GM64_MAX_TILES <= GM64_WAVES * GM64_TPW, "tiles per wave");
+
+// Tile index of (pair (a, b), a <= b, column block t) and its decode.
+__device__ inline int gm64_tile_of(int a, int b, int t, int k1, int k2) {
+  int n = 0;
+  for (int aa = 0; aa < 4; ++aa)
+    for (int bb = aa; bb < 4; ++bb) {
+      const int lo = gm64_tlo(aa, bb, k1, k2);
+      if (aa == a && bb == b) return n + t - lo;
+      n += gm64_thi(aa, k1, k2) - lo + 1;
+    }
+  return -1;
+}
+struct gm64_tile { int a, b, t; };
+__device__ inline gm64_tile gm64_decode(int tile, int k1, int k2) {
+  int n = 0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = a; b < 4; ++b) {
+      const int lo = gm64_tlo(a, b, k1, k2), cnt = gm64_thi(a, k1, k2) - lo + 1;
+      if (tile < n + cnt) return {a, b, lo + tile - n};
+      n += cnt;
+    }
+  return {0, 0, 0};
+}
 
 __global__ __launch_bounds__(64 * GM64_WAVES) void k_gram_mfma64(batch_ref br) {
   extern __shared__ __attribute__((aligned(16))) char sm_gm[];
@@ -186,65 +246,104 @@ __global__ __launch_bounds__(64 * GM64_WAVES) void k_gram_mfma64(batch_ref br) {
     const int S = d.S, k1 = d.k1, k2 = d.k2, N = k1 + k2, NL = 2 * N - 1;
     const int j = item % S, pass = item / S;
     const int len1 = pass ? d.H1 : d.W1, len2 = pass ? d.H2 : d.W2;
-    const int L = len1 + k2 - 1;
     const int stride = pass ? d.Hmax : d.Wmax;
     const int P = stride + GM_PAD;
     const c64* base = pass ? d.ey : d.ex;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     double* Rc = (double*)sm_gm;                       // [64][GM64_RS]: R[p][{0, k2, N, N + k2}]
-    double* sd = Rc + 64 * GM64_RS + 3;                // [4][P] staged re / im of e1 and -e2 (odd offset: 16-B aligned below)
-    sd = (double*)(((size_t)sd + 15) & ~(size_t)15);
-    // this lane's operands: A rows p = 16 pb + lane % 16 (four blocks pb),
-    // B column jj = lane % 16 (columns 0..3 map to R's q in {0, k2, N, N + k2})
-    const int i16 = lane & 15, kk = lane >> 4;
-    mcol ca[4];
+    double* sd = Rc + 64 * GM64_RS + 4;                // [4][P] staged x_0..x_3 (2592 B in: 16-B aligned)
+    double* Dt = sd;                                   // [tiles][16][16], over the staging area once it is free
+    // x_a is nonzero on [0, len_a): 16-row blocks up to the longer one, in steps of four
+    const int nsteps = (max(len1, len2) + 63) >> 6;
+    const int ntile = gm64_tiles(k1, k2);
+    int ta[GM64_TPW], tb[GM64_TPW];
 #pragma unroll
-    for (int pb = 0; pb < 4; ++pb) ca[pb] = column_of(16 * pb + i16, k2, N);
-    const int qs[4] = {0, k2, N, N + k2};
-    const mcol cb = i16 < 4 ? column_of(qs[i16], k2, N) : mcol{-1, 0};
-    v4d acc[4] = {};
-    for (int ch = 0; ch < d.nch; ++ch) {
+    for (int u = 0; u < GM64_TPW; ++u) {
+      const gm64_tile tl = gm64_decode(w + GM64_WAVES * u, k1, k2);
+      ta[u] = tl.a * P + GM_PAD_L + lane;
+      tb[u] = tl.b * P + GM_PAD_L + 16 * tl.t + lane;
+    }
+    const int nt = __builtin_amdgcn_readfirstlane(ntile > w ? (ntile - w + GM64_WAVES - 1) / GM64_WAVES : 0);
+    v4d acc[GM64_TPW] = {};
+    // channel ch's entries t = tid + 1024 q (q < GM64_PF) are loaded into
+    // registers while the previous channel's steps run, and staged after them
+    constexpr int GM64_PF = 3;
+    c64 fa[GM64_PF], fb[GM64_PF];
+    auto fetch = [&](int ch) __attribute__((always_inline)) {
       const c64* e1 = base + ((size_t)(ch * 2 + 0) * S + j) * stride;
       const c64* e2 = base + ((size_t)(ch * 2 + 1) * S + j) * stride;
-      for (int t = tid; t < P; t += 64 * GM64_WAVES) {
-        const int i1 = t - GM_PAD_L;
-        const c64 a = (i1 >= 0 && i1 < len1) ? e1[i1] : c64{0.0, 0.0};
-        const c64 b = (i1 >= 0 && i1 < len2) ? e2[i1] : c64{0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < GM64_PF; ++q) {
+        const int i1 = tid + 64 * GM64_WAVES * q - GM_PAD_L;
+        fa[q] = (i1 >= 0 && i1 < len1) ? e1[i1] : c64{0.0, 0.0};
+        fb[q] = (i1 >= 0 && i1 < len2) ? e2[i1] : c64{0.0, 0.0};
+      }
+    };
+    auto put = [&](int ch) __attribute__((always_inline)) {
+      auto st4 = [&](int t, c64 a, c64 b) __attribute__((always_inline)) {
         sd[0 * P + t] = a.re; sd[1 * P + t] = -b.re;
         sd[2 * P + t] = a.im; sd[3 * P + t] = -b.im;
+      };
+#pragma unroll
+      for (int q = 0; q < GM64_PF; ++q) {
+        const int t = tid + 64 * GM64_WAVES * q;
+        if (t < P) st4(t, fa[q], fb[q]);
       }
-      __syncthreads();
-      const double* pa[4];
-#pragma unroll
-      for (int pb = 0; pb < 4; ++pb) pa[pb] = ca[pb].arr >= 0 ? sd + ca[pb].arr * P + GM_PAD_L - ca[pb].shift : nullptr;
-      const double* pbp = cb.arr >= 0 ? sd + cb.arr * P + GM_PAD_L - cb.shift : nullptr;
-      // K = 4 rows per step: lane supplies row r0 + lane / 16; wave w takes
-      // steps w, w + GM64_WAVES, ...
-      for (int r0 = 4 * w; r0 < L; r0 += 4 * GM64_WAVES) {
-        const int r = r0 + kk;
-        const double bv = pbp ? pbp[r] : 0.0;
-#pragma unroll
-        for (int pb = 0; pb < 4; ++pb) {
-          const double av = pa[pb] ? pa[pb][r] : 0.0;
-          acc[pb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[pb], 0, 0, 0);
-        }
+      const c64* e1 = base + ((size_t)(ch * 2 + 0) * S + j) * stride;
+      const c64* e2 = base + ((size_t)(ch * 2 + 1) * S + j) * stride;
+      for (int t = tid + 64 * GM64_WAVES * GM64_PF; t < P; t += 64 * GM64_WAVES) {
+        const int i1 = t - GM_PAD_L;   // >= 0 here
+        st4(t, i1 < len1 ? e1[i1] : c64{0.0, 0.0}, i1 < len2 ? e2[i1] : c64{0.0, 0.0});
       }
-      __syncthreads();  // staging buffers are rewritten for the next channel
-    }
-    // the waves' partial columns summed into Rc in wave order
-    for (int ww = 0; ww < GM64_WAVES; ++ww) {
-      if (w == ww && i16 < 4) {
+    };
+    fetch(0);
+    put(0);
+    __syncthreads();
+    for (int ch = 0; ch < d.nch; ++ch) {
+      if (ch + 1 < d.nch) fetch(ch + 1);
+      // the wave's tile count is fixed per loop, so the steps carry no branch
+      auto steps = [&](auto ntc) __attribute__((always_inline)) {
+        constexpr int n = decltype(ntc)::value;
+#pragma unroll 2
+        for (int st = 0; st < nsteps; ++st)
 #pragma unroll
-        for (int pb = 0; pb < 4; ++pb)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int p = 16 * pb + 4 * v + kk;   // D row 4 v + lane / 16, column lane % 16
-            if (ww == 0) Rc[p * GM64_RS + i16] = acc[pb][v];
-            else Rc[p * GM64_RS + i16] += acc[pb][v];
+          for (int u = 0; u < n; ++u) {
+            const double av = sd[ta[u] + 64 * st], bv = sd[tb[u] + 64 * st];
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
           }
+      };
+      if (nt >= 3) steps(std::integral_constant<int, 3>{});
+      else if (nt == 2) steps(std::integral_constant<int, 2>{});
+      else if (nt == 1) steps(std::integral_constant<int, 1>{});
+      __syncthreads();  // staging buffers are rewritten for the next channel (or by the tiles)
+      if (ch + 1 < d.nch) {
+        put(ch + 1);
+        __syncthreads();
       }
-      __syncthreads();
     }
+#pragma unroll
+    for (int u = 0; u < GM64_TPW; ++u)
+      if (u < nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          Dt[(w + GM64_WAVES * u) * 256 + (4 * v + (lane >> 4)) * 16 + (lane & 15)] = acc[u][v];
+    __syncthreads();
+    // R[p][qi] = c_{a(p), qi}(s(p)): a diagonal of the pair's tiles, i ascending
+    if (tid < 4 * 2 * N) {
+      const int p = tid >> 2, qi = tid & 3;
+      const int part = p >= N ? 1 : 0, cp = p - part * N, f = cp < k2 ? 0 : 1;
+      const int a = part * 2 + f, s = f ? cp - k2 : cp;
+      const int lo = min(a, qi), hi = max(a, qi), l = a <= qi ? s : -s;
+      const int t0 = gm64_tlo(lo, hi, k1, k2);
+      const double* D = Dt + (size_t)gm64_tile_of(lo, hi, t0, k1, k2) * 256;
+      double sum = 0.0;
+      for (int i = 0; i < 16; ++i) {
+        const int jj = i + l, t = (jj >> 4) - t0;   // jj >> 4 = floor(jj / 16)
+        sum += D[t * 256 + i * 16 + (jj & 15)];
+      }
+      Rc[p * GM64_RS + qi] = sum;
+    }
+    __syncthreads();
     // G[p][c] for c in {0 (column 0), 1 (column k2)}
     auto G = [&](int p, int c) -> c64 {
       return c64{Rc[p * GM64_RS + c] + Rc[(N + p) * GM64_RS + 2 + c], Rc[p * GM64_RS + 2 + c] - Rc[(N + p) * GM64_RS + c]};
@@ -260,6 +359,8 @@ __global__ __launch_bounds__(64 * GM64_WAVES) void k_gram_mfma64(batch_ref br) {
       }
       d.corr[((size_t)pass * S + j) * NL + li] = cdd{{g.re, 0.0}, {g.im, 0.0}};
     }
+    // the next item's staging rewrites only the tiles' area, whose reads
+    // ended at the barrier above; Rc is rewritten after two more barriers
   });
 }
 
@@ -267,7 +368,8 @@ __global__ __launch_bounds__(64 * GM64_WAVES) void k_gram_mfma64(batch_ref br) {
 
 size_t gram_mfma_lds_bytes(int maxStride, int fmt) {
   const size_t P = (size_t)maxStride + GM_PAD;
-  if (fmt == 2) return 64 * GM64_RS * sizeof(double) + 32 + 4 * P * sizeof(double);
+  if (fmt == 2)
+    return 64 * GM64_RS * sizeof(double) + 32 + std::max<size_t>(4 * P, GM64_MAX_TILES * 256) * sizeof(double);
   return 64 * GM_RS * sizeof(float) + 4 * P * (fmt == 0 ? sizeof(float) : sizeof(unsigned short));
 }
 

@@ -169,8 +169,9 @@ def test_mfma64_grams_within_fp64_bound(P):
         |G_mfma64 - G_dd| <= (L + 3) 2^-53 (|M|^T |M|);
     a layout or index mistake breaks this by orders of magnitude.  Against
     the oracle the Gram keeps the double-double form's 1e-12 of max |G|."""
+    # (3, 29) and (12, 20): 34 correlation tiles, the most any k1 + k2 <= 32 needs
     for (m, n, k1, k2) in [(64, 64, 5, 5), (96, 140, 9, 11), (40, 33, 3, 7), (30, 250, 15, 17),
-                           (20, 30, 16, 16), (44, 36, 1, 6)]:
+                           (20, 30, 16, 16), (44, 36, 1, 6), (24, 40, 3, 29), (30, 28, 12, 20)]:
         B1, B2, _, _, _ = _pair(37, m, n, k1, k2, np.float32)
         b1, b2 = to_dev(B1, torch.float32), to_dev(B2, torch.float32)
         G = P.sample_grams(b1, b2, m, n, precision=P.Precision.MFMA64).cpu().numpy()
