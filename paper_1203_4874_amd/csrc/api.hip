@@ -438,6 +438,7 @@ struct chunk_view {
   int colGroups;        // the column filter's row groups of the frames (bit g set for group g)
   int gram_fmt;   // gram_format() of the call's precision
   int maxStride;  // largest Hmax / Wmax (matrix-core Gram staging)
+  bool finLean;   // no frame's scale solve refines or records diagnostics
   const void* mlp;  // the learned form's network (device mlp blob) or NULL
 };
 
@@ -470,12 +471,12 @@ hipError_t enqueue_chunk(dev_state& ds, const chunk_view& cv, bool latent, bool 
   if (cv.mlp) {
     // the learned form: plain kernels (the fallback), the network's weights,
     // the learned kernels, and the judge between them
-    CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, 0, 1, st));
+    CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, 0, 1, cv.finLean, st));
     CBP_TRY(launch_mlp_frames(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.mlp, st));
-    CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, 1, 0, st));
+    CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, 1, 0, cv.finLean, st));
     CBP_TRY(launch_judge(br(Q_FINALIZE), cv.grid[Q_FINALIZE], st));
   } else {
-    CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, 0, 0, st));
+    CBP_TRY(launch_finalize(br(Q_FINALIZE), cv.grid[Q_FINALIZE], cv.maxS, 0, 0, cv.finLean, st));
   }
   if (latent) {
     CBP_TRY(launch_kernel_dft<T>(br(Q_KRDFT), cv.grid[Q_KRDFT], st));
@@ -606,7 +607,10 @@ cbp_status build_batch(const std::vector<frame_req>& reqs, const cbp_options* o,
     cv.colGroups = 0;
     cv.gram_fmt = gram_format(o->precision);
     cv.mlp = o->learned ? o->mlp_blob : nullptr;
+    cv.finLean = true;
     for (int i = 0; i < cnt; ++i) {
+      const frame_desc& fd = descs[f0 + i];
+      cv.finLean = cv.finLean && solve_refine_max(fd.variant) == 0 && fd.diag == nullptr && !(fd.variant & VAR_ONE_AXIS);
       const frame_plan& p = bb->plans[f0 + i];
       cv.maxStride = std::max({cv.maxStride, p.Hmax, p.Wmax});
       cv.maxN = std::max(cv.maxN, p.N);

@@ -394,12 +394,14 @@ hipError_t launch_gram(const batch_ref& br, int grid, hipStream_t st);
 // dense Gram matrices (2 S N N complex FP64, [pass][sample][p][q]); items of Q_GRAMM
 hipError_t launch_gram_expand(const batch_ref& br, int grid, double* out, hipStream_t st);
 hipError_t launch_sample(const batch_ref& br, int grid, int maxN, hipStream_t st);
-hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned, int plain_only,
+// lean: every frame's scale solve runs without refinement or diagnostics
+// (its coupling block shares the solver's X region: less LDS)
+hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned, int plain_only, bool lean,
                            hipStream_t st);
 // the learned form's judge: keeps the plain kernels where their per-sample
 // residual objective is smaller (items of Q_FINALIZE)
 hipError_t launch_judge(const batch_ref& br, int grid, hipStream_t st);
-size_t finalize_lds_bytes(int S, int learned);
+size_t finalize_lds_bytes(int S, int learned, bool lean = false);
 size_t sample_lds_bytes(int N);
 
 // gram_mfma.hip: the per-sample Gram on the matrix cores (fmt 0: FP32

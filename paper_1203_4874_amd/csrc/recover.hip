@@ -233,8 +233,9 @@ __device__ inline __attribute__((always_inline)) bool learned_assembly(const c64
                                         double* K, cbp_diag* diag, int c);
 
 // LDS of the plain finalize: twiddles, the two diagonal blocks, the solver.
-__host__ __device__ inline size_t fin_base_bytes(int S) {
-  return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) + small_lds_bytes(2 * S);
+// lean: the scale solve keeps no caller half (see finalize_frame).
+__host__ __device__ inline size_t fin_base_bytes(int S, bool lean = false) {
+  return (size_t)CBP_MAX_S * sizeof(c64) + 2 * (size_t)CBP_MAX_S * sizeof(dd) + small_lds_bytes(2 * S, !lean);
 }
 
 // Kernels from the per-sample scales: both kernels' normalisation (divide by
@@ -415,7 +416,13 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
   c64* tw = (c64*)sm_fin;                        // S
   dd* Da = (dd*)(tw + CBP_MAX_S);                // S
   dd* Db = Da + CBP_MAX_S;                       // S
-  small_ws w = small_carve((char*)(Db + CBP_MAX_S), n2);
+  // The coupling block (below) is read through H by the Newton refinement
+  // and by the diagnostics' Rayleigh quotient after the solver has built X;
+  // a solve with neither reads it only before (A and hmax come from it), so
+  // it may share X's region (lean: no caller half, 9 KB less LDS at S = 17,
+  // which lets the workgroup fit on a CU beside the FFT passes' workgroups).
+  const bool lean = solve_refine_max(variant) == 0 && diag == nullptr;
+  small_ws w = small_carve((char*)(Db + CBP_MAX_S), n2, !lean);
   // after the scale solve, its matrix region (4 S^2 entries) holds the
   // averaged spectra / inverse DFTs (2 S^2) and the half-transformed ones (2 S^2)
   c64* kbuf = w.A;
@@ -425,7 +432,8 @@ __device__ inline __attribute__((always_inline)) void finalize_frame(const c64* 
   // [i][j], written by the sample solves), staged in the solver's matrix
   // region (4 S^2 entries, filled with H's rounding once they are read); the
   // coupling block C (S^2 double-double entries) goes to the W region, which
-  // the solver leaves free, so every read of H is an LDS read
+  // the solver leaves free (or, lean, which it fills with X only after C's
+  // last read), so every read of H is an LDS read
   c64* pql = w.A;
   cdd* cmat = (cdd*)w.W;
   for (int e0 = 0; e0 < 4 * SS; e0 += 8 * SMALL_NT) {   // eight loads in flight per lane
@@ -848,10 +856,10 @@ __global__ void k_diag_init(batch_ref br) {
 // inversion's two vectors, taken from the same W region (2S (2S + 1)
 // entries, the last region of the solver's LDS) plus what they need beyond
 // it.
-size_t finalize_lds_bytes(int S, int learned) {
-  const size_t base = fin_base_bytes(S);
+size_t finalize_lds_bytes(int S, int learned, bool lean) {
+  const size_t base = fin_base_bytes(S, lean);
   const size_t need = ((size_t)S * S + 2 * CBP_MAX_S) * sizeof(c64);
-  const size_t have = (size_t)(2 * S) * (2 * S + 1) * sizeof(c64);
+  const size_t have = lean ? (size_t)(2 * S) * (2 * S) * sizeof(double) : (size_t)(2 * S) * (2 * S + 1) * sizeof(c64);
   return learned && need > have ? base + (need - have) : base;
 }
 
@@ -893,10 +901,11 @@ hipError_t launch_judge(const batch_ref& br, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned, int plain_only,
+hipError_t launch_finalize(const batch_ref& br, int grid, int maxS, int learned, int plain_only, bool lean,
                            hipStream_t st) {
   prof_begin(PH_FINALIZE, st);
-  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(SMALL_NT), finalize_lds_bytes(maxS, learned), st, br, plain_only);
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(SMALL_NT), finalize_lds_bytes(maxS, learned, lean), st, br,
+                     plain_only);
   prof_end(PH_FINALIZE, st);
   return hipGetLastError();
 }
