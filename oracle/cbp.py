@@ -78,8 +78,8 @@ def unit_roots_matrix(S: int, length: int) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# O2  unit-circle evaluation (Sec. 4 eq. 3; Sec. 5: evaluation at points
-#     around the unit circle is exactly a DFT)
+# O2  unit-circle evaluation (Sec. 4 eq. 3; Sec. 5: the evaluations at the
+#     S-th roots of unity form a length-S DFT)
 # --------------------------------------------------------------------------
 
 def unit_circle_eval(B: np.ndarray, S: int):
