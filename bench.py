@@ -46,6 +46,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X FP64 matrix cores (dense)
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
 
 
@@ -609,6 +610,27 @@ def main():
                 end_to_end=dict(achieved=per_launch / (tm["ms_per_step"] * 1e-3) / 1e9,
                                 frac=per_launch / (tm["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                 note="the same bytes over the whole step (every kernel of the path)"))
+    if args.precision == "mfma64" and ph.get("gram"):
+        # the MFMA64 Gram against the FP64 matrix-core peak: issued = the
+        # v_mfma_f64_16x16x4f64 tiles it runs (2048 flops each: one per 16 x 16
+        # lag-correlation tile and 64 rows), useful = the four columns of R
+        # = M^T M it needs (4 x 2N x L real MACs per sample, pass and channel)
+        def tiles(ka, kb):
+            kk = [kb, ka, kb, ka]
+            return sum(((14 + kk[a]) >> 4) - (0 if a == b else -((kk[b] + 14) >> 4)) + 1
+                       for a in range(4) for b in range(a, 4))
+        N = k1 + k2
+        issued = useful = 0.0
+        for l1, l2 in ((W1, W2), (H1, H2)):
+            steps = (max(l1, l2) + 63) // 64
+            issued += args.batch * S * 3 * tiles(k1, k2) * steps * 2048.0
+            useful += args.batch * S * 3 * 4 * 2 * N * (l1 + k2 - 1) * 2.0
+        t = ph["gram"] * 1e-6
+        roof["gram_mfma"] = dict(kernel="gram", bound="mfma", unit="TFLOP/s", peak=FP64_MFMA_PEAK_TFLOPS,
+                                 avg_us=ph["gram"], issued=issued / t / 1e12, useful=useful / t / 1e12,
+                                 frac_issued=issued / t / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+                                 frac_useful=useful / t / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+                                 tiles_per_64_rows=tiles(k1, k2))
 
     # ---- the other forms on the stream
     extra = {}
